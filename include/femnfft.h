@@ -1,0 +1,162 @@
+/*
+ * femnfft -- NFFT fast summation of 2D magnetostatic potentials and fields on MI355X.
+ *
+ * Operation (Kritsikis, Toussaint, Fruchart, "Fast computation of magnetostatic
+ * fields by Non-uniform Fast Fourier Transforms"): for targets r_i (mesh nodes)
+ * and sources r_j (quadrature points) of weight w_j = omega_j det J(r_j) carrying
+ * a charge density q_j (volume rho_j or surface sigma_j), the discrete Green sum
+ * of the paper's eq. (2)
+ *
+ *     phi_i = sum_j w_j q_j G(r_i - r_j),         G(r) = -(1/2 pi) ln |r|
+ *
+ * (G is the 2D Green function given with eq. (1)) and the field H = -grad phi
+ * (introduction):
+ *
+ *     H_i   = (1/2 pi) sum_j w_j q_j (r_i - r_j) / |r_i - r_j|^2.
+ *
+ * Pairs at distance zero contribute nothing.  The sums are evaluated in
+ * O(N log N) by the NFFT method of the paper's "NFFT" section: spread onto an
+ * oversampled grid with a Kaiser-Bessel window, 2D FFT, multiply by the Fourier
+ * coefficients of the kernel smoothed near the origin (window deconvolution
+ * folded into the same table), inverse FFT, gather at the targets, plus a
+ * near-field correction in the smoothing zone.  The transposes (adjoints) of
+ * both maps with respect to q are provided for gradients.
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer on the device that was current
+ *     at fn_create, unless stated otherwise.  The caller owns all of them.
+ *   - 2-vectors are interleaved [n][2] (x, y), FP64.  Scalars per point FP64.
+ *   - All work is enqueued on the stream given to fn_create; no call waits for
+ *     the device except fn_set_geometry (it reads back the bounding box) and
+ *     the fn_fem_* set-up call.  Outputs are valid once the stream reaches them.
+ *   - The library allocates no device memory after fn_set_workspace: the caller
+ *     provides one workspace buffer (e.g. a torch uint8 tensor).
+ *   - Call order per context: fn_create -> fn_workspace_size -> fn_set_workspace
+ *     -> fn_set_geometry -> fn_set_charges -> fn_eval*; fn_eval_*_adjoint only
+ *     needs fn_set_geometry.  Out-of-order calls return FN_E_STATE.
+ *   - A context is not thread-safe; use one context per stream.
+ *   - Every function returns FN_OK (0) or an FN_E_* code; fn_last_error()
+ *     gives a message.  No C++ exception crosses this interface.
+ */
+#ifndef FEMNFFT_H
+#define FEMNFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FN_OK = 0,
+    FN_E_INVAL = 1,       /* null pointer, bad size or parameter, non-finite input */
+    FN_E_STATE = 2,       /* call out of order */
+    FN_E_DOMAIN = 3,      /* degenerate geometry (all points coincide) */
+    FN_E_NOMEM = 4,       /* workspace too small */
+    FN_E_DEVICE = 5,      /* HIP runtime error (includes asynchronous faults) */
+    FN_E_UNSUPPORTED = 6  /* parameter combination not implemented */
+};
+
+enum {
+    FN_FP64 = 0,       /* spread, FFT, gather, near field all in FP64 */
+    FN_FP32_MIXED = 1  /* FP32 spread/FFT/gather (wide accumulation); FP64 near field and final sum */
+};
+
+/*
+ * Parameters of the method (all lengths on the unit torus the points are mapped to).
+ *   grid      G, the oversampled FFT grid per dimension; power of two, 64..8192.
+ *             The bandwidth is n = G/2 (oversampling factor 2).
+ *   m         Kaiser-Bessel half-width in grid cells (2m taps per dimension), 2..8.
+ *   p         regularization degree: the kernel is replaced near the origin by an
+ *             even polynomial matching ln r and its first p-1 derivatives at eps_I
+ *             (the paper's "smoothness degree"), 1..12.
+ *   eps_I     near-field radius; 0 < eps_I, eps_I * G <= 64.
+ *   eps_B     width of the boundary regularization near |x| = 1/2; 0 < eps_B < 1/4.
+ *   precision FN_FP64 or FN_FP32_MIXED.
+ */
+typedef struct fn_params {
+    int32_t grid;
+    int32_t m;
+    int32_t p;
+    int32_t precision;
+    double eps_I;
+    double eps_B;
+    int32_t flags;      /* reserved, must be 0 */
+    int32_t reserved;
+} fn_params;
+
+/* Read-only facts about a context after fn_set_geometry (host struct). */
+typedef struct fn_info {
+    double centre[2];       /* c: bounding-box midpoint of all points */
+    double scale;           /* s: torus coordinate = s (r - c) */
+    int64_t n_tgt, n_src;
+    int32_t win_lo[2];      /* first grid index (x, y) of the data window */
+    int32_t win_ext[2];     /* window extent in cells (x, y) */
+    int32_t tiles[2];       /* spread/gather tiles per dimension */
+    int32_t near_cells;     /* near-field radius in grid cells (ceil) */
+    size_t workspace_bytes; /* bytes required for (n_tgt, n_src) */
+} fn_info;
+
+typedef struct fn_ctx fn_ctx;
+
+/* Fill *p with defaults for grid G: m = 6, p = 8, eps_I = 7/(G/2), eps_B = 1/16,
+ * precision FN_FP32_MIXED. */
+int fn_params_default(fn_params *p, int32_t grid);
+
+/* Create a context bound to the current device and to the HIP stream
+ * `stream` (hipStream_t, may be NULL for the null stream).  Validates the
+ * parameters and prepares the host-side plan (regularization polynomials,
+ * window transform).  *out receives the context; free it with fn_destroy. */
+int fn_create(const fn_params *params, void *stream, fn_ctx **out);
+int fn_destroy(fn_ctx *ctx);
+
+/* Bytes of device workspace needed for n_tgt targets and n_src sources
+ * (an upper bound that does not depend on where the points lie). */
+int fn_workspace_size(const fn_ctx *ctx, int64_t n_tgt, int64_t n_src, size_t *bytes);
+
+/* Hand the context a device buffer of `bytes` bytes, 256-byte aligned.  The
+ * context uses it until fn_destroy or the next fn_set_workspace; the caller must
+ * keep it alive that long.  Builds the kernel's Fourier table (b_l and the
+ * deconvolution) inside it. */
+int fn_set_workspace(fn_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Targets tgt_xy [n_tgt][2], sources src_xy [n_src][2] with weights src_w [n_src]
+ * (w_j = omega_j det J(r_j) of eq. (2)).  Maps all points to the unit torus
+ * (centre c = bounding-box midpoint, D = 2 max |r - c|, s = (1/2 - eps_B)/D),
+ * bins them by grid cell and keeps sorted copies in the workspace.  The input
+ * buffers are not referenced after the call.  Blocks until the bounding box is
+ * known.  FN_E_DOMAIN if every point coincides; FN_E_NOMEM if the workspace is
+ * smaller than fn_workspace_size(n_tgt, n_src). */
+int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy,
+                    int64_t n_src, const double *src_xy, const double *src_w);
+
+/* Charge densities q [n_src] (rho_j or sigma_j of eq. (2)); copied into the
+ * workspace as s_j = w_j q_j in binned order. */
+int fn_set_charges(fn_ctx *ctx, const double *q);
+
+/* phi [n_tgt] and/or H [n_tgt][2] at the targets; either pointer may be NULL
+ * in fn_eval (not both).  Results in the caller's target order. */
+int fn_eval(fn_ctx *ctx, double *phi, double *H);
+int fn_eval_phi(fn_ctx *ctx, double *phi);
+int fn_eval_H(fn_ctx *ctx, double *H);
+
+/* Transposes with respect to q (need fn_set_geometry only):
+ *   fn_eval_phi_adjoint:  u_j = w_j sum_i v_i G(r_i - r_j)          v [n_tgt], u [n_src]
+ *   fn_eval_H_adjoint:    u_j = w_j sum_i V_i . (-grad G)(r_i - r_j)
+ *                             = w_j sum_i V_i . (r_i - r_j) / (2 pi |r_i - r_j|^2)
+ *                                                                    V [n_tgt][2], u [n_src]
+ * so that <H(q), V> = <q, u> and <phi(q), v> = <q, u> up to rounding. */
+int fn_eval_phi_adjoint(fn_ctx *ctx, const double *v, double *u);
+int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u);
+
+int fn_get_info(const fn_ctx *ctx, fn_info *info);
+
+/* Message of the last error on this context (or of the last failed
+ * fn_create when ctx is NULL).  Valid until the next call on the context. */
+const char *fn_last_error(const fn_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEMNFFT_H */

@@ -1,0 +1,85 @@
+"""ctypes declarations for libfemnfft.so (argument marshalling only).
+
+The library is built in-tree by paper_0807_2387_amd.build; importing this module
+raises if it is missing, so no code path can silently run without it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfemnfft.so")
+
+FN_OK, FN_E_INVAL, FN_E_STATE, FN_E_DOMAIN, FN_E_NOMEM, FN_E_DEVICE, FN_E_UNSUPPORTED = range(7)
+FN_FP64, FN_FP32_MIXED = 0, 1
+ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: "FN_E_NOMEM",
+             5: "FN_E_DEVICE", 6: "FN_E_UNSUPPORTED"}
+
+# exported C-ABI symbols (include/femnfft.h)
+SYMBOLS = (
+    "fn_params_default", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
+    "fn_set_geometry", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
+    "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_get_info", "fn_last_error",
+)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("eps_I", ctypes.c_double), ("eps_B", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_double * 2), ("scale", ctypes.c_double),
+                ("n_tgt", ctypes.c_int64), ("n_src", ctypes.c_int64),
+                ("win_lo", ctypes.c_int32 * 2), ("win_ext", ctypes.c_int32 * 2),
+                ("tiles", ctypes.c_int32 * 2), ("near_cells", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class FemNfftError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_0807_2387_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    sig = {
+        "fn_params_default": ([ctypes.POINTER(Params), I32], ctypes.c_int),
+        "fn_create": ([ctypes.POINTER(Params), P, ctypes.POINTER(P)], ctypes.c_int),
+        "fn_destroy": ([P], ctypes.c_int),
+        "fn_workspace_size": ([P, I64, I64, ctypes.POINTER(SZ)], ctypes.c_int),
+        "fn_set_workspace": ([P, P, SZ], ctypes.c_int),
+        "fn_set_geometry": ([P, I64, P, I64, P, P], ctypes.c_int),
+        "fn_set_charges": ([P, P], ctypes.c_int),
+        "fn_eval": ([P, P, P], ctypes.c_int),
+        "fn_eval_phi": ([P, P], ctypes.c_int),
+        "fn_eval_H": ([P, P], ctypes.c_int),
+        "fn_eval_phi_adjoint": ([P, P, P], ctypes.c_int),
+        "fn_eval_H_adjoint": ([P, P, P], ctypes.c_int),
+        "fn_get_info": ([P, ctypes.POINTER(Info)], ctypes.c_int),
+        "fn_last_error": ([P], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(rc, ctx=None):
+    if rc != FN_OK:
+        msg = lib().fn_last_error(ctx)
+        raise FemNfftError(rc, msg.decode() if msg else "")

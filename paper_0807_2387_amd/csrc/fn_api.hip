@@ -1,0 +1,707 @@
+// Host runtime of femnfft: parameter validation, the plan (regularized kernel,
+// window transform, Fourier table), workspace layout, geometry set-up and the
+// evaluation pipelines behind the C-ABI declared in include/femnfft.h.
+#include "fn_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+namespace fn {
+
+static constexpr double PI = 3.14159265358979323846264338327950288;
+
+// I0(x) by its power series sum_k (x^2/4)^k / (k!)^2 (all terms positive; used
+// for x <= 40, where 120 terms reach full FP64 precision).
+double bessel_i0(double x)
+{
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 200; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+void twiddles(int N, std::vector<double> &re, std::vector<double> &im)
+{
+    re.resize(N);
+    im.resize(N);
+    for (int k = 0; k < N; ++k) {
+        // reduce to the first octant for accuracy: angle = -2 pi k / N
+        long double a = -2.0L * (long double)PI * (long double)k / (long double)N;
+        re[k] = (double)std::cos(a);
+        im[k] = (double)std::sin(a);
+    }
+}
+
+// r^q K^{(q)}(r) for K(r) = -(1/2pi) ln r.
+static double K_scaled_deriv(int q, double r)
+{
+    if (q == 0) return -std::log(r) / (2.0 * PI);
+    double f = 1.0;
+    for (int i = 2; i < q; ++i) f *= i;  // (q-1)!
+    return -((q % 2 == 1) ? 1.0 : -1.0) * f / (2.0 * PI);
+}
+
+static double falling(int a, int q)
+{
+    if (q > a) return 0.0;
+    double r = 1.0;
+    for (int i = 0; i < q; ++i) r *= (double)(a - i);
+    return r;
+}
+
+// Gaussian elimination with partial pivoting; returns false if singular.
+static bool solve(std::vector<double> A, std::vector<double> b, int n, std::vector<double> &x)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0.0) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    x.assign(n, 0.0);
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * x[k];
+        x[r] = s / A[r * n + r];
+    }
+    return true;
+}
+
+static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
+{
+    P.G = prm.grid;
+    P.n = prm.grid / 2;
+    P.m = prm.m;
+    P.p = prm.p;
+    P.precision = prm.precision;
+    P.eps_I = prm.eps_I;
+    P.eps_B = prm.eps_B;
+    P.log2G = 0;
+    while ((1 << P.log2G) < P.G) ++P.log2G;
+    const double sigma = (double)P.G / P.n;
+    P.kb_b = PI * (2.0 - 1.0 / sigma);
+    const double mb = P.m * P.kb_b;
+    const double i0mb = bessel_i0(mb);
+    P.win_norm = 1.0 / (2.0 * PI * i0mb * std::exp(-mb));
+    // inner polynomial: sum_k a_k (r/eps)^{2k}, derivatives 0..p-1 match K at eps
+    {
+        const int p = P.p;
+        std::vector<double> A(p * p), b(p), x;
+        for (int q = 0; q < p; ++q) {
+            for (int k = 0; k < p; ++k) A[q * p + k] = falling(2 * k, q);
+            b[q] = K_scaled_deriv(q, P.eps_I);
+        }
+        if (!solve(A, b, p, x)) {
+            err = "inner regularization system is singular";
+            return false;
+        }
+        for (int k = 0; k < MAXP; ++k) P.a[k] = k < p ? x[k] : 0.0;
+    }
+    // boundary polynomial in t = (r - rB)/eps_B of degree 2p-2: Taylor part fixed
+    // by K at rB, remaining p-1 coefficients make derivatives 1..p-1 vanish at t = 1
+    {
+        const int p = P.p;
+        const double rB = 0.5 - P.eps_B;
+        P.cB.assign(2 * p - 1, 0.0);
+        double fact = 1.0;
+        for (int q = 0; q < p; ++q) {
+            if (q > 0) fact *= q;
+            P.cB[q] = K_scaled_deriv(q, rB) * std::pow(P.eps_B / rB, q) / fact;
+        }
+        if (p > 1) {
+            const int nu = p - 1;
+            std::vector<double> A(nu * nu), b(nu), x;
+            for (int qi = 0; qi < nu; ++qi) {
+                const int q = qi + 1;
+                double rhs = 0.0;
+                for (int k = 0; k < p; ++k) rhs -= P.cB[k] * falling(k, q);
+                b[qi] = rhs;
+                for (int ki = 0; ki < nu; ++ki) A[qi * nu + ki] = falling(p + ki, q);
+            }
+            if (!solve(A, b, nu, x)) {
+                err = "boundary regularization system is singular";
+                return false;
+            }
+            for (int ki = 0; ki < nu; ++ki) P.cB[p + ki] = x[ki];
+        }
+    }
+    P.psihat.resize(P.n / 2 + 1);
+    for (int l = 0; l <= P.n / 2; ++l) {
+        const double w = 2.0 * PI * l / P.G;
+        P.psihat[l] = bessel_i0(P.m * std::sqrt(P.kb_b * P.kb_b - w * w)) / i0mb;
+    }
+    return true;
+}
+
+// slots of the 8192-double reduction scratch
+enum {
+    RED_COEF = 0,      // T_I coefficients (MAXP)
+    RED_CB = 16,       // T_B coefficients (<= 2 MAXP - 1)
+    RED_SUMQ = 64,     // sum of s_j (+ 256 partials)
+    RED_SUMV = 512,    // sum of v_i (+ 256 partials)
+    RED_PART = 1024,   // bounding-box partials (8 x 256)
+    RED_PSI = 4096     // window transform, n/2 + 1 <= 2049 values
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
+{
+    Layout L{};
+    const size_t rs = P.precision == FN_FP64 ? 8 : 4;
+    const int64_t nh = P.n / 2;
+    L.emax = P.G / 2 + 2 * P.m + 4;
+    L.ldS = (L.emax + 63) / 64 * 64;
+    const int64_t ncell = L.emax * L.emax;
+    const int64_t tiles1 = (L.emax + TILE - 1) / TILE;
+    const int64_t PT = TILE + 2 * P.m - 1;
+    const int64_t nmax = std::max<int64_t>(std::max(nt, ns), 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    L.off_W = take((size_t)(nh + 1) * (nh + 1) * rs);
+    L.off_tw = take((size_t)P.G * 2 * rs);
+    L.off_tw64 = take((size_t)P.n * 16);
+    const int64_t N[2] = {std::max<int64_t>(nt, 1), std::max<int64_t>(ns, 1)};
+    for (int s = 0; s < 2; ++s) {
+        L.off_key[s] = take(N[s] * 4);
+        L.off_perm[s] = take(N[s] * 4);
+        L.off_fr32[s] = take(N[s] * 8);
+        L.off_fr64[s] = take(N[s] * 16);
+        L.off_u64[s] = take(N[s] * 16);
+        L.off_cstart[s] = take((size_t)(ncell + 1) * 4);
+    }
+    L.off_w = take(N[1] * 8);
+    L.off_val = take(N[1] * rs);
+    L.off_val64 = take(N[1] * 8);
+    L.off_aval = take(2 * N[0] * rs);
+    L.off_aval64 = take(2 * N[0] * 8);
+    L.off_ptile = take((size_t)2 * tiles1 * tiles1 * PT * PT * 8);
+    L.off_grid = take((size_t)3 * ncell * rs);
+    // spectra: 2 fields each for input and output; the region also hosts the
+    // n x n FP64 complex scratch of the plan FFT
+    size_t specb = (size_t)2 * (nh + 1) * L.ldS * 2 * rs;
+    size_t need = (size_t)P.n * P.n * 16;
+    if (2 * specb < need) specb = (need + 1) / 2;
+    L.off_spec = take(specb);
+    L.off_spec2 = take(specb);
+    L.off_far = take((size_t)3 * nmax * 8);
+    L.off_red = take(8192 * 8);  // see the RED_* slots below
+    L.off_skey = take(nmax * 4);
+    L.off_sval = take(nmax * 4);
+    const int64_t nblk = (nmax + 4095) / 4096;
+    L.off_hist = take((size_t)256 * nblk * 4);
+    L.total = o;
+    return L;
+}
+
+static void bind_buffers(fn_ctx *c)
+{
+    char *b = static_cast<char *>(c->ws);
+    const Layout &L = c->lay;
+    Buffers &B = c->buf;
+    B.W = b + L.off_W;
+    B.tw = b + L.off_tw;
+    B.tw64 = reinterpret_cast<double2 *>(b + L.off_tw64);
+    for (int s = 0; s < 2; ++s) {
+        B.key[s] = reinterpret_cast<uint32_t *>(b + L.off_key[s]);
+        B.perm[s] = reinterpret_cast<uint32_t *>(b + L.off_perm[s]);
+        B.fr32[s] = reinterpret_cast<float *>(b + L.off_fr32[s]);
+        B.fr64[s] = reinterpret_cast<double *>(b + L.off_fr64[s]);
+        B.u64[s] = reinterpret_cast<double *>(b + L.off_u64[s]);
+        B.cstart[s] = reinterpret_cast<uint32_t *>(b + L.off_cstart[s]);
+    }
+    B.w = reinterpret_cast<double *>(b + L.off_w);
+    B.val = b + L.off_val;
+    B.val64 = reinterpret_cast<double *>(b + L.off_val64);
+    B.aval = b + L.off_aval;
+    B.aval64 = reinterpret_cast<double *>(b + L.off_aval64);
+    B.ptile = reinterpret_cast<double *>(b + L.off_ptile);
+    B.grid = b + L.off_grid;
+    B.spec = b + L.off_spec;
+    B.spec2 = b + L.off_spec2;
+    B.far = reinterpret_cast<double *>(b + L.off_far);
+    B.red = reinterpret_cast<double *>(b + L.off_red);
+    B.skey = reinterpret_cast<uint32_t *>(b + L.off_skey);
+    B.sval = reinterpret_cast<uint32_t *>(b + L.off_sval);
+    B.hist = reinterpret_cast<uint32_t *>(b + L.off_hist);
+    B.scratch64 = reinterpret_cast<double *>(b + L.off_spec);
+}
+
+}  // namespace fn
+
+using namespace fn;
+
+static thread_local std::string g_create_err;
+
+#define FN_SET_ERR(ctx, code, msg)         \
+    do {                                   \
+        (ctx)->err = (msg);                \
+        return (code);                     \
+    } while (0)
+
+#define FN_HIP(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            (ctx)->err = std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_);    \
+            return FN_E_DEVICE;                                                                  \
+        }                                                                                        \
+    } while (0)
+
+static int check_device(fn_ctx *c)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->err = std::string("pending HIP error: ") + hipGetErrorString(e);
+        return FN_E_DEVICE;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device) {
+        if (hipSetDevice(c->device) != hipSuccess) {
+            c->err = "cannot select the context's device";
+            return FN_E_DEVICE;
+        }
+    }
+    return FN_OK;
+}
+
+extern "C" {
+
+int fn_params_default(fn_params *p, int32_t grid)
+{
+    if (!p) return FN_E_INVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->grid = grid;
+    p->m = 6;
+    p->p = 8;
+    p->precision = FN_FP32_MIXED;
+    p->eps_I = grid >= 2 ? 7.0 / (grid / 2) : 0.0;
+    p->eps_B = 1.0 / 16.0;
+    return FN_OK;
+}
+
+static int validate_params(const fn_params *p, std::string &err)
+{
+    if (!p) { err = "params is NULL"; return FN_E_INVAL; }
+    const int G = p->grid;
+    if (G < 64 || G > MAXG || (G & (G - 1))) { err = "grid must be a power of two in [64, 8192]"; return FN_E_INVAL; }
+    if (p->m < 2 || p->m > MAXM) { err = "m must be in [2, 8]"; return FN_E_INVAL; }
+    if (p->p < 1 || p->p > MAXP) { err = "p must be in [1, 12]"; return FN_E_INVAL; }
+    if (!(p->eps_B > 0.0) || !(p->eps_B < 0.25)) { err = "eps_B must be in (0, 1/4)"; return FN_E_INVAL; }
+    if (!(p->eps_I > 0.0) || !(p->eps_I * G <= 64.0) || !(p->eps_I < 0.5 - p->eps_B)) {
+        err = "eps_I must be positive, eps_I*grid <= 64 and eps_I < 1/2 - eps_B";
+        return FN_E_INVAL;
+    }
+    if (p->precision != FN_FP64 && p->precision != FN_FP32_MIXED) { err = "unknown precision"; return FN_E_INVAL; }
+    if (p->flags != 0) { err = "flags must be 0"; return FN_E_UNSUPPORTED; }
+    return FN_OK;
+}
+
+int fn_create(const fn_params *params, void *stream, fn_ctx **out)
+{
+    if (!out) { g_create_err = "out is NULL"; return FN_E_INVAL; }
+    *out = nullptr;
+    std::string err;
+    int rc = validate_params(params, err);
+    if (rc) { g_create_err = err; return rc; }
+    fn_ctx *c = new (std::nothrow) fn_ctx();
+    if (!c) { g_create_err = "out of host memory"; return FN_E_NOMEM; }
+    c->prm = *params;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        g_create_err = "no HIP device";
+        return FN_E_DEVICE;
+    }
+    if (!build_host_plan(*params, c->plan, err)) {
+        delete c;
+        g_create_err = err;
+        return FN_E_INVAL;
+    }
+    *out = c;
+    return FN_OK;
+}
+
+int fn_destroy(fn_ctx *ctx)
+{
+    delete ctx;
+    return FN_OK;
+}
+
+int fn_workspace_size(const fn_ctx *ctx, int64_t n_tgt, int64_t n_src, size_t *bytes)
+{
+    if (!ctx || !bytes) return FN_E_INVAL;
+    if (n_tgt < 0 || n_src < 0 || n_tgt > (int64_t)UINT32_MAX / 2 || n_src > (int64_t)UINT32_MAX / 2) {
+        const_cast<fn_ctx *>(ctx)->err = "point counts must be in [0, 2^31)";
+        return FN_E_INVAL;
+    }
+    *bytes = make_layout(ctx->plan, n_tgt, n_src).total;
+    return FN_OK;
+}
+
+int fn_set_workspace(fn_ctx *ctx, void *dev_ptr, size_t bytes)
+{
+    if (!ctx) return FN_E_INVAL;
+    if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) FN_SET_ERR(ctx, FN_E_INVAL, "workspace must be non-NULL and 256-byte aligned");
+    ctx->ws = dev_ptr;
+    ctx->ws_bytes = bytes;
+    ctx->plan_ready = ctx->geom_ready = ctx->charges_ready = false;
+    return FN_OK;
+}
+
+static int build_device_plan(fn_ctx *c)
+{
+    const Plan &P = c->plan;
+    Buffers &B = c->buf;
+    hipStream_t st = c->stream;
+    // twiddles
+    std::vector<double> re, im;
+    twiddles(P.G, re, im);
+    if (P.precision == FN_FP64) {
+        std::vector<double2> t(P.G);
+        for (int k = 0; k < P.G; ++k) t[k] = make_double2(re[k], im[k]);
+        FN_HIP(c, hipMemcpyAsync(B.tw, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+        FN_HIP(c, hipStreamSynchronize(st));
+    } else {
+        std::vector<float2> t(P.G);
+        for (int k = 0; k < P.G; ++k) t[k] = make_float2((float)re[k], (float)im[k]);
+        FN_HIP(c, hipMemcpyAsync(B.tw, t.data(), t.size() * sizeof(float2), hipMemcpyHostToDevice, st));
+        FN_HIP(c, hipStreamSynchronize(st));
+    }
+    twiddles(P.n, re, im);
+    {
+        std::vector<double2> t(P.n);
+        for (int k = 0; k < P.n; ++k) t[k] = make_double2(re[k], im[k]);
+        FN_HIP(c, hipMemcpyAsync(B.tw64, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+        FN_HIP(c, hipStreamSynchronize(st));
+    }
+    double *dcoef = c->buf.red + RED_COEF;
+    double *dcB = c->buf.red + RED_CB;
+    double *dpsi = c->buf.red + RED_PSI;
+    FN_HIP(c, hipMemcpyAsync(dcoef, P.a, sizeof(double) * MAXP, hipMemcpyHostToDevice, st));
+    FN_HIP(c, hipMemcpyAsync(dcB, P.cB.data(), sizeof(double) * P.cB.size(), hipMemcpyHostToDevice, st));
+    FN_HIP(c, hipMemcpyAsync(dpsi, P.psihat.data(), sizeof(double) * P.psihat.size(), hipMemcpyHostToDevice, st));
+    double2 *scr = reinterpret_cast<double2 *>(B.scratch64);
+    FN_HIP(c, launch_kr_samples(scr, P.n, dcoef, P.p, P.eps_I, P.eps_B, dcB, (int)P.cB.size(), st));
+    FN_HIP(c, launch_fft2d_c2c64(scr, P.n, B.tw64, st));
+    FN_HIP(c, launch_make_W(scr, P.n, dpsi, P.precision, B.W, st));
+    FN_HIP(c, hipStreamSynchronize(st));
+    c->plan_ready = true;
+    return FN_OK;
+}
+
+static int bbox_of(fn_ctx *c, const double *xy, int64_t n, double out[4], double *nonfin)
+{
+    // out = (min x, min y, max x, max y)
+    out[0] = out[1] = 1e308;
+    out[2] = out[3] = -1e308;
+    if (n == 0) return FN_OK;
+    const int nblk = (int)std::min<int64_t>(256, (n + 255) / 256);
+    double *part = c->buf.red + RED_PART;  // 8 * 256 doubles
+    FN_HIP(c, launch_bbox(xy, n, part, nblk, c->stream));
+    FN_HIP(c, launch_nonfinite(xy, 2 * n, part + 4 * 256, nblk, c->stream));
+    std::vector<double> h(8 * 256);
+    FN_HIP(c, hipMemcpyAsync(h.data(), part, sizeof(double) * 8 * 256, hipMemcpyDeviceToHost, c->stream));
+    FN_HIP(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < nblk; ++b) {
+        out[0] = std::min(out[0], h[4 * b]);
+        out[1] = std::min(out[1], h[4 * b + 1]);
+        out[2] = std::max(out[2], -h[4 * b + 2]);
+        out[3] = std::max(out[3], -h[4 * b + 3]);
+        *nonfin += h[4 * 256 + 4 * b];
+    }
+    return FN_OK;
+}
+
+static int maxdist_of(fn_ctx *c, const double *xy, int64_t n, double cx, double cy, double *m2)
+{
+    if (n == 0) return FN_OK;
+    const int nblk = (int)std::min<int64_t>(256, (n + 255) / 256);
+    double *part = c->buf.red + RED_PART;
+    FN_HIP(c, launch_maxdist(xy, n, cx, cy, part, nblk, c->stream));
+    std::vector<double> h(4 * 256);
+    FN_HIP(c, hipMemcpyAsync(h.data(), part, sizeof(double) * 4 * nblk, hipMemcpyDeviceToHost, c->stream));
+    FN_HIP(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < nblk; ++b) *m2 = std::max(*m2, h[4 * b]);
+    return FN_OK;
+}
+
+int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_src, const double *src_xy,
+                    const double *src_w)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn_ctx *c = ctx;
+    if (!c->ws) FN_SET_ERR(c, FN_E_STATE, "fn_set_workspace must be called before fn_set_geometry");
+    if (n_tgt < 0 || n_src < 0 || n_tgt + n_src < 1 || n_tgt > (int64_t)UINT32_MAX / 2 ||
+        n_src > (int64_t)UINT32_MAX / 2)
+        FN_SET_ERR(c, FN_E_INVAL, "need n_tgt, n_src >= 0, n_tgt + n_src >= 1, both < 2^31");
+    if ((n_tgt > 0 && !tgt_xy) || (n_src > 0 && (!src_xy || !src_w)))
+        FN_SET_ERR(c, FN_E_INVAL, "NULL point or weight array");
+    int rc = check_device(c);
+    if (rc) return rc;
+    c->geom_ready = c->charges_ready = false;
+    Layout L = make_layout(c->plan, n_tgt, n_src);
+    if (L.total > c->ws_bytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "workspace too small: %zu bytes needed, %zu given", L.total, c->ws_bytes);
+        FN_SET_ERR(c, FN_E_NOMEM, msg);
+    }
+    c->lay = L;
+    bind_buffers(c);
+    if (!c->plan_ready) {
+        rc = build_device_plan(c);
+        if (rc) return rc;
+    }
+    const Plan &P = c->plan;
+    Geom g;
+    g.nt = n_tgt;
+    g.ns = n_src;
+    double bt[4], bs[4], nonfin = 0.0;
+    rc = bbox_of(c, tgt_xy, n_tgt, bt, &nonfin);
+    if (rc) return rc;
+    rc = bbox_of(c, src_xy, n_src, bs, &nonfin);
+    if (rc) return rc;
+    if (n_src > 0) {
+        double wn = 0.0, dummy[4];
+        (void)dummy;
+        const int nblk = (int)std::min<int64_t>(256, (n_src + 255) / 256);
+        FN_HIP(c, launch_nonfinite(src_w, n_src, c->buf.red + RED_PART, nblk, c->stream));
+        std::vector<double> h(4 * 256);
+        FN_HIP(c, hipMemcpyAsync(h.data(), c->buf.red + RED_PART, sizeof(double) * 4 * nblk, hipMemcpyDeviceToHost,
+                                 c->stream));
+        FN_HIP(c, hipStreamSynchronize(c->stream));
+        for (int b = 0; b < nblk; ++b) wn += h[4 * b];
+        nonfin += wn;
+    }
+    if (nonfin > 0.0) FN_SET_ERR(c, FN_E_INVAL, "non-finite coordinate or weight");
+    const double lo[2] = {std::min(bt[0], bs[0]), std::min(bt[1], bs[1])};
+    const double hi[2] = {std::max(bt[2], bs[2]), std::max(bt[3], bs[3])};
+    g.c[0] = 0.5 * (lo[0] + hi[0]);
+    g.c[1] = 0.5 * (lo[1] + hi[1]);
+    double m2 = 0.0;
+    rc = maxdist_of(c, tgt_xy, n_tgt, g.c[0], g.c[1], &m2);
+    if (rc) return rc;
+    rc = maxdist_of(c, src_xy, n_src, g.c[0], g.c[1], &m2);
+    if (rc) return rc;
+    const double D = 2.0 * std::sqrt(m2);
+    if (!(D > 0.0) || !std::isfinite(D)) FN_SET_ERR(c, FN_E_DOMAIN, "all points coincide");
+    g.s = (0.5 - P.eps_B) / D;
+    for (int d = 0; d < 2; ++d) {
+        const double umin = (g.s * (lo[d] - g.c[d]) + 0.5) * P.G;
+        const double umax = (g.s * (hi[d] - g.c[d]) + 0.5) * P.G;
+        const int wlo = (int)std::floor(umin) - P.m;
+        const int whi = (int)std::floor(umax) + P.m + 2;
+        g.wlo[d] = wlo;
+        g.ext[d] = whi - wlo;
+        if (g.ext[d] > L.emax || wlo < 0 || whi > P.G)
+            FN_SET_ERR(c, FN_E_DEVICE, "internal: data window exceeds its bound");
+        g.ntile[d] = (g.ext[d] + TILE - 1) / TILE;
+    }
+    g.rnear = (int)std::ceil(P.eps_I * P.G);
+    const int64_t ncell = (int64_t)g.ext[0] * g.ext[1];
+    int keybits = 1;
+    while (((int64_t)1 << keybits) < ncell) ++keybits;
+    Buffers &B = c->buf;
+    const double *xy[2] = {tgt_xy, src_xy};
+    const int64_t N[2] = {n_tgt, n_src};
+    for (int s = 0; s < 2; ++s) {
+        if (N[s] > 0) {
+            FN_HIP(c, launch_prepare(xy[s], N[s], g.c[0], g.c[1], g.s, P.G, P.m, g.wlo[0], g.wlo[1], g.ext[0],
+                                     g.ext[1], B.key[s], B.perm[s], c->stream));
+            FN_HIP(c, radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, N[s], keybits, c->stream));
+            FN_HIP(c, launch_finish_points(xy[s], s == 1 ? src_w : nullptr, N[s], B.perm[s], g.c[0], g.c[1], g.s,
+                                           P.G, B.fr32[s], B.fr64[s], B.u64[s], s == 1 ? B.w : nullptr,
+                                           c->stream));
+        }
+        FN_HIP(c, launch_cellstart(B.key[s], N[s], ncell, B.cstart[s], c->stream));
+    }
+    FN_HIP(c, hipStreamSynchronize(c->stream));
+    c->geom = g;
+    c->geom_ready = true;
+    return FN_OK;
+}
+
+int fn_set_charges(fn_ctx *ctx, const double *q)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn_ctx *c = ctx;
+    if (!c->geom_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_geometry must succeed before fn_set_charges");
+    if (c->geom.ns > 0 && !q) FN_SET_ERR(c, FN_E_INVAL, "q is NULL");
+    int rc = check_device(c);
+    if (rc) return rc;
+    if (c->geom.ns > 0) {
+        FN_HIP(c, launch_set_values(q, c->buf.w, c->buf.perm[1], c->geom.ns, 1, c->plan.precision, c->buf.val,
+                                    c->buf.val64, c->stream));
+        FN_HIP(c, launch_sum(c->buf.val64, c->geom.ns, c->buf.red + RED_SUMQ, c->stream));
+    }
+    c->charges_ready = true;
+    return FN_OK;
+}
+
+static NearArgs near_args(const fn_ctx *c)
+{
+    NearArgs na{};
+    const Plan &P = c->plan;
+    const double eg = P.eps_I * P.G;
+    na.eps2g = eg * eg;
+    na.ginv = 1.0 / P.G;
+    for (int k = 0; k < MAXP; ++k) na.a[k] = P.a[k];
+    na.p = P.p;
+    na.rnear = c->geom.rnear;
+    na.scale = c->geom.s;
+    na.offset = std::log(c->geom.s) / (2.0 * PI);
+    return na;
+}
+
+static int eval_impl(fn_ctx *c, double *phi, double *H)
+{
+    if (!c->charges_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_charges must be called before evaluation");
+    if (!phi && !H) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
+    int rc = check_device(c);
+    if (rc) return rc;
+    const Plan &P = c->plan;
+    const Geom &g = c->geom;
+    const Buffers &B = c->buf;
+    hipStream_t st = c->stream;
+    if (g.nt == 0) return FN_OK;
+    if (g.ns == 0) {
+        if (phi) FN_HIP(c, launch_fill(phi, g.nt, 0.0, st));
+        if (H) FN_HIP(c, launch_fill(H, 2 * g.nt, 0.0, st));
+        return FN_OK;
+    }
+    const int want_phi = phi != nullptr, want_h = H != nullptr;
+    const int prec = P.precision;
+    const size_t rs = prec == FN_FP64 ? 8 : 4;
+    const int64_t fstride = (int64_t)g.ext[0] * g.ext[1];
+    const int64_t ldS = c->lay.ldS;
+    const int nh = P.n / 2;
+    const int64_t sfstride = (int64_t)(nh + 1) * ldS;
+    (void)rs;
+    FN_HIP(c, launch_spread(prec, P, g, 1, B, B.val, 1, st));
+    FN_HIP(c, launch_fold(prec, g, P.m, B.ptile, 1, B.grid, fstride, st));
+    FN_HIP(c, launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], 1, B.spec, ldS, sfstride, B.tw, st));
+    FN_HIP(c, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
+                          want_h ? COL_PHI_HY : COL_PHI, B.W, B.tw, st));
+    FN_HIP(c, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0], g.ext[1], 1, want_phi,
+                              want_h, B.tw, st));
+    FN_HIP(c, launch_gather(prec, P, g, 0, B, want_h ? 3 : 1, fstride, B.far, g.nt, st));
+    NearArgs na = near_args(c);
+    FN_HIP(c, launch_near_fwd(g, B, na, B.red + RED_SUMQ, want_phi, want_h, phi, H, st));
+    return FN_OK;
+}
+
+int fn_eval(fn_ctx *ctx, double *phi, double *H)
+{
+    if (!ctx) return FN_E_INVAL;
+    return eval_impl(ctx, phi, H);
+}
+
+int fn_eval_phi(fn_ctx *ctx, double *phi)
+{
+    if (!ctx) return FN_E_INVAL;
+    if (!phi) FN_SET_ERR(ctx, FN_E_INVAL, "phi is NULL");
+    return eval_impl(ctx, phi, nullptr);
+}
+
+int fn_eval_H(fn_ctx *ctx, double *H)
+{
+    if (!ctx) return FN_E_INVAL;
+    if (!H) FN_SET_ERR(ctx, FN_E_INVAL, "H is NULL");
+    return eval_impl(ctx, nullptr, H);
+}
+
+static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
+{
+    if (!c->geom_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_geometry must succeed before an adjoint evaluation");
+    const Plan &P = c->plan;
+    const Geom &g = c->geom;
+    if ((g.nt > 0 && !in) || (g.ns > 0 && !u)) FN_SET_ERR(c, FN_E_INVAL, "NULL input or output");
+    int rc = check_device(c);
+    if (rc) return rc;
+    const Buffers &B = c->buf;
+    hipStream_t st = c->stream;
+    if (g.ns == 0) return FN_OK;
+    if (g.nt == 0) {
+        FN_HIP(c, launch_fill(u, g.ns, 0.0, st));
+        return FN_OK;
+    }
+    const int prec = P.precision;
+    const int64_t fstride = (int64_t)g.ext[0] * g.ext[1];
+    const int64_t ldS = c->lay.ldS;
+    const int nh = P.n / 2;
+    const int64_t sfstride = (int64_t)(nh + 1) * ldS;
+    const int nf = kind == 0 ? 2 : 1;
+    FN_HIP(c, launch_set_values(in, nullptr, B.perm[0], g.nt, nf, prec, B.aval, B.aval64, st));
+    if (kind == 1) FN_HIP(c, launch_sum(B.aval64, g.nt, B.red + RED_SUMV, st));
+    FN_HIP(c, launch_spread(prec, P, g, 0, B, B.aval, nf, st));
+    FN_HIP(c, launch_fold(prec, g, P.m, B.ptile, nf, B.grid, fstride, st));
+    FN_HIP(c, launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], nf, B.spec, ldS, sfstride, B.tw, st));
+    FN_HIP(c, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
+                          kind == 0 ? COL_ADJ_H : COL_PHI, B.W, B.tw, st));
+    FN_HIP(c, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0], g.ext[1], 0, 1, 0,
+                              B.tw, st));
+    FN_HIP(c, launch_gather(prec, P, g, 1, B, 1, fstride, B.far, g.ns, st));
+    NearArgs na = near_args(c);
+    FN_HIP(c, launch_near_adj(g, B, na, kind, B.red + RED_SUMV, u, st));
+    return FN_OK;
+}
+
+int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u)
+{
+    if (!ctx) return FN_E_INVAL;
+    return adjoint_impl(ctx, V, u, 0);
+}
+
+int fn_eval_phi_adjoint(fn_ctx *ctx, const double *v, double *u)
+{
+    if (!ctx) return FN_E_INVAL;
+    return adjoint_impl(ctx, v, u, 1);
+}
+
+int fn_get_info(const fn_ctx *ctx, fn_info *info)
+{
+    if (!ctx || !info) return FN_E_INVAL;
+    std::memset(info, 0, sizeof(*info));
+    const Geom &g = ctx->geom;
+    info->centre[0] = g.c[0];
+    info->centre[1] = g.c[1];
+    info->scale = g.s;
+    info->n_tgt = g.nt;
+    info->n_src = g.ns;
+    for (int d = 0; d < 2; ++d) {
+        info->win_lo[d] = g.wlo[d];
+        info->win_ext[d] = g.ext[d];
+        info->tiles[d] = g.ntile[d];
+    }
+    info->near_cells = g.rnear;
+    info->workspace_bytes = make_layout(ctx->plan, g.nt, g.ns).total;
+    return FN_OK;
+}
+
+const char *fn_last_error(const fn_ctx *ctx)
+{
+    if (!ctx) return g_create_err.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,532 @@
+// 2D FFT passes of the fast summation, and the kernel's Fourier table.
+//
+// Every line transform runs in LDS as a Stockham autosort FFT: each thread
+// holds 32 complex values in registers per pass (radix-8 passes, then one
+// radix-4 or radix-2 pass), so a line of length N uses N/32 threads and a
+// 256-thread workgroup holds 8192 complex values whatever N is.  Twiddles come
+// from an FP64-generated table, never from recurrences.  Inverse transforms
+// are conj(FFT(conj(x))) and unnormalized.
+//
+// Grid layout: the real grids hold only the data window (ext_x x ext_y cells,
+// row-major, x contiguous); everything outside it is zero and is supplied as
+// zero padding at load time.  Because sources and targets share the window
+// origin, the shift phase of the window cancels between forward and inverse
+// transforms and the window can be treated as starting at index 0.
+//
+//   rows_fwd  : real rows -> R2C (two real lines packed in one complex FFT),
+//               keep l_x in [0, n/2]; writes S[f][l_x][y] (y contiguous)
+//   cols      : per l_x: FFT over y (zero-padded to G), multiply by the table
+//               W(|l_x|,|l_y|) = omega b_l / (psi^(l_x/G) psi^(l_y/G))^2 on
+//               |l_y| <= n/2 (zero elsewhere) and by -2 pi i l_y for H_y (or
+//               the adjoint combination), inverse FFT, keep y < ext_y
+//   rows_inv  : C2R of the half spectra (pairs of real outputs share one
+//               complex inverse FFT); H_x = C2R((-2 pi i l_x) T_phi) needs no
+//               column pass of its own because l_x is constant per column
+#include "fn_internal.h"
+
+namespace fn {
+
+namespace {
+
+template <typename C> __device__ __forceinline__ C mk(decltype(C::x) a, decltype(C::x) b)
+{
+    C r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b)
+{
+    return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C> __device__ __forceinline__ C cmi(C a) { return mk<C>(a.y, -a.x); }  // a * (-i)
+template <typename C> __device__ __forceinline__ C conjc(C a) { return mk<C>(a.x, -a.y); }
+
+template <typename C> __device__ __forceinline__ void dft2(C *v)
+{
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename C> __device__ __forceinline__ void dft4(C &x0, C &x1, C &x2, C &x3)
+{
+    C s0 = cadd(x0, x2), s1 = csub(x0, x2), s2 = cadd(x1, x3), s3 = cmi(csub(x1, x3));
+    x0 = cadd(s0, s2);
+    x2 = csub(s0, s2);
+    x1 = cadd(s1, s3);
+    x3 = csub(s1, s3);
+}
+
+template <typename C> __device__ __forceinline__ void dft4v(C *v) { dft4(v[0], v[1], v[2], v[3]); }
+
+template <typename C> __device__ __forceinline__ void dft8(C *v)
+{
+    using R = decltype(C::x);
+    const R h = (R)0.70710678118654752440084436210485;
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    // W^1 = (1 - i)/sqrt2, W^2 = -i, W^3 = (-1 - i)/sqrt2
+    C t1 = mk<C>(h * (o1.x + o1.y), h * (o1.y - o1.x));
+    C t2 = cmi(o2);
+    C t3 = mk<C>(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1);
+    v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2);
+    v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3);
+    v[7] = csub(e3, t3);
+}
+
+template <int RAD, typename C> __device__ __forceinline__ void dftR(C *v)
+{
+    if (RAD == 2) dft2(v);
+    else if (RAD == 4) dft4v(v);
+    else dft8(v);
+}
+
+// One Stockham pass over a line in LDS.  NT threads, each FFT_EPT/RAD butterflies.
+template <int RAD, typename C>
+__device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, const C *__restrict__ tw)
+{
+    constexpr int PER = FFT_EPT / RAD;
+    const int nb = N / RAD;
+    C v[FFT_EPT];
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+        const int j = lt + c * NT;
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[c * RAD + r] = buf[j + r * nb];
+    }
+    __syncthreads();
+    const int stride = N / (L * RAD);
+#pragma unroll
+    for (int c = 0; c < PER; ++c) {
+        const int j = lt + c * NT;
+        const int k = j & (L - 1);
+        if (L > 1) {
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) v[c * RAD + r] = cmul(v[c * RAD + r], tw[r * k * stride]);
+        }
+        dftR<RAD>(&v[c * RAD]);
+        const int o = (j - k) * RAD + k;
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) buf[o + q * L] = v[c * RAD + q];
+    }
+    __syncthreads();
+}
+
+// Forward FFT of one LDS line (in place).  All threads of the block must call it.
+template <typename C>
+__device__ void fft_line(C *buf, int N, int log2N, int lt, int NT, const C *__restrict__ tw)
+{
+    int L = 1, rem = log2N;
+    while (rem >= 3) {
+        fft_pass<8>(buf, N, L, lt, NT, tw);
+        L <<= 3;
+        rem -= 3;
+    }
+    if (rem == 2) fft_pass<4>(buf, N, L, lt, NT, tw);
+    else if (rem == 1) fft_pass<2>(buf, N, L, lt, NT, tw);
+}
+
+template <typename C> __device__ __forceinline__ void conj_line(C *buf, int N, int lt, int NT)
+{
+    for (int e = lt; e < N; e += NT) buf[e].y = -buf[e].y;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- plan kernels
+
+// K_R sampled on the n x n grid (numpy FFT order), as complex FP64.
+__global__ void k_kr_samples(double2 *a, int n, const double *__restrict__ coef, int p, double eps_I,
+                             double eps_B, const double *__restrict__ cB, int ncB)
+{
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    int j1 = (int)(idx / n), j2 = (int)(idx % n);
+    double c1 = j1 < n / 2 ? j1 : j1 - n;
+    double c2 = j2 < n / 2 ? j2 : j2 - n;
+    double r = sqrt(c1 * c1 + c2 * c2) / n;
+    double rB = 0.5 - eps_B, v;
+    if (r < eps_I) {
+        double rho2 = (r / eps_I) * (r / eps_I), acc = 0.0;
+        for (int k = p - 1; k >= 0; --k) acc = acc * rho2 + coef[k];
+        v = acc;
+    } else if (r <= rB) {
+        v = -log(r) * 0.15915494309189533576888376337251436;
+    } else {
+        double t = r > 0.5 ? 1.0 : (r - rB) / eps_B, acc = 0.0;
+        for (int k = ncB - 1; k >= 0; --k) acc = acc * t + cB[k];
+        v = acc;
+    }
+    a[idx] = make_double2(v, 0.0);
+}
+
+// In-place C2C forward FFT of `lines` lines of length N; element e of line q at
+// a[q * dist + e * stride].
+__global__ void __launch_bounds__(256) k_lines64(double2 *a, int N, int log2N, int64_t stride, int64_t dist,
+                                                 int lines, const double2 *__restrict__ tw)
+{
+    extern __shared__ double2 sh64[];
+    const int NT = N / FFT_EPT, per = blockDim.x / NT;
+    const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
+    const int q = blockIdx.x * per + li;
+    double2 *buf = sh64 + (int64_t)li * N;
+    for (int e = lt; e < N; e += NT) buf[e] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
+    __syncthreads();
+    fft_line(buf, N, log2N, lt, NT, tw);
+    if (q < lines)
+        for (int e = lt; e < N; e += NT) a[q * dist + e * stride] = buf[e];
+}
+
+// W[lx * (n/2+1) + ly] = omega(lx) omega(ly) Re(b_l) / (psihat(lx) psihat(ly))^2, lx, ly in [0, n/2].
+// bl holds n^2 * b_l (unnormalized DFT of the samples).
+template <typename R>
+__global__ void k_make_W(const double2 *__restrict__ bl, int n, const double *__restrict__ psihat, R *W)
+{
+    const int nh = n / 2;
+    int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)(nh + 1) * (nh + 1)) return;
+    int lx = (int)(idx / (nh + 1)), ly = (int)(idx % (nh + 1));
+    double b = bl[(int64_t)(lx % n) * n + (ly % n)].x / ((double)n * n);
+    double om = (lx == nh ? 0.5 : 1.0) * (ly == nh ? 0.5 : 1.0);
+    double ph = psihat[lx] * psihat[ly];
+    W[idx] = (R)(om * b / (ph * ph));
+}
+
+// ---------------------------------------------------------------- grid passes
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_rows_fwd(const R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
+                                                  int nfield, cplx<R> *__restrict__ spec, int64_t ldS,
+                                                  int64_t sfstride, int G, int log2G, int nh,
+                                                  const cplx<R> *__restrict__ tw)
+{
+    using C = cplx<R>;
+    extern __shared__ char smem_rf[];
+    C *sh = reinterpret_cast<C *>(smem_rf);
+    const int NT = G / FFT_EPT, per = blockDim.x / NT;
+    const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
+    const int q = blockIdx.x * per + li;
+    C *buf = sh + (int64_t)li * G;
+    // line q: nfield == 1 packs rows 2q, 2q+1; nfield == 2 packs fields 0, 1 of row q
+    int ya, yb;
+    const R *ra, *rb;
+    if (nfield == 1) {
+        ya = 2 * q;
+        yb = 2 * q + 1;
+        ra = ya < Ey ? grid + (int64_t)ya * Ex : nullptr;
+        rb = yb < Ey ? grid + (int64_t)yb * Ex : nullptr;
+    } else {
+        ya = yb = q;
+        ra = q < Ey ? grid + (int64_t)q * Ex : nullptr;
+        rb = q < Ey ? grid + fstride + (int64_t)q * Ex : nullptr;
+    }
+    for (int e = lt; e < G; e += NT) {
+        R a = (ra && e < Ex) ? ra[e] : (R)0;
+        R b = (rb && e < Ex) ? rb[e] : (R)0;
+        buf[e] = mk<C>(a, b);
+    }
+    __syncthreads();
+    fft_line(buf, G, log2G, lt, NT, tw);
+    C *sa = spec;
+    C *sb = (nfield == 1) ? spec : spec + sfstride;
+    for (int l = lt; l <= nh; l += NT) {
+        C z = buf[l], zc = conjc(buf[(G - l) & (G - 1)]);
+        C A = mk<C>((R)0.5 * (z.x + zc.x), (R)0.5 * (z.y + zc.y));
+        C B = mk<C>((R)0.5 * (z.y - zc.y), (R)-0.5 * (z.x - zc.x));
+        if (ra) sa[(int64_t)l * ldS + ya] = A;
+        if (rb) sb[(int64_t)l * ldS + yb] = B;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
+                                              cplx<R> *__restrict__ out, int64_t ofstride, int64_t ldS,
+                                              int Ey, int mode, int G, int log2G, int nh,
+                                              const R *__restrict__ W, const cplx<R> *__restrict__ tw)
+{
+    using C = cplx<R>;
+    extern __shared__ char smem_c[];
+    C *sh = reinterpret_cast<C *>(smem_c);
+    const int NT = G / FFT_EPT, per = blockDim.x / NT;
+    const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
+    const int qx = blockIdx.x * per + li;  // l_x of this line
+    const bool valid = qx <= nh;
+    C *buf = sh + (int64_t)li * G;
+    const R twopi = (R)6.283185307179586476925286766559;
+    C acc[FFT_EPT];
+    const int nin = (mode == COL_ADJ_H) ? 2 : 1;
+    for (int f = 0; f < nin; ++f) {
+        const C *col = spec + f * sfstride + (int64_t)qx * ldS;
+        for (int e = lt; e < G; e += NT) buf[e] = (valid && e < Ey) ? col[e] : mk<C>((R)0, (R)0);
+        __syncthreads();
+        fft_line(buf, G, log2G, lt, NT, tw);
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int k = lt + i * NT;
+            const int ly = k <= G / 2 ? k : k - G;
+            const int aly = ly < 0 ? -ly : ly;
+            C x = buf[k];
+            R w = (valid && aly <= nh) ? W[(int64_t)qx * (nh + 1) + aly] : (R)0;
+            C v = mk<C>(w * x.x, w * x.y);
+            if (mode == COL_ADJ_H) {
+                // (2 pi i l_d) v, l_d = l_x for field 0, l_y for field 1
+                R l = (R)(f == 0 ? qx : ly) * twopi;
+                C t = mk<C>(-l * v.y, l * v.x);
+                acc[i] = (f == 0) ? t : cadd(acc[i], t);
+            } else {
+                acc[i] = v;
+            }
+        }
+        __syncthreads();
+    }
+    const int nout = (mode == COL_PHI_HY) ? 2 : 1;
+    for (int o = 0; o < nout; ++o) {
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int k = lt + i * NT;
+            C v = acc[i];
+            if (o == 1) {  // (-2 pi i l_y) v
+                const int ly = k <= G / 2 ? k : k - G;
+                R l = (R)ly * twopi;
+                v = mk<C>(l * v.y, -l * v.x);
+            }
+            buf[k] = conjc(v);
+        }
+        __syncthreads();
+        fft_line(buf, G, log2G, lt, NT, tw);
+        if (valid) {
+            C *dst = out + o * ofstride + (int64_t)qx * ldS;
+            for (int e = lt; e < Ey; e += NT) dst[e] = conjc(buf[e]);
+        }
+        __syncthreads();
+    }
+}
+
+// Inverse row pass.  Requested real outputs are paired into complex inverse FFTs.
+// Output list entries: src (0 = T_phi/T, 1 = T_Hy), mul (0 none, 1 = -2 pi i l_x),
+// dst field (0 phi, 1 Hx, 2 Hy), row offset (0 or 1).
+struct OutSpec {
+    int n;
+    int src[6], mul[6], dst[6], dr[6];
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_rows_inv(const cplx<R> *__restrict__ T, int64_t tfstride, int64_t ldS,
+                                                  R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
+                                                  OutSpec os, int G, int log2G, int nh,
+                                                  const cplx<R> *__restrict__ tw)
+{
+    using C = cplx<R>;
+    extern __shared__ char smem_ri[];
+    C *sh = reinterpret_cast<C *>(smem_ri);
+    const int NT = G / FFT_EPT, per = blockDim.x / NT;
+    const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
+    const int y0 = 2 * (blockIdx.x * per + li);
+    C *buf = sh + (int64_t)li * G;
+    const R twopi = (R)6.283185307179586476925286766559;
+    for (int pr = 0; pr < os.n; pr += 2) {
+        const bool hasb = pr + 1 < os.n;
+        const int ya = y0 + os.dr[pr], yb = hasb ? y0 + os.dr[pr + 1] : -1;
+        const bool va = ya < Ey, vb = hasb && yb < Ey;
+        const C *ta = T + os.src[pr] * tfstride;
+        const C *tb = hasb ? T + os.src[pr + 1] * tfstride : T;
+        const int ma = os.mul[pr], mb = hasb ? os.mul[pr + 1] : 0;
+        for (int e = lt; e < G; e += NT) {
+            C A = mk<C>((R)0, (R)0), B = mk<C>((R)0, (R)0);
+            int l = -1;
+            bool cj = false;
+            if (e <= nh) l = e;
+            else if (e >= G - nh) { l = G - e; cj = true; }
+            if (l >= 0) {
+                const R mlt = (R)l * twopi;
+                if (va) {
+                    A = ta[(int64_t)l * ldS + ya];
+                    if (ma) A = mk<C>(mlt * A.y, -mlt * A.x);
+                    if (l == 0) A.y = (R)0;
+                    if (cj) A = conjc(A);
+                }
+                if (vb) {
+                    B = tb[(int64_t)l * ldS + yb];
+                    if (mb) B = mk<C>(mlt * B.y, -mlt * B.x);
+                    if (l == 0) B.y = (R)0;
+                    if (cj) B = conjc(B);
+                }
+            }
+            // z = A + i B, conjugated for the inverse-by-forward trick
+            buf[e] = mk<C>(A.x - B.y, -(A.y + B.x));
+        }
+        __syncthreads();
+        fft_line(buf, G, log2G, lt, NT, tw);
+        R *ga = grid + os.dst[pr] * fstride + (int64_t)ya * Ex;
+        R *gb = grid + (hasb ? os.dst[pr + 1] : 0) * fstride + (int64_t)(hasb ? yb : 0) * Ex;
+        for (int e = lt; e < Ex; e += NT) {
+            C z = buf[e];  // conj of the inverse transform: real part a, imag -b
+            if (va) ga[e] = z.x;
+            if (vb) gb[e] = -z.y;
+        }
+        __syncthreads();
+    }
+}
+
+inline int ilog2(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+}  // namespace
+
+hipError_t launch_kr_samples(double2 *a, int n, const double *coef, int p, double eps_I, double eps_B,
+                             const double *cB, int ncB, hipStream_t st)
+{
+    int64_t tot = (int64_t)n * n;
+    k_kr_samples<<<(int)((tot + 255) / 256), 256, 0, st>>>(a, n, coef, p, eps_I, eps_B, cB, ncB);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft2d_c2c64(double2 *a, int n, const double2 *tw, hipStream_t st)
+{
+    const int NT = n / FFT_EPT;
+    const int per = 256 / NT;
+    const size_t lds = (size_t)per * n * sizeof(double2);
+    const int lg = ilog2(n);
+    int nb = (n + per - 1) / per;
+    hipError_t e = hipFuncSetAttribute((const void *)k_lines64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_lines64<<<nb, 256, lds, st>>>(a, n, lg, 1, n, n, tw);  // rows
+    k_lines64<<<nb, 256, lds, st>>>(a, n, lg, n, 1, n, tw);  // columns
+    return hipGetLastError();
+}
+
+hipError_t launch_make_W(const double2 *bl, int n, const double *psihat, int precision, void *W,
+                         hipStream_t st)
+{
+    int64_t tot = (int64_t)(n / 2 + 1) * (n / 2 + 1);
+    int nb = (int)((tot + 255) / 256);
+    if (precision == FN_FP64) k_make_W<double><<<nb, 256, 0, st>>>(bl, n, psihat, (double *)W);
+    else k_make_W<float><<<nb, 256, 0, st>>>(bl, n, psihat, (float *)W);
+    return hipGetLastError();
+}
+
+template <typename R>
+static size_t fft_lds_bytes(int G)
+{
+    const int NT = G / FFT_EPT, per = 256 / NT;
+    return (size_t)per * G * sizeof(cplx<R>);
+}
+
+template <typename R>
+static hipError_t rows_fwd_t(int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey, int nfield,
+                             void *spec, int64_t ldS, int64_t sfstride, const void *tw, hipStream_t st)
+{
+    const int NT = G / FFT_EPT, per = 256 / NT;
+    const int lines = (nfield == 1) ? (Ey + 1) / 2 : Ey;
+    const int nb = (lines + per - 1) / per;
+    hipError_t e = hipFuncSetAttribute((const void *)k_rows_fwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)fft_lds_bytes<R>(G));
+    if (e != hipSuccess) return e;
+    k_rows_fwd<R><<<nb, 256, fft_lds_bytes<R>(G), st>>>((const R *)grid, fstride, Ex, Ey, nfield,
+                                                       (cplx<R> *)spec, ldS, sfstride, G, ilog2(G), nh,
+                                                       (const cplx<R> *)tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_fwd(int precision, int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey,
+                           int nfield, void *spec, int64_t ldS, int64_t sfstride, const void *tw,
+                           hipStream_t st)
+{
+    if (precision == FN_FP64)
+        return rows_fwd_t<double>(G, nh, grid, fstride, Ex, Ey, nfield, spec, ldS, sfstride, tw, st);
+    return rows_fwd_t<float>(G, nh, grid, fstride, Ex, Ey, nfield, spec, ldS, sfstride, tw, st);
+}
+
+template <typename R>
+static hipError_t cols_t(int G, int nh, const void *spec, int64_t sfstride, void *out, int64_t ofstride,
+                         int64_t ldS, int Ey, int mode, const void *W, const void *tw, hipStream_t st)
+{
+    const int NT = G / FFT_EPT, per = 256 / NT;
+    const int nb = (nh + 1 + per - 1) / per;
+    hipError_t e = hipFuncSetAttribute((const void *)k_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)fft_lds_bytes<R>(G));
+    if (e != hipSuccess) return e;
+    k_cols<R><<<nb, 256, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, sfstride, (cplx<R> *)out, ofstride,
+                                                   ldS, Ey, mode, G, ilog2(G), nh, (const R *)W,
+                                                   (const cplx<R> *)tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t sfstride, void *out,
+                       int64_t ofstride, int64_t ldS, int Ey, int mode, const void *W, const void *tw,
+                       hipStream_t st)
+{
+    if (precision == FN_FP64) return cols_t<double>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, W, tw, st);
+    return cols_t<float>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, W, tw, st);
+}
+
+template <typename R>
+static hipError_t rows_inv_t(int G, int nh, const void *T, int64_t tfstride, int64_t ldS, void *grid,
+                             int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h,
+                             const void *tw, hipStream_t st)
+{
+    OutSpec os{};
+    auto add = [&](int src, int mul, int dst, int dr) {
+        os.src[os.n] = src;
+        os.mul[os.n] = mul;
+        os.dst[os.n] = dst;
+        os.dr[os.n] = dr;
+        ++os.n;
+    };
+    if (!fwd) {
+        add(0, 0, 0, 0);
+        add(0, 0, 0, 1);
+    } else {
+        // a complex transform pairs the same field on two rows: fields of very
+        // different magnitude (phi and H) must not share one transform, or the
+        // rounding of the larger one swamps the smaller one
+        if (want_phi && want_h) {
+            add(0, 0, 0, 0); add(0, 0, 0, 1);   // phi_y + i phi_y+1
+            add(0, 1, 1, 0); add(0, 1, 1, 1);   // Hx_y + i Hx_y+1
+            add(1, 0, 2, 0); add(1, 0, 2, 1);   // Hy_y + i Hy_y+1
+        } else if (want_phi) {
+            add(0, 0, 0, 0); add(0, 0, 0, 1);
+        } else {
+            add(0, 1, 1, 0); add(0, 1, 1, 1);
+            add(1, 0, 2, 0); add(1, 0, 2, 1);
+        }
+    }
+    const int NT = G / FFT_EPT, per = 256 / NT;
+    const int lines = (Ey + 1) / 2;
+    const int nb = (lines + per - 1) / per;
+    hipError_t e = hipFuncSetAttribute((const void *)k_rows_inv<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)fft_lds_bytes<R>(G));
+    if (e != hipSuccess) return e;
+    k_rows_inv<R><<<nb, 256, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)T, tfstride, ldS, (R *)grid, fstride,
+                                                        Ex, Ey, os, G, ilog2(G), nh, (const cplx<R> *)tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_inv(int precision, int G, int nh, const void *T, int64_t tfstride, int64_t ldS,
+                           void *grid, int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h,
+                           const void *tw, hipStream_t st)
+{
+    if (precision == FN_FP64)
+        return rows_inv_t<double>(G, nh, T, tfstride, ldS, grid, fstride, Ex, Ey, fwd, want_phi, want_h, tw, st);
+    return rows_inv_t<float>(G, nh, T, tfstride, ldS, grid, fstride, Ex, Ey, fwd, want_phi, want_h, tw, st);
+}
+
+size_t fft_lds_limit(int precision, int G)
+{
+    return precision == FN_FP64 ? fft_lds_bytes<double>(G) : fft_lds_bytes<float>(G);
+}
+
+}  // namespace fn

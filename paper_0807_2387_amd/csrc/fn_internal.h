@@ -1,0 +1,175 @@
+// Internal declarations of the femnfft library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "femnfft.h"
+
+namespace fn {
+
+constexpr int TILE = 32;        // spread / gather tile edge in grid cells
+constexpr int MAXM = 8;         // largest window half-width
+constexpr int MAXP = 12;        // largest regularization degree
+constexpr int FFT_EPT = 32;     // complex elements held per thread in the LDS FFT
+constexpr int MAXG = 8192;      // largest FFT grid
+
+template <typename R> struct cplx_t;
+template <> struct cplx_t<float> { using type = float2; };
+template <> struct cplx_t<double> { using type = double2; };
+template <typename R> using cplx = typename cplx_t<R>::type;
+
+// Host-side plan: everything that depends only on the parameters.
+struct Plan {
+    int G = 0, n = 0, m = 0, p = 0, log2G = 0;
+    int precision = FN_FP32_MIXED;
+    double eps_I = 0, eps_B = 0;
+    double kb_b = 0;                 // Kaiser-Bessel shape b = pi (2 - 1/sigma)
+    double win_norm = 0;             // 1 / (2 pi I0(m b) e^{-m b})
+    double a[MAXP] = {0};            // inner polynomial T_I(r) = sum_k a_k (r/eps_I)^{2k}
+    std::vector<double> cB;          // boundary polynomial in t = (r - r_B)/eps_B
+    std::vector<double> psihat;      // window transform at l/G, l = 0..n/2
+};
+
+// Per-geometry facts (host copy).
+struct Geom {
+    int64_t nt = 0, ns = 0;
+    double c[2] = {0, 0};
+    double s = 0;
+    int32_t wlo[2] = {0, 0};
+    int32_t ext[2] = {0, 0};         // window extent (cells) x, y
+    int32_t ntile[2] = {0, 0};       // TILE tiles per dim
+    int32_t rnear = 0;               // near radius in cells
+};
+
+// Device arrays carved out of the caller's workspace.
+struct Buffers {
+    // plan
+    void *W = nullptr;               // multiplier table [(n/2+1) x (n/2+1)], R
+    void *tw = nullptr;              // FFT twiddles e^{-2 pi i k/G}, k < G, cplx<R>
+    double2 *tw64 = nullptr;         // FP64 twiddles for the plan FFT (length n)
+    // geometry, per point set (0 = targets, 1 = sources), sorted by cell
+    uint32_t *key[2] = {nullptr, nullptr};
+    uint32_t *perm[2] = {nullptr, nullptr};
+    float *fr32[2] = {nullptr, nullptr};   // [2][N] in-cell fractions, FP32
+    double *fr64[2] = {nullptr, nullptr};  // [2][N] in-cell fractions, FP64
+    double *u64[2] = {nullptr, nullptr};   // [2][N] grid coordinates, FP64
+    uint32_t *cstart[2] = {nullptr, nullptr}; // [ncell + 1]
+    double *w = nullptr;             // source weights, sorted
+    // per-evaluation data
+    void *val = nullptr;             // charges s_j = w_j q_j, R, sorted sources
+    double *val64 = nullptr;         // the same in FP64 (near field)
+    void *aval = nullptr;            // adjoint inputs (v or V), R, [2][nt] sorted targets
+    double *aval64 = nullptr;        // the same in FP64
+    double *ptile = nullptr;         // padded tile partial sums, FP64, 2 fields
+    void *grid = nullptr;            // real grids, R, 3 fields x ext^2 (max)
+    void *spec = nullptr;            // half spectra, cplx<R>, 2 fields x (n/2+1) x ldS
+    void *spec2 = nullptr;           // column-pass outputs, cplx<R>, 2 fields
+    double *far = nullptr;           // [3][max(nt, ns)] far-field results, sorted order
+    double *red = nullptr;           // reduction scratch
+    // sort scratch
+    uint32_t *skey = nullptr, *sval = nullptr, *hist = nullptr;
+    double *scratch64 = nullptr;     // plan FFT scratch (n x n complex) aliases grid/spec
+};
+
+struct Layout {
+    size_t total = 0;
+    size_t off_W, off_tw, off_tw64;
+    size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_u64[2], off_cstart[2];
+    size_t off_w, off_val, off_val64, off_aval, off_aval64, off_ptile, off_grid, off_spec, off_spec2, off_far, off_red;
+    size_t off_skey, off_sval, off_hist;
+    int64_t emax = 0;                // bound on the window extent
+    int64_t ldS = 0;                 // leading dimension of the spectra
+};
+
+}  // namespace fn
+
+struct fn_ctx {
+    fn_params prm{};
+    fn::Plan plan;
+    fn::Geom geom;
+    fn::Buffers buf;
+    fn::Layout lay;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t ws_nt = 0, ws_ns = 0;    // sizes the workspace was laid out for
+    bool plan_ready = false;
+    bool geom_ready = false;
+    bool charges_ready = false;
+    std::string err;
+};
+
+namespace fn {
+
+// ---- kernel launchers (defined in the .hip files) ----
+// geometry
+hipError_t launch_bbox(const double *p, int64_t n, double *part, int nblk, hipStream_t st);
+hipError_t launch_maxdist(const double *p, int64_t n, double cx, double cy, double *part, int nblk,
+                          hipStream_t st);
+hipError_t launch_nonfinite(const double *p, int64_t n, double *part, int nblk, hipStream_t st);
+hipError_t launch_prepare(const double *xy, int64_t n, double cx, double cy, double s, int G, int m,
+                          int wlox, int wloy, int extx, int exty, uint32_t *key, uint32_t *idx,
+                          hipStream_t st);
+hipError_t radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, uint32_t *hist,
+                      int64_t n, int keybits, hipStream_t st);  // result in key/val
+hipError_t launch_finish_points(const double *xy, const double *w, int64_t n, const uint32_t *perm,
+                                double cx, double cy, double s, int G, float *fr32, double *fr64,
+                                double *u64, double *wsorted, hipStream_t st);
+hipError_t launch_cellstart(const uint32_t *key, int64_t n, int64_t ncell, uint32_t *cstart,
+                            hipStream_t st);
+// plan
+hipError_t launch_kr_samples(double2 *a, int n, const double *coef, int p, double eps_I, double eps_B,
+                             const double *cB, int ncB, hipStream_t st);
+hipError_t launch_fft2d_c2c64(double2 *a, int n, const double2 *tw, hipStream_t st);
+hipError_t launch_make_W(const double2 *bl, int n, const double *psihat, int precision, void *W,
+                         hipStream_t st);
+// charges / reductions
+hipError_t launch_set_values(const double *q, const double *w, const uint32_t *perm, int64_t n,
+                             int ncomp, int precision, void *val, double *val64, hipStream_t st);
+hipError_t launch_sum(const double *x, int64_t n, double *red, hipStream_t st);  // red[0] = sum
+hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
+// spread / fold / gather
+hipError_t launch_spread(int precision, const Plan &P, const Geom &g, int set, const Buffers &b,
+                         const void *val, int nfield, hipStream_t st);
+hipError_t launch_fold(int precision, const Geom &g, int m, const double *ptile, int nfield, void *grid,
+                       int64_t fstride, hipStream_t st);
+hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, const Buffers &b,
+                         int nfield, int64_t fstride, double *far, int64_t farstride, hipStream_t st);
+// FFT passes
+enum ColMode { COL_PHI = 0, COL_PHI_HY = 1, COL_ADJ_H = 2 };
+hipError_t launch_rows_fwd(int precision, int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey,
+                           int nfield, void *spec, int64_t ldS, int64_t sfstride, const void *tw,
+                           hipStream_t st);
+hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t sfstride, void *out,
+                       int64_t ofstride, int64_t ldS, int Ey, int mode, const void *W, const void *tw,
+                       hipStream_t st);
+hipError_t launch_rows_inv(int precision, int G, int nh, const void *T, int64_t tfstride, int64_t ldS,
+                           void *grid, int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h,
+                           const void *tw, hipStream_t st);
+size_t fft_lds_limit(int precision, int G);
+// near field + final
+struct NearArgs {
+    double eps2g;        // eps_I^2 in grid units^2
+    double ginv;         // 1/G
+    double a[MAXP];      // T_I coefficients
+    int p;
+    int rnear;
+    double scale;        // s
+    double offset;       // (ln s / 2 pi)
+};
+hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, const double *sum_s,
+                           int want_phi, int want_h, double *phi, double *H, hipStream_t st);
+hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int kind,
+                           const double *sum_v, double *u, hipStream_t st);
+
+// host helpers
+double bessel_i0(double x);
+void twiddles(int N, std::vector<double> &re, std::vector<double> &im);
+
+}  // namespace fn

@@ -1,0 +1,375 @@
+// Spreading onto and gathering from the oversampled grid (the paper's
+// "diffusion" of the point data to the regular grid X through a smooth,
+// localized window), with a Kaiser-Bessel window.
+//
+// Window (grid-cell units, normalized by I0(m b)):
+//   psi(t) = (e^{-b t^2/(z + m)} - e^{-b (z + m)}) / (2 pi z I0e(m b)),  z = sqrt(m^2 - t^2), |t| < m
+// which equals sinh(b z) / (pi z I0(m b)); zero for |t| >= m.  A point with grid
+// coordinate u has taps k = floor(u) - m + 1 + a, a = 0..2m-1, at t = u - k.
+//
+// Spread: one workgroup per TILE x TILE tile of base cells.  Every wave owns a
+// private FP64 accumulator for the padded tile (TILE + 2m - 1 cells a side) in
+// LDS; the window products (FP32 or FP64) are added with LDS atomics that only
+// that wave touches, so the summation order is fixed and no global atomics are
+// used.  The wave copies are summed in a fixed order into a per-tile buffer, and
+// fold() adds the (at most four) padded tiles covering each cell.
+//
+// Gather: one workgroup per tile; the padded grid tile of every field is staged
+// in LDS; each thread takes one target: rows of 2m taps are summed in the grid
+// precision, the 2m row sums are accumulated in FP64.
+#include "fn_internal.h"
+
+namespace fn {
+
+namespace {
+
+constexpr int SPREAD_WAVES = 2;
+constexpr int SPREAD_NT = 64 * SPREAD_WAVES;
+
+// z - m is formed as -t^2/(z + m): for the central taps z is close to m and the
+// direct difference would lose most of the FP32 mantissa.
+template <typename R>
+__device__ __forceinline__ R kb_psi(R t, R m, R b, R wnorm)
+{
+    const R t2 = t * t;
+    const R z2 = m * m - t2;
+    if (!(z2 > (R)0)) return (R)0;
+    const R z = sqrt(z2);
+    const R zm = z + m;
+    return (exp(-b * t2 / zm) - exp(-b * zm)) * wnorm / z;
+}
+
+template <typename R> __device__ __forceinline__ R frac_of(const float *f32, const double *f64, int64_t i);
+template <> __device__ __forceinline__ float frac_of<float>(const float *f32, const double *, int64_t i)
+{
+    return f32[i];
+}
+template <> __device__ __forceinline__ double frac_of<double>(const float *, const double *f64, int64_t i)
+{
+    return f64[i];
+}
+
+// rows [y0, y0 + TILE) x cells [x0, x1) of a cell-sorted point set: per-row start and prefix
+struct TileRows {
+    uint32_t start[TILE];
+    uint32_t pre[TILE + 1];
+};
+
+__device__ __forceinline__ void tile_rows(TileRows &tr, const uint32_t *__restrict__ cstart, int Ex, int Ey,
+                                          int x0, int y0)
+{
+    const int x1 = min(x0 + TILE, Ex);
+    if (threadIdx.x < TILE) {
+        const int y = y0 + threadIdx.x;
+        uint32_t s = 0, e = 0;
+        if (y < Ey) {
+            s = cstart[(int64_t)y * Ex + x0];
+            e = cstart[(int64_t)y * Ex + x1];
+        }
+        tr.start[threadIdx.x] = s;
+        tr.pre[threadIdx.x + 1] = e - s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        tr.pre[0] = 0;
+        for (int r = 1; r <= TILE; ++r) tr.pre[r] += tr.pre[r - 1];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int64_t tile_point(const TileRows &tr, uint32_t k)
+{
+    int lo = 0, hi = TILE - 1;  // largest r with pre[r] <= k
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tr.pre[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return (int64_t)tr.start[lo] + (k - tr.pre[lo]);
+}
+
+template <typename R, int M2>
+__global__ void __launch_bounds__(SPREAD_NT) k_spread(const uint32_t *__restrict__ key, const float *__restrict__ fr32,
+                                                      const double *__restrict__ fr64, const R *__restrict__ val,
+                                                      int64_t N, const uint32_t *__restrict__ cstart, int Ex, int Ey,
+                                                      int ntx, int nty, double b, double wnorm, int nfield,
+                                                      double *__restrict__ ptile)
+{
+    constexpr int m = M2 / 2;
+    constexpr int PT = TILE + M2 - 1;
+    constexpr int PT2 = PT * PT;
+    extern __shared__ double acc[];  // [SPREAD_WAVES][nfield][PT2]
+    __shared__ TileRows tr;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int wv = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < SPREAD_WAVES * nfield * PT2; i += SPREAD_NT) acc[i] = 0.0;
+    tile_rows(tr, cstart, Ex, Ey, x0, y0);
+    const uint32_t P = tr.pre[TILE];
+    double *myacc = acc + (int64_t)wv * nfield * PT2;
+    const R rm = (R)m, rb = (R)b, rw = (R)wnorm;
+    for (uint32_t k = threadIdx.x; k < P; k += SPREAD_NT) {
+        const int64_t i = tile_point(tr, k);
+        const uint32_t kk = key[i];
+        const int lx = (int)(kk % (uint32_t)Ex) - x0, ly = (int)(kk / (uint32_t)Ex) - y0;
+        const R fx = frac_of<R>(fr32, fr64, i), fy = frac_of<R>(fr32, fr64, N + i);
+        R wx[M2], wy[M2];
+#pragma unroll
+        for (int a = 0; a < M2; ++a) {
+            wx[a] = kb_psi<R>(fx + (R)(m - 1 - a), rm, rb, rw);
+            wy[a] = kb_psi<R>(fy + (R)(m - 1 - a), rm, rb, rw);
+        }
+        for (int f = 0; f < nfield; ++f) {
+            const R v = val[(int64_t)f * N + i];
+            double *af = myacc + f * PT2 + ly * PT + lx;
+#pragma unroll
+            for (int bb = 0; bb < M2; ++bb) {
+                const R vy = v * wy[bb];
+#pragma unroll
+                for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)(vy * wx[a]));
+            }
+        }
+    }
+    __syncthreads();
+    const int ntiles = ntx * nty;
+    for (int f = 0; f < nfield; ++f)
+        for (int c = threadIdx.x; c < PT2; c += SPREAD_NT) {
+            double v = acc[f * PT2 + c];
+            for (int w = 1; w < SPREAD_WAVES; ++w) v += acc[((int64_t)w * nfield + f) * PT2 + c];
+            ptile[((int64_t)f * ntiles + tile) * PT2 + c] = v;
+        }
+}
+
+template <typename R>
+__global__ void k_fold(const double *__restrict__ ptile, int Ex, int Ey, int ntx, int nty, int PT, int nfield,
+                       R *__restrict__ grid, int64_t fstride)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)Ex * Ey) return;
+    const int X = (int)(idx % Ex), Y = (int)(idx / Ex);
+    const int tx = X / TILE, ty = Y / TILE, lx = X % TILE, ly = Y % TILE;
+    const int64_t ntiles = (int64_t)ntx * nty, PT2 = (int64_t)PT * PT;
+    for (int f = 0; f < nfield; ++f) {
+        const double *pf = ptile + f * ntiles * PT2;
+        double v = pf[((int64_t)ty * ntx + tx) * PT2 + ly * PT + lx];
+        const bool left = tx > 0 && lx + TILE < PT, down = ty > 0 && ly + TILE < PT;
+        if (left) v += pf[((int64_t)ty * ntx + tx - 1) * PT2 + ly * PT + lx + TILE];
+        if (down) v += pf[((int64_t)(ty - 1) * ntx + tx) * PT2 + (ly + TILE) * PT + lx];
+        if (left && down) v += pf[((int64_t)(ty - 1) * ntx + tx - 1) * PT2 + (ly + TILE) * PT + lx + TILE];
+        grid[f * fstride + idx] = (R)v;
+    }
+}
+
+template <typename R, int M2>
+__global__ void __launch_bounds__(256) k_gather(const uint32_t *__restrict__ key, const float *__restrict__ fr32,
+                                                const double *__restrict__ fr64, int64_t N,
+                                                const uint32_t *__restrict__ cstart, int Ex, int Ey, int ntx,
+                                                double b, double wnorm, const R *__restrict__ grid,
+                                                int64_t fstride, int nfield, double *__restrict__ far,
+                                                int64_t farstride)
+{
+    constexpr int m = M2 / 2;
+    constexpr int PT = TILE + M2 - 1;
+    constexpr int PT2 = PT * PT;
+    extern __shared__ char smem_g[];
+    R *L = reinterpret_cast<R *>(smem_g);  // [nfield][PT2]
+    __shared__ TileRows tr;
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    tile_rows(tr, cstart, Ex, Ey, x0, y0);
+    const uint32_t P = tr.pre[TILE];
+    if (P == 0) return;  // uniform across the block
+    for (int f = 0; f < nfield; ++f)
+        for (int c = threadIdx.x; c < PT2; c += blockDim.x) {
+            const int X = x0 + c % PT, Y = y0 + c / PT;
+            L[f * PT2 + c] = (X < Ex && Y < Ey) ? grid[f * fstride + (int64_t)Y * Ex + X] : (R)0;
+        }
+    __syncthreads();
+    const R rm = (R)m, rb = (R)b, rw = (R)wnorm;
+    for (uint32_t k = threadIdx.x; k < P; k += blockDim.x) {
+        const int64_t i = tile_point(tr, k);
+        const uint32_t kk = key[i];
+        const int lx = (int)(kk % (uint32_t)Ex) - x0, ly = (int)(kk / (uint32_t)Ex) - y0;
+        const R fx = frac_of<R>(fr32, fr64, i), fy = frac_of<R>(fr32, fr64, N + i);
+        R wx[M2], wy[M2];
+#pragma unroll
+        for (int a = 0; a < M2; ++a) {
+            wx[a] = kb_psi<R>(fx + (R)(m - 1 - a), rm, rb, rw);
+            wy[a] = kb_psi<R>(fy + (R)(m - 1 - a), rm, rb, rw);
+        }
+        for (int f = 0; f < nfield; ++f) {
+            const R *lf = L + f * PT2 + ly * PT + lx;
+            double acc = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < M2; ++bb) {
+                R rs = (R)0;
+#pragma unroll
+                for (int a = 0; a < M2; ++a) rs += wx[a] * lf[bb * PT + a];
+                acc += (double)wy[bb] * (double)rs;
+            }
+            far[(int64_t)f * farstride + i] = acc;
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_set_values(const double *__restrict__ q, const double *__restrict__ w,
+                             const uint32_t *__restrict__ perm, int64_t n, int ncomp, R *__restrict__ val,
+                             double *__restrict__ val64)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t i = perm[k];
+    const double wk = w ? w[k] : 1.0;
+    for (int c = 0; c < ncomp; ++c) {
+        const double v = wk * q[i * ncomp + c];
+        val[c * n + k] = (R)v;
+        val64[c * n + k] = v;
+    }
+}
+
+constexpr int SUMB = 256;
+__global__ void __launch_bounds__(SUMB) k_sum_partial(const double *__restrict__ x, int64_t n,
+                                                      double *__restrict__ part)
+{
+    __shared__ double sh[SUMB];
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)SUMB + threadIdx.x; i < n; i += (int64_t)gridDim.x * SUMB) v += x[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = SUMB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <typename R, int M2>
+hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
+                    hipStream_t st)
+{
+    constexpr int PT = TILE + M2 - 1;
+    const int ntiles = g.ntile[0] * g.ntile[1];
+    const size_t lds = (size_t)SPREAD_WAVES * nfield * PT * PT * sizeof(double);
+    const int64_t N = set ? g.ns : g.nt;
+    auto kern = k_spread<R, M2>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    kern<<<ntiles, SPREAD_NT, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], (const R *)val, N,
+                                         b.cstart[set], g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], P.kb_b,
+                                         P.win_norm, nfield, b.ptile);
+    return hipGetLastError();
+}
+
+template <typename R, int M2>
+hipError_t gather_t(const Plan &P, const Geom &g, int set, const Buffers &b, int nfield, int64_t fstride,
+                    double *far, int64_t farstride, hipStream_t st)
+{
+    constexpr int PT = TILE + M2 - 1;
+    const int ntiles = g.ntile[0] * g.ntile[1];
+    const size_t lds = (size_t)nfield * PT * PT * sizeof(R);
+    const int64_t N = set ? g.ns : g.nt;
+    k_gather<R, M2><<<ntiles, 256, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], N, b.cstart[set], g.ext[0],
+                                             g.ext[1], g.ntile[0], P.kb_b, P.win_norm, (const R *)b.grid,
+                                             fstride, nfield, far, farstride);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t spread_m(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
+                    hipStream_t st)
+{
+    switch (P.m) {
+    case 2: return spread_t<R, 4>(P, g, set, b, val, nfield, st);
+    case 3: return spread_t<R, 6>(P, g, set, b, val, nfield, st);
+    case 4: return spread_t<R, 8>(P, g, set, b, val, nfield, st);
+    case 5: return spread_t<R, 10>(P, g, set, b, val, nfield, st);
+    case 6: return spread_t<R, 12>(P, g, set, b, val, nfield, st);
+    case 7: return spread_t<R, 14>(P, g, set, b, val, nfield, st);
+    case 8: return spread_t<R, 16>(P, g, set, b, val, nfield, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t gather_m(const Plan &P, const Geom &g, int set, const Buffers &b, int nfield, int64_t fstride,
+                    double *far, int64_t farstride, hipStream_t st)
+{
+    switch (P.m) {
+    case 2: return gather_t<R, 4>(P, g, set, b, nfield, fstride, far, farstride, st);
+    case 3: return gather_t<R, 6>(P, g, set, b, nfield, fstride, far, farstride, st);
+    case 4: return gather_t<R, 8>(P, g, set, b, nfield, fstride, far, farstride, st);
+    case 5: return gather_t<R, 10>(P, g, set, b, nfield, fstride, far, farstride, st);
+    case 6: return gather_t<R, 12>(P, g, set, b, nfield, fstride, far, farstride, st);
+    case 7: return gather_t<R, 14>(P, g, set, b, nfield, fstride, far, farstride, st);
+    case 8: return gather_t<R, 16>(P, g, set, b, nfield, fstride, far, farstride, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_spread(int precision, const Plan &P, const Geom &g, int set, const Buffers &b, const void *val,
+                         int nfield, hipStream_t st)
+{
+    return precision == FN_FP64 ? spread_m<double>(P, g, set, b, val, nfield, st)
+                                : spread_m<float>(P, g, set, b, val, nfield, st);
+}
+
+hipError_t launch_fold(int precision, const Geom &g, int m, const double *ptile, int nfield, void *grid,
+                       int64_t fstride, hipStream_t st)
+{
+    const int64_t tot = (int64_t)g.ext[0] * g.ext[1];
+    const int nb = (int)((tot + 255) / 256);
+    const int PT = TILE + 2 * m - 1;
+    if (precision == FN_FP64)
+        k_fold<double><<<nb, 256, 0, st>>>(ptile, g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], PT, nfield,
+                                           (double *)grid, fstride);
+    else
+        k_fold<float><<<nb, 256, 0, st>>>(ptile, g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], PT, nfield,
+                                          (float *)grid, fstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, const Buffers &b, int nfield,
+                         int64_t fstride, double *far, int64_t farstride, hipStream_t st)
+{
+    return precision == FN_FP64 ? gather_m<double>(P, g, set, b, nfield, fstride, far, farstride, st)
+                                : gather_m<float>(P, g, set, b, nfield, fstride, far, farstride, st);
+}
+
+hipError_t launch_set_values(const double *q, const double *w, const uint32_t *perm, int64_t n, int ncomp,
+                             int precision, void *val, double *val64, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const int nb = (int)((n + 255) / 256);
+    if (precision == FN_FP64)
+        k_set_values<double><<<nb, 256, 0, st>>>(q, w, perm, n, ncomp, (double *)val, val64);
+    else
+        k_set_values<float><<<nb, 256, 0, st>>>(q, w, perm, n, ncomp, (float *)val, val64);
+    return hipGetLastError();
+}
+
+// red[0] = sum of x (fixed-order tree; red needs 1 + 256 doubles)
+hipError_t launch_sum(const double *x, int64_t n, double *red, hipStream_t st)
+{
+    k_sum_partial<<<256, SUMB, 0, st>>>(x, n, red + 1);
+    k_sum_partial<<<1, SUMB, 0, st>>>(red + 1, 256, red);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(double *x, int64_t n, double v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    k_fill<<<(int)((n + 255) / 256), 256, 0, st>>>(x, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace fn
