@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the FEM-NFFT fast summation, forward + adjoint, on one MI355X.
+
+One step = set_charges(q) + eval(phi, H) + H adjoint(V) over the whole point set
+(every stage of the hot path: spread, FFTs with the kernel multiply, gather,
+FP64 near field and final sum, and the transposed pipeline).  Inputs are
+resident in HBM before the timed region.
+
+Workload (default): rounded square of side 4 (corner radius 1/2), about 2^24
+jittered-lattice targets and 2^24 + 31k sources (cell points with charge
+-div M, boundary Gauss points with M.n), M a unit field whose angle is a sum of
+32 random cosine modes; FP32-mixed path, FFT grid 8192^2, Kaiser-Bessel m = 6,
+regularization degree p = 8, near radius eps_I = 7/4096.
+
+Prints ONE JSON line (rank 0).  `value` = (N_src + N_tgt) / (seconds per step).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP64_VEC_TFLOPS = 78.6
+FP32_VEC_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 24, help="about this many targets (and sources)")
+    ap.add_argument("--grid", type=int, default=8192)
+    ap.add_argument("--m", type=int, default=6)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--c", type=float, default=7.0, help="eps_I = c / (grid/2)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and the sampled accuracy check")
+    ap.add_argument("--samples", type=int, default=256, help="sampled targets/sources for the O1 check")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build evaluates one mesh per device and has no "
+              "multi-GPU path (see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_0807_2387_amd as fn
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    d = synth.rounded_square_cloud(N=args.n, seed=synth.SEED_BASE + 4)
+    y, x, w, q = d["y"], d["x"], d["w"], d["q"]
+    V = (d["h"] ** 2) * d["M_tgt"]          # l_i M_i with the lattice cell area as nodal mass
+    nt, ns = len(y), len(x)
+    log(f"workload: {nt} targets, {ns} sources (synth {time.time() - t0:.1f}s)")
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ty, tx, tw, tq, tV = tt(y), tt(x), tt(w), tt(q), tt(V)
+    eps_I = args.c / (args.grid // 2)
+
+    def run(precision, steps, warmup, profile):
+        S = fn.Solver(grid=args.grid, m=args.m, p=args.p, eps_I=eps_I, precision=precision)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        S.set_geometry(ty, tx, tw)
+        torch.cuda.synchronize()
+        t_geom = time.perf_counter() - g0
+        phi = torch.empty(nt, dtype=torch.float64, device=dev)
+        H = torch.empty(nt, 2, dtype=torch.float64, device=dev)
+        u = torch.empty(ns, dtype=torch.float64, device=dev)
+
+        def step():
+            S.set_charges(tq)
+            S.eval(out_phi=phi, out_H=H)
+            S.adjoint_H(tV, out=u)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if profile:
+            S.set_profiling(True)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - a
+        prof = S.profile() if profile else None
+        if profile:
+            S.set_profiling(False)
+        info = S.info()
+        return dict(sec=el / steps, t_geom=t_geom, prof=prof, info=info, phi=phi, H=H, u=u, S=S)
+
+    r = run(fn.FN_FP32_MIXED, args.steps, args.warmup, True)
+    ms = r["sec"] * 1e3
+    value = (nt + ns) / r["sec"]
+    log(f"FP32-mixed: {ms:.3f} ms/step, {value:.4e} points/s, set_geometry {r['t_geom'] * 1e3:.1f} ms")
+    stages = {k: v[0] / max(args.steps, 1) for k, v in r["prof"].items() if v[1]}
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]):
+        log(f"  {k:12s} {v:9.3f} ms/step")
+
+    # dominant kernel and its roofline
+    dom = max(stages, key=stages.get)
+    dom_ms = stages[dom]
+    calls = r["prof"][dom][1] / max(args.steps, 1)
+    roof = roofline(dom, dom_ms / calls, calls, args, r["info"], nt, ns)
+
+    out = {
+        "metric": "source+target points/s for forward+adjoint fast summation at <=1e-6 rel L2 vs FP64",
+        "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "rounded square side 4, jittered lattice, 32-mode smooth M",
+                   "n_tgt": nt, "n_src": ns, "grid": args.grid, "m": args.m, "p": args.p,
+                   "eps_I": eps_I, "precision": "fp32_mixed", "parallelism": "single_gpu"},
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "set_geometry_ms": r["t_geom"] * 1e3,
+        "roofline": roof,
+    }
+
+    if not args.no_cpu:
+        err, cpu = accuracy_and_cpu(d, r, args, nt, ns)
+        out["rel_l2_vs_fp64_oracle"] = err
+        out["cpu_baseline"] = cpu
+    else:
+        out["cpu_baseline"] = None
+
+    phi32, H32, u32 = r["phi"], r["H"], r["u"]
+    del r
+    if not args.no_fp64:
+        torch.cuda.empty_cache()
+        f = run(fn.FN_FP64, max(2, args.steps // 3), 1, False)
+        out["fp64_path"] = {"ms_per_step": f["sec"] * 1e3, "points_per_s": (nt + ns) / f["sec"],
+                            "speedup_of_fp32_mixed": f["sec"] / (ms * 1e-3)}
+        rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        out["fp32_vs_fp64_path_rel_l2"] = {"phi": rel(phi32, f["phi"]), "H": rel(H32, f["H"]),
+                                           "HT": rel(u32, f["u"])}
+        del f
+    print(json.dumps(out), flush=True)
+
+
+def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
+    """Roofline of the dominant stage; the work model per stage is stated in the design doc."""
+    G, m = args.grid, args.m
+    ex, ey = info["win_ext"]
+    cells = ex * ey
+    W2 = (2 * m) ** 2
+    sec = ms_per_launch * 1e-3
+    nh = G // 4
+    if stage in ("near", "a_near"):
+        return None  # filled by near_roofline once the pair count is known
+    if stage in ("spread", "a_spread"):
+        npt, nf = (ns, 1) if stage == "spread" else (nt, 2)
+        byts = npt * (12 + 4 * nf) + cells * 4 * nf
+    elif stage in ("gather", "a_gather"):
+        npt, nf = (nt, 3) if stage == "gather" else (ns, 1)
+        byts = npt * (12 + 8 * nf) + cells * 4 * nf
+    elif stage in ("rows_fwd", "a_rows_fwd"):
+        nf = 1 if stage == "rows_fwd" else 2
+        byts = nf * (cells * 4 + (nh + 1) * ey * 8)
+    elif stage in ("cols", "a_cols"):
+        nin, nout = (1, 2) if stage == "cols" else (2, 1)
+        byts = (nin + nout) * (nh + 1) * ey * 8
+    elif stage in ("rows_inv", "a_rows_inv"):
+        nin, nout = (2, 3) if stage == "rows_inv" else (1, 1)
+        byts = nin * (nh + 1) * ey * 8 + nout * cells * 4
+    else:
+        byts = (nt + ns) * 16
+    ach = byts / sec / 1e9
+    return {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "ms_per_launch": ms_per_launch,
+            "algorithmic_bytes_per_launch": byts}
+
+
+def accuracy_and_cpu(d, r, args, nt, ns):
+    """Sampled check against the FP64 direct-sum oracle, and the oracle's own rate."""
+    from oracle import direct
+    y, x, w, q = d["y"], d["x"], d["w"], d["q"]
+    V = (d["h"] ** 2) * d["M_tgt"]
+    rng = np.random.default_rng(12345)
+    it = np.sort(rng.choice(nt, args.samples, replace=False))
+    js = np.sort(rng.choice(ns, args.samples, replace=False))
+    a = time.perf_counter()
+    phi1, H1 = direct.forward(y[it], x, w, q)
+    t_f = time.perf_counter() - a
+    a = time.perf_counter()
+    u1 = direct.adjoint(y, x[js], w[js], V=V)
+    t_a = time.perf_counter() - a
+    phi, H, u = r["phi"].cpu().numpy()[it], r["H"].cpu().numpy()[it], r["u"].cpu().numpy()[js]
+    rel = lambda a_, b_: float(np.linalg.norm(a_ - b_) / np.linalg.norm(b_))
+    err = {"phi": rel(phi, phi1), "H": rel(H, H1), "HT": rel(u, u1), "samples": args.samples}
+    # whole-job CPU time extrapolated linearly from the sample (the direct sum is exactly O(N_t N_s))
+    t_full = t_f * nt / len(it) + t_a * ns / len(js)
+    cpu = {"value": (nt + ns) / t_full, "unit": "points/s", "cores": direct.threads(), "kind": "oracle",
+           "sample": f"O1 direct FP64 sum for {len(it)} targets x {ns} sources (phi, H) and "
+                     f"{len(js)} sources x {nt} targets (H adjoint), extrapolated linearly; "
+                     f"{t_f + t_a:.1f} s of CPU work"}
+    log(f"vs O1 (sampled): {err}; CPU oracle {cpu['value']:.3e} points/s on {cpu['cores']} threads")
+    return err, cpu
+
+
+if __name__ == "__main__":
+    main()

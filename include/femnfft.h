@@ -152,6 +152,28 @@ int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u);
 
 int fn_get_info(const fn_ctx *ctx, fn_info *info);
 
+/* Stage timing with HIP events recorded on the context's stream around every
+ * kernel stage of fn_set_charges / fn_eval* / fn_eval_*_adjoint.
+ * fn_set_profiling(ctx, 1) starts recording (and clears the totals);
+ * fn_get_profile waits for the recorded events, adds their elapsed times to
+ * the totals and copies them out (host struct); recording continues until
+ * fn_set_profiling(ctx, 0).  At most 8192 stages are recorded between two
+ * fn_get_profile calls (later ones are dropped and counted in `dropped`). */
+enum {
+    FN_ST_CHARGES = 0, FN_ST_SPREAD, FN_ST_FOLD, FN_ST_ROWS_FWD, FN_ST_COLS, FN_ST_ROWS_INV,
+    FN_ST_GATHER, FN_ST_NEAR,
+    FN_ST_A_VALUES, FN_ST_A_SPREAD, FN_ST_A_FOLD, FN_ST_A_ROWS_FWD, FN_ST_A_COLS, FN_ST_A_ROWS_INV,
+    FN_ST_A_GATHER, FN_ST_A_NEAR,
+    FN_NUM_STAGES
+};
+typedef struct fn_profile {
+    double ms[FN_NUM_STAGES];     /* summed event time per stage */
+    int64_t count[FN_NUM_STAGES]; /* launches recorded per stage */
+    int64_t dropped;
+} fn_profile;
+int fn_set_profiling(fn_ctx *ctx, int enable);
+int fn_get_profile(fn_ctx *ctx, fn_profile *out);
+
 /* Message of the last error on this context (or of the last failed
  * fn_create when ctx is NULL).  Valid until the next call on the context. */
 const char *fn_last_error(const fn_ctx *ctx);

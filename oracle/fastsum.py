@@ -31,9 +31,12 @@ near-field correction).  This module takes those steps one by one:
                     for the gradient components.
   S5  inverse FFT   g'_k = sum_l f^_l e^{2 pi i l.k/G}.
   S6  gather        f(y_i) = sum_k g'_k psi(G y_i1 - k1) psi(G y_i2 - k2).
-  S7  near field    for |y_i - x_j| < eps_I add s_j (K - T_I)(r), or -s_j T_I(0)
-                    at r = 0; H adds -s_j grad(K - T_I).  Then
+  S7  near field    for |y_i - x_j| < eps_I add s_j (K - T_I)(r); H adds
+                    -s_j grad(K - T_I).  Then
                     phi = far + near + (ln s / 2pi) sum_j s_j,  H = s (far + near).
+                    A pair at r = 0 is not part of the exact sum: it removes its far
+                    value T_I(0) and its share ln(s)/2pi of the offset, i.e. adds
+                    -s_j (T_I(0) + ln(s)/2pi).
   S8  adjoint       the exact transpose of S2..S7 with respect to the charges.
 
 Every library call is a plain primitive (numpy FFT, scipy sparse matvec for the
@@ -287,7 +290,7 @@ class FastSum:
         s_src = self.w * np.asarray(q, np.float64)
         phi, H = self.far_forward(s_src)
         sj = s_src[self.nj]
-        kphi = np.where(self.zero, -self.a[0], self.kphi)
+        kphi = np.where(self.zero, -(self.a[0] + np.log(self.s) / TWO_PI), self.kphi)
         kf = np.where(self.zero, 0.0, self.kf)
         nt = len(self.y)
         phi = phi + np.bincount(self.ni, weights=sj * kphi, minlength=nt)
@@ -314,7 +317,7 @@ class FastSum:
         v = np.asarray(v, np.float64)
         spec = self.W * np.fft.fft2(self._grid(self.By, v))
         u = self.Bx.T @ self._back(spec)
-        kphi = np.where(self.zero, -self.a[0], self.kphi)
+        kphi = np.where(self.zero, -(self.a[0] + np.log(self.s) / TWO_PI), self.kphi)
         u = u + np.bincount(self.nj, weights=v[self.ni] * kphi, minlength=len(self.x))
         u = u + np.log(self.s) / TWO_PI * v.sum()
         return self.w * u

@@ -125,6 +125,15 @@ class Solver:
         self._check(_lib.lib().fn_eval_phi_adjoint(self._ctx, _dev_ptr(v, "v"), _dev_ptr(u, "u")))
         return u
 
+    def set_profiling(self, enable=True):
+        self._check(_lib.lib().fn_set_profiling(self._ctx, int(bool(enable))))
+
+    def profile(self):
+        """Per-stage event time (ms) and launch counts since profiling was enabled."""
+        pr = _lib.Profile()
+        self._check(_lib.lib().fn_get_profile(self._ctx, ctypes.byref(pr)))
+        return {name: (pr.ms[i], pr.count[i]) for i, name in enumerate(_lib.STAGES)}
+
     def info(self):
         i = _lib.Info()
         self._check(_lib.lib().fn_get_info(self._ctx, ctypes.byref(i)))

@@ -21,7 +21,11 @@ SYMBOLS = (
     "fn_params_default", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
     "fn_set_geometry", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
     "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_get_info", "fn_last_error",
+    "fn_set_profiling", "fn_get_profile",
 )
+
+STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather", "near",
+          "a_values", "a_spread", "a_fold", "a_rows_fwd", "a_cols", "a_rows_inv", "a_gather", "a_near")
 
 
 class Params(ctypes.Structure):
@@ -36,6 +40,10 @@ class Info(ctypes.Structure):
                 ("win_lo", ctypes.c_int32 * 2), ("win_ext", ctypes.c_int32 * 2),
                 ("tiles", ctypes.c_int32 * 2), ("near_cells", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("count", ctypes.c_int64 * 16), ("dropped", ctypes.c_int64)]
 
 
 class FemNfftError(RuntimeError):
@@ -70,6 +78,8 @@ def lib():
         "fn_eval_H_adjoint": ([P, P, P], ctypes.c_int),
         "fn_get_info": ([P, ctypes.POINTER(Info)], ctypes.c_int),
         "fn_last_error": ([P], ctypes.c_char_p),
+        "fn_set_profiling": ([P, ctypes.c_int], ctypes.c_int),
+        "fn_get_profile": ([P, ctypes.POINTER(Profile)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -268,6 +268,35 @@ static thread_local std::string g_create_err;
         }                                                                                        \
     } while (0)
 
+// Run `call` (a launcher returning hipError_t) as stage `st`, bracketed by events
+// when profiling is on.
+#define FN_STAGE(ctx, st, call)                                                                  \
+    do {                                                                                         \
+        const int pi_ = prof_begin(ctx, st);                                                     \
+        FN_HIP(ctx, call);                                                                       \
+        prof_end(ctx, pi_);                                                                      \
+    } while (0)
+
+static constexpr size_t PROF_MAX = 8192;
+
+static int prof_begin(fn_ctx *c, int st)
+{
+    if (!c->prof_on) return -1;
+    if (c->prof_next >= PROF_MAX) {
+        c->prof.dropped++;
+        return -1;
+    }
+    const size_t i = c->prof_next++;
+    c->prof_stage[i] = st;
+    hipEventRecord(c->prof_ev[2 * i], c->stream);
+    return (int)i;
+}
+
+static void prof_end(fn_ctx *c, int i)
+{
+    if (i >= 0) hipEventRecord(c->prof_ev[2 * i + 1], c->stream);
+}
+
 static int check_device(fn_ctx *c)
 {
     hipError_t e = hipGetLastError();
@@ -344,6 +373,8 @@ int fn_create(const fn_params *params, void *stream, fn_ctx **out)
 
 int fn_destroy(fn_ctx *ctx)
 {
+    if (ctx)
+        for (auto &e : ctx->prof_ev) hipEventDestroy(e);
     delete ctx;
     return FN_OK;
 }
@@ -550,9 +581,9 @@ int fn_set_charges(fn_ctx *ctx, const double *q)
     int rc = check_device(c);
     if (rc) return rc;
     if (c->geom.ns > 0) {
-        FN_HIP(c, launch_set_values(q, c->buf.w, c->buf.perm[1], c->geom.ns, 1, c->plan.precision, c->buf.val,
-                                    c->buf.val64, c->stream));
-        FN_HIP(c, launch_sum(c->buf.val64, c->geom.ns, c->buf.red + RED_SUMQ, c->stream));
+        FN_STAGE(c, FN_ST_CHARGES, launch_set_values(q, c->buf.w, c->buf.perm[1], c->geom.ns, 1, c->plan.precision,
+                                                     c->buf.val, c->buf.val64, c->stream));
+        FN_STAGE(c, FN_ST_CHARGES, launch_sum(c->buf.val64, c->geom.ns, c->buf.red + RED_SUMQ, c->stream));
     }
     c->charges_ready = true;
     return FN_OK;
@@ -597,16 +628,17 @@ static int eval_impl(fn_ctx *c, double *phi, double *H)
     const int nh = P.n / 2;
     const int64_t sfstride = (int64_t)(nh + 1) * ldS;
     (void)rs;
-    FN_HIP(c, launch_spread(prec, P, g, 1, B, B.val, 1, st));
-    FN_HIP(c, launch_fold(prec, g, P.m, B.ptile, 1, B.grid, fstride, st));
-    FN_HIP(c, launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], 1, B.spec, ldS, sfstride, B.tw, st));
-    FN_HIP(c, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
-                          want_h ? COL_PHI_HY : COL_PHI, B.W, B.tw, st));
-    FN_HIP(c, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0], g.ext[1], 1, want_phi,
-                              want_h, B.tw, st));
-    FN_HIP(c, launch_gather(prec, P, g, 0, B, want_h ? 3 : 1, fstride, B.far, g.nt, st));
+    FN_STAGE(c, FN_ST_SPREAD, launch_spread(prec, P, g, 1, B, B.val, 1, st));
+    FN_STAGE(c, FN_ST_FOLD, launch_fold(prec, g, P.m, B.ptile, 1, B.grid, fstride, st));
+    FN_STAGE(c, FN_ST_ROWS_FWD,
+             launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], 1, B.spec, ldS, sfstride, B.tw, st));
+    FN_STAGE(c, FN_ST_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
+                                        want_h ? COL_PHI_HY : COL_PHI, B.W, B.tw, st));
+    FN_STAGE(c, FN_ST_ROWS_INV, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0],
+                                                g.ext[1], 1, want_phi, want_h, B.tw, st));
+    FN_STAGE(c, FN_ST_GATHER, launch_gather(prec, P, g, 0, B, want_h ? 3 : 1, fstride, B.far, g.nt, st));
     NearArgs na = near_args(c);
-    FN_HIP(c, launch_near_fwd(g, B, na, B.red + RED_SUMQ, want_phi, want_h, phi, H, st));
+    FN_STAGE(c, FN_ST_NEAR, launch_near_fwd(g, B, na, B.red + RED_SUMQ, want_phi, want_h, phi, H, st));
     return FN_OK;
 }
 
@@ -651,18 +683,19 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
     const int nh = P.n / 2;
     const int64_t sfstride = (int64_t)(nh + 1) * ldS;
     const int nf = kind == 0 ? 2 : 1;
-    FN_HIP(c, launch_set_values(in, nullptr, B.perm[0], g.nt, nf, prec, B.aval, B.aval64, st));
-    if (kind == 1) FN_HIP(c, launch_sum(B.aval64, g.nt, B.red + RED_SUMV, st));
-    FN_HIP(c, launch_spread(prec, P, g, 0, B, B.aval, nf, st));
-    FN_HIP(c, launch_fold(prec, g, P.m, B.ptile, nf, B.grid, fstride, st));
-    FN_HIP(c, launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], nf, B.spec, ldS, sfstride, B.tw, st));
-    FN_HIP(c, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
-                          kind == 0 ? COL_ADJ_H : COL_PHI, B.W, B.tw, st));
-    FN_HIP(c, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0], g.ext[1], 0, 1, 0,
-                              B.tw, st));
-    FN_HIP(c, launch_gather(prec, P, g, 1, B, 1, fstride, B.far, g.ns, st));
+    FN_STAGE(c, FN_ST_A_VALUES, launch_set_values(in, nullptr, B.perm[0], g.nt, nf, prec, B.aval, B.aval64, st));
+    if (kind == 1) FN_STAGE(c, FN_ST_A_VALUES, launch_sum(B.aval64, g.nt, B.red + RED_SUMV, st));
+    FN_STAGE(c, FN_ST_A_SPREAD, launch_spread(prec, P, g, 0, B, B.aval, nf, st));
+    FN_STAGE(c, FN_ST_A_FOLD, launch_fold(prec, g, P.m, B.ptile, nf, B.grid, fstride, st));
+    FN_STAGE(c, FN_ST_A_ROWS_FWD,
+             launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], nf, B.spec, ldS, sfstride, B.tw, st));
+    FN_STAGE(c, FN_ST_A_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
+                                          kind == 0 ? COL_ADJ_H : COL_PHI, B.W, B.tw, st));
+    FN_STAGE(c, FN_ST_A_ROWS_INV, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0],
+                                                  g.ext[1], 0, 1, 0, B.tw, st));
+    FN_STAGE(c, FN_ST_A_GATHER, launch_gather(prec, P, g, 1, B, 1, fstride, B.far, g.ns, st));
     NearArgs na = near_args(c);
-    FN_HIP(c, launch_near_adj(g, B, na, kind, B.red + RED_SUMV, u, st));
+    FN_STAGE(c, FN_ST_A_NEAR, launch_near_adj(g, B, na, kind, B.red + RED_SUMV, u, st));
     return FN_OK;
 }
 
@@ -695,6 +728,37 @@ int fn_get_info(const fn_ctx *ctx, fn_info *info)
     }
     info->near_cells = g.rnear;
     info->workspace_bytes = make_layout(ctx->plan, g.nt, g.ns).total;
+    return FN_OK;
+}
+
+int fn_set_profiling(fn_ctx *ctx, int enable)
+{
+    if (!ctx) return FN_E_INVAL;
+    if (enable && ctx->prof_ev.empty()) {
+        ctx->prof_ev.resize(2 * PROF_MAX);
+        ctx->prof_stage.resize(PROF_MAX);
+        for (auto &e : ctx->prof_ev) FN_HIP(ctx, hipEventCreate(&e));
+    }
+    ctx->prof_on = enable != 0;
+    if (enable) {
+        std::memset(&ctx->prof, 0, sizeof(ctx->prof));
+        ctx->prof_next = 0;
+    }
+    return FN_OK;
+}
+
+int fn_get_profile(fn_ctx *ctx, fn_profile *out)
+{
+    if (!ctx || !out) return FN_E_INVAL;
+    for (size_t i = 0; i < ctx->prof_next; ++i) {
+        FN_HIP(ctx, hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
+        float ms = 0.f;
+        FN_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+        ctx->prof.ms[ctx->prof_stage[i]] += ms;
+        ctx->prof.count[ctx->prof_stage[i]] += 1;
+    }
+    ctx->prof_next = 0;
+    *out = ctx->prof;
     return FN_OK;
 }
 

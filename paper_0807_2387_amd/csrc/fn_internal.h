@@ -99,6 +99,12 @@ struct fn_ctx {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     int64_t ws_nt = 0, ws_ns = 0;    // sizes the workspace was laid out for
+    // stage profiling (events recorded on the stream)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;      // pool, 2 per stage record
+    std::vector<int> prof_stage;          // stage of each recorded pair
+    size_t prof_next = 0;
+    fn_profile prof{};
     bool plan_ready = false;
     bool geom_ready = false;
     bool charges_ready = false;

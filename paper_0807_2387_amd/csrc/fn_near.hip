@@ -4,9 +4,9 @@
 // for r >= eps_I and the even polynomial T_I(r) = sum_k a_k (r/eps_I)^{2k}
 // inside (matching K and its first p-1 derivatives at eps_I) -- the paper's
 // "correction in the smoothing zone".  For every pair closer than eps_I this
-// kernel adds s_j (K - T_I)(r) to phi and -s_j grad(K - T_I) to H; a coincident
-// pair adds -s_j T_I(0) (the far field holds K_R(0) = a_0 for it; the exact sum
-// has no self term).  The correction and its first p-1 derivatives vanish at
+// kernel adds s_j (K - T_I)(r) to phi and -s_j grad(K - T_I) to H.  A coincident
+// pair is not part of the exact sum: the far field holds K_R(0) = a_0 for it and
+// the final offset its share ln(s)/2pi, so it adds -s_j (a_0 + ln(s)/2pi).  The correction and its first p-1 derivatives vanish at
 // eps_I, so pairs on the boundary of the zone contribute nothing either way.
 //
 // Coordinates are FP64 grid units u = (s (r - c) + 1/2) G; since G is a power
@@ -17,13 +17,16 @@
 // with T(x) = sum_k a_k x^k, T'(x) = sum_{k>=1} k a_k x^{k-1}.
 //
 // Final: phi = far + near + (ln s / 2pi) sum_j s_j,  H = s (far + near), written
-// to the caller's order.  The adjoint kernels loop over targets near each source
-// and produce u_j = w_j s (far + near) for H^T and u_j = w_j (far + near +
-// (ln s / 2pi) sum_i v_i) for phi^T.
+// to the caller's order.  The transposes loop over targets near each source:
+// u_j = w_j s (far + near) for H^T and u_j = w_j (far + near + (ln s / 2pi)
+// sum_i v_i) for phi^T.
 //
-// One thread per (cell-sorted) output point; the neighbour candidates are the
-// point sets' cells within rnear cells in each direction, read through the
-// cell-start table, so any point density works.
+// Work decomposition: one workgroup per NB x NB block of "home" cells of the
+// output point set.  The points of the other set lying in the block's rows and
+// columns widened by rnear cells are staged into LDS in chunks of at most CAP
+// points (coalesced copies), so any point density works.  Each thread owns up
+// to TPT home points and, for every staged row, loops only over the cells that
+// can hold a point within eps_I of its own cell.  Everything is FP64.
 #include "fn_internal.h"
 
 namespace fn {
@@ -32,131 +35,223 @@ namespace {
 
 constexpr double INV_2PI = 0.15915494309189533576888376337251436;
 constexpr double INV_4PI = 0.07957747154594766788444188168625718;
+constexpr int NB = 16;           // home block edge, cells
+constexpr int NTH = 256;         // threads per block
+constexpr int TPT = 1;           // home points per thread per batch
+constexpr int MAXROWS = NB + 2 * 64 + 2;
 
-struct NearK {
-    double a[MAXP];
-    int p;
+enum { MODE_FWD = 0, MODE_ADJ_H = 1, MODE_ADJ_PHI = 2 };
+
+struct NearSets {
+    // output ("home") set
+    int64_t n_out;
+    const uint32_t *key_out;
+    const double *u_out;          // [2][n_out]
+    const uint32_t *perm_out;
+    const uint32_t *cs_out;
+    const double *far;            // [3][n_out] (fwd) or [n_out] (adjoint)
+    const double *w_out;          // source weights (adjoints)
+    // input set
+    int64_t n_in;
+    const double *u_in;           // [2][n_in]
+    const uint32_t *cs_in;
+    const double *pay;            // fwd: s [n_in]; adj H: V [2][n_in]; adj phi: v [n_in]
+    int Ex, Ey, nbx;
 };
 
-__device__ __forceinline__ void poly2(const NearK &k, double x, double &T, double &dT)
+__device__ __forceinline__ void poly2(const double *a, int p, double x, double &T, double &dT)
 {
-    double t = k.a[k.p - 1], d = 0.0;
-    for (int i = k.p - 1; i >= 1; --i) {
-        d = d * x + (double)i * k.a[i];
-        t = t * x + k.a[i - 1];
+    double t = a[p - 1], d = 0.0;
+    for (int i = p - 1; i >= 1; --i) {
+        d = fma(d, x, (double)i * a[i]);
+        t = fma(t, x, a[i - 1]);
     }
     T = t;
     dT = d;
 }
 
-__global__ void __launch_bounds__(256) k_near_fwd(int64_t nt, const uint32_t *__restrict__ tkey,
-                                                  const double *__restrict__ tu, const uint32_t *__restrict__ tperm,
-                                                  int64_t ns, const double *__restrict__ su,
-                                                  const double *__restrict__ sval,
-                                                  const uint32_t *__restrict__ scstart, int Ex, int Ey,
-                                                  const double *__restrict__ far, int64_t farstride, NearArgs na,
-                                                  const double *__restrict__ sum_s, int want_phi, int want_h,
-                                                  double *__restrict__ phi, double *__restrict__ H)
+// 1/x for a normal positive x: hardware estimate refined by two Newton steps
+// (each step squares the relative error, from ~2^-26 to below 2^-53).
+__device__ __forceinline__ double rcp64(double x)
 {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= nt) return;
-    NearK kk;
-    kk.p = na.p;
-#pragma unroll
-    for (int i = 0; i < MAXP; ++i) kk.a[i] = na.a[i];
-    const uint32_t key = tkey[k];
-    const int cx = (int)(key % (uint32_t)Ex), cy = (int)(key / (uint32_t)Ex);
-    const double ux = tu[k], uy = tu[nt + k];
-    const double inv_e2 = 1.0 / na.eps2g;
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ int find_row(const uint32_t *pre, int nrow, uint32_t k)
+{
+    int lo = 0, hi = nrow - 1;  // largest r with pre[r] <= k
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int MODE, int CAP>
+__global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const double *__restrict__ sum_in,
+                                              int want_phi, int want_h, double *__restrict__ out0,
+                                              double *__restrict__ out1)
+{
+    constexpr int PAY = MODE == MODE_ADJ_H ? 2 : 1;
+    __shared__ double2 sxy[CAP];
+    __shared__ double spay[PAY][CAP];
+    __shared__ uint32_t hpre[NB + 1], hstart[NB];          // home rows
+    __shared__ uint32_t ipre[MAXROWS + 1], istart[MAXROWS]; // input rows
+    __shared__ double sa[MAXP];
+
+    const int Ex = S.Ex, Ey = S.Ey, R = na.rnear;
+    const int bx = blockIdx.x % S.nbx, by = blockIdx.x / S.nbx;
+    const int hx0 = bx * NB, hy0 = by * NB;
+    const int hx1 = min(hx0 + NB, Ex);
+    const int nhrow = min(NB, Ey - hy0);
+    const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NB + R, Ey);
+    const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NB + R, Ex);
+    const int nirow = iy1 - iy0;
+    const int tid = threadIdx.x;
+
+    if (tid < MAXP) sa[tid] = na.a[tid];
+    if (tid < nhrow) {
+        const int64_t rb = (int64_t)(hy0 + tid) * Ex;
+        const uint32_t s0 = S.cs_out[rb + hx0];
+        hstart[tid] = s0;
+        hpre[tid + 1] = S.cs_out[rb + hx1] - s0;
+    }
+    for (int r = tid; r < nirow; r += NTH) {
+        const int64_t rb = (int64_t)(iy0 + r) * Ex;
+        const uint32_t s0 = S.cs_in[rb + ix0];
+        istart[r] = s0;
+        ipre[r + 1] = S.cs_in[rb + ix1] - s0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        hpre[0] = 0;
+        for (int r = 1; r <= nhrow; ++r) hpre[r] += hpre[r - 1];
+        ipre[0] = 0;
+        for (int r = 1; r <= nirow; ++r) ipre[r] += ipre[r - 1];
+    }
+    __syncthreads();
+    const uint32_t nhome = hpre[nhrow], nin = ipre[nirow];
+    if (nhome == 0) return;  // uniform
+
+    const double e2 = na.eps2g, inv_e2 = 1.0 / na.eps2g;
     const double c0 = log(1.0 / na.ginv) * INV_2PI;
-    double pn = 0.0, hx = 0.0, hy = 0.0;
-    const int R = na.rnear;
-    const int ylo = max(cy - R, 0), yhi = min(cy + R, Ey - 1);
-    const int xlo = max(cx - R, 0), xhi = min(cx + R, Ex - 1);
-    for (int row = ylo; row <= yhi; ++row) {
-        const int64_t rb = (int64_t)row * Ex;
-        const uint32_t j0 = scstart[rb + xlo], j1 = scstart[rb + xhi + 1];
-        for (uint32_t j = j0; j < j1; ++j) {
-            const double dx = ux - su[j], dy = uy - su[ns + j];
-            const double r2 = dx * dx + dy * dy;
-            if (r2 >= na.eps2g) continue;
-            const double s = sval[j];
-            if (r2 == 0.0) {
-                pn -= s * kk.a[0];
-                continue;
-            }
-            double T, dT;
-            poly2(kk, r2 * inv_e2, T, dT);
-            if (want_phi) pn += s * (c0 - INV_4PI * log(r2) - T);
-            if (want_h) {
-                const double f = s * (INV_2PI / r2 + 2.0 * dT * inv_e2);
-                hx += f * dx;
-                hy += f * dy;
+    const int p = na.p;
+
+    for (uint32_t hb = 0; hb < nhome; hb += NTH * TPT) {
+        double px[TPT], py[TPT], acc0[TPT], acc1[TPT], acc2[TPT];
+        int cx[TPT], cy[TPT];
+        int64_t gi[TPT];
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+            const uint32_t k = hb + tid + t * NTH;
+            acc0[t] = acc1[t] = acc2[t] = 0.0;
+            gi[t] = -1;
+            cx[t] = cy[t] = 0;
+            px[t] = py[t] = 0.0;
+            if (k < nhome) {
+                const int r = find_row(hpre, nhrow, k);
+                const int64_t i = (int64_t)hstart[r] + (k - hpre[r]);
+                gi[t] = i;
+                const uint32_t key = S.key_out[i];
+                cx[t] = (int)(key % (uint32_t)Ex);
+                cy[t] = (int)(key / (uint32_t)Ex);
+                px[t] = S.u_out[i];
+                py[t] = S.u_out[S.n_out + i];
             }
         }
-    }
-    const int64_t i = tperm[k];
-    if (want_phi) phi[i] = far[k] + pn + na.offset * sum_s[0];
-    if (want_h) {
-        const double G = 1.0 / na.ginv;
-        H[2 * i] = na.scale * (far[farstride + k] + G * hx);
-        H[2 * i + 1] = na.scale * (far[2 * farstride + k] + G * hy);
+        for (uint32_t c_lo = 0; c_lo < nin; c_lo += CAP) {
+            const uint32_t c_hi = min(nin, c_lo + (uint32_t)CAP);
+            __syncthreads();
+            for (uint32_t k = c_lo + tid; k < c_hi; k += NTH) {
+                const int r = find_row(ipre, nirow, k);
+                const int64_t j = (int64_t)istart[r] + (k - ipre[r]);
+                sxy[k - c_lo] = make_double2(S.u_in[j], S.u_in[S.n_in + j]);
+                spay[0][k - c_lo] = S.pay[j];
+                if (PAY == 2) spay[PAY - 1][k - c_lo] = S.pay[S.n_in + j];
+            }
+            __syncthreads();
+            const int r_first = find_row(ipre, nirow, c_lo);
+            const int r_last = find_row(ipre, nirow, c_hi - 1);
+#pragma unroll
+            for (int t = 0; t < TPT; ++t) {
+                if (gi[t] < 0) continue;
+                const int ylo = max(r_first, cy[t] - R - iy0), yhi = min(r_last, cy[t] + R - iy0);
+                for (int r = ylo; r <= yhi; ++r) {
+                    const int ady = abs(iy0 + r - cy[t]);
+                    const double a = (double)max(ady - 1, 0);
+                    const int xr = min(R, (int)(sqrt(max(e2 - a * a, 0.0)) + 1.0));
+                    const int c0c = max(cx[t] - xr, ix0), c1c = min(cx[t] + xr, ix1 - 1);
+                    if (c0c > c1c) continue;
+                    const int64_t rb = (int64_t)(iy0 + r) * Ex;
+                    uint32_t lo = ipre[r] + (S.cs_in[rb + c0c] - istart[r]);
+                    uint32_t hi = ipre[r] + (S.cs_in[rb + c1c + 1] - istart[r]);
+                    lo = max(lo, c_lo) - c_lo;
+                    hi = min(hi, c_hi);
+                    hi = hi > c_lo ? hi - c_lo : 0;
+                    const double tx = px[t], ty = py[t];
+                    double a0 = acc0[t], a1 = acc1[t], a2 = acc2[t];
+                    for (uint32_t jj = lo; jj < hi; ++jj) {
+                        const double2 q = sxy[jj];
+                        // fwd: target minus source; adjoint: target (input) minus source (home)
+                        const double dx = MODE == MODE_FWD ? tx - q.x : q.x - tx;
+                        const double dy = MODE == MODE_FWD ? ty - q.y : q.y - ty;
+                        const double r2 = fma(dx, dx, dy * dy);
+                        if (r2 >= e2) continue;
+                        if (MODE == MODE_ADJ_H) {
+                            if (r2 == 0.0) continue;
+                            double T, dT;
+                            poly2(sa, p, r2 * inv_e2, T, dT);
+                            const double f = fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2));
+                            a0 = fma(f, fma(spay[0][jj], dx, spay[1][jj] * dy), a0);
+                        } else {
+                            const double s = spay[0][jj];
+                            if (r2 == 0.0) {
+                                a0 = fma(-s, sa[0] + na.offset, a0);
+                                continue;
+                            }
+                            double T, dT;
+                            poly2(sa, p, r2 * inv_e2, T, dT);
+                            if (MODE == MODE_ADJ_PHI || want_phi) a0 = fma(s, c0 - INV_4PI * log(r2) - T, a0);
+                            if (MODE == MODE_FWD && want_h) {
+                                const double f = s * fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2));
+                                a1 = fma(f, dx, a1);
+                                a2 = fma(f, dy, a2);
+                            }
+                        }
+                    }
+                    acc0[t] = a0;
+                    acc1[t] = a1;
+                    acc2[t] = a2;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+            const int64_t i = gi[t];
+            if (i < 0) continue;
+            const int64_t o = S.perm_out[i];
+            if (MODE == MODE_FWD) {
+                if (want_phi) out0[o] = S.far[i] + acc0[t] + na.offset * sum_in[0];
+                if (want_h) {
+                    const double G = 1.0 / na.ginv;
+                    out1[2 * o] = na.scale * fma(G, acc1[t], S.far[S.n_out + i]);
+                    out1[2 * o + 1] = na.scale * fma(G, acc2[t], S.far[2 * S.n_out + i]);
+                }
+            } else if (MODE == MODE_ADJ_H) {
+                out0[o] = S.w_out[i] * na.scale * fma(1.0 / na.ginv, acc0[t], S.far[i]);
+            } else {
+                out0[o] = S.w_out[i] * (S.far[i] + acc0[t] + na.offset * sum_in[0]);
+            }
+        }
     }
 }
 
-// kind 0: H^T (V), kind 1: phi^T (v).  Loops over targets near each source.
-__global__ void __launch_bounds__(256) k_near_adj(int64_t ns, const uint32_t *__restrict__ skey,
-                                                  const double *__restrict__ su, const uint32_t *__restrict__ sperm,
-                                                  const double *__restrict__ sw, int64_t nt,
-                                                  const double *__restrict__ tu, const double *__restrict__ tval,
-                                                  const uint32_t *__restrict__ tcstart, int Ex, int Ey,
-                                                  const double *__restrict__ far, NearArgs na, int kind,
-                                                  const double *__restrict__ sum_v, double *__restrict__ u)
-{
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= ns) return;
-    NearK kk;
-    kk.p = na.p;
-#pragma unroll
-    for (int i = 0; i < MAXP; ++i) kk.a[i] = na.a[i];
-    const uint32_t key = skey[j];
-    const int cx = (int)(key % (uint32_t)Ex), cy = (int)(key / (uint32_t)Ex);
-    const double ux = su[j], uy = su[ns + j];
-    const double inv_e2 = 1.0 / na.eps2g;
-    const double c0 = log(1.0 / na.ginv) * INV_2PI;
-    double acc = 0.0;
-    const int R = na.rnear;
-    const int ylo = max(cy - R, 0), yhi = min(cy + R, Ey - 1);
-    const int xlo = max(cx - R, 0), xhi = min(cx + R, Ex - 1);
-    for (int row = ylo; row <= yhi; ++row) {
-        const int64_t rb = (int64_t)row * Ex;
-        const uint32_t i0 = tcstart[rb + xlo], i1 = tcstart[rb + xhi + 1];
-        for (uint32_t i = i0; i < i1; ++i) {
-            const double dx = tu[i] - ux, dy = tu[nt + i] - uy;  // target minus source
-            const double r2 = dx * dx + dy * dy;
-            if (r2 >= na.eps2g) continue;
-            if (kind == 1) {
-                const double v = tval[i];
-                if (r2 == 0.0) {
-                    acc -= v * kk.a[0];
-                    continue;
-                }
-                double T, dT;
-                poly2(kk, r2 * inv_e2, T, dT);
-                acc += v * (c0 - INV_4PI * log(r2) - T);
-            } else {
-                if (r2 == 0.0) continue;
-                double T, dT;
-                poly2(kk, r2 * inv_e2, T, dT);
-                const double f = INV_2PI / r2 + 2.0 * dT * inv_e2;
-                acc += f * (tval[i] * dx + tval[nt + i] * dy);
-            }
-        }
-    }
-    const int64_t o = sperm[j];
-    if (kind == 1) u[o] = sw[j] * (far[j] + acc + na.offset * sum_v[0]);
-    else u[o] = sw[j] * na.scale * (far[j] + acc / na.ginv);
-}
+constexpr int CAP_FWD = 2048;
+constexpr int CAP_ADJ = 2048;
 
 }  // namespace
 
@@ -164,9 +259,23 @@ hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, 
                            int want_phi, int want_h, double *phi, double *H, hipStream_t st)
 {
     if (g.nt == 0) return hipSuccess;
-    const int nb = (int)((g.nt + 255) / 256);
-    k_near_fwd<<<nb, 256, 0, st>>>(g.nt, b.key[0], b.u64[0], b.perm[0], g.ns, b.u64[1], b.val64, b.cstart[1],
-                                   g.ext[0], g.ext[1], b.far, g.nt, na, sum_s, want_phi, want_h, phi, H);
+    NearSets S{};
+    S.n_out = g.nt;
+    S.key_out = b.key[0];
+    S.u_out = b.u64[0];
+    S.perm_out = b.perm[0];
+    S.cs_out = b.cstart[0];
+    S.far = b.far;
+    S.w_out = nullptr;
+    S.n_in = g.ns;
+    S.u_in = b.u64[1];
+    S.cs_in = b.cstart[1];
+    S.pay = b.val64;
+    S.Ex = g.ext[0];
+    S.Ey = g.ext[1];
+    S.nbx = (g.ext[0] + NB - 1) / NB;
+    const int nby = (g.ext[1] + NB - 1) / NB;
+    k_near<MODE_FWD, CAP_FWD><<<S.nbx * nby, NTH, 0, st>>>(S, na, sum_s, want_phi, want_h, phi, H);
     return hipGetLastError();
 }
 
@@ -174,9 +283,26 @@ hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, 
                            double *u, hipStream_t st)
 {
     if (g.ns == 0) return hipSuccess;
-    const int nb = (int)((g.ns + 255) / 256);
-    k_near_adj<<<nb, 256, 0, st>>>(g.ns, b.key[1], b.u64[1], b.perm[1], b.w, g.nt, b.u64[0], b.aval64,
-                                   b.cstart[0], g.ext[0], g.ext[1], b.far, na, kind, sum_v, u);
+    NearSets S{};
+    S.n_out = g.ns;
+    S.key_out = b.key[1];
+    S.u_out = b.u64[1];
+    S.perm_out = b.perm[1];
+    S.cs_out = b.cstart[1];
+    S.far = b.far;
+    S.w_out = b.w;
+    S.n_in = g.nt;
+    S.u_in = b.u64[0];
+    S.cs_in = b.cstart[0];
+    S.pay = b.aval64;
+    S.Ex = g.ext[0];
+    S.Ey = g.ext[1];
+    S.nbx = (g.ext[0] + NB - 1) / NB;
+    const int nby = (g.ext[1] + NB - 1) / NB;
+    if (kind == 0)
+        k_near<MODE_ADJ_H, CAP_ADJ><<<S.nbx * nby, NTH, 0, st>>>(S, na, sum_v, 0, 0, u, nullptr);
+    else
+        k_near<MODE_ADJ_PHI, CAP_ADJ><<<S.nbx * nby, NTH, 0, st>>>(S, na, sum_v, 0, 0, u, nullptr);
     return hipGetLastError();
 }
 

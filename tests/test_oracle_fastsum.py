@@ -1,0 +1,192 @@
+"""Pins of oracle O2 (the fast summation's steps in FP64 numpy) against independent facts:
+the window's Fourier transform by numerical integration, the regularization's derivative
+conditions by high-precision differentiation, the trigonometric interpolation property of
+b_l, a brute-force NDFT, the direct sum O1, single-source exactness and the adjoint identity."""
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate
+
+import synth
+from oracle import direct
+from oracle import fastsum as fs
+from tests.conftest import rel_l2
+
+pytestmark = pytest.mark.cpu
+
+
+@pytest.mark.parametrize("m", [4, 6, 8])
+def test_kaiser_bessel_transform_pair(m):
+    """The untruncated window's transform I0(m sqrt(b^2 - (2 pi xi)^2)) vanishes for |2 pi xi| > b,
+    so the pair can be checked exactly by inverting over that band: psi(t) for |t| < m."""
+    b = np.pi * 1.5
+    xmax = b / (2 * np.pi)
+    for t in (0.0, 0.37, 1.5, 3.2, m - 0.3):
+        num = 2 * integrate.quad(lambda xi: fs.kb_psi_hat(xi, m, b) * np.cos(2 * np.pi * xi * t),
+                                 0, xmax, epsabs=1e-15, epsrel=1e-13, limit=200)[0]
+        assert abs(num - fs.kb_psi(np.array([t]), m, b)[0]) < 1e-12
+    assert np.allclose(fs.kb_psi(np.array([m, -m, m + 0.5]), m, b), 0.0)
+
+
+def test_truncated_window_transform_gap_shrinks_with_m():
+    """Truncating the window to |t| < m makes its transform differ from I0(...) by the window
+    error, which must fall fast with m."""
+    b = np.pi * 1.5
+    gaps = []
+    for m in (4, 6, 8):
+        g = 0.0
+        for xi in (0.0, 0.1, 0.25):
+            num = 2 * integrate.quad(lambda t: fs.kb_psi(np.array([t]), m, b)[0] * np.cos(2 * np.pi * xi * t),
+                                     0, m, epsabs=1e-16, epsrel=1e-14, limit=400)[0]
+            g = max(g, abs(num - fs.kb_psi_hat(xi, m, b)))
+        gaps.append(g)
+    assert gaps[0] < 1e-7 and gaps[1] < gaps[0] / 100 and gaps[2] < 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+def test_inner_polynomial_matches_log_derivatives(p):
+    eps = 0.013
+    a = fs.inner_coeffs(p, eps)
+    mpmath.mp.dps = 40
+    T = lambda r: sum(mpmath.mpf(a[k]) * (r / eps) ** (2 * k) for k in range(p))
+    K = lambda r: -mpmath.log(r) / (2 * mpmath.pi)
+    for q in range(p):
+        dT = mpmath.diff(T, mpmath.mpf(eps), q)
+        dK = mpmath.diff(K, mpmath.mpf(eps), q)
+        assert abs(float(dT - dK)) < 1e-10 * max(1.0, abs(float(dK)))
+
+
+@pytest.mark.parametrize("p", [2, 4, 8])
+def test_boundary_polynomial_conditions(p):
+    """In t = (r - r_B)/eps_B: the q-th t-derivative equals eps_B^q K^(q)(r_B) at t = 0 and
+    vanishes at t = 1 (q >= 1), relative to the size of the terms summed."""
+    epsB = 1.0 / 16
+    c = fs.boundary_coeffs(p, epsB)
+    rB = 0.5 - epsB
+    mpmath.mp.dps = 40
+    P = lambda t: sum(mpmath.mpf(c[k]) * t ** k for k in range(len(c)))
+    K = lambda t: -mpmath.log(rB + epsB * t) / (2 * mpmath.pi)
+    for q in range(p):
+        scale = sum(abs(c[k]) * fs._ff(k, q) for k in range(len(c)))
+        assert abs(float(mpmath.diff(P, 0, q) - mpmath.diff(K, 0, q))) < 1e-13 * max(scale, 1.0)
+    for q in range(1, p):
+        scale = sum(abs(c[k]) * fs._ff(k, q) for k in range(len(c)))
+        assert abs(float(mpmath.diff(P, 1, q))) < 1e-13 * max(scale, 1.0)
+
+
+def test_regularized_kernel_is_continuous_and_equals_log_between():
+    prm = fs.Params(G=128, m=6, p=4, eps_I=4 / 64)
+    r = np.linspace(0.07, 0.43, 50)
+    assert np.allclose(fs.K_R(r, prm), -np.log(r) / (2 * np.pi), rtol=0, atol=1e-15)
+    for r0 in (prm.eps_I, 0.5 - prm.eps_B, 0.5):
+        e = 1e-9
+        lo, hi = fs.K_R(np.array([r0 - e]), prm)[0], fs.K_R(np.array([r0 + e]), prm)[0]
+        assert abs(hi - lo) < 1e-7
+
+
+def test_b_coefficients_interpolate_on_the_bandwidth_grid():
+    """b_l is real and even, and its symmetric trigonometric sum reproduces K_R at the n-grid
+    points (it is the trigonometric interpolant of the sampled kernel)."""
+    prm = fs.Params(G=64, m=4, p=3, eps_I=3 / 32)
+    n = prm.n
+    b = fs.b_coeffs(prm)
+    assert np.allclose(b, b[(-np.arange(n)) % n][:, (-np.arange(n)) % n], atol=1e-17)
+    l = np.arange(-n // 2, n // 2 + 1)
+    om = np.where(np.abs(l) == n // 2, 0.5, 1.0)
+    rng = np.random.default_rng(1)
+    for _ in range(6):
+        j = rng.integers(-n // 2, n // 2, size=2)
+        ph1 = np.exp(2j * np.pi * l * j[0] / n) * om
+        ph2 = np.exp(2j * np.pi * l * j[1] / n) * om
+        val = (ph1[:, None] * ph2[None, :] * b[np.mod(l, n)][:, np.mod(l, n)]).sum().real
+        assert abs(val - fs.K_R(np.array([np.hypot(*j) / n]), prm)[0]) < 1e-13
+
+
+def test_windowed_pipeline_matches_brute_force_ndft():
+    """Spread + FFT + deconvolution + multiply + inverse + gather equals the direct trigonometric
+    sum up to the window error (Kaiser-Bessel bound ~4e-14 at m = 8, sigma = 2)."""
+    prm = fs.Params(G=64, m=8, p=3, eps_I=3 / 32)
+    y, x, w, q = synth.random_cloud(40, 50, 2)
+    F = fs.FastSum(y, x, w, prm)
+    s = w * q
+    phi, H = F.far_forward(s)
+    phi0, H0 = fs.direct_ndft(F.yt, F.xt, s, prm)
+    assert rel_l2(phi, phi0) < 1e-12 and rel_l2(H, H0) < 1e-12
+    prm6 = fs.Params(G=64, m=6, p=3, eps_I=3 / 32)
+    F6 = fs.FastSum(y, x, w, prm6)
+    phi6, H6 = F6.far_forward(s)
+    assert 1e-13 < rel_l2(phi6, phi0) < 1e-8  # window error grows as m shrinks
+
+
+def test_fast_sum_matches_direct_sum():
+    y, x, w, q = synth.random_cloud(500, 700, 3)
+    prm = fs.Params(G=512, m=8, p=10, eps_I=10 / 256)
+    F = fs.FastSum(y, x, w, prm)
+    phi, H = F.forward(q)
+    phi1, H1 = direct.forward(y, x, w, q)
+    assert rel_l2(phi, phi1) < 1e-8 and rel_l2(H, H1) < 1e-7
+    V = np.random.default_rng(4).standard_normal((500, 2))
+    assert rel_l2(F.adjoint_H(V), direct.adjoint(y, x, w, V=V)) < 1e-7
+    v = V[:, 0].copy()
+    assert rel_l2(F.adjoint_phi(v), direct.adjoint(y, x, w, v=v)) < 1e-8
+
+
+def test_single_source_potential_and_field():
+    """One source: phi = -(s/2pi) ln r and H = (s/2pi) d/r^2 exactly, across the near/far seam
+    and including the ln(scale) offset (the sum of charges is not zero here)."""
+    x = np.array([[0.3, -0.2]])
+    w = np.array([0.7])
+    q = np.array([1.3])
+    r = np.concatenate([np.geomspace(1e-6, 2.0, 40)])
+    ang = np.linspace(0, 2 * np.pi, 40, endpoint=False)
+    y = x + np.stack([r * np.cos(ang), r * np.sin(ang)], axis=1)
+    y = np.concatenate([y, x + np.array([[-2.0, 0.0]])])
+    prm = fs.Params(G=512, m=8, p=10, eps_I=10 / 256)
+    F = fs.FastSum(y, x, w, prm)
+    phi, H = F.forward(q)
+    s = w[0] * q[0]
+    d = y - x
+    rr = np.hypot(d[:, 0], d[:, 1])
+    assert np.abs(phi + s / (2 * np.pi) * np.log(rr)).max() < 1e-8
+    Hex = s / (2 * np.pi) * d / rr[:, None] ** 2
+    # the largest relative error sits at the largest separation (next to the boundary zone)
+    assert (np.linalg.norm(H - Hex, axis=1) / np.linalg.norm(Hex, axis=1)).max() < 1e-6
+
+
+def test_coincident_target_and_source_contribute_nothing():
+    y = np.array([[0.0, 0.0], [0.5, 0.1]])
+    x = np.array([[0.0, 0.0], [-0.4, 0.3]])
+    w = np.array([1.0, 1.0])
+    q = np.array([1.0, -0.5])
+    prm = fs.Params(G=512, m=8, p=10, eps_I=10 / 256)
+    F = fs.FastSum(y, x, w, prm)
+    phi, H = F.forward(q)
+    phi1, H1 = direct.forward(y, x, w, q)
+    assert np.abs(phi - phi1).max() < 1e-8 and np.abs(H - H1).max() < 1e-7
+    v = np.array([0.3, -1.1])
+    u1 = direct.adjoint(y, x, w, v=v)
+    assert np.abs(F.adjoint_phi(v) - u1).max() < 1e-8
+
+
+def test_fast_sum_adjoint_identity():
+    y, x, w, q = synth.random_cloud(300, 400, 5)
+    prm = fs.Params(G=128, m=6, p=4, eps_I=4 / 64)
+    F = fs.FastSum(y, x, w, prm)
+    rng = np.random.default_rng(6)
+    V = rng.standard_normal((300, 2))
+    v = rng.standard_normal(300)
+    phi, H = F.forward(q)
+    assert abs(np.sum(H * V) - np.dot(q, F.adjoint_H(V))) < 1e-12 * np.abs(H * V).sum()
+    assert abs(np.dot(phi, v) - np.dot(q, F.adjoint_phi(v))) < 1e-12 * np.abs(phi * v).sum()
+
+
+def test_accuracy_improves_with_regularization_degree_and_radius():
+    """The kernel-truncation error falls with p (at fixed eps_I n) and with eps_I n."""
+    d = synth.rounded_square_cloud(N=4096, seed=5)
+    y, x, w, q = d["y"], d["x"], d["w"], d["q"]
+    phi1, H1 = direct.forward(y, x, w, q)
+    e = {}
+    for p, c in ((2, 4), (4, 4), (6, 6), (8, 8)):
+        phi, H = fs.FastSum(y, x, w, fs.Params(G=256, m=6, p=p, eps_I=c / 128)).forward(q)
+        e[(p, c)] = rel_l2(H, H1)
+    assert e[(2, 4)] > e[(4, 4)] > e[(6, 6)] > e[(8, 8)]
