@@ -187,7 +187,6 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
         L.off_perm[s] = take(N[s] * 4);
         L.off_fr32[s] = take(N[s] * 8);
         L.off_fr64[s] = take(N[s] * 16);
-        L.off_u64[s] = take(N[s] * 16);
         L.off_cstart[s] = take((size_t)(ncell + 1) * 4);
     }
     L.off_w = take(N[1] * 8);
@@ -227,7 +226,6 @@ static void bind_buffers(fn_ctx *c)
         B.perm[s] = reinterpret_cast<uint32_t *>(b + L.off_perm[s]);
         B.fr32[s] = reinterpret_cast<float *>(b + L.off_fr32[s]);
         B.fr64[s] = reinterpret_cast<double *>(b + L.off_fr64[s]);
-        B.u64[s] = reinterpret_cast<double *>(b + L.off_u64[s]);
         B.cstart[s] = reinterpret_cast<uint32_t *>(b + L.off_cstart[s]);
     }
     B.w = reinterpret_cast<double *>(b + L.off_w);
@@ -538,8 +536,8 @@ int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_
     if (!(D > 0.0) || !std::isfinite(D)) FN_SET_ERR(c, FN_E_DOMAIN, "all points coincide");
     g.s = (0.5 - P.eps_B) / D;
     for (int d = 0; d < 2; ++d) {
-        const double umin = (g.s * (lo[d] - g.c[d]) + 0.5) * P.G;
-        const double umax = (g.s * (hi[d] - g.c[d]) + 0.5) * P.G;
+        const double umin = (g.s * (lo[d] - g.c[d])) * P.G + 0.5 * P.G;
+        const double umax = (g.s * (hi[d] - g.c[d])) * P.G + 0.5 * P.G;
         const int wlo = (int)std::floor(umin) - P.m;
         const int whi = (int)std::floor(umax) + P.m + 2;
         g.wlo[d] = wlo;
@@ -561,8 +559,7 @@ int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_
                                      g.ext[1], B.key[s], B.perm[s], c->stream));
             FN_HIP(c, radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, N[s], keybits, c->stream));
             FN_HIP(c, launch_finish_points(xy[s], s == 1 ? src_w : nullptr, N[s], B.perm[s], g.c[0], g.c[1], g.s,
-                                           P.G, B.fr32[s], B.fr64[s], B.u64[s], s == 1 ? B.w : nullptr,
-                                           c->stream));
+                                           P.G, B.fr32[s], B.fr64[s], s == 1 ? B.w : nullptr, c->stream));
         }
         FN_HIP(c, launch_cellstart(B.key[s], N[s], ncell, B.cstart[s], c->stream));
     }
@@ -596,7 +593,10 @@ static NearArgs near_args(const fn_ctx *c)
     const double eg = P.eps_I * P.G;
     na.eps2g = eg * eg;
     na.ginv = 1.0 / P.G;
-    for (int k = 0; k < MAXP; ++k) na.a[k] = P.a[k];
+    for (int k = 0; k < MAXP; ++k) {
+        na.a[k] = P.a[k];
+        na.da[k] = k * P.a[k];
+    }
     na.p = P.p;
     na.rnear = c->geom.rnear;
     na.scale = c->geom.s;

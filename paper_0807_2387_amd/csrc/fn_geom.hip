@@ -3,9 +3,12 @@
 //
 // Torus map: c = bounding-box midpoint, D = 2 max |r - c|, s = (1/2 - eps_B)/D,
 // so every pairwise distance is at most 1/2 - eps_B on the unit torus and the
-// periodized kernel never wraps.  Grid coordinate u = (s (r - c) + 1/2) G;
-// a point's window taps are floor(u) - m + 1 + a, a = 0..2m-1, and its "base
-// cell" (the first tap, relative to the data window origin) is its bin key.
+// periodized kernel never wraps.  With the centred grid coordinate v = s (r - c) G
+// the point sits at grid position u = v + G/2; its window taps are
+// floor(u) - m + 1 + a, a = 0..2m-1, and its "base cell" (the first tap, relative
+// to the data window origin) is its bin key.  Positions are kept as (base cell,
+// in-cell fraction v - floor(v)) so that differences of nearby points are exact
+// to the last bit of the fraction.
 #include "fn_internal.h"
 
 #include <cfloat>
@@ -53,16 +56,19 @@ __global__ void __launch_bounds__(RB) k_reduce(const double *__restrict__ p, int
         for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = sh[k][0];
 }
 
+// Centred grid coordinate v = s (r - c) G (exactly t G for the torus coordinate t,
+// G being a power of two); the point's taps are floor(v) + G/2 - m + 1 + a.
 __global__ void k_prepare(const double *__restrict__ xy, int64_t n, double cx, double cy, double s,
                           double G, int m, int wlox, int wloy, int extx, int exty,
                           uint32_t *__restrict__ key, uint32_t *__restrict__ idx)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double ux = (s * (xy[2 * i] - cx) + 0.5) * G;
-    double uy = (s * (xy[2 * i + 1] - cy) + 0.5) * G;
-    int bx = (int)floor(ux) - m + 1 - wlox;
-    int by = (int)floor(uy) - m + 1 - wloy;
+    const double vx = (s * (xy[2 * i] - cx)) * G;
+    const double vy = (s * (xy[2 * i + 1] - cy)) * G;
+    const int half = (int)(0.5 * G);
+    int bx = (int)floor(vx) + half - m + 1 - wlox;
+    int by = (int)floor(vy) + half - m + 1 - wloy;
     // the window is sized with a margin; clamping only guards against a rounding slip
     bx = min(max(bx, 0), extx - 2 * m);
     by = min(max(by, 0), exty - 2 * m);
@@ -70,23 +76,22 @@ __global__ void k_prepare(const double *__restrict__ xy, int64_t n, double cx, d
     idx[i] = (uint32_t)i;
 }
 
+// In-cell fractions v - floor(v) (exact in FP64), sorted order.
 __global__ void k_finish_points(const double *__restrict__ xy, const double *__restrict__ w, int64_t n,
                                 const uint32_t *__restrict__ perm, double cx, double cy, double s,
                                 double G, float *__restrict__ fr32, double *__restrict__ fr64,
-                                double *__restrict__ u64, double *__restrict__ wsorted)
+                                double *__restrict__ wsorted)
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t i = perm[k];
-    double ux = (s * (xy[2 * (int64_t)i] - cx) + 0.5) * G;
-    double uy = (s * (xy[2 * (int64_t)i + 1] - cy) + 0.5) * G;
-    double fx = ux - floor(ux), fy = uy - floor(uy);
+    const double vx = (s * (xy[2 * (int64_t)i] - cx)) * G;
+    const double vy = (s * (xy[2 * (int64_t)i + 1] - cy)) * G;
+    const double fx = vx - floor(vx), fy = vy - floor(vy);
     fr32[k] = (float)fx;
     fr32[n + k] = (float)fy;
     fr64[k] = fx;
     fr64[n + k] = fy;
-    u64[k] = ux;
-    u64[n + k] = uy;
     if (wsorted) wsorted[k] = w[i];
 }
 
@@ -242,11 +247,11 @@ hipError_t radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *va
 
 hipError_t launch_finish_points(const double *xy, const double *w, int64_t n, const uint32_t *perm,
                                 double cx, double cy, double s, int G, float *fr32, double *fr64,
-                                double *u64, double *wsorted, hipStream_t st)
+                                double *wsorted, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
     int nb = (int)((n + 255) / 256);
-    k_finish_points<<<nb, 256, 0, st>>>(xy, w, n, perm, cx, cy, s, (double)G, fr32, fr64, u64, wsorted);
+    k_finish_points<<<nb, 256, 0, st>>>(xy, w, n, perm, cx, cy, s, (double)G, fr32, fr64, wsorted);
     return hipGetLastError();
 }
 

@@ -57,7 +57,6 @@ struct Buffers {
     uint32_t *perm[2] = {nullptr, nullptr};
     float *fr32[2] = {nullptr, nullptr};   // [2][N] in-cell fractions, FP32
     double *fr64[2] = {nullptr, nullptr};  // [2][N] in-cell fractions, FP64
-    double *u64[2] = {nullptr, nullptr};   // [2][N] grid coordinates, FP64
     uint32_t *cstart[2] = {nullptr, nullptr}; // [ncell + 1]
     double *w = nullptr;             // source weights, sorted
     // per-evaluation data
@@ -79,7 +78,7 @@ struct Buffers {
 struct Layout {
     size_t total = 0;
     size_t off_W, off_tw, off_tw64;
-    size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_u64[2], off_cstart[2];
+    size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_cstart[2];
     size_t off_w, off_val, off_val64, off_aval, off_aval64, off_ptile, off_grid, off_spec, off_spec2, off_far, off_red;
     size_t off_skey, off_sval, off_hist;
     int64_t emax = 0;                // bound on the window extent
@@ -126,7 +125,7 @@ hipError_t radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *va
                       int64_t n, int keybits, hipStream_t st);  // result in key/val
 hipError_t launch_finish_points(const double *xy, const double *w, int64_t n, const uint32_t *perm,
                                 double cx, double cy, double s, int G, float *fr32, double *fr64,
-                                double *u64, double *wsorted, hipStream_t st);
+                                double *wsorted, hipStream_t st);
 hipError_t launch_cellstart(const uint32_t *key, int64_t n, int64_t ncell, uint32_t *cstart,
                             hipStream_t st);
 // plan
@@ -163,7 +162,8 @@ size_t fft_lds_limit(int precision, int G);
 struct NearArgs {
     double eps2g;        // eps_I^2 in grid units^2
     double ginv;         // 1/G
-    double a[MAXP];      // T_I coefficients
+    double a[MAXP];      // T_I coefficients: T(x) = sum_k a_k x^k, x = (r/eps_I)^2
+    double da[MAXP];     // k a_k (coefficients of T')
     int p;
     int rnear;
     double scale;        // s
