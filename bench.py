@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and the sampled accuracy check")
     ap.add_argument("--samples", type=int, default=256, help="sampled targets/sources for the O1 check")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one elementwise kernel over 256 MiB (read and write) before the timed region, "
+                         "as the byte-counter calibration for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -62,8 +65,8 @@ def src_hash(path):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build evaluates one mesh per device and has no "
-              "multi-GPU path (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library evaluates one point set per device and has "
+              "no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
@@ -99,6 +102,11 @@ def main():
 
         for _ in range(warmup):
             step()
+        if args.calib_copy and profile:
+            src = torch.ones(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB
+            dst = torch.empty_like(src)
+            torch.add(src, 1.0, out=dst)
+            del src, dst
         torch.cuda.synchronize()
         if profile:
             S.set_profiling(True)
@@ -162,16 +170,33 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# FP64 flops per interacting pair of the near-field kernels (an FMA counts 2), from the
+# formulas they evaluate, p = regularization degree.  Forward (phi and H): offset 4,
+# r^2 3, rho^2 1, T and T' 4(p-1), ln 34, phi term 4, 1/r^2 8, field factor 4, H sums 4.
+# Adjoint (H^T): offset 4, r^2 3, rho^2 1, T' 2(p-1), 1/r^2 8, factor 3, V.d 3, sum 2.
+def near_flops_per_pair(stage, p):
+    if stage == "near":          # phi and H: offsets, r^2, T and T', ln, 1/r^2, accumulations
+        return 62 + 4 * (p - 1)
+    return 24 + 2 * (p - 1)      # H^T: offsets, r^2, T', 1/r^2, V.d, accumulation
+
+
 def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
-    """Roofline of the dominant stage; the work model per stage is stated in the design doc."""
+    """Roofline of the dominant stage.  Near field: FP64 flops per interacting pair times the
+    pair count, against the FP64 vector peak.  Grid stages: the bytes they must move at least
+    (points' cell, fractions and values once, grid cells once per field), against HBM peak."""
     G, m = args.grid, args.m
     ex, ey = info["win_ext"]
     cells = ex * ey
-    W2 = (2 * m) ** 2
     sec = ms_per_launch * 1e-3
     nh = G // 4
     if stage in ("near", "a_near"):
-        return None  # filled by near_roofline once the pair count is known
+        pairs = info["near_pairs"]
+        fl = near_flops_per_pair(stage, args.p)
+        ach = pairs * fl / sec / 1e12
+        traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1")
+        return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_VEC_TFLOPS, "traffic": traffic, "ms_per_launch": ms_per_launch,
+                "pairs_per_launch": pairs, "fp64_flops_per_pair": fl}
     if stage in ("spread", "a_spread"):
         npt, nf = (ns, 1) if stage == "spread" else (nt, 2)
         byts = npt * (12 + 4 * nf) + cells * 4 * nf
@@ -193,6 +218,22 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
     return {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": None, "ms_per_launch": ms_per_launch,
             "algorithmic_bytes_per_launch": byts}
+
+
+def counter_traffic(kernel_prefix):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source (its sha256 prefix is stored with the numbers)."""
+    path = os.path.join(HERE, "profiles", "counters.json")
+    src = os.path.join(HERE, "paper_0807_2387_amd", "csrc", "fn_near.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("kernels", {}).get(kernel_prefix)
+    if not ent or ent.get("source_sha256_16") != src_hash(src):
+        return None
+    return ent.get("hbm_bytes_per_launch")
 
 
 def accuracy_and_cpu(d, r, args, nt, ns):

@@ -71,7 +71,7 @@ enum {
  *   p         regularization degree: the kernel is replaced near the origin by an
  *             even polynomial matching ln r and its first p-1 derivatives at eps_I
  *             (the paper's "smoothness degree"), 1..12.
- *   eps_I     near-field radius; 0 < eps_I, eps_I * G <= 64.
+ *   eps_I     near-field radius; 0 < eps_I, eps_I * G <= 32.
  *   eps_B     width of the boundary regularization near |x| = 1/2; 0 < eps_B < 1/4.
  *   precision FN_FP64 or FN_FP32_MIXED.
  */
@@ -96,6 +96,7 @@ typedef struct fn_info {
     int32_t tiles[2];       /* spread/gather tiles per dimension */
     int32_t near_cells;     /* near-field radius in grid cells (ceil) */
     size_t workspace_bytes; /* bytes required for (n_tgt, n_src) */
+    int64_t near_pairs;     /* (target, source) pairs closer than eps_I */
 } fn_info;
 
 typedef struct fn_ctx fn_ctx;

@@ -139,4 +139,4 @@ class Solver:
         self._check(_lib.lib().fn_get_info(self._ctx, ctypes.byref(i)))
         return dict(centre=tuple(i.centre), scale=i.scale, n_tgt=i.n_tgt, n_src=i.n_src,
                     win_lo=tuple(i.win_lo), win_ext=tuple(i.win_ext), tiles=tuple(i.tiles),
-                    near_cells=i.near_cells, workspace_bytes=i.workspace_bytes)
+                    near_cells=i.near_cells, workspace_bytes=i.workspace_bytes, near_pairs=i.near_pairs)

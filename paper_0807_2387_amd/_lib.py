@@ -39,7 +39,7 @@ class Info(ctypes.Structure):
                 ("n_tgt", ctypes.c_int64), ("n_src", ctypes.c_int64),
                 ("win_lo", ctypes.c_int32 * 2), ("win_ext", ctypes.c_int32 * 2),
                 ("tiles", ctypes.c_int32 * 2), ("near_cells", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("near_pairs", ctypes.c_int64)]
 
 
 class Profile(ctypes.Structure):

@@ -335,8 +335,8 @@ static int validate_params(const fn_params *p, std::string &err)
     if (p->m < 2 || p->m > MAXM) { err = "m must be in [2, 8]"; return FN_E_INVAL; }
     if (p->p < 1 || p->p > MAXP) { err = "p must be in [1, 12]"; return FN_E_INVAL; }
     if (!(p->eps_B > 0.0) || !(p->eps_B < 0.25)) { err = "eps_B must be in (0, 1/4)"; return FN_E_INVAL; }
-    if (!(p->eps_I > 0.0) || !(p->eps_I * G <= 64.0) || !(p->eps_I < 0.5 - p->eps_B)) {
-        err = "eps_I must be positive, eps_I*grid <= 64 and eps_I < 1/2 - eps_B";
+    if (!(p->eps_I > 0.0) || !(p->eps_I * G <= 32.0) || !(p->eps_I < 0.5 - p->eps_B)) {
+        err = "eps_I must be positive, eps_I*grid <= 32 and eps_I < 1/2 - eps_B";
         return FN_E_INVAL;
     }
     if (p->precision != FN_FP64 && p->precision != FN_FP32_MIXED) { err = "unknown precision"; return FN_E_INVAL; }
@@ -437,6 +437,24 @@ static int build_device_plan(fn_ctx *c)
     FN_HIP(c, hipStreamSynchronize(st));
     c->plan_ready = true;
     return FN_OK;
+}
+
+static NearArgs near_args(const fn_ctx *c)
+{
+    NearArgs na{};
+    const Plan &P = c->plan;
+    const double eg = P.eps_I * P.G;
+    na.eps2g = eg * eg;
+    na.ginv = 1.0 / P.G;
+    for (int k = 0; k < MAXP; ++k) na.a[k] = P.a[k];
+    for (int k = 0; k < 9; ++k) na.lc[k] = 1.0 / (2 * k + 3);
+    na.ln2hi = 0.693147180559945286227;
+    na.ln2lo = 2.319046813846299558e-17;
+    na.p = P.p;
+    na.rnear = c->geom.rnear;
+    na.scale = c->geom.s;
+    na.offset = std::log(c->geom.s) / (2.0 * PI);
+    return na;
 }
 
 static int bbox_of(fn_ctx *c, const double *xy, int64_t n, double out[4], double *nonfin)
@@ -565,6 +583,18 @@ int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_
     }
     FN_HIP(c, hipStreamSynchronize(c->stream));
     c->geom = g;
+    // number of (target, source) pairs closer than eps_I: the near field's unit of work
+    c->geom.near_pairs = 0;
+    if (n_tgt > 0 && n_src > 0) {
+        NearArgs na = near_args(c);
+        double *cnt = B.far;  // one count per source
+        FN_HIP(c, launch_near_adj(c->geom, B, na, 2, B.red + RED_SUMV, cnt, c->stream));
+        FN_HIP(c, launch_sum(cnt, n_src, B.red + RED_SUMV, c->stream));
+        double tot = 0.0;
+        FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        FN_HIP(c, hipStreamSynchronize(c->stream));
+        c->geom.near_pairs = (int64_t)(tot + 0.5);
+    }
     c->geom_ready = true;
     return FN_OK;
 }
@@ -584,24 +614,6 @@ int fn_set_charges(fn_ctx *ctx, const double *q)
     }
     c->charges_ready = true;
     return FN_OK;
-}
-
-static NearArgs near_args(const fn_ctx *c)
-{
-    NearArgs na{};
-    const Plan &P = c->plan;
-    const double eg = P.eps_I * P.G;
-    na.eps2g = eg * eg;
-    na.ginv = 1.0 / P.G;
-    for (int k = 0; k < MAXP; ++k) {
-        na.a[k] = P.a[k];
-        na.da[k] = k * P.a[k];
-    }
-    na.p = P.p;
-    na.rnear = c->geom.rnear;
-    na.scale = c->geom.s;
-    na.offset = std::log(c->geom.s) / (2.0 * PI);
-    return na;
 }
 
 static int eval_impl(fn_ctx *c, double *phi, double *H)
@@ -727,6 +739,7 @@ int fn_get_info(const fn_ctx *ctx, fn_info *info)
         info->tiles[d] = g.ntile[d];
     }
     info->near_cells = g.rnear;
+    info->near_pairs = g.near_pairs;
     info->workspace_bytes = make_layout(ctx->plan, g.nt, g.ns).total;
     return FN_OK;
 }

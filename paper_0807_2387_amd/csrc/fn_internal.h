@@ -44,6 +44,7 @@ struct Geom {
     int32_t ext[2] = {0, 0};         // window extent (cells) x, y
     int32_t ntile[2] = {0, 0};       // TILE tiles per dim
     int32_t rnear = 0;               // near radius in cells
+    int64_t near_pairs = 0;          // pairs closer than eps_I
 };
 
 // Device arrays carved out of the caller's workspace.
@@ -163,7 +164,8 @@ struct NearArgs {
     double eps2g;        // eps_I^2 in grid units^2
     double ginv;         // 1/G
     double a[MAXP];      // T_I coefficients: T(x) = sum_k a_k x^k, x = (r/eps_I)^2
-    double da[MAXP];     // k a_k (coefficients of T')
+    double lc[9];        // 1/(2k+1), k = 1..9 (series of the logarithm)
+    double ln2hi, ln2lo; // ln 2 in two parts
     int p;
     int rnear;
     double scale;        // s

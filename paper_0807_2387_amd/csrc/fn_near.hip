@@ -6,8 +6,9 @@
 // "correction in the smoothing zone".  For every pair closer than eps_I this
 // kernel adds s_j (K - T_I)(r) to phi and -s_j grad(K - T_I) to H.  A coincident
 // pair is not part of the exact sum: the far field holds K_R(0) = a_0 for it and
-// the final offset its share ln(s)/2pi, so it adds -s_j (a_0 + ln(s)/2pi).  The correction and its first p-1 derivatives vanish at
-// eps_I, so pairs on the boundary of the zone contribute nothing either way.
+// the final offset its share ln(s)/2pi, so it adds -s_j (a_0 + ln(s)/2pi).
+// The correction and its first p-1 derivatives vanish at eps_I, so pairs on the
+// boundary of the zone contribute nothing either way.
 //
 // Positions are (integer grid cell, FP64 in-cell fraction); a pair's offset in
 // grid units is d = (c_i - c_j) + (f_i - f_j), exact up to the rounding of the
@@ -25,11 +26,11 @@
 // sum_i v_i) for phi^T.
 //
 // Work decomposition: one workgroup per NB x NB block of "home" cells of the
-// output point set.  The points of the other set lying in the block's rows and
+// output point set; the points of the other set lying in the block's rows and
 // columns widened by rnear cells are staged into LDS in chunks of at most CAP
-// points (coalesced copies), so any point density works.  Each thread owns up
-// to TPT home points and, for every staged row, loops only over the cells that
-// can hold a point within eps_I of its own cell.  Everything is FP64.
+// points (coalesced copies), so any point density works.  Each thread owns one
+// home point at a time and, for every staged row within rnear, loops over the
+// cells within the disk bound of its own cell.  Everything is FP64.
 #include "fn_internal.h"
 
 namespace fn {
@@ -39,11 +40,12 @@ namespace {
 constexpr double INV_2PI = 0.15915494309189533576888376337251436;
 constexpr double INV_4PI = 0.07957747154594766788444188168625718;
 constexpr int NB = 16;           // home block edge, cells
+constexpr int NSEG = NB;         // home row segments per block
 constexpr int NTH = 256;         // threads per block
-constexpr int TPT = 1;           // home points per thread per batch
-constexpr int MAXROWS = NB + 2 * 64 + 2;
+constexpr int MAXRN = 32;        // largest near radius in cells (rows listed per thread: 2 rnear + 1)
+constexpr int MAXROWS = NB + 2 * MAXRN + 2;
 
-enum { MODE_FWD = 0, MODE_ADJ_H = 1, MODE_ADJ_PHI = 2 };
+enum { MODE_FWD_BOTH = 0, MODE_ADJ_H = 1, MODE_ADJ_PHI = 2, MODE_COUNT = 3, MODE_FWD_PHI = 4, MODE_FWD_H = 5 };
 
 struct NearSets {
     // output ("home") set
@@ -63,16 +65,17 @@ struct NearSets {
     int Ex, Ey, nbx;
 };
 
-// T(x) = sum_{k<P} a_k x^k and T'(x) = sum_{k>=1} k a_k x^{k-1}, Horner, unrolled; the
+// T(x) = sum_{k<P} a_k x^k and T'(x) = sum_{k>=1} k a_k x^{k-1} in one Horner sweep
+// (the derivative accumulates the running value: synthetic division); the
 // coefficients are kernel arguments, so they live in scalar registers.
 template <int P>
 __device__ __forceinline__ void poly2(const NearArgs &na, double x, double &T, double &dT)
 {
     double t = na.a[P - 1], d = 0.0;
 #pragma unroll
-    for (int i = P - 1; i >= 1; --i) {
-        d = fma(d, x, na.da[i]);
-        t = fma(t, x, na.a[i - 1]);
+    for (int i = P - 2; i >= 0; --i) {
+        d = (i == P - 2) ? t : fma(d, x, t);
+        t = fma(t, x, na.a[i]);
     }
     T = t;
     dT = d;
@@ -81,10 +84,13 @@ __device__ __forceinline__ void poly2(const NearArgs &na, double x, double &T, d
 template <int P>
 __device__ __forceinline__ double poly_d(const NearArgs &na, double x)
 {
-    double d = 0.0;
+    double t = na.a[P - 1], d = 0.0;
 #pragma unroll
-    for (int i = P - 1; i >= 1; --i) d = fma(d, x, na.da[i]);
-    return d;
+    for (int i = P - 2; i >= 1; --i) {
+        d = (i == P - 2) ? t : fma(d, x, t);
+        t = fma(t, x, na.a[i]);
+    }
+    return P > 2 ? fma(d, x, t) : (P == 2 ? t : 0.0);
 }
 
 // 1/x for a normal positive x: hardware estimate refined by two Newton steps
@@ -99,36 +105,30 @@ __device__ __forceinline__ double rcp64(double x)
 }
 
 // ln x for a normal positive x: x = 2^e m with m in [sqrt(1/2), sqrt(2)),
-// ln m = 2 atanh(f), f = (m - 1)/(m + 1), |f| <= 0.1716, by its series to the
-// f^21 term (truncation below 1e-18 relative); ln 2 is split in two parts.
-__device__ __forceinline__ double ln64(double x)
+// ln m = 2 atanh(f), f = (m - 1)/(m + 1), |f| <= 0.1716, by its series up to
+// f^19 (truncation below 3e-16 absolute); the series coefficients 1/(2k+1) and
+// ln 2 (split in two parts) come in as kernel arguments.
+__device__ __forceinline__ double ln64(double x, const NearArgs &na)
 {
     int e = __builtin_amdgcn_frexp_exp(x);
     double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
-    if (m < 0.70710678118654752440) {
-        m *= 2.0;
-        e -= 1;
-    }
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
     const double f = (m - 1.0) * rcp64(m + 1.0);
     const double z = f * f;
-    double s = 1.0 / 21.0;
-    s = fma(s, z, 1.0 / 19.0);
-    s = fma(s, z, 1.0 / 17.0);
-    s = fma(s, z, 1.0 / 15.0);
-    s = fma(s, z, 1.0 / 13.0);
-    s = fma(s, z, 1.0 / 11.0);
-    s = fma(s, z, 1.0 / 9.0);
-    s = fma(s, z, 1.0 / 7.0);
-    s = fma(s, z, 1.0 / 5.0);
-    s = fma(s, z, 1.0 / 3.0);
-    const double lnm = fma(2.0 * f * z, s, 2.0 * f);
+    double s = na.lc[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) s = fma(s, z, na.lc[k]);
+    const double f2 = f + f;
+    const double lnm = fma(f2 * z, s, f2);
     const double de = (double)e;
-    return fma(de, 0.693147180559945286227, fma(de, 2.319046813846299558e-17, lnm));
+    return fma(de, na.ln2hi, fma(de, na.ln2lo, lnm));
 }
 
-__device__ __forceinline__ int find_row(const uint32_t *pre, int nrow, uint32_t k)
+__device__ __forceinline__ int find_seg(const uint32_t *pre, int nseg, uint32_t k)
 {
-    int lo = 0, hi = nrow - 1;  // largest r with pre[r] <= k
+    int lo = 0, hi = nseg - 1;  // largest s with pre[s] <= k
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (pre[mid] <= k) lo = mid; else hi = mid - 1;
@@ -138,31 +138,38 @@ __device__ __forceinline__ int find_row(const uint32_t *pre, int nrow, uint32_t 
 
 template <int MODE, int CAP, int P>
 __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const double *__restrict__ sum_in,
-                                              int want_phi, int want_h, double *__restrict__ out0,
-                                              double *__restrict__ out1)
+                                              double *__restrict__ out0, double *__restrict__ out1)
 {
+    constexpr bool FWD = MODE == MODE_FWD_BOTH || MODE == MODE_FWD_PHI || MODE == MODE_FWD_H;
+    constexpr bool WANT_PHI = MODE == MODE_FWD_BOTH || MODE == MODE_FWD_PHI || MODE == MODE_ADJ_PHI;
+    constexpr bool WANT_H = MODE == MODE_FWD_BOTH || MODE == MODE_FWD_H;
     constexpr int PAY = MODE == MODE_ADJ_H ? 2 : 1;
     __shared__ double2 sxy[CAP];     // in-cell fractions
     __shared__ uint32_t scell[CAP];  // cell offsets from the region origin, x | y << 16
     __shared__ double spay[PAY][CAP];
-    __shared__ uint32_t hpre[NB + 1], hstart[NB];          // home rows
+    __shared__ uint32_t hpre[NSEG + 1], hstart[NSEG];       // home row segments
     __shared__ uint32_t ipre[MAXROWS + 1], istart[MAXROWS]; // input rows
+    __shared__ int xrad[MAXRN + 2];                         // cell half-width per row offset
 
     const int Ex = S.Ex, Ey = S.Ey, R = na.rnear;
     const int bx = blockIdx.x % S.nbx, by = blockIdx.x / S.nbx;
     const int hx0 = bx * NB, hy0 = by * NB;
-    const int hx1 = min(hx0 + NB, Ex);
-    const int nhrow = min(NB, Ey - hy0);
     const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NB + R, Ey);
     const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NB + R, Ex);
     const int nirow = iy1 - iy0;
     const int tid = threadIdx.x;
 
-    if (tid < nhrow) {
-        const int64_t rb = (int64_t)(hy0 + tid) * Ex;
-        const uint32_t s0 = S.cs_out[rb + hx0];
+    if (tid < NSEG) {  // segment = one row of the home block
+        const int y = hy0 + tid;
+        const int x0 = hx0, x1 = min(x0 + NB, Ex);
+        uint32_t s0 = 0, cnt = 0;
+        if (y < Ey && x0 < Ex) {
+            const int64_t rb = (int64_t)y * Ex;
+            s0 = S.cs_out[rb + x0];
+            cnt = S.cs_out[rb + x1] - s0;
+        }
         hstart[tid] = s0;
-        hpre[tid + 1] = S.cs_out[rb + hx1] - s0;
+        hpre[tid + 1] = cnt;
     }
     for (int r = tid; r < nirow; r += NTH) {
         const int64_t rb = (int64_t)(iy0 + r) * Ex;
@@ -170,130 +177,123 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
         istart[r] = s0;
         ipre[r + 1] = S.cs_in[rb + ix1] - s0;
     }
+    // a point in a cell |dy| rows away is at least (|dy| - 1)+ cells away vertically,
+    // so its cell can be at most ceil(sqrt(e2 - ((|dy| - 1)+)^2)) columns away
+    if (tid <= R) {
+        const double a = (double)max(tid - 1, 0);
+        xrad[tid] = min(R, (int)(sqrt(max(na.eps2g - a * a, 0.0)) + 1.0));
+    }
     __syncthreads();
     if (tid == 0) {
         hpre[0] = 0;
-        for (int r = 1; r <= nhrow; ++r) hpre[r] += hpre[r - 1];
+        for (int s = 1; s <= NSEG; ++s) hpre[s] += hpre[s - 1];
         ipre[0] = 0;
         for (int r = 1; r <= nirow; ++r) ipre[r] += ipre[r - 1];
     }
     __syncthreads();
-    const uint32_t nhome = hpre[nhrow], nin = ipre[nirow];
+    const uint32_t nhome = hpre[NSEG], nin = ipre[nirow];
     if (nhome == 0) return;  // uniform
 
     const double e2 = na.eps2g, inv_e2 = 1.0 / na.eps2g;
     const double c0 = log(1.0 / na.ginv) * INV_2PI;
 
-    for (uint32_t hb = 0; hb < nhome; hb += NTH * TPT) {
-        double px[TPT], py[TPT], acc0[TPT], acc1[TPT], acc2[TPT];  // px, py: home fractions
-        int cx[TPT], cy[TPT];
-        int64_t gi[TPT];
-#pragma unroll
-        for (int t = 0; t < TPT; ++t) {
-            const uint32_t k = hb + tid + t * NTH;
-            acc0[t] = acc1[t] = acc2[t] = 0.0;
-            gi[t] = -1;
-            cx[t] = cy[t] = 0;
-            px[t] = py[t] = 0.0;
-            if (k < nhome) {
-                const int r = find_row(hpre, nhrow, k);
-                const int64_t i = (int64_t)hstart[r] + (k - hpre[r]);
-                gi[t] = i;
-                const uint32_t key = S.key_out[i];
-                cx[t] = (int)(key % (uint32_t)Ex);
-                cy[t] = (int)(key / (uint32_t)Ex);
-                px[t] = S.f_out[i];
-                py[t] = S.f_out[S.n_out + i];
-            }
+    for (uint32_t hb = 0; hb < nhome; hb += NTH) {
+        const uint32_t k = hb + tid;
+        const bool valid = k < nhome;
+        int64_t gi = -1;
+        int cx = 0, cy = 0;
+        double px = 0.0, py = 0.0;
+        if (valid) {
+            const int sgi = find_seg(hpre, NSEG, k);
+            gi = (int64_t)hstart[sgi] + (k - hpre[sgi]);
+            const uint32_t key = S.key_out[gi];
+            cx = (int)(key % (uint32_t)Ex);
+            cy = (int)(key / (uint32_t)Ex);
+            px = S.f_out[gi];
+            py = S.f_out[S.n_out + gi];
         }
+        const int hcx = cx - ix0, hcy = cy - iy0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (uint32_t c_lo = 0; c_lo < nin; c_lo += CAP) {
             const uint32_t c_hi = min(nin, c_lo + (uint32_t)CAP);
             __syncthreads();
-            for (uint32_t k = c_lo + tid; k < c_hi; k += NTH) {
-                const int r = find_row(ipre, nirow, k);
-                const int64_t j = (int64_t)istart[r] + (k - ipre[r]);
-                sxy[k - c_lo] = make_double2(S.f_in[j], S.f_in[S.n_in + j]);
+            for (uint32_t kk = c_lo + tid; kk < c_hi; kk += NTH) {
+                const int r = find_seg(ipre, nirow, kk);
+                const int64_t j = (int64_t)istart[r] + (kk - ipre[r]);
+                sxy[kk - c_lo] = make_double2(S.f_in[j], S.f_in[S.n_in + j]);
                 const uint32_t kj = S.key_in[j];
-                scell[k - c_lo] = (kj % (uint32_t)Ex - (uint32_t)ix0) | ((kj / (uint32_t)Ex - (uint32_t)iy0) << 16);
-                spay[0][k - c_lo] = S.pay[j];
-                if (PAY == 2) spay[PAY - 1][k - c_lo] = S.pay[S.n_in + j];
+                scell[kk - c_lo] = (kj % (uint32_t)Ex - (uint32_t)ix0) | ((kj / (uint32_t)Ex - (uint32_t)iy0) << 16);
+                spay[0][kk - c_lo] = S.pay[j];
+                if (PAY == 2) spay[PAY - 1][kk - c_lo] = S.pay[S.n_in + j];
             }
             __syncthreads();
-            const int r_first = find_row(ipre, nirow, c_lo);
-            const int r_last = find_row(ipre, nirow, c_hi - 1);
-#pragma unroll
-            for (int t = 0; t < TPT; ++t) {
-                if (gi[t] < 0) continue;
-                const int ylo = max(r_first, cy[t] - R - iy0), yhi = min(r_last, cy[t] + R - iy0);
-                for (int r = ylo; r <= yhi; ++r) {
-                    const int ady = abs(iy0 + r - cy[t]);
-                    const double a = (double)max(ady - 1, 0);
-                    const int xr = min(R, (int)(sqrt(max(e2 - a * a, 0.0)) + 1.0));
-                    const int c0c = max(cx[t] - xr, ix0), c1c = min(cx[t] + xr, ix1 - 1);
-                    if (c0c > c1c) continue;
-                    const int64_t rb = (int64_t)(iy0 + r) * Ex;
-                    uint32_t lo = ipre[r] + (S.cs_in[rb + c0c] - istart[r]);
-                    uint32_t hi = ipre[r] + (S.cs_in[rb + c1c + 1] - istart[r]);
-                    lo = max(lo, c_lo) - c_lo;
-                    hi = min(hi, c_hi);
-                    hi = hi > c_lo ? hi - c_lo : 0;
-                    const double tx = px[t], ty = py[t];
-                    const int hcx = cx[t] - ix0, hcy = cy[t] - iy0;
-                    double a0 = acc0[t], a1 = acc1[t], a2 = acc2[t];
-                    for (uint32_t jj = lo; jj < hi; ++jj) {
-                        const double2 q = sxy[jj];
-                        const uint32_t pc = scell[jj];
-                        const int qcx = (int)(pc & 0xffffu), qcy = (int)(pc >> 16);
-                        // fwd: target minus source; adjoint: target (input) minus source (home)
-                        const double dx = MODE == MODE_FWD ? (double)(hcx - qcx) + (tx - q.x)
-                                                           : (double)(qcx - hcx) + (q.x - tx);
-                        const double dy = MODE == MODE_FWD ? (double)(hcy - qcy) + (ty - q.y)
-                                                           : (double)(qcy - hcy) + (q.y - ty);
-                        const double r2 = fma(dx, dx, dy * dy);
-                        if (r2 >= e2) continue;
-                        if (MODE == MODE_ADJ_H) {
-                            if (r2 == 0.0) continue;
-                            const double dT = poly_d<P>(na, r2 * inv_e2);
-                            const double f = fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2));
-                            a0 = fma(f, fma(spay[0][jj], dx, spay[1][jj] * dy), a0);
-                        } else {
-                            const double s = spay[0][jj];
-                            if (r2 == 0.0) {
-                                a0 = fma(-s, na.a[0] + na.offset, a0);
-                                continue;
-                            }
-                            double T, dT;
-                            poly2<P>(na, r2 * inv_e2, T, dT);
-                            if (MODE == MODE_ADJ_PHI || want_phi) a0 = fma(s, c0 - INV_4PI * ln64(r2) - T, a0);
-                            if (MODE == MODE_FWD && want_h) {
-                                const double f = s * fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2));
-                                a1 = fma(f, dx, a1);
-                                a2 = fma(f, dy, a2);
-                            }
+            if (!valid) continue;
+            const int r_first = find_seg(ipre, nirow, c_lo);
+            const int r_last = find_seg(ipre, nirow, c_hi - 1);
+            const int ylo = max(r_first, hcy - R), yhi = min(r_last, hcy + R);
+            for (int r = ylo; r <= yhi; ++r) {
+                const int xr = xrad[abs(r - hcy)];
+                const int c0c = max(hcx - xr, 0) + ix0, c1c = min(hcx + xr, ix1 - ix0 - 1) + ix0;
+                const int64_t rb = (int64_t)(iy0 + r) * Ex;
+                uint32_t lo = ipre[r] + (S.cs_in[rb + c0c] - istart[r]);
+                uint32_t hi = ipre[r] + (S.cs_in[rb + c1c + 1] - istart[r]);
+                lo = max(lo, c_lo) - c_lo;
+                hi = min(hi, c_hi);
+                hi = hi > c_lo ? hi - c_lo : 0;
+                for (uint32_t jj = lo; jj < hi; ++jj) {
+                    const double2 q = sxy[jj];
+                    const uint32_t pc = scell[jj];
+                    const int qcx = (int)(pc & 0xffffu), qcy = (int)(pc >> 16);
+                    // forward: target minus source; adjoint: target (input) minus source (home)
+                    const double dx = FWD ? (double)(hcx - qcx) + (px - q.x) : (double)(qcx - hcx) + (q.x - px);
+                    const double dy = FWD ? (double)(hcy - qcy) + (py - q.y) : (double)(qcy - hcy) + (q.y - py);
+                    const double r2 = fma(dx, dx, dy * dy);
+                    if (!(r2 < e2)) continue;
+                    if (MODE == MODE_COUNT) {
+                        a0 += 1.0;
+                        continue;
+                    }
+                    // coincident pairs: r2 = 0 is replaced by 1 for the arithmetic and the
+                    // pair's share is swapped for -(a_0 + ln(s)/2pi) (phi) and 0 (H)
+                    const bool zero = r2 == 0.0;
+                    const double r2s = zero ? 1.0 : r2;
+                    const double x = r2s * inv_e2;
+                    if (MODE == MODE_ADJ_H) {
+                        const double dT = poly_d<P>(na, x);
+                        const double f = zero ? 0.0 : fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2s));
+                        a0 = fma(f, fma(spay[0][jj], dx, spay[1][jj] * dy), a0);
+                    } else {
+                        const double s = spay[0][jj];
+                        double T, dT;
+                        poly2<P>(na, x, T, dT);
+                        if (WANT_PHI) {
+                            const double kp = c0 - INV_4PI * ln64(r2s, na) - T;
+                            a0 = fma(s, zero ? -(na.a[0] + na.offset) : kp, a0);
+                        }
+                        if (WANT_H) {
+                            const double f = zero ? 0.0 : s * fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2s));
+                            a1 = fma(f, dx, a1);
+                            a2 = fma(f, dy, a2);
                         }
                     }
-                    acc0[t] = a0;
-                    acc1[t] = a1;
-                    acc2[t] = a2;
                 }
             }
         }
-#pragma unroll
-        for (int t = 0; t < TPT; ++t) {
-            const int64_t i = gi[t];
-            if (i < 0) continue;
-            const int64_t o = S.perm_out[i];
-            if (MODE == MODE_FWD) {
-                if (want_phi) out0[o] = S.far[i] + acc0[t] + na.offset * sum_in[0];
-                if (want_h) {
+        if (valid) {
+            const int64_t o = S.perm_out[gi];
+            if (FWD) {
+                if (WANT_PHI) out0[o] = S.far[gi] + a0 + na.offset * sum_in[0];
+                if (WANT_H) {
                     const double G = 1.0 / na.ginv;
-                    out1[2 * o] = na.scale * fma(G, acc1[t], S.far[S.n_out + i]);
-                    out1[2 * o + 1] = na.scale * fma(G, acc2[t], S.far[2 * S.n_out + i]);
+                    out1[2 * o] = na.scale * fma(G, a1, S.far[S.n_out + gi]);
+                    out1[2 * o + 1] = na.scale * fma(G, a2, S.far[2 * S.n_out + gi]);
                 }
+            } else if (MODE == MODE_COUNT) {
+                out0[o] = a0;
             } else if (MODE == MODE_ADJ_H) {
-                out0[o] = S.w_out[i] * na.scale * fma(1.0 / na.ginv, acc0[t], S.far[i]);
+                out0[o] = S.w_out[gi] * na.scale * fma(1.0 / na.ginv, a0, S.far[gi]);
             } else {
-                out0[o] = S.w_out[i] * (S.far[i] + acc0[t] + na.offset * sum_in[0]);
+                out0[o] = S.w_out[gi] * (S.far[gi] + a0 + na.offset * sum_in[0]);
             }
         }
     }
@@ -303,25 +303,47 @@ constexpr int CAP_FWD = 2048;
 constexpr int CAP_ADJ = 2048;
 
 template <int MODE, int CAP, int P>
-hipError_t launch_p(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum,
-                    int want_phi, int want_h, double *o0, double *o1)
+hipError_t launch_p(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum, double *o0,
+                    double *o1)
 {
-    k_near<MODE, CAP, P><<<nblk, NTH, 0, st>>>(S, na, sum, want_phi, want_h, o0, o1);
+    k_near<MODE, CAP, P><<<nblk, NTH, 0, st>>>(S, na, sum, o0, o1);
     return hipGetLastError();
 }
 
 template <int MODE, int CAP>
-hipError_t launch_mode(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum,
-                       int want_phi, int want_h, double *o0, double *o1)
+hipError_t launch_mode(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum, double *o0,
+                       double *o1)
 {
     switch (na.p) {
 #define FN_NEAR_CASE(PP) \
-    case PP: return launch_p<MODE, CAP, PP>(nblk, st, S, na, sum, want_phi, want_h, o0, o1);
+    case PP: return launch_p<MODE, CAP, PP>(nblk, st, S, na, sum, o0, o1);
     FN_NEAR_CASE(1) FN_NEAR_CASE(2) FN_NEAR_CASE(3) FN_NEAR_CASE(4) FN_NEAR_CASE(5) FN_NEAR_CASE(6)
     FN_NEAR_CASE(7) FN_NEAR_CASE(8) FN_NEAR_CASE(9) FN_NEAR_CASE(10) FN_NEAR_CASE(11) FN_NEAR_CASE(12)
 #undef FN_NEAR_CASE
     default: return hipErrorInvalidValue;
     }
+}
+
+NearSets make_sets(const Geom &g, const Buffers &b, int out_set)
+{
+    NearSets S{};
+    const int in_set = 1 - out_set;
+    S.n_out = out_set ? g.ns : g.nt;
+    S.key_out = b.key[out_set];
+    S.f_out = b.fr64[out_set];
+    S.perm_out = b.perm[out_set];
+    S.cs_out = b.cstart[out_set];
+    S.far = b.far;
+    S.w_out = out_set ? b.w : nullptr;
+    S.n_in = in_set ? g.ns : g.nt;
+    S.key_in = b.key[in_set];
+    S.f_in = b.fr64[in_set];
+    S.cs_in = b.cstart[in_set];
+    S.pay = out_set ? b.aval64 : b.val64;
+    S.Ex = g.ext[0];
+    S.Ey = g.ext[1];
+    S.nbx = (g.ext[0] + NB - 1) / NB;
+    return S;
 }
 
 }  // namespace
@@ -330,49 +352,23 @@ hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, 
                            int want_phi, int want_h, double *phi, double *H, hipStream_t st)
 {
     if (g.nt == 0) return hipSuccess;
-    NearSets S{};
-    S.n_out = g.nt;
-    S.key_out = b.key[0];
-    S.f_out = b.fr64[0];
-    S.perm_out = b.perm[0];
-    S.cs_out = b.cstart[0];
-    S.far = b.far;
-    S.w_out = nullptr;
-    S.n_in = g.ns;
-    S.key_in = b.key[1];
-    S.f_in = b.fr64[1];
-    S.cs_in = b.cstart[1];
-    S.pay = b.val64;
-    S.Ex = g.ext[0];
-    S.Ey = g.ext[1];
-    S.nbx = (g.ext[0] + NB - 1) / NB;
-    const int nby = (g.ext[1] + NB - 1) / NB;
-    return launch_mode<MODE_FWD, CAP_FWD>(S.nbx * nby, st, S, na, sum_s, want_phi, want_h, phi, H);
+    const NearSets S = make_sets(g, b, 0);
+    const int nblk = S.nbx * ((g.ext[1] + NB - 1) / NB);
+    if (want_phi && want_h) return launch_mode<MODE_FWD_BOTH, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
+    if (want_phi) return launch_mode<MODE_FWD_PHI, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
+    return launch_mode<MODE_FWD_H, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
 }
 
+// kind 0: H^T (V), kind 1: phi^T (v), kind 2: count pairs closer than eps_I per source.
 hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int kind, const double *sum_v,
                            double *u, hipStream_t st)
 {
     if (g.ns == 0) return hipSuccess;
-    NearSets S{};
-    S.n_out = g.ns;
-    S.key_out = b.key[1];
-    S.f_out = b.fr64[1];
-    S.perm_out = b.perm[1];
-    S.cs_out = b.cstart[1];
-    S.far = b.far;
-    S.w_out = b.w;
-    S.n_in = g.nt;
-    S.key_in = b.key[0];
-    S.f_in = b.fr64[0];
-    S.cs_in = b.cstart[0];
-    S.pay = b.aval64;
-    S.Ex = g.ext[0];
-    S.Ey = g.ext[1];
-    S.nbx = (g.ext[0] + NB - 1) / NB;
-    const int nby = (g.ext[1] + NB - 1) / NB;
-    if (kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ>(S.nbx * nby, st, S, na, sum_v, 0, 0, u, nullptr);
-    return launch_mode<MODE_ADJ_PHI, CAP_ADJ>(S.nbx * nby, st, S, na, sum_v, 0, 0, u, nullptr);
+    const NearSets S = make_sets(g, b, 1);
+    const int nblk = S.nbx * ((g.ext[1] + NB - 1) / NB);
+    if (kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
+    if (kind == 1) return launch_mode<MODE_ADJ_PHI, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
+    return launch_p<MODE_COUNT, CAP_ADJ, 1>(nblk, st, S, na, sum_v, u, nullptr);
 }
 
 }  // namespace fn

@@ -42,7 +42,7 @@ def test_params_default_and_validation():
     ctx = ctypes.c_void_p()
     bad = []
     for field, val in (("grid", 100), ("grid", 16384), ("m", 1), ("m", 9), ("p", 0), ("p", 13),
-                       ("eps_I", 0.0), ("eps_I", 0.2), ("eps_B", 0.3), ("precision", 7)):
+                       ("eps_I", 0.0), ("eps_I", 0.1), ("eps_B", 0.3), ("precision", 7)):
         q = _lib.Params()
         L.fn_params_default(ctypes.byref(q), 512)
         setattr(q, field, val)
