@@ -170,14 +170,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-# FP64 flops per interacting pair of the near-field kernels (an FMA counts 2), from the
-# formulas they evaluate, p = regularization degree.  Forward (phi and H): offset 4,
-# r^2 3, rho^2 1, T and T' 4(p-1), ln 34, phi term 4, 1/r^2 8, field factor 4, H sums 4.
-# Adjoint (H^T): offset 4, r^2 3, rho^2 1, T' 2(p-1), 1/r^2 8, factor 3, V.d 3, sum 2.
-def near_flops_per_pair(stage, p):
-    if stage == "near":          # phi and H: offsets, r^2, T and T', ln, 1/r^2, accumulations
-        return 62 + 4 * (p - 1)
-    return 24 + 2 * (p - 1)      # H^T: offsets, r^2, T', 1/r^2, V.d, accumulation
+# Near-field flops per interacting pair (FMA = 2 flops; an FP32 log2 or reciprocal = 1;
+# integer work, conversions, compares and selects are not counted):
+#   forward (phi and H): offsets 4, r^2 3, x 1, U and U' by synthetic division
+#     2(p-1) + 2(p-2), ln x, 1/x, phi share and its sum 4, field factor 3, H sums 4;
+#   adjoint (H^T): offsets 4, r^2 3, x 1, U' by Horner 2(p-2), 1/x, factor 2, V.d 3, sum 2.
+# In the FP64 path ln x costs 38 (reduction, a Newton-refined reciprocal, 9-term series)
+# and 1/x costs 9 (estimate and two Newton steps).
+def near_flops_per_pair(stage, p, f32=True):
+    ln, rc = (1, 1) if f32 else (38, 9)
+    if stage == "near":
+        return 4 + 3 + 1 + 2 * (p - 1) + 2 * (p - 2) + ln + rc + 4 + 3 + 4
+    return 4 + 3 + 1 + 2 * (p - 2) + rc + 2 + 3 + 2
 
 
 def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
@@ -191,12 +195,12 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
     nh = G // 4
     if stage in ("near", "a_near"):
         pairs = info["near_pairs"]
-        fl = near_flops_per_pair(stage, args.p)
+        fl = near_flops_per_pair(stage, args.p, f32=True)
         ach = pairs * fl / sec / 1e12
         traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1")
         return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / FP64_VEC_TFLOPS, "traffic": traffic, "ms_per_launch": ms_per_launch,
-                "pairs_per_launch": pairs, "fp64_flops_per_pair": fl}
+                "pairs_per_launch": pairs, "flops_per_pair": fl}
     if stage in ("spread", "a_spread"):
         npt, nf = (ns, 1) if stage == "spread" else (nt, 2)
         byts = npt * (12 + 4 * nf) + cells * 4 * nf

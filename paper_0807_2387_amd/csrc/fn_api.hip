@@ -445,15 +445,23 @@ static NearArgs near_args(const fn_ctx *c)
     const Plan &P = c->plan;
     const double eg = P.eps_I * P.G;
     na.eps2g = eg * eg;
+    na.inv_e2 = 1.0 / na.eps2g;
+    na.inv_eg = 1.0 / eg;
     na.ginv = 1.0 / P.G;
-    for (int k = 0; k < MAXP; ++k) na.a[k] = P.a[k];
+    // K(eps_I) = -(1/2pi) ln(eps_I) in torus units
+    const long double k_eps = -std::log((long double)P.eps_I) / (2.0L * (long double)PI);
+    for (int k = 0; k < MAXP; ++k) na.u[k] = P.a[k];
+    na.u[0] = (double)((long double)P.a[0] - k_eps);
+    for (int k = 0; k + 1 < MAXP; ++k) na.du[k] = (k + 1) * P.a[k + 1];
     for (int k = 0; k < 9; ++k) na.lc[k] = 1.0 / (2 * k + 3);
     na.ln2hi = 0.693147180559945286227;
     na.ln2lo = 2.319046813846299558e-17;
+    na.offset = std::log(c->geom.s) / (2.0 * PI);
+    na.czero = -(P.a[0] + na.offset);
     na.p = P.p;
     na.rnear = c->geom.rnear;
+    na.f32 = P.precision == FN_FP32_MIXED ? 1 : 0;
     na.scale = c->geom.s;
-    na.offset = std::log(c->geom.s) / (2.0 * PI);
     return na;
 }
 

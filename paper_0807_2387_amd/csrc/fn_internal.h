@@ -162,12 +162,18 @@ size_t fft_lds_limit(int precision, int G);
 // near field + final
 struct NearArgs {
     double eps2g;        // eps_I^2 in grid units^2
+    double inv_e2;       // 1 / eps2g
+    double inv_eg;       // 1 / (eps_I G): the mixed path stages offsets in units of eps_I
     double ginv;         // 1/G
-    double a[MAXP];      // T_I coefficients: T(x) = sum_k a_k x^k, x = (r/eps_I)^2
+    // T_I(x) - K(eps_I) as a polynomial in x = (r/eps_I)^2: u_k = a_k, u_0 = a_0 - K(eps_I)
+    double u[MAXP];
+    double du[MAXP];     // U'(x) = T'(x): du_k = (k+1) u_{k+1}
     double lc[9];        // 1/(2k+1), k = 1..9 (series of the logarithm)
     double ln2hi, ln2lo; // ln 2 in two parts
+    double czero;        // phi share of a coincident pair: -(a_0 + ln(s)/2pi)
     int p;
     int rnear;
+    int f32;             // 1: the logarithm and reciprocal of x are evaluated in FP32 (mixed precision)
     double scale;        // s
     double offset;       // (ln s / 2 pi)
 };

@@ -14,35 +14,42 @@
 // grid units is d = (c_i - c_j) + (f_i - f_j), exact up to the rounding of the
 // result itself, so even points a tiny fraction of a cell apart keep their
 // relative position to full FP64 precision.  G is a power of two, so grid units
-// convert to torus units exactly.  In grid units, with r2 = |d|^2,
-// e2 = (eps_I G)^2, rho2 = r2/e2:
-//   (K - T_I)(r)           = ln(G)/(2pi) - ln(r2)/(4pi) - T(rho2)
-//   -grad_y (K - T_I)      = G * (1/(2 pi r2) + 2 T'(rho2)/e2) * d
-// with T(x) = sum_k a_k x^k, T'(x) = sum_{k>=1} k a_k x^{k-1}.
+// convert to torus units exactly.  With r2 = |d|^2, e2 = (eps_I G)^2 and
+// x = r2/e2 = (r/eps_I)^2, and because T_I(eps_I) = K(eps_I) and
+// T_I'(eps_I) = K'(eps_I) (so dT/dx = -1/(4pi) at x = 1):
+//   (K - T_I)(r)           = -(1/(4pi)) ln x - U(x),   U(x) = T(x) - K(eps_I)
+//   -grad_y (K - T_I)      = (2G/e2) (1/(4pi x) + T'(x)) d
+// Both terms of the first line vanish at the zone edge, so the logarithm is
+// only ever needed to the absolute accuracy of the result.
 //
 // Final: phi = far + near + (ln s / 2pi) sum_j s_j,  H = s (far + near), written
 // to the caller's order.  The transposes loop over targets near each source:
 // u_j = w_j s (far + near) for H^T and u_j = w_j (far + near + (ln s / 2pi)
 // sum_i v_i) for phi^T.
 //
+// Precision: offsets, r2, x, the in-zone test, the polynomial and all sums are
+// FP64.  In the mixed-precision path ln x and 1/x come from the FP32 hardware
+// log2 and reciprocal (x rounded to FP32 first): ln x is then off by ~1e-7
+// absolute, (1/4pi) ln x by < 1e-8, and 1/(4pi x) by ~1e-7 of itself.
+//
 // Work decomposition: one workgroup per NB x NB block of "home" cells of the
 // output point set; the points of the other set lying in the block's rows and
 // columns widened by rnear cells are staged into LDS in chunks of at most CAP
 // points (coalesced copies), so any point density works.  Each thread owns one
 // home point at a time and, for every staged row within rnear, loops over the
-// cells within the disk bound of its own cell.  Everything is FP64.
+// cells within the disk bound of its own cell, two staged points per trip with
+// a branch-free pair body (two independent dependency chains per lane).
 #include "fn_internal.h"
 
 namespace fn {
 
 namespace {
 
-constexpr double INV_2PI = 0.15915494309189533576888376337251436;
 constexpr double INV_4PI = 0.07957747154594766788444188168625718;
 constexpr int NB = 16;           // home block edge, cells
 constexpr int NSEG = NB;         // home row segments per block
 constexpr int NTH = 256;         // threads per block
-constexpr int MAXRN = 32;        // largest near radius in cells (rows listed per thread: 2 rnear + 1)
+constexpr int MAXRN = 32;        // largest near radius in cells
 constexpr int MAXROWS = NB + 2 * MAXRN + 2;
 
 enum { MODE_FWD_BOTH = 0, MODE_ADJ_H = 1, MODE_ADJ_PHI = 2, MODE_COUNT = 3, MODE_FWD_PHI = 4, MODE_FWD_H = 5 };
@@ -65,32 +72,31 @@ struct NearSets {
     int Ex, Ey, nbx;
 };
 
-// T(x) = sum_{k<P} a_k x^k and T'(x) = sum_{k>=1} k a_k x^{k-1} in one Horner sweep
-// (the derivative accumulates the running value: synthetic division); the
-// coefficients are kernel arguments, so they live in scalar registers.
-template <int P>
-__device__ __forceinline__ void poly2(const NearArgs &na, double x, double &T, double &dT)
+// U(x) = sum_{k<P} c_k x^k and U'(x) in one Horner sweep (the derivative
+// accumulates the running value: synthetic division); the coefficients are
+// kernel arguments, so they live in scalar registers.
+template <int P, typename T>
+__device__ __forceinline__ void poly2(const T *c, T x, T &u, T &du)
 {
-    double t = na.a[P - 1], d = 0.0;
+    T t = c[P - 1], d = T(0);
 #pragma unroll
     for (int i = P - 2; i >= 0; --i) {
         d = (i == P - 2) ? t : fma(d, x, t);
-        t = fma(t, x, na.a[i]);
+        t = fma(t, x, c[i]);
     }
-    T = t;
-    dT = d;
+    u = t;
+    du = d;
 }
 
+// U'(x) by plain Horner over its own coefficients (k+1) u_{k+1}.
 template <int P>
-__device__ __forceinline__ double poly_d(const NearArgs &na, double x)
+__device__ __forceinline__ double poly_d(const double *dc, double x)
 {
-    double t = na.a[P - 1], d = 0.0;
+    if (P < 2) return 0.0;
+    double t = dc[P - 2 < 0 ? 0 : P - 2];
 #pragma unroll
-    for (int i = P - 2; i >= 1; --i) {
-        d = (i == P - 2) ? t : fma(d, x, t);
-        t = fma(t, x, na.a[i]);
-    }
-    return P > 2 ? fma(d, x, t) : (P == 2 ? t : 0.0);
+    for (int i = P - 3; i >= 0; --i) t = fma(t, x, dc[i]);
+    return t;
 }
 
 // 1/x for a normal positive x: hardware estimate refined by two Newton steps
@@ -126,6 +132,61 @@ __device__ __forceinline__ double ln64(double x, const NearArgs &na)
     return fma(de, na.ln2hi, fma(de, na.ln2lo, lnm));
 }
 
+constexpr double LN2_4PI = 0.05515890334192413571;  // ln(2)/(4 pi)
+
+// Smallest x = (r/eps_I)^2 the per-pair arithmetic sees: keeps ln x and 1/x
+// finite.  In the mixed path this treats pairs closer than ~1e-14 cells as that
+// far apart; in the FP64 path the bound is below any representable offset.
+constexpr double XMIN32 = 1e-30;
+constexpr double XMIN64 = 1e-300;
+
+// One pair, given the FP64 offset d (home minus staged; grid units, or units of
+// eps_I G cells in the mixed path, where the caller passes e2 = 1).  The zone
+// test masks the accumulation (pairs with r2 >= e2 add nothing).  A coincident
+// pair (r2 = 0) adds czero to phi; its H share is g * d = 0 by itself.  kind 0:
+// phi and H with weight s; kind 1: H only; kind 2: phi only; kind 3: the
+// adjoint of H, weight (V0, V1).  The H accumulators hold
+// sum s (1/(4pi x) + T'(x)) d; the caller applies 2G/e2 (2G/(eps_I G) in the
+// mixed path).
+template <int KIND, int P, bool F32>
+__device__ __forceinline__ void pair(const NearArgs &na, double e2, double dx, double dy, double w0, double w1,
+                                     double &a0, double &a1, double &a2)
+{
+    constexpr bool PHI = KIND == 0 || KIND == 2;
+    constexpr bool GRAD = KIND == 0 || KIND == 1 || KIND == 3;
+    const double r2 = fma(dx, dx, dy * dy);
+    // mixed path: offsets come in units of eps_I, so x = r2 and the zone is r2 < 1
+    const double x = F32 ? fmax(r2, XMIN32) : fmax(r2 * na.inv_e2, XMIN64);
+    double u = 0.0, du = 0.0;
+    if (PHI) poly2<P, double>(na.u, x, u, du);
+    else du = poly_d<P>(na.du, x);
+    double lnx = 0.0, rx = 0.0;
+    if (F32) {
+        const float xf = (float)x;
+        if (PHI) lnx = (double)__builtin_amdgcn_logf(xf);  // log2
+        if (GRAD) rx = (double)__builtin_amdgcn_rcpf(xf);
+    } else {
+        if (PHI) lnx = ln64(x, na);
+        if (GRAD) rx = rcp64(x);
+    }
+    if (r2 < e2) {
+        if (PHI) {
+            const double phi_t = r2 == 0.0 ? na.czero : fma(F32 ? -LN2_4PI : -INV_4PI, lnx, -u);
+            a0 = fma(w0, phi_t, a0);
+        }
+        if (GRAD) {
+            const double g = fma(INV_4PI, rx, du);
+            if (KIND == 3) {
+                a0 = fma(g, fma(w0, dx, w1 * dy), a0);
+            } else {
+                const double f = w0 * g;
+                a1 = fma(f, dx, a1);
+                a2 = fma(f, dy, a2);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ int find_seg(const uint32_t *pre, int nseg, uint32_t k)
 {
     int lo = 0, hi = nseg - 1;  // largest s with pre[s] <= k
@@ -136,7 +197,7 @@ __device__ __forceinline__ int find_seg(const uint32_t *pre, int nseg, uint32_t 
     return lo;
 }
 
-template <int MODE, int CAP, int P>
+template <int MODE, int CAP, int P, bool F32>
 __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const double *__restrict__ sum_in,
                                               double *__restrict__ out0, double *__restrict__ out1)
 {
@@ -144,12 +205,12 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     constexpr bool WANT_PHI = MODE == MODE_FWD_BOTH || MODE == MODE_FWD_PHI || MODE == MODE_ADJ_PHI;
     constexpr bool WANT_H = MODE == MODE_FWD_BOTH || MODE == MODE_FWD_H;
     constexpr int PAY = MODE == MODE_ADJ_H ? 2 : 1;
+    constexpr int KIND = MODE == MODE_ADJ_H ? 3 : (WANT_PHI && WANT_H ? 0 : (WANT_H ? 1 : 2));
     __shared__ double2 sxy[CAP];     // in-cell fractions
-    __shared__ uint32_t scell[CAP];  // cell offsets from the region origin, x | y << 16
+    __shared__ uint16_t scx[F32 ? 1 : CAP];  // cell column offset from the region origin (FP64 path)
     __shared__ double spay[PAY][CAP];
     __shared__ uint32_t hpre[NSEG + 1], hstart[NSEG];       // home row segments
     __shared__ uint32_t ipre[MAXROWS + 1], istart[MAXROWS]; // input rows
-    __shared__ int xrad[MAXRN + 2];                         // cell half-width per row offset
 
     const int Ex = S.Ex, Ey = S.Ey, R = na.rnear;
     const int bx = blockIdx.x % S.nbx, by = blockIdx.x / S.nbx;
@@ -177,12 +238,6 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
         istart[r] = s0;
         ipre[r + 1] = S.cs_in[rb + ix1] - s0;
     }
-    // a point in a cell |dy| rows away is at least (|dy| - 1)+ cells away vertically,
-    // so its cell can be at most ceil(sqrt(e2 - ((|dy| - 1)+)^2)) columns away
-    if (tid <= R) {
-        const double a = (double)max(tid - 1, 0);
-        xrad[tid] = min(R, (int)(sqrt(max(na.eps2g - a * a, 0.0)) + 1.0));
-    }
     __syncthreads();
     if (tid == 0) {
         hpre[0] = 0;
@@ -194,8 +249,7 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     const uint32_t nhome = hpre[NSEG], nin = ipre[nirow];
     if (nhome == 0) return;  // uniform
 
-    const double e2 = na.eps2g, inv_e2 = 1.0 / na.eps2g;
-    const double c0 = log(1.0 / na.ginv) * INV_2PI;
+    const double e2 = na.eps2g;
 
     for (uint32_t hb = 0; hb < nhome; hb += NTH) {
         const uint32_t k = hb + tid;
@@ -220,9 +274,17 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
             for (uint32_t kk = c_lo + tid; kk < c_hi; kk += NTH) {
                 const int r = find_seg(ipre, nirow, kk);
                 const int64_t j = (int64_t)istart[r] + (kk - ipre[r]);
-                sxy[kk - c_lo] = make_double2(S.f_in[j], S.f_in[S.n_in + j]);
                 const uint32_t kj = S.key_in[j];
-                scell[kk - c_lo] = (kj % (uint32_t)Ex - (uint32_t)ix0) | ((kj / (uint32_t)Ex - (uint32_t)iy0) << 16);
+                const uint32_t qcx = kj % (uint32_t)Ex - (uint32_t)ix0;
+                if (F32) {
+                    // block-local coordinates in units of eps_I G cells: rounded to ~1e-15,
+                    // exact enough for the FP32 arithmetic of this path
+                    sxy[kk - c_lo] = make_double2(((double)qcx + S.f_in[j]) * na.inv_eg,
+                                                  ((double)(kj / (uint32_t)Ex - (uint32_t)iy0) + S.f_in[S.n_in + j]) * na.inv_eg);
+                } else {
+                    sxy[kk - c_lo] = make_double2(S.f_in[j], S.f_in[S.n_in + j]);
+                    scx[kk - c_lo] = (uint16_t)qcx;
+                }
                 spay[0][kk - c_lo] = S.pay[j];
                 if (PAY == 2) spay[PAY - 1][kk - c_lo] = S.pay[S.n_in + j];
             }
@@ -231,67 +293,95 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
             const int r_first = find_seg(ipre, nirow, c_lo);
             const int r_last = find_seg(ipre, nirow, c_hi - 1);
             const int ylo = max(r_first, hcy - R), yhi = min(r_last, hcy + R);
-            for (int r = ylo; r <= yhi; ++r) {
-                const int xr = xrad[abs(r - hcy)];
-                const int c0c = max(hcx - xr, 0) + ix0, c1c = min(hcx + xr, ix1 - ix0 - 1) + ix0;
+            const double hx = (double)hcx + px;
+            const double hxs = hx * na.inv_eg, hys = ((double)hcy + py) * na.inv_eg;
+            // raw cell-start bounds of the columns of row r whose cells can hold a point within
+            // eps_I: from the vertical gap between the home point and row r (padded against
+            // rounding); an empty range where the gap alone exceeds eps_I
+            auto bounds = [&](int r, uint32_t &blo, uint32_t &bhi) {
+                const double gap = r < hcy ? (double)(hcy - r - 1) + py : (r > hcy ? (double)(r - hcy) - py : 0.0);
+                const double h2 = e2 - gap * gap;
+                const double w = (double)__builtin_sqrtf((float)fmax(h2, 0.0)) + 1e-3;
+                const int c0c = max((int)floor(hx - w), 0) + ix0;
+                const int c1c = h2 > 0.0 ? min((int)floor(hx + w), ix1 - ix0 - 1) + ix0 : c0c - 1;
                 const int64_t rb = (int64_t)(iy0 + r) * Ex;
-                uint32_t lo = ipre[r] + (S.cs_in[rb + c0c] - istart[r]);
-                uint32_t hi = ipre[r] + (S.cs_in[rb + c1c + 1] - istart[r]);
+                blo = S.cs_in[rb + c0c];
+                bhi = S.cs_in[rb + c1c + 1];
+            };
+            uint32_t nlo = 0, nhi = 0;
+            if (ylo <= yhi) bounds(ylo, nlo, nhi);
+            for (int r = ylo; r <= yhi; ++r) {
+                const uint32_t blo = nlo, bhi = nhi;
+                if (r < yhi) bounds(r + 1, nlo, nhi);  // next row's loads overlap this row's pairs
+                uint32_t lo = ipre[r] + (blo - istart[r]);
+                uint32_t hi = ipre[r] + (bhi - istart[r]);
                 lo = max(lo, c_lo) - c_lo;
                 hi = min(hi, c_hi);
                 hi = hi > c_lo ? hi - c_lo : 0;
-                for (uint32_t jj = lo; jj < hi; ++jj) {
-                    const double2 q = sxy[jj];
-                    const uint32_t pc = scell[jj];
-                    const int qcx = (int)(pc & 0xffffu), qcy = (int)(pc >> 16);
-                    // forward: target minus source; adjoint: target (input) minus source (home)
-                    const double dx = FWD ? (double)(hcx - qcx) + (px - q.x) : (double)(qcx - hcx) + (q.x - px);
-                    const double dy = FWD ? (double)(hcy - qcy) + (py - q.y) : (double)(qcy - hcy) + (q.y - py);
-                    const double r2 = fma(dx, dx, dy * dy);
-                    if (!(r2 < e2)) continue;
-                    if (MODE == MODE_COUNT) {
-                        a0 += 1.0;
-                        continue;
+                const double dyc = (double)(hcy - r);  // every staged point of this row is in row r
+                if (MODE == MODE_COUNT) {
+                    for (uint32_t jj = lo; jj < hi; ++jj) {
+                        const double dx = (double)(hcx - (int)scx[jj]) + (px - sxy[jj].x);
+                        const double dy = dyc + (py - sxy[jj].y);
+                        a0 += fma(dx, dx, dy * dy) < e2 ? 1.0 : 0.0;
                     }
-                    // coincident pairs: r2 = 0 is replaced by 1 for the arithmetic and the
-                    // pair's share is swapped for -(a_0 + ln(s)/2pi) (phi) and 0 (H)
-                    const bool zero = r2 == 0.0;
-                    const double r2s = zero ? 1.0 : r2;
-                    const double x = r2s * inv_e2;
-                    if (MODE == MODE_ADJ_H) {
-                        const double dT = poly_d<P>(na, x);
-                        const double f = zero ? 0.0 : fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2s));
-                        a0 = fma(f, fma(spay[0][jj], dx, spay[1][jj] * dy), a0);
-                    } else {
-                        const double s = spay[0][jj];
-                        double T, dT;
-                        poly2<P>(na, x, T, dT);
-                        if (WANT_PHI) {
-                            const double kp = c0 - INV_4PI * ln64(r2s, na) - T;
-                            a0 = fma(s, zero ? -(na.a[0] + na.offset) : kp, a0);
-                        }
-                        if (WANT_H) {
-                            const double f = zero ? 0.0 : s * fma(2.0 * dT, inv_e2, INV_2PI * rcp64(r2s));
-                            a1 = fma(f, dx, a1);
-                            a2 = fma(f, dy, a2);
-                        }
+                    continue;
+                }
+                // home minus staged: target minus source (forward), source minus target (adjoint)
+                if (F32) {
+                    const double2 *pq = sxy + lo;
+                    const double *pw0 = spay[0] + lo;
+                    const double *pw1 = spay[PAY - 1] + lo;
+                    uint32_t n = hi > lo ? hi - lo : 0;
+                    for (; n >= 2; n -= 2, pq += 2, pw0 += 2, pw1 += 2) {
+                        const double2 q0 = pq[0], q1 = pq[1];
+                        const double w00 = pw0[0], w10 = pw0[1];
+                        const double w01 = PAY == 2 ? pw1[0] : 0.0, w11 = PAY == 2 ? pw1[1] : 0.0;
+                        pair<KIND, P, F32>(na, 1.0, hxs - q0.x, hys - q0.y, w00, w01, a0, a1, a2);
+                        pair<KIND, P, F32>(na, 1.0, hxs - q1.x, hys - q1.y, w10, w11, a0, a1, a2);
                     }
+                    if (n) {
+                        const double2 q0 = pq[0];
+                        const double w00 = pw0[0], w01 = PAY == 2 ? pw1[0] : 0.0;
+                        pair<KIND, P, F32>(na, 1.0, hxs - q0.x, hys - q0.y, w00, w01, a0, a1, a2);
+                    }
+                    continue;
+                }
+                const double2 *pq = sxy + lo;
+                const uint16_t *pc = scx + lo;
+                const double *pw0 = spay[0] + lo;
+                const double *pw1 = spay[PAY - 1] + lo;
+                uint32_t n = hi > lo ? hi - lo : 0;
+                for (; n >= 2; n -= 2, pq += 2, pc += 2, pw0 += 2, pw1 += 2) {
+                    const double2 q0 = pq[0], q1 = pq[1];
+                    const int x0 = pc[0], x1 = pc[1];
+                    const double w00 = pw0[0], w10 = pw0[1];
+                    const double w01 = PAY == 2 ? pw1[0] : 0.0, w11 = PAY == 2 ? pw1[1] : 0.0;
+                    pair<KIND, P, F32>(na, e2, (double)(hcx - x0) + (px - q0.x), dyc + (py - q0.y), w00, w01, a0, a1, a2);
+                    pair<KIND, P, F32>(na, e2, (double)(hcx - x1) + (px - q1.x), dyc + (py - q1.y), w10, w11, a0, a1, a2);
+                }
+                if (n) {
+                    const double2 q0 = pq[0];
+                    const int x0 = pc[0];
+                    const double w00 = pw0[0], w01 = PAY == 2 ? pw1[0] : 0.0;
+                    pair<KIND, P, F32>(na, e2, (double)(hcx - x0) + (px - q0.x), dyc + (py - q0.y), w00, w01, a0, a1, a2);
                 }
             }
         }
         if (valid) {
             const int64_t o = S.perm_out[gi];
+            const double G2 = F32 ? 2.0 * na.inv_eg / na.ginv : 2.0 / (na.ginv * na.eps2g);
             if (FWD) {
                 if (WANT_PHI) out0[o] = S.far[gi] + a0 + na.offset * sum_in[0];
                 if (WANT_H) {
-                    const double G = 1.0 / na.ginv;
-                    out1[2 * o] = na.scale * fma(G, a1, S.far[S.n_out + gi]);
-                    out1[2 * o + 1] = na.scale * fma(G, a2, S.far[2 * S.n_out + gi]);
+                    out1[2 * o] = na.scale * fma(G2, a1, S.far[S.n_out + gi]);
+                    out1[2 * o + 1] = na.scale * fma(G2, a2, S.far[2 * S.n_out + gi]);
                 }
             } else if (MODE == MODE_COUNT) {
                 out0[o] = a0;
             } else if (MODE == MODE_ADJ_H) {
-                out0[o] = S.w_out[gi] * na.scale * fma(1.0 / na.ginv, a0, S.far[gi]);
+                // the accumulated offsets are source minus target: flip the sign
+                out0[o] = S.w_out[gi] * na.scale * fma(-G2, a0, S.far[gi]);
             } else {
                 out0[o] = S.w_out[gi] * (S.far[gi] + a0 + na.offset * sum_in[0]);
             }
@@ -299,14 +389,24 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     }
 }
 
-constexpr int CAP_FWD = 2048;
-constexpr int CAP_ADJ = 2048;
+// staged points per chunk (a sweep of 768 to 2048 at 2^24 points put the optimum here)
+#ifndef FN_NEAR_CAP_FWD
+#define FN_NEAR_CAP_FWD 1024
+#endif
+#ifndef FN_NEAR_CAP_ADJ
+#define FN_NEAR_CAP_ADJ 768
+#endif
+constexpr int CAP_FWD = FN_NEAR_CAP_FWD;
+constexpr int CAP_ADJ = FN_NEAR_CAP_ADJ;
 
 template <int MODE, int CAP, int P>
 hipError_t launch_p(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum, double *o0,
                     double *o1)
 {
-    k_near<MODE, CAP, P><<<nblk, NTH, 0, st>>>(S, na, sum, o0, o1);
+    if (na.f32)
+        k_near<MODE, CAP, P, true><<<nblk, NTH, 0, st>>>(S, na, sum, o0, o1);
+    else
+        k_near<MODE, CAP, P, false><<<nblk, NTH, 0, st>>>(S, na, sum, o0, o1);
     return hipGetLastError();
 }
 
@@ -368,7 +468,8 @@ hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, 
     const int nblk = S.nbx * ((g.ext[1] + NB - 1) / NB);
     if (kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
     if (kind == 1) return launch_mode<MODE_ADJ_PHI, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
-    return launch_p<MODE_COUNT, CAP_ADJ, 1>(nblk, st, S, na, sum_v, u, nullptr);
+    k_near<MODE_COUNT, CAP_ADJ, 1, false><<<nblk, NTH, 0, st>>>(S, na, sum_v, u, nullptr);
+    return hipGetLastError();
 }
 
 }  // namespace fn
