@@ -291,3 +291,27 @@ def test_error_codes(torch, fn):
     S.set_charges(dev(torch, q))
     phi, _ = S.eval()
     assert torch.isfinite(phi).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", ["disk", "magic_cylinder"])
+def test_paper_tables_claim_on_gpu(torch, fn, shape, precision):
+    """The claim of the paper's Tables 1 and 2 (fast summation error within 3.5% of the
+    direct FEM sum's error against the analytic potential), for the HIP path at the
+    paper's p = 2 on the tables' smallest meshes."""
+    from tests import test_golden_tables as gt
+    N = 400 if shape == "disk" else 1192
+    nodes, tris, bedges, M, exact = (gt.disk_case if shape == "disk" else gt.magic_case)(N)
+    print(f"paper-table case {shape} N={N} {precision}", flush=True)
+    x, w = fem.sources(nodes, tris, bedges)
+    q = fem.charges(nodes, tris, bedges, M)
+    phi1, _ = direct.forward(nodes, x, w, q, want_H=False)
+    G = gt.grid_rule(len(nodes))
+    prm = fs.Params(G=G, m=4, p=2, eps_I=4 / (G // 2))
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    z = np.zeros((len(nodes), 2))
+    phi, _, _, _, _ = run_gpu(torch, fn, nodes, x, w, q, z, z[:, 0], prm, P)
+    rms = lambda a: float(np.sqrt(np.mean((a - exact) ** 2)))
+    bound = max(gt.max_printed_gap(gt.load_table("paper_table1_disk.txt")),
+                gt.max_printed_gap(gt.load_table("paper_table2_magic_cylinder.txt")))
+    assert abs(rms(phi) - rms(phi1)) <= bound * rms(phi1)
