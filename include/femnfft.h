@@ -28,7 +28,7 @@
  *   - 2-vectors are interleaved [n][2] (x, y), FP64.  Scalars per point FP64.
  *   - All work is enqueued on the stream given to fn_create; no call waits for
  *     the device except fn_set_geometry (it reads back the bounding box) and
- *     the fn_fem_* set-up call.  Outputs are valid once the stream reaches them.
+ *     fn_mesh_set.  Outputs are valid once the stream reaches them.
  *   - The library allocates no device memory after fn_set_workspace: the caller
  *     provides one workspace buffer (e.g. a torch uint8 tensor).
  *   - Call order per context: fn_create -> fn_workspace_size -> fn_set_workspace
@@ -60,7 +60,8 @@ enum {
 
 enum {
     FN_FP64 = 0,       /* spread, FFT, gather, near field all in FP64 */
-    FN_FP32_MIXED = 1  /* FP32 spread/FFT/gather (wide accumulation); FP64 near field and final sum */
+    FN_FP32_MIXED = 1  /* FP32 spread/FFT/gather (wide accumulation); near field FP64 except its
+                          per-pair ln x and 1/x (FP32 hardware instructions); FP64 final sum */
 };
 
 /*
@@ -178,6 +179,68 @@ int fn_get_profile(fn_ctx *ctx, fn_profile *out);
 /* Message of the last error on this context (or of the last failed
  * fn_create when ctx is NULL).  Valid until the next call on the context. */
 const char *fn_last_error(const fn_ctx *ctx);
+
+/*
+ * P1 finite-element front (the paper's "Discretization" section): a triangle
+ * mesh with nodal magnetization M, the volume charge rho = -div M_h (constant per
+ * triangle) and the surface charge sigma = M_h . n on the boundary, integrated by
+ * a 3-point rule per triangle (barycentric (2/3, 1/6, 1/6) and permutations,
+ * weight |T|/3) and 2-point Gauss-Legendre per boundary edge (weight |e|/2).
+ * The paper's quadrature footnote is missing; this rule is the reading taken.
+ *
+ *   nodes   [n_nodes][2]  FP64
+ *   tris    [n_tris][3]   int32 vertex indices (either orientation)
+ *   bedges  [n_bedges][2] int32 boundary edges (a, b) with the domain on the left
+ *           of a -> b (outer boundary counter-clockwise, holes clockwise);
+ *           outward normal (b - a) rotated by -90 degrees.
+ *
+ * Sources: S = 3 n_tris + 2 n_bedges quadrature points, the 3 volume points of
+ * triangle t at 3t + k (k-th point nearest vertex k), then the 2 surface points of
+ * edge e at 3 n_tris + 2e + k (Gauss points 1/2 -+ 1/(2 sqrt 3) along a -> b).
+ * The charge operator is q = C M [S] (rho on volume points, sigma on surface
+ * points) and C^T its exact transpose (nodal 2-vectors).  The lumped mass is
+ * l_i = sum over triangles at node i of |T|/3.
+ *
+ * A mesh object holds copies of the arrays (in a caller workspace, as for the
+ * context) plus its geometry and a node -> incident slot list, so that C^T and l
+ * are fixed-order gathers (bitwise reproducible).  Every array argument is a
+ * device pointer; work runs on the mesh's stream, except inside fn_energy, which
+ * uses the context's stream.  Calls that overlap on one mesh race.
+ */
+typedef struct fn_mesh fn_mesh;
+
+/* n_nodes >= 3, n_tris >= 1, n_bedges >= 0 (sizes are fixed for the object). */
+int fn_mesh_create(int64_t n_nodes, int64_t n_tris, int64_t n_bedges, void *stream, fn_mesh **out);
+int fn_mesh_destroy(fn_mesh *mesh);
+int fn_mesh_workspace_size(const fn_mesh *mesh, size_t *bytes);
+int fn_mesh_set_workspace(fn_mesh *mesh, void *dev_ptr, size_t bytes);  /* 256-byte aligned */
+/* Copy and check the mesh (indices in range, finite nodes: FN_E_INVAL; zero-area
+ * triangles -- twice the area at most 1e-12 of |dx1 dy2| + |dy1 dx2| -- or
+ * zero-length edges: FN_E_DOMAIN), build its geometry, sources,
+ * lumped mass and incidence list.  Blocks until done. */
+int fn_mesh_set(fn_mesh *mesh, const double *nodes, const int32_t *tris, const int32_t *bedges);
+int fn_mesh_sources(fn_mesh *mesh, double *x, double *w);           /* x [S][2], w [S]; either may be NULL */
+int fn_mesh_lumped_mass(fn_mesh *mesh, double *ell);                /* ell [n_nodes] */
+int fn_mesh_charges(fn_mesh *mesh, const double *M, double *q);     /* M [n_nodes][2] -> q [S] */
+int fn_mesh_charges_T(fn_mesh *mesh, const double *u, double *out); /* u [S] -> out [n_nodes][2] */
+
+/* Use the mesh's nodes as targets and its quadrature points as sources of the
+ * context (fn_set_geometry with them). */
+int fn_bind_mesh(fn_ctx *ctx, fn_mesh *mesh);
+
+/* Demagnetizing energy of nodal magnetization M [n_nodes][2] and its gradient:
+ *     H = fast-sum field at the nodes of q = C M,
+ *     E = -1/2 sum_i l_i M_i . H_i                     -> *E (one device double)
+ *     grad = dE/dM = -1/2 (l H + C^T u),  u = H-adjoint of V = l M
+ *                                                      -> grad [n_nodes][2] (may be NULL)
+ * Needs fn_bind_mesh(ctx, mesh) after the mesh's last fn_mesh_set.  Runs on the
+ * context's stream; uses the mesh's scratch (q, H, V, u) and the context's
+ * charges (a following fn_eval sees C M). */
+int fn_energy(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *grad);
+
+/* Message of the last error on this mesh (or of the last failed fn_mesh_create
+ * when mesh is NULL). */
+const char *fn_mesh_last_error(const fn_mesh *mesh);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,11 @@ memory and the current stream) into the C calls.
     s.set_charges(q)
     phi, H = s.eval()
     u = s.adjoint_H(V)                                       # u_j = w_j sum_i V_i.(-grad G)(r_i - r_j)
+
+    mesh = Mesh(nodes, tris, bedges)                         # P1 triangle mesh (float64 / int32 tensors)
+    s.bind_mesh(mesh)                                        # targets = nodes, sources = quadrature points
+    E, dE = s.energy(M)                                      # demagnetizing energy and dE/dM
+    E = DemagEnergy.apply(M, s, mesh)                        # the same as a torch autograd function
 """
 from __future__ import annotations
 
@@ -17,7 +22,7 @@ import ctypes
 from . import _lib
 from ._lib import FN_FP32_MIXED, FN_FP64, FemNfftError  # noqa: F401
 
-__all__ = ["Solver", "default_params", "FN_FP64", "FN_FP32_MIXED", "FemNfftError"]
+__all__ = ["Solver", "Mesh", "DemagEnergy", "default_params", "FN_FP64", "FN_FP32_MIXED", "FemNfftError"]
 
 
 def default_params(grid):
@@ -31,12 +36,13 @@ def _torch():
     return torch
 
 
-def _dev_ptr(t, name, shape_tail=()):
+def _dev_ptr(t, name, shape_tail=(), dtype=None):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
-    if t.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64")
+    want = dtype if dtype is not None else torch.float64
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {want}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if shape_tail and tuple(t.shape[1:]) != tuple(shape_tail):
@@ -125,6 +131,30 @@ class Solver:
         self._check(_lib.lib().fn_eval_phi_adjoint(self._ctx, _dev_ptr(v, "v"), _dev_ptr(u, "u")))
         return u
 
+    def bind_mesh(self, mesh):
+        """Targets = the mesh's nodes, sources = its quadrature points (fn_bind_mesh)."""
+        torch = _torch()
+        L = _lib.lib()
+        need = self.workspace_bytes(mesh.n_nodes, mesh.n_sources)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._check(L.fn_set_workspace(self._ctx, ctypes.c_void_p(self._ws.data_ptr()), ctypes.c_size_t(need)))
+        self._check(L.fn_bind_mesh(self._ctx, mesh._mesh))
+        self.n_tgt, self.n_src = mesh.n_nodes, mesh.n_sources
+        self._mesh = mesh
+        return self
+
+    def energy(self, M, grad=True):
+        """E = -1/2 sum_i l_i M_i . H_i (0-d tensor) and, if grad, dE/dM [n_nodes, 2] (fn_energy)."""
+        torch = _torch()
+        mesh = self._mesh
+        E = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty(mesh.n_nodes, 2, dtype=torch.float64, device=self.device) if grad else None
+        self._check(_lib.lib().fn_energy(self._ctx, mesh._mesh, _dev_ptr(M, "M", (2,)), ctypes.c_void_p(E.data_ptr()),
+                                         _dev_ptr(g, "grad", (2,)) if g is not None else None))
+        return E, g
+
     def set_profiling(self, enable=True):
         self._check(_lib.lib().fn_set_profiling(self._ctx, int(bool(enable))))
 
@@ -140,3 +170,95 @@ class Solver:
         return dict(centre=tuple(i.centre), scale=i.scale, n_tgt=i.n_tgt, n_src=i.n_src,
                     win_lo=tuple(i.win_lo), win_ext=tuple(i.win_ext), tiles=tuple(i.tiles),
                     near_cells=i.near_cells, workspace_bytes=i.workspace_bytes, near_pairs=i.near_pairs)
+
+
+class Mesh:
+    """A P1 triangle mesh on the device (fn_mesh_*): nodes [N, 2] float64, tris [T, 3] int32,
+    bedges [E, 2] int32 (domain on the left of each boundary edge)."""
+
+    def __init__(self, nodes, tris, bedges, stream=None):
+        torch = _torch()
+        L = _lib.lib()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n_nodes, self.n_tris, self.n_bedges = int(nodes.shape[0]), int(tris.shape[0]), int(bedges.shape[0])
+        self.n_sources = 3 * self.n_tris + 2 * self.n_bedges
+        m = ctypes.c_void_p()
+        _lib.check_mesh(L.fn_mesh_create(self.n_nodes, self.n_tris, self.n_bedges,
+                                         ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(m)))
+        self._mesh = m
+        b = ctypes.c_size_t()
+        self._check(L.fn_mesh_workspace_size(m, ctypes.byref(b)))
+        self._ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        self._check(L.fn_mesh_set_workspace(m, ctypes.c_void_p(self._ws.data_ptr()), b))
+        self._check(L.fn_mesh_set(m, _dev_ptr(nodes, "nodes", (2,)), _dev_ptr(tris, "tris", (3,), torch.int32),
+                                  _dev_ptr(bedges, "bedges", (2,), torch.int32) if self.n_bedges else None))
+
+    def __del__(self):
+        m = getattr(self, "_mesh", None)
+        if m:
+            try:
+                _lib.lib().fn_mesh_destroy(m)
+            except Exception:
+                pass
+            self._mesh = None
+
+    def _check(self, rc):
+        _lib.check_mesh(rc, self._mesh)
+
+    def sources(self):
+        torch = _torch()
+        x = torch.empty(self.n_sources, 2, dtype=torch.float64, device=self.device)
+        w = torch.empty(self.n_sources, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_mesh_sources(self._mesh, _dev_ptr(x, "x", (2,)), _dev_ptr(w, "w")))
+        return x, w
+
+    def lumped_mass(self):
+        torch = _torch()
+        ell = torch.empty(self.n_nodes, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_mesh_lumped_mass(self._mesh, _dev_ptr(ell, "ell")))
+        return ell
+
+    def charges(self, M):
+        torch = _torch()
+        q = torch.empty(self.n_sources, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_mesh_charges(self._mesh, _dev_ptr(M, "M", (2,)), _dev_ptr(q, "q")))
+        return q
+
+    def charges_T(self, u):
+        torch = _torch()
+        out = torch.empty(self.n_nodes, 2, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_mesh_charges_T(self._mesh, _dev_ptr(u, "u"), _dev_ptr(out, "out", (2,))))
+        return out
+
+
+def _demag_energy_class():
+    torch = _torch()
+
+    class DemagEnergy(torch.autograd.Function):
+        """E(M) = -1/2 sum_i l_i M_i . H_i(M) with its exact gradient from the library
+        (fn_energy); the solver must be bound to the mesh (Solver.bind_mesh)."""
+
+        @staticmethod
+        def forward(ctx, M, solver, mesh):
+            if getattr(solver, "_mesh", None) is not mesh:
+                raise FemNfftError(2, "solver is not bound to this mesh (Solver.bind_mesh)")
+            Mc = M.detach().contiguous()
+            E, g = solver.energy(Mc, grad=ctx.needs_input_grad[0])
+            ctx.save_for_backward(g if g is not None else E)
+            return E
+
+        @staticmethod
+        def backward(ctx, gE):
+            (g,) = ctx.saved_tensors
+            return gE * g, None, None
+
+    return DemagEnergy
+
+
+def __getattr__(name):
+    if name == "DemagEnergy":
+        cls = _demag_energy_class()
+        globals()["DemagEnergy"] = cls
+        return cls
+    raise AttributeError(name)

@@ -22,6 +22,9 @@ SYMBOLS = (
     "fn_set_geometry", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
     "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_get_info", "fn_last_error",
     "fn_set_profiling", "fn_get_profile",
+    "fn_mesh_create", "fn_mesh_destroy", "fn_mesh_workspace_size", "fn_mesh_set_workspace", "fn_mesh_set",
+    "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
+    "fn_energy", "fn_mesh_last_error",
 )
 
 STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather", "near",
@@ -80,6 +83,18 @@ def lib():
         "fn_last_error": ([P], ctypes.c_char_p),
         "fn_set_profiling": ([P, ctypes.c_int], ctypes.c_int),
         "fn_get_profile": ([P, ctypes.POINTER(Profile)], ctypes.c_int),
+        "fn_mesh_create": ([I64, I64, I64, P, ctypes.POINTER(P)], ctypes.c_int),
+        "fn_mesh_destroy": ([P], ctypes.c_int),
+        "fn_mesh_workspace_size": ([P, ctypes.POINTER(SZ)], ctypes.c_int),
+        "fn_mesh_set_workspace": ([P, P, SZ], ctypes.c_int),
+        "fn_mesh_set": ([P, P, P, P], ctypes.c_int),
+        "fn_mesh_sources": ([P, P, P], ctypes.c_int),
+        "fn_mesh_lumped_mass": ([P, P], ctypes.c_int),
+        "fn_mesh_charges": ([P, P, P], ctypes.c_int),
+        "fn_mesh_charges_T": ([P, P, P], ctypes.c_int),
+        "fn_bind_mesh": ([P, P], ctypes.c_int),
+        "fn_energy": ([P, P, P, P, P], ctypes.c_int),
+        "fn_mesh_last_error": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -92,4 +107,10 @@ def lib():
 def check(rc, ctx=None):
     if rc != FN_OK:
         msg = lib().fn_last_error(ctx)
+        raise FemNfftError(rc, msg.decode() if msg else "")
+
+
+def check_mesh(rc, mesh=None):
+    if rc != FN_OK:
+        msg = lib().fn_mesh_last_error(mesh)
         raise FemNfftError(rc, msg.decode() if msg else "")

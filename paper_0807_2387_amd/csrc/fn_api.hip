@@ -251,6 +251,13 @@ using namespace fn;
 
 static thread_local std::string g_create_err;
 
+int ctx_hip(fn_ctx *ctx, hipError_t e)
+{
+    if (e == hipSuccess) return FN_OK;
+    ctx->err = std::string("HIP error: ") + hipGetErrorString(e);
+    return FN_E_DEVICE;
+}
+
 #define FN_SET_ERR(ctx, code, msg)         \
     do {                                   \
         (ctx)->err = (msg);                \
@@ -515,6 +522,7 @@ int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_
     int rc = check_device(c);
     if (rc) return rc;
     c->geom_ready = c->charges_ready = false;
+    c->mesh = nullptr;
     Layout L = make_layout(c->plan, n_tgt, n_src);
     if (L.total > c->ws_bytes) {
         char msg[160];

@@ -88,6 +88,8 @@ struct Layout {
 
 }  // namespace fn
 
+struct fn_mesh;
+
 struct fn_ctx {
     fn_params prm{};
     fn::Plan plan;
@@ -108,8 +110,13 @@ struct fn_ctx {
     bool plan_ready = false;
     bool geom_ready = false;
     bool charges_ready = false;
+    const fn_mesh *mesh = nullptr;   // mesh whose nodes and sources are the geometry (fn_bind_mesh)
+    uint64_t mesh_stamp = 0;
     std::string err;
 };
+
+// FN_OK, or FN_E_DEVICE with the HIP message stored in ctx->err
+int ctx_hip(fn_ctx *ctx, hipError_t e);
 
 namespace fn {
 
