@@ -106,6 +106,14 @@ typedef struct fn_ctx fn_ctx;
  * precision FN_FP32_MIXED. */
 int fn_params_default(fn_params *p, int32_t grid);
 
+/* Parameters for n_tgt targets and n_src sources at the accuracy the library is
+ * tuned for (relative L2 error of phi, H and the adjoints a few 1e-7 against the
+ * exact sum on FEM meshes): grid G = 2^ceil(log2(2 sqrt((n_tgt + n_src)/2)))
+ * (about one bandwidth cell per point, clamped to 64..8192), m = 6, and
+ * p = 8, eps_I = 7/(G/2) -- or p = 10, eps_I = 8/(G/2) below 2^22 points in
+ * total, where the boundary-layer error of H is a larger share. */
+int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p);
+
 /* Create a context bound to the current device and to the HIP stream
  * `stream` (hipStream_t, may be NULL for the null stream).  Validates the
  * parameters and prepares the host-side plan (regularization polynomials,
@@ -241,6 +249,48 @@ int fn_energy(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *gr
 /* Message of the last error on this mesh (or of the last failed fn_mesh_create
  * when mesh is NULL). */
 const char *fn_mesh_last_error(const fn_mesh *mesh);
+
+/*
+ * Batches: B independent problems (e.g. one per mesh) in one object, each with
+ * its own parameters (typically its own grid), evaluated on one stream.  Inputs
+ * and outputs are the members' arrays concatenated; tgt_off / src_off are HOST
+ * arrays of B + 1 offsets (0 = tgt_off[0] <= tgt_off[1] <= ...), in points.  Each
+ * member needs at least one point.  Member b's targets are
+ * tgt_xy[tgt_off[b] .. tgt_off[b+1]) and so on; phi, H, q, V, v, u likewise.
+ * The workspace is one caller buffer carved into the members' workspaces.
+ */
+typedef struct fn_batch fn_batch;
+int fn_batch_create(int32_t count, const fn_params *params /* [count] */, void *stream, fn_batch **out);
+int fn_batch_destroy(fn_batch *batch);
+int fn_batch_workspace_size(fn_batch *batch, const int64_t *tgt_off, const int64_t *src_off, size_t *bytes);
+int fn_batch_set_workspace(fn_batch *batch, void *dev_ptr, size_t bytes);  /* 256-byte aligned */
+int fn_set_geometry_batch(fn_batch *batch, const int64_t *tgt_off, const double *tgt_xy,
+                          const int64_t *src_off, const double *src_xy, const double *src_w);
+int fn_batch_set_charges(fn_batch *batch, const double *q);
+int fn_batch_eval(fn_batch *batch, double *phi, double *H);        /* either may be NULL, not both */
+int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u);
+int fn_batch_eval_phi_adjoint(fn_batch *batch, const double *v, double *u);
+int fn_batch_member(fn_batch *batch, int32_t i, fn_ctx **out);    /* borrow member i's context */
+const char *fn_batch_last_error(const fn_batch *batch);
+
+/*
+ * Graph capture.  fn_graph_begin(stream) starts capturing (hipStreamCaptureModeThreadLocal)
+ * the work this thread then issues on `stream` (non-NULL): fn_set_charges,
+ * fn_eval*, fn_eval_*_adjoint, fn_energy, fn_mesh_charges(_T) and the fn_batch_*
+ * evaluations record their kernels with the argument values and pointers of that
+ * moment; fn_graph_end instantiates the graph; fn_graph_launch replays it (on any
+ * stream), reading whatever the recorded input buffers hold then.  Calls that
+ * wait for the device (fn_set_geometry, fn_mesh_set, fn_get_profile) return
+ * FN_E_STATE during capture; stage profiling is not recorded inside graphs.  The
+ * recorded contexts, meshes and buffers must outlive the graph, and replays of
+ * one graph (or a replay and a direct call on the same context) must not overlap.
+ */
+typedef struct fn_graph fn_graph;
+int fn_graph_begin(void *stream);
+int fn_graph_end(void *stream, fn_graph **out);
+int fn_graph_launch(fn_graph *graph, void *stream);
+int fn_graph_destroy(fn_graph *graph);
+const char *fn_graph_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -14,20 +14,36 @@ memory and the current stream) into the C calls.
     s.bind_mesh(mesh)                                        # targets = nodes, sources = quadrature points
     E, dE = s.energy(M)                                      # demagnetizing energy and dE/dM
     E = DemagEnergy.apply(M, s, mesh)                        # the same as a torch autograd function
+
+    b = Batch([dict(grid=512), dict(grid=1024)])             # independent problems on one stream
+    b.set_geometry(tgt_off, tgt_xy, src_off, src_xy, src_w)  # CSR offsets, concatenated arrays
+    g = Graph()
+    with g.capture(stream):                                  # record library calls issued on `stream`
+        b.set_charges(q); b.eval(out_phi=phi, out_H=H)
+    g.launch(stream)                                         # replay them with one launch
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 from . import _lib
 from ._lib import FN_FP32_MIXED, FN_FP64, FemNfftError  # noqa: F401
 
-__all__ = ["Solver", "Mesh", "DemagEnergy", "default_params", "FN_FP64", "FN_FP32_MIXED", "FemNfftError"]
+__all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params", "FN_FP64", "FN_FP32_MIXED",
+           "FemNfftError"]
 
 
 def default_params(grid):
     p = _lib.Params()
     _lib.check(_lib.lib().fn_params_default(ctypes.byref(p), int(grid)))
+    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision)
+
+
+def auto_params(n_tgt, n_src, precision=FN_FP32_MIXED):
+    """Grid and regularization for a problem size (fn_params_auto)."""
+    p = _lib.Params()
+    _lib.check(_lib.lib().fn_params_auto(int(n_tgt), int(n_src), int(precision), ctypes.byref(p)))
     return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision)
 
 
@@ -230,6 +246,123 @@ class Mesh:
         out = torch.empty(self.n_nodes, 2, dtype=torch.float64, device=self.device)
         self._check(_lib.lib().fn_mesh_charges_T(self._mesh, _dev_ptr(u, "u"), _dev_ptr(out, "out", (2,))))
         return out
+
+
+def _params(d):
+    base = default_params(int(d["grid"]))
+    base.update({k: v for k, v in d.items() if v is not None})
+    return _lib.Params(grid=int(base["grid"]), m=int(base["m"]), p=int(base["p"]), precision=int(base["precision"]),
+                       eps_I=float(base["eps_I"]), eps_B=float(base["eps_B"]), flags=0, reserved=0)
+
+
+class Batch:
+    """Independent problems evaluated on one stream (fn_batch_*): members' arrays are
+    concatenated; offsets are host sequences of B + 1 point counts (CSR)."""
+
+    def __init__(self, params, stream=None):
+        torch = _torch()
+        L = _lib.lib()
+        self.count = len(params)
+        arr = (_lib.Params * self.count)(*[_params(dict(d)) for d in params])
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = ctypes.c_void_p()
+        _lib.check_batch(L.fn_batch_create(self.count, arr, ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(b)))
+        self._b = b
+        self._ws = None
+
+    def __del__(self):
+        b = getattr(self, "_b", None)
+        if b:
+            try:
+                _lib.lib().fn_batch_destroy(b)
+            except Exception:
+                pass
+            self._b = None
+
+    def _check(self, rc):
+        _lib.check_batch(rc, self._b)
+
+    def set_geometry(self, tgt_off, tgt_xy, src_off, src_xy, src_w):
+        torch = _torch()
+        L = _lib.lib()
+        to = (ctypes.c_int64 * (self.count + 1))(*[int(v) for v in tgt_off])
+        so = (ctypes.c_int64 * (self.count + 1))(*[int(v) for v in src_off])
+        need = ctypes.c_size_t()
+        self._check(L.fn_batch_workspace_size(self._b, to, so, ctypes.byref(need)))
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = None
+            self._ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+            self._check(L.fn_batch_set_workspace(self._b, ctypes.c_void_p(self._ws.data_ptr()), need))
+        self._check(L.fn_set_geometry_batch(self._b, to, _dev_ptr(tgt_xy, "tgt_xy", (2,)), so,
+                                            _dev_ptr(src_xy, "src_xy", (2,)), _dev_ptr(src_w, "src_w")))
+        self.n_tgt, self.n_src = int(tgt_off[-1]), int(src_off[-1])
+        return self
+
+    def set_charges(self, q):
+        self._check(_lib.lib().fn_batch_set_charges(self._b, _dev_ptr(q, "q")))
+        return self
+
+    def eval(self, out_phi=None, out_H=None):
+        torch = _torch()
+        p = out_phi if out_phi is not None else torch.empty(self.n_tgt, dtype=torch.float64, device=self.device)
+        h = out_H if out_H is not None else torch.empty(self.n_tgt, 2, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_batch_eval(self._b, _dev_ptr(p, "phi"), _dev_ptr(h, "H", (2,))))
+        return p, h
+
+    def adjoint_H(self, V, out=None):
+        torch = _torch()
+        u = out if out is not None else torch.empty(self.n_src, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_batch_eval_H_adjoint(self._b, _dev_ptr(V, "V", (2,)), _dev_ptr(u, "u")))
+        return u
+
+    def adjoint_phi(self, v, out=None):
+        torch = _torch()
+        u = out if out is not None else torch.empty(self.n_src, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_batch_eval_phi_adjoint(self._b, _dev_ptr(v, "v"), _dev_ptr(u, "u")))
+        return u
+
+
+class Graph:
+    """A HIP graph of library calls recorded on one (non-default) stream (fn_graph_*)."""
+
+    def __init__(self):
+        self._g = None
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g:
+            try:
+                _lib.lib().fn_graph_destroy(g)
+            except Exception:
+                pass
+            self._g = None
+
+    @contextlib.contextmanager
+    def capture(self, stream):
+        L = _lib.lib()
+        if self._g:
+            L.fn_graph_destroy(self._g)
+            self._g = None
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        _lib.check_graph(L.fn_graph_begin(sp))
+        ok = False
+        try:
+            yield self
+            ok = True
+        finally:
+            g = ctypes.c_void_p()
+            rc = L.fn_graph_end(sp, ctypes.byref(g))
+            if ok:
+                _lib.check_graph(rc)
+                self._g = g
+            elif g:
+                L.fn_graph_destroy(g)
+
+    def launch(self, stream):
+        if not self._g:
+            raise FemNfftError(2, "nothing captured")
+        _lib.check_graph(_lib.lib().fn_graph_launch(self._g, ctypes.c_void_p(stream.cuda_stream)))
 
 
 def _demag_energy_class():

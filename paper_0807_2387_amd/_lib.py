@@ -18,13 +18,17 @@ ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: 
 
 # exported C-ABI symbols (include/femnfft.h)
 SYMBOLS = (
-    "fn_params_default", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
+    "fn_params_default", "fn_params_auto", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
     "fn_set_geometry", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
     "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_get_info", "fn_last_error",
     "fn_set_profiling", "fn_get_profile",
     "fn_mesh_create", "fn_mesh_destroy", "fn_mesh_workspace_size", "fn_mesh_set_workspace", "fn_mesh_set",
     "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
     "fn_energy", "fn_mesh_last_error",
+    "fn_batch_create", "fn_batch_destroy", "fn_batch_workspace_size", "fn_batch_set_workspace",
+    "fn_set_geometry_batch", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint",
+    "fn_batch_eval_phi_adjoint", "fn_batch_member", "fn_batch_last_error",
+    "fn_graph_begin", "fn_graph_end", "fn_graph_launch", "fn_graph_destroy", "fn_graph_last_error",
 )
 
 STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather", "near",
@@ -68,6 +72,7 @@ def lib():
     P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
     sig = {
         "fn_params_default": ([ctypes.POINTER(Params), I32], ctypes.c_int),
+        "fn_params_auto": ([I64, I64, I32, ctypes.POINTER(Params)], ctypes.c_int),
         "fn_create": ([ctypes.POINTER(Params), P, ctypes.POINTER(P)], ctypes.c_int),
         "fn_destroy": ([P], ctypes.c_int),
         "fn_workspace_size": ([P, I64, I64, ctypes.POINTER(SZ)], ctypes.c_int),
@@ -95,6 +100,22 @@ def lib():
         "fn_bind_mesh": ([P, P], ctypes.c_int),
         "fn_energy": ([P, P, P, P, P], ctypes.c_int),
         "fn_mesh_last_error": ([P], ctypes.c_char_p),
+        "fn_batch_create": ([I32, ctypes.POINTER(Params), P, ctypes.POINTER(P)], ctypes.c_int),
+        "fn_batch_destroy": ([P], ctypes.c_int),
+        "fn_batch_workspace_size": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(SZ)], ctypes.c_int),
+        "fn_batch_set_workspace": ([P, P, SZ], ctypes.c_int),
+        "fn_set_geometry_batch": ([P, ctypes.POINTER(I64), P, ctypes.POINTER(I64), P, P], ctypes.c_int),
+        "fn_batch_set_charges": ([P, P], ctypes.c_int),
+        "fn_batch_eval": ([P, P, P], ctypes.c_int),
+        "fn_batch_eval_H_adjoint": ([P, P, P], ctypes.c_int),
+        "fn_batch_eval_phi_adjoint": ([P, P, P], ctypes.c_int),
+        "fn_batch_member": ([P, I32, ctypes.POINTER(P)], ctypes.c_int),
+        "fn_batch_last_error": ([P], ctypes.c_char_p),
+        "fn_graph_begin": ([P], ctypes.c_int),
+        "fn_graph_end": ([P, ctypes.POINTER(P)], ctypes.c_int),
+        "fn_graph_launch": ([P, P], ctypes.c_int),
+        "fn_graph_destroy": ([P], ctypes.c_int),
+        "fn_graph_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -107,6 +128,18 @@ def lib():
 def check(rc, ctx=None):
     if rc != FN_OK:
         msg = lib().fn_last_error(ctx)
+        raise FemNfftError(rc, msg.decode() if msg else "")
+
+
+def check_batch(rc, batch=None):
+    if rc != FN_OK:
+        msg = lib().fn_batch_last_error(batch)
+        raise FemNfftError(rc, msg.decode() if msg else "")
+
+
+def check_graph(rc):
+    if rc != FN_OK:
+        msg = lib().fn_graph_last_error()
         raise FemNfftError(rc, msg.decode() if msg else "")
 
 

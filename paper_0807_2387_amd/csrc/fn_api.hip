@@ -286,7 +286,7 @@ static constexpr size_t PROF_MAX = 8192;
 
 static int prof_begin(fn_ctx *c, int st)
 {
-    if (!c->prof_on) return -1;
+    if (!c->prof_on || stream_capturing(c->stream)) return -1;
     if (c->prof_next >= PROF_MAX) {
         c->prof.dropped++;
         return -1;
@@ -331,6 +331,24 @@ int fn_params_default(fn_params *p, int32_t grid)
     p->precision = FN_FP32_MIXED;
     p->eps_I = grid >= 2 ? 7.0 / (grid / 2) : 0.0;
     p->eps_B = 1.0 / 16.0;
+    return FN_OK;
+}
+
+int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p)
+{
+    if (!p || n_tgt < 0 || n_src < 0) return FN_E_INVAL;
+    // about 4 grid cells (one bandwidth cell) per target and per source on average:
+    // G = 2^ceil(log2(2 sqrt((n_tgt + n_src) / 2)))
+    const double want = 2.0 * std::sqrt(0.5 * (double)(n_tgt + n_src));
+    int32_t G = 64;
+    while (G < MAXG && G < want) G *= 2;
+    fn_params_default(p, G);
+    p->precision = precision;
+    if (n_tgt + n_src < ((int64_t)1 << 22)) {
+        // small problems: the boundary-layer error of H weighs more and the near field is cheap
+        p->p = 10;
+        p->eps_I = 8.0 / (G / 2);
+    }
     return FN_OK;
 }
 
@@ -519,6 +537,7 @@ int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_
         FN_SET_ERR(c, FN_E_INVAL, "need n_tgt, n_src >= 0, n_tgt + n_src >= 1, both < 2^31");
     if ((n_tgt > 0 && !tgt_xy) || (n_src > 0 && (!src_xy || !src_w)))
         FN_SET_ERR(c, FN_E_INVAL, "NULL point or weight array");
+    if (stream_capturing(c->stream)) FN_SET_ERR(c, FN_E_STATE, "fn_set_geometry waits for the device: not allowed during graph capture");
     int rc = check_device(c);
     if (rc) return rc;
     c->geom_ready = c->charges_ready = false;
@@ -779,6 +798,7 @@ int fn_set_profiling(fn_ctx *ctx, int enable)
 int fn_get_profile(fn_ctx *ctx, fn_profile *out)
 {
     if (!ctx || !out) return FN_E_INVAL;
+    if (stream_capturing(ctx->stream)) FN_SET_ERR(ctx, FN_E_STATE, "fn_get_profile waits for the device: not allowed during graph capture");
     for (size_t i = 0; i < ctx->prof_next; ++i) {
         FN_HIP(ctx, hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
         float ms = 0.f;

@@ -407,6 +407,7 @@ int fn_mesh_set(fn_mesh *mesh, const double *nodes, const int32_t *tris, const i
     fn_mesh *m = mesh;
     if (!m->ws) MESH_ERR(m, FN_E_STATE, "fn_mesh_set_workspace must be called before fn_mesh_set");
     if (!nodes || !tris || (m->E > 0 && !bedges)) MESH_ERR(m, FN_E_INVAL, "NULL mesh array");
+    if (stream_capturing(m->stream)) MESH_ERR(m, FN_E_STATE, "fn_mesh_set waits for the device: not allowed during graph capture");
     int rc = mesh_select_device(m);
     if (rc) return rc;
     m->ready = false;

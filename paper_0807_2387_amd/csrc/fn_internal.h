@@ -118,6 +118,13 @@ struct fn_ctx {
 // FN_OK, or FN_E_DEVICE with the HIP message stored in ctx->err
 int ctx_hip(fn_ctx *ctx, hipError_t e);
 
+// true while work issued on `st` is being captured into a graph
+inline bool stream_capturing(hipStream_t st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
 namespace fn {
 
 // ---- kernel launchers (defined in the .hip files) ----

@@ -1,0 +1,177 @@
+"""Batches (fn_batch_*) and graph capture (fn_graph_*) through the C-ABI.
+
+Graph replays run the very kernels of the eager calls on the same data, so a replay
+must equal the eager result bitwise; every replay is checked, with eager work and
+device synchronizations between replays.  Batch members must match the oracle as
+single contexts do (FP64 1e-10 / FP32 1e-6 vs O2; 1e-6 vs O1 at the default
+parameters).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, fem
+from oracle import fastsum as fs
+from tests.conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def fn():
+    import paper_0807_2387_amd as _fn
+    return _fn
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def test_graph_replays_equal_eager(torch, fn):
+    print("graph replay: single context", flush=True)
+    y, x, w, q = synth.random_cloud(20000, 30011, seed=21)
+    rng = np.random.default_rng(22)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        S = fn.Solver(grid=512, m=6, p=8, eps_I=7 / 256, precision=fn.FN_FP32_MIXED)
+        S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
+        qd, Vd = dev(torch, q), dev(torch, rng.standard_normal((len(y), 2)))
+        phi = torch.empty(len(y), dtype=torch.float64, device="cuda")
+        H = torch.empty(len(y), 2, dtype=torch.float64, device="cuda")
+        u = torch.empty(len(x), dtype=torch.float64, device="cuda")
+        S.set_charges(qd)  # warm-up: per-kernel attributes are set on first use
+        S.eval(out_phi=phi, out_H=H)
+        S.adjoint_H(Vd, out=u)
+        g = fn.Graph()
+        with g.capture(st):
+            S.set_charges(qd)
+            S.eval(out_phi=phi, out_H=H)
+            S.adjoint_H(Vd, out=u)
+        for rep in range(3):
+            qd.copy_(dev(torch, rng.standard_normal(len(x))))
+            Vd.copy_(dev(torch, rng.standard_normal((len(y), 2))))
+            S.set_charges(qd)
+            pe, he = S.eval()
+            ue = S.adjoint_H(Vd)
+            st.synchronize()
+            g.launch(st)
+            st.synchronize()
+            assert torch.equal(phi, pe) and torch.equal(H, he) and torch.equal(u, ue), f"replay {rep}"
+
+
+def member_clouds():
+    # (nt, ns, grid, p, c, seed): different sizes and grids in one batch
+    return [(700, 900, 64, 4, 4.0, 31), (3000, 2100, 128, 6, 6.0, 32), (12000, 15013, 256, 8, 7.0, 33),
+            (1, 5, 64, 2, 2.0, 34), (5000, 1, 128, 4, 4.0, 35), (9000, 9000, 256, 8, 7.0, 36)]
+
+
+def concat(parts):
+    off = np.concatenate([[0], np.cumsum([len(a) for a in parts])]).astype(np.int64)
+    return off, np.concatenate(parts, axis=0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_members_match_oracle(torch, fn, precision):
+    print(f"batch vs O2 {precision}", flush=True)
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    ys, xs, ws, qs, Vs, vs, prms = [], [], [], [], [], [], []
+    for nt, ns, G, p, c, seed in member_clouds():
+        y, x, w, q = synth.random_cloud(nt, ns, seed, neutral=ns > 1)
+        rng = np.random.default_rng(seed + 7)
+        ys.append(y), xs.append(x), ws.append(w), qs.append(q)
+        Vs.append(rng.standard_normal((nt, 2))), vs.append(rng.standard_normal(nt))
+        prms.append(fs.Params(G=G, m=6, p=p, eps_I=c / (G // 2)))
+    toff, Y = concat(ys)
+    soff, X = concat(xs)
+    W, Q, V, v = np.concatenate(ws), np.concatenate(qs), np.concatenate(Vs), np.concatenate(vs)
+    B = fn.Batch([dict(grid=pr.G, m=pr.m, p=pr.p, eps_I=pr.eps_I, precision=P) for pr in prms])
+    B.set_geometry(toff, dev(torch, Y), soff, dev(torch, X), dev(torch, W))
+    B.set_charges(dev(torch, Q))
+    phi, H = B.eval()
+    u = B.adjoint_H(dev(torch, V))
+    up = B.adjoint_phi(dev(torch, v))
+    phi, H, u, up = (a.cpu().numpy() for a in (phi, H, u, up))
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    for i, pr in enumerate(prms):
+        F = fs.FastSum(ys[i], xs[i], ws[i], pr)
+        p2, h2 = F.forward(qs[i])
+        t, s = slice(toff[i], toff[i + 1]), slice(soff[i], soff[i + 1])
+        errs = dict(phi=rel_l2(phi[t], p2), H=rel_l2(H[t], h2), HT=rel_l2(u[s], F.adjoint_H(Vs[i])),
+                    phiT=rel_l2(up[s], F.adjoint_phi(vs[i])))
+        print(i, errs, flush=True)
+        assert max(errs.values()) < tol, (i, errs)
+
+
+@pytest.mark.slow
+def test_c3_batch_of_64_meshes_vs_direct_sum(torch, fn):
+    print("C3: generating 64 meshes", flush=True)
+    meshes = synth.batch_meshes()
+    ys, xs, ws, qs, Vs = [], [], [], [], []
+    for m in meshes:
+        x, w = fem.sources(m["nodes"], m["tris"], m["bedges"])
+        ys.append(m["nodes"]), xs.append(x), ws.append(w)
+        qs.append(fem.charges(m["nodes"], m["tris"], m["bedges"], m["M"]))
+        # the adjoint input of the energy gradient: V = l M (lumped mass times M)
+        Vs.append(fem.lumped_mass(m["nodes"], m["tris"])[:, None] * m["M"])
+    toff, Y = concat(ys)
+    soff, X = concat(xs)
+    W, Q, V = np.concatenate(ws), np.concatenate(qs), np.concatenate(Vs)
+    rng = np.random.default_rng(64)
+    print(f"C3: {len(Y)} nodes, {len(X)} sources", flush=True)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        B = fn.Batch([fn.auto_params(len(y), len(x), fn.FN_FP32_MIXED) for y, x in zip(ys, xs)])
+        B.set_geometry(toff, dev(torch, Y), soff, dev(torch, X), dev(torch, W))
+        Qd, Vd = dev(torch, Q), dev(torch, V)
+        phi = torch.empty(len(Y), dtype=torch.float64, device="cuda")
+        H = torch.empty(len(Y), 2, dtype=torch.float64, device="cuda")
+        u = torch.empty(len(X), dtype=torch.float64, device="cuda")
+
+        def step():
+            B.set_charges(Qd)
+            B.eval(out_phi=phi, out_H=H)
+            B.adjoint_H(Vd, out=u)
+
+        step()
+        st.synchronize()
+        a = time.perf_counter()
+        for _ in range(3):
+            step()
+        st.synchronize()
+        t_eager = (time.perf_counter() - a) / 3
+        ref = (phi.clone(), H.clone(), u.clone())
+        g = fn.Graph()
+        with g.capture(st):
+            step()
+        st.synchronize()
+        a = time.perf_counter()
+        for _ in range(3):
+            g.launch(st)
+        st.synchronize()
+        t_graph = (time.perf_counter() - a) / 3
+        assert torch.equal(phi, ref[0]) and torch.equal(H, ref[1]) and torch.equal(u, ref[2])
+    print(f"C3 step (forward + H adjoint): eager {t_eager * 1e3:.2f} ms, graph {t_graph * 1e3:.2f} ms, "
+          f"{(len(Y) + len(X)) / t_graph:.3e} points/s", flush=True)
+    phi, H, u = phi.cpu().numpy(), H.cpu().numpy(), u.cpu().numpy()
+    e_phi, e_H, e_u, r_phi, r_H, r_u = [], [], [], [], [], []
+    for i in range(len(meshes)):
+        it = np.sort(rng.choice(len(ys[i]), 64, replace=False))
+        js = np.sort(rng.choice(len(xs[i]), 64, replace=False))
+        p1, h1 = direct.forward(ys[i][it], xs[i], ws[i], qs[i])
+        u1 = direct.adjoint(ys[i], xs[i][js], ws[i][js], V=V[toff[i]:toff[i + 1]])
+        e_phi.append(phi[toff[i] + it] - p1), r_phi.append(p1)
+        e_H.append(H[toff[i] + it] - h1), r_H.append(h1)
+        e_u.append(u[soff[i] + js] - u1), r_u.append(u1)
+    err = {k: float(np.linalg.norm(np.concatenate(e)) / np.linalg.norm(np.concatenate(r)))
+           for k, e, r in (("phi", e_phi, r_phi), ("H", e_H, r_H), ("HT", e_u, r_u))}
+    print("C3 vs O1 (64 targets and sources sampled per mesh):", err, flush=True)
+    assert max(err.values()) < 5e-7  # measured about 2.3e-7
