@@ -629,6 +629,11 @@ int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_
         FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         FN_HIP(c, hipStreamSynchronize(c->stream));
         c->geom.near_pairs = (int64_t)(tot + 0.5);
+        FN_HIP(c, launch_coincident_count(c->geom, B, cnt, c->stream));
+        FN_HIP(c, launch_sum(cnt, n_tgt, B.red + RED_SUMV, c->stream));
+        FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        FN_HIP(c, hipStreamSynchronize(c->stream));
+        c->geom.coincident = (int64_t)(tot + 0.5);
     }
     c->geom_ready = true;
     return FN_OK;
@@ -686,6 +691,7 @@ static int eval_impl(fn_ctx *c, double *phi, double *H)
     FN_STAGE(c, FN_ST_GATHER, launch_gather(prec, P, g, 0, B, want_h ? 3 : 1, fstride, B.far, g.nt, st));
     NearArgs na = near_args(c);
     FN_STAGE(c, FN_ST_NEAR, launch_near_fwd(g, B, na, B.red + RED_SUMQ, want_phi, want_h, phi, H, st));
+    if (want_phi && g.coincident > 0) FN_STAGE(c, FN_ST_NEAR, launch_near_coincident(g, B, na, 0, phi, st));
     return FN_OK;
 }
 
@@ -743,6 +749,7 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
     FN_STAGE(c, FN_ST_A_GATHER, launch_gather(prec, P, g, 1, B, 1, fstride, B.far, g.ns, st));
     NearArgs na = near_args(c);
     FN_STAGE(c, FN_ST_A_NEAR, launch_near_adj(g, B, na, kind, B.red + RED_SUMV, u, st));
+    if (kind == 1 && g.coincident > 0) FN_STAGE(c, FN_ST_A_NEAR, launch_near_coincident(g, B, na, 1, u, st));
     return FN_OK;
 }
 

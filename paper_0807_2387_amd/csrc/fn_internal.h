@@ -45,6 +45,7 @@ struct Geom {
     int32_t ntile[2] = {0, 0};       // TILE tiles per dim
     int32_t rnear = 0;               // near radius in cells
     int64_t near_pairs = 0;          // pairs closer than eps_I
+    int64_t coincident = 0;          // (target, source) pairs at exactly the same position
 };
 
 // Device arrays carved out of the caller's workspace.
@@ -195,6 +196,9 @@ hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, 
                            int want_phi, int want_h, double *phi, double *H, hipStream_t st);
 hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int kind,
                            const double *sum_v, double *u, hipStream_t st);
+hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, double *out,
+                                  hipStream_t st);
+hipError_t launch_coincident_count(const Geom &g, const Buffers &b, double *cnt, hipStream_t st);
 
 // host helpers
 double bessel_i0(double x);

@@ -134,16 +134,17 @@ __device__ __forceinline__ double ln64(double x, const NearArgs &na)
 
 constexpr double LN2_4PI = 0.05515890334192413571;  // ln(2)/(4 pi)
 
-// Smallest x = (r/eps_I)^2 the per-pair arithmetic sees: keeps ln x and 1/x
-// finite.  In the mixed path this treats pairs closer than ~1e-14 cells as that
-// far apart; in the FP64 path the bound is below any representable offset.
+// x = (r/eps_I)^2 + XMIN keeps ln x and 1/x finite.  In the mixed path this
+// moves only pairs closer than ~1e-14 cells; in the FP64 path the shift is
+// below any representable offset.
 constexpr double XMIN32 = 1e-30;
 constexpr double XMIN64 = 1e-300;
 
 // One pair, given the FP64 offset d (home minus staged; grid units, or units of
 // eps_I G cells in the mixed path, where the caller passes e2 = 1).  The zone
 // test masks the accumulation (pairs with r2 >= e2 add nothing).  A coincident
-// pair (r2 = 0) adds czero to phi; its H share is g * d = 0 by itself.  kind 0:
+// pair (r2 = 0) adds phi_X = -(ln(XMIN)/(4pi) + U(XMIN)) to phi here -- replaced
+// by czero afterwards (k_coincident) -- and, since d = 0, nothing to H.  kind 0:
 // phi and H with weight s; kind 1: H only; kind 2: phi only; kind 3: the
 // adjoint of H, weight (V0, V1).  The H accumulators hold
 // sum s (1/(4pi x) + T'(x)) d; the caller applies 2G/e2 (2G/(eps_I G) in the
@@ -156,7 +157,7 @@ __device__ __forceinline__ void pair(const NearArgs &na, double e2, double dx, d
     constexpr bool GRAD = KIND == 0 || KIND == 1 || KIND == 3;
     const double r2 = fma(dx, dx, dy * dy);
     // mixed path: offsets come in units of eps_I, so x = r2 and the zone is r2 < 1
-    const double x = F32 ? fmax(r2, XMIN32) : fmax(r2 * na.inv_e2, XMIN64);
+    const double x = F32 ? r2 + XMIN32 : fma(r2, na.inv_e2, XMIN64);
     double u = 0.0, du = 0.0;
     if (PHI) poly2<P, double>(na.u, x, u, du);
     else du = poly_d<P>(na.du, x);
@@ -171,7 +172,7 @@ __device__ __forceinline__ void pair(const NearArgs &na, double e2, double dx, d
     }
     if (r2 < e2) {
         if (PHI) {
-            const double phi_t = r2 == 0.0 ? na.czero : fma(F32 ? -LN2_4PI : -INV_4PI, lnx, -u);
+            const double phi_t = fma(F32 ? -LN2_4PI : -INV_4PI, lnx, -u);
             a0 = fma(w0, phi_t, a0);
         }
         if (GRAD) {
@@ -389,6 +390,42 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     }
 }
 
+// Coincident pairs (equal cell and fractions, i.e. r2 = 0 in the near kernel)
+// received phi_X there; add (czero - phi_X) times the other set's values in the
+// home point's own cell.  Forward: phi_i += (czero - phi_X) sum s_j; adjoint of
+// phi: u_j += w_j (czero - phi_X) sum v_i.  Runs only when set_geometry found
+// such pairs.
+template <int P, bool F32>
+__global__ void __launch_bounds__(256) k_coincident(NearSets S, NearArgs na, int adjoint, double *__restrict__ out)
+{
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gi >= S.n_out) return;
+    const uint32_t key = S.key_out[gi];
+    const double px = S.f_out[gi], py = S.f_out[S.n_out + gi];
+    double acc = 0.0;
+    for (uint32_t j = S.cs_in[key]; j < S.cs_in[key + 1]; ++j)
+        if (S.f_in[j] == px && S.f_in[S.n_in + j] == py) acc += S.pay[j];
+    if (acc == 0.0) return;
+    double phx = 0.0, d1 = 0.0, d2 = 0.0;
+    pair<2, P, F32>(na, F32 ? 1.0 : na.eps2g, 0.0, 0.0, 1.0, 0.0, phx, d1, d2);
+    const double f = (na.czero - phx) * acc;
+    const int64_t o = S.perm_out[gi];
+    out[o] += adjoint ? S.w_out[gi] * f : f;
+}
+
+// Count, per home point, the points of the other set at exactly its position.
+__global__ void __launch_bounds__(256) k_coincident_count(NearSets S, double *__restrict__ cnt)
+{
+    const int64_t gi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gi >= S.n_out) return;
+    const uint32_t key = S.key_out[gi];
+    const double px = S.f_out[gi], py = S.f_out[S.n_out + gi];
+    double c = 0.0;
+    for (uint32_t j = S.cs_in[key]; j < S.cs_in[key + 1]; ++j)
+        c += (S.f_in[j] == px && S.f_in[S.n_in + j] == py) ? 1.0 : 0.0;
+    cnt[gi] = c;
+}
+
 // staged points per chunk (a sweep of 768 to 2048 at 2^24 points put the optimum here)
 #ifndef FN_NEAR_CAP_FWD
 #define FN_NEAR_CAP_FWD 1024
@@ -446,7 +483,45 @@ NearSets make_sets(const Geom &g, const Buffers &b, int out_set)
     return S;
 }
 
+template <int P>
+hipError_t coincident_p(const NearSets &S, const NearArgs &na, int adjoint, double *out, hipStream_t st)
+{
+    const int nb = (int)((S.n_out + 255) / 256);
+    if (na.f32)
+        k_coincident<P, true><<<nb, 256, 0, st>>>(S, na, adjoint, out);
+    else
+        k_coincident<P, false><<<nb, 256, 0, st>>>(S, na, adjoint, out);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+// phi (forward, out_set 0) or the phi adjoint (out_set 1): replace phi_X by czero
+// for coincident pairs.
+hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, double *out,
+                                  hipStream_t st)
+{
+    if ((out_set ? g.ns : g.nt) == 0 || (out_set ? g.nt : g.ns) == 0) return hipSuccess;
+    NearSets S = make_sets(g, b, out_set);
+    if (out_set) S.pay = b.aval64;  // v [n_tgt]
+    switch (na.p) {
+#define FN_CO_CASE(PP) \
+    case PP: return coincident_p<PP>(S, na, out_set, out, st);
+    FN_CO_CASE(1) FN_CO_CASE(2) FN_CO_CASE(3) FN_CO_CASE(4) FN_CO_CASE(5) FN_CO_CASE(6)
+    FN_CO_CASE(7) FN_CO_CASE(8) FN_CO_CASE(9) FN_CO_CASE(10) FN_CO_CASE(11) FN_CO_CASE(12)
+#undef FN_CO_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// cnt [n_tgt]: sources at exactly each (sorted) target's position
+hipError_t launch_coincident_count(const Geom &g, const Buffers &b, double *cnt, hipStream_t st)
+{
+    if (g.nt == 0 || g.ns == 0) return hipSuccess;
+    const NearSets S = make_sets(g, b, 0);
+    k_coincident_count<<<(int)((g.nt + 255) / 256), 256, 0, st>>>(S, cnt);
+    return hipGetLastError();
+}
 
 hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, const double *sum_s,
                            int want_phi, int want_h, double *phi, double *H, hipStream_t st)
