@@ -141,6 +141,40 @@ static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
             for (int ki = 0; ki < nu; ++ki) P.cB[p + ki] = x[ki];
         }
     }
+    // window taps as polynomials in u = 2f - 1 (interpolation at WPD + 1 Chebyshev nodes)
+    {
+        const int D = WPD, nn = D + 1;
+        const long double b = P.kb_b, mm = P.m;
+        const long double i0mbl = i0mb;
+        auto psi = [&](long double t) -> long double {
+            const long double z2 = mm * mm - t * t;
+            if (!(z2 > 0.0L)) return 0.0L;
+            const long double z = std::sqrt(z2);
+            return std::sinh(b * z) / ((long double)PI * z * i0mbl);
+        };
+        std::vector<double> A(nn * nn), rhs(nn), x;
+        std::vector<double> un(nn);
+        for (int k = 0; k < nn; ++k) un[k] = std::cos(PI * (k + 0.5) / nn);
+        for (int r = 0; r < nn; ++r) {
+            double pw = 1.0;
+            for (int k = 0; k < nn; ++k) {
+                A[r * nn + k] = pw;
+                pw *= un[r];
+            }
+        }
+        for (int a = 0; a < P.m; ++a) {
+            for (int r = 0; r < nn; ++r)
+                rhs[r] = (double)psi(0.5L * ((long double)un[r] + 1.0L) + (long double)(P.m - 1 - a));
+            if (!solve(A, rhs, nn, x)) {
+                err = "window interpolation system is singular";
+                return false;
+            }
+            for (int j = 0; j < 4; ++j) {
+                P.wpoly.c[a][j] = (float)x[2 * j];          // even part
+                P.wpoly.c[a][4 + j] = (float)x[2 * j + 1];  // odd part
+            }
+        }
+    }
     P.psihat.resize(P.n / 2 + 1);
     for (int l = 0; l <= P.n / 2; ++l) {
         const double w = 2.0 * PI * l / P.G;

@@ -24,10 +24,21 @@ template <> struct cplx_t<double> { using type = double2; };
 template <typename R> using cplx = typename cplx_t<R>::type;
 
 // Host-side plan: everything that depends only on the parameters.
+// The window's taps of a point with in-cell fraction f, as polynomials of degree
+// WPD in u = 2f - 1 interpolated at Chebyshev nodes; used by the FP32 spread and
+// gather.  The window is even, so tap 2m-1-a at u is tap a at -u: only taps
+// a < m are stored, split as p_a(u) = E_a(u^2) + u O_a(u^2) with E_a's
+// coefficients at c[a][0..3] and O_a's at c[a][4..7] (ascending powers of u^2).
+constexpr int WPD = 7;
+struct WinPoly {
+    float c[MAXM][WPD + 1];
+};
+
 struct Plan {
     int G = 0, n = 0, m = 0, p = 0, log2G = 0;
     int precision = FN_FP32_MIXED;
     double eps_I = 0, eps_B = 0;
+    WinPoly wpoly{};                 // per-tap polynomials of the window (FP32 path)
     double kb_b = 0;                 // Kaiser-Bessel shape b = pi (2 - 1/sigma)
     double win_norm = 0;             // 1 / (2 pi I0(m b) e^{-m b})
     double a[MAXP] = {0};            // inner polynomial T_I(r) = sum_k a_k (r/eps_I)^{2k}

@@ -2,7 +2,9 @@
 // "diffusion" of the point data to the regular grid X through a smooth,
 // localized window), with a Kaiser-Bessel window.
 //
-// Window (grid-cell units, normalized by I0(m b)):
+// Window (grid-cell units, normalized by I0(m b)); the FP32 path evaluates the
+// taps as degree-7 polynomials of the in-cell fraction fitted at plan time (max
+// error 8e-8 of the peak, below the closed form's FP32 rounding):
 //   psi(t) = (e^{-b t^2/(z + m)} - e^{-b (z + m)}) / (2 pi z I0e(m b)),  z = sqrt(m^2 - t^2), |t| < m
 // which equals sinh(b z) / (pi z I0(m b)); zero for |t| >= m.  A point with grid
 // coordinate u has taps k = floor(u) - m + 1 + a, a = 0..2m-1, at t = u - k.
@@ -19,10 +21,15 @@
 // precision, the 2m row sums are accumulated in FP64.
 #include "fn_internal.h"
 
+#include <type_traits>
+
 namespace fn {
 
 namespace {
 
+#ifndef FN_SPREAD_CELLS
+#define FN_SPREAD_CELLS 1  // mixed path: one thread per grid cell (k_spread_cells)
+#endif
 constexpr int SPREAD_WAVES = 2;
 constexpr int SPREAD_NT = 64 * SPREAD_WAVES;
 
@@ -37,6 +44,29 @@ __device__ __forceinline__ R kb_psi(R t, R m, R b, R wnorm)
     const R z = sqrt(z2);
     const R zm = z + m;
     return (exp(-b * t2 / zm) - exp(-b * zm)) * wnorm / z;
+}
+
+// The 2m taps of the window at fraction f into w[]: the FP32 path evaluates the
+// tap polynomials (taps a and 2m-1-a from one even/odd pair in u = 2f - 1, the
+// coefficients uniform across the wave), the FP64 path the closed form.
+template <typename R, int M2>
+__device__ __forceinline__ void taps(const WinPoly &wp, R f, R rm, R rb, R rw, R (&w)[M2])
+{
+    constexpr int m = M2 / 2;
+    if (sizeof(R) == 4) {
+        const float u = fmaf(2.0f, (float)f, -1.0f);
+        const float v = u * u;
+#pragma unroll
+        for (int a = 0; a < m; ++a) {
+            const float e = fmaf(fmaf(fmaf(wp.c[a][3], v, wp.c[a][2]), v, wp.c[a][1]), v, wp.c[a][0]);
+            const float o = fmaf(fmaf(fmaf(wp.c[a][7], v, wp.c[a][6]), v, wp.c[a][5]), v, wp.c[a][4]);
+            w[a] = (R)fmaf(u, o, e);
+            w[M2 - 1 - a] = (R)fmaf(-u, o, e);
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < M2; ++a) w[a] = kb_psi<R>(f + (R)(m - 1 - a), rm, rb, rw);
 }
 
 template <typename R> __device__ __forceinline__ R frac_of(const float *f32, const double *f64, int64_t i);
@@ -92,7 +122,7 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread(const uint32_t *__restrict
                                                       const double *__restrict__ fr64, const R *__restrict__ val,
                                                       int64_t N, const uint32_t *__restrict__ cstart, int Ex, int Ey,
                                                       int ntx, int nty, double b, double wnorm, int nfield,
-                                                      double *__restrict__ ptile)
+                                                      double *__restrict__ ptile, const WinPoly wp)
 {
     constexpr int m = M2 / 2;
     constexpr int PT = TILE + M2 - 1;
@@ -114,11 +144,8 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread(const uint32_t *__restrict
         const int lx = (int)(kk % (uint32_t)Ex) - x0, ly = (int)(kk / (uint32_t)Ex) - y0;
         const R fx = frac_of<R>(fr32, fr64, i), fy = frac_of<R>(fr32, fr64, N + i);
         R wx[M2], wy[M2];
-#pragma unroll
-        for (int a = 0; a < M2; ++a) {
-            wx[a] = kb_psi<R>(fx + (R)(m - 1 - a), rm, rb, rw);
-            wy[a] = kb_psi<R>(fy + (R)(m - 1 - a), rm, rb, rw);
-        }
+        taps<R, M2>(wp, fx, rm, rb, rw, wx);
+        taps<R, M2>(wp, fy, rm, rb, rw, wy);
         for (int f = 0; f < nfield; ++f) {
             const R v = val[(int64_t)f * N + i];
             double *af = myacc + f * PT2 + ly * PT + lx;
@@ -129,6 +156,79 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread(const uint32_t *__restrict
                 for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)(vy * wx[a]));
             }
         }
+    }
+    __syncthreads();
+    const int ntiles = ntx * nty;
+    for (int f = 0; f < nfield; ++f)
+        for (int c = threadIdx.x; c < PT2; c += SPREAD_NT) {
+            double v = acc[f * PT2 + c];
+            for (int w = 1; w < SPREAD_WAVES; ++w) v += acc[((int64_t)w * nfield + f) * PT2 + c];
+            ptile[((int64_t)f * ntiles + tile) * PT2 + c] = v;
+        }
+}
+
+// Mixed-precision spread, one thread per grid cell: the points of a cell share one
+// 2m x 2m footprint, so their window products are summed in FP32 registers (a
+// handful of terms) and added to the wave's FP64 accumulator once per cell; the
+// footprint is done in row groups of at most 72 accumulators.  The lanes of a
+// wave hold consecutive cells of a tile row, so every LDS atomic instruction
+// touches consecutive addresses.  Same accumulator layout and fixed per-wave
+// summation order as k_spread.
+template <int M2>
+__global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restrict__ fr32,
+                                                            const float *__restrict__ val, int64_t N,
+                                                            const uint32_t *__restrict__ cstart, int Ex, int Ey,
+                                                            int ntx, int nty, int nfield, double *__restrict__ ptile,
+                                                            const WinPoly wp)
+{
+    constexpr int PT = TILE + M2 - 1;
+    constexpr int PT2 = PT * PT;
+    constexpr int RG = (72 / M2) < M2 ? (72 / M2) : M2;
+    extern __shared__ double acc[];  // [SPREAD_WAVES][nfield][PT2]
+    const int tile = blockIdx.x;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int wv = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < SPREAD_WAVES * nfield * PT2; i += SPREAD_NT) acc[i] = 0.0;
+    __syncthreads();
+    double *myacc = acc + (int64_t)wv * nfield * PT2;
+    for (int c = threadIdx.x; c < TILE * TILE; c += SPREAD_NT) {
+        const int lx = c % TILE, ly = c / TILE;
+        const int gx = x0 + lx, gy = y0 + ly;
+        uint32_t s0 = 0, s1 = 0;
+        if (gx < Ex && gy < Ey) {
+            const int64_t cell = (int64_t)gy * Ex + gx;
+            s0 = cstart[cell];
+            s1 = cstart[cell + 1];
+        }
+        if (s0 == s1) continue;
+        for (int f = 0; f < nfield; ++f)
+#pragma unroll
+            for (int g0 = 0; g0 < M2; g0 += RG) {
+                float r[RG][M2];
+#pragma unroll
+                for (int bb = 0; bb < RG; ++bb)
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) r[bb][a] = 0.f;
+                for (uint32_t i = s0; i < s1; ++i) {
+                    const float v = val[(int64_t)f * N + i];
+                    float wx[M2], wy[M2];
+                    taps<float, M2>(wp, fr32[i], 0.f, 0.f, 0.f, wx);
+                    taps<float, M2>(wp, fr32[N + i], 0.f, 0.f, 0.f, wy);
+#pragma unroll
+                    for (int bb = 0; bb < RG; ++bb) {
+                        const float vy = g0 + bb < M2 ? v * wy[g0 + bb < M2 ? g0 + bb : 0] : 0.f;
+#pragma unroll
+                        for (int a = 0; a < M2; ++a) r[bb][a] = fmaf(vy, wx[a], r[bb][a]);
+                    }
+                }
+                double *af = myacc + f * PT2 + (ly + g0) * PT + lx;
+#pragma unroll
+                for (int bb = 0; bb < RG; ++bb)
+                    if (g0 + bb < M2)
+#pragma unroll
+                        for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)r[bb][a]);
+            }
     }
     __syncthreads();
     const int ntiles = ntx * nty;
@@ -166,7 +266,7 @@ __global__ void __launch_bounds__(256) k_gather(const uint32_t *__restrict__ key
                                                 const uint32_t *__restrict__ cstart, int Ex, int Ey, int ntx,
                                                 double b, double wnorm, const R *__restrict__ grid,
                                                 int64_t fstride, int nfield, double *__restrict__ far,
-                                                int64_t farstride)
+                                                int64_t farstride, const WinPoly wp)
 {
     constexpr int m = M2 / 2;
     constexpr int PT = TILE + M2 - 1;
@@ -193,11 +293,8 @@ __global__ void __launch_bounds__(256) k_gather(const uint32_t *__restrict__ key
         const int lx = (int)(kk % (uint32_t)Ex) - x0, ly = (int)(kk / (uint32_t)Ex) - y0;
         const R fx = frac_of<R>(fr32, fr64, i), fy = frac_of<R>(fr32, fr64, N + i);
         R wx[M2], wy[M2];
-#pragma unroll
-        for (int a = 0; a < M2; ++a) {
-            wx[a] = kb_psi<R>(fx + (R)(m - 1 - a), rm, rb, rw);
-            wy[a] = kb_psi<R>(fy + (R)(m - 1 - a), rm, rb, rw);
-        }
+        taps<R, M2>(wp, fx, rm, rb, rw, wx);
+        taps<R, M2>(wp, fy, rm, rb, rw, wy);
         for (int f = 0; f < nfield; ++f) {
             const R *lf = L + f * PT2 + ly * PT + lx;
             double acc = 0.0;
@@ -253,12 +350,22 @@ hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, con
     const int ntiles = g.ntile[0] * g.ntile[1];
     const size_t lds = (size_t)SPREAD_WAVES * nfield * PT * PT * sizeof(double);
     const int64_t N = set ? g.ns : g.nt;
+#if FN_SPREAD_CELLS
+    if (std::is_same<R, float>::value) {
+        auto kc = k_spread_cells<M2>;
+        hipError_t e = hipFuncSetAttribute((const void *)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        kc<<<ntiles, SPREAD_NT, lds, st>>>(b.fr32[set], (const float *)val, N, b.cstart[set], g.ext[0], g.ext[1],
+                                           g.ntile[0], g.ntile[1], nfield, b.ptile, P.wpoly);
+        return hipGetLastError();
+    }
+#endif
     auto kern = k_spread<R, M2>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     kern<<<ntiles, SPREAD_NT, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], (const R *)val, N,
                                          b.cstart[set], g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], P.kb_b,
-                                         P.win_norm, nfield, b.ptile);
+                                         P.win_norm, nfield, b.ptile, P.wpoly);
     return hipGetLastError();
 }
 
@@ -272,7 +379,7 @@ hipError_t gather_t(const Plan &P, const Geom &g, int set, const Buffers &b, int
     const int64_t N = set ? g.ns : g.nt;
     k_gather<R, M2><<<ntiles, 256, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], N, b.cstart[set], g.ext[0],
                                              g.ext[1], g.ntile[0], P.kb_b, P.win_norm, (const R *)b.grid,
-                                             fstride, nfield, far, farstride);
+                                             fstride, nfield, far, farstride, P.wpoly);
     return hipGetLastError();
 }
 
