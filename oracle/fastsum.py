@@ -20,7 +20,9 @@ near-field correction).  This module takes those steps one by one:
                     T_B(1/2) beyond.  b_l = (1/n^2) sum_{j in I_n} K_R(|j|/n)
                     e^{-2 pi i j.l/n}.  Kaiser-Bessel window psi(t) =
                     sinh(b sqrt(m^2-t^2)) / (pi sqrt(m^2-t^2)) on |t| < m cells,
-                    b = pi (2 - 1/sigma), sigma = G/n = 2, with its Fourier
+                    b = pi (2 - 1/sigma), sigma = G/n (2 unless the bandwidth
+                    n is set; the paper leaves the NFFT's oversampling to the
+                    NFFT package), with its Fourier
                     transform I0(m sqrt(b^2 - (2 pi xi)^2)); both divided by
                     I0(m b) (a constant that cancels).
   S2  spread        g_k = sum_j s_j psi(G x_j1 - k1) psi(G x_j2 - k2), 2m taps/dim.
@@ -63,10 +65,11 @@ class Params:
     p: int            # regularization (smoothness) degree
     eps_I: float      # near-field radius, torus units
     eps_B: float = 1.0 / 16.0  # boundary regularization width, torus units
+    band: int = 0     # bandwidth n (even, G/2 <= n < G); 0 means n = G/2 (oversampling 2)
 
     @property
     def n(self):
-        return self.G // 2
+        return self.band if self.band else self.G // 2
 
     @property
     def kb_b(self):

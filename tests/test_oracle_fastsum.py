@@ -84,10 +84,11 @@ def test_regularized_kernel_is_continuous_and_equals_log_between():
         assert abs(hi - lo) < 1e-7
 
 
-def test_b_coefficients_interpolate_on_the_bandwidth_grid():
+@pytest.mark.parametrize("band", [0, 48])
+def test_b_coefficients_interpolate_on_the_bandwidth_grid(band):
     """b_l is real and even, and its symmetric trigonometric sum reproduces K_R at the n-grid
-    points (it is the trigonometric interpolant of the sampled kernel)."""
-    prm = fs.Params(G=64, m=4, p=3, eps_I=3 / 32)
+    points (it is the trigonometric interpolant of the sampled kernel); n = G/2 and n = 3G/4."""
+    prm = fs.Params(G=64, m=4, p=3, eps_I=3 / 32, band=band)
     n = prm.n
     b = fs.b_coeffs(prm)
     assert np.allclose(b, b[(-np.arange(n)) % n][:, (-np.arange(n)) % n], atol=1e-17)
@@ -102,17 +103,19 @@ def test_b_coefficients_interpolate_on_the_bandwidth_grid():
         assert abs(val - fs.K_R(np.array([np.hypot(*j) / n]), prm)[0]) < 1e-13
 
 
-def test_windowed_pipeline_matches_brute_force_ndft():
+@pytest.mark.parametrize("band", [0, 48])
+def test_windowed_pipeline_matches_brute_force_ndft(band):
     """Spread + FFT + deconvolution + multiply + inverse + gather equals the direct trigonometric
-    sum up to the window error (Kaiser-Bessel bound ~4e-14 at m = 8, sigma = 2)."""
-    prm = fs.Params(G=64, m=8, p=3, eps_I=3 / 32)
+    sum up to the window error (Kaiser-Bessel bound ~e^{-b m}: 4e-14 at m = 8, sigma = 2; 2e-14
+    at sigma = 4/3, where b = 1.25 pi)."""
+    prm = fs.Params(G=64, m=8, p=3, eps_I=3 / 32, band=band)
     y, x, w, q = synth.random_cloud(40, 50, 2)
     F = fs.FastSum(y, x, w, prm)
     s = w * q
     phi, H = F.far_forward(s)
     phi0, H0 = fs.direct_ndft(F.yt, F.xt, s, prm)
     assert rel_l2(phi, phi0) < 1e-12 and rel_l2(H, H0) < 1e-12
-    prm6 = fs.Params(G=64, m=6, p=3, eps_I=3 / 32)
+    prm6 = fs.Params(G=64, m=6, p=3, eps_I=3 / 32, band=band)
     F6 = fs.FastSum(y, x, w, prm6)
     phi6, H6 = F6.far_forward(s)
     assert 1e-13 < rel_l2(phi6, phi0) < 1e-8  # window error grows as m shrinks
@@ -129,6 +132,19 @@ def test_fast_sum_matches_direct_sum():
     assert rel_l2(F.adjoint_H(V), direct.adjoint(y, x, w, V=V)) < 1e-7
     v = V[:, 0].copy()
     assert rel_l2(F.adjoint_phi(v), direct.adjoint(y, x, w, v=v)) < 1e-8
+
+
+def test_fast_sum_matches_direct_sum_at_lower_oversampling():
+    """Bandwidth n = 3G/4 (oversampling 4/3) with n eps_I fixed: same accuracy class, a
+    near-field radius 2/3 as large."""
+    y, x, w, q = synth.random_cloud(500, 700, 3)
+    prm = fs.Params(G=512, m=8, p=10, eps_I=10 / 384, band=384)
+    F = fs.FastSum(y, x, w, prm)
+    phi, H = F.forward(q)
+    phi1, H1 = direct.forward(y, x, w, q)
+    assert rel_l2(phi, phi1) < 1e-8 and rel_l2(H, H1) < 1e-7
+    V = np.random.default_rng(4).standard_normal((500, 2))
+    assert rel_l2(F.adjoint_H(V), direct.adjoint(y, x, w, V=V)) < 1e-7
 
 
 def test_single_source_potential_and_field():
