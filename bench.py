@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--grid", type=int, default=8192)
     ap.add_argument("--m", type=int, default=6)
     ap.add_argument("--p", type=int, default=8)
-    ap.add_argument("--c", type=float, default=7.0, help="eps_I = c / (grid/2)")
+    ap.add_argument("--c", type=float, default=7.0, help="eps_I = c / n")
+    ap.add_argument("--band", type=int, default=None,
+                    help="bandwidth n (default 3 grid/4, oversampling 4/3; 0 means grid/2)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and the sampled accuracy check")
     ap.add_argument("--samples", type=int, default=256, help="sampled targets/sources for the O1 check")
@@ -82,10 +84,13 @@ def main():
     log(f"workload: {nt} targets, {ns} sources (synth {time.time() - t0:.1f}s)")
     tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ty, tx, tw, tq, tV = tt(y), tt(x), tt(w), tt(q), tt(V)
-    eps_I = args.c / (args.grid // 2)
+    if args.band is None:
+        args.band = 3 * args.grid // 4
+    nband = args.band or args.grid // 2
+    eps_I = args.c / nband
 
     def run(precision, steps, warmup, profile):
-        S = fn.Solver(grid=args.grid, m=args.m, p=args.p, eps_I=eps_I, precision=precision)
+        S = fn.Solver(grid=args.grid, m=args.m, p=args.p, eps_I=eps_I, precision=precision, n=args.band)
         torch.cuda.synchronize()
         g0 = time.perf_counter()
         S.set_geometry(ty, tx, tw)
@@ -142,7 +147,7 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "rounded square side 4, jittered lattice, 32-mode smooth M",
-                   "n_tgt": nt, "n_src": ns, "grid": args.grid, "m": args.m, "p": args.p,
+                   "n_tgt": nt, "n_src": ns, "grid": args.grid, "bandwidth": nband, "m": args.m, "p": args.p,
                    "eps_I": eps_I, "precision": "fp32_mixed", "parallelism": "single_gpu"},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "set_geometry_ms": r["t_geom"] * 1e3,
@@ -192,12 +197,12 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
     ex, ey = info["win_ext"]
     cells = ex * ey
     sec = ms_per_launch * 1e-3
-    nh = G // 4
+    nh = (args.band or G // 2) // 2
     if stage in ("near", "a_near"):
         pairs = info["near_pairs"]
         fl = near_flops_per_pair(stage, args.p, f32=True)
         ach = pairs * fl / sec / 1e12
-        traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1")
+        traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1", args.band or G // 2)
         return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / FP64_VEC_TFLOPS, "traffic": traffic, "ms_per_launch": ms_per_launch,
                 "pairs_per_launch": pairs, "flops_per_pair": fl}
@@ -224,9 +229,10 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
             "algorithmic_bytes_per_launch": byts}
 
 
-def counter_traffic(kernel_prefix):
+def counter_traffic(kernel_prefix, bandwidth):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source (its sha256 prefix is stored with the numbers)."""
+    the current kernel source (its sha256 prefix is stored with the numbers) and on this
+    workload's bandwidth."""
     path = os.path.join(HERE, "profiles", "counters.json")
     src = os.path.join(HERE, "paper_0807_2387_amd", "csrc", "fn_near.hip")
     try:
@@ -235,7 +241,7 @@ def counter_traffic(kernel_prefix):
     except (OSError, ValueError):
         return None
     ent = rec.get("kernels", {}).get(kernel_prefix)
-    if not ent or ent.get("source_sha256_16") != src_hash(src):
+    if not ent or ent.get("source_sha256_16") != src_hash(src) or ent.get("bandwidth") != bandwidth:
         return None
     return ent.get("hbm_bytes_per_launch")
 

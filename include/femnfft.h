@@ -75,6 +75,7 @@ enum {
  *   eps_I     near-field radius; 0 < eps_I, eps_I * G <= 32.
  *   eps_B     width of the boundary regularization near |x| = 1/2; 0 < eps_B < 1/4.
  *   precision FN_FP64 or FN_FP32_MIXED.
+ *   n         bandwidth; the window shape is b = pi (2 - 1/sigma), sigma = G/n.
  */
 typedef struct fn_params {
     int32_t grid;
@@ -84,7 +85,9 @@ typedef struct fn_params {
     double eps_I;
     double eps_B;
     int32_t flags;      /* reserved, must be 0 */
-    int32_t reserved;
+    int32_t n;          /* bandwidth (kept Fourier modes |l| <= n/2): 0 means G/2 (oversampling
+                           2); otherwise even, G/2 <= n <= 3G/4, a power of two or three
+                           times one (3G/4: oversampling 4/3) */
 } fn_params;
 
 /* Read-only facts about a context after fn_set_geometry (host struct). */
@@ -107,11 +110,11 @@ typedef struct fn_ctx fn_ctx;
 int fn_params_default(fn_params *p, int32_t grid);
 
 /* Parameters for n_tgt targets and n_src sources at the accuracy the library is
- * tuned for (relative L2 error of phi, H and the adjoints a few 1e-7 against the
+ * tuned for (relative L2 error of phi, H and the adjoints ~1e-7 against the
  * exact sum on FEM meshes): grid G = 2^ceil(log2(2 sqrt((n_tgt + n_src)/2)))
- * (about one bandwidth cell per point, clamped to 64..8192), m = 6, and
- * p = 8, eps_I = 7/(G/2) -- or p = 10, eps_I = 8/(G/2) below 2^22 points in
- * total, where the boundary-layer error of H is a larger share. */
+ * (clamped to 64..8192), m = 6, bandwidth n = 3G/4 (oversampling 4/3; G/2 for
+ * G = 64), and p = 8, eps_I = 7/n -- or p = 10, eps_I = 8/n below 2^22 points
+ * in total, where the boundary-layer error of H is a larger share. */
 int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p);
 
 /* Create a context bound to the current device and to the HIP stream

@@ -37,14 +37,14 @@ __all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", 
 def default_params(grid):
     p = _lib.Params()
     _lib.check(_lib.lib().fn_params_default(ctypes.byref(p), int(grid)))
-    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision)
+    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n)
 
 
 def auto_params(n_tgt, n_src, precision=FN_FP32_MIXED):
     """Grid and regularization for a problem size (fn_params_auto)."""
     p = _lib.Params()
     _lib.check(_lib.lib().fn_params_auto(int(n_tgt), int(n_src), int(precision), ctypes.byref(p)))
-    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision)
+    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n)
 
 
 def _torch():
@@ -69,14 +69,14 @@ def _dev_ptr(t, name, shape_tail=(), dtype=None):
 class Solver:
     """One fast-summation context bound to the current device and torch stream."""
 
-    def __init__(self, grid, m=None, p=None, eps_I=None, eps_B=None, precision=FN_FP32_MIXED, stream=None):
+    def __init__(self, grid, m=None, p=None, eps_I=None, eps_B=None, precision=FN_FP32_MIXED, stream=None, n=0):
         torch = _torch()
         L = _lib.lib()
         d = default_params(grid)
         prm = _lib.Params(grid=int(grid), m=int(m if m is not None else d["m"]),
                           p=int(p if p is not None else d["p"]), precision=int(precision),
                           eps_I=float(eps_I if eps_I is not None else d["eps_I"]),
-                          eps_B=float(eps_B if eps_B is not None else d["eps_B"]), flags=0, reserved=0)
+                          eps_B=float(eps_B if eps_B is not None else d["eps_B"]), flags=0, n=int(n or 0))
         self.params = prm
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -252,7 +252,7 @@ def _params(d):
     base = default_params(int(d["grid"]))
     base.update({k: v for k, v in d.items() if v is not None})
     return _lib.Params(grid=int(base["grid"]), m=int(base["m"]), p=int(base["p"]), precision=int(base["precision"]),
-                       eps_I=float(base["eps_I"]), eps_B=float(base["eps_B"]), flags=0, reserved=0)
+                       eps_I=float(base["eps_I"]), eps_B=float(base["eps_B"]), flags=0, n=int(base.get("n") or 0))
 
 
 class Batch:

@@ -38,7 +38,7 @@ STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather",
 class Params(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("eps_I", ctypes.c_double), ("eps_B", ctypes.c_double),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("n", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -92,7 +92,8 @@ template <int RAD, typename C> __device__ __forceinline__ void dftR(C *v)
 }
 
 // One Stockham pass over a line in LDS.  NT threads, each FFT_EPT/RAD butterflies.
-template <int RAD, typename C>
+// The twiddle table holds N * TWM entries (a line of a transform TWM times longer).
+template <int RAD, int TWM, typename C>
 __device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, const C *__restrict__ tw)
 {
     constexpr int PER = FFT_EPT / RAD;
@@ -112,7 +113,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, c
         const int k = j & (L - 1);
         if (L > 1) {
 #pragma unroll
-            for (int r = 1; r < RAD; ++r) v[c * RAD + r] = cmul(v[c * RAD + r], tw[r * k * stride]);
+            for (int r = 1; r < RAD; ++r) v[c * RAD + r] = cmul(v[c * RAD + r], tw[r * k * stride * TWM]);
         }
         dftR<RAD>(&v[c * RAD]);
         const int o = (j - k) * RAD + k;
@@ -122,18 +123,20 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, c
     __syncthreads();
 }
 
-// Forward FFT of one LDS line (in place).  All threads of the block must call it.
-template <typename C>
+// Forward FFT of one LDS line (in place), N a power of two.  All threads of the
+// block must call it.  TWM: the twiddle table belongs to a transform TWM times
+// longer (entry TWM k is e^{-2 pi i k / N}).
+template <int TWM = 1, typename C>
 __device__ void fft_line(C *buf, int N, int log2N, int lt, int NT, const C *__restrict__ tw)
 {
     int L = 1, rem = log2N;
     while (rem >= 3) {
-        fft_pass<8>(buf, N, L, lt, NT, tw);
+        fft_pass<8, TWM>(buf, N, L, lt, NT, tw);
         L <<= 3;
         rem -= 3;
     }
-    if (rem == 2) fft_pass<4>(buf, N, L, lt, NT, tw);
-    else if (rem == 1) fft_pass<2>(buf, N, L, lt, NT, tw);
+    if (rem == 2) fft_pass<4, TWM>(buf, N, L, lt, NT, tw);
+    else if (rem == 1) fft_pass<2, TWM>(buf, N, L, lt, NT, tw);
 }
 
 template <typename C> __device__ __forceinline__ void conj_line(C *buf, int N, int lt, int NT)
@@ -169,19 +172,45 @@ __global__ void k_kr_samples(double2 *a, int n, const double *__restrict__ coef,
     a[idx] = make_double2(v, 0.0);
 }
 
-// In-place C2C forward FFT of `lines` lines of length N; element e of line q at
-// a[q * dist + e * stride].
+// In-place C2C forward FFT of `lines` lines of length N (a power of two, or three
+// times one: r3 = 1); element e of line q at a[q * dist + e * stride]; tw holds
+// the N twiddles e^{-2 pi i k/N}.  The block has exactly N/FFT_EPT threads per
+// line.  For N = 3M the three decimated sequences x[3i + s] are transformed as
+// M-point lines side by side, then X[j + rM] = sum_s omega^{rs} w^{sj} Y_s[j]
+// (w = e^{-2 pi i/N}, omega = w^M) in place.
 __global__ void __launch_bounds__(256) k_lines64(double2 *a, int N, int log2N, int64_t stride, int64_t dist,
-                                                 int lines, const double2 *__restrict__ tw)
+                                                 int lines, const double2 *__restrict__ tw, int r3)
 {
     extern __shared__ double2 sh64[];
     const int NT = N / FFT_EPT, per = blockDim.x / NT;
     const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
     const int q = blockIdx.x * per + li;
     double2 *buf = sh64 + (int64_t)li * N;
-    for (int e = lt; e < N; e += NT) buf[e] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
-    __syncthreads();
-    fft_line(buf, N, log2N, lt, NT, tw);
+    if (!r3) {
+        for (int e = lt; e < N; e += NT) buf[e] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
+        __syncthreads();
+        fft_line(buf, N, log2N, lt, NT, tw);
+    } else {
+        const int M = N / 3, NTs = NT / 3, grp = lt / NTs, slt = lt % NTs;
+        for (int e = lt; e < N; e += NT)
+            buf[(e % 3) * M + e / 3] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
+        __syncthreads();
+        fft_line<3>(buf + grp * M, M, log2N, slt, NTs, tw);
+        const double c3 = -0.5, s3 = -0.86602540378443864676372317075294;  // omega = e^{-2 pi i/3}
+        for (int j = lt; j < M; j += NT) {
+            const double2 y0 = buf[j];
+            const double2 y1 = cmul(buf[M + j], tw[j]);
+            const double2 y2 = cmul(buf[2 * M + j], tw[2 * j]);
+            const double2 sp = make_double2(y1.x + y2.x, y1.y + y2.y);
+            const double2 sm = make_double2(y1.x - y2.x, y1.y - y2.y);
+            buf[j] = make_double2(y0.x + sp.x, y0.y + sp.y);
+            // y0 + c3 (y1 + y2) +- i s3 (y1 - y2)
+            const double2 base = make_double2(y0.x + c3 * sp.x, y0.y + c3 * sp.y);
+            buf[M + j] = make_double2(base.x - s3 * sm.y, base.y + s3 * sm.x);
+            buf[2 * M + j] = make_double2(base.x + s3 * sm.y, base.y - s3 * sm.x);
+        }
+        __syncthreads();
+    }
     if (q < lines)
         for (int e = lt; e < N; e += NT) a[q * dist + e * stride] = buf[e];
 }
@@ -394,17 +423,21 @@ hipError_t launch_kr_samples(double2 *a, int n, const double *coef, int p, doubl
     return hipGetLastError();
 }
 
+// n a power of two or three times one (n / FFT_EPT threads per line, at most 256).
 hipError_t launch_fft2d_c2c64(double2 *a, int n, const double2 *tw, hipStream_t st)
 {
+    const int r3 = (n % 3 == 0) ? 1 : 0;
+    const int M = r3 ? n / 3 : n;
+    if ((M & (M - 1)) || M < FFT_EPT || n / FFT_EPT > 256) return hipErrorInvalidValue;
     const int NT = n / FFT_EPT;
     const int per = 256 / NT;
     const size_t lds = (size_t)per * n * sizeof(double2);
-    const int lg = ilog2(n);
+    const int lg = ilog2(M);
     int nb = (n + per - 1) / per;
     hipError_t e = hipFuncSetAttribute((const void *)k_lines64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    k_lines64<<<nb, 256, lds, st>>>(a, n, lg, 1, n, n, tw);  // rows
-    k_lines64<<<nb, 256, lds, st>>>(a, n, lg, n, 1, n, tw);  // columns
+    k_lines64<<<nb, NT * per, lds, st>>>(a, n, lg, 1, n, n, tw, r3);  // rows
+    k_lines64<<<nb, NT * per, lds, st>>>(a, n, lg, n, 1, n, tw, r3);  // columns
     return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ def dev(torch, a):
 
 
 def run_gpu(torch, fn, y, x, w, q, V, v, prm, precision):
-    S = fn.Solver(grid=prm.G, m=prm.m, p=prm.p, eps_I=prm.eps_I, eps_B=prm.eps_B, precision=precision)
+    S = fn.Solver(grid=prm.G, m=prm.m, p=prm.p, eps_I=prm.eps_I, eps_B=prm.eps_B, precision=precision,
+                  n=prm.band)
     S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
     S.set_charges(dev(torch, q))
     phi, H = S.eval()
@@ -53,19 +54,23 @@ CASES = [
     ("ragged", 1000, 1531, 128, 6, 4, 4.0, 2),
     ("m8", 3000, 2000, 256, 8, 6, 6.0, 4),
     ("multi_tile", 20000, 30011, 512, 6, 8, 7.0, 3),
+    # bandwidth 3G/4 (oversampling 4/3): a length-3*2^k plan transform; eps_I = c/n
+    ("band_3G4", 20000, 30011, 512, 6, 8, 7.0, 5, 384),
+    ("band_3G4_small", 1000, 1531, 128, 6, 4, 4.0, 6, 96),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_parity_with_step_by_step_oracle(torch, fn, case, precision):
-    name, nt, ns, G, m, p, c, seed = case
+    name, nt, ns, G, m, p, c, seed = case[:8]
+    band = case[8] if len(case) > 8 else 0
     print(f"case {name} {precision}", flush=True)
     y, x, w, q = synth.random_cloud(nt, ns, seed)
     rng = np.random.default_rng(seed + 100)
     V = rng.standard_normal((nt, 2))
     v = rng.standard_normal(nt)
-    prm = fs.Params(G=G, m=m, p=p, eps_I=c / (G // 2))
+    prm = fs.Params(G=G, m=m, p=p, eps_I=c / (band or G // 2), band=band)
     F = fs.FastSum(y, x, w, prm)
     phi2, H2 = F.forward(q)
     u2, up2 = F.adjoint_H(V), F.adjoint_phi(v)
