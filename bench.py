@@ -49,7 +49,7 @@ def parse():
                     help="bandwidth n (default 3 grid/4, oversampling 4/3; 0 means grid/2)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and the sampled accuracy check")
-    ap.add_argument("--samples", type=int, default=512, help="sampled targets/sources for the O1 check")
+    ap.add_argument("--samples", type=int, default=1024, help="sampled targets/sources for the O1 check")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one elementwise kernel over 256 MiB (read and write) before the timed region, "
                          "as the byte-counter calibration for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
@@ -203,7 +203,8 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
         pairs = info["near_pairs"]
         fl = near_flops_per_pair(stage, args.p, f32=True)
         ach = pairs * fl / sec / 1e12
-        traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1", args.band or G // 2)
+        nb = args.band or G // 2
+        traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1", nb, args.c / nb)
         return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / FP64_VEC_TFLOPS, "traffic": traffic, "ms_per_launch": ms_per_launch,
                 "pairs_per_launch": pairs, "flops_per_pair": fl}
@@ -230,10 +231,10 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
             "algorithmic_bytes_per_launch": byts}
 
 
-def counter_traffic(kernel_prefix, bandwidth):
+def counter_traffic(kernel_prefix, bandwidth, eps_I):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
     the current kernel source (its sha256 prefix is stored with the numbers) and on this
-    workload's bandwidth."""
+    workload's bandwidth and near radius."""
     path = os.path.join(HERE, "profiles", "counters.json")
     src = os.path.join(HERE, "paper_0807_2387_amd", "csrc", "fn_near.hip")
     try:
@@ -244,17 +245,45 @@ def counter_traffic(kernel_prefix, bandwidth):
     ent = rec.get("kernels", {}).get(kernel_prefix)
     if not ent or ent.get("source_sha256_16") != src_hash(src) or ent.get("bandwidth") != bandwidth:
         return None
+    if ent.get("eps_I") is None or abs(ent["eps_I"] - eps_I) > 1e-12 * eps_I:
+        return None
     return ent.get("hbm_bytes_per_launch")
 
 
+def stratified_sample(mask, k, rng):
+    """k indices, half drawn from the points where mask holds and half from the rest, with the
+    weight (stratum size / stratum sample size) that makes weighted sums unbiased."""
+    idx, wts = [], []
+    for sel in (np.flatnonzero(mask), np.flatnonzero(~mask)):
+        kk = min(len(sel), k // 2)
+        if kk == 0:
+            continue
+        idx.append(rng.choice(sel, kk, replace=False))
+        wts.append(np.full(kk, len(sel) / kk))
+    idx, wts = np.concatenate(idx), np.concatenate(wts)
+    o = np.argsort(idx)
+    return idx[o], wts[o]
+
+
 def accuracy_and_cpu(d, r, args, nt, ns):
-    """Sampled check against the FP64 direct-sum oracle, and the oracle's own rate."""
+    """Sampled check against the FP64 direct-sum oracle, and the oracle's own rate.
+
+    The fast sum's error is not spread evenly: most of the H error sits on targets about
+    eps_I from the boundary line charges, a layer holding about 1% of the points.  Targets
+    and sources are therefore sampled in two strata (within side/80 of the boundary, and the
+    rest; every boundary quadrature point counts as near), half the sample in each, and the
+    relative L2 errors are the stratum-weighted estimates of the all-points values."""
+    import synth
     from oracle import direct
     y, x, w, q = d["y"], d["x"], d["w"], d["q"]
     V = (d["h"] ** 2) * d["M_tgt"]
+    side, rc = 4.0, 0.5
+    band = side / 80
     rng = np.random.default_rng(12345)
-    it = np.sort(rng.choice(nt, args.samples, replace=False))
-    js = np.sort(rng.choice(ns, args.samples, replace=False))
+    it, wt = stratified_sample(synth.rounded_rect_sdf(y, side, side, rc) > -band, args.samples, rng)
+    near_s = synth.rounded_rect_sdf(x, side, side, rc) > -band
+    near_s[w != d["h"] ** 2] = True  # boundary quadrature points
+    js, wsr = stratified_sample(near_s, args.samples, rng)
     a = time.perf_counter()
     phi1, H1 = direct.forward(y[it], x, w, q)
     t_f = time.perf_counter() - a
@@ -262,8 +291,14 @@ def accuracy_and_cpu(d, r, args, nt, ns):
     u1 = direct.adjoint(y, x[js], w[js], V=V)
     t_a = time.perf_counter() - a
     phi, H, u = r["phi"].cpu().numpy()[it], r["H"].cpu().numpy()[it], r["u"].cpu().numpy()[js]
-    rel = lambda a_, b_: float(np.linalg.norm(a_ - b_) / np.linalg.norm(b_))
-    err = {"phi": rel(phi, phi1), "H": rel(H, H1), "HT": rel(u, u1), "samples": args.samples}
+
+    def rel(a_, b_, wgt):
+        e2 = ((a_ - b_) ** 2).reshape(len(wgt), -1).sum(axis=1)
+        r2 = (b_ ** 2).reshape(len(wgt), -1).sum(axis=1)
+        return float(np.sqrt(np.dot(wgt, e2) / np.dot(wgt, r2)))
+
+    err = {"phi": rel(phi, phi1, wt), "H": rel(H, H1, wt), "HT": rel(u, u1, wsr),
+           "samples": f"{len(it)} targets and {len(js)} sources, stratified by distance to the boundary"}
     # whole-job CPU time extrapolated linearly from the sample (the direct sum is exactly O(N_t N_s))
     t_full = t_f * nt / len(it) + t_a * ns / len(js)
     cpu = {"value": (nt + ns) / t_full, "unit": "points/s", "cores": direct.threads(), "kind": "oracle",
