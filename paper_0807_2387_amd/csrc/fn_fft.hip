@@ -127,7 +127,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, c
 // block must call it.  TWM: the twiddle table belongs to a transform TWM times
 // longer (entry TWM k is e^{-2 pi i k / N}).
 template <int TWM = 1, typename C>
-__device__ void fft_line(C *buf, int N, int log2N, int lt, int NT, const C *__restrict__ tw)
+__device__ __forceinline__ void fft_line(C *buf, int N, int log2N, int lt, int NT, const C *__restrict__ tw)
 {
     int L = 1, rem = log2N;
     while (rem >= 3) {
@@ -178,7 +178,7 @@ __global__ void k_kr_samples(double2 *a, int n, const double *__restrict__ coef,
 // line.  For N = 3M the three decimated sequences x[3i + s] are transformed as
 // M-point lines side by side, then X[j + rM] = sum_s omega^{rs} w^{sj} Y_s[j]
 // (w = e^{-2 pi i/N}, omega = w^M) in place.
-__global__ void __launch_bounds__(256) k_lines64(double2 *a, int N, int log2N, int64_t stride, int64_t dist,
+__global__ void __launch_bounds__(512) k_lines64(double2 *a, int N, int log2N, int64_t stride, int64_t dist,
                                                  int lines, const double2 *__restrict__ tw, int r3)
 {
     extern __shared__ double2 sh64[];
@@ -233,7 +233,7 @@ __global__ void k_make_W(const double2 *__restrict__ bl, int n, const double *__
 // ---------------------------------------------------------------- grid passes
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_rows_fwd(const R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
+__global__ void __launch_bounds__(512) k_rows_fwd(const R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
                                                   int nfield, cplx<R> *__restrict__ spec, int64_t ldS,
                                                   int64_t sfstride, int G, int log2G, int nh,
                                                   const cplx<R> *__restrict__ tw)
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) k_rows_fwd(const R *__restrict__ grid, in
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
+__global__ void __launch_bounds__(512) k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
                                               cplx<R> *__restrict__ out, int64_t ofstride, int64_t ldS,
                                               int Ey, int mode, int G, int log2G, int nh,
                                               const R *__restrict__ W, const cplx<R> *__restrict__ tw)
@@ -349,7 +349,7 @@ struct OutSpec {
 };
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_rows_inv(const cplx<R> *__restrict__ T, int64_t tfstride, int64_t ldS,
+__global__ void __launch_bounds__(512) k_rows_inv(const cplx<R> *__restrict__ T, int64_t tfstride, int64_t ldS,
                                                   R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
                                                   OutSpec os, int G, int log2G, int nh,
                                                   const cplx<R> *__restrict__ tw)
@@ -423,14 +423,19 @@ hipError_t launch_kr_samples(double2 *a, int n, const double *coef, int p, doubl
     return hipGetLastError();
 }
 
-// n a power of two or three times one (n / FFT_EPT threads per line, at most 256).
+// Line FFTs of length N run on NT = N / FFT_EPT threads; a block holds enough
+// lines to make at least 256 threads (one line of 512 threads at N = 8192).
+static inline int fft_nt(int N) { return N / FFT_EPT; }
+static inline int fft_per(int N) { return fft_nt(N) >= 256 ? 1 : 256 / fft_nt(N); }
+
+// n a power of two or three times one (n / FFT_EPT threads per line, at most 512).
 hipError_t launch_fft2d_c2c64(double2 *a, int n, const double2 *tw, hipStream_t st)
 {
     const int r3 = (n % 3 == 0) ? 1 : 0;
     const int M = r3 ? n / 3 : n;
-    if ((M & (M - 1)) || M < FFT_EPT || n / FFT_EPT > 256) return hipErrorInvalidValue;
-    const int NT = n / FFT_EPT;
-    const int per = 256 / NT;
+    if ((M & (M - 1)) || M < FFT_EPT || n / FFT_EPT > 512) return hipErrorInvalidValue;
+    const int NT = fft_nt(n);
+    const int per = fft_per(n);
     const size_t lds = (size_t)per * n * sizeof(double2);
     const int lg = ilog2(M);
     int nb = (n + per - 1) / per;
@@ -454,21 +459,20 @@ hipError_t launch_make_W(const double2 *bl, int n, const double *psihat, int pre
 template <typename R>
 static size_t fft_lds_bytes(int G)
 {
-    const int NT = G / FFT_EPT, per = 256 / NT;
-    return (size_t)per * G * sizeof(cplx<R>);
+    return (size_t)fft_per(G) * G * sizeof(cplx<R>);
 }
 
 template <typename R>
 static hipError_t rows_fwd_t(int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey, int nfield,
                              void *spec, int64_t ldS, int64_t sfstride, const void *tw, hipStream_t st)
 {
-    const int NT = G / FFT_EPT, per = 256 / NT;
+    const int NT = fft_nt(G), per = fft_per(G);
     const int lines = (nfield == 1) ? (Ey + 1) / 2 : Ey;
     const int nb = (lines + per - 1) / per;
     hipError_t e = hipFuncSetAttribute((const void *)k_rows_fwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)fft_lds_bytes<R>(G));
     if (e != hipSuccess) return e;
-    k_rows_fwd<R><<<nb, 256, fft_lds_bytes<R>(G), st>>>((const R *)grid, fstride, Ex, Ey, nfield,
+    k_rows_fwd<R><<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const R *)grid, fstride, Ex, Ey, nfield,
                                                        (cplx<R> *)spec, ldS, sfstride, G, ilog2(G), nh,
                                                        (const cplx<R> *)tw);
     return hipGetLastError();
@@ -487,12 +491,12 @@ template <typename R>
 static hipError_t cols_t(int G, int nh, const void *spec, int64_t sfstride, void *out, int64_t ofstride,
                          int64_t ldS, int Ey, int mode, const void *W, const void *tw, hipStream_t st)
 {
-    const int NT = G / FFT_EPT, per = 256 / NT;
+    const int NT = fft_nt(G), per = fft_per(G);
     const int nb = (nh + 1 + per - 1) / per;
     hipError_t e = hipFuncSetAttribute((const void *)k_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)fft_lds_bytes<R>(G));
     if (e != hipSuccess) return e;
-    k_cols<R><<<nb, 256, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, sfstride, (cplx<R> *)out, ofstride,
+    k_cols<R><<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, sfstride, (cplx<R> *)out, ofstride,
                                                    ldS, Ey, mode, G, ilog2(G), nh, (const R *)W,
                                                    (const cplx<R> *)tw);
     return hipGetLastError();
@@ -537,13 +541,13 @@ static hipError_t rows_inv_t(int G, int nh, const void *T, int64_t tfstride, int
             add(1, 0, 2, 0); add(1, 0, 2, 1);
         }
     }
-    const int NT = G / FFT_EPT, per = 256 / NT;
+    const int NT = fft_nt(G), per = fft_per(G);
     const int lines = (Ey + 1) / 2;
     const int nb = (lines + per - 1) / per;
     hipError_t e = hipFuncSetAttribute((const void *)k_rows_inv<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)fft_lds_bytes<R>(G));
     if (e != hipSuccess) return e;
-    k_rows_inv<R><<<nb, 256, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)T, tfstride, ldS, (R *)grid, fstride,
+    k_rows_inv<R><<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)T, tfstride, ldS, (R *)grid, fstride,
                                                         Ex, Ey, os, G, ilog2(G), nh, (const cplx<R> *)tw);
     return hipGetLastError();
 }
@@ -557,9 +561,5 @@ hipError_t launch_rows_inv(int precision, int G, int nh, const void *T, int64_t 
     return rows_inv_t<float>(G, nh, T, tfstride, ldS, grid, fstride, Ex, Ey, fwd, want_phi, want_h, tw, st);
 }
 
-size_t fft_lds_limit(int precision, int G)
-{
-    return precision == FN_FP64 ? fft_lds_bytes<double>(G) : fft_lds_bytes<float>(G);
-}
 
 }  // namespace fn

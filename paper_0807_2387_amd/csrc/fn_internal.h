@@ -15,7 +15,7 @@ namespace fn {
 constexpr int TILE = 32;        // spread / gather tile edge in grid cells
 constexpr int MAXM = 8;         // largest window half-width
 constexpr int MAXP = 12;        // largest regularization degree
-constexpr int FFT_EPT = 32;     // complex elements held per thread in the LDS FFT
+constexpr int FFT_EPT = 16;     // complex elements held per thread in the LDS FFT
 constexpr int MAXG = 8192;      // largest FFT grid
 
 template <typename R> struct cplx_t;
@@ -184,7 +184,6 @@ hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t s
 hipError_t launch_rows_inv(int precision, int G, int nh, const void *T, int64_t tfstride, int64_t ldS,
                            void *grid, int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h,
                            const void *tw, hipStream_t st);
-size_t fft_lds_limit(int precision, int G);
 // near field + final
 struct NearArgs {
     double eps2g;        // eps_I^2 in grid units^2

@@ -178,20 +178,25 @@ template <int M2>
 __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restrict__ fr32,
                                                             const float *__restrict__ val, int64_t N,
                                                             const uint32_t *__restrict__ cstart, int Ex, int Ey,
-                                                            int ntx, int nty, int nfield, double *__restrict__ ptile,
+                                                            int ntx, int nty, double *__restrict__ ptile,
                                                             const WinPoly wp)
 {
     constexpr int PT = TILE + M2 - 1;
     constexpr int PT2 = PT * PT;
     constexpr int RG = (72 / M2) < M2 ? (72 / M2) : M2;
-    extern __shared__ double acc[];  // [SPREAD_WAVES][nfield][PT2]
-    const int tile = blockIdx.x;
+    extern __shared__ double acc[];  // [SPREAD_WAVES][PT2]
+    // one block per (field, tile): a block's LDS holds one field, so a two-field
+    // spread keeps the occupancy of a one-field one
+    const int ntiles = ntx * nty;
+    const int f = blockIdx.x / ntiles;
+    const int tile = blockIdx.x - f * ntiles;
     const int tx = tile % ntx, ty = tile / ntx;
     const int x0 = tx * TILE, y0 = ty * TILE;
     const int wv = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < SPREAD_WAVES * nfield * PT2; i += SPREAD_NT) acc[i] = 0.0;
+    for (int i = threadIdx.x; i < SPREAD_WAVES * PT2; i += SPREAD_NT) acc[i] = 0.0;
     __syncthreads();
-    double *myacc = acc + (int64_t)wv * nfield * PT2;
+    double *myacc = acc + (int64_t)wv * PT2;
+    const float *fval = val + (int64_t)f * N;
     for (int c = threadIdx.x; c < TILE * TILE; c += SPREAD_NT) {
         const int lx = c % TILE, ly = c / TILE;
         const int gx = x0 + lx, gy = y0 + ly;
@@ -202,42 +207,39 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
             s1 = cstart[cell + 1];
         }
         if (s0 == s1) continue;
-        for (int f = 0; f < nfield; ++f)
 #pragma unroll
-            for (int g0 = 0; g0 < M2; g0 += RG) {
-                float r[RG][M2];
+        for (int g0 = 0; g0 < M2; g0 += RG) {
+            float r[RG][M2];
 #pragma unroll
-                for (int bb = 0; bb < RG; ++bb)
+            for (int bb = 0; bb < RG; ++bb)
 #pragma unroll
-                    for (int a = 0; a < M2; ++a) r[bb][a] = 0.f;
-                for (uint32_t i = s0; i < s1; ++i) {
-                    const float v = val[(int64_t)f * N + i];
-                    float wx[M2], wy[M2];
-                    taps<float, M2>(wp, fr32[i], 0.f, 0.f, 0.f, wx);
-                    taps<float, M2>(wp, fr32[N + i], 0.f, 0.f, 0.f, wy);
+                for (int a = 0; a < M2; ++a) r[bb][a] = 0.f;
+            for (uint32_t i = s0; i < s1; ++i) {
+                const float v = fval[i];
+                float wx[M2], wy[M2];
+                taps<float, M2>(wp, fr32[i], 0.f, 0.f, 0.f, wx);
+                taps<float, M2>(wp, fr32[N + i], 0.f, 0.f, 0.f, wy);
 #pragma unroll
-                    for (int bb = 0; bb < RG; ++bb) {
-                        const float vy = g0 + bb < M2 ? v * wy[g0 + bb < M2 ? g0 + bb : 0] : 0.f;
+                for (int bb = 0; bb < RG; ++bb) {
+                    const float vy = g0 + bb < M2 ? v * wy[g0 + bb < M2 ? g0 + bb : 0] : 0.f;
 #pragma unroll
-                        for (int a = 0; a < M2; ++a) r[bb][a] = fmaf(vy, wx[a], r[bb][a]);
-                    }
+                    for (int a = 0; a < M2; ++a) r[bb][a] = fmaf(vy, wx[a], r[bb][a]);
                 }
-                double *af = myacc + f * PT2 + (ly + g0) * PT + lx;
-#pragma unroll
-                for (int bb = 0; bb < RG; ++bb)
-                    if (g0 + bb < M2)
-#pragma unroll
-                        for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)r[bb][a]);
             }
+            double *af = myacc + (ly + g0) * PT + lx;
+#pragma unroll
+            for (int bb = 0; bb < RG; ++bb)
+                if (g0 + bb < M2)
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)r[bb][a]);
+        }
     }
     __syncthreads();
-    const int ntiles = ntx * nty;
-    for (int f = 0; f < nfield; ++f)
-        for (int c = threadIdx.x; c < PT2; c += SPREAD_NT) {
-            double v = acc[f * PT2 + c];
-            for (int w = 1; w < SPREAD_WAVES; ++w) v += acc[((int64_t)w * nfield + f) * PT2 + c];
-            ptile[((int64_t)f * ntiles + tile) * PT2 + c] = v;
-        }
+    for (int c = threadIdx.x; c < PT2; c += SPREAD_NT) {
+        double v = acc[c];
+        for (int w = 1; w < SPREAD_WAVES; ++w) v += acc[(int64_t)w * PT2 + c];
+        ptile[((int64_t)f * ntiles + tile) * PT2 + c] = v;
+    }
 }
 
 template <typename R>
@@ -353,10 +355,11 @@ hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, con
 #if FN_SPREAD_CELLS
     if (std::is_same<R, float>::value) {
         auto kc = k_spread_cells<M2>;
-        hipError_t e = hipFuncSetAttribute((const void *)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const size_t lds1 = (size_t)SPREAD_WAVES * PT * PT * sizeof(double);
+        hipError_t e = hipFuncSetAttribute((const void *)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
         if (e != hipSuccess) return e;
-        kc<<<ntiles, SPREAD_NT, lds, st>>>(b.fr32[set], (const float *)val, N, b.cstart[set], g.ext[0], g.ext[1],
-                                           g.ntile[0], g.ntile[1], nfield, b.ptile, P.wpoly);
+        kc<<<ntiles * nfield, SPREAD_NT, lds1, st>>>(b.fr32[set], (const float *)val, N, b.cstart[set], g.ext[0],
+                                                     g.ext[1], g.ntile[0], g.ntile[1], b.ptile, P.wpoly);
         return hipGetLastError();
     }
 #endif
