@@ -91,6 +91,11 @@ template <int RAD, typename C> __device__ __forceinline__ void dftR(C *v)
     else dft8(v);
 }
 
+// A line of N elements sits in LDS with one pad slot after every 8 elements:
+// element i at lp(i).  Without it the first two radix-8 passes store 8 outputs
+// per lane at a 64-byte lane stride (16- and 8-way bank conflicts).
+__host__ __device__ constexpr int lp(int i) { return i + (i >> 3); }
+
 // One Stockham pass over a line in LDS.  NT threads, each FFT_EPT/RAD butterflies.
 // The twiddle table holds N * TWM entries (a line of a transform TWM times longer).
 template <int RAD, int TWM, typename C>
@@ -103,7 +108,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, c
     for (int c = 0; c < PER; ++c) {
         const int j = lt + c * NT;
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) v[c * RAD + r] = buf[j + r * nb];
+        for (int r = 0; r < RAD; ++r) v[c * RAD + r] = buf[lp(j + r * nb)];
     }
     __syncthreads();
     const int stride = N / (L * RAD);
@@ -118,7 +123,7 @@ __device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, c
         dftR<RAD>(&v[c * RAD]);
         const int o = (j - k) * RAD + k;
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) buf[o + q * L] = v[c * RAD + q];
+        for (int q = 0; q < RAD; ++q) buf[lp(o + q * L)] = v[c * RAD + q];
     }
     __syncthreads();
 }
@@ -137,12 +142,6 @@ __device__ __forceinline__ void fft_line(C *buf, int N, int log2N, int lt, int N
     }
     if (rem == 2) fft_pass<4, TWM>(buf, N, L, lt, NT, tw);
     else if (rem == 1) fft_pass<2, TWM>(buf, N, L, lt, NT, tw);
-}
-
-template <typename C> __device__ __forceinline__ void conj_line(C *buf, int N, int lt, int NT)
-{
-    for (int e = lt; e < N; e += NT) buf[e].y = -buf[e].y;
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------- plan kernels
@@ -178,41 +177,41 @@ __global__ void k_kr_samples(double2 *a, int n, const double *__restrict__ coef,
 // line.  For N = 3M the three decimated sequences x[3i + s] are transformed as
 // M-point lines side by side, then X[j + rM] = sum_s omega^{rs} w^{sj} Y_s[j]
 // (w = e^{-2 pi i/N}, omega = w^M) in place.
-__global__ void __launch_bounds__(512) k_lines64(double2 *a, int N, int log2N, int64_t stride, int64_t dist,
+__global__ void __launch_bounds__(1024) k_lines64(double2 *a, int N, int log2N, int64_t stride, int64_t dist,
                                                  int lines, const double2 *__restrict__ tw, int r3)
 {
     extern __shared__ double2 sh64[];
     const int NT = N / FFT_EPT, per = blockDim.x / NT;
     const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
     const int q = blockIdx.x * per + li;
-    double2 *buf = sh64 + (int64_t)li * N;
+    double2 *buf = sh64 + (int64_t)li * lp(N);
     if (!r3) {
-        for (int e = lt; e < N; e += NT) buf[e] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
+        for (int e = lt; e < N; e += NT) buf[lp(e)] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
         __syncthreads();
         fft_line(buf, N, log2N, lt, NT, tw);
     } else {
         const int M = N / 3, NTs = NT / 3, grp = lt / NTs, slt = lt % NTs;
         for (int e = lt; e < N; e += NT)
-            buf[(e % 3) * M + e / 3] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
+            buf[lp((e % 3) * M + e / 3)] = q < lines ? a[q * dist + e * stride] : make_double2(0, 0);
         __syncthreads();
-        fft_line<3>(buf + grp * M, M, log2N, slt, NTs, tw);
+        fft_line<3>(buf + lp(grp * M), M, log2N, slt, NTs, tw);  // M is a multiple of 8
         const double c3 = -0.5, s3 = -0.86602540378443864676372317075294;  // omega = e^{-2 pi i/3}
         for (int j = lt; j < M; j += NT) {
-            const double2 y0 = buf[j];
-            const double2 y1 = cmul(buf[M + j], tw[j]);
-            const double2 y2 = cmul(buf[2 * M + j], tw[2 * j]);
+            const double2 y0 = buf[lp(j)];
+            const double2 y1 = cmul(buf[lp(M + j)], tw[j]);
+            const double2 y2 = cmul(buf[lp(2 * M + j)], tw[2 * j]);
             const double2 sp = make_double2(y1.x + y2.x, y1.y + y2.y);
             const double2 sm = make_double2(y1.x - y2.x, y1.y - y2.y);
-            buf[j] = make_double2(y0.x + sp.x, y0.y + sp.y);
+            buf[lp(j)] = make_double2(y0.x + sp.x, y0.y + sp.y);
             // y0 + c3 (y1 + y2) +- i s3 (y1 - y2)
             const double2 base = make_double2(y0.x + c3 * sp.x, y0.y + c3 * sp.y);
-            buf[M + j] = make_double2(base.x - s3 * sm.y, base.y + s3 * sm.x);
-            buf[2 * M + j] = make_double2(base.x + s3 * sm.y, base.y - s3 * sm.x);
+            buf[lp(M + j)] = make_double2(base.x - s3 * sm.y, base.y + s3 * sm.x);
+            buf[lp(2 * M + j)] = make_double2(base.x + s3 * sm.y, base.y - s3 * sm.x);
         }
         __syncthreads();
     }
     if (q < lines)
-        for (int e = lt; e < N; e += NT) a[q * dist + e * stride] = buf[e];
+        for (int e = lt; e < N; e += NT) a[q * dist + e * stride] = buf[lp(e)];
 }
 
 // W[lx * (n/2+1) + ly] = omega(lx) omega(ly) Re(b_l) / (psihat(lx) psihat(ly))^2, lx, ly in [0, n/2].
@@ -232,8 +231,13 @@ __global__ void k_make_W(const double2 *__restrict__ bl, int n, const double *__
 
 // ---------------------------------------------------------------- grid passes
 
+// FP32 row passes: two 1024-thread blocks (72 KB of LDS each) fit a CU when a
+// thread holds at most 64 registers, which they do without spilling; the FP64
+// line (147 KB) leaves room for one block only, so its registers are not capped.
+#define FN_ROWS_WAVES __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
+
 template <typename R>
-__global__ void __launch_bounds__(512) k_rows_fwd(const R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
+__global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_fwd(const R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
                                                   int nfield, cplx<R> *__restrict__ spec, int64_t ldS,
                                                   int64_t sfstride, int G, int log2G, int nh,
                                                   const cplx<R> *__restrict__ tw)
@@ -243,8 +247,8 @@ __global__ void __launch_bounds__(512) k_rows_fwd(const R *__restrict__ grid, in
     C *sh = reinterpret_cast<C *>(smem_rf);
     const int NT = G / FFT_EPT, per = blockDim.x / NT;
     const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
-    const int q = blockIdx.x * per + li;
-    C *buf = sh + (int64_t)li * G;
+    const int q = xcd_block(blockIdx.x, gridDim.x) * per + li;  // spec is written transposed
+    C *buf = sh + (int64_t)li * lp(G);
     // line q: nfield == 1 packs rows 2q, 2q+1; nfield == 2 packs fields 0, 1 of row q
     int ya, yb;
     const R *ra, *rb;
@@ -261,14 +265,14 @@ __global__ void __launch_bounds__(512) k_rows_fwd(const R *__restrict__ grid, in
     for (int e = lt; e < G; e += NT) {
         R a = (ra && e < Ex) ? ra[e] : (R)0;
         R b = (rb && e < Ex) ? rb[e] : (R)0;
-        buf[e] = mk<C>(a, b);
+        buf[lp(e)] = mk<C>(a, b);
     }
     __syncthreads();
     fft_line(buf, G, log2G, lt, NT, tw);
     C *sa = spec;
     C *sb = (nfield == 1) ? spec : spec + sfstride;
     for (int l = lt; l <= nh; l += NT) {
-        C z = buf[l], zc = conjc(buf[(G - l) & (G - 1)]);
+        C z = buf[lp(l)], zc = conjc(buf[lp((G - l) & (G - 1))]);
         C A = mk<C>((R)0.5 * (z.x + zc.x), (R)0.5 * (z.y + zc.y));
         C B = mk<C>((R)0.5 * (z.y - zc.y), (R)-0.5 * (z.x - zc.x));
         if (ra) sa[(int64_t)l * ldS + ya] = A;
@@ -277,7 +281,7 @@ __global__ void __launch_bounds__(512) k_rows_fwd(const R *__restrict__ grid, in
 }
 
 template <typename R>
-__global__ void __launch_bounds__(512) k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
+__global__ void __launch_bounds__(1024) k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
                                               cplx<R> *__restrict__ out, int64_t ofstride, int64_t ldS,
                                               int Ey, int mode, int G, int log2G, int nh,
                                               const R *__restrict__ W, const cplx<R> *__restrict__ tw)
@@ -289,13 +293,13 @@ __global__ void __launch_bounds__(512) k_cols(const cplx<R> *__restrict__ spec, 
     const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
     const int qx = blockIdx.x * per + li;  // l_x of this line
     const bool valid = qx <= nh;
-    C *buf = sh + (int64_t)li * G;
+    C *buf = sh + (int64_t)li * lp(G);
     const R twopi = (R)6.283185307179586476925286766559;
     C acc[FFT_EPT];
     const int nin = (mode == COL_ADJ_H) ? 2 : 1;
     for (int f = 0; f < nin; ++f) {
         const C *col = spec + f * sfstride + (int64_t)qx * ldS;
-        for (int e = lt; e < G; e += NT) buf[e] = (valid && e < Ey) ? col[e] : mk<C>((R)0, (R)0);
+        for (int e = lt; e < G; e += NT) buf[lp(e)] = (valid && e < Ey) ? col[e] : mk<C>((R)0, (R)0);
         __syncthreads();
         fft_line(buf, G, log2G, lt, NT, tw);
 #pragma unroll
@@ -303,7 +307,7 @@ __global__ void __launch_bounds__(512) k_cols(const cplx<R> *__restrict__ spec, 
             const int k = lt + i * NT;
             const int ly = k <= G / 2 ? k : k - G;
             const int aly = ly < 0 ? -ly : ly;
-            C x = buf[k];
+            C x = buf[lp(k)];
             R w = (valid && aly <= nh) ? W[(int64_t)qx * (nh + 1) + aly] : (R)0;
             C v = mk<C>(w * x.x, w * x.y);
             if (mode == COL_ADJ_H) {
@@ -328,13 +332,13 @@ __global__ void __launch_bounds__(512) k_cols(const cplx<R> *__restrict__ spec, 
                 R l = (R)ly * twopi;
                 v = mk<C>(l * v.y, -l * v.x);
             }
-            buf[k] = conjc(v);
+            buf[lp(k)] = conjc(v);
         }
         __syncthreads();
         fft_line(buf, G, log2G, lt, NT, tw);
         if (valid) {
             C *dst = out + o * ofstride + (int64_t)qx * ldS;
-            for (int e = lt; e < Ey; e += NT) dst[e] = conjc(buf[e]);
+            for (int e = lt; e < Ey; e += NT) dst[e] = conjc(buf[lp(e)]);
         }
         __syncthreads();
     }
@@ -349,7 +353,7 @@ struct OutSpec {
 };
 
 template <typename R>
-__global__ void __launch_bounds__(512) k_rows_inv(const cplx<R> *__restrict__ T, int64_t tfstride, int64_t ldS,
+__global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_inv(const cplx<R> *__restrict__ T, int64_t tfstride, int64_t ldS,
                                                   R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
                                                   OutSpec os, int G, int log2G, int nh,
                                                   const cplx<R> *__restrict__ tw)
@@ -359,8 +363,8 @@ __global__ void __launch_bounds__(512) k_rows_inv(const cplx<R> *__restrict__ T,
     C *sh = reinterpret_cast<C *>(smem_ri);
     const int NT = G / FFT_EPT, per = blockDim.x / NT;
     const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
-    const int y0 = 2 * (blockIdx.x * per + li);
-    C *buf = sh + (int64_t)li * G;
+    const int y0 = 2 * (xcd_block(blockIdx.x, gridDim.x) * per + li);  // T is read transposed
+    C *buf = sh + (int64_t)li * lp(G);
     const R twopi = (R)6.283185307179586476925286766559;
     for (int pr = 0; pr < os.n; pr += 2) {
         const bool hasb = pr + 1 < os.n;
@@ -391,14 +395,14 @@ __global__ void __launch_bounds__(512) k_rows_inv(const cplx<R> *__restrict__ T,
                 }
             }
             // z = A + i B, conjugated for the inverse-by-forward trick
-            buf[e] = mk<C>(A.x - B.y, -(A.y + B.x));
+            buf[lp(e)] = mk<C>(A.x - B.y, -(A.y + B.x));
         }
         __syncthreads();
         fft_line(buf, G, log2G, lt, NT, tw);
         R *ga = grid + os.dst[pr] * fstride + (int64_t)ya * Ex;
         R *gb = grid + (hasb ? os.dst[pr + 1] : 0) * fstride + (int64_t)(hasb ? yb : 0) * Ex;
         for (int e = lt; e < Ex; e += NT) {
-            C z = buf[e];  // conj of the inverse transform: real part a, imag -b
+            C z = buf[lp(e)];  // conj of the inverse transform: real part a, imag -b
             if (va) ga[e] = z.x;
             if (vb) gb[e] = -z.y;
         }
@@ -424,19 +428,19 @@ hipError_t launch_kr_samples(double2 *a, int n, const double *coef, int p, doubl
 }
 
 // Line FFTs of length N run on NT = N / FFT_EPT threads; a block holds enough
-// lines to make at least 256 threads (one line of 512 threads at N = 8192).
+// lines to make at least 256 threads (one line of 1024 threads at N = 8192).
 static inline int fft_nt(int N) { return N / FFT_EPT; }
 static inline int fft_per(int N) { return fft_nt(N) >= 256 ? 1 : 256 / fft_nt(N); }
 
-// n a power of two or three times one (n / FFT_EPT threads per line, at most 512).
+// n a power of two or three times one (n / FFT_EPT threads per line, at most 1024).
 hipError_t launch_fft2d_c2c64(double2 *a, int n, const double2 *tw, hipStream_t st)
 {
     const int r3 = (n % 3 == 0) ? 1 : 0;
     const int M = r3 ? n / 3 : n;
-    if ((M & (M - 1)) || M < FFT_EPT || n / FFT_EPT > 512) return hipErrorInvalidValue;
+    if ((M & (M - 1)) || M < FFT_EPT || n / FFT_EPT > 1024) return hipErrorInvalidValue;
     const int NT = fft_nt(n);
     const int per = fft_per(n);
-    const size_t lds = (size_t)per * n * sizeof(double2);
+    const size_t lds = (size_t)per * lp(n) * sizeof(double2);
     const int lg = ilog2(M);
     int nb = (n + per - 1) / per;
     hipError_t e = hipFuncSetAttribute((const void *)k_lines64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -459,7 +463,7 @@ hipError_t launch_make_W(const double2 *bl, int n, const double *psihat, int pre
 template <typename R>
 static size_t fft_lds_bytes(int G)
 {
-    return (size_t)fft_per(G) * G * sizeof(cplx<R>);
+    return (size_t)fft_per(G) * lp(G) * sizeof(cplx<R>);
 }
 
 template <typename R>

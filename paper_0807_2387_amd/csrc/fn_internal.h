@@ -15,8 +15,20 @@ namespace fn {
 constexpr int TILE = 32;        // spread / gather tile edge in grid cells
 constexpr int MAXM = 8;         // largest window half-width
 constexpr int MAXP = 12;        // largest regularization degree
-constexpr int FFT_EPT = 16;     // complex elements held per thread in the LDS FFT
+constexpr int FFT_EPT = 8;      // complex elements held per thread in the LDS FFT
 constexpr int MAXG = 8192;      // largest FFT grid
+
+// Workgroups are handed to the 8 XCDs round-robin (block b to XCD b % 8), and
+// each XCD has its own L2.  xcd_block maps the i-th block of XCD x to logical
+// block x * (nb / 8) + min(x, nb % 8) + i, a bijection of [0, nb), so that one
+// XCD works on a contiguous range of lines and blocks sharing cache lines meet
+// in one L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int x = b % NXCD, i = b / NXCD, q = nb / NXCD, r = nb % NXCD;
+    return x * q + (x < r ? x : r) + i;
+}
 
 template <typename R> struct cplx_t;
 template <> struct cplx_t<float> { using type = float2; };
