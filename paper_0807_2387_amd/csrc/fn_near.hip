@@ -74,11 +74,13 @@ struct NearSets {
 
 // U(x) = sum_{k<P} c_k x^k and U'(x) in one Horner sweep (the derivative
 // accumulates the running value: synthetic division); the coefficients are
-// kernel arguments, so they live in scalar registers.
+// kernel arguments, so they live in scalar registers.  lead = c[P-1] comes in a
+// vector register: a VALU instruction takes one scalar operand, so a scalar
+// leading coefficient would cost a register copy in every call.
 template <int P, typename T>
-__device__ __forceinline__ void poly2(const T *c, T x, T &u, T &du)
+__device__ __forceinline__ void poly2(const T *c, T lead, T x, T &u, T &du)
 {
-    T t = c[P - 1], d = T(0);
+    T t = lead, d = T(0);
 #pragma unroll
     for (int i = P - 2; i >= 0; --i) {
         d = (i == P - 2) ? t : fma(d, x, t);
@@ -90,10 +92,10 @@ __device__ __forceinline__ void poly2(const T *c, T x, T &u, T &du)
 
 // U'(x) by plain Horner over its own coefficients (k+1) u_{k+1}.
 template <int P>
-__device__ __forceinline__ double poly_d(const double *dc, double x)
+__device__ __forceinline__ double poly_d(const double *dc, double lead, double x)
 {
     if (P < 2) return 0.0;
-    double t = dc[P - 2 < 0 ? 0 : P - 2];
+    double t = lead;  // dc[P - 2], in a vector register
 #pragma unroll
     for (int i = P - 3; i >= 0; --i) t = fma(t, x, dc[i]);
     return t;
@@ -134,7 +136,8 @@ __device__ __forceinline__ double ln64(double x, const NearArgs &na)
 
 constexpr double LN2_4PI = 0.05515890334192413571;  // ln(2)/(4 pi)
 
-// x = (r/eps_I)^2 + XMIN keeps ln x and 1/x finite.  In the mixed path this
+// x = (r/eps_I)^2 + XMIN keeps ln x and 1/x finite (XMIN enters through the
+// innermost FMA, so x costs two instructions in the mixed path).  In the mixed path this
 // moves only pairs closer than ~1e-14 cells; in the FP64 path the shift is
 // below any representable offset.
 constexpr double XMIN32 = 1e-30;
@@ -150,17 +153,18 @@ constexpr double XMIN64 = 1e-300;
 // sum s (1/(4pi x) + T'(x)) d; the caller applies 2G/e2 (2G/(eps_I G) in the
 // mixed path).
 template <int KIND, int P, bool F32>
-__device__ __forceinline__ void pair(const NearArgs &na, double e2, double dx, double dy, double w0, double w1,
-                                     double &a0, double &a1, double &a2)
+__device__ __forceinline__ void pair(const NearArgs &na, double lead, double e2, double dx, double dy, double w0,
+                                     double w1, double &a0, double &a1, double &a2)
 {
     constexpr bool PHI = KIND == 0 || KIND == 2;
     constexpr bool GRAD = KIND == 0 || KIND == 1 || KIND == 3;
-    const double r2 = fma(dx, dx, dy * dy);
-    // mixed path: offsets come in units of eps_I, so x = r2 and the zone is r2 < 1
-    const double x = F32 ? r2 + XMIN32 : fma(r2, na.inv_e2, XMIN64);
+    // mixed path: offsets come in units of eps_I, so x = r2 + XMIN and the zone is x < 1
+    // (adding XMIN below 1e-14 cannot move x across 1); FP64 path: the zone test on r2
+    const double r2 = F32 ? 0.0 : fma(dx, dx, dy * dy);
+    const double x = F32 ? fma(dx, dx, fma(dy, dy, XMIN32)) : fma(r2, na.inv_e2, XMIN64);
     double u = 0.0, du = 0.0;
-    if (PHI) poly2<P, double>(na.u, x, u, du);
-    else du = poly_d<P>(na.du, x);
+    if (PHI) poly2<P, double>(na.u, lead, x, u, du);
+    else du = poly_d<P>(na.du, lead, x);
     double lnx = 0.0, rx = 0.0;
     if (F32) {
         const float xf = (float)x;
@@ -170,7 +174,7 @@ __device__ __forceinline__ void pair(const NearArgs &na, double e2, double dx, d
         if (PHI) lnx = ln64(x, na);
         if (GRAD) rx = rcp64(x);
     }
-    if (r2 < e2) {
+    if ((F32 ? x : r2) < e2) {
         if (PHI) {
             const double phi_t = fma(F32 ? -LN2_4PI : -INV_4PI, lnx, -u);
             a0 = fma(w0, phi_t, a0);
@@ -251,6 +255,9 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     if (nhome == 0) return;  // uniform
 
     const double e2 = na.eps2g;
+    // leading polynomial coefficient, pinned to a vector register (see poly2)
+    double lead = (KIND == 0 || KIND == 2) ? na.u[P - 1] : na.du[P < 2 ? 0 : P - 2];
+    asm volatile("" : "+v"(lead));
 
     for (uint32_t hb = 0; hb < nhome; hb += NTH) {
         const uint32_t k = hb + tid;
@@ -338,13 +345,13 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
                         const double2 q0 = pq[0], q1 = pq[1];
                         const double w00 = pw0[0], w10 = pw0[1];
                         const double w01 = PAY == 2 ? pw1[0] : 0.0, w11 = PAY == 2 ? pw1[1] : 0.0;
-                        pair<KIND, P, F32>(na, 1.0, hxs - q0.x, hys - q0.y, w00, w01, a0, a1, a2);
-                        pair<KIND, P, F32>(na, 1.0, hxs - q1.x, hys - q1.y, w10, w11, a0, a1, a2);
+                        pair<KIND, P, F32>(na, lead, 1.0, hxs - q0.x, hys - q0.y, w00, w01, a0, a1, a2);
+                        pair<KIND, P, F32>(na, lead, 1.0, hxs - q1.x, hys - q1.y, w10, w11, a0, a1, a2);
                     }
                     if (n) {
                         const double2 q0 = pq[0];
                         const double w00 = pw0[0], w01 = PAY == 2 ? pw1[0] : 0.0;
-                        pair<KIND, P, F32>(na, 1.0, hxs - q0.x, hys - q0.y, w00, w01, a0, a1, a2);
+                        pair<KIND, P, F32>(na, lead, 1.0, hxs - q0.x, hys - q0.y, w00, w01, a0, a1, a2);
                     }
                     continue;
                 }
@@ -358,14 +365,14 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
                     const int x0 = pc[0], x1 = pc[1];
                     const double w00 = pw0[0], w10 = pw0[1];
                     const double w01 = PAY == 2 ? pw1[0] : 0.0, w11 = PAY == 2 ? pw1[1] : 0.0;
-                    pair<KIND, P, F32>(na, e2, (double)(hcx - x0) + (px - q0.x), dyc + (py - q0.y), w00, w01, a0, a1, a2);
-                    pair<KIND, P, F32>(na, e2, (double)(hcx - x1) + (px - q1.x), dyc + (py - q1.y), w10, w11, a0, a1, a2);
+                    pair<KIND, P, F32>(na, lead, e2, (double)(hcx - x0) + (px - q0.x), dyc + (py - q0.y), w00, w01, a0, a1, a2);
+                    pair<KIND, P, F32>(na, lead, e2, (double)(hcx - x1) + (px - q1.x), dyc + (py - q1.y), w10, w11, a0, a1, a2);
                 }
                 if (n) {
                     const double2 q0 = pq[0];
                     const int x0 = pc[0];
                     const double w00 = pw0[0], w01 = PAY == 2 ? pw1[0] : 0.0;
-                    pair<KIND, P, F32>(na, e2, (double)(hcx - x0) + (px - q0.x), dyc + (py - q0.y), w00, w01, a0, a1, a2);
+                    pair<KIND, P, F32>(na, lead, e2, (double)(hcx - x0) + (px - q0.x), dyc + (py - q0.y), w00, w01, a0, a1, a2);
                 }
             }
         }
@@ -407,7 +414,7 @@ __global__ void __launch_bounds__(256) k_coincident(NearSets S, NearArgs na, int
         if (S.f_in[j] == px && S.f_in[S.n_in + j] == py) acc += S.pay[j];
     if (acc == 0.0) return;
     double phx = 0.0, d1 = 0.0, d2 = 0.0;
-    pair<2, P, F32>(na, F32 ? 1.0 : na.eps2g, 0.0, 0.0, 1.0, 0.0, phx, d1, d2);
+    pair<2, P, F32>(na, na.u[P - 1], F32 ? 1.0 : na.eps2g, 0.0, 0.0, 1.0, 0.0, phx, d1, d2);
     const double f = (na.czero - phx) * acc;
     const int64_t o = S.perm_out[gi];
     out[o] += adjoint ? S.w_out[gi] * f : f;
