@@ -9,8 +9,10 @@ resident in HBM before the timed region.
 Workload (default): rounded square of side 4 (corner radius 1/2), about 2^24
 jittered-lattice targets and 2^24 + 31k sources (cell points with charge
 -div M, boundary Gauss points with M.n), M a unit field whose angle is a sum of
-32 random cosine modes; FP32-mixed path, FFT grid 8192^2, Kaiser-Bessel m = 6,
-regularization degree p = 8, near radius eps_I = 7/4096.
+32 random cosine modes; FP32-mixed path, FFT grid 8192^2, bandwidth n = 6144,
+Kaiser-Bessel m = 6, regularization degree p = 6; the volume sources use the
+near radius eps_I = 3.5/n, the 31k boundary Gauss points (surface sources) their
+own eps_S = 9/n (fn_set_geometry_split).
 
 Prints ONE JSON line (rank 0).  `value` = (N_src + N_tgt) / (seconds per step).
 """
@@ -42,9 +44,11 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 24, help="about this many targets (and sources)")
     ap.add_argument("--grid", type=int, default=8192)
     ap.add_argument("--m", type=int, default=6)
-    ap.add_argument("--p", type=int, default=8)
-    ap.add_argument("--c", type=float, default=6.0,
-                    help="eps_I = c / n (6 at n = 3 grid/4: H within 3e-7 of the direct sum here)")
+    ap.add_argument("--p", type=int, default=6)
+    ap.add_argument("--c", type=float, default=3.5,
+                    help="eps_I = c / n for the volume sources (all sources when --cs 0)")
+    ap.add_argument("--cs", type=float, default=9.0,
+                    help="surface sources (the boundary Gauss points) get eps_S = cs / n; 0: one class")
     ap.add_argument("--band", type=int, default=None,
                     help="bandwidth n (default 3 grid/4, oversampling 4/3; 0 means grid/2)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
@@ -89,12 +93,17 @@ def main():
         args.band = 3 * args.grid // 4
     nband = args.band or args.grid // 2
     eps_I = args.c / nband
+    eps_S = args.cs / nband if args.cs else 0.0
+    n_surf = int(np.sum(w != d["h"] ** 2)) if args.cs else 0  # boundary points come last
+    if n_surf:
+        assert np.all(w[ns - n_surf:] != d["h"] ** 2)
 
     def run(precision, steps, warmup, profile):
-        S = fn.Solver(grid=args.grid, m=args.m, p=args.p, eps_I=eps_I, precision=precision, n=args.band)
+        S = fn.Solver(grid=args.grid, m=args.m, p=args.p, eps_I=eps_I, precision=precision, n=args.band,
+                      eps_S=eps_S)
         torch.cuda.synchronize()
         g0 = time.perf_counter()
-        S.set_geometry(ty, tx, tw)
+        S.set_geometry(ty, tx, tw, n_surf=n_surf)
         torch.cuda.synchronize()
         t_geom = time.perf_counter() - g0
         phi = torch.empty(nt, dtype=torch.float64, device=dev)
@@ -149,7 +158,8 @@ def main():
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "rounded square side 4, jittered lattice, 32-mode smooth M",
                    "n_tgt": nt, "n_src": ns, "grid": args.grid, "bandwidth": nband, "m": args.m, "p": args.p,
-                   "eps_I": eps_I, "precision": "fp32_mixed", "parallelism": "single_gpu"},
+                   "eps_I": eps_I, "eps_S": eps_S, "n_surf": n_surf, "precision": "fp32_mixed",
+                   "parallelism": "single_gpu"},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "set_geometry_ms": r["t_geom"] * 1e3,
         "roofline": roof,

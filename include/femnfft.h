@@ -67,7 +67,6 @@ enum {
 /*
  * Parameters of the method (all lengths on the unit torus the points are mapped to).
  *   grid      G, the oversampled FFT grid per dimension; power of two, 64..8192.
- *             The bandwidth is n = G/2 (oversampling factor 2).
  *   m         Kaiser-Bessel half-width in grid cells (2m taps per dimension), 2..8.
  *   p         regularization degree: the kernel is replaced near the origin by an
  *             even polynomial matching ln r and its first p-1 derivatives at eps_I
@@ -76,6 +75,14 @@ enum {
  *   eps_B     width of the boundary regularization near |x| = 1/2; 0 < eps_B < 1/4.
  *   precision FN_FP64 or FN_FP32_MIXED.
  *   n         bandwidth; the window shape is b = pi (2 - 1/sigma), sigma = G/n.
+ *   eps_S     near-field radius of surface sources (fn_set_geometry_split), 0 or in
+ *             the range of eps_I.  The sum is linear in the sources, so each class can
+ *             be summed with its own regularized kernel: the surface (line) charges
+ *             with K_R at eps_S, the others with K_R at eps_I.  Line charges need the
+ *             larger radius -- the error of the truncated Fourier series of K_R
+ *             concentrates near |r| = eps_I, where a line tangent to that circle sums
+ *             it up while an area density averages it out -- so eps_I can then be set
+ *             for the volume charges alone.  0: every source uses eps_I.
  */
 typedef struct fn_params {
     int32_t grid;
@@ -88,6 +95,7 @@ typedef struct fn_params {
     int32_t n;          /* bandwidth (kept Fourier modes |l| <= n/2): 0 means G/2 (oversampling
                            2); otherwise even, G/2 <= n <= 3G/4, a power of two or three
                            times one (3G/4: oversampling 4/3) */
+    double eps_S;       /* near-field radius of the surface sources; 0: none (see above) */
 } fn_params;
 
 /* Read-only facts about a context after fn_set_geometry (host struct). */
@@ -100,7 +108,12 @@ typedef struct fn_info {
     int32_t tiles[2];       /* spread/gather tiles per dimension */
     int32_t near_cells;     /* near-field radius in grid cells (ceil) */
     size_t workspace_bytes; /* bytes required for (n_tgt, n_src) */
-    int64_t near_pairs;     /* (target, source) pairs closer than eps_I */
+    int64_t near_pairs;     /* (target, source) pairs closer than eps_I; with surface sources,
+                               (target, volume source) pairs only */
+    int64_t n_surf;         /* surface sources (the last n_surf sources), 0 without eps_S */
+    int64_t near_pairs_surf;/* (target, surface source) pairs closer than eps_S */
+    int32_t near_cells_surf;/* eps_S in grid cells (ceil) */
+    int32_t reserved;
 } fn_info;
 
 typedef struct fn_ctx fn_ctx;
@@ -144,6 +157,15 @@ int fn_set_workspace(fn_ctx *ctx, void *dev_ptr, size_t bytes);
 int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy,
                     int64_t n_src, const double *src_xy, const double *src_w);
 
+/* As fn_set_geometry, with the last n_surf sources (0 <= n_surf <= n_src) marked as
+ * surface quadrature points (boundary-edge points of the charge density sigma of eq.
+ * (2)).  With eps_S > 0 they are summed with the kernel regularized at eps_S and
+ * near-field radius eps_S, the other n_src - n_surf with eps_I; with eps_S = 0 the
+ * call is fn_set_geometry.  The result is the sum of the two fast summations.
+ * Order of the sources, weights, charges and adjoint outputs is unchanged. */
+int fn_set_geometry_split(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_src,
+                          const double *src_xy, const double *src_w, int64_t n_surf);
+
 /* Charge densities q [n_src] (rho_j or sigma_j of eq. (2)); copied into the
  * workspace as s_j = w_j q_j in binned order. */
 int fn_set_charges(fn_ctx *ctx, const double *q);
@@ -177,6 +199,7 @@ enum {
     FN_ST_GATHER, FN_ST_NEAR,
     FN_ST_A_VALUES, FN_ST_A_SPREAD, FN_ST_A_FOLD, FN_ST_A_ROWS_FWD, FN_ST_A_COLS, FN_ST_A_ROWS_INV,
     FN_ST_A_GATHER, FN_ST_A_NEAR,
+    FN_ST_NEAR_SURF, FN_ST_A_NEAR_SURF,   /* near field of the surface sources (eps_S) */
     FN_NUM_STAGES
 };
 typedef struct fn_profile {
@@ -236,7 +259,8 @@ int fn_mesh_charges(fn_mesh *mesh, const double *M, double *q);     /* M [n_node
 int fn_mesh_charges_T(fn_mesh *mesh, const double *u, double *out); /* u [S] -> out [n_nodes][2] */
 
 /* Use the mesh's nodes as targets and its quadrature points as sources of the
- * context (fn_set_geometry with them). */
+ * context (fn_set_geometry_split with them: the boundary-edge points are the
+ * surface sources, which take eps_S when it is set). */
 int fn_bind_mesh(fn_ctx *ctx, fn_mesh *mesh);
 
 /* Demagnetizing energy of nodal magnetization M [n_nodes][2] and its gradient:
@@ -269,6 +293,11 @@ int fn_batch_workspace_size(fn_batch *batch, const int64_t *tgt_off, const int64
 int fn_batch_set_workspace(fn_batch *batch, void *dev_ptr, size_t bytes);  /* 256-byte aligned */
 int fn_set_geometry_batch(fn_batch *batch, const int64_t *tgt_off, const double *tgt_xy,
                           const int64_t *src_off, const double *src_xy, const double *src_w);
+/* As fn_set_geometry_batch; member i's last n_surf[i] sources are surface sources
+ * (fn_set_geometry_split).  n_surf [count] is a host array; NULL means none. */
+int fn_set_geometry_batch_split(fn_batch *batch, const int64_t *tgt_off, const double *tgt_xy,
+                                const int64_t *src_off, const double *src_xy, const double *src_w,
+                                const int64_t *n_surf);
 int fn_batch_set_charges(fn_batch *batch, const double *q);
 int fn_batch_eval(fn_batch *batch, double *phi, double *H);        /* either may be NULL, not both */
 int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u);

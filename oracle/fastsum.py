@@ -182,8 +182,9 @@ def kb_psi_hat(xi, m, b):
 # S0 torus map
 # ----------------------------------------------------------------------------
 
-def torus_map(y, x, eps_B):
-    allp = np.concatenate([y, x], axis=0)
+def torus_map(y, x, eps_B, extra=None):
+    """c, s and the mapped points; extra points take part in c and D only."""
+    allp = np.concatenate([y, x] + ([np.asarray(extra, np.float64)] if extra is not None else []), axis=0)
     lo, hi = allp.min(0), allp.max(0)
     c = 0.5 * (lo + hi)
     D = 2.0 * np.sqrt(((allp - c) ** 2).sum(1).max())
@@ -253,14 +254,20 @@ def _near_kernels(d, prm: Params, a):
 
 
 class FastSum:
-    """One geometry (targets y, sources x, weights w) and one parameter set."""
+    """One geometry (targets y, sources x, weights w) and one parameter set.
 
-    def __init__(self, y, x, w, prm: Params):
+    map_with: further points of the same problem that are not summed here but take
+    part in the torus map (S0 is defined over all points of a problem).  The sum is
+    linear in the sources, so a problem whose sources are split into classes (say
+    volume and surface charges) is the sum of one FastSum per class, each with the
+    other classes' points in map_with and its own parameters."""
+
+    def __init__(self, y, x, w, prm: Params, map_with=None):
         self.prm = prm
         self.y = np.asarray(y, np.float64)
         self.x = np.asarray(x, np.float64)
         self.w = np.asarray(w, np.float64)
-        self.c, self.s, self.yt, self.xt = torus_map(self.y, self.x, prm.eps_B)
+        self.c, self.s, self.yt, self.xt = torus_map(self.y, self.x, prm.eps_B, map_with)
         self.Bx = window_matrix(self.xt, prm)
         self.By = window_matrix(self.yt, prm)
         self.W, self.L1, self.L2 = multiplier(prm)

@@ -37,14 +37,16 @@ __all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", 
 def default_params(grid):
     p = _lib.Params()
     _lib.check(_lib.lib().fn_params_default(ctypes.byref(p), int(grid)))
-    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n)
+    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n,
+                eps_S=p.eps_S)
 
 
 def auto_params(n_tgt, n_src, precision=FN_FP32_MIXED):
     """Grid and regularization for a problem size (fn_params_auto)."""
     p = _lib.Params()
     _lib.check(_lib.lib().fn_params_auto(int(n_tgt), int(n_src), int(precision), ctypes.byref(p)))
-    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n)
+    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n,
+                eps_S=p.eps_S)
 
 
 def _torch():
@@ -69,14 +71,16 @@ def _dev_ptr(t, name, shape_tail=(), dtype=None):
 class Solver:
     """One fast-summation context bound to the current device and torch stream."""
 
-    def __init__(self, grid, m=None, p=None, eps_I=None, eps_B=None, precision=FN_FP32_MIXED, stream=None, n=0):
+    def __init__(self, grid, m=None, p=None, eps_I=None, eps_B=None, precision=FN_FP32_MIXED, stream=None, n=0,
+                 eps_S=0.0):
         torch = _torch()
         L = _lib.lib()
         d = default_params(grid)
         prm = _lib.Params(grid=int(grid), m=int(m if m is not None else d["m"]),
                           p=int(p if p is not None else d["p"]), precision=int(precision),
                           eps_I=float(eps_I if eps_I is not None else d["eps_I"]),
-                          eps_B=float(eps_B if eps_B is not None else d["eps_B"]), flags=0, n=int(n or 0))
+                          eps_B=float(eps_B if eps_B is not None else d["eps_B"]), flags=0, n=int(n or 0),
+                          eps_S=float(eps_S or 0.0))
         self.params = prm
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -103,7 +107,9 @@ class Solver:
         self._check(_lib.lib().fn_workspace_size(self._ctx, int(n_tgt), int(n_src), ctypes.byref(b)))
         return b.value
 
-    def set_geometry(self, tgt_xy, src_xy, src_w):
+    def set_geometry(self, tgt_xy, src_xy, src_w, n_surf=0):
+        """Targets, sources and weights (device tensors); the last n_surf sources are
+        surface quadrature points (fn_set_geometry_split)."""
         torch = _torch()
         L = _lib.lib()
         nt, ns = int(tgt_xy.shape[0]), int(src_xy.shape[0])
@@ -115,7 +121,10 @@ class Solver:
         pt = _dev_ptr(tgt_xy, "tgt_xy", (2,)) if nt else None
         ps = _dev_ptr(src_xy, "src_xy", (2,)) if ns else None
         pw = _dev_ptr(src_w, "src_w") if ns else None
-        self._check(L.fn_set_geometry(self._ctx, nt, pt, ns, ps, pw))
+        if n_surf:
+            self._check(L.fn_set_geometry_split(self._ctx, nt, pt, ns, ps, pw, int(n_surf)))
+        else:
+            self._check(L.fn_set_geometry(self._ctx, nt, pt, ns, ps, pw))
         self.n_tgt, self.n_src = nt, ns
         self._geom_refs = (tgt_xy, src_xy, src_w)  # inputs must outlive the enqueued work
         return self
@@ -185,7 +194,8 @@ class Solver:
         self._check(_lib.lib().fn_get_info(self._ctx, ctypes.byref(i)))
         return dict(centre=tuple(i.centre), scale=i.scale, n_tgt=i.n_tgt, n_src=i.n_src,
                     win_lo=tuple(i.win_lo), win_ext=tuple(i.win_ext), tiles=tuple(i.tiles),
-                    near_cells=i.near_cells, workspace_bytes=i.workspace_bytes, near_pairs=i.near_pairs)
+                    near_cells=i.near_cells, workspace_bytes=i.workspace_bytes, near_pairs=i.near_pairs,
+                    n_surf=i.n_surf, near_pairs_surf=i.near_pairs_surf, near_cells_surf=i.near_cells_surf)
 
 
 class Mesh:
@@ -252,7 +262,8 @@ def _params(d):
     base = default_params(int(d["grid"]))
     base.update({k: v for k, v in d.items() if v is not None})
     return _lib.Params(grid=int(base["grid"]), m=int(base["m"]), p=int(base["p"]), precision=int(base["precision"]),
-                       eps_I=float(base["eps_I"]), eps_B=float(base["eps_B"]), flags=0, n=int(base.get("n") or 0))
+                       eps_I=float(base["eps_I"]), eps_B=float(base["eps_B"]), flags=0, n=int(base.get("n") or 0),
+                       eps_S=float(base.get("eps_S") or 0.0))
 
 
 class Batch:
@@ -283,7 +294,8 @@ class Batch:
     def _check(self, rc):
         _lib.check_batch(rc, self._b)
 
-    def set_geometry(self, tgt_off, tgt_xy, src_off, src_xy, src_w):
+    def set_geometry(self, tgt_off, tgt_xy, src_off, src_xy, src_w, n_surf=None):
+        """n_surf: per-member counts of trailing surface sources (None: none)."""
         torch = _torch()
         L = _lib.lib()
         to = (ctypes.c_int64 * (self.count + 1))(*[int(v) for v in tgt_off])
@@ -294,8 +306,13 @@ class Batch:
             self._ws = None
             self._ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
             self._check(L.fn_batch_set_workspace(self._b, ctypes.c_void_p(self._ws.data_ptr()), need))
-        self._check(L.fn_set_geometry_batch(self._b, to, _dev_ptr(tgt_xy, "tgt_xy", (2,)), so,
-                                            _dev_ptr(src_xy, "src_xy", (2,)), _dev_ptr(src_w, "src_w")))
+        if n_surf is not None:
+            nsf = (ctypes.c_int64 * self.count)(*[int(v) for v in n_surf])
+            self._check(L.fn_set_geometry_batch_split(self._b, to, _dev_ptr(tgt_xy, "tgt_xy", (2,)), so,
+                                                      _dev_ptr(src_xy, "src_xy", (2,)), _dev_ptr(src_w, "src_w"), nsf))
+        else:
+            self._check(L.fn_set_geometry_batch(self._b, to, _dev_ptr(tgt_xy, "tgt_xy", (2,)), so,
+                                                _dev_ptr(src_xy, "src_xy", (2,)), _dev_ptr(src_w, "src_w")))
         self.n_tgt, self.n_src = int(tgt_off[-1]), int(src_off[-1])
         return self
 

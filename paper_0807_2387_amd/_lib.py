@@ -19,26 +19,27 @@ ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: 
 # exported C-ABI symbols (include/femnfft.h)
 SYMBOLS = (
     "fn_params_default", "fn_params_auto", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
-    "fn_set_geometry", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
+    "fn_set_geometry", "fn_set_geometry_split", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
     "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_get_info", "fn_last_error",
     "fn_set_profiling", "fn_get_profile",
     "fn_mesh_create", "fn_mesh_destroy", "fn_mesh_workspace_size", "fn_mesh_set_workspace", "fn_mesh_set",
     "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
     "fn_energy", "fn_mesh_last_error",
     "fn_batch_create", "fn_batch_destroy", "fn_batch_workspace_size", "fn_batch_set_workspace",
-    "fn_set_geometry_batch", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint",
+    "fn_set_geometry_batch", "fn_set_geometry_batch_split", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint",
     "fn_batch_eval_phi_adjoint", "fn_batch_member", "fn_batch_last_error",
     "fn_graph_begin", "fn_graph_end", "fn_graph_launch", "fn_graph_destroy", "fn_graph_last_error",
 )
 
 STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather", "near",
-          "a_values", "a_spread", "a_fold", "a_rows_fwd", "a_cols", "a_rows_inv", "a_gather", "a_near")
+          "a_values", "a_spread", "a_fold", "a_rows_fwd", "a_cols", "a_rows_inv", "a_gather", "a_near",
+          "near_surf", "a_near_surf")
 
 
 class Params(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("eps_I", ctypes.c_double), ("eps_B", ctypes.c_double),
-                ("flags", ctypes.c_int32), ("n", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("n", ctypes.c_int32), ("eps_S", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -46,11 +47,14 @@ class Info(ctypes.Structure):
                 ("n_tgt", ctypes.c_int64), ("n_src", ctypes.c_int64),
                 ("win_lo", ctypes.c_int32 * 2), ("win_ext", ctypes.c_int32 * 2),
                 ("tiles", ctypes.c_int32 * 2), ("near_cells", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_size_t), ("near_pairs", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_size_t), ("near_pairs", ctypes.c_int64),
+                ("n_surf", ctypes.c_int64), ("near_pairs_surf", ctypes.c_int64),
+                ("near_cells_surf", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 16), ("count", ctypes.c_int64 * 16), ("dropped", ctypes.c_int64)]
+    _fields_ = [("ms", ctypes.c_double * len(STAGES)), ("count", ctypes.c_int64 * len(STAGES)),
+                ("dropped", ctypes.c_int64)]
 
 
 class FemNfftError(RuntimeError):
@@ -78,6 +82,7 @@ def lib():
         "fn_workspace_size": ([P, I64, I64, ctypes.POINTER(SZ)], ctypes.c_int),
         "fn_set_workspace": ([P, P, SZ], ctypes.c_int),
         "fn_set_geometry": ([P, I64, P, I64, P, P], ctypes.c_int),
+        "fn_set_geometry_split": ([P, I64, P, I64, P, P, I64], ctypes.c_int),
         "fn_set_charges": ([P, P], ctypes.c_int),
         "fn_eval": ([P, P, P], ctypes.c_int),
         "fn_eval_phi": ([P, P], ctypes.c_int),
@@ -105,6 +110,8 @@ def lib():
         "fn_batch_workspace_size": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(SZ)], ctypes.c_int),
         "fn_batch_set_workspace": ([P, P, SZ], ctypes.c_int),
         "fn_set_geometry_batch": ([P, ctypes.POINTER(I64), P, ctypes.POINTER(I64), P, P], ctypes.c_int),
+        "fn_set_geometry_batch_split": ([P, ctypes.POINTER(I64), P, ctypes.POINTER(I64), P, P, ctypes.POINTER(I64)],
+                                        ctypes.c_int),
         "fn_batch_set_charges": ([P, P], ctypes.c_int),
         "fn_batch_eval": ([P, P, P], ctypes.c_int),
         "fn_batch_eval_H_adjoint": ([P, P, P], ctypes.c_int),

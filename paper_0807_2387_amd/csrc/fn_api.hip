@@ -83,6 +83,20 @@ static bool solve(std::vector<double> A, std::vector<double> b, int n, std::vect
     return true;
 }
 
+// Inner regularization polynomial at radius eps: T_I(r) = sum_k a_k (r/eps)^{2k} with
+// derivatives 0..p-1 equal to those of K at eps.
+static bool inner_poly(int p, double eps, double *a)
+{
+    std::vector<double> A(p * p), b(p), x;
+    for (int q = 0; q < p; ++q) {
+        for (int k = 0; k < p; ++k) A[q * p + k] = falling(2 * k, q);
+        b[q] = K_scaled_deriv(q, eps);
+    }
+    if (!solve(A, b, p, x)) return false;
+    for (int k = 0; k < MAXP; ++k) a[k] = k < p ? x[k] : 0.0;
+    return true;
+}
+
 static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
 {
     P.G = prm.grid;
@@ -92,6 +106,7 @@ static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
     P.precision = prm.precision;
     P.eps_I = prm.eps_I;
     P.eps_B = prm.eps_B;
+    P.eps_S = prm.eps_S;
     P.log2G = 0;
     while ((1 << P.log2G) < P.G) ++P.log2G;
     const double sigma = (double)P.G / P.n;
@@ -99,19 +114,10 @@ static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
     const double mb = P.m * P.kb_b;
     const double i0mb = bessel_i0(mb);
     P.win_norm = 1.0 / (2.0 * PI * i0mb * std::exp(-mb));
-    // inner polynomial: sum_k a_k (r/eps)^{2k}, derivatives 0..p-1 match K at eps
-    {
-        const int p = P.p;
-        std::vector<double> A(p * p), b(p), x;
-        for (int q = 0; q < p; ++q) {
-            for (int k = 0; k < p; ++k) A[q * p + k] = falling(2 * k, q);
-            b[q] = K_scaled_deriv(q, P.eps_I);
-        }
-        if (!solve(A, b, p, x)) {
-            err = "inner regularization system is singular";
-            return false;
-        }
-        for (int k = 0; k < MAXP; ++k) P.a[k] = k < p ? x[k] : 0.0;
+    // inner polynomials: at eps_I, and at eps_S for the surface sources
+    if (!inner_poly(P.p, P.eps_I, P.a) || (P.eps_S > 0.0 && !inner_poly(P.p, P.eps_S, P.aS))) {
+        err = "inner regularization system is singular";
+        return false;
     }
     // boundary polynomial in t = (r - rB)/eps_B of degree 2p-2: Taylor part fixed
     // by K at rB, remaining p-1 coefficients make derivatives 1..p-1 vanish at t = 1
@@ -213,6 +219,7 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
         return r;
     };
     L.off_W = take((size_t)(nh + 1) * (nh + 1) * rs);
+    L.off_W2 = P.eps_S > 0.0 ? take((size_t)(nh + 1) * (nh + 1) * rs) : L.off_W;
     L.off_tw = take((size_t)P.G * 2 * rs);
     L.off_tw64 = take((size_t)P.n * 16);
     const int64_t N[2] = {std::max<int64_t>(nt, 1), std::max<int64_t>(ns, 1)};
@@ -223,6 +230,8 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
         L.off_fr64[s] = take(N[s] * 16);
         L.off_cstart[s] = take((size_t)(ncell + 1) * 4);
     }
+    // the surface sources share the per-point source arrays, not the cell starts
+    L.off_cstart[2] = P.eps_S > 0.0 ? take((size_t)(ncell + 1) * 4) : L.off_cstart[1];
     L.off_w = take(N[1] * 8);
     L.off_val = take(N[1] * rs);
     L.off_val64 = take(N[1] * 8);
@@ -253,6 +262,7 @@ static void bind_buffers(fn_ctx *c)
     const Layout &L = c->lay;
     Buffers &B = c->buf;
     B.W = b + L.off_W;
+    B.W2 = b + L.off_W2;
     B.tw = b + L.off_tw;
     B.tw64 = reinterpret_cast<double2 *>(b + L.off_tw64);
     for (int s = 0; s < 2; ++s) {
@@ -262,6 +272,11 @@ static void bind_buffers(fn_ctx *c)
         B.fr64[s] = reinterpret_cast<double *>(b + L.off_fr64[s]);
         B.cstart[s] = reinterpret_cast<uint32_t *>(b + L.off_cstart[s]);
     }
+    B.cstart[2] = reinterpret_cast<uint32_t *>(b + L.off_cstart[2]);
+    B.key[2] = B.key[1];
+    B.perm[2] = B.perm[1];
+    B.fr32[2] = B.fr32[1];
+    B.fr64[2] = B.fr64[1];
     B.w = reinterpret_cast<double *>(b + L.off_w);
     B.val = b + L.off_val;
     B.val64 = reinterpret_cast<double *>(b + L.off_val64);
@@ -277,6 +292,19 @@ static void bind_buffers(fn_ctx *c)
     B.sval = reinterpret_cast<uint32_t *>(b + L.off_sval);
     B.hist = reinterpret_cast<uint32_t *>(b + L.off_hist);
     B.scratch64 = reinterpret_cast<double *>(b + L.off_spec);
+}
+
+// Source sets 1 and 2 split the source arrays at ns1 = ns - nsurf: keys and
+// permutations at offset ns1, the [2][N] fraction arrays at 2 ns1 (so that each set
+// keeps the [2][N] layout of its own size).
+static void bind_source_sets(fn_ctx *c, int64_t ns, int64_t nsurf)
+{
+    Buffers &B = c->buf;
+    const int64_t ns1 = ns - nsurf;
+    B.key[2] = B.key[1] + ns1;
+    B.perm[2] = B.perm[1] + ns1;
+    B.fr32[2] = B.fr32[1] + 2 * ns1;
+    B.fr64[2] = B.fr64[1] + 2 * ns1;
 }
 
 }  // namespace fn
@@ -405,6 +433,10 @@ static int validate_params(const fn_params *p, std::string &err)
         return FN_E_INVAL;
     }
     if (p->precision != FN_FP64 && p->precision != FN_FP32_MIXED) { err = "unknown precision"; return FN_E_INVAL; }
+    if (p->eps_S != 0.0 && (!(p->eps_S > 0.0) || !(p->eps_S * G <= 32.0) || !(p->eps_S < 0.5 - p->eps_B))) {
+        err = "eps_S must be 0, or positive with eps_S*grid <= 32 and eps_S < 1/2 - eps_B";
+        return FN_E_INVAL;
+    }
     if (p->flags != 0) { err = "flags must be 0"; return FN_E_UNSUPPORTED; }
     if (p->n != 0) {
         const int n = p->n;
@@ -507,32 +539,42 @@ static int build_device_plan(fn_ctx *c)
     FN_HIP(c, launch_kr_samples(scr, P.n, dcoef, P.p, P.eps_I, P.eps_B, dcB, (int)P.cB.size(), st));
     FN_HIP(c, launch_fft2d_c2c64(scr, P.n, B.tw64, st));
     FN_HIP(c, launch_make_W(scr, P.n, dpsi, P.precision, B.W, st));
+    if (P.eps_S > 0.0) {  // the kernel regularized at eps_S (same boundary part)
+        FN_HIP(c, hipStreamSynchronize(st));
+        FN_HIP(c, hipMemcpyAsync(dcoef, P.aS, sizeof(double) * MAXP, hipMemcpyHostToDevice, st));
+        FN_HIP(c, launch_kr_samples(scr, P.n, dcoef, P.p, P.eps_S, P.eps_B, dcB, (int)P.cB.size(), st));
+        FN_HIP(c, launch_fft2d_c2c64(scr, P.n, B.tw64, st));
+        FN_HIP(c, launch_make_W(scr, P.n, dpsi, P.precision, B.W2, st));
+    }
     FN_HIP(c, hipStreamSynchronize(st));
     c->plan_ready = true;
     return FN_OK;
 }
 
-static NearArgs near_args(const fn_ctx *c)
+// Near-field arguments of source class cls (0: eps_I, 1: surface sources at eps_S).
+static NearArgs near_args(const fn_ctx *c, int cls = 0)
 {
     NearArgs na{};
     const Plan &P = c->plan;
-    const double eg = P.eps_I * P.G;
+    const double eps = cls ? P.eps_S : P.eps_I;
+    const double *a = cls ? P.aS : P.a;
+    const double eg = eps * P.G;
     na.eps2g = eg * eg;
     na.inv_e2 = 1.0 / na.eps2g;
     na.inv_eg = 1.0 / eg;
     na.ginv = 1.0 / P.G;
     // K(eps_I) = -(1/2pi) ln(eps_I) in torus units
-    const long double k_eps = -std::log((long double)P.eps_I) / (2.0L * (long double)PI);
-    for (int k = 0; k < MAXP; ++k) na.u[k] = P.a[k];
-    na.u[0] = (double)((long double)P.a[0] - k_eps);
-    for (int k = 0; k + 1 < MAXP; ++k) na.du[k] = (k + 1) * P.a[k + 1];
+    const long double k_eps = -std::log((long double)eps) / (2.0L * (long double)PI);
+    for (int k = 0; k < MAXP; ++k) na.u[k] = a[k];
+    na.u[0] = (double)((long double)a[0] - k_eps);
+    for (int k = 0; k + 1 < MAXP; ++k) na.du[k] = (k + 1) * a[k + 1];
     for (int k = 0; k < 9; ++k) na.lc[k] = 1.0 / (2 * k + 3);
     na.ln2hi = 0.693147180559945286227;
     na.ln2lo = 2.319046813846299558e-17;
     na.offset = std::log(c->geom.s) / (2.0 * PI);
-    na.czero = -(P.a[0] + na.offset);
+    na.czero = -(a[0] + na.offset);
     na.p = P.p;
-    na.rnear = c->geom.rnear;
+    na.rnear = cls ? c->geom.rnear_s : c->geom.rnear;
     na.f32 = P.precision == FN_FP32_MIXED ? 1 : 0;
     na.scale = c->geom.s;
     return na;
@@ -574,17 +616,16 @@ static int maxdist_of(fn_ctx *c, const double *xy, int64_t n, double cx, double 
     return FN_OK;
 }
 
-int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_src, const double *src_xy,
-                    const double *src_w)
+static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int64_t n_src, const double *src_xy,
+                             const double *src_w, int64_t n_surf)
 {
-    if (!ctx) return FN_E_INVAL;
-    fn_ctx *c = ctx;
     if (!c->ws) FN_SET_ERR(c, FN_E_STATE, "fn_set_workspace must be called before fn_set_geometry");
     if (n_tgt < 0 || n_src < 0 || n_tgt + n_src < 1 || n_tgt > (int64_t)UINT32_MAX / 2 ||
         n_src > (int64_t)UINT32_MAX / 2)
         FN_SET_ERR(c, FN_E_INVAL, "need n_tgt, n_src >= 0, n_tgt + n_src >= 1, both < 2^31");
     if ((n_tgt > 0 && !tgt_xy) || (n_src > 0 && (!src_xy || !src_w)))
         FN_SET_ERR(c, FN_E_INVAL, "NULL point or weight array");
+    if (n_surf < 0 || n_surf > n_src) FN_SET_ERR(c, FN_E_INVAL, "need 0 <= n_surf <= n_src");
     if (stream_capturing(c->stream)) FN_SET_ERR(c, FN_E_STATE, "fn_set_geometry waits for the device: not allowed during graph capture");
     int rc = check_device(c);
     if (rc) return rc;
@@ -648,43 +689,67 @@ int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_
         g.ntile[d] = (g.ext[d] + TILE - 1) / TILE;
     }
     g.rnear = (int)std::ceil(P.eps_I * P.G);
+    // a second source class only when the plan has a surface radius
+    g.nsurf = P.eps_S > 0.0 ? n_surf : 0;
+    g.rnear_s = P.eps_S > 0.0 ? (int)std::ceil(P.eps_S * P.G) : 0;
     const int64_t ncell = (int64_t)g.ext[0] * g.ext[1];
     int keybits = 1;
     while (((int64_t)1 << keybits) < ncell) ++keybits;
     Buffers &B = c->buf;
-    const double *xy[2] = {tgt_xy, src_xy};
-    const int64_t N[2] = {n_tgt, n_src};
-    for (int s = 0; s < 2; ++s) {
-        if (N[s] > 0) {
-            FN_HIP(c, launch_prepare(xy[s], N[s], g.c[0], g.c[1], g.s, P.G, P.m, g.wlo[0], g.wlo[1], g.ext[0],
+    bind_source_sets(c, n_src, g.nsurf);
+    const int nsets = g.nsurf > 0 ? 3 : 2;
+    for (int s = 0; s < nsets; ++s) {
+        const int64_t n = set_size(g, s), base = set_base(g, s);
+        const double *xy = s == 0 ? tgt_xy : src_xy + 2 * base;
+        if (n > 0) {
+            FN_HIP(c, launch_prepare(xy, n, g.c[0], g.c[1], g.s, P.G, P.m, g.wlo[0], g.wlo[1], g.ext[0],
                                      g.ext[1], B.key[s], B.perm[s], c->stream));
-            FN_HIP(c, radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, N[s], keybits, c->stream));
-            FN_HIP(c, launch_finish_points(xy[s], s == 1 ? src_w : nullptr, N[s], B.perm[s], g.c[0], g.c[1], g.s,
-                                           P.G, B.fr32[s], B.fr64[s], s == 1 ? B.w : nullptr, c->stream));
+            FN_HIP(c, radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, n, keybits, c->stream));
+            FN_HIP(c, launch_finish_points(xy, s ? src_w + base : nullptr, n, B.perm[s], g.c[0], g.c[1], g.s,
+                                           P.G, B.fr32[s], B.fr64[s], s ? B.w + base : nullptr, c->stream));
         }
-        FN_HIP(c, launch_cellstart(B.key[s], N[s], ncell, B.cstart[s], c->stream));
+        FN_HIP(c, launch_cellstart(B.key[s], n, ncell, B.cstart[s], c->stream));
     }
     FN_HIP(c, hipStreamSynchronize(c->stream));
     c->geom = g;
-    // number of (target, source) pairs closer than eps_I: the near field's unit of work
-    c->geom.near_pairs = 0;
-    if (n_tgt > 0 && n_src > 0) {
-        NearArgs na = near_args(c);
-        double *cnt = B.far;  // one count per source
-        FN_HIP(c, launch_near_adj(c->geom, B, na, 2, B.red + RED_SUMV, cnt, c->stream));
-        FN_HIP(c, launch_sum(cnt, n_src, B.red + RED_SUMV, c->stream));
-        double tot = 0.0;
-        FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        FN_HIP(c, hipStreamSynchronize(c->stream));
-        c->geom.near_pairs = (int64_t)(tot + 0.5);
-        FN_HIP(c, launch_coincident_count(c->geom, B, cnt, c->stream));
-        FN_HIP(c, launch_sum(cnt, n_tgt, B.red + RED_SUMV, c->stream));
-        FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        FN_HIP(c, hipStreamSynchronize(c->stream));
-        c->geom.coincident = (int64_t)(tot + 0.5);
+    // per source class: (target, source) pairs closer than the class radius (the near
+    // field's unit of work) and pairs at exactly the same position
+    for (int s = 1; s < nsets; ++s) {
+        int64_t pairs = 0, coinc = 0;
+        if (n_tgt > 0 && set_size(c->geom, s) > 0) {
+            NearArgs na = near_args(c, s - 1);
+            double *cnt = B.far;  // one count per source of the class
+            double tot = 0.0;
+            FN_HIP(c, launch_near_adj(c->geom, B, na, s, 2, B.red + RED_SUMV, cnt, c->stream));
+            FN_HIP(c, launch_sum(cnt, set_size(c->geom, s), B.red + RED_SUMV, c->stream));
+            FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            FN_HIP(c, hipStreamSynchronize(c->stream));
+            pairs = (int64_t)(tot + 0.5);
+            FN_HIP(c, launch_coincident_count(c->geom, B, s, cnt, c->stream));
+            FN_HIP(c, launch_sum(cnt, n_tgt, B.red + RED_SUMV, c->stream));
+            FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            FN_HIP(c, hipStreamSynchronize(c->stream));
+            coinc = (int64_t)(tot + 0.5);
+        }
+        (s == 1 ? c->geom.near_pairs : c->geom.near_pairs_s) = pairs;
+        (s == 1 ? c->geom.coincident : c->geom.coincident_s) = coinc;
     }
     c->geom_ready = true;
     return FN_OK;
+}
+
+int fn_set_geometry(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_src, const double *src_xy,
+                    const double *src_w)
+{
+    if (!ctx) return FN_E_INVAL;
+    return set_geometry_impl(ctx, n_tgt, tgt_xy, n_src, src_xy, src_w, 0);
+}
+
+int fn_set_geometry_split(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_src, const double *src_xy,
+                          const double *src_w, int64_t n_surf)
+{
+    if (!ctx) return FN_E_INVAL;
+    return set_geometry_impl(ctx, n_tgt, tgt_xy, n_src, src_xy, src_w, n_surf);
 }
 
 int fn_set_charges(fn_ctx *ctx, const double *q)
@@ -696,8 +761,17 @@ int fn_set_charges(fn_ctx *ctx, const double *q)
     int rc = check_device(c);
     if (rc) return rc;
     if (c->geom.ns > 0) {
-        FN_STAGE(c, FN_ST_CHARGES, launch_set_values(q, c->buf.w, c->buf.perm[1], c->geom.ns, 1, c->plan.precision,
-                                                     c->buf.val, c->buf.val64, c->stream));
+        // per source set: its permutation indexes its own part of q (sets 1 and 2 are
+        // consecutive in q, in the sorted weights and in the sorted values)
+        const Geom &g = c->geom;
+        const size_t rs = c->plan.precision == FN_FP64 ? 8 : 4;
+        for (int s = 1; s <= 2; ++s) {
+            const int64_t n = set_size(g, s), base = set_base(g, s);
+            if (n == 0) continue;
+            FN_STAGE(c, FN_ST_CHARGES,
+                     launch_set_values(q + base, c->buf.w + base, c->buf.perm[s], n, 1, c->plan.precision,
+                                       static_cast<char *>(c->buf.val) + base * rs, c->buf.val64 + base, c->stream));
+        }
         FN_STAGE(c, FN_ST_CHARGES, launch_sum(c->buf.val64, c->geom.ns, c->buf.red + RED_SUMQ, c->stream));
     }
     c->charges_ready = true;
@@ -728,18 +802,30 @@ static int eval_impl(fn_ctx *c, double *phi, double *H)
     const int nh = P.n / 2;
     const int64_t sfstride = (int64_t)(nh + 1) * ldS;
     (void)rs;
-    FN_STAGE(c, FN_ST_SPREAD, launch_spread(prec, P, g, 1, B, B.val, 1, st));
-    FN_STAGE(c, FN_ST_FOLD, launch_fold(prec, g, P.m, B.ptile, 1, B.grid, fstride, st));
-    FN_STAGE(c, FN_ST_ROWS_FWD,
-             launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], 1, B.spec, ldS, sfstride, B.tw, st));
-    FN_STAGE(c, FN_ST_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
-                                        want_h ? COL_PHI_HY : COL_PHI, B.W, B.tw, st));
+    // with surface sources the two classes are spread as two fields and meet in the
+    // column pass, each times its own multiplier table: sum_k W_k F_k
+    const int ncls = g.nsurf > 0 ? 2 : 1;
+    const size_t tfield = (size_t)g.ntile[0] * g.ntile[1] * (TILE + 2 * P.m - 1) * (TILE + 2 * P.m - 1);
+    const char *val_s = static_cast<const char *>(B.val) + set_base(g, 2) * rs;
+    FN_STAGE(c, FN_ST_SPREAD, launch_spread(prec, P, g, 1, B, B.val, 1, B.ptile, st));
+    if (ncls == 2) FN_STAGE(c, FN_ST_SPREAD, launch_spread(prec, P, g, 2, B, val_s, 1, B.ptile + tfield, st));
+    FN_STAGE(c, FN_ST_FOLD, launch_fold(prec, g, P.m, B.ptile, ncls, B.grid, fstride, st));
+    FN_STAGE(c, FN_ST_ROWS_FWD, launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], ncls, B.spec,
+                                                ldS, sfstride, B.tw, st));
+    FN_STAGE(c, FN_ST_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1], COL_FWD,
+                                        ncls, want_h, B.W, B.W2, B.tw, st));
     FN_STAGE(c, FN_ST_ROWS_INV, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0],
-                                                g.ext[1], 1, want_phi, want_h, B.tw, st));
-    FN_STAGE(c, FN_ST_GATHER, launch_gather(prec, P, g, 0, B, want_h ? 3 : 1, fstride, B.far, g.nt, st));
-    NearArgs na = near_args(c);
-    FN_STAGE(c, FN_ST_NEAR, launch_near_fwd(g, B, na, B.red + RED_SUMQ, want_phi, want_h, phi, H, st));
-    if (want_phi && g.coincident > 0) FN_STAGE(c, FN_ST_NEAR, launch_near_coincident(g, B, na, 0, phi, st));
+                                                g.ext[1], 1, want_phi, want_h, 1, B.tw, st));
+    FN_STAGE(c, FN_ST_GATHER, launch_gather(prec, P, g, 0, B, B.grid, want_h ? 3 : 1, fstride, B.far, g.nt, st));
+    for (int k = 0; k < ncls; ++k) {
+        const int set = 1 + k;
+        if (set_size(g, set) == 0 && k > 0) continue;
+        NearArgs na = near_args(c, k);
+        const int stg = k ? FN_ST_NEAR_SURF : FN_ST_NEAR;
+        FN_STAGE(c, stg, launch_near_fwd(g, B, na, set, k > 0, B.red + RED_SUMQ, want_phi, want_h, phi, H, st));
+        if (want_phi && (k ? g.coincident_s : g.coincident) > 0)
+            FN_STAGE(c, stg, launch_near_coincident(g, B, na, 0, set, phi, st));
+    }
     return FN_OK;
 }
 
@@ -784,20 +870,37 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
     const int nh = P.n / 2;
     const int64_t sfstride = (int64_t)(nh + 1) * ldS;
     const int nf = kind == 0 ? 2 : 1;
+    // with surface sources the column pass makes one spectrum per class (W_k times the
+    // common input), each class gathers from its own grid
+    const int ncls = g.nsurf > 0 ? 2 : 1;
     FN_STAGE(c, FN_ST_A_VALUES, launch_set_values(in, nullptr, B.perm[0], g.nt, nf, prec, B.aval, B.aval64, st));
     if (kind == 1) FN_STAGE(c, FN_ST_A_VALUES, launch_sum(B.aval64, g.nt, B.red + RED_SUMV, st));
-    FN_STAGE(c, FN_ST_A_SPREAD, launch_spread(prec, P, g, 0, B, B.aval, nf, st));
+    FN_STAGE(c, FN_ST_A_SPREAD, launch_spread(prec, P, g, 0, B, B.aval, nf, B.ptile, st));
     FN_STAGE(c, FN_ST_A_FOLD, launch_fold(prec, g, P.m, B.ptile, nf, B.grid, fstride, st));
     FN_STAGE(c, FN_ST_A_ROWS_FWD,
              launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], nf, B.spec, ldS, sfstride, B.tw, st));
     FN_STAGE(c, FN_ST_A_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
-                                          kind == 0 ? COL_ADJ_H : COL_PHI, B.W, B.tw, st));
+                                          kind == 0 ? COL_ADJ_H : COL_ADJ_PHI, ncls, 0, B.W, B.W2, B.tw, st));
     FN_STAGE(c, FN_ST_A_ROWS_INV, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0],
-                                                  g.ext[1], 0, 1, 0, B.tw, st));
-    FN_STAGE(c, FN_ST_A_GATHER, launch_gather(prec, P, g, 1, B, 1, fstride, B.far, g.ns, st));
-    NearArgs na = near_args(c);
-    FN_STAGE(c, FN_ST_A_NEAR, launch_near_adj(g, B, na, kind, B.red + RED_SUMV, u, st));
-    if (kind == 1 && g.coincident > 0) FN_STAGE(c, FN_ST_A_NEAR, launch_near_coincident(g, B, na, 1, u, st));
+                                                  g.ext[1], 0, 1, 0, ncls, B.tw, st));
+    const size_t rs = prec == FN_FP64 ? 8 : 4;
+    for (int k = 0; k < ncls; ++k) {
+        const int set = 1 + k;
+        if (set_size(g, set) == 0) continue;
+        const void *grid_k = static_cast<const char *>(B.grid) + (size_t)k * fstride * rs;
+        FN_STAGE(c, FN_ST_A_GATHER, launch_gather(prec, P, g, set, B, grid_k, 1, fstride, B.far + set_base(g, set),
+                                                  set_size(g, set), st));
+    }
+    for (int k = 0; k < ncls; ++k) {
+        const int set = 1 + k;
+        if (set_size(g, set) == 0) continue;
+        NearArgs na = near_args(c, k);
+        double *u_k = u + set_base(g, set);
+        const int stg = k ? FN_ST_A_NEAR_SURF : FN_ST_A_NEAR;
+        FN_STAGE(c, stg, launch_near_adj(g, B, na, set, kind, B.red + RED_SUMV, u_k, st));
+        if (kind == 1 && (k ? g.coincident_s : g.coincident) > 0)
+            FN_STAGE(c, stg, launch_near_coincident(g, B, na, set, 0, u_k, st));
+    }
     return FN_OK;
 }
 
@@ -830,6 +933,9 @@ int fn_get_info(const fn_ctx *ctx, fn_info *info)
     }
     info->near_cells = g.rnear;
     info->near_pairs = g.near_pairs;
+    info->n_surf = g.nsurf;
+    info->near_pairs_surf = g.near_pairs_s;
+    info->near_cells_surf = g.rnear_s;
     info->workspace_bytes = make_layout(ctx->plan, g.nt, g.ns).total;
     return FN_OK;
 }

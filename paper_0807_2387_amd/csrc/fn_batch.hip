@@ -121,6 +121,13 @@ int fn_batch_set_workspace(fn_batch *batch, void *dev_ptr, size_t bytes)
 int fn_set_geometry_batch(fn_batch *batch, const int64_t *tgt_off, const double *tgt_xy, const int64_t *src_off,
                           const double *src_xy, const double *src_w)
 {
+    return fn_set_geometry_batch_split(batch, tgt_off, tgt_xy, src_off, src_xy, src_w, nullptr);
+}
+
+int fn_set_geometry_batch_split(fn_batch *batch, const int64_t *tgt_off, const double *tgt_xy,
+                                const int64_t *src_off, const double *src_xy, const double *src_w,
+                                const int64_t *n_surf)
+{
     if (!batch) return FN_E_INVAL;
     fn_batch *b = batch;
     if (!b->ws) BATCH_ERR(b, FN_E_STATE, "fn_batch_set_workspace must be called before fn_set_geometry_batch");
@@ -137,8 +144,9 @@ int fn_set_geometry_batch(fn_batch *batch, const int64_t *tgt_off, const double 
         const size_t sz = (i + 1 < B ? offs[i + 1] : total) - offs[i];
         rc = fn_set_workspace(b->ctx[i], base + offs[i], sz);
         if (rc) return member_err(b, i, rc);
-        rc = fn_set_geometry(b->ctx[i], nt, nt ? tgt_xy + 2 * tgt_off[i] : nullptr, ns,
-                             ns ? src_xy + 2 * src_off[i] : nullptr, ns ? src_w + src_off[i] : nullptr);
+        rc = fn_set_geometry_split(b->ctx[i], nt, nt ? tgt_xy + 2 * tgt_off[i] : nullptr, ns,
+                                   ns ? src_xy + 2 * src_off[i] : nullptr, ns ? src_w + src_off[i] : nullptr,
+                                   n_surf ? n_surf[i] : 0);
         if (rc) return member_err(b, i, rc);
     }
     b->toff.assign(tgt_off, tgt_off + B + 1);

@@ -520,7 +520,8 @@ int fn_bind_mesh(fn_ctx *ctx, fn_mesh *mesh)
         return FN_E_INVAL;
     }
     ctx->mesh = nullptr;
-    int rc = fn_set_geometry(ctx, mesh->N, mesh->b.nodes, mesh->S, mesh->b.x, mesh->b.w);
+    // sources: 3 volume points per triangle, then 2 surface points per boundary edge
+    int rc = fn_set_geometry_split(ctx, mesh->N, mesh->b.nodes, mesh->S, mesh->b.x, mesh->b.w, 2 * mesh->E);
     if (rc) return rc;
     ctx->mesh = mesh;
     ctx->mesh_stamp = mesh->stamp;

@@ -282,9 +282,10 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_fwd(const R *__rest
 
 template <typename R>
 __global__ void __launch_bounds__(1024) k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
-                                              cplx<R> *__restrict__ out, int64_t ofstride, int64_t ldS,
-                                              int Ey, int mode, int G, int log2G, int nh,
-                                              const R *__restrict__ W, const cplx<R> *__restrict__ tw)
+                                               cplx<R> *__restrict__ out, int64_t ofstride, int64_t ldS,
+                                               int Ey, int mode, int nclass, int hy, int G, int log2G, int nh,
+                                               const R *__restrict__ W0, const R *__restrict__ W1,
+                                               const cplx<R> *__restrict__ tw)
 {
     using C = cplx<R>;
     extern __shared__ char smem_c[];
@@ -295,8 +296,13 @@ __global__ void __launch_bounds__(1024) k_cols(const cplx<R> *__restrict__ spec,
     const bool valid = qx <= nh;
     C *buf = sh + (int64_t)li * lp(G);
     const R twopi = (R)6.283185307179586476925286766559;
+    // multiplier of class k at (qx, |l_y|); zero outside the band
+    auto wmul = [&](int k, int aly) -> R {
+        const R *W = k == 0 ? W0 : W1;
+        return (valid && aly <= nh) ? W[(int64_t)qx * (nh + 1) + aly] : (R)0;
+    };
     C acc[FFT_EPT];
-    const int nin = (mode == COL_ADJ_H) ? 2 : 1;
+    const int nin = mode == COL_FWD ? nclass : (mode == COL_ADJ_H ? 2 : 1);
     for (int f = 0; f < nin; ++f) {
         const C *col = spec + f * sfstride + (int64_t)qx * ldS;
         for (int e = lt; e < G; e += NT) buf[lp(e)] = (valid && e < Ey) ? col[e] : mk<C>((R)0, (R)0);
@@ -306,31 +312,37 @@ __global__ void __launch_bounds__(1024) k_cols(const cplx<R> *__restrict__ spec,
         for (int i = 0; i < FFT_EPT; ++i) {
             const int k = lt + i * NT;
             const int ly = k <= G / 2 ? k : k - G;
-            const int aly = ly < 0 ? -ly : ly;
-            C x = buf[lp(k)];
-            R w = (valid && aly <= nh) ? W[(int64_t)qx * (nh + 1) + aly] : (R)0;
-            C v = mk<C>(w * x.x, w * x.y);
-            if (mode == COL_ADJ_H) {
-                // (2 pi i l_d) v, l_d = l_x for field 0, l_y for field 1
-                R l = (R)(f == 0 ? qx : ly) * twopi;
-                C t = mk<C>(-l * v.y, l * v.x);
-                acc[i] = (f == 0) ? t : cadd(acc[i], t);
+            const C x = buf[lp(k)];
+            C t;
+            if (mode == COL_FWD) {
+                const R w = wmul(f, ly < 0 ? -ly : ly);
+                t = mk<C>(w * x.x, w * x.y);
+            } else if (mode == COL_ADJ_H) {
+                // (2 pi i l_d) x, l_d = l_x for component 0, l_y for component 1
+                const R l = (R)(f == 0 ? qx : ly) * twopi;
+                t = mk<C>(-l * x.y, l * x.x);
             } else {
-                acc[i] = v;
+                t = x;
             }
+            acc[i] = (f == 0) ? t : cadd(acc[i], t);
         }
         __syncthreads();
     }
-    const int nout = (mode == COL_PHI_HY) ? 2 : 1;
+    const int nout = mode == COL_FWD ? (hy ? 2 : 1) : nclass;
     for (int o = 0; o < nout; ++o) {
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
             const int k = lt + i * NT;
+            const int ly = k <= G / 2 ? k : k - G;
             C v = acc[i];
-            if (o == 1) {  // (-2 pi i l_y) v
-                const int ly = k <= G / 2 ? k : k - G;
-                R l = (R)ly * twopi;
-                v = mk<C>(l * v.y, -l * v.x);
+            if (mode == COL_FWD) {
+                if (o == 1) {  // (-2 pi i l_y) v
+                    const R l = (R)ly * twopi;
+                    v = mk<C>(l * v.y, -l * v.x);
+                }
+            } else {
+                const R w = wmul(o, ly < 0 ? -ly : ly);
+                v = mk<C>(w * v.x, w * v.y);
             }
             buf[lp(k)] = conjc(v);
         }
@@ -493,7 +505,8 @@ hipError_t launch_rows_fwd(int precision, int G, int nh, const void *grid, int64
 
 template <typename R>
 static hipError_t cols_t(int G, int nh, const void *spec, int64_t sfstride, void *out, int64_t ofstride,
-                         int64_t ldS, int Ey, int mode, const void *W, const void *tw, hipStream_t st)
+                         int64_t ldS, int Ey, int mode, int nclass, int hy, const void *W0, const void *W1,
+                         const void *tw, hipStream_t st)
 {
     const int NT = fft_nt(G), per = fft_per(G);
     const int nb = (nh + 1 + per - 1) / per;
@@ -501,22 +514,26 @@ static hipError_t cols_t(int G, int nh, const void *spec, int64_t sfstride, void
                                        (int)fft_lds_bytes<R>(G));
     if (e != hipSuccess) return e;
     k_cols<R><<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, sfstride, (cplx<R> *)out, ofstride,
-                                                   ldS, Ey, mode, G, ilog2(G), nh, (const R *)W,
-                                                   (const cplx<R> *)tw);
+                                                          ldS, Ey, mode, nclass, hy, G, ilog2(G), nh,
+                                                          (const R *)W0, (const R *)W1, (const cplx<R> *)tw);
     return hipGetLastError();
 }
 
 hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t sfstride, void *out,
-                       int64_t ofstride, int64_t ldS, int Ey, int mode, const void *W, const void *tw,
-                       hipStream_t st)
+                       int64_t ofstride, int64_t ldS, int Ey, int mode, int nclass, int hy, const void *W0,
+                       const void *W1, const void *tw, hipStream_t st)
 {
-    if (precision == FN_FP64) return cols_t<double>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, W, tw, st);
-    return cols_t<float>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, W, tw, st);
+    // every table a class needs must be there: the kernel reads W1 only when nclass == 2
+    if (nclass < 1 || nclass > 2 || !W0 || (nclass == 2 && !W1)) return hipErrorInvalidValue;
+    if (mode != COL_FWD && mode != COL_ADJ_PHI && mode != COL_ADJ_H) return hipErrorInvalidValue;
+    if (precision == FN_FP64)
+        return cols_t<double>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, nclass, hy, W0, W1, tw, st);
+    return cols_t<float>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, nclass, hy, W0, W1, tw, st);
 }
 
 template <typename R>
 static hipError_t rows_inv_t(int G, int nh, const void *T, int64_t tfstride, int64_t ldS, void *grid,
-                             int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h,
+                             int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h, int nout,
                              const void *tw, hipStream_t st)
 {
     OutSpec os{};
@@ -528,8 +545,10 @@ static hipError_t rows_inv_t(int G, int nh, const void *T, int64_t tfstride, int
         ++os.n;
     };
     if (!fwd) {
-        add(0, 0, 0, 0);
-        add(0, 0, 0, 1);
+        for (int k = 0; k < nout; ++k) {
+            add(k, 0, k, 0);
+            add(k, 0, k, 1);
+        }
     } else {
         // a complex transform pairs the same field on two rows: fields of very
         // different magnitude (phi and H) must not share one transform, or the
@@ -558,11 +577,14 @@ static hipError_t rows_inv_t(int G, int nh, const void *T, int64_t tfstride, int
 
 hipError_t launch_rows_inv(int precision, int G, int nh, const void *T, int64_t tfstride, int64_t ldS,
                            void *grid, int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h,
-                           const void *tw, hipStream_t st)
+                           int nout, const void *tw, hipStream_t st)
 {
+    if (nout < 1 || nout > 2) return hipErrorInvalidValue;
     if (precision == FN_FP64)
-        return rows_inv_t<double>(G, nh, T, tfstride, ldS, grid, fstride, Ex, Ey, fwd, want_phi, want_h, tw, st);
-    return rows_inv_t<float>(G, nh, T, tfstride, ldS, grid, fstride, Ex, Ey, fwd, want_phi, want_h, tw, st);
+        return rows_inv_t<double>(G, nh, T, tfstride, ldS, grid, fstride, Ex, Ey, fwd, want_phi, want_h, nout,
+                                  tw, st);
+    return rows_inv_t<float>(G, nh, T, tfstride, ldS, grid, fstride, Ex, Ey, fwd, want_phi, want_h, nout, tw,
+                             st);
 }
 
 

@@ -50,10 +50,12 @@ struct Plan {
     int G = 0, n = 0, m = 0, p = 0, log2G = 0;
     int precision = FN_FP32_MIXED;
     double eps_I = 0, eps_B = 0;
+    double eps_S = 0;                // near radius of the surface sources (0: no second class)
     WinPoly wpoly{};                 // per-tap polynomials of the window (FP32 path)
     double kb_b = 0;                 // Kaiser-Bessel shape b = pi (2 - 1/sigma)
     double win_norm = 0;             // 1 / (2 pi I0(m b) e^{-m b})
     double a[MAXP] = {0};            // inner polynomial T_I(r) = sum_k a_k (r/eps_I)^{2k}
+    double aS[MAXP] = {0};           // the same at eps_S (surface sources)
     std::vector<double> cB;          // boundary polynomial in t = (r - r_B)/eps_B
     std::vector<double> psihat;      // window transform at l/G, l = 0..n/2
 };
@@ -69,23 +71,36 @@ struct Geom {
     int32_t rnear = 0;               // near radius in cells
     int64_t near_pairs = 0;          // pairs closer than eps_I
     int64_t coincident = 0;          // (target, source) pairs at exactly the same position
+    // surface sources: the last nsurf sources, near radius eps_S (nsurf > 0 only when
+    // the plan has eps_S > 0); the counts above then cover the volume sources only
+    int64_t nsurf = 0;
+    int32_t rnear_s = 0;
+    int64_t near_pairs_s = 0;
+    int64_t coincident_s = 0;
 };
+
+// Point sets: 0 = targets, 1 = (volume) sources, 2 = surface sources.  Sets 1 and 2
+// share the source arrays: set 2 starts at source index set_base(g, 2).
+inline int64_t set_size(const Geom &g, int s) { return s == 0 ? g.nt : (s == 1 ? g.ns - g.nsurf : g.nsurf); }
+inline int64_t set_base(const Geom &g, int s) { return s == 2 ? g.ns - g.nsurf : 0; }
 
 // Device arrays carved out of the caller's workspace.
 struct Buffers {
     // plan
     void *W = nullptr;               // multiplier table [(n/2+1) x (n/2+1)], R
+    void *W2 = nullptr;              // the same for the kernel regularized at eps_S
     void *tw = nullptr;              // FFT twiddles e^{-2 pi i k/G}, k < G, cplx<R>
     double2 *tw64 = nullptr;         // FP64 twiddles for the plan FFT (length n)
-    // geometry, per point set (0 = targets, 1 = sources), sorted by cell
-    uint32_t *key[2] = {nullptr, nullptr};
-    uint32_t *perm[2] = {nullptr, nullptr};
-    float *fr32[2] = {nullptr, nullptr};   // [2][N] in-cell fractions, FP32
-    double *fr64[2] = {nullptr, nullptr};  // [2][N] in-cell fractions, FP64
-    uint32_t *cstart[2] = {nullptr, nullptr}; // [ncell + 1]
-    double *w = nullptr;             // source weights, sorted
+    // geometry, per point set (see set_size), each sorted by cell; perm[s] holds indices
+    // relative to the set's first point
+    uint32_t *key[3] = {nullptr, nullptr, nullptr};
+    uint32_t *perm[3] = {nullptr, nullptr, nullptr};
+    float *fr32[3] = {nullptr, nullptr, nullptr};   // [2][N] in-cell fractions, FP32
+    double *fr64[3] = {nullptr, nullptr, nullptr};  // [2][N] in-cell fractions, FP64
+    uint32_t *cstart[3] = {nullptr, nullptr, nullptr}; // [ncell + 1]
+    double *w = nullptr;             // source weights, sorted (set 1, then set 2)
     // per-evaluation data
-    void *val = nullptr;             // charges s_j = w_j q_j, R, sorted sources
+    void *val = nullptr;             // charges s_j = w_j q_j, R, sorted sources (set 1, then set 2)
     double *val64 = nullptr;         // the same in FP64 (near field)
     void *aval = nullptr;            // adjoint inputs (v or V), R, [2][nt] sorted targets
     double *aval64 = nullptr;        // the same in FP64
@@ -102,8 +117,8 @@ struct Buffers {
 
 struct Layout {
     size_t total = 0;
-    size_t off_W, off_tw, off_tw64;
-    size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_cstart[2];
+    size_t off_W, off_W2, off_tw, off_tw64;
+    size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_cstart[3];
     size_t off_w, off_val, off_val64, off_aval, off_aval64, off_ptile, off_grid, off_spec, off_spec2, off_far, off_red;
     size_t off_skey, off_sval, off_hist;
     int64_t emax = 0;                // bound on the window extent
@@ -180,22 +195,30 @@ hipError_t launch_sum(const double *x, int64_t n, double *red, hipStream_t st); 
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 // spread / fold / gather
 hipError_t launch_spread(int precision, const Plan &P, const Geom &g, int set, const Buffers &b,
-                         const void *val, int nfield, hipStream_t st);
+                         const void *val, int nfield, double *ptile, hipStream_t st);
 hipError_t launch_fold(int precision, const Geom &g, int m, const double *ptile, int nfield, void *grid,
                        int64_t fstride, hipStream_t st);
 hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, const Buffers &b,
-                         int nfield, int64_t fstride, double *far, int64_t farstride, hipStream_t st);
+                         const void *grid, int nfield, int64_t fstride, double *far, int64_t farstride,
+                         hipStream_t st);
 // FFT passes
-enum ColMode { COL_PHI = 0, COL_PHI_HY = 1, COL_ADJ_H = 2 };
+// Column pass over nclass multiplier tables (W0, and W1 when nclass = 2):
+//   COL_FWD     inputs x_k, one per class: acc = sum_k W_k x_k; outputs acc and, with hy,
+//               -2 pi i l_y acc
+//   COL_ADJ_PHI input x: outputs W_k x, k < nclass
+//   COL_ADJ_H   inputs x_0, x_1 (the two components): acc = sum_d 2 pi i l_d x_d;
+//               outputs W_k acc, k < nclass
+enum ColMode { COL_FWD = 0, COL_ADJ_PHI = 1, COL_ADJ_H = 2 };
 hipError_t launch_rows_fwd(int precision, int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey,
                            int nfield, void *spec, int64_t ldS, int64_t sfstride, const void *tw,
                            hipStream_t st);
 hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t sfstride, void *out,
-                       int64_t ofstride, int64_t ldS, int Ey, int mode, const void *W, const void *tw,
-                       hipStream_t st);
+                       int64_t ofstride, int64_t ldS, int Ey, int mode, int nclass, int hy, const void *W0,
+                       const void *W1, const void *tw, hipStream_t st);
+// fwd: phi / H grids from T_phi (and T_Hy); adjoint: nout real grids from nout spectra
 hipError_t launch_rows_inv(int precision, int G, int nh, const void *T, int64_t tfstride, int64_t ldS,
                            void *grid, int64_t fstride, int Ex, int Ey, int fwd, int want_phi, int want_h,
-                           const void *tw, hipStream_t st);
+                           int nout, const void *tw, hipStream_t st);
 // near field + final
 struct NearArgs {
     double eps2g;        // eps_I^2 in grid units^2
@@ -214,13 +237,16 @@ struct NearArgs {
     double scale;        // s
     double offset;       // (ln s / 2 pi)
 };
-hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, const double *sum_s,
-                           int want_phi, int want_h, double *phi, double *H, hipStream_t st);
-hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int kind,
+// forward: targets against source set in_set; accum = 0 writes far + near (+ the
+// scale term of all charges), accum = 1 adds the near part only
+hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, int in_set, int accum,
+                           const double *sum_s, int want_phi, int want_h, double *phi, double *H, hipStream_t st);
+// adjoint: source set out_set against the targets; u is that set's part of the output
+hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int kind,
                            const double *sum_v, double *u, hipStream_t st);
-hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, double *out,
-                                  hipStream_t st);
-hipError_t launch_coincident_count(const Geom &g, const Buffers &b, double *cnt, hipStream_t st);
+hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int in_set,
+                                  double *out, hipStream_t st);
+hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, double *cnt, hipStream_t st);
 
 // host helpers
 double bessel_i0(double x);

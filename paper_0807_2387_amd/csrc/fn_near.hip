@@ -70,6 +70,7 @@ struct NearSets {
     const uint32_t *cs_in;
     const double *pay;            // fwd: s [n_in]; adj H: V [2][n_in]; adj phi: v [n_in]
     int Ex, Ey, nbx;
+    int accum;                    // forward only: add the near part to phi / H instead of writing far + near
 };
 
 // U(x) = sum_{k<P} c_k x^k and U'(x) in one Horner sweep (the derivative
@@ -253,6 +254,7 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     __syncthreads();
     const uint32_t nhome = hpre[NSEG], nin = ipre[nirow];
     if (nhome == 0) return;  // uniform
+    if (FWD && S.accum && nin == 0) return;  // nothing to add to this block's targets (uniform)
 
     const double e2 = na.eps2g;
     // leading polynomial coefficient, pinned to a vector register (see poly2)
@@ -379,7 +381,13 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
         if (valid) {
             const int64_t o = S.perm_out[gi];
             const double G2 = F32 ? 2.0 * na.inv_eg / na.ginv : 2.0 / (na.ginv * na.eps2g);
-            if (FWD) {
+            if (FWD && S.accum) {
+                if (WANT_PHI) out0[o] += a0;
+                if (WANT_H) {
+                    out1[2 * o] = fma(na.scale * G2, a1, out1[2 * o]);
+                    out1[2 * o + 1] = fma(na.scale * G2, a2, out1[2 * o + 1]);
+                }
+            } else if (FWD) {
                 if (WANT_PHI) out0[o] = S.far[gi] + a0 + na.offset * sum_in[0];
                 if (WANT_H) {
                     out1[2 * o] = na.scale * fma(G2, a1, S.far[S.n_out + gi]);
@@ -468,25 +476,28 @@ hipError_t launch_mode(int nblk, hipStream_t st, const NearSets &S, const NearAr
     }
 }
 
-NearSets make_sets(const Geom &g, const Buffers &b, int out_set)
+// Home set out_set against input set in_set (targets against a source set, or a
+// source set against the targets).  The sorted arrays of a source set start at its
+// base within the source arrays; far-field results follow the home set's order.
+NearSets make_sets(const Geom &g, const Buffers &b, int out_set, int in_set)
 {
     NearSets S{};
-    const int in_set = 1 - out_set;
-    S.n_out = out_set ? g.ns : g.nt;
+    S.n_out = set_size(g, out_set);
     S.key_out = b.key[out_set];
     S.f_out = b.fr64[out_set];
     S.perm_out = b.perm[out_set];
     S.cs_out = b.cstart[out_set];
-    S.far = b.far;
-    S.w_out = out_set ? b.w : nullptr;
-    S.n_in = in_set ? g.ns : g.nt;
+    S.far = out_set ? b.far + set_base(g, out_set) : b.far;
+    S.w_out = out_set ? b.w + set_base(g, out_set) : nullptr;
+    S.n_in = set_size(g, in_set);
     S.key_in = b.key[in_set];
     S.f_in = b.fr64[in_set];
     S.cs_in = b.cstart[in_set];
-    S.pay = out_set ? b.aval64 : b.val64;
+    S.pay = out_set ? b.aval64 : b.val64 + set_base(g, in_set);
     S.Ex = g.ext[0];
     S.Ey = g.ext[1];
     S.nbx = (g.ext[0] + NB - 1) / NB;
+    S.accum = 0;
     return S;
 }
 
@@ -503,17 +514,16 @@ hipError_t coincident_p(const NearSets &S, const NearArgs &na, int adjoint, doub
 
 }  // namespace
 
-// phi (forward, out_set 0) or the phi adjoint (out_set 1): replace phi_X by czero
-// for coincident pairs.
-hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, double *out,
-                                  hipStream_t st)
+// phi (forward, out_set 0 against source set in_set) or the phi adjoint (source set
+// out_set against the targets): replace phi_X by czero for coincident pairs.
+hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int in_set,
+                                  double *out, hipStream_t st)
 {
-    if ((out_set ? g.ns : g.nt) == 0 || (out_set ? g.nt : g.ns) == 0) return hipSuccess;
-    NearSets S = make_sets(g, b, out_set);
-    if (out_set) S.pay = b.aval64;  // v [n_tgt]
+    if (set_size(g, out_set) == 0 || set_size(g, in_set) == 0) return hipSuccess;
+    NearSets S = make_sets(g, b, out_set, in_set);
     switch (na.p) {
 #define FN_CO_CASE(PP) \
-    case PP: return coincident_p<PP>(S, na, out_set, out, st);
+    case PP: return coincident_p<PP>(S, na, out_set != 0, out, st);
     FN_CO_CASE(1) FN_CO_CASE(2) FN_CO_CASE(3) FN_CO_CASE(4) FN_CO_CASE(5) FN_CO_CASE(6)
     FN_CO_CASE(7) FN_CO_CASE(8) FN_CO_CASE(9) FN_CO_CASE(10) FN_CO_CASE(11) FN_CO_CASE(12)
 #undef FN_CO_CASE
@@ -521,32 +531,35 @@ hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArg
     }
 }
 
-// cnt [n_tgt]: sources at exactly each (sorted) target's position
-hipError_t launch_coincident_count(const Geom &g, const Buffers &b, double *cnt, hipStream_t st)
+// cnt [n_tgt]: points of source set in_set at exactly each (sorted) target's position
+hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, double *cnt, hipStream_t st)
 {
-    if (g.nt == 0 || g.ns == 0) return hipSuccess;
-    const NearSets S = make_sets(g, b, 0);
+    if (g.nt == 0) return hipSuccess;
+    if (set_size(g, in_set) == 0) return launch_fill(cnt, g.nt, 0.0, st);
+    const NearSets S = make_sets(g, b, 0, in_set);
     k_coincident_count<<<(int)((g.nt + 255) / 256), 256, 0, st>>>(S, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, const double *sum_s,
-                           int want_phi, int want_h, double *phi, double *H, hipStream_t st)
+hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, int in_set, int accum,
+                           const double *sum_s, int want_phi, int want_h, double *phi, double *H, hipStream_t st)
 {
     if (g.nt == 0) return hipSuccess;
-    const NearSets S = make_sets(g, b, 0);
+    NearSets S = make_sets(g, b, 0, in_set);
+    S.accum = accum;
     const int nblk = S.nbx * ((g.ext[1] + NB - 1) / NB);
     if (want_phi && want_h) return launch_mode<MODE_FWD_BOTH, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
     if (want_phi) return launch_mode<MODE_FWD_PHI, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
     return launch_mode<MODE_FWD_H, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
 }
 
-// kind 0: H^T (V), kind 1: phi^T (v), kind 2: count pairs closer than eps_I per source.
-hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int kind, const double *sum_v,
-                           double *u, hipStream_t st)
+// kind 0: H^T (V), kind 1: phi^T (v), kind 2: count pairs closer than the class radius
+// per source.  u is the part of the output that belongs to source set out_set.
+hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int kind,
+                           const double *sum_v, double *u, hipStream_t st)
 {
-    if (g.ns == 0) return hipSuccess;
-    const NearSets S = make_sets(g, b, 1);
+    if (set_size(g, out_set) == 0) return hipSuccess;
+    const NearSets S = make_sets(g, b, out_set, 0);
     const int nblk = S.nbx * ((g.ext[1] + NB - 1) / NB);
     if (kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
     if (kind == 1) return launch_mode<MODE_ADJ_PHI, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);

@@ -346,12 +346,12 @@ __global__ void __launch_bounds__(SUMB) k_sum_partial(const double *__restrict__
 
 template <typename R, int M2>
 hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
-                    hipStream_t st)
+                    double *ptile, hipStream_t st)
 {
     constexpr int PT = TILE + M2 - 1;
     const int ntiles = g.ntile[0] * g.ntile[1];
     const size_t lds = (size_t)SPREAD_WAVES * nfield * PT * PT * sizeof(double);
-    const int64_t N = set ? g.ns : g.nt;
+    const int64_t N = set_size(g, set);
 #if FN_SPREAD_CELLS
     if (std::is_same<R, float>::value) {
         auto kc = k_spread_cells<M2>;
@@ -359,7 +359,7 @@ hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, con
         hipError_t e = hipFuncSetAttribute((const void *)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
         if (e != hipSuccess) return e;
         kc<<<ntiles * nfield, SPREAD_NT, lds1, st>>>(b.fr32[set], (const float *)val, N, b.cstart[set], g.ext[0],
-                                                     g.ext[1], g.ntile[0], g.ntile[1], b.ptile, P.wpoly);
+                                                     g.ext[1], g.ntile[0], g.ntile[1], ptile, P.wpoly);
         return hipGetLastError();
     }
 #endif
@@ -368,63 +368,65 @@ hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, con
     if (e != hipSuccess) return e;
     kern<<<ntiles, SPREAD_NT, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], (const R *)val, N,
                                          b.cstart[set], g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], P.kb_b,
-                                         P.win_norm, nfield, b.ptile, P.wpoly);
+                                         P.win_norm, nfield, ptile, P.wpoly);
     return hipGetLastError();
 }
 
 template <typename R, int M2>
-hipError_t gather_t(const Plan &P, const Geom &g, int set, const Buffers &b, int nfield, int64_t fstride,
-                    double *far, int64_t farstride, hipStream_t st)
+hipError_t gather_t(const Plan &P, const Geom &g, int set, const Buffers &b, const void *grid, int nfield,
+                    int64_t fstride, double *far, int64_t farstride, hipStream_t st)
 {
     constexpr int PT = TILE + M2 - 1;
     const int ntiles = g.ntile[0] * g.ntile[1];
     const size_t lds = (size_t)nfield * PT * PT * sizeof(R);
-    const int64_t N = set ? g.ns : g.nt;
+    const int64_t N = set_size(g, set);
     k_gather<R, M2><<<ntiles, 256, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], N, b.cstart[set], g.ext[0],
-                                             g.ext[1], g.ntile[0], P.kb_b, P.win_norm, (const R *)b.grid,
+                                             g.ext[1], g.ntile[0], P.kb_b, P.win_norm, (const R *)grid,
                                              fstride, nfield, far, farstride, P.wpoly);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t spread_m(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
-                    hipStream_t st)
+                    double *ptile, hipStream_t st)
 {
     switch (P.m) {
-    case 2: return spread_t<R, 4>(P, g, set, b, val, nfield, st);
-    case 3: return spread_t<R, 6>(P, g, set, b, val, nfield, st);
-    case 4: return spread_t<R, 8>(P, g, set, b, val, nfield, st);
-    case 5: return spread_t<R, 10>(P, g, set, b, val, nfield, st);
-    case 6: return spread_t<R, 12>(P, g, set, b, val, nfield, st);
-    case 7: return spread_t<R, 14>(P, g, set, b, val, nfield, st);
-    case 8: return spread_t<R, 16>(P, g, set, b, val, nfield, st);
+    case 2: return spread_t<R, 4>(P, g, set, b, val, nfield, ptile, st);
+    case 3: return spread_t<R, 6>(P, g, set, b, val, nfield, ptile, st);
+    case 4: return spread_t<R, 8>(P, g, set, b, val, nfield, ptile, st);
+    case 5: return spread_t<R, 10>(P, g, set, b, val, nfield, ptile, st);
+    case 6: return spread_t<R, 12>(P, g, set, b, val, nfield, ptile, st);
+    case 7: return spread_t<R, 14>(P, g, set, b, val, nfield, ptile, st);
+    case 8: return spread_t<R, 16>(P, g, set, b, val, nfield, ptile, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename R>
-hipError_t gather_m(const Plan &P, const Geom &g, int set, const Buffers &b, int nfield, int64_t fstride,
+hipError_t gather_m(const Plan &P, const Geom &g, int set, const Buffers &b, const void *grid, int nfield, int64_t fstride,
                     double *far, int64_t farstride, hipStream_t st)
 {
     switch (P.m) {
-    case 2: return gather_t<R, 4>(P, g, set, b, nfield, fstride, far, farstride, st);
-    case 3: return gather_t<R, 6>(P, g, set, b, nfield, fstride, far, farstride, st);
-    case 4: return gather_t<R, 8>(P, g, set, b, nfield, fstride, far, farstride, st);
-    case 5: return gather_t<R, 10>(P, g, set, b, nfield, fstride, far, farstride, st);
-    case 6: return gather_t<R, 12>(P, g, set, b, nfield, fstride, far, farstride, st);
-    case 7: return gather_t<R, 14>(P, g, set, b, nfield, fstride, far, farstride, st);
-    case 8: return gather_t<R, 16>(P, g, set, b, nfield, fstride, far, farstride, st);
+    case 2: return gather_t<R, 4>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 3: return gather_t<R, 6>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 4: return gather_t<R, 8>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 5: return gather_t<R, 10>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 6: return gather_t<R, 12>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 7: return gather_t<R, 14>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 8: return gather_t<R, 16>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
+// Spread nfield value arrays of point set `set` into the padded tiles at ptile
+// (field f of the set at ptile + f * ntiles * PT^2).
 hipError_t launch_spread(int precision, const Plan &P, const Geom &g, int set, const Buffers &b, const void *val,
-                         int nfield, hipStream_t st)
+                         int nfield, double *ptile, hipStream_t st)
 {
-    return precision == FN_FP64 ? spread_m<double>(P, g, set, b, val, nfield, st)
-                                : spread_m<float>(P, g, set, b, val, nfield, st);
+    return precision == FN_FP64 ? spread_m<double>(P, g, set, b, val, nfield, ptile, st)
+                                : spread_m<float>(P, g, set, b, val, nfield, ptile, st);
 }
 
 hipError_t launch_fold(int precision, const Geom &g, int m, const double *ptile, int nfield, void *grid,
@@ -442,11 +444,12 @@ hipError_t launch_fold(int precision, const Geom &g, int m, const double *ptile,
     return hipGetLastError();
 }
 
-hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, const Buffers &b, int nfield,
-                         int64_t fstride, double *far, int64_t farstride, hipStream_t st)
+// Interpolate nfield grids (grid, grid + fstride, ...) at the points of `set`.
+hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, const Buffers &b, const void *grid,
+                         int nfield, int64_t fstride, double *far, int64_t farstride, hipStream_t st)
 {
-    return precision == FN_FP64 ? gather_m<double>(P, g, set, b, nfield, fstride, far, farstride, st)
-                                : gather_m<float>(P, g, set, b, nfield, fstride, far, farstride, st);
+    return precision == FN_FP64 ? gather_m<double>(P, g, set, b, grid, nfield, fstride, far, farstride, st)
+                                : gather_m<float>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
 }
 
 hipError_t launch_set_values(const double *q, const double *w, const uint32_t *perm, int64_t n, int ncomp,

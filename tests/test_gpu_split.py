@@ -1,0 +1,272 @@
+"""Surface sources with their own near radius (fn_set_geometry_split, eps_S) through the C-ABI.
+
+The sum is linear in the sources, so the expected values are two step-by-step oracle fast
+sums (O2), one per class -- volume sources at eps_I, surface sources at eps_S -- with the
+torus map taken over all points (map_with), added for the targets and concatenated for the
+adjoint outputs.  Tolerances as for one class: FP64 path 1e-10, FP32-mixed path 1e-6
+(relative L2 per output kind).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, fem
+from oracle import fastsum as fs
+from tests.conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def fn():
+    import paper_0807_2387_amd as _fn
+    return _fn
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def oracle_split(y, x, w, ns1, prm_v, prm_s):
+    """Per-class oracle fast sums (None for an empty class)."""
+    Fv = fs.FastSum(y, x[:ns1], w[:ns1], prm_v, map_with=x[ns1:] if ns1 < len(x) else None) if ns1 > 0 else None
+    Fs = fs.FastSum(y, x[ns1:], w[ns1:], prm_s, map_with=x[:ns1] if ns1 > 0 else None) if ns1 < len(x) else None
+    return Fv, Fs
+
+
+def oracle_outputs(Fv, Fs, ns1, q, V, v):
+    phi, H, u, up = 0.0, 0.0, [], []
+    for F, qq in ((Fv, q[:ns1]), (Fs, q[ns1:])):
+        if F is None:
+            continue
+        p_, H_ = F.forward(qq)
+        phi, H = phi + p_, H + H_
+        u.append(F.adjoint_H(V))
+        up.append(F.adjoint_phi(v))
+    return phi, H, np.concatenate(u), np.concatenate(up)
+
+
+def surface_ring(n, R, seed):
+    """n charges on a circle of radius R (midpoints of a regular n-gon's edges)."""
+    t = 2 * np.pi * (np.arange(n) + 0.5) / n
+    xs = R * np.stack([np.cos(t), np.sin(t)], axis=1)
+    ws = np.full(n, 2 * np.pi * R / max(n, 1))
+    qs = np.cos(t) + 0.1 * np.random.default_rng(seed).standard_normal(n)
+    return xs, ws, qs
+
+
+def cloud_with_ring(nt, nv, nsurf, seed):
+    y, x, w, q = synth.random_cloud(nt, nv, seed)
+    xs, ws, qs = surface_ring(nsurf, 1.0, seed + 1)
+    return y, np.concatenate([x, xs]), np.concatenate([w, ws]), np.concatenate([q, qs]), nv
+
+
+def rounded_square(N, seed):
+    d = synth.rounded_square_cloud(N=N, seed=seed)
+    ns1 = int(np.sum(d["w"] == d["h"] ** 2))
+    return d["y"], d["x"], d["w"], d["q"], ns1
+
+
+# name, workload, G, band, m, p, c_volume, c_surface
+CASES = [
+    ("square_small", lambda: rounded_square(4000, 41), 128, 96, 6, 6, 4.0, 8.0),
+    ("square_multi_tile", lambda: rounded_square(20000, 42), 256, 192, 6, 8, 5.0, 10.0),
+    ("cloud_ring", lambda: cloud_with_ring(3000, 4000, 500, 43), 256, 0, 6, 8, 4.0, 7.0),
+    ("ring_only", lambda: cloud_with_ring(1500, 0, 700, 44), 128, 0, 4, 4, 3.0, 5.0),
+    ("one_surface", lambda: cloud_with_ring(1200, 1700, 1, 45), 128, 96, 6, 4, 3.0, 6.0),
+    ("m8_ragged", lambda: cloud_with_ring(999, 1531, 257, 46), 128, 0, 8, 6, 4.0, 9.0),
+]
+
+
+def run_split(torch, fn, y, x, w, q, V, v, ns1, G, band, m, p, eps_v, eps_s, P):
+    S = fn.Solver(grid=G, m=m, p=p, eps_I=eps_v, eps_S=eps_s, precision=P, n=band)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=len(x) - ns1)
+    S.set_charges(dev(torch, q))
+    phi, H = S.eval()
+    u = S.adjoint_H(dev(torch, V))
+    up = S.adjoint_phi(dev(torch, v))
+    torch.cuda.synchronize()
+    return phi.cpu().numpy(), H.cpu().numpy(), u.cpu().numpy(), up.cpu().numpy(), S
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_split_matches_per_class_oracle(torch, fn, case, precision):
+    name, make, G, band, m, p, cv, cs = case
+    print(f"split case {name} {precision}", flush=True)
+    y, x, w, q, ns1 = make()
+    nb = band or G // 2
+    prm_v = fs.Params(G=G, m=m, p=p, eps_I=cv / nb, band=band)
+    prm_s = fs.Params(G=G, m=m, p=p, eps_I=cs / nb, band=band)
+    rng = np.random.default_rng(len(y))
+    V = rng.standard_normal((len(y), 2))
+    v = rng.standard_normal(len(y))
+    Fv, Fs = oracle_split(y, x, w, ns1, prm_v, prm_s)
+    phi2, H2, u2, up2 = oracle_outputs(Fv, Fs, ns1, q, V, v)
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    phi, H, u, up, S = run_split(torch, fn, y, x, w, q, V, v, ns1, G, band, m, p, cv / nb, cs / nb, P)
+    errs = dict(phi=rel_l2(phi, phi2), H=rel_l2(H, H2), HT=rel_l2(u, u2), phiT=rel_l2(up, up2))
+    print(errs, flush=True)
+    assert max(errs.values()) < (1e-10 if precision == "fp64" else 1e-6), errs
+    info = S.info()
+    assert info["n_surf"] == len(x) - ns1
+    assert info["near_cells_surf"] == int(np.ceil(cs / nb * G))
+    if Fs is not None:
+        assert abs(info["near_pairs_surf"] - len(Fs.ni)) <= 1e-6 * len(Fs.ni) + 2
+    if Fv is not None:
+        assert abs(info["near_pairs"] - len(Fv.ni)) <= 1e-6 * len(Fv.ni) + 2
+
+
+def test_no_surface_sources_is_the_one_class_sum(torch, fn):
+    """eps_S set but n_surf = 0 (and fn_set_geometry itself): every source takes eps_I."""
+    y, x, w, q = synth.random_cloud(1500, 2000, 47)
+    G = 128
+    prm = fs.Params(G=G, m=6, p=6, eps_I=5 / 64)
+    F = fs.FastSum(y, x, w, prm)
+    phi2, H2 = F.forward(q)
+    for n_surf in (0, None):
+        S = fn.Solver(grid=G, m=6, p=6, eps_I=5 / 64, eps_S=9 / 64, precision=fn.FN_FP64)
+        if n_surf is None:
+            S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
+        else:
+            S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=n_surf)
+        S.set_charges(dev(torch, q))
+        phi, H = S.eval()
+        assert rel_l2(phi.cpu().numpy(), phi2) < 1e-10 and rel_l2(H.cpu().numpy(), H2) < 1e-10
+        assert S.info()["n_surf"] == 0
+
+
+def test_surface_radius_ignored_without_eps_S(torch, fn):
+    """n_surf given but eps_S = 0: one class at eps_I."""
+    y, x, w, q, ns1 = cloud_with_ring(1200, 1500, 300, 48)
+    prm = fs.Params(G=128, m=6, p=6, eps_I=5 / 64)
+    phi2, H2 = fs.FastSum(y, x, w, prm).forward(q)
+    S = fn.Solver(grid=128, m=6, p=6, eps_I=5 / 64, precision=fn.FN_FP64)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=len(x) - ns1)
+    S.set_charges(dev(torch, q))
+    phi, H = S.eval()
+    assert rel_l2(phi.cpu().numpy(), phi2) < 1e-10 and rel_l2(H.cpu().numpy(), H2) < 1e-10
+    assert S.info()["n_surf"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_coincident_points_in_both_classes(torch, fn, precision):
+    """Targets placed exactly on volume and on surface sources: the pairs at r = 0 are not part
+    of the sum, in either class (forward and phi adjoint)."""
+    y, x, w, q, ns1 = cloud_with_ring(800, 900, 200, 49)
+    y = np.concatenate([y, x[5:25], x[ns1 + 3:ns1 + 40]])
+    rng = np.random.default_rng(50)
+    V, v = rng.standard_normal((len(y), 2)), rng.standard_normal(len(y))
+    G = 128
+    prm_v, prm_s = fs.Params(G=G, m=6, p=6, eps_I=4 / 64), fs.Params(G=G, m=6, p=6, eps_I=7 / 64)
+    Fv, Fs = oracle_split(y, x, w, ns1, prm_v, prm_s)
+    phi2, H2, u2, up2 = oracle_outputs(Fv, Fs, ns1, q, V, v)
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    phi, H, u, up, _ = run_split(torch, fn, y, x, w, q, V, v, ns1, G, 0, 6, 6, 4 / 64, 7 / 64, P)
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    errs = dict(phi=rel_l2(phi, phi2), H=rel_l2(H, H2), HT=rel_l2(u, u2), phiT=rel_l2(up, up2))
+    assert max(errs.values()) < tol, errs
+    # and against the exact sum, where the coincident pairs are left out
+    phi1, _ = direct.forward(y, x, w, q)
+    assert rel_l2(phi, phi1) < 1e-5
+
+
+def test_split_graph_replay_equals_eager(torch, fn):
+    y, x, w, q, ns1 = rounded_square(8000, 51)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        S = fn.Solver(grid=256, m=6, p=8, eps_I=5 / 192, eps_S=10 / 192, n=192, precision=fn.FN_FP32_MIXED)
+        S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=len(x) - ns1)
+        qd, Vd = dev(torch, q), dev(torch, np.random.default_rng(52).standard_normal((len(y), 2)))
+        phi = torch.empty(len(y), dtype=torch.float64, device="cuda")
+        H = torch.empty(len(y), 2, dtype=torch.float64, device="cuda")
+        u = torch.empty(len(x), dtype=torch.float64, device="cuda")
+        S.set_charges(qd)
+        S.eval(out_phi=phi, out_H=H)
+        S.adjoint_H(Vd, out=u)
+        g = fn.Graph()
+        with g.capture(st):
+            S.set_charges(qd)
+            S.eval(out_phi=phi, out_H=H)
+            S.adjoint_H(Vd, out=u)
+        rng = np.random.default_rng(53)
+        for rep in range(3):
+            qd.copy_(dev(torch, rng.standard_normal(len(x))))
+            Vd.copy_(dev(torch, rng.standard_normal((len(y), 2))))
+            S.set_charges(qd)
+            pe, he = S.eval()
+            ue = S.adjoint_H(Vd)
+            st.synchronize()
+            g.launch(st)
+            st.synchronize()
+            assert torch.equal(phi, pe) and torch.equal(H, he) and torch.equal(u, ue), f"replay {rep}"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_members_with_surface_sources(torch, fn, precision):
+    members = [cloud_with_ring(700, 900, 120, 60), rounded_square(3000, 61), cloud_with_ring(400, 0, 90, 62),
+               cloud_with_ring(600, 800, 0, 63)]
+    grids = [(128, 0, 4.0, 7.0), (128, 96, 4.0, 8.0), (64, 0, 3.0, 5.0), (128, 0, 4.0, 7.0)]
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    ys, xs, ws, qs, nsf, Vs, prms = [], [], [], [], [], [], []
+    for (y, x, w, q, ns1), (G, band, cv, cs) in zip(members, grids):
+        nb = band or G // 2
+        ys.append(y), xs.append(x), ws.append(w), qs.append(q), nsf.append(len(x) - ns1)
+        Vs.append(np.random.default_rng(len(y)).standard_normal((len(y), 2)))
+        prms.append((fs.Params(G=G, m=6, p=6, eps_I=cv / nb, band=band), fs.Params(G=G, m=6, p=6, eps_I=cs / nb, band=band)))
+    toff = np.concatenate([[0], np.cumsum([len(a) for a in ys])])
+    soff = np.concatenate([[0], np.cumsum([len(a) for a in xs])])
+    B = fn.Batch([dict(grid=pv.G, m=6, p=6, eps_I=pv.eps_I, eps_S=ps.eps_I, n=pv.band, precision=P)
+                  for pv, ps in prms])
+    B.set_geometry(toff, dev(torch, np.concatenate(ys)), soff, dev(torch, np.concatenate(xs)),
+                   dev(torch, np.concatenate(ws)), n_surf=nsf)
+    B.set_charges(dev(torch, np.concatenate(qs)))
+    phi, H = B.eval()
+    u = B.adjoint_H(dev(torch, np.concatenate(Vs)))
+    phi, H, u = phi.cpu().numpy(), H.cpu().numpy(), u.cpu().numpy()
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    for i, (pv, ps) in enumerate(prms):
+        ns1 = len(xs[i]) - nsf[i]
+        Fv, Fs = oracle_split(ys[i], xs[i], ws[i], ns1, pv, ps)
+        v0 = np.zeros(len(ys[i]))
+        phi2, H2, u2, _ = oracle_outputs(Fv, Fs, ns1, qs[i], Vs[i], v0)
+        t, s = slice(toff[i], toff[i + 1]), slice(soff[i], soff[i + 1])
+        errs = dict(phi=rel_l2(phi[t], phi2), H=rel_l2(H[t], H2), HT=rel_l2(u[s], u2))
+        print(i, errs, flush=True)
+        assert max(errs.values()) < tol, (i, errs)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_energy_with_surface_radius(torch, fn, precision):
+    """The FEM front binds boundary-edge points as surface sources: energy and gradient against
+    the per-class oracle on the mesh's quadrature points."""
+    nodes, tris, bedges = synth.annulus_mesh(R1=0.5, R2=1.0, N=3000, seed=synth.SEED_BASE + 3)
+    M = synth.M_smooth(nodes, seed=synth.SEED_BASE + 10)
+    x, w = fem.sources(nodes, tris, bedges)
+    ns1 = 3 * len(tris)
+    q = fem.charges(nodes, tris, bedges, M)
+    ell = fem.lumped_mass(nodes, tris)
+    prm_v, prm_s = fs.Params(G=256, m=6, p=6, eps_I=5 / 128), fs.Params(G=256, m=6, p=6, eps_I=9 / 128)
+    Fv, Fs = oracle_split(nodes, x, w, ns1, prm_v, prm_s)
+    _, H0 = Fv.forward(q[:ns1])
+    H0 = H0 + Fs.forward(q[ns1:])[1]
+    E0 = fem.energy(M, H0, ell)
+    u0 = np.concatenate([Fv.adjoint_H(ell[:, None] * M), Fs.adjoint_H(ell[:, None] * M)])
+    g0 = fem.energy_grad(H0, ell, fem.charges_T(nodes, tris, bedges, u0))
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    S = fn.Solver(grid=256, m=6, p=6, eps_I=5 / 128, eps_S=9 / 128, precision=P)
+    mesh = fn.Mesh(dev(torch, nodes), torch.from_numpy(tris.astype(np.int32)).cuda(),
+                   torch.from_numpy(bedges.astype(np.int32)).cuda())
+    S.bind_mesh(mesh)
+    assert S.info()["n_surf"] == 2 * len(bedges)
+    E, g = S.energy(dev(torch, M))
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    assert abs(float(E) - E0) <= tol * abs(E0)
+    assert rel_l2(g.cpu().numpy(), g0) < tol

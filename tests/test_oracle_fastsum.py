@@ -206,3 +206,53 @@ def test_accuracy_improves_with_regularization_degree_and_radius():
         phi, H = fs.FastSum(y, x, w, fs.Params(G=256, m=6, p=p, eps_I=c / 128)).forward(q)
         e[(p, c)] = rel_l2(H, H1)
     assert e[(2, 4)] > e[(4, 4)] > e[(6, 6)] > e[(8, 8)]
+
+
+def test_sum_over_a_partition_of_the_sources_is_the_whole_sum():
+    """Eq. (2) is linear in the sources: with the torus map taken over all points (map_with),
+    the fast sums over two disjoint source subsets add up to the fast sum over all sources at
+    the same parameters, and the adjoints are the restrictions of the whole adjoint."""
+    y, x, w, q = synth.random_cloud(300, 400, 7)
+    prm = fs.Params(G=128, m=6, p=6, eps_I=5 / 64)
+    k = 170
+    F = fs.FastSum(y, x, w, prm)
+    Fa = fs.FastSum(y, x[:k], w[:k], prm, map_with=x[k:])
+    Fb = fs.FastSum(y, x[k:], w[k:], prm, map_with=x[:k])
+    assert Fa.s == F.s and Fb.s == F.s and np.all(Fa.c == F.c)
+    phi, H = F.forward(q)
+    pa, Ha = Fa.forward(q[:k])
+    pb, Hb = Fb.forward(q[k:])
+    assert rel_l2(pa + pb, phi) < 1e-12 and rel_l2(Ha + Hb, H) < 1e-12
+    rng = np.random.default_rng(8)
+    V, v = rng.standard_normal((300, 2)), rng.standard_normal(300)
+    assert rel_l2(np.concatenate([Fa.adjoint_H(V), Fb.adjoint_H(V)]), F.adjoint_H(V)) < 1e-12
+    assert rel_l2(np.concatenate([Fa.adjoint_phi(v), Fb.adjoint_phi(v)]), F.adjoint_phi(v)) < 1e-12
+
+
+def test_two_source_classes_with_their_own_radius_match_the_direct_sum():
+    """The rounded-square workload (jittered lattice of volume charges plus the boundary
+    line of surface charges, at the bench's density of about 2.3 points per grid cell):
+    each class summed with its own regularization radius and the torus map over all
+    points.  Together the two fast sums match the direct sum O1, and giving the line its
+    larger radius lowers the H error several times over the one-radius sum (the line's
+    truncation error dominates the latter)."""
+    d = synth.rounded_square_cloud(N=16384, seed=synth.SEED_BASE + 4)
+    y, x, w, q = d["y"], d["x"], d["w"], d["q"]
+    ns1 = int(np.sum(w == d["h"] ** 2))
+    assert np.all(w[:ns1] == d["h"] ** 2) and not np.any(w[ns1:] == d["h"] ** 2)
+    G, n = 256, 192
+    prm_v = fs.Params(G=G, m=6, p=8, eps_I=6 / n, band=n)
+    prm_s = fs.Params(G=G, m=6, p=8, eps_I=10 / n, band=n)
+    Fv = fs.FastSum(y, x[:ns1], w[:ns1], prm_v, map_with=x[ns1:])
+    Fs = fs.FastSum(y, x[ns1:], w[ns1:], prm_s, map_with=x[:ns1])
+    F1 = fs.FastSum(y, x[ns1:], w[ns1:], prm_v, map_with=x[:ns1])  # line at the volume radius
+    pv, Hv = Fv.forward(q[:ns1])
+    ps, Hs = Fs.forward(q[ns1:])
+    _, H1s = F1.forward(q[ns1:])
+    phi1, H1 = direct.forward(y, x, w, q)
+    e_phi, e_H, e_one = rel_l2(pv + ps, phi1), rel_l2(Hv + Hs, H1), rel_l2(Hv + H1s, H1)
+    assert e_phi < 1e-7 and e_H < 5e-7, (e_phi, e_H)
+    assert e_one > 3 * e_H, (e_one, e_H)
+    V = d["h"] ** 2 * d["M_tgt"]  # the adjoint input of the energy gradient: nodal mass times M
+    u = np.concatenate([Fv.adjoint_H(V), Fs.adjoint_H(V)])
+    assert rel_l2(u, direct.adjoint(y, x, w, V=V)) < 5e-7
