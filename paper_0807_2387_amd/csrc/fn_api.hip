@@ -248,6 +248,11 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
     L.off_spec2 = take(specb);
     L.off_far = take((size_t)3 * nmax * 8);
     L.off_red = take(8192 * 8);  // see the RED_* slots below
+    {
+        const int64_t nb1 = (L.emax + 15) / 16;  // near-field home blocks per dimension (16 cells)
+        L.off_blk_fs = take((size_t)nb1 * nb1 * 4);
+        L.off_blk_as = take((size_t)nb1 * nb1 * 4);
+    }
     L.off_skey = take(nmax * 4);
     L.off_sval = take(nmax * 4);
     const int64_t nblk = (nmax + 4095) / 4096;
@@ -288,6 +293,8 @@ static void bind_buffers(fn_ctx *c)
     B.spec2 = b + L.off_spec2;
     B.far = reinterpret_cast<double *>(b + L.off_far);
     B.red = reinterpret_cast<double *>(b + L.off_red);
+    B.blk_fs = reinterpret_cast<uint32_t *>(b + L.off_blk_fs);
+    B.blk_as = reinterpret_cast<uint32_t *>(b + L.off_blk_as);
     B.skey = reinterpret_cast<uint32_t *>(b + L.off_skey);
     B.sval = reinterpret_cast<uint32_t *>(b + L.off_sval);
     B.hist = reinterpret_cast<uint32_t *>(b + L.off_hist);
@@ -712,6 +719,16 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
     }
     FN_HIP(c, hipStreamSynchronize(c->stream));
     c->geom = g;
+    if (nsets == 3) {  // the sparse surface class: list the near blocks it needs
+        uint32_t cnt[2] = {0, 0};
+        uint32_t *dcnt = reinterpret_cast<uint32_t *>(B.red + RED_PART);
+        FN_HIP(c, launch_block_list(c->geom, B, 0, 2, g.rnear_s, 1, B.blk_fs, dcnt, c->stream));
+        FN_HIP(c, launch_block_list(c->geom, B, 2, 0, g.rnear_s, 0, B.blk_as, dcnt + 1, c->stream));
+        FN_HIP(c, hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+        FN_HIP(c, hipStreamSynchronize(c->stream));
+        c->geom.nblk_fs = (int32_t)cnt[0];
+        c->geom.nblk_as = (int32_t)cnt[1];
+    }
     // per source class: (target, source) pairs closer than the class radius (the near
     // field's unit of work) and pairs at exactly the same position
     for (int s = 1; s < nsets; ++s) {
@@ -720,7 +737,8 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
             NearArgs na = near_args(c, s - 1);
             double *cnt = B.far;  // one count per source of the class
             double tot = 0.0;
-            FN_HIP(c, launch_near_adj(c->geom, B, na, s, 2, B.red + RED_SUMV, cnt, c->stream));
+            FN_HIP(c, launch_near_adj(c->geom, B, na, s, 2, B.red + RED_SUMV, cnt, s == 2 ? B.blk_as : nullptr,
+                                      c->geom.nblk_as, c->stream));
             FN_HIP(c, launch_sum(cnt, set_size(c->geom, s), B.red + RED_SUMV, c->stream));
             FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
             FN_HIP(c, hipStreamSynchronize(c->stream));
@@ -822,7 +840,8 @@ static int eval_impl(fn_ctx *c, double *phi, double *H)
         if (set_size(g, set) == 0 && k > 0) continue;
         NearArgs na = near_args(c, k);
         const int stg = k ? FN_ST_NEAR_SURF : FN_ST_NEAR;
-        FN_STAGE(c, stg, launch_near_fwd(g, B, na, set, k > 0, B.red + RED_SUMQ, want_phi, want_h, phi, H, st));
+        FN_STAGE(c, stg, launch_near_fwd(g, B, na, set, k > 0, B.red + RED_SUMQ, want_phi, want_h, phi, H,
+                                         k ? B.blk_fs : nullptr, g.nblk_fs, st));
         if (want_phi && (k ? g.coincident_s : g.coincident) > 0)
             FN_STAGE(c, stg, launch_near_coincident(g, B, na, 0, set, phi, st));
     }
@@ -897,7 +916,8 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
         NearArgs na = near_args(c, k);
         double *u_k = u + set_base(g, set);
         const int stg = k ? FN_ST_A_NEAR_SURF : FN_ST_A_NEAR;
-        FN_STAGE(c, stg, launch_near_adj(g, B, na, set, kind, B.red + RED_SUMV, u_k, st));
+        FN_STAGE(c, stg, launch_near_adj(g, B, na, set, kind, B.red + RED_SUMV, u_k, k ? B.blk_as : nullptr,
+                                         g.nblk_as, st));
         if (kind == 1 && (k ? g.coincident_s : g.coincident) > 0)
             FN_STAGE(c, stg, launch_near_coincident(g, B, na, set, 0, u_k, st));
     }

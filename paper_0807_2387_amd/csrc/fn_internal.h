@@ -77,6 +77,7 @@ struct Geom {
     int32_t rnear_s = 0;
     int64_t near_pairs_s = 0;
     int64_t coincident_s = 0;
+    int32_t nblk_fs = 0, nblk_as = 0;  // listed near blocks of the surface class (forward, adjoint)
 };
 
 // Point sets: 0 = targets, 1 = (volume) sources, 2 = surface sources.  Sets 1 and 2
@@ -110,6 +111,8 @@ struct Buffers {
     void *spec2 = nullptr;           // column-pass outputs, cplx<R>, 2 fields
     double *far = nullptr;           // [3][max(nt, ns)] far-field results, sorted order
     double *red = nullptr;           // reduction scratch
+    uint32_t *blk_fs = nullptr;      // near blocks of the surface class: targets near surface sources
+    uint32_t *blk_as = nullptr;      // near blocks of the surface class: blocks holding surface sources
     // sort scratch
     uint32_t *skey = nullptr, *sval = nullptr, *hist = nullptr;
     double *scratch64 = nullptr;     // plan FFT scratch (n x n complex) aliases grid/spec
@@ -120,6 +123,7 @@ struct Layout {
     size_t off_W, off_W2, off_tw, off_tw64;
     size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_cstart[3];
     size_t off_w, off_val, off_val64, off_aval, off_aval64, off_ptile, off_grid, off_spec, off_spec2, off_far, off_red;
+    size_t off_blk_fs, off_blk_as;
     size_t off_skey, off_sval, off_hist;
     int64_t emax = 0;                // bound on the window extent
     int64_t ldS = 0;                 // leading dimension of the spectra
@@ -240,10 +244,17 @@ struct NearArgs {
 // forward: targets against source set in_set; accum = 0 writes far + near (+ the
 // scale term of all charges), accum = 1 adds the near part only
 hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, int in_set, int accum,
-                           const double *sum_s, int want_phi, int want_h, double *phi, double *H, hipStream_t st);
+                           const double *sum_s, int want_phi, int want_h, double *phi, double *H,
+                           const uint32_t *blocks, int nblocks, hipStream_t st);
 // adjoint: source set out_set against the targets; u is that set's part of the output
 hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int kind,
-                           const double *sum_v, double *u, hipStream_t st);
+                           const double *sum_v, double *u, const uint32_t *blocks, int nblocks, hipStream_t st);
+// The near field's home blocks (NB x NB cells) of the geometry, and the list of those with
+// home points of out_set (and, if need_in, points of in_set within R cells): the sparse
+// surface class runs only over these.  *count (device) receives the list length.
+int near_blocks(const Geom &g);
+hipError_t launch_block_list(const Geom &g, const Buffers &b, int out_set, int in_set, int R, int need_in,
+                             uint32_t *list, uint32_t *count, hipStream_t st);
 hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int in_set,
                                   double *out, hipStream_t st);
 hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, double *cnt, hipStream_t st);

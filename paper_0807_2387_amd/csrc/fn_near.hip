@@ -71,6 +71,7 @@ struct NearSets {
     const double *pay;            // fwd: s [n_in]; adj H: V [2][n_in]; adj phi: v [n_in]
     int Ex, Ey, nbx;
     int accum;                    // forward only: add the near part to phi / H instead of writing far + near
+    const uint32_t *blocks;       // home blocks to run (block i of the launch is blocks[i]); NULL: all
 };
 
 // U(x) = sum_{k<P} c_k x^k and U'(x) in one Horner sweep (the derivative
@@ -219,7 +220,8 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     __shared__ uint32_t ipre[MAXROWS + 1], istart[MAXROWS]; // input rows
 
     const int Ex = S.Ex, Ey = S.Ey, R = na.rnear;
-    const int bx = blockIdx.x % S.nbx, by = blockIdx.x / S.nbx;
+    const int bid = S.blocks ? (int)S.blocks[blockIdx.x] : (int)blockIdx.x;
+    const int bx = bid % S.nbx, by = bid / S.nbx;
     const int hx0 = bx * NB, hy0 = by * NB;
     const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NB + R, Ey);
     const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NB + R, Ex);
@@ -450,6 +452,10 @@ __global__ void __launch_bounds__(256) k_coincident_count(NearSets S, double *__
 #endif
 constexpr int CAP_FWD = FN_NEAR_CAP_FWD;
 constexpr int CAP_ADJ = FN_NEAR_CAP_ADJ;
+// surface-source class (a thin strip of sources): forward blocks stage few sources,
+// adjoint blocks (home = surface points) stage the dense targets around them
+constexpr int CAP_FWD_S = 512;
+constexpr int CAP_ADJ_S = 1024;
 
 template <int MODE, int CAP, int P>
 hipError_t launch_p(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum, double *o0,
@@ -498,7 +504,37 @@ NearSets make_sets(const Geom &g, const Buffers &b, int out_set, int in_set)
     S.Ey = g.ext[1];
     S.nbx = (g.ext[0] + NB - 1) / NB;
     S.accum = 0;
+    S.blocks = nullptr;
     return S;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v)
+{
+    if (threadIdx.x == 0) p[0] = v;
+}
+
+// Home blocks with work: home points in the block and, if need_in, points of the
+// input set within R cells of it.  One thread per block; the list order depends on
+// the atomics, the blocks' results do not.
+__global__ void k_block_list(NearSets S, int nblk, int R, int need_in, uint32_t *__restrict__ list,
+                             uint32_t *__restrict__ count)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    const int bx = b % S.nbx, by = b / S.nbx;
+    const int hx0 = bx * NB, hy0 = by * NB;
+    const int hx1 = min(hx0 + NB, S.Ex), hy1 = min(hy0 + NB, S.Ey);
+    uint32_t home = 0;
+    for (int y = hy0; y < hy1; ++y) home += S.cs_out[(int64_t)y * S.Ex + hx1] - S.cs_out[(int64_t)y * S.Ex + hx0];
+    if (home == 0) return;
+    if (need_in) {
+        const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NB + R, S.Ey);
+        const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NB + R, S.Ex);
+        uint32_t in = 0;
+        for (int y = iy0; y < iy1; ++y) in += S.cs_in[(int64_t)y * S.Ex + ix1] - S.cs_in[(int64_t)y * S.Ex + ix0];
+        if (in == 0) return;
+    }
+    list[atomicAdd(count, 1u)] = (uint32_t)b;
 }
 
 template <int P>
@@ -541,13 +577,33 @@ hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, 
     return hipGetLastError();
 }
 
+int near_blocks(const Geom &g) { return ((g.ext[0] + NB - 1) / NB) * ((g.ext[1] + NB - 1) / NB); }
+
+hipError_t launch_block_list(const Geom &g, const Buffers &b, int out_set, int in_set, int R, int need_in,
+                             uint32_t *list, uint32_t *count, hipStream_t st)
+{
+    const int nblk = near_blocks(g);
+    const NearSets S = make_sets(g, b, out_set, in_set);
+    k_fill_u32<<<1, 1, 0, st>>>(count, 0u);
+    k_block_list<<<(nblk + 255) / 256, 256, 0, st>>>(S, nblk, R, need_in, list, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, int in_set, int accum,
-                           const double *sum_s, int want_phi, int want_h, double *phi, double *H, hipStream_t st)
+                           const double *sum_s, int want_phi, int want_h, double *phi, double *H,
+                           const uint32_t *blocks, int nblocks, hipStream_t st)
 {
     if (g.nt == 0) return hipSuccess;
     NearSets S = make_sets(g, b, 0, in_set);
     S.accum = accum;
-    const int nblk = S.nbx * ((g.ext[1] + NB - 1) / NB);
+    S.blocks = blocks;
+    const int nblk = blocks ? nblocks : near_blocks(g);
+    if (nblk == 0) return hipSuccess;
+    if (in_set == 2) {
+        if (want_phi && want_h) return launch_mode<MODE_FWD_BOTH, CAP_FWD_S>(nblk, st, S, na, sum_s, phi, H);
+        if (want_phi) return launch_mode<MODE_FWD_PHI, CAP_FWD_S>(nblk, st, S, na, sum_s, phi, H);
+        return launch_mode<MODE_FWD_H, CAP_FWD_S>(nblk, st, S, na, sum_s, phi, H);
+    }
     if (want_phi && want_h) return launch_mode<MODE_FWD_BOTH, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
     if (want_phi) return launch_mode<MODE_FWD_PHI, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
     return launch_mode<MODE_FWD_H, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
@@ -556,11 +612,15 @@ hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, 
 // kind 0: H^T (V), kind 1: phi^T (v), kind 2: count pairs closer than the class radius
 // per source.  u is the part of the output that belongs to source set out_set.
 hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int kind,
-                           const double *sum_v, double *u, hipStream_t st)
+                           const double *sum_v, double *u, const uint32_t *blocks, int nblocks, hipStream_t st)
 {
     if (set_size(g, out_set) == 0) return hipSuccess;
-    const NearSets S = make_sets(g, b, out_set, 0);
-    const int nblk = S.nbx * ((g.ext[1] + NB - 1) / NB);
+    NearSets S = make_sets(g, b, out_set, 0);
+    S.blocks = blocks;
+    const int nblk = blocks ? nblocks : near_blocks(g);
+    if (nblk == 0) return hipSuccess;
+    if (out_set == 2 && kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ_S>(nblk, st, S, na, sum_v, u, nullptr);
+    if (out_set == 2 && kind == 1) return launch_mode<MODE_ADJ_PHI, CAP_ADJ_S>(nblk, st, S, na, sum_v, u, nullptr);
     if (kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
     if (kind == 1) return launch_mode<MODE_ADJ_PHI, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
     k_near<MODE_COUNT, CAP_ADJ, 1, false><<<nblk, NTH, 0, st>>>(S, na, sum_v, u, nullptr);
