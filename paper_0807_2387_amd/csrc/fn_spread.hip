@@ -31,6 +31,7 @@ namespace {
 #define FN_SPREAD_CELLS 1  // mixed path: one thread per grid cell (k_spread_cells)
 #endif
 constexpr int SPREAD_WAVES = 2;
+constexpr uint32_t SPREAD_FLUSH = 8;  // points per FP32 register sum in k_spread_cells
 constexpr int SPREAD_NT = 64 * SPREAD_WAVES;
 
 // z - m is formed as -t^2/(z + m): for the central taps z is close to m and the
@@ -207,31 +208,36 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
             s1 = cstart[cell + 1];
         }
         if (s0 == s1) continue;
+        // at most SPREAD_FLUSH points per FP32 register sum, then into the FP64 accumulator
+        // (a dense cluster can put thousands of points in one cell)
+        for (uint32_t i0 = s0; i0 < s1; i0 += SPREAD_FLUSH) {
+            const uint32_t i1 = min(s1, i0 + SPREAD_FLUSH);
 #pragma unroll
-        for (int g0 = 0; g0 < M2; g0 += RG) {
-            float r[RG][M2];
+            for (int g0 = 0; g0 < M2; g0 += RG) {
+                float r[RG][M2];
 #pragma unroll
-            for (int bb = 0; bb < RG; ++bb)
+                for (int bb = 0; bb < RG; ++bb)
 #pragma unroll
-                for (int a = 0; a < M2; ++a) r[bb][a] = 0.f;
-            for (uint32_t i = s0; i < s1; ++i) {
-                const float v = fval[i];
-                float wx[M2], wy[M2];
-                taps<float, M2>(wp, fr32[i], 0.f, 0.f, 0.f, wx);
-                taps<float, M2>(wp, fr32[N + i], 0.f, 0.f, 0.f, wy);
+                    for (int a = 0; a < M2; ++a) r[bb][a] = 0.f;
+                for (uint32_t i = i0; i < i1; ++i) {
+                    const float v = fval[i];
+                    float wx[M2], wy[M2];
+                    taps<float, M2>(wp, fr32[i], 0.f, 0.f, 0.f, wx);
+                    taps<float, M2>(wp, fr32[N + i], 0.f, 0.f, 0.f, wy);
 #pragma unroll
-                for (int bb = 0; bb < RG; ++bb) {
-                    const float vy = g0 + bb < M2 ? v * wy[g0 + bb < M2 ? g0 + bb : 0] : 0.f;
+                    for (int bb = 0; bb < RG; ++bb) {
+                        const float vy = g0 + bb < M2 ? v * wy[g0 + bb < M2 ? g0 + bb : 0] : 0.f;
 #pragma unroll
-                    for (int a = 0; a < M2; ++a) r[bb][a] = fmaf(vy, wx[a], r[bb][a]);
+                        for (int a = 0; a < M2; ++a) r[bb][a] = fmaf(vy, wx[a], r[bb][a]);
+                    }
                 }
+                double *af = myacc + (ly + g0) * PT + lx;
+#pragma unroll
+                for (int bb = 0; bb < RG; ++bb)
+                    if (g0 + bb < M2)
+#pragma unroll
+                        for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)r[bb][a]);
             }
-            double *af = myacc + (ly + g0) * PT + lx;
-#pragma unroll
-            for (int bb = 0; bb < RG; ++bb)
-                if (g0 + bb < M2)
-#pragma unroll
-                    for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)r[bb][a]);
         }
     }
     __syncthreads();
