@@ -702,11 +702,6 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
     const int64_t ncell = (int64_t)g.ext[0] * g.ext[1];
     int keybits = 1;
     while (((int64_t)1 << keybits) < ncell) ++keybits;
-    // x-fraction bits below the cell index up to the radix passes' 8-bit digits (an even
-    // number of them): points of a cell sorted by x at no extra sort pass
-    int passes = (keybits + 7) / 8;
-    passes += passes % 2;
-    const int fbits = std::min(std::min(8 * passes, 32) - keybits, 16);
     Buffers &B = c->buf;
     bind_source_sets(c, n_src, g.nsurf);
     const int nsets = g.nsurf > 0 ? 3 : 2;
@@ -715,9 +710,8 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
         const double *xy = s == 0 ? tgt_xy : src_xy + 2 * base;
         if (n > 0) {
             FN_HIP(c, launch_prepare(xy, n, g.c[0], g.c[1], g.s, P.G, P.m, g.wlo[0], g.wlo[1], g.ext[0],
-                                     g.ext[1], fbits, B.key[s], B.perm[s], c->stream));
-            FN_HIP(c, radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, n, keybits + fbits, c->stream));
-            FN_HIP(c, launch_key_shift(B.key[s], n, fbits, c->stream));
+                                     g.ext[1], B.key[s], B.perm[s], c->stream));
+            FN_HIP(c, radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, n, keybits, c->stream));
             FN_HIP(c, launch_finish_points(xy, s ? src_w + base : nullptr, n, B.perm[s], g.c[0], g.c[1], g.s,
                                            P.G, B.fr32[s], B.fr64[s], s ? B.w + base : nullptr, c->stream));
         }

@@ -58,11 +58,8 @@ __global__ void __launch_bounds__(RB) k_reduce(const double *__restrict__ p, int
 
 // Centred grid coordinate v = s (r - c) G (exactly t G for the torus coordinate t,
 // G being a power of two); the point's taps are floor(v) + G/2 - m + 1 + a.
-// Sort key: the window cell index, followed by fbits bits of the in-cell x fraction, so
-// that the points of a cell come out ordered by x (the near field trims its row windows
-// with that order; any order is correct).  k_key_shift drops the fraction bits again.
 __global__ void k_prepare(const double *__restrict__ xy, int64_t n, double cx, double cy, double s,
-                          double G, int m, int wlox, int wloy, int extx, int exty, int fbits,
+                          double G, int m, int wlox, int wloy, int extx, int exty,
                           uint32_t *__restrict__ key, uint32_t *__restrict__ idx)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -75,17 +72,8 @@ __global__ void k_prepare(const double *__restrict__ xy, int64_t n, double cx, d
     // the window is sized with a margin; clamping only guards against a rounding slip
     bx = min(max(bx, 0), extx - 2 * m);
     by = min(max(by, 0), exty - 2 * m);
-    const uint32_t cell = (uint32_t)by * (uint32_t)extx + (uint32_t)bx;
-    const uint32_t nq = 1u << fbits;
-    const uint32_t q = min((uint32_t)((vx - floor(vx)) * (double)nq), nq - 1u);
-    key[i] = fbits ? (cell << fbits) | q : cell;
+    key[i] = (uint32_t)by * (uint32_t)extx + (uint32_t)bx;
     idx[i] = (uint32_t)i;
-}
-
-__global__ void k_key_shift(uint32_t *__restrict__ key, int64_t n, int fbits)
-{
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) key[i] >>= fbits;
 }
 
 // In-cell fractions v - floor(v) (exact in FP64), sorted order.
@@ -228,20 +216,12 @@ hipError_t launch_nonfinite(const double *p, int64_t n, double *part, int nblk, 
 }
 
 hipError_t launch_prepare(const double *xy, int64_t n, double cx, double cy, double s, int G, int m,
-                          int wlox, int wloy, int extx, int exty, int fbits, uint32_t *key, uint32_t *idx,
+                          int wlox, int wloy, int extx, int exty, uint32_t *key, uint32_t *idx,
                           hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    if (fbits < 0 || fbits > 16) return hipErrorInvalidValue;
     int nb = (int)((n + 255) / 256);
-    k_prepare<<<nb, 256, 0, st>>>(xy, n, cx, cy, s, (double)G, m, wlox, wloy, extx, exty, fbits, key, idx);
-    return hipGetLastError();
-}
-
-hipError_t launch_key_shift(uint32_t *key, int64_t n, int fbits, hipStream_t st)
-{
-    if (n == 0 || fbits == 0) return hipSuccess;
-    k_key_shift<<<(int)((n + 255) / 256), 256, 0, st>>>(key, n, fbits);
+    k_prepare<<<nb, 256, 0, st>>>(xy, n, cx, cy, s, (double)G, m, wlox, wloy, extx, exty, key, idx);
     return hipGetLastError();
 }
 

@@ -177,9 +177,8 @@ hipError_t launch_maxdist(const double *p, int64_t n, double cx, double cy, doub
                           hipStream_t st);
 hipError_t launch_nonfinite(const double *p, int64_t n, double *part, int nblk, hipStream_t st);
 hipError_t launch_prepare(const double *xy, int64_t n, double cx, double cy, double s, int G, int m,
-                          int wlox, int wloy, int extx, int exty, int fbits, uint32_t *key, uint32_t *idx,
+                          int wlox, int wloy, int extx, int exty, uint32_t *key, uint32_t *idx,
                           hipStream_t st);
-hipError_t launch_key_shift(uint32_t *key, int64_t n, int fbits, hipStream_t st);  // key >>= fbits
 hipError_t radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, uint32_t *hist,
                       int64_t n, int keybits, hipStream_t st);  // result in key/val
 hipError_t launch_finish_points(const double *xy, const double *w, int64_t n, const uint32_t *perm,

@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
             // raw cell-start bounds of the columns of row r whose cells can hold a point within
             // eps_I: from the vertical gap between the home point and row r (padded against
             // rounding); an empty range where the gap alone exceeds eps_I
-            auto bounds = [&](int r, uint32_t &blo, uint32_t &bhi, double &wr) {
+            auto bounds = [&](int r, uint32_t &blo, uint32_t &bhi) {
                 const double gap = r < hcy ? (double)(hcy - r - 1) + py : (r > hcy ? (double)(r - hcy) - py : 0.0);
                 const double h2 = e2 - gap * gap;
                 const double w = (double)__builtin_amdgcn_sqrtf((float)fmax(h2, 0.0)) + 1e-3;  // hardware sqrt, ~1 ulp: far inside the margin
@@ -319,28 +319,17 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
                 const int64_t rb = (int64_t)(iy0 + r) * Ex;
                 blo = S.cs_in[rb + c0c];
                 bhi = S.cs_in[rb + c1c + 1];
-                wr = w;
             };
             uint32_t nlo = 0, nhi = 0;
-            double nw = 0.0;
-            if (ylo <= yhi) bounds(ylo, nlo, nhi, nw);
+            if (ylo <= yhi) bounds(ylo, nlo, nhi);
             for (int r = ylo; r <= yhi; ++r) {
                 const uint32_t blo = nlo, bhi = nhi;
-                const double wr = nw;
-                if (r < yhi) bounds(r + 1, nlo, nhi, nw);  // next row's loads overlap this row's pairs
+                if (r < yhi) bounds(r + 1, nlo, nhi);  // next row's loads overlap this row's pairs
                 uint32_t lo = ipre[r] + (blo - istart[r]);
                 uint32_t hi = ipre[r] + (bhi - istart[r]);
                 lo = max(lo, c_lo) - c_lo;
                 hi = min(hi, c_hi);
                 hi = hi > c_lo ? hi - c_lo : 0;
-                if (F32 && MODE != MODE_COUNT) {
-                    // trim the whole end cells to |x - hx| <= w: a cell's points are sorted by x,
-                    // and a scan that stops at the first point inside never drops one (any order
-                    // is correct, sorted order makes the trim effective)
-                    const double xl = (hx - wr) * na.inv_eg, xh = (hx + wr) * na.inv_eg;
-                    while (lo < hi && sxy[lo].x < xl) ++lo;
-                    while (hi > lo && sxy[hi - 1].x > xh) --hi;
-                }
                 const double dyc = (double)(hcy - r);  // every staged point of this row is in row r
                 if (MODE == MODE_COUNT) {
                     for (uint32_t jj = lo; jj < hi; ++jj) {
@@ -455,11 +444,13 @@ __global__ void __launch_bounds__(256) k_coincident_count(NearSets S, double *__
 }
 
 // staged points per chunk (a sweep of 768 to 2048 at 2^24 points put the optimum here)
+// Staging capacities (points per LDS chunk): smaller chunks keep more blocks per CU;
+// measured best at a near radius of 5 cells (volume sources at n eps_I = 3.5).
 #ifndef FN_NEAR_CAP_FWD
-#define FN_NEAR_CAP_FWD 1024
+#define FN_NEAR_CAP_FWD 768
 #endif
 #ifndef FN_NEAR_CAP_ADJ
-#define FN_NEAR_CAP_ADJ 768
+#define FN_NEAR_CAP_ADJ 512
 #endif
 constexpr int CAP_FWD = FN_NEAR_CAP_FWD;
 constexpr int CAP_ADJ = FN_NEAR_CAP_ADJ;
