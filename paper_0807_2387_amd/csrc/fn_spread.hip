@@ -194,6 +194,19 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
     const int tx = tile % ntx, ty = tile / ntx;
     const int x0 = tx * TILE, y0 = ty * TILE;
     const int wv = threadIdx.x >> 6;
+    // an empty tile (a sparse point set) only writes its zero partial sums
+    __shared__ int tile_pts;
+    if (threadIdx.x == 0) tile_pts = 0;
+    __syncthreads();
+    if (threadIdx.x < TILE && y0 + (int)threadIdx.x < Ey && x0 < Ex) {
+        const int64_t rb = (int64_t)(y0 + threadIdx.x) * Ex;
+        if (cstart[rb + min(x0 + TILE, Ex)] != cstart[rb + x0]) atomicOr(&tile_pts, 1);
+    }
+    __syncthreads();
+    if (tile_pts == 0) {  // uniform
+        for (int c = threadIdx.x; c < PT2; c += SPREAD_NT) ptile[((int64_t)f * ntiles + tile) * PT2 + c] = 0.0;
+        return;
+    }
     for (int i = threadIdx.x; i < SPREAD_WAVES * PT2; i += SPREAD_NT) acc[i] = 0.0;
     __syncthreads();
     double *myacc = acc + (int64_t)wv * PT2;
