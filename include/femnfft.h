@@ -185,6 +185,15 @@ int fn_eval_H(fn_ctx *ctx, double *H);
 int fn_eval_phi_adjoint(fn_ctx *ctx, const double *v, double *u);
 int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u);
 
+/* fn_eval(ctx, phi, H) and fn_eval_H_adjoint(ctx, V, u) in one call, the two running at
+ * the same time: the adjoint on a second stream the context owns (created on the first
+ * call, default priority, freed by fn_destroy), forked from and joined back into the
+ * context's stream with events, so the call is ordered like the two calls on that stream
+ * (and can be captured into a graph once it has run once).  The forward's near field
+ * (arithmetic-bound) then overlaps the adjoint's FFT passes (latency-bound).  Each
+ * pipeline has its own scratch in the workspace.  Results equal those of the two calls. */
+int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V, double *u);
+
 int fn_get_info(const fn_ctx *ctx, fn_info *info);
 
 /* Stage timing with HIP events recorded on the context's stream around every

@@ -20,7 +20,7 @@ ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: 
 SYMBOLS = (
     "fn_params_default", "fn_params_auto", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
     "fn_set_geometry", "fn_set_geometry_split", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
-    "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_get_info", "fn_last_error",
+    "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_eval_with_H_adjoint", "fn_get_info", "fn_last_error",
     "fn_set_profiling", "fn_get_profile",
     "fn_mesh_create", "fn_mesh_destroy", "fn_mesh_workspace_size", "fn_mesh_set_workspace", "fn_mesh_set",
     "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
@@ -89,6 +89,7 @@ def lib():
         "fn_eval_H": ([P, P], ctypes.c_int),
         "fn_eval_phi_adjoint": ([P, P, P], ctypes.c_int),
         "fn_eval_H_adjoint": ([P, P, P], ctypes.c_int),
+        "fn_eval_with_H_adjoint": ([P, P, P, P, P], ctypes.c_int),
         "fn_get_info": ([P, ctypes.POINTER(Info)], ctypes.c_int),
         "fn_last_error": ([P], ctypes.c_char_p),
         "fn_set_profiling": ([P, ctypes.c_int], ctypes.c_int),

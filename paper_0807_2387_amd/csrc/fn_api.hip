@@ -247,6 +247,11 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
     L.off_spec = take(specb);
     L.off_spec2 = take(specb);
     L.off_far = take((size_t)3 * nmax * 8);
+    L.off_grid_a = take((size_t)3 * ncell * rs);
+    L.off_spec_a = take(specb);
+    L.off_spec2_a = take(specb);
+    L.off_ptile_a = take((size_t)2 * tiles1 * tiles1 * PT * PT * 8);
+    L.off_far_a = take((size_t)nmax * 8);  // the adjoint gathers one field
     L.off_red = take(8192 * 8);  // see the RED_* slots below
     {
         const int64_t nb1 = (L.emax + 15) / 16;  // near-field home blocks per dimension (16 cells)
@@ -292,6 +297,11 @@ static void bind_buffers(fn_ctx *c)
     B.spec = b + L.off_spec;
     B.spec2 = b + L.off_spec2;
     B.far = reinterpret_cast<double *>(b + L.off_far);
+    B.grid_a = b + L.off_grid_a;
+    B.spec_a = b + L.off_spec_a;
+    B.spec2_a = b + L.off_spec2_a;
+    B.ptile_a = reinterpret_cast<double *>(b + L.off_ptile_a);
+    B.far_a = reinterpret_cast<double *>(b + L.off_far_a);
     B.red = reinterpret_cast<double *>(b + L.off_red);
     B.blk_fs = reinterpret_cast<uint32_t *>(b + L.off_blk_fs);
     B.blk_as = reinterpret_cast<uint32_t *>(b + L.off_blk_as);
@@ -355,20 +365,20 @@ static constexpr size_t PROF_MAX = 8192;
 
 static int prof_begin(fn_ctx *c, int st)
 {
-    if (!c->prof_on || stream_capturing(c->stream)) return -1;
+    if (!c->prof_on || stream_capturing(c->cur)) return -1;
     if (c->prof_next >= PROF_MAX) {
         c->prof.dropped++;
         return -1;
     }
     const size_t i = c->prof_next++;
     c->prof_stage[i] = st;
-    hipEventRecord(c->prof_ev[2 * i], c->stream);
+    hipEventRecord(c->prof_ev[2 * i], c->cur);
     return (int)i;
 }
 
 static void prof_end(fn_ctx *c, int i)
 {
-    if (i >= 0) hipEventRecord(c->prof_ev[2 * i + 1], c->stream);
+    if (i >= 0) hipEventRecord(c->prof_ev[2 * i + 1], c->cur);
 }
 
 static int check_device(fn_ctx *c)
@@ -483,8 +493,15 @@ int fn_create(const fn_params *params, void *stream, fn_ctx **out)
 
 int fn_destroy(fn_ctx *ctx)
 {
-    if (ctx)
+    if (ctx) {
         for (auto &e : ctx->prof_ev) hipEventDestroy(e);
+        if (ctx->stream2) {
+            hipStreamSynchronize(ctx->stream2);
+            hipStreamDestroy(ctx->stream2);
+        }
+        if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+        if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+    }
     delete ctx;
     return FN_OK;
 }
@@ -778,6 +795,7 @@ int fn_set_charges(fn_ctx *ctx, const double *q)
     if (c->geom.ns > 0 && !q) FN_SET_ERR(c, FN_E_INVAL, "q is NULL");
     int rc = check_device(c);
     if (rc) return rc;
+    c->cur = c->stream;
     if (c->geom.ns > 0) {
         // per source set: its permutation indexes its own part of q (sets 1 and 2 are
         // consecutive in q, in the sorted weights and in the sorted values)
@@ -796,7 +814,7 @@ int fn_set_charges(fn_ctx *ctx, const double *q)
     return FN_OK;
 }
 
-static int eval_impl(fn_ctx *c, double *phi, double *H)
+static int eval_impl(fn_ctx *c, double *phi, double *H, hipStream_t st)
 {
     if (!c->charges_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_charges must be called before evaluation");
     if (!phi && !H) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
@@ -805,7 +823,7 @@ static int eval_impl(fn_ctx *c, double *phi, double *H)
     const Plan &P = c->plan;
     const Geom &g = c->geom;
     const Buffers &B = c->buf;
-    hipStream_t st = c->stream;
+    c->cur = st;
     if (g.nt == 0) return FN_OK;
     if (g.ns == 0) {
         if (phi) FN_HIP(c, launch_fill(phi, g.nt, 0.0, st));
@@ -851,24 +869,24 @@ static int eval_impl(fn_ctx *c, double *phi, double *H)
 int fn_eval(fn_ctx *ctx, double *phi, double *H)
 {
     if (!ctx) return FN_E_INVAL;
-    return eval_impl(ctx, phi, H);
+    return eval_impl(ctx, phi, H, ctx->stream);
 }
 
 int fn_eval_phi(fn_ctx *ctx, double *phi)
 {
     if (!ctx) return FN_E_INVAL;
     if (!phi) FN_SET_ERR(ctx, FN_E_INVAL, "phi is NULL");
-    return eval_impl(ctx, phi, nullptr);
+    return eval_impl(ctx, phi, nullptr, ctx->stream);
 }
 
 int fn_eval_H(fn_ctx *ctx, double *H)
 {
     if (!ctx) return FN_E_INVAL;
     if (!H) FN_SET_ERR(ctx, FN_E_INVAL, "H is NULL");
-    return eval_impl(ctx, nullptr, H);
+    return eval_impl(ctx, nullptr, H, ctx->stream);
 }
 
-static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
+static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind, hipStream_t st)
 {
     if (!c->geom_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_geometry must succeed before an adjoint evaluation");
     const Plan &P = c->plan;
@@ -876,8 +894,14 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
     if ((g.nt > 0 && !in) || (g.ns > 0 && !u)) FN_SET_ERR(c, FN_E_INVAL, "NULL input or output");
     int rc = check_device(c);
     if (rc) return rc;
-    const Buffers &B = c->buf;
-    hipStream_t st = c->stream;
+    // the adjoint runs on its own far-field scratch
+    Buffers B = c->buf;
+    B.grid = B.grid_a;
+    B.spec = B.spec_a;
+    B.spec2 = B.spec2_a;
+    B.ptile = B.ptile_a;
+    B.far = B.far_a;
+    c->cur = st;
     if (g.ns == 0) return FN_OK;
     if (g.nt == 0) {
         FN_HIP(c, launch_fill(u, g.ns, 0.0, st));
@@ -927,13 +951,45 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind)
 int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u)
 {
     if (!ctx) return FN_E_INVAL;
-    return adjoint_impl(ctx, V, u, 0);
+    return adjoint_impl(ctx, V, u, 0, ctx->stream);
 }
 
 int fn_eval_phi_adjoint(fn_ctx *ctx, const double *v, double *u)
 {
     if (!ctx) return FN_E_INVAL;
-    return adjoint_impl(ctx, v, u, 1);
+    return adjoint_impl(ctx, v, u, 1, ctx->stream);
+}
+
+int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V, double *u)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn_ctx *c = ctx;
+    if (!c->charges_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_charges must be called before evaluation");
+    if (!phi && !H) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
+    if ((c->geom.nt > 0 && !V) || (c->geom.ns > 0 && !u)) FN_SET_ERR(c, FN_E_INVAL, "NULL input or output");
+    int rc = check_device(c);
+    if (rc) return rc;
+    if (!c->stream2) {
+        if (stream_capturing(c->stream))
+            FN_SET_ERR(c, FN_E_STATE, "call fn_eval_with_H_adjoint once before capturing it (it creates its stream)");
+        FN_HIP(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+        FN_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        FN_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    // fork: the adjoint on the second stream after the work already on the context's
+    // stream; the forward on the context's stream; join before anything queued later
+    FN_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+    FN_HIP(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+    rc = adjoint_impl(c, V, u, 0, c->stream2);
+    if (rc == FN_OK) rc = eval_impl(c, phi, H, c->stream);
+    // join even after an error, so that the context's stream never runs ahead of the fork
+    const hipError_t e1 = hipEventRecord(c->ev_join, c->stream2);
+    const hipError_t e2 = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    c->cur = c->stream;
+    if (rc) return rc;
+    FN_HIP(c, e1);
+    FN_HIP(c, e2);
+    return FN_OK;
 }
 
 int fn_get_info(const fn_ctx *ctx, fn_info *info)

@@ -110,6 +110,10 @@ struct Buffers {
     void *spec = nullptr;            // half spectra, cplx<R>, 2 fields x (n/2+1) x ldS
     void *spec2 = nullptr;           // column-pass outputs, cplx<R>, 2 fields
     double *far = nullptr;           // [3][max(nt, ns)] far-field results, sorted order
+    // the adjoint's own far-field scratch (grid, spectra, tile sums, results), so that a
+    // forward and an adjoint evaluation can run at the same time (fn_eval_with_H_adjoint)
+    void *grid_a = nullptr, *spec_a = nullptr, *spec2_a = nullptr;
+    double *ptile_a = nullptr, *far_a = nullptr;
     double *red = nullptr;           // reduction scratch
     uint32_t *blk_fs = nullptr;      // near blocks of the surface class: targets near surface sources
     uint32_t *blk_as = nullptr;      // near blocks of the surface class: blocks holding surface sources
@@ -124,6 +128,7 @@ struct Layout {
     size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_cstart[3];
     size_t off_w, off_val, off_val64, off_aval, off_aval64, off_ptile, off_grid, off_spec, off_spec2, off_far, off_red;
     size_t off_blk_fs, off_blk_as;
+    size_t off_grid_a, off_spec_a, off_spec2_a, off_ptile_a, off_far_a;
     size_t off_skey, off_sval, off_hist;
     int64_t emax = 0;                // bound on the window extent
     int64_t ldS = 0;                 // leading dimension of the spectra
@@ -140,6 +145,9 @@ struct fn_ctx {
     fn::Buffers buf;
     fn::Layout lay;
     hipStream_t stream = nullptr;
+    hipStream_t cur = nullptr;       // stream the pipeline being enqueued runs on (stage events)
+    hipStream_t stream2 = nullptr;   // second stream of fn_eval_with_H_adjoint (created on first use)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     void *ws = nullptr;
     size_t ws_bytes = 0;

@@ -270,3 +270,67 @@ def test_energy_with_surface_radius(torch, fn, precision):
     tol = 1e-10 if precision == "fp64" else 1e-6
     assert abs(float(E) - E0) <= tol * abs(E0)
     assert rel_l2(g.cpu().numpy(), g0) < tol
+
+
+def _close(a, b):
+    # the two pipelines run the same kernels on the same inputs; only the order in which
+    # a tile's LDS sums are added can differ between launches
+    return rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-12
+
+
+@pytest.mark.parametrize("surface", [True, False], ids=["two_class", "one_class"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_forward_and_H_adjoint_equal_the_two_calls(torch, fn, surface, precision):
+    print(f"fused eval + H adjoint surface={surface} {precision}", flush=True)
+    y, x, w, q, ns1 = rounded_square(12000, 61)
+    if not surface:
+        ns1 = len(x)
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    S = fn.Solver(grid=256, m=6, p=6, eps_I=4 / 192, eps_S=9 / 192 if surface else 0.0, n=192, precision=P)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=len(x) - ns1)
+    S.set_charges(dev(torch, q))
+    Vd = dev(torch, np.random.default_rng(62).standard_normal((len(y), 2)))
+    pe, he = S.eval()
+    ue = S.adjoint_H(Vd)
+    for rep in range(2):
+        pf, hf, uf = S.eval_with_H_adjoint(Vd)
+        torch.cuda.synchronize()
+        assert _close(pf, pe) and _close(hf, he) and _close(uf, ue), f"call {rep}"
+    # and against the oracle, as for the separate calls
+    nb = 192
+    Fv, Fs = oracle_split(y, x, w, ns1, fs.Params(G=256, m=6, p=6, eps_I=4 / nb, band=nb),
+                          fs.Params(G=256, m=6, p=6, eps_I=9 / nb, band=nb))
+    phi2, H2, u2, _ = oracle_outputs(Fv, Fs, ns1, q, Vd.cpu().numpy(), np.zeros(len(y)))
+    errs = dict(phi=rel_l2(pf.cpu().numpy(), phi2), H=rel_l2(hf.cpu().numpy(), H2),
+                HT=rel_l2(uf.cpu().numpy(), u2))
+    print(errs, flush=True)
+    assert max(errs.values()) < (1e-10 if precision == "fp64" else 1e-6), errs
+
+
+def test_fused_call_graph_replay_equals_eager(torch, fn):
+    y, x, w, q, ns1 = rounded_square(8000, 71)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        S = fn.Solver(grid=256, m=6, p=6, eps_I=4 / 192, eps_S=9 / 192, n=192, precision=fn.FN_FP32_MIXED)
+        S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=len(x) - ns1)
+        qd, Vd = dev(torch, q), dev(torch, np.random.default_rng(72).standard_normal((len(y), 2)))
+        phi = torch.empty(len(y), dtype=torch.float64, device="cuda")
+        H = torch.empty(len(y), 2, dtype=torch.float64, device="cuda")
+        u = torch.empty(len(x), dtype=torch.float64, device="cuda")
+        S.set_charges(qd)
+        S.eval_with_H_adjoint(Vd, out_phi=phi, out_H=H, out_u=u)
+        g = fn.Graph()
+        with g.capture(st):
+            S.set_charges(qd)
+            S.eval_with_H_adjoint(Vd, out_phi=phi, out_H=H, out_u=u)
+        rng = np.random.default_rng(73)
+        for rep in range(3):
+            qd.copy_(dev(torch, rng.standard_normal(len(x))))
+            Vd.copy_(dev(torch, rng.standard_normal((len(y), 2))))
+            S.set_charges(qd)
+            pe, he = S.eval()
+            ue = S.adjoint_H(Vd)
+            st.synchronize()
+            g.launch(st)
+            st.synchronize()
+            assert _close(phi, pe) and _close(H, he) and _close(u, ue), f"replay {rep}"
