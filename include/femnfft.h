@@ -171,7 +171,8 @@ int fn_set_geometry_split(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int6
 int fn_set_charges(fn_ctx *ctx, const double *q);
 
 /* phi [n_tgt] and/or H [n_tgt][2] at the targets; either pointer may be NULL
- * in fn_eval (not both).  Results in the caller's target order. */
+ * in fn_eval (not both, unless n_tgt is 0: then nothing is written and any
+ * output may be NULL).  Results in the caller's target order. */
 int fn_eval(fn_ctx *ctx, double *phi, double *H);
 int fn_eval_phi(fn_ctx *ctx, double *phi);
 int fn_eval_H(fn_ctx *ctx, double *H);

@@ -817,7 +817,7 @@ int fn_set_charges(fn_ctx *ctx, const double *q)
 static int eval_impl(fn_ctx *c, double *phi, double *H, hipStream_t st)
 {
     if (!c->charges_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_charges must be called before evaluation");
-    if (!phi && !H) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
+    if (!phi && !H && c->geom.nt > 0) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
     int rc = check_device(c);
     if (rc) return rc;
     const Plan &P = c->plan;
@@ -875,14 +875,14 @@ int fn_eval(fn_ctx *ctx, double *phi, double *H)
 int fn_eval_phi(fn_ctx *ctx, double *phi)
 {
     if (!ctx) return FN_E_INVAL;
-    if (!phi) FN_SET_ERR(ctx, FN_E_INVAL, "phi is NULL");
+    if (!phi && ctx->geom.nt > 0) FN_SET_ERR(ctx, FN_E_INVAL, "phi is NULL");
     return eval_impl(ctx, phi, nullptr, ctx->stream);
 }
 
 int fn_eval_H(fn_ctx *ctx, double *H)
 {
     if (!ctx) return FN_E_INVAL;
-    if (!H) FN_SET_ERR(ctx, FN_E_INVAL, "H is NULL");
+    if (!H && ctx->geom.nt > 0) FN_SET_ERR(ctx, FN_E_INVAL, "H is NULL");
     return eval_impl(ctx, nullptr, H, ctx->stream);
 }
 
@@ -965,7 +965,7 @@ int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V,
     if (!ctx) return FN_E_INVAL;
     fn_ctx *c = ctx;
     if (!c->charges_ready) FN_SET_ERR(c, FN_E_STATE, "fn_set_charges must be called before evaluation");
-    if (!phi && !H) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
+    if (!phi && !H && c->geom.nt > 0) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
     if ((c->geom.nt > 0 && !V) || (c->geom.ns > 0 && !u)) FN_SET_ERR(c, FN_E_INVAL, "NULL input or output");
     int rc = check_device(c);
     if (rc) return rc;

@@ -213,10 +213,18 @@ def test_no_sources_and_no_targets(torch, fn):
     S.set_charges(dev(torch, q[:0]))
     phi, H = S.eval()
     assert torch.all(phi == 0) and torch.all(H == 0)
+    phi, H, u = S.eval_with_H_adjoint(dev(torch, np.ones((50, 2))))
+    torch.cuda.synchronize()
+    assert torch.all(phi == 0) and torch.all(H == 0) and u.shape[0] == 0
     S.set_geometry(dev(torch, y[:0]), dev(torch, x), dev(torch, w))
     S.set_charges(dev(torch, q))
     u = S.adjoint_H(dev(torch, np.zeros((0, 2))))
     assert torch.all(u == 0) and u.shape[0] == 60
+    phi, H = S.eval()
+    assert phi.shape[0] == 0 and H.shape[0] == 0
+    phi, H, u = S.eval_with_H_adjoint(dev(torch, np.zeros((0, 2))))
+    torch.cuda.synchronize()
+    assert torch.all(u == 0) and u.shape[0] == 60 and phi.shape[0] == 0
 
 
 def test_single_source_against_closed_form(torch, fn):
