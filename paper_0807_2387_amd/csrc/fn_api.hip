@@ -189,14 +189,16 @@ static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
     return true;
 }
 
-// slots of the 8192-double reduction scratch
+// slots of the 16384-double reduction scratch
 enum {
     RED_COEF = 0,      // T_I coefficients (MAXP)
     RED_CB = 16,       // T_B coefficients (<= 2 MAXP - 1)
     RED_SUMQ = 64,     // sum of s_j (+ 256 partials)
     RED_SUMV = 512,    // sum of v_i (+ 256 partials)
     RED_PART = 1024,   // bounding-box partials (8 x 256)
-    RED_PSI = 4096     // window transform, n/2 + 1 <= 2049 values
+    RED_PSI = 4096,    // window transform, n/2 + 1 <= 3073 values (n <= 3G/4)
+    RED_QPART = 8192,  // block sums of the charges (2 x 1024)
+    RED_VPART = 10240  // block sums of the phi-adjoint input (1024)
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -252,7 +254,7 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
     L.off_spec2_a = take(specb);
     L.off_ptile_a = take((size_t)2 * tiles1 * tiles1 * PT * PT * 8);
     L.off_far_a = take((size_t)nmax * 8);  // the adjoint gathers one field
-    L.off_red = take(8192 * 8);  // see the RED_* slots below
+    L.off_red = take(16384 * 8);  // see the RED_* slots below
     {
         const int64_t nb1 = (L.emax + 15) / 16;  // near-field home blocks per dimension (16 cells)
         L.off_blk_fs = take((size_t)nb1 * nb1 * 4);
@@ -801,14 +803,19 @@ int fn_set_charges(fn_ctx *ctx, const double *q)
         // consecutive in q, in the sorted weights and in the sorted values)
         const Geom &g = c->geom;
         const size_t rs = c->plan.precision == FN_FP64 ? 8 : 4;
+        double *part = c->buf.red + RED_QPART;
+        int np = 0;
         for (int s = 1; s <= 2; ++s) {
             const int64_t n = set_size(g, s), base = set_base(g, s);
             if (n == 0) continue;
+            int nb = 0;
             FN_STAGE(c, FN_ST_CHARGES,
                      launch_set_values(q + base, c->buf.w + base, c->buf.perm[s], n, 1, c->plan.precision,
-                                       static_cast<char *>(c->buf.val) + base * rs, c->buf.val64 + base, c->stream));
+                                       static_cast<char *>(c->buf.val) + base * rs, c->buf.val64 + base, part + np,
+                                       &nb, c->stream));
+            np += nb;
         }
-        FN_STAGE(c, FN_ST_CHARGES, launch_sum(c->buf.val64, c->geom.ns, c->buf.red + RED_SUMQ, c->stream));
+        FN_STAGE(c, FN_ST_CHARGES, launch_sum_partials(part, np, c->buf.red + RED_SUMQ, c->stream));
     }
     c->charges_ready = true;
     return FN_OK;
@@ -916,8 +923,10 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind, hipStr
     // with surface sources the column pass makes one spectrum per class (W_k times the
     // common input), each class gathers from its own grid
     const int ncls = g.nsurf > 0 ? 2 : 1;
-    FN_STAGE(c, FN_ST_A_VALUES, launch_set_values(in, nullptr, B.perm[0], g.nt, nf, prec, B.aval, B.aval64, st));
-    if (kind == 1) FN_STAGE(c, FN_ST_A_VALUES, launch_sum(B.aval64, g.nt, B.red + RED_SUMV, st));
+    int nbv = 0;
+    FN_STAGE(c, FN_ST_A_VALUES, launch_set_values(in, nullptr, B.perm[0], g.nt, nf, prec, B.aval, B.aval64,
+                                                  kind == 1 ? B.red + RED_VPART : nullptr, &nbv, st));
+    if (kind == 1) FN_STAGE(c, FN_ST_A_VALUES, launch_sum_partials(B.red + RED_VPART, nbv, B.red + RED_SUMV, st));
     FN_STAGE(c, FN_ST_A_SPREAD, launch_spread(prec, P, g, 0, B, B.aval, nf, B.ptile, st));
     FN_STAGE(c, FN_ST_A_FOLD, launch_fold(prec, g, P.m, B.ptile, nf, B.grid, fstride, st));
     FN_STAGE(c, FN_ST_A_ROWS_FWD,

@@ -201,8 +201,12 @@ hipError_t launch_fft2d_c2c64(double2 *a, int n, const double2 *tw, hipStream_t 
 hipError_t launch_make_W(const double2 *bl, int n, const double *psihat, int precision, void *W,
                          hipStream_t st);
 // charges / reductions
+// val[c][k] = w_k q[perm_k][c] (ncomp 1 or 2); part (may be NULL): one sum of component 0
+// per block launched, *nblk of them (at most 1024)
 hipError_t launch_set_values(const double *q, const double *w, const uint32_t *perm, int64_t n,
-                             int ncomp, int precision, void *val, double *val64, hipStream_t st);
+                             int ncomp, int precision, void *val, double *val64, double *part, int *nblk,
+                             hipStream_t st);
+hipError_t launch_sum_partials(const double *part, int64_t np, double *red, hipStream_t st);
 hipError_t launch_sum(const double *x, int64_t n, double *red, hipStream_t st);  // red[0] = sum
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 // spread / fold / gather

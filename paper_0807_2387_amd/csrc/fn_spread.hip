@@ -331,19 +331,70 @@ __global__ void __launch_bounds__(256) k_gather(const uint32_t *__restrict__ key
     }
 }
 
-template <typename R>
-__global__ void k_set_values(const double *__restrict__ q, const double *__restrict__ w,
-                             const uint32_t *__restrict__ perm, int64_t n, int ncomp, R *__restrict__ val,
-                             double *__restrict__ val64)
+// Values in binned order: val[c][k] = w_k q[perm_k][c] (w = NULL: 1), in the working
+// precision and in FP64.  Grid-stride, SV_U elements per thread per trip with all
+// their index and value loads issued before the first store (the value loads are
+// gathers through perm); with part != NULL each block also writes the sum of its
+// component-0 values, in a fixed order.  VEC: NC = 2 values of a point read as one
+// 16-byte load (q 16-byte aligned).
+constexpr int SV_NT = 256, SV_U = 4, SV_MAXB = 1024;
+
+template <typename R, int NC, bool VEC>
+__global__ void __launch_bounds__(SV_NT) k_set_values(const double *__restrict__ q, const double *__restrict__ w,
+                                                      const uint32_t *__restrict__ perm, int64_t n,
+                                                      R *__restrict__ val, double *__restrict__ val64,
+                                                      double *__restrict__ part)
 {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int64_t i = perm[k];
-    const double wk = w ? w[k] : 1.0;
-    for (int c = 0; c < ncomp; ++c) {
-        const double v = wk * q[i * ncomp + c];
-        val[c * n + k] = (R)v;
-        val64[c * n + k] = v;
+    const int64_t stride = (int64_t)gridDim.x * SV_NT;
+    double acc = 0.0;
+    for (int64_t k0 = blockIdx.x * (int64_t)SV_NT + threadIdx.x; k0 < n; k0 += SV_U * stride) {
+        uint32_t pi[SV_U];
+        double wk[SV_U], v0[SV_U], v1[SV_U];
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+            const int64_t k = k0 + u * stride;
+            pi[u] = k < n ? perm[k] : 0u;
+            wk[u] = (w && k < n) ? w[k] : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+            v0[u] = v1[u] = 0.0;
+            if (k0 + u * stride < n) {
+                if (NC == 2 && VEC) {
+                    const double2 t = reinterpret_cast<const double2 *>(q)[pi[u]];
+                    v0[u] = t.x;
+                    v1[u] = t.y;
+                } else {
+                    v0[u] = q[(int64_t)pi[u] * NC];
+                    if (NC == 2) v1[u] = q[(int64_t)pi[u] * NC + 1];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SV_U; ++u) {
+            const int64_t k = k0 + u * stride;
+            if (k < n) {
+                const double a = wk[u] * v0[u];
+                val[k] = (R)a;
+                val64[k] = a;
+                acc += a;
+                if (NC == 2) {
+                    const double b = wk[u] * v1[u];
+                    val[n + k] = (R)b;
+                    val64[n + k] = b;
+                }
+            }
+        }
+    }
+    if (part) {
+        __shared__ double sh[SV_NT];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = SV_NT / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
     }
 }
 
@@ -471,15 +522,37 @@ hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, c
                                 : gather_m<float>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
 }
 
-hipError_t launch_set_values(const double *q, const double *w, const uint32_t *perm, int64_t n, int ncomp,
-                             int precision, void *val, double *val64, hipStream_t st)
+template <typename R>
+static void set_values_t(const double *q, const double *w, const uint32_t *perm, int64_t n, int ncomp, R *val,
+                         double *val64, double *part, int nb, hipStream_t st)
 {
-    if (n == 0) return hipSuccess;
-    const int nb = (int)((n + 255) / 256);
-    if (precision == FN_FP64)
-        k_set_values<double><<<nb, 256, 0, st>>>(q, w, perm, n, ncomp, (double *)val, val64);
+    if (ncomp == 1)
+        k_set_values<R, 1, false><<<nb, SV_NT, 0, st>>>(q, w, perm, n, val, val64, part);
+    else if ((reinterpret_cast<uintptr_t>(q) & 15) == 0)
+        k_set_values<R, 2, true><<<nb, SV_NT, 0, st>>>(q, w, perm, n, val, val64, part);
     else
-        k_set_values<float><<<nb, 256, 0, st>>>(q, w, perm, n, ncomp, (float *)val, val64);
+        k_set_values<R, 2, false><<<nb, SV_NT, 0, st>>>(q, w, perm, n, val, val64, part);
+}
+
+hipError_t launch_set_values(const double *q, const double *w, const uint32_t *perm, int64_t n, int ncomp,
+                             int precision, void *val, double *val64, double *part, int *nblk, hipStream_t st)
+{
+    if (nblk) *nblk = 0;
+    if (n == 0) return hipSuccess;
+    if (ncomp != 1 && ncomp != 2) return hipErrorInvalidValue;
+    const int nb = (int)std::min<int64_t>(SV_MAXB, (n + (int64_t)SV_NT * SV_U - 1) / ((int64_t)SV_NT * SV_U));
+    if (precision == FN_FP64)
+        set_values_t<double>(q, w, perm, n, ncomp, (double *)val, val64, part, nb, st);
+    else
+        set_values_t<float>(q, w, perm, n, ncomp, (float *)val, val64, part, nb, st);
+    if (nblk) *nblk = nb;
+    return hipGetLastError();
+}
+
+// red[0] = sum of the np block sums (fixed order)
+hipError_t launch_sum_partials(const double *part, int64_t np, double *red, hipStream_t st)
+{
+    k_sum_partial<<<1, SUMB, 0, st>>>(part, np, red);
     return hipGetLastError();
 }
 
