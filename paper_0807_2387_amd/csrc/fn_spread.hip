@@ -211,15 +211,22 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
     __syncthreads();
     double *myacc = acc + (int64_t)wv * PT2;
     const float *fval = val + (int64_t)f * N;
+    // point range of cell c of the tile (empty outside the grid)
+    auto cell_range = [&](int c, uint32_t &a, uint32_t &b) {
+        const int gx = x0 + c % TILE, gy = y0 + c / TILE;
+        a = b = 0;
+        if (c < TILE * TILE && gx < Ex && gy < Ey) {
+            const int64_t cell = (int64_t)gy * Ex + gx;
+            a = cstart[cell];
+            b = cstart[cell + 1];
+        }
+    };
+    uint32_t n0, n1;
+    cell_range(threadIdx.x, n0, n1);
     for (int c = threadIdx.x; c < TILE * TILE; c += SPREAD_NT) {
         const int lx = c % TILE, ly = c / TILE;
-        const int gx = x0 + lx, gy = y0 + ly;
-        uint32_t s0 = 0, s1 = 0;
-        if (gx < Ex && gy < Ey) {
-            const int64_t cell = (int64_t)gy * Ex + gx;
-            s0 = cstart[cell];
-            s1 = cstart[cell + 1];
-        }
+        const uint32_t s0 = n0, s1 = n1;
+        cell_range(c + SPREAD_NT, n0, n1);  // the next cell's range loads while this one runs
         if (s0 == s1) continue;
         // at most SPREAD_FLUSH points per FP32 register sum, then into the FP64 accumulator
         // (a dense cluster can put thousands of points in one cell)
@@ -308,11 +315,27 @@ __global__ void __launch_bounds__(256) k_gather(const uint32_t *__restrict__ key
         }
     __syncthreads();
     const R rm = (R)m, rb = (R)b, rw = (R)wnorm;
+    // the next target's cell and fractions load while this one is summed
+    int64_t ni = 0;
+    uint32_t nk = 0;
+    R nfx = (R)0, nfy = (R)0;
+    if (threadIdx.x < P) {
+        ni = tile_point(tr, threadIdx.x);
+        nk = key[ni];
+        nfx = frac_of<R>(fr32, fr64, ni);
+        nfy = frac_of<R>(fr32, fr64, N + ni);
+    }
     for (uint32_t k = threadIdx.x; k < P; k += blockDim.x) {
-        const int64_t i = tile_point(tr, k);
-        const uint32_t kk = key[i];
+        const int64_t i = ni;
+        const uint32_t kk = nk;
+        const R fx = nfx, fy = nfy;
+        if (k + blockDim.x < P) {
+            ni = tile_point(tr, k + blockDim.x);
+            nk = key[ni];
+            nfx = frac_of<R>(fr32, fr64, ni);
+            nfy = frac_of<R>(fr32, fr64, N + ni);
+        }
         const int lx = (int)(kk % (uint32_t)Ex) - x0, ly = (int)(kk / (uint32_t)Ex) - y0;
-        const R fx = frac_of<R>(fr32, fr64, i), fy = frac_of<R>(fr32, fr64, N + i);
         R wx[M2], wy[M2];
         taps<R, M2>(wp, fx, rm, rb, rw, wx);
         taps<R, M2>(wp, fy, rm, rb, rw, wy);
