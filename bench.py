@@ -54,7 +54,7 @@ def parse():
                     help="bandwidth n (default 3 grid/4, oversampling 4/3; 0 means grid/2)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and the sampled accuracy check")
-    ap.add_argument("--samples", type=int, default=1024, help="sampled targets/sources for the O1 check")
+    ap.add_argument("--samples", type=int, default=1536, help="sampled targets/sources for the O1 check")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the forward and the H adjoint one after the other on one stream instead of "
                          "at the same time (fn_eval_with_H_adjoint)")
