@@ -190,9 +190,13 @@ int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u);
  * the same time: the adjoint on a second stream the context owns (created on the first
  * call, default priority, freed by fn_destroy), forked from and joined back into the
  * context's stream with events, so the call is ordered like the two calls on that stream
- * (and can be captured into a graph once it has run once).  The forward's near field
- * (arithmetic-bound) then overlaps the adjoint's FFT passes (latency-bound).  Each
- * pipeline has its own scratch in the workspace.  Results equal those of the two calls. */
+ * and can be captured into a graph once it has run once (FN_E_STATE if the first call is
+ * made under capture).  Each direction has its own far-field scratch in the workspace;
+ * one direction's kernels take the CUs the other leaves free.  Arguments as for the two
+ * calls (phi or H may be NULL, not both unless n_tgt is 0; V [n_tgt][2], u [n_src]); the
+ * outputs are written concurrently and must not overlap each other or the inputs.
+ * Results equal those of the two calls up to the order of additions inside a tile's
+ * spread (to ~1e-16 relative). */
 int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V, double *u);
 
 int fn_get_info(const fn_ctx *ctx, fn_info *info);
