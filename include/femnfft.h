@@ -195,8 +195,7 @@ int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u);
  * one direction's kernels take the CUs the other leaves free.  Arguments as for the two
  * calls (phi or H may be NULL, not both unless n_tgt is 0; V [n_tgt][2], u [n_src]); the
  * outputs are written concurrently and must not overlap each other or the inputs.
- * Results equal those of the two calls up to the order of additions inside a tile's
- * spread (to ~1e-16 relative). */
+ * Results equal those of the two calls (every kernel sums in a fixed order). */
 int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V, double *u);
 
 int fn_get_info(const fn_ctx *ctx, fn_info *info);
