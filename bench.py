@@ -11,9 +11,9 @@ Workload (default): rounded square of side 4 (corner radius 1/2), about 2^24
 jittered-lattice targets and 2^24 + 31k sources (cell points with charge
 -div M, boundary Gauss points with M.n), M a unit field whose angle is a sum of
 32 random cosine modes; FP32-mixed path, FFT grid 8192^2, bandwidth n = 6144,
-Kaiser-Bessel m = 6, regularization degree p = 6; the volume sources use the
-near radius eps_I = 3.5/n, the 31k boundary Gauss points (surface sources) their
-own eps_S = 9/n (fn_set_geometry_split).
+Kaiser-Bessel m = 6, regularization degree p = 5; the volume sources use the
+near radius eps_I = 3.25/n, the 31k boundary Gauss points (surface sources) their
+own eps_S = 11/n (fn_set_geometry_split).
 
 Prints ONE JSON line (rank 0).  `value` = (N_src + N_tgt) / (seconds per step).
 """
@@ -45,10 +45,10 @@ def parse():
     ap.add_argument("--n", type=int, default=1 << 24, help="about this many targets (and sources)")
     ap.add_argument("--grid", type=int, default=8192)
     ap.add_argument("--m", type=int, default=6)
-    ap.add_argument("--p", type=int, default=6)
-    ap.add_argument("--c", type=float, default=3.5,
+    ap.add_argument("--p", type=int, default=5)
+    ap.add_argument("--c", type=float, default=3.25,
                     help="eps_I = c / n for the volume sources (all sources when --cs 0)")
-    ap.add_argument("--cs", type=float, default=9.0,
+    ap.add_argument("--cs", type=float, default=11.0,
                     help="surface sources (the boundary Gauss points) get eps_S = cs / n; 0: one class")
     ap.add_argument("--band", type=int, default=None,
                     help="bandwidth n (default 3 grid/4, oversampling 4/3; 0 means grid/2)")
