@@ -981,9 +981,21 @@ int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V,
     if (!c->stream2) {
         if (stream_capturing(c->stream))
             FN_SET_ERR(c, FN_E_STATE, "call fn_eval_with_H_adjoint once before capturing it (it creates its stream)");
-        FN_HIP(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
-        FN_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        FN_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        // all three or none: a failed creation leaves the context as it was
+        hipStream_t s2 = nullptr;
+        hipEvent_t e1 = nullptr, e2 = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&e2, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (e2) hipEventDestroy(e2);
+            if (e1) hipEventDestroy(e1);
+            if (s2) hipStreamDestroy(s2);
+            FN_HIP(c, e);
+        }
+        c->stream2 = s2;
+        c->ev_fork = e1;
+        c->ev_join = e2;
     }
     // fork: the adjoint on the second stream after the work already on the context's
     // stream; the forward on the context's stream; join before anything queued later
