@@ -13,7 +13,8 @@ jittered-lattice targets and 2^24 + 31k sources (cell points with charge
 32 random cosine modes; FP32-mixed path, FFT grid 8192^2, bandwidth n = 6144,
 Kaiser-Bessel m = 6, regularization degree p = 5; the volume sources use the
 near radius eps_I = 3.25/n, the 31k boundary Gauss points (surface sources) their
-own eps_S = 11/n (fn_set_geometry_split).
+own eps_S = 11/n (fn_set_geometry_split); boundary regularization zone eps_B = 1/32
+(the torus map scales the workload to a distance of at most 1/2 - eps_B).
 
 Prints ONE JSON line (rank 0).  `value` = (N_src + N_tgt) / (seconds per step).
 """
@@ -50,6 +51,8 @@ def parse():
                     help="eps_I = c / n for the volume sources (all sources when --cs 0)")
     ap.add_argument("--cs", type=float, default=11.0,
                     help="surface sources (the boundary Gauss points) get eps_S = cs / n; 0: one class")
+    ap.add_argument("--eps-b", type=float, default=1 / 32,
+                    help="width of the boundary regularization zone in torus units (the library's default is 1/16)")
     ap.add_argument("--band", type=int, default=None,
                     help="bandwidth n (default 3 grid/4, oversampling 4/3; 0 means grid/2)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
@@ -104,7 +107,7 @@ def main():
 
     def run(precision, steps, warmup, profile):
         S = fn.Solver(grid=args.grid, m=args.m, p=args.p, eps_I=eps_I, precision=precision, n=args.band,
-                      eps_S=eps_S)
+                      eps_S=eps_S, eps_B=args.eps_b)
         torch.cuda.synchronize()
         g0 = time.perf_counter()
         S.set_geometry(ty, tx, tw, n_surf=n_surf)
@@ -169,6 +172,7 @@ def main():
         "config": {"workload": "rounded square side 4, jittered lattice, 32-mode smooth M",
                    "n_tgt": nt, "n_src": ns, "grid": args.grid, "bandwidth": nband, "m": args.m, "p": args.p,
                    "eps_I": eps_I, "eps_S": eps_S, "n_surf": n_surf, "precision": "fp32_mixed",
+                   "eps_B": args.eps_b,
                    "overlap": not args.no_overlap,
                    "parallelism": "single_gpu"},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},

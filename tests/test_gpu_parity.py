@@ -57,6 +57,8 @@ CASES = [
     # bandwidth 3G/4 (oversampling 4/3): a length-3*2^k plan transform; eps_I = c/n
     ("band_3G4", 20000, 30011, 512, 6, 8, 7.0, 5, 384),
     ("band_3G4_small", 1000, 1531, 128, 6, 4, 4.0, 6, 96),
+    # the bench's regularization: p = 5, a narrower boundary zone eps_B = 1/32
+    ("p5_epsB32", 20000, 30011, 512, 6, 5, 4.0, 7, 384, 1 / 32),
 ]
 
 
@@ -65,12 +67,13 @@ CASES = [
 def test_parity_with_step_by_step_oracle(torch, fn, case, precision):
     name, nt, ns, G, m, p, c, seed = case[:8]
     band = case[8] if len(case) > 8 else 0
+    eps_B = case[9] if len(case) > 9 else 1 / 16
     print(f"case {name} {precision}", flush=True)
     y, x, w, q = synth.random_cloud(nt, ns, seed)
     rng = np.random.default_rng(seed + 100)
     V = rng.standard_normal((nt, 2))
     v = rng.standard_normal(nt)
-    prm = fs.Params(G=G, m=m, p=p, eps_I=c / (band or G // 2), band=band)
+    prm = fs.Params(G=G, m=m, p=p, eps_I=c / (band or G // 2), band=band, eps_B=eps_B)
     F = fs.FastSum(y, x, w, prm)
     phi2, H2 = F.forward(q)
     u2, up2 = F.adjoint_H(V), F.adjoint_phi(v)

@@ -56,11 +56,10 @@ def test_inner_polynomial_matches_log_derivatives(p):
         assert abs(float(dT - dK)) < 1e-10 * max(1.0, abs(float(dK)))
 
 
-@pytest.mark.parametrize("p", [2, 4, 8])
-def test_boundary_polynomial_conditions(p):
+@pytest.mark.parametrize("p,epsB", [(2, 1 / 16), (4, 1 / 16), (8, 1 / 16), (5, 1 / 32), (5, 1 / 48)])
+def test_boundary_polynomial_conditions(p, epsB):
     """In t = (r - r_B)/eps_B: the q-th t-derivative equals eps_B^q K^(q)(r_B) at t = 0 and
     vanishes at t = 1 (q >= 1), relative to the size of the terms summed."""
-    epsB = 1.0 / 16
     c = fs.boundary_coeffs(p, epsB)
     rB = 0.5 - epsB
     mpmath.mp.dps = 40
