@@ -230,7 +230,8 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
         fl = near_flops_per_pair(stage, args.p, f32=True)
         ach = pairs * fl / sec / 1e12
         nb = args.band or G // 2
-        traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1", nb, args.c / nb)
+        traffic = counter_traffic("k_near<0" if stage == "near" else "k_near<1", nb, args.c / nb, args.eps_b,
+                                  args.n)
         return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / FP64_VEC_TFLOPS, "traffic": traffic, "ms_per_launch": ms_per_launch,
                 "pairs_per_launch": pairs, "flops_per_pair": fl}
@@ -257,10 +258,10 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
             "algorithmic_bytes_per_launch": byts}
 
 
-def counter_traffic(kernel_prefix, bandwidth, eps_I):
+def counter_traffic(kernel_prefix, bandwidth, eps_I, eps_B, n_points):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
     the current kernel source (its sha256 prefix is stored with the numbers) and on this
-    workload's bandwidth and near radius."""
+    workload: size, bandwidth, near radius and boundary zone (which sets the points per cell)."""
     path = os.path.join(HERE, "profiles", "counters.json")
     src = os.path.join(HERE, "paper_0807_2387_amd", "csrc", "fn_near.hip")
     try:
@@ -272,6 +273,8 @@ def counter_traffic(kernel_prefix, bandwidth, eps_I):
     if not ent or ent.get("source_sha256_16") != src_hash(src) or ent.get("bandwidth") != bandwidth:
         return None
     if ent.get("eps_I") is None or abs(ent["eps_I"] - eps_I) > 1e-12 * eps_I:
+        return None
+    if ent.get("eps_B") is None or abs(ent["eps_B"] - eps_B) > 1e-12 or ent.get("n_points") != n_points:
         return None
     return ent.get("hbm_bytes_per_launch")
 

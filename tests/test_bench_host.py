@@ -1,0 +1,55 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the stratified sample's
+weights, the near-field flop accounting and the roofline record."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_stratified_sample_weights_sum_to_the_strata():
+    rng = np.random.default_rng(0)
+    mask = rng.random(10000) < 0.03
+    idx, w = bench.stratified_sample(mask, 400, rng)
+    assert np.all(np.diff(idx) > 0)  # sorted, no repeats
+    assert abs(w[mask[idx]].sum() - mask.sum()) < 1e-9
+    assert abs(w[~mask[idx]].sum() - (~mask).sum()) < 1e-9
+    # a weighted mean of any per-point quantity is unbiased: here exact for a constant
+    assert abs(np.dot(w, np.ones(len(idx))) - len(mask)) < 1e-9
+
+
+def test_near_flop_accounting():
+    # forward: offsets 4, r^2 3, x 1, U and U' 2(p-1) + 2(p-2), ln 1, 1/x 1, phi 4, field 3, H 4
+    assert bench.near_flops_per_pair("near", 6) == 39
+    assert bench.near_flops_per_pair("near", 5) == 35
+    # adjoint of H: offsets 4, r^2 3, x 1, U' 2(p-2), 1/x 1, factor 2, V.d 3, sum 2
+    assert bench.near_flops_per_pair("a_near", 5) == 22
+    # FP64 path: ln 38 and 1/x 9 instead of one instruction each
+    assert bench.near_flops_per_pair("near", 5, f32=False) == 35 - 2 + 38 + 9
+
+
+def test_counter_traffic_only_for_the_setting_it_was_taken_on():
+    import json
+    rec = json.load(open(os.path.join(ROOT, "profiles", "counters.json")))
+    ent = rec["kernels"]["k_near<0"]
+    args = (ent["bandwidth"], ent["eps_I"], ent["eps_B"], ent["n_points"])
+    current = ent["source_sha256_16"] == bench.src_hash(
+        os.path.join(ROOT, "paper_0807_2387_amd", "csrc", "fn_near.hip"))
+    # counters taken on another near-field source are not reported
+    assert bench.counter_traffic("k_near<0", *args) == (ent["hbm_bytes_per_launch"] if current else None)
+    assert bench.counter_traffic("k_near<0", args[0], args[1] * 1.1, args[2], args[3]) is None
+    assert bench.counter_traffic("k_near<0", args[0], args[1], args[2] * 2, args[3]) is None
+    assert bench.counter_traffic("k_near<0", args[0], args[1], args[2], args[3] // 2) is None
+    assert bench.counter_traffic("k_near<0", args[0] // 2, args[1], args[2], args[3]) is None
