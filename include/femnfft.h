@@ -186,8 +186,9 @@ int fn_eval_H(fn_ctx *ctx, double *H);
 int fn_eval_phi_adjoint(fn_ctx *ctx, const double *v, double *u);
 int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u);
 
-/* fn_eval(ctx, phi, H) and fn_eval_H_adjoint(ctx, V, u) in one call, the two running at
- * the same time: the adjoint on a second stream the context owns (created on the first
+/* phi of eq. (2) with H = -grad phi at the targets, and the transpose of the H map
+ * applied to V: fn_eval(ctx, phi, H) and fn_eval_H_adjoint(ctx, V, u) in one call, the
+ * two running at the same time (the pair a gradient of the demagnetizing energy needs): the adjoint on a second stream the context owns (created on the first
  * call, default priority, freed by fn_destroy), forked from and joined back into the
  * context's stream with events, so the call is ordered like the two calls on that stream
  * and can be captured into a graph once it has run once (FN_E_STATE if the first call is
