@@ -284,7 +284,9 @@ int fn_bind_mesh(fn_ctx *ctx, fn_mesh *mesh);
  *                                                      -> grad [n_nodes][2] (may be NULL)
  * Needs fn_bind_mesh(ctx, mesh) after the mesh's last fn_mesh_set.  Runs on the
  * context's stream; uses the mesh's scratch (q, H, V, u) and the context's
- * charges (a following fn_eval sees C M). */
+ * charges (a following fn_eval sees C M).  With grad, H and u are computed at once
+ * as in fn_eval_with_H_adjoint (V needs only M), except under graph capture before
+ * that call has created its stream: then one after the other. */
 int fn_energy(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *grad);
 
 /* Message of the last error on this mesh (or of the last failed fn_mesh_create

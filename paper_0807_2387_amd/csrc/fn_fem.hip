@@ -232,8 +232,20 @@ __global__ void k_energy_terms(const double *__restrict__ M, const double *__res
     if (i >= N) return;
     const double mx = M[2 * i], my = M[2 * i + 1];
     e[i] = ell[i] * (mx * H[2 * i] + my * H[2 * i + 1]);
-    V[2 * i] = ell[i] * mx;
-    V[2 * i + 1] = ell[i] * my;
+    if (V) {
+        V[2 * i] = ell[i] * mx;
+        V[2 * i + 1] = ell[i] * my;
+    }
+}
+
+// V_i = l_i M_i alone (the adjoint's input needs M, not H)
+__global__ void k_lumped_V(const double *__restrict__ M, const double *__restrict__ ell, int64_t N,
+                           double *__restrict__ V)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    V[2 * i] = ell[i] * M[2 * i];
+    V[2 * i + 1] = ell[i] * M[2 * i + 1];
 }
 
 __global__ void k_half_neg(const double *__restrict__ sum, double *__restrict__ E)
@@ -545,9 +557,19 @@ int fn_energy(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *gr
     if (rc) return rc;
     rc = fn_set_charges(ctx, b.q);
     if (rc) return rc;
-    rc = fn_eval_H(ctx, b.H);
+    // with the gradient, H and the H adjoint of V = l M run at once (fn_eval_with_H_adjoint),
+    // unless that call would have to create its stream under graph capture
+    const bool fused = grad && (ctx->stream2 || !stream_capturing(st));
+    if (fused) {
+        k_lumped_V<<<nb_of(mesh->N), FB, 0, st>>>(M, b.ell, mesh->N, b.V);
+        rc = ctx_hip(ctx, hipGetLastError());
+        if (rc) return rc;
+        rc = fn_eval_with_H_adjoint(ctx, nullptr, b.H, b.V, b.u);
+    } else {
+        rc = fn_eval_H(ctx, b.H);
+    }
     if (rc) return rc;
-    k_energy_terms<<<nb_of(mesh->N), FB, 0, st>>>(M, b.H, b.ell, mesh->N, b.e, b.V);
+    k_energy_terms<<<nb_of(mesh->N), FB, 0, st>>>(M, b.H, b.ell, mesh->N, b.e, fused ? nullptr : b.V);
     rc = ctx_hip(ctx, hipGetLastError());
     if (rc) return rc;
     rc = ctx_hip(ctx, launch_sum(b.e, mesh->N, b.red, st));
@@ -556,8 +578,10 @@ int fn_energy(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *gr
     rc = ctx_hip(ctx, hipGetLastError());
     if (rc) return rc;
     if (!grad) return FN_OK;
-    rc = fn_eval_H_adjoint(ctx, b.V, b.u);
-    if (rc) return rc;
+    if (!fused) {
+        rc = fn_eval_H_adjoint(ctx, b.V, b.u);
+        if (rc) return rc;
+    }
     k_charges_T<true><<<nb_of(mesh->N), FB, 0, st>>>(b.off, b.slot, mesh->N, mesh->T, mesh->E, b.tg, b.eg, b.u, b.ell,
                                                      b.H, grad);
     return ctx_hip(ctx, hipGetLastError());
