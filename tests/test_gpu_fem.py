@@ -174,3 +174,42 @@ def test_mesh_errors(torch, fn):
     with pytest.raises(fn.FemNfftError) as ei:
         S.energy(dev(torch, M))
     assert ei.value.code == 2
+
+
+def test_energy_under_capture_with_and_without_the_overlapped_stream(torch, fn):
+    """fn_energy with the gradient runs H and the H adjoint at once once the context has
+    its second stream; captured before that, it runs them one after the other.  Both
+    give the eager result."""
+    import ctypes
+    print("energy capture, fresh context then overlapped", flush=True)
+    nodes, tris, bedges, M = annulus(N=3000, seed=6)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        S = fn.Solver(grid=256, m=6, p=6, eps_I=6 / 128, precision=fn.FN_FP32_MIXED)
+        mesh = make_mesh(torch, fn, nodes, tris, bedges)
+        S.bind_mesh(mesh)
+        Md = dev(torch, M)
+        E = torch.empty((), dtype=torch.float64, device="cuda")
+        g = torch.empty(len(nodes), 2, dtype=torch.float64, device="cuda")
+        L = fn._lib.lib()
+        args = (S._ctx, mesh._mesh, ctypes.c_void_p(Md.data_ptr()), ctypes.c_void_p(E.data_ptr()),
+                ctypes.c_void_p(g.data_ptr()))
+        G1 = fn.Graph()
+        with G1.capture(st):
+            assert L.fn_energy(*args) == 0  # no second stream yet: one after the other
+        G1.launch(st)
+        st.synchronize()
+        E1, g1 = E.clone(), g.clone()
+        E2, g2 = S.energy(Md)  # eager: creates the stream, overlapped
+        st.synchronize()
+        rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        assert abs(float(E1) - float(E2)) <= 1e-12 * abs(float(E2)) and rel(g1, g2) < 1e-12
+        G2 = fn.Graph()
+        with G2.capture(st):
+            assert L.fn_energy(*args) == 0  # overlapped, captured across both streams
+        for rep in range(3):
+            E.zero_()
+            g.zero_()
+            G2.launch(st)
+            st.synchronize()
+            assert abs(float(E) - float(E2)) <= 1e-12 * abs(float(E2)) and rel(g, g2) < 1e-12, rep
