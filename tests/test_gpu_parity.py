@@ -331,3 +331,23 @@ def test_paper_tables_claim_on_gpu(torch, fn, shape, precision):
     bound = max(gt.max_printed_gap(gt.load_table("paper_table1_disk.txt")),
                 gt.max_printed_gap(gt.load_table("paper_table2_magic_cylinder.txt")))
     assert abs(rms(phi) - rms(phi1)) <= bound * rms(phi1)
+
+
+def test_adjoint_input_at_an_8_byte_offset(torch, fn):
+    """V [n][2] that is 8- but not 16-byte aligned takes the scalar-load path of the value
+    kernel; the result equals that of an aligned copy."""
+    print("adjoint input alignment", flush=True)
+    y, x, w, q = synth.random_cloud(5000, 7000, 21)
+    V = np.random.default_rng(22).standard_normal((len(y), 2))
+    S = fn.Solver(grid=256, m=6, p=6, eps_I=6 / 128, precision=fn.FN_FP32_MIXED)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
+    S.set_charges(dev(torch, q))
+    Va = dev(torch, V)
+    buf = torch.empty(2 * len(y) + 1, dtype=torch.float64, device="cuda")
+    Vo = buf[1:].view(len(y), 2)
+    Vo.copy_(Va)
+    assert Vo.data_ptr() % 16 == 8 and Va.data_ptr() % 16 == 0
+    ua = S.adjoint_H(Va)
+    uo = S.adjoint_H(Vo)
+    torch.cuda.synchronize()
+    assert torch.equal(ua, uo)
