@@ -261,7 +261,7 @@ hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, 
 // adjoint: source set out_set against the targets; u is that set's part of the output
 hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int kind,
                            const double *sum_v, double *u, const uint32_t *blocks, int nblocks, hipStream_t st);
-// The near field's home blocks (NB x NB cells) of the geometry, and the list of those with
+// The near field's home blocks (NBX x NBY cells) of the geometry, and the list of those with
 // home points of out_set (and, if need_in, points of in_set within R cells): the sparse
 // surface class runs only over these.  *count (device) receives the list length.
 int near_blocks(const Geom &g);

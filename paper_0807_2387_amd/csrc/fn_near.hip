@@ -32,7 +32,7 @@
 // log2 and reciprocal (x rounded to FP32 first): ln x is then off by ~1e-7
 // absolute, (1/4pi) ln x by < 1e-8, and 1/(4pi x) by ~1e-7 of itself.
 //
-// Work decomposition: one workgroup per NB x NB block of "home" cells of the
+// Work decomposition: one workgroup per NBX x NBY block of "home" cells of the
 // output point set; the points of the other set lying in the block's rows and
 // columns widened by rnear cells are staged into LDS in chunks of at most CAP
 // points (coalesced copies), so any point density works.  Each thread owns one
@@ -46,11 +46,22 @@ namespace fn {
 namespace {
 
 constexpr double INV_4PI = 0.07957747154594766788444188168625718;
-constexpr int NB = 16;           // home block edge, cells
-constexpr int NSEG = NB;         // home row segments per block
+// Home blocks are wider than tall: the 64 home points of a wave (cell order) then
+// mostly share one home row, so their row windows have the same vertical gaps and
+// similar trip counts (measured: 16 x 16 -> 32 x 8 cut the forward near field by 7%
+// and the adjoint by 9%, at 2.3 points per cell and a radius of 5 cells).
+#ifndef FN_NEAR_NBX
+#define FN_NEAR_NBX 32
+#endif
+#ifndef FN_NEAR_NBY
+#define FN_NEAR_NBY 8
+#endif
+constexpr int NBX = FN_NEAR_NBX;  // home block width, cells
+constexpr int NBY = FN_NEAR_NBY;  // home block height, cells
+constexpr int NSEG = NBY;         // home row segments per block
 constexpr int NTH = 256;         // threads per block
 constexpr int MAXRN = 32;        // largest near radius in cells
-constexpr int MAXROWS = NB + 2 * MAXRN + 2;
+constexpr int MAXROWS = NBY + 2 * MAXRN + 2;
 
 enum { MODE_FWD_BOTH = 0, MODE_ADJ_H = 1, MODE_ADJ_PHI = 2, MODE_COUNT = 3, MODE_FWD_PHI = 4, MODE_FWD_H = 5 };
 
@@ -222,15 +233,15 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     const int Ex = S.Ex, Ey = S.Ey, R = na.rnear;
     const int bid = S.blocks ? (int)S.blocks[blockIdx.x] : (int)blockIdx.x;
     const int bx = bid % S.nbx, by = bid / S.nbx;
-    const int hx0 = bx * NB, hy0 = by * NB;
-    const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NB + R, Ey);
-    const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NB + R, Ex);
+    const int hx0 = bx * NBX, hy0 = by * NBY;
+    const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NBY + R, Ey);
+    const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NBX + R, Ex);
     const int nirow = iy1 - iy0;
     const int tid = threadIdx.x;
 
     if (tid < NSEG) {  // segment = one row of the home block
         const int y = hy0 + tid;
-        const int x0 = hx0, x1 = min(x0 + NB, Ex);
+        const int x0 = hx0, x1 = min(x0 + NBX, Ex);
         uint32_t s0 = 0, cnt = 0;
         if (y < Ey && x0 < Ex) {
             const int64_t rb = (int64_t)y * Ex;
@@ -443,11 +454,11 @@ __global__ void __launch_bounds__(256) k_coincident_count(NearSets S, double *__
     cnt[gi] = c;
 }
 
-// staged points per chunk (a sweep of 768 to 2048 at 2^24 points put the optimum here)
-// Staging capacities (points per LDS chunk): smaller chunks keep more blocks per CU;
-// measured best at a near radius of 5 cells (volume sources at n eps_I = 3.5).
+// Staging capacities (points per LDS chunk): smaller chunks keep more blocks per CU,
+// larger ones need fewer chunk passes; measured best with 32 x 8 home blocks at a near
+// radius of 5 cells and about 2.3 points per cell.
 #ifndef FN_NEAR_CAP_FWD
-#define FN_NEAR_CAP_FWD 768
+#define FN_NEAR_CAP_FWD 1024
 #endif
 #ifndef FN_NEAR_CAP_ADJ
 #define FN_NEAR_CAP_ADJ 512
@@ -504,7 +515,7 @@ NearSets make_sets(const Geom &g, const Buffers &b, int out_set, int in_set)
     S.pay = out_set ? b.aval64 : b.val64 + set_base(g, in_set);
     S.Ex = g.ext[0];
     S.Ey = g.ext[1];
-    S.nbx = (g.ext[0] + NB - 1) / NB;
+    S.nbx = (g.ext[0] + NBX - 1) / NBX;
     S.accum = 0;
     S.blocks = nullptr;
     return S;
@@ -524,14 +535,14 @@ __global__ void k_block_list(NearSets S, int nblk, int R, int need_in, uint32_t 
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblk) return;
     const int bx = b % S.nbx, by = b / S.nbx;
-    const int hx0 = bx * NB, hy0 = by * NB;
-    const int hx1 = min(hx0 + NB, S.Ex), hy1 = min(hy0 + NB, S.Ey);
+    const int hx0 = bx * NBX, hy0 = by * NBY;
+    const int hx1 = min(hx0 + NBX, S.Ex), hy1 = min(hy0 + NBY, S.Ey);
     uint32_t home = 0;
     for (int y = hy0; y < hy1; ++y) home += S.cs_out[(int64_t)y * S.Ex + hx1] - S.cs_out[(int64_t)y * S.Ex + hx0];
     if (home == 0) return;
     if (need_in) {
-        const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NB + R, S.Ey);
-        const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NB + R, S.Ex);
+        const int iy0 = max(hy0 - R, 0), iy1 = min(hy0 + NBY + R, S.Ey);
+        const int ix0 = max(hx0 - R, 0), ix1 = min(hx0 + NBX + R, S.Ex);
         uint32_t in = 0;
         for (int y = iy0; y < iy1; ++y) in += S.cs_in[(int64_t)y * S.Ex + ix1] - S.cs_in[(int64_t)y * S.Ex + ix0];
         if (in == 0) return;
@@ -579,7 +590,7 @@ hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, 
     return hipGetLastError();
 }
 
-int near_blocks(const Geom &g) { return ((g.ext[0] + NB - 1) / NB) * ((g.ext[1] + NB - 1) / NB); }
+int near_blocks(const Geom &g) { return ((g.ext[0] + NBX - 1) / NBX) * ((g.ext[1] + NBY - 1) / NBY); }
 
 hipError_t launch_block_list(const Geom &g, const Buffers &b, int out_set, int in_set, int R, int need_in,
                              uint32_t *list, uint32_t *count, hipStream_t st)
