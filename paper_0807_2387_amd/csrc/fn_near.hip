@@ -49,7 +49,7 @@ constexpr double INV_4PI = 0.07957747154594766788444188168625718;
 // Home blocks are wider than tall: the 64 home points of a wave (cell order) then
 // mostly share one home row, so their row windows have the same vertical gaps and
 // similar trip counts (measured: 16 x 16 -> 32 x 8 cut the forward near field by 7%
-// and the adjoint by 9%, at 2.3 points per cell and a radius of 5 cells).
+// and the adjoint by 9%, at 2.0 points per cell and a radius of 5 cells).
 #ifndef FN_NEAR_NBX
 #define FN_NEAR_NBX 32
 #endif
@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(256) k_coincident_count(NearSets S, double *__
 
 // Staging capacities (points per LDS chunk): smaller chunks keep more blocks per CU,
 // larger ones need fewer chunk passes; measured best with 32 x 8 home blocks at a near
-// radius of 5 cells and about 2.3 points per cell.
+// radius of 5 cells and about 2.0 points per cell.
 #ifndef FN_NEAR_CAP_FWD
 #define FN_NEAR_CAP_FWD 1024
 #endif
