@@ -479,6 +479,7 @@ int fn_create(const fn_params *params, void *stream, fn_ctx **out)
     if (!c) { g_create_err = "out of host memory"; return FN_E_NOMEM; }
     c->prm = *params;
     c->stream = static_cast<hipStream_t>(stream);
+    c->cur = c->stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         g_create_err = "no HIP device";
