@@ -317,6 +317,14 @@ int fn_set_geometry_batch_split(fn_batch *batch, const int64_t *tgt_off, const d
 int fn_batch_set_charges(fn_batch *batch, const double *q);
 int fn_batch_eval(fn_batch *batch, double *phi, double *H);        /* either may be NULL, not both */
 int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u);
+/* fn_batch_eval(batch, phi, H) and fn_batch_eval_H_adjoint(batch, V, u) in one call, as
+ * fn_eval_with_H_adjoint does for one context (phi and H = -grad phi of eq. (2), and the
+ * transpose of the H map): every member's adjoint on a second stream the batch owns
+ * (created on the first call, default priority, freed by fn_batch_destroy), its forward
+ * on the batch stream, with one fork and one join for the whole batch.  Capturable once
+ * it has run once (FN_E_STATE if the first call is made under capture); outputs must not
+ * overlap each other or the inputs; results equal those of the two calls. */
+int fn_batch_eval_with_H_adjoint(fn_batch *batch, double *phi, double *H, const double *V, double *u);
 int fn_batch_eval_phi_adjoint(fn_batch *batch, const double *v, double *u);
 int fn_batch_member(fn_batch *batch, int32_t i, fn_ctx **out);    /* borrow member i's context */
 const char *fn_batch_last_error(const fn_batch *batch);

@@ -344,6 +344,17 @@ class Batch:
         self._check(_lib.lib().fn_batch_eval_H_adjoint(self._b, _dev_ptr(V, "V", (2,)), _dev_ptr(u, "u")))
         return u
 
+    def eval_with_H_adjoint(self, V, out_phi=None, out_H=None, out_u=None):
+        """phi, H = eval() and u = adjoint_H(V) in one call that runs the two at once on
+        two streams (fn_batch_eval_with_H_adjoint); returns (phi, H, u)."""
+        torch = _torch()
+        p = out_phi if out_phi is not None else torch.empty(self.n_tgt, dtype=torch.float64, device=self.device)
+        h = out_H if out_H is not None else torch.empty(self.n_tgt, 2, dtype=torch.float64, device=self.device)
+        u = out_u if out_u is not None else torch.empty(self.n_src, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_batch_eval_with_H_adjoint(self._b, _dev_ptr(p, "phi"), _dev_ptr(h, "H", (2,)),
+                                                            _dev_ptr(V, "V", (2,)), _dev_ptr(u, "u")))
+        return p, h, u
+
     def adjoint_phi(self, v, out=None):
         torch = _torch()
         u = out if out is not None else torch.empty(self.n_src, dtype=torch.float64, device=self.device)

@@ -26,7 +26,7 @@ SYMBOLS = (
     "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
     "fn_energy", "fn_mesh_last_error",
     "fn_batch_create", "fn_batch_destroy", "fn_batch_workspace_size", "fn_batch_set_workspace",
-    "fn_set_geometry_batch", "fn_set_geometry_batch_split", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint",
+    "fn_set_geometry_batch", "fn_set_geometry_batch_split", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint", "fn_batch_eval_with_H_adjoint",
     "fn_batch_eval_phi_adjoint", "fn_batch_member", "fn_batch_last_error",
     "fn_graph_begin", "fn_graph_end", "fn_graph_launch", "fn_graph_destroy", "fn_graph_last_error",
 )
@@ -116,6 +116,7 @@ def lib():
         "fn_batch_set_charges": ([P, P], ctypes.c_int),
         "fn_batch_eval": ([P, P, P], ctypes.c_int),
         "fn_batch_eval_H_adjoint": ([P, P, P], ctypes.c_int),
+        "fn_batch_eval_with_H_adjoint": ([P, P, P, P, P], ctypes.c_int),
         "fn_batch_eval_phi_adjoint": ([P, P, P], ctypes.c_int),
         "fn_batch_member": ([P, I32, ctypes.POINTER(P)], ctypes.c_int),
         "fn_batch_last_error": ([P], ctypes.c_char_p),

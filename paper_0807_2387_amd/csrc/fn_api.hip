@@ -958,6 +958,20 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind, hipStr
     return FN_OK;
 }
 
+int fn_internal_eval_on_stream(fn_ctx *c, double *phi, double *H, hipStream_t st)
+{
+    const int rc = eval_impl(c, phi, H, st);
+    c->cur = c->stream;
+    return rc;
+}
+
+int fn_internal_adjoint_H_on_stream(fn_ctx *c, const double *V, double *u, hipStream_t st)
+{
+    const int rc = adjoint_impl(c, V, u, 0, st);
+    c->cur = c->stream;
+    return rc;
+}
+
 int fn_eval_H_adjoint(fn_ctx *ctx, const double *V, double *u)
 {
     if (!ctx) return FN_E_INVAL;

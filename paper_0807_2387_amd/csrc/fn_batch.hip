@@ -17,6 +17,8 @@
 
 struct fn_batch {
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;  // second stream of fn_batch_eval_with_H_adjoint (created on first use)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<fn_ctx *> ctx;
     std::vector<int64_t> toff, soff;  // host copies of the offsets of the last geometry
     std::vector<size_t> wsoff;        // workspace offset of each member
@@ -95,8 +97,15 @@ int fn_batch_create(int32_t count, const fn_params *params, void *stream, fn_bat
 
 int fn_batch_destroy(fn_batch *batch)
 {
-    if (batch)
+    if (batch) {
         for (fn_ctx *c : batch->ctx) fn_destroy(c);
+        if (batch->stream2) {
+            hipStreamSynchronize(batch->stream2);
+            hipStreamDestroy(batch->stream2);
+        }
+        if (batch->ev_fork) hipEventDestroy(batch->ev_fork);
+        if (batch->ev_join) hipEventDestroy(batch->ev_join);
+    }
     delete batch;
     return FN_OK;
 }
@@ -194,6 +203,56 @@ static int batch_adjoint(fn_batch *batch, const double *in, int comps, double *u
 }
 
 int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u) { return batch_adjoint(batch, V, 2, u, true); }
+
+int fn_batch_eval_with_H_adjoint(fn_batch *batch, double *phi, double *H, const double *V, double *u)
+{
+    if (!batch) return FN_E_INVAL;
+    if (!batch->geom_ready) BATCH_ERR(batch, FN_E_STATE, "fn_set_geometry_batch must succeed first");
+    if (!batch->stream2) {
+        if (stream_capturing(batch->stream))
+            BATCH_ERR(batch, FN_E_STATE, "call fn_batch_eval_with_H_adjoint once before capturing it (it creates its stream)");
+        hipStream_t s2 = nullptr;
+        hipEvent_t e1 = nullptr, e2 = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&e2, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (e2) hipEventDestroy(e2);
+            if (e1) hipEventDestroy(e1);
+            if (s2) hipStreamDestroy(s2);
+            BATCH_ERR(batch, FN_E_DEVICE, std::string("creating the second stream: ") + hipGetErrorString(e));
+        }
+        batch->stream2 = s2;
+        batch->ev_fork = e1;
+        batch->ev_join = e2;
+    }
+    // one fork for the whole batch: every member's adjoint on the second stream, its
+    // forward on the batch stream, one join at the end
+    hipError_t e = hipEventRecord(batch->ev_fork, batch->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(batch->stream2, batch->ev_fork, 0);
+    if (e != hipSuccess) BATCH_ERR(batch, FN_E_DEVICE, std::string("fork: ") + hipGetErrorString(e));
+    int rc = FN_OK;
+    for (size_t i = 0; i < batch->ctx.size() && rc == FN_OK; ++i) {
+        const int64_t nt = batch->toff[i + 1] - batch->toff[i], ns = batch->soff[i + 1] - batch->soff[i];
+        if (ns > 0) {
+            rc = fn_internal_adjoint_H_on_stream(batch->ctx[i], V ? V + 2 * batch->toff[i] : nullptr,
+                                                 u ? u + batch->soff[i] : nullptr, batch->stream2);
+            if (rc) rc = member_err(batch, (int)i, rc);
+        }
+        if (rc == FN_OK && nt > 0) {
+            rc = fn_internal_eval_on_stream(batch->ctx[i], phi ? phi + batch->toff[i] : nullptr,
+                                            H ? H + 2 * batch->toff[i] : nullptr, batch->stream);
+            if (rc) rc = member_err(batch, (int)i, rc);
+        }
+    }
+    // join even after an error, so that the batch stream never runs ahead of the fork
+    const hipError_t e1 = hipEventRecord(batch->ev_join, batch->stream2);
+    const hipError_t e2 = hipStreamWaitEvent(batch->stream, batch->ev_join, 0);
+    if (rc) return rc;
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        BATCH_ERR(batch, FN_E_DEVICE, std::string("join: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return FN_OK;
+}
 
 int fn_batch_eval_phi_adjoint(fn_batch *batch, const double *v, double *u)
 {

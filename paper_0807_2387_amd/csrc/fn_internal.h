@@ -169,6 +169,16 @@ struct fn_ctx {
 // FN_OK, or FN_E_DEVICE with the HIP message stored in ctx->err
 int ctx_hip(fn_ctx *ctx, hipError_t e);
 
+// fn_eval / fn_eval_H_adjoint with their work enqueued on `st` (which must be ordered
+// after the context's stream by the caller; the two directions use separate scratch).
+// Library-internal (hidden from the shared object's exports).
+extern "C" {
+__attribute__((visibility("hidden"))) int fn_internal_eval_on_stream(fn_ctx *c, double *phi, double *H,
+                                                                     hipStream_t st);
+__attribute__((visibility("hidden"))) int fn_internal_adjoint_H_on_stream(fn_ctx *c, const double *V, double *u,
+                                                                          hipStream_t st);
+}
+
 // true while work issued on `st` is being captured into a graph
 inline bool stream_capturing(hipStream_t st)
 {

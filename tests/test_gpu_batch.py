@@ -175,3 +175,32 @@ def test_c3_batch_of_64_meshes_vs_direct_sum(torch, fn):
            for k, e, r in (("phi", e_phi, r_phi), ("H", e_H, r_H), ("HT", e_u, r_u))}
     print("C3 vs O1 (64 targets and sources sampled per mesh):", err, flush=True)
     assert max(err.values()) < 5e-7  # measured about 2.3e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_overlapped_call_equals_the_two_calls(torch, fn, precision):
+    """fn_batch_eval_with_H_adjoint (all members' adjoints on the batch's second stream,
+    their forwards on the batch stream) gives the results of fn_batch_eval and
+    fn_batch_eval_H_adjoint, on two calls in a row."""
+    print(f"batch overlapped call {precision}", flush=True)
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    ys, xs, ws, qs, Vs, prms = [], [], [], [], [], []
+    for nt, ns, G, p, c, seed in member_clouds():
+        y, x, w, q = synth.random_cloud(nt, ns, seed, neutral=ns > 1)
+        ys.append(y), xs.append(x), ws.append(w), qs.append(q)
+        Vs.append(np.random.default_rng(seed + 9).standard_normal((nt, 2)))
+        prms.append(fs.Params(G=G, m=6, p=p, eps_I=c / (G // 2)))
+    toff, Y = concat(ys)
+    soff, X = concat(xs)
+    W, Q, V = np.concatenate(ws), np.concatenate(qs), np.concatenate(Vs)
+    B = fn.Batch([dict(grid=pr.G, m=pr.m, p=pr.p, eps_I=pr.eps_I, precision=P) for pr in prms])
+    B.set_geometry(toff, dev(torch, Y), soff, dev(torch, X), dev(torch, W))
+    B.set_charges(dev(torch, Q))
+    Vd = dev(torch, V)
+    pe, he = B.eval()
+    ue = B.adjoint_H(Vd)
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    for rep in range(2):
+        pf, hf, uf = B.eval_with_H_adjoint(Vd)
+        torch.cuda.synchronize()
+        assert rel(pf, pe) < 1e-12 and rel(hf, he) < 1e-12 and rel(uf, ue) < 1e-12, rep
