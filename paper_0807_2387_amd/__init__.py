@@ -9,6 +9,10 @@ memory and the current stream) into the C calls.
     s.set_charges(q)
     phi, H = s.eval()
     u = s.adjoint_H(V)                                       # u_j = w_j sum_i V_i.(-grad G)(r_i - r_j)
+    phi, H, u = s.eval_with_H_adjoint(V)                     # both at once, on two streams
+
+    s = Solver(grid=8192, m=6, p=5, eps_I=3.25/6144, eps_S=11/6144, eps_B=1/32, n=6144)
+    s.set_geometry(tgt_xy, src_xy, src_w, n_surf=k)          # last k sources: surface charges at eps_S
 
     mesh = Mesh(nodes, tris, bedges)                         # P1 triangle mesh (float64 / int32 tensors)
     s.bind_mesh(mesh)                                        # targets = nodes, sources = quadrature points
