@@ -49,13 +49,27 @@ and the DFT sign.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
+from scipy import fft as sfft
 from scipy import sparse, special
 from scipy.spatial import cKDTree
 
 TWO_PI = 2.0 * np.pi
+
+# The 2D FFTs are scipy's (the same pocketfft transform as numpy's) with worker threads:
+# a G = 8192 transform then takes a fraction of a second instead of seconds.
+_WORKERS = max(1, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
+
+
+def fft2(a):
+    return sfft.fft2(a, workers=_WORKERS)
+
+
+def ifft2(a):
+    return sfft.ifft2(a, workers=_WORKERS)
 
 
 @dataclass
@@ -152,7 +166,7 @@ def b_coeffs(prm: Params):
     j = np.fft.fftfreq(n) * n
     J1, J2 = np.meshgrid(j, j, indexing="ij")
     samples = K_R(np.hypot(J1, J2) / n, prm)
-    return np.fft.fft2(samples).real / (n * n)
+    return fft2(samples).real / (n * n)
 
 
 # ----------------------------------------------------------------------------
@@ -216,16 +230,22 @@ def window_matrix(pt, prm: Params):
 
 
 def multiplier(prm: Params, b=None):
-    """W_l (G x G, FFT order) and the integer frequencies l1, l2."""
+    """W_l (G x G, FFT order) and the integer frequencies l1 [G, 1], l2 [1, G] (they
+    broadcast to the G x G grid of l = (l1, l2)).  Every factor but b_l depends on one
+    component of l only, so it is evaluated once per component value and the two
+    factors multiplied per element."""
     G, n, m = prm.G, prm.n, prm.m
     if b is None:
         b = b_coeffs(prm)
     l = np.rint(np.fft.fftfreq(G) * G).astype(np.int64)
-    L1, L2 = np.meshgrid(l, l, indexing="ij")
-    band = (np.abs(L1) <= n // 2) & (np.abs(L2) <= n // 2)
-    om = np.where(np.abs(L1) == n // 2, 0.5, 1.0) * np.where(np.abs(L2) == n // 2, 0.5, 1.0)
+    L1, L2 = l[:, None], l[None, :]
+    inband = np.abs(l) <= n // 2
+    band = inband[:, None] & inband[None, :]
+    om1 = np.where(np.abs(l) == n // 2, 0.5, 1.0)
+    om = om1[:, None] * om1[None, :]
     bl = b[np.mod(L1, n), np.mod(L2, n)]
-    ph = kb_psi_hat(L1 / G, m, prm.kb_b) * kb_psi_hat(L2 / G, m, prm.kb_b)
+    ph1 = kb_psi_hat(l / G, m, prm.kb_b)
+    ph = ph1[:, None] * ph1[None, :]
     W = np.where(band, om * bl / (ph * ph), 0.0)
     return W, L1, L2
 
@@ -285,10 +305,10 @@ class FastSum:
 
     def _back(self, spec):
         G = self.prm.G
-        return (np.fft.ifft2(spec) * (G * G)).real.ravel()
+        return (ifft2(spec) * (G * G)).real.ravel()
 
     def far_forward(self, s_src):
-        gh = np.fft.fft2(self._grid(self.Bx, s_src))
+        gh = fft2(self._grid(self.Bx, s_src))
         W = self.W
         phi = self.By.T @ self._back(W * gh)
         hx = self.By.T @ self._back(-1j * TWO_PI * self.L1 * W * gh)
@@ -313,8 +333,8 @@ class FastSum:
         """u_j = w_j sum_i V_i . (-grad G)(y_i - x_j), the transpose of forward()'s H map."""
         V = np.asarray(V, np.float64)
         W = self.W
-        vx = np.fft.fft2(self._grid(self.By, V[:, 0]))
-        vy = np.fft.fft2(self._grid(self.By, V[:, 1]))
+        vx = fft2(self._grid(self.By, V[:, 0]))
+        vy = fft2(self._grid(self.By, V[:, 1]))
         spec = 1j * TWO_PI * (self.L1 * W * vx + self.L2 * W * vy)
         u = self.Bx.T @ self._back(spec)
         kf = np.where(self.zero, 0.0, self.kf)
@@ -325,7 +345,7 @@ class FastSum:
     def adjoint_phi(self, v):
         """u_j = w_j sum_i v_i G(y_i - x_j), the transpose of forward()'s phi map."""
         v = np.asarray(v, np.float64)
-        spec = self.W * np.fft.fft2(self._grid(self.By, v))
+        spec = self.W * fft2(self._grid(self.By, v))
         u = self.Bx.T @ self._back(spec)
         kphi = np.where(self.zero, -(self.a[0] + np.log(self.s) / TWO_PI), self.kphi)
         u = u + np.bincount(self.nj, weights=v[self.ni] * kphi, minlength=len(self.x))

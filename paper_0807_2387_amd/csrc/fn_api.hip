@@ -32,7 +32,7 @@ void twiddles(int N, std::vector<double> &re, std::vector<double> &im)
     re.resize(N);
     im.resize(N);
     for (int k = 0; k < N; ++k) {
-        // reduce to the first octant for accuracy: angle = -2 pi k / N
+        // angle -2 pi k / N in long double, rounded to double once
         long double a = -2.0L * (long double)PI * (long double)k / (long double)N;
         re[k] = (double)std::cos(a);
         im[k] = (double)std::sin(a);
@@ -181,6 +181,20 @@ static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
             }
         }
     }
+    {
+        std::vector<double> re, im;
+        twiddles(P.G, re, im);
+        if (P.precision == FN_FP64) {
+            P.twG64.resize(2 * (size_t)P.G);
+            for (int k = 0; k < P.G; ++k) P.twG64[2 * k] = re[k], P.twG64[2 * k + 1] = im[k];
+        } else {
+            P.twG32.resize(2 * (size_t)P.G);
+            for (int k = 0; k < P.G; ++k) P.twG32[2 * k] = (float)re[k], P.twG32[2 * k + 1] = (float)im[k];
+        }
+        twiddles(P.n, re, im);
+        P.twn.resize(2 * (size_t)P.n);
+        for (int k = 0; k < P.n; ++k) P.twn[2 * k] = re[k], P.twn[2 * k + 1] = im[k];
+    }
     P.psihat.resize(P.n / 2 + 1);
     for (int l = 0; l <= P.n / 2; ++l) {
         const double w = 2.0 * PI * l / P.G;
@@ -255,11 +269,9 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
     L.off_ptile_a = take((size_t)2 * tiles1 * tiles1 * PT * PT * 8);
     L.off_far_a = take((size_t)nmax * 8);  // the adjoint gathers one field
     L.off_red = take(16384 * 8);  // see the RED_* slots below
-    {
-        const int64_t nb1 = (L.emax + 15) / 16;  // near-field home blocks per dimension (16 cells)
-        L.off_blk_fs = take((size_t)nb1 * nb1 * 4);
-        L.off_blk_as = take((size_t)nb1 * nb1 * 4);
-    }
+    L.nblk_cap = near_blocks_bound(L.emax);  // near-field home blocks of the largest window
+    L.off_blk_fs = take((size_t)L.nblk_cap * 4);
+    L.off_blk_as = take((size_t)L.nblk_cap * 4);
     L.off_skey = take(nmax * 4);
     L.off_sval = take(nmax * 4);
     const int64_t nblk = (nmax + 4095) / 4096;
@@ -535,27 +547,12 @@ static int build_device_plan(fn_ctx *c)
     const Plan &P = c->plan;
     Buffers &B = c->buf;
     hipStream_t st = c->stream;
-    // twiddles
-    std::vector<double> re, im;
-    twiddles(P.G, re, im);
-    if (P.precision == FN_FP64) {
-        std::vector<double2> t(P.G);
-        for (int k = 0; k < P.G; ++k) t[k] = make_double2(re[k], im[k]);
-        FN_HIP(c, hipMemcpyAsync(B.tw, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-        FN_HIP(c, hipStreamSynchronize(st));
-    } else {
-        std::vector<float2> t(P.G);
-        for (int k = 0; k < P.G; ++k) t[k] = make_float2((float)re[k], (float)im[k]);
-        FN_HIP(c, hipMemcpyAsync(B.tw, t.data(), t.size() * sizeof(float2), hipMemcpyHostToDevice, st));
-        FN_HIP(c, hipStreamSynchronize(st));
-    }
-    twiddles(P.n, re, im);
-    {
-        std::vector<double2> t(P.n);
-        for (int k = 0; k < P.n; ++k) t[k] = make_double2(re[k], im[k]);
-        FN_HIP(c, hipMemcpyAsync(B.tw64, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-        FN_HIP(c, hipStreamSynchronize(st));
-    }
+    // twiddles (tabulated at fn_create)
+    if (P.precision == FN_FP64)
+        FN_HIP(c, hipMemcpyAsync(B.tw, P.twG64.data(), P.twG64.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    else
+        FN_HIP(c, hipMemcpyAsync(B.tw, P.twG32.data(), P.twG32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    FN_HIP(c, hipMemcpyAsync(B.tw64, P.twn.data(), P.twn.size() * sizeof(double), hipMemcpyHostToDevice, st));
     double *dcoef = c->buf.red + RED_COEF;
     double *dcB = c->buf.red + RED_CB;
     double *dpsi = c->buf.red + RED_PSI;
@@ -617,8 +614,8 @@ static int bbox_of(fn_ctx *c, const double *xy, int64_t n, double out[4], double
     double *part = c->buf.red + RED_PART;  // 8 * 256 doubles
     FN_HIP(c, launch_bbox(xy, n, part, nblk, c->stream));
     FN_HIP(c, launch_nonfinite(xy, 2 * n, part + 4 * 256, nblk, c->stream));
-    std::vector<double> h(8 * 256);
-    FN_HIP(c, hipMemcpyAsync(h.data(), part, sizeof(double) * 8 * 256, hipMemcpyDeviceToHost, c->stream));
+    double h[8 * 256];
+    FN_HIP(c, hipMemcpyAsync(h, part, sizeof(double) * 8 * 256, hipMemcpyDeviceToHost, c->stream));
     FN_HIP(c, hipStreamSynchronize(c->stream));
     for (int b = 0; b < nblk; ++b) {
         out[0] = std::min(out[0], h[4 * b]);
@@ -636,8 +633,8 @@ static int maxdist_of(fn_ctx *c, const double *xy, int64_t n, double cx, double 
     const int nblk = (int)std::min<int64_t>(256, (n + 255) / 256);
     double *part = c->buf.red + RED_PART;
     FN_HIP(c, launch_maxdist(xy, n, cx, cy, part, nblk, c->stream));
-    std::vector<double> h(4 * 256);
-    FN_HIP(c, hipMemcpyAsync(h.data(), part, sizeof(double) * 4 * nblk, hipMemcpyDeviceToHost, c->stream));
+    double h[4 * 256];
+    FN_HIP(c, hipMemcpyAsync(h, part, sizeof(double) * 4 * nblk, hipMemcpyDeviceToHost, c->stream));
     FN_HIP(c, hipStreamSynchronize(c->stream));
     for (int b = 0; b < nblk; ++b) *m2 = std::max(*m2, h[4 * b]);
     return FN_OK;
@@ -684,8 +681,8 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
         (void)dummy;
         const int nblk = (int)std::min<int64_t>(256, (n_src + 255) / 256);
         FN_HIP(c, launch_nonfinite(src_w, n_src, c->buf.red + RED_PART, nblk, c->stream));
-        std::vector<double> h(4 * 256);
-        FN_HIP(c, hipMemcpyAsync(h.data(), c->buf.red + RED_PART, sizeof(double) * 4 * nblk, hipMemcpyDeviceToHost,
+        double h[4 * 256];
+        FN_HIP(c, hipMemcpyAsync(h, c->buf.red + RED_PART, sizeof(double) * 4 * nblk, hipMemcpyDeviceToHost,
                                  c->stream));
         FN_HIP(c, hipStreamSynchronize(c->stream));
         for (int b = 0; b < nblk; ++b) wn += h[4 * b];
@@ -742,10 +739,15 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
     if (nsets == 3) {  // the sparse surface class: list the near blocks it needs
         uint32_t cnt[2] = {0, 0};
         uint32_t *dcnt = reinterpret_cast<uint32_t *>(B.red + RED_PART);
-        FN_HIP(c, launch_block_list(c->geom, B, 0, 2, g.rnear_s, 1, B.blk_fs, dcnt, c->stream));
-        FN_HIP(c, launch_block_list(c->geom, B, 2, 0, g.rnear_s, 0, B.blk_as, dcnt + 1, c->stream));
+        const uint32_t cap = (uint32_t)L.nblk_cap;
+        FN_HIP(c, launch_block_list(c->geom, B, 0, 2, g.rnear_s, 1, B.blk_fs, cap, dcnt, c->stream));
+        FN_HIP(c, launch_block_list(c->geom, B, 2, 0, g.rnear_s, 0, B.blk_as, cap, dcnt + 1, c->stream));
         FN_HIP(c, hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
         FN_HIP(c, hipStreamSynchronize(c->stream));
+        if (cnt[0] > cap || cnt[1] > cap) {
+            c->geom_ready = false;
+            FN_SET_ERR(c, FN_E_DEVICE, "internal: near-field block list exceeds its capacity");
+        }
         c->geom.nblk_fs = (int32_t)cnt[0];
         c->geom.nblk_as = (int32_t)cnt[1];
     }

@@ -208,6 +208,19 @@ int fn_batch_eval_with_H_adjoint(fn_batch *batch, double *phi, double *H, const 
 {
     if (!batch) return FN_E_INVAL;
     if (!batch->geom_ready) BATCH_ERR(batch, FN_E_STATE, "fn_set_geometry_batch must succeed first");
+    // every argument is checked before anything is enqueued, so that an error leaves the
+    // outputs untouched
+    {
+        const size_t B = batch->ctx.size();
+        const int64_t nt = batch->toff[B] - batch->toff[0], ns = batch->soff[B] - batch->soff[0];
+        for (size_t i = 0; i < B; ++i)
+            if (!batch->ctx[i]->charges_ready) {
+                batch->err = "member " + std::to_string(i) + ": fn_batch_set_charges must be called before evaluation";
+                return FN_E_STATE;
+            }
+        if (nt > 0 && !phi && !H) BATCH_ERR(batch, FN_E_INVAL, "both outputs are NULL");
+        if ((nt > 0 && !V) || (ns > 0 && !u)) BATCH_ERR(batch, FN_E_INVAL, "NULL input or output");
+    }
     if (!batch->stream2) {
         if (stream_capturing(batch->stream))
             BATCH_ERR(batch, FN_E_STATE, "call fn_batch_eval_with_H_adjoint once before capturing it (it creates its stream)");

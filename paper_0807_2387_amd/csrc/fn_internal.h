@@ -58,6 +58,11 @@ struct Plan {
     double aS[MAXP] = {0};           // the same at eps_S (surface sources)
     std::vector<double> cB;          // boundary polynomial in t = (r - r_B)/eps_B
     std::vector<double> psihat;      // window transform at l/G, l = 0..n/2
+    // FFT twiddles e^{-2 pi i k/N} computed at fn_create: length G in the grid precision
+    // (float2 or double2 pairs as consecutive values) and length n in FP64 (plan transform)
+    std::vector<double> twG64;       // [G][2], FP64 path
+    std::vector<float> twG32;        // [G][2], FP32-mixed path
+    std::vector<double> twn;         // [n][2]
 };
 
 // Per-geometry facts (host copy).
@@ -131,6 +136,7 @@ struct Layout {
     size_t off_grid_a, off_spec_a, off_spec2_a, off_ptile_a, off_far_a;
     size_t off_skey, off_sval, off_hist;
     int64_t emax = 0;                // bound on the window extent
+    int64_t nblk_cap = 0;            // capacity of the near-field block lists
     int64_t ldS = 0;                 // leading dimension of the spectra
 };
 
@@ -274,9 +280,12 @@ hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, 
 // The near field's home blocks (NBX x NBY cells) of the geometry, and the list of those with
 // home points of out_set (and, if need_in, points of in_set within R cells): the sparse
 // surface class runs only over these.  *count (device) receives the list length.
+// near_blocks_bound(emax): the block count of any window of at most emax x emax cells (the
+// capacity of the lists).  Entries beyond cap are counted in *count but not written.
 int near_blocks(const Geom &g);
+int64_t near_blocks_bound(int64_t emax);
 hipError_t launch_block_list(const Geom &g, const Buffers &b, int out_set, int in_set, int R, int need_in,
-                             uint32_t *list, uint32_t *count, hipStream_t st);
+                             uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t st);
 hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int in_set,
                                   double *out, hipStream_t st);
 hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, double *cnt, hipStream_t st);

@@ -529,7 +529,7 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v)
 // Home blocks with work: home points in the block and, if need_in, points of the
 // input set within R cells of it.  One thread per block; the list order depends on
 // the atomics, the blocks' results do not.
-__global__ void k_block_list(NearSets S, int nblk, int R, int need_in, uint32_t *__restrict__ list,
+__global__ void k_block_list(NearSets S, int nblk, int R, int need_in, uint32_t cap, uint32_t *__restrict__ list,
                              uint32_t *__restrict__ count)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -547,7 +547,8 @@ __global__ void k_block_list(NearSets S, int nblk, int R, int need_in, uint32_t 
         for (int y = iy0; y < iy1; ++y) in += S.cs_in[(int64_t)y * S.Ex + ix1] - S.cs_in[(int64_t)y * S.Ex + ix0];
         if (in == 0) return;
     }
-    list[atomicAdd(count, 1u)] = (uint32_t)b;
+    const uint32_t slot = atomicAdd(count, 1u);
+    if (slot < cap) list[slot] = (uint32_t)b;  // a count above cap is reported by the host
 }
 
 template <int P>
@@ -592,13 +593,15 @@ hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, 
 
 int near_blocks(const Geom &g) { return ((g.ext[0] + NBX - 1) / NBX) * ((g.ext[1] + NBY - 1) / NBY); }
 
+int64_t near_blocks_bound(int64_t emax) { return ((emax + NBX - 1) / NBX) * ((emax + NBY - 1) / NBY); }
+
 hipError_t launch_block_list(const Geom &g, const Buffers &b, int out_set, int in_set, int R, int need_in,
-                             uint32_t *list, uint32_t *count, hipStream_t st)
+                             uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t st)
 {
     const int nblk = near_blocks(g);
     const NearSets S = make_sets(g, b, out_set, in_set);
     k_fill_u32<<<1, 1, 0, st>>>(count, 0u);
-    k_block_list<<<(nblk + 255) / 256, 256, 0, st>>>(S, nblk, R, need_in, list, count);
+    k_block_list<<<(nblk + 255) / 256, 256, 0, st>>>(S, nblk, R, need_in, cap, list, count);
     return hipGetLastError();
 }
 

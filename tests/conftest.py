@@ -21,6 +21,23 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def max_rel(a, b):
+    """max_i |a_i - b_i| / max_i |b_i| (element by element, scaled by the largest value)."""
+    import numpy as np
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def parity_err(a, b):
+    """Error figure of a parity check: max(relative L2, per-element error / 10).
+
+    `parity_err(a, b) < tol` holds when ||a - b||_2 / ||b||_2 < tol AND every element
+    satisfies |a_i - b_i| < 10 tol max_j |b_j|, so a fault confined to a few tiles, FFT
+    lines or near blocks cannot hide under the norm of millions of correct values."""
+    return max(rel_l2(a, b), 0.1 * max_rel(a, b))
+
+
 @pytest.fixture(scope="session")
 def o1():
     from oracle import direct

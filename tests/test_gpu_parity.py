@@ -14,7 +14,7 @@ import pytest
 import synth
 from oracle import direct, fem
 from oracle import fastsum as fs
-from tests.conftest import rel_l2
+from tests.conftest import parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -80,7 +80,7 @@ def test_parity_with_step_by_step_oracle(torch, fn, case, precision):
     P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
     phi, H, u, up, _ = run_gpu(torch, fn, y, x, w, q, V, v, prm, P)
     tol = 1e-10 if precision == "fp64" else 1e-6
-    errs = dict(phi=rel_l2(phi, phi2), H=rel_l2(H, H2), HT=rel_l2(u, u2), phiT=rel_l2(up, up2))
+    errs = dict(phi=parity_err(phi, phi2), H=parity_err(H, H2), HT=parity_err(u, u2), phiT=parity_err(up, up2))
     print(errs, flush=True)
     assert max(errs.values()) < tol, errs
 
@@ -103,8 +103,8 @@ def test_disk_c1_fp64(torch, fn):
     F = fs.FastSum(y, x, w, prm)
     phi2, H2 = F.forward(q)
     phi, H, u, up, _ = run_gpu(torch, fn, y, x, w, q, V, v, prm, fn.FN_FP64)
-    assert rel_l2(phi, phi2) < 1e-10 and rel_l2(H, H2) < 1e-10
-    assert rel_l2(u, F.adjoint_H(V)) < 1e-10 and rel_l2(up, F.adjoint_phi(v)) < 1e-10
+    assert parity_err(phi, phi2) < 1e-10 and parity_err(H, H2) < 1e-10
+    assert parity_err(u, F.adjoint_H(V)) < 1e-10 and parity_err(up, F.adjoint_phi(v)) < 1e-10
     phi1, H1 = direct.forward(y, x, w, q)
     # at these pinned parameters the fast method's error stays below the discretization error
     # (closed form phi = x/2); the ratio is printed for the record
@@ -137,7 +137,7 @@ def test_ellipse_c2(torch, fn, precision):
     if precision == "fp64":
         F = fs.FastSum(y, x, w, prm)
         phi2, H2 = F.forward(q)
-        e2 = dict(phi=rel_l2(phi, phi2), H=rel_l2(H, H2), HT=rel_l2(u, F.adjoint_H(V)))
+        e2 = dict(phi=parity_err(phi, phi2), H=parity_err(H, H2), HT=parity_err(u, F.adjoint_H(V)))
         print("vs O2", e2, flush=True)
         assert max(e2.values()) < 1e-10, e2
 
@@ -182,8 +182,8 @@ def test_targets_equal_sources(torch, fn):
     F = fs.FastSum(y, x, w, prm)
     phi2, H2 = F.forward(q)
     phi, H, u, up, _ = run_gpu(torch, fn, y, x, w, q, V, v, prm, fn.FN_FP64)
-    assert rel_l2(phi, phi2) < 1e-10 and rel_l2(H, H2) < 1e-10
-    assert rel_l2(u, F.adjoint_H(V)) < 1e-10 and rel_l2(up, F.adjoint_phi(v)) < 1e-10
+    assert parity_err(phi, phi2) < 1e-10 and parity_err(H, H2) < 1e-10
+    assert parity_err(u, F.adjoint_H(V)) < 1e-10 and parity_err(up, F.adjoint_phi(v)) < 1e-10
     phi1, H1 = direct.forward(y, x, w, q)
     assert rel_l2(phi, phi1) < 1e-5 and rel_l2(H, H1) < 1e-4
 
@@ -204,8 +204,8 @@ def test_dense_cluster_exercises_near_field_chunking(torch, fn):
     phi2, H2 = F.forward(q)
     for P, tol in ((fn.FN_FP64, 1e-10), (fn.FN_FP32_MIXED, 1e-6)):
         phi, H, u, up, _ = run_gpu(torch, fn, y, x, w, q, V, v, prm, P)
-        e = dict(phi=rel_l2(phi, phi2), H=rel_l2(H, H2), HT=rel_l2(u, F.adjoint_H(V)),
-                 phiT=rel_l2(up, F.adjoint_phi(v)))
+        e = dict(phi=parity_err(phi, phi2), H=parity_err(H, H2), HT=parity_err(u, F.adjoint_H(V)),
+                 phiT=parity_err(up, F.adjoint_phi(v)))
         assert max(e.values()) < tol, (P, e)
 
 

@@ -12,7 +12,7 @@ import pytest
 import synth
 from oracle import direct, fem
 from oracle import fastsum as fs
-from tests.conftest import rel_l2
+from tests.conftest import parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -112,7 +112,7 @@ def test_split_matches_per_class_oracle(torch, fn, case, precision):
     phi2, H2, u2, up2 = oracle_outputs(Fv, Fs, ns1, q, V, v)
     P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
     phi, H, u, up, S = run_split(torch, fn, y, x, w, q, V, v, ns1, G, band, m, p, cv / nb, cs / nb, P)
-    errs = dict(phi=rel_l2(phi, phi2), H=rel_l2(H, H2), HT=rel_l2(u, u2), phiT=rel_l2(up, up2))
+    errs = dict(phi=parity_err(phi, phi2), H=parity_err(H, H2), HT=parity_err(u, u2), phiT=parity_err(up, up2))
     print(errs, flush=True)
     assert max(errs.values()) < (1e-10 if precision == "fp64" else 1e-6), errs
     info = S.info()
@@ -139,7 +139,7 @@ def test_no_surface_sources_is_the_one_class_sum(torch, fn):
             S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=n_surf)
         S.set_charges(dev(torch, q))
         phi, H = S.eval()
-        assert rel_l2(phi.cpu().numpy(), phi2) < 1e-10 and rel_l2(H.cpu().numpy(), H2) < 1e-10
+        assert parity_err(phi.cpu().numpy(), phi2) < 1e-10 and parity_err(H.cpu().numpy(), H2) < 1e-10
         assert S.info()["n_surf"] == 0
 
 
@@ -152,7 +152,7 @@ def test_surface_radius_ignored_without_eps_S(torch, fn):
     S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w), n_surf=len(x) - ns1)
     S.set_charges(dev(torch, q))
     phi, H = S.eval()
-    assert rel_l2(phi.cpu().numpy(), phi2) < 1e-10 and rel_l2(H.cpu().numpy(), H2) < 1e-10
+    assert parity_err(phi.cpu().numpy(), phi2) < 1e-10 and parity_err(H.cpu().numpy(), H2) < 1e-10
     assert S.info()["n_surf"] == 0
 
 
@@ -171,7 +171,7 @@ def test_coincident_points_in_both_classes(torch, fn, precision):
     P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
     phi, H, u, up, _ = run_split(torch, fn, y, x, w, q, V, v, ns1, G, 0, 6, 6, 4 / 64, 7 / 64, P)
     tol = 1e-10 if precision == "fp64" else 1e-6
-    errs = dict(phi=rel_l2(phi, phi2), H=rel_l2(H, H2), HT=rel_l2(u, u2), phiT=rel_l2(up, up2))
+    errs = dict(phi=parity_err(phi, phi2), H=parity_err(H, H2), HT=parity_err(u, u2), phiT=parity_err(up, up2))
     assert max(errs.values()) < tol, errs
     # and against the exact sum, where the coincident pairs are left out
     phi1, _ = direct.forward(y, x, w, q)
@@ -238,7 +238,7 @@ def test_batch_members_with_surface_sources(torch, fn, precision):
         v0 = np.zeros(len(ys[i]))
         phi2, H2, u2, _ = oracle_outputs(Fv, Fs, ns1, qs[i], Vs[i], v0)
         t, s = slice(toff[i], toff[i + 1]), slice(soff[i], soff[i + 1])
-        errs = dict(phi=rel_l2(phi[t], phi2), H=rel_l2(H[t], H2), HT=rel_l2(u[s], u2))
+        errs = dict(phi=parity_err(phi[t], phi2), H=parity_err(H[t], H2), HT=parity_err(u[s], u2))
         print(i, errs, flush=True)
         assert max(errs.values()) < tol, (i, errs)
 
@@ -269,13 +269,13 @@ def test_energy_with_surface_radius(torch, fn, precision):
     E, g = S.energy(dev(torch, M))
     tol = 1e-10 if precision == "fp64" else 1e-6
     assert abs(float(E) - E0) <= tol * abs(E0)
-    assert rel_l2(g.cpu().numpy(), g0) < tol
+    assert parity_err(g.cpu().numpy(), g0) < tol
 
 
 def _close(a, b):
     # the two pipelines run the same kernels on the same inputs, each summing in a fixed
     # order: the results agree to rounding at most (bitwise in practice)
-    return rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-12
+    return parity_err(a.cpu().numpy(), b.cpu().numpy()) < 1e-12
 
 
 @pytest.mark.parametrize("surface", [True, False], ids=["two_class", "one_class"])
@@ -301,8 +301,8 @@ def test_fused_forward_and_H_adjoint_equal_the_two_calls(torch, fn, surface, pre
     Fv, Fs = oracle_split(y, x, w, ns1, fs.Params(G=256, m=6, p=6, eps_I=4 / nb, band=nb),
                           fs.Params(G=256, m=6, p=6, eps_I=9 / nb, band=nb))
     phi2, H2, u2, _ = oracle_outputs(Fv, Fs, ns1, q, Vd.cpu().numpy(), np.zeros(len(y)))
-    errs = dict(phi=rel_l2(pf.cpu().numpy(), phi2), H=rel_l2(hf.cpu().numpy(), H2),
-                HT=rel_l2(uf.cpu().numpy(), u2))
+    errs = dict(phi=parity_err(pf.cpu().numpy(), phi2), H=parity_err(hf.cpu().numpy(), H2),
+                HT=parity_err(uf.cpu().numpy(), u2))
     print(errs, flush=True)
     assert max(errs.values()) < (1e-10 if precision == "fp64" else 1e-6), errs
 
