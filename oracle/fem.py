@@ -20,9 +20,28 @@ The energy E = -1/2 sum_i l_i M_i.H_i uses the lumped nodal mass
 l_i = sum_{T containing i} |T|/3 (the physical demagnetizing energy, mu0 = 1);
 its exact gradient for H = A C M is -1/2 (L H + C^T A^T L M).
 
+Outputs at the quadrature points (the charge form of the same energy): with the
+potential of eq. (2) taken at the quadrature points themselves, a point's own
+charge left out (the pair at distance 0 is not part of the sum, like any
+coincident pair),
+    phi_j = sum_{k != j} s_k G(r_j - r_k),   s = w q,
+the energy of the charges in their own potential is E_q = 1/2 sum_j s_j phi_j
+(= 1/2 int rho phi + 1/2 oint sigma phi with both integrals by the same
+quadrature: the physical energy of the definitions given with eq. (1), mu0 = 1).
+The matrix [G(r_j - r_k)]_{j != k} is symmetric, so dE_q/dq = w phi and
+dE_q/dM = C^T (w phi): one potential evaluation gives the energy and its gradient.
+
+FEM-consistent field: the P1 interpolant of the nodal potential has the constant
+gradient sum_k phi_{i_k} grad(lambda_k) on each triangle (lambda_k its hat
+functions), so H_T = -that; its lumped projection onto the nodes is
+H_i = (1/l_i) sum_{T containing i} (|T|/3) H_T.
+
 Pins: charge neutrality (divergence theorem), closed-form potentials of
 uniformly magnetized polygons/disks/ellipses and of the magic cylinder,
-adjoint identity of C and C^T, finite differences of E -- tests/test_oracle_fem.py.
+adjoint identity of C and C^T, finite differences of E (tests/test_oracle_direct.py);
+the charge-form energy against the disk and ellipse energies, its exact central
+difference, the P1 gradient on linear potentials and on the ellipse's uniform
+interior field, the own-charge exclusion by hand (tests/test_oracle_charge_form.py).
 """
 from __future__ import annotations
 
@@ -109,3 +128,38 @@ def energy(M, H, ell):
 def energy_grad(H, ell, CtATLM):
     """dE/dM = -1/2 (l H + C^T A^T (l M)); the caller supplies C^T A^T (l M)."""
     return -0.5 * (ell[:, None] * H + CtATLM)
+
+
+def phi_at_sources(x, w, q):
+    """phi_j = sum_{k != j} w_k q_k G(r_j - r_k) at the quadrature points, by the plain
+    direct sum (oracle O1 with targets = sources: a pair at distance 0 is skipped, so
+    each point's own charge is left out)."""
+    from . import direct
+    phi, _ = direct.forward(np.asarray(x, np.float64), x, w, q, want_H=False)
+    return phi
+
+
+def charge_energy(w, q, phi_s):
+    """E_q = 1/2 sum_j w_j q_j phi_j (phi_j from phi_at_sources)."""
+    return 0.5 * float(np.dot(np.asarray(w) * np.asarray(q), phi_s))
+
+
+def charge_energy_grad(nodes, tris, bedges, w, phi_s):
+    """dE_q/dM = C^T (w phi): the potential matrix between distinct points is symmetric."""
+    return charges_T(nodes, tris, bedges, np.asarray(w) * np.asarray(phi_s))
+
+
+def p1_gradient(nodes, tris, phi):
+    """H_T = -grad of the P1 interpolant of the nodal potential phi [N], per triangle [T, 2]."""
+    _, _, grads = _tri_geom(nodes, tris)
+    return -sum(phi[tris[:, k]][:, None] * grads[k] for k in range(3))
+
+
+def p1_gradient_nodal(nodes, tris, phi):
+    """Lumped projection of p1_gradient onto the nodes: H_i = (1/l_i) sum_{T at i} (|T|/3) H_T."""
+    _, area, _ = _tri_geom(nodes, tris)
+    HT = p1_gradient(nodes, tris, phi)
+    out = np.zeros((len(nodes), 2))
+    for k in range(3):
+        np.add.at(out, tris[:, k], (area / 3.0)[:, None] * HT)
+    return out / lumped_mass(nodes, tris)[:, None]
