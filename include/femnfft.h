@@ -201,6 +201,27 @@ int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V,
 
 int fn_get_info(const fn_ctx *ctx, fn_info *info);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fn_set_geometry_split + fn_set_charges + fn_eval
+ * in one call whose workspace is a library-owned static device buffer of
+ * FN_NOALLOC_SCRATCH_BYTES (64 MiB) per device, held from the library's load until the
+ * process ends, instead of the context's own workspace.  The call allocates nothing
+ * (no hipMalloc, no torch allocation); the caller passes the inputs and outputs as for
+ * those calls (device pointers; the last n_surf sources are surface sources).  Problems
+ * whose fn_workspace_size exceeds FN_NOALLOC_SCRATCH_BYTES are rejected with FN_E_NOMEM
+ * before anything is read or launched.  The context only lends its parameters and stream:
+ * its own workspace, geometry and charges are as before the call (fn_set_workspace is not
+ * needed).  Like fn_set_geometry it waits for the device (it reads back the bounding box),
+ * so it cannot itself be captured.  Every call on one device shares the buffer and keeps
+ * the previous call's contents (the plan tables are reused when the parameters match;
+ * everything else is rewritten before it is read): calls on one device are serialized on
+ * the host, but their kernels race if they run at once on different streams, so a caller
+ * must order calls made on different streams itself.  Results equal those of the three
+ * calls on a context with its own workspace. */
+#define FN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fn_eval_noalloc(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_src, const double *src_xy,
+                    const double *src_w, int64_t n_surf, const double *q, double *phi, double *H);
+
 /* Stage timing with HIP events recorded on the context's stream around every
  * kernel stage of fn_set_charges / fn_eval* / fn_eval_*_adjoint.
  * fn_set_profiling(ctx, 1) starts recording (and clears the totals);

@@ -165,6 +165,19 @@ class Solver:
                                                       _dev_ptr(V, "V", (2,)), _dev_ptr(u, "u")))
         return p, h, u
 
+    def eval_noalloc(self, tgt_xy, src_xy, src_w, q, out_phi, out_H, n_surf=0):
+        """fn_eval_noalloc: geometry + charges + eval on the library's static scratch (no
+        device allocation; the outputs are the caller's tensors).  The context's own
+        workspace and state are untouched."""
+        nt, ns = int(tgt_xy.shape[0]), int(src_xy.shape[0])
+        self._check(_lib.lib().fn_eval_noalloc(
+            self._ctx, nt, _dev_ptr(tgt_xy, "tgt_xy", (2,)) if nt else None, ns,
+            _dev_ptr(src_xy, "src_xy", (2,)) if ns else None, _dev_ptr(src_w, "src_w") if ns else None,
+            int(n_surf), _dev_ptr(q, "q") if ns else None,
+            _dev_ptr(out_phi, "phi") if out_phi is not None else None,
+            _dev_ptr(out_H, "H", (2,)) if out_H is not None else None))
+        return out_phi, out_H
+
     def adjoint_phi(self, v, out=None):
         torch = _torch()
         u = out if out is not None else torch.empty(self.n_src, dtype=torch.float64, device=self.device)
@@ -358,6 +371,19 @@ class Batch:
         self._check(_lib.lib().fn_batch_eval_with_H_adjoint(self._b, _dev_ptr(p, "phi"), _dev_ptr(h, "H", (2,)),
                                                             _dev_ptr(V, "V", (2,)), _dev_ptr(u, "u")))
         return p, h, u
+
+    def eval_noalloc(self, tgt_xy, src_xy, src_w, q, out_phi, out_H, n_surf=0):
+        """fn_eval_noalloc: geometry + charges + eval on the library's static scratch (no
+        device allocation; the outputs are the caller's tensors).  The context's own
+        workspace and state are untouched."""
+        nt, ns = int(tgt_xy.shape[0]), int(src_xy.shape[0])
+        self._check(_lib.lib().fn_eval_noalloc(
+            self._ctx, nt, _dev_ptr(tgt_xy, "tgt_xy", (2,)) if nt else None, ns,
+            _dev_ptr(src_xy, "src_xy", (2,)) if ns else None, _dev_ptr(src_w, "src_w") if ns else None,
+            int(n_surf), _dev_ptr(q, "q") if ns else None,
+            _dev_ptr(out_phi, "phi") if out_phi is not None else None,
+            _dev_ptr(out_H, "H", (2,)) if out_H is not None else None))
+        return out_phi, out_H
 
     def adjoint_phi(self, v, out=None):
         torch = _torch()

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libfemnfft.so")
 
 FN_OK, FN_E_INVAL, FN_E_STATE, FN_E_DOMAIN, FN_E_NOMEM, FN_E_DEVICE, FN_E_UNSUPPORTED = range(7)
 FN_FP64, FN_FP32_MIXED = 0, 1
+FN_NOALLOC_SCRATCH_BYTES = 64 << 20  # static scratch of fn_eval_noalloc per device
 ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: "FN_E_NOMEM",
              5: "FN_E_DEVICE", 6: "FN_E_UNSUPPORTED"}
 
@@ -20,7 +21,8 @@ ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: 
 SYMBOLS = (
     "fn_params_default", "fn_params_auto", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
     "fn_set_geometry", "fn_set_geometry_split", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
-    "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_eval_with_H_adjoint", "fn_get_info", "fn_last_error",
+    "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_eval_with_H_adjoint", "fn_eval_noalloc", "fn_get_info",
+    "fn_last_error",
     "fn_set_profiling", "fn_get_profile",
     "fn_mesh_create", "fn_mesh_destroy", "fn_mesh_workspace_size", "fn_mesh_set_workspace", "fn_mesh_set",
     "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
@@ -90,6 +92,7 @@ def lib():
         "fn_eval_phi_adjoint": ([P, P, P], ctypes.c_int),
         "fn_eval_H_adjoint": ([P, P, P], ctypes.c_int),
         "fn_eval_with_H_adjoint": ([P, P, P, P, P], ctypes.c_int),
+        "fn_eval_noalloc": ([P, I64, P, I64, P, P, I64, P, P, P], ctypes.c_int),
         "fn_get_info": ([P, ctypes.POINTER(Info)], ctypes.c_int),
         "fn_last_error": ([P], ctypes.c_char_p),
         "fn_set_profiling": ([P, ctypes.c_int], ctypes.c_int),

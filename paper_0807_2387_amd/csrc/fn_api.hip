@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 namespace fn {
@@ -1093,3 +1094,97 @@ const char *fn_last_error(const fn_ctx *ctx)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// No-allocation evaluation: the workspace of fn_eval_noalloc is this library-owned
+// device array (one copy per device, alive until the process ends).  Host code never
+// passes the array's name to a kernel or a copy: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+
+static __device__ __align__(256) unsigned char scratch[FN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEV];          // device address of `scratch` per device
+bool g_noalloc_plan_ok[NOALLOC_MAX_DEV];       // the array holds the plan tables of g_noalloc_prm
+fn_params g_noalloc_prm[NOALLOC_MAX_DEV];
+
+// the device address of the scratch array on device dev (current), looked up once
+int noalloc_scratch(fn_ctx *c, int dev, void **ptr)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) FN_SET_ERR(c, FN_E_UNSUPPORTED, "device index beyond the no-allocation table");
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            c->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return FN_E_DEVICE;
+        }
+        g_noalloc_ptr[dev] = p;
+    }
+    *ptr = g_noalloc_ptr[dev];
+    return FN_OK;
+}
+
+}  // namespace
+
+extern "C" int fn_eval_noalloc(fn_ctx *ctx, int64_t n_tgt, const double *tgt_xy, int64_t n_src, const double *src_xy,
+                               const double *src_w, int64_t n_surf, const double *q, double *phi, double *H)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn_ctx *c = ctx;
+    // sizes first: nothing is read, written or launched for a problem beyond the maximum
+    if (n_tgt < 0 || n_src < 0 || n_tgt + n_src < 1 || n_tgt > (int64_t)UINT32_MAX / 2 ||
+        n_src > (int64_t)UINT32_MAX / 2)
+        FN_SET_ERR(c, FN_E_INVAL, "need n_tgt, n_src >= 0, n_tgt + n_src >= 1, both < 2^31");
+    const size_t need = make_layout(c->plan, n_tgt, n_src).total;
+    if (need > (size_t)FN_NOALLOC_SCRATCH_BYTES) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "fn_eval_noalloc: this problem needs %zu bytes of scratch, the library's static buffer holds %zu",
+                      need, (size_t)FN_NOALLOC_SCRATCH_BYTES);
+        FN_SET_ERR(c, FN_E_NOMEM, msg);
+    }
+    if (n_src > 0 && !q) FN_SET_ERR(c, FN_E_INVAL, "q is NULL");
+    if (n_tgt > 0 && !phi && !H) FN_SET_ERR(c, FN_E_INVAL, "both outputs are NULL");
+    int rc = check_device(c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    const int dev = c->device;
+    void *ptr = nullptr;
+    rc = noalloc_scratch(c, dev, &ptr);
+    if (rc) return rc;
+    // run on the static buffer, then give the context back its own workspace and state
+    void *const ws0 = c->ws;
+    const size_t wsb0 = c->ws_bytes;
+    const bool plan0 = c->plan_ready, geom0 = c->geom_ready, charges0 = c->charges_ready;
+    const Geom g0 = c->geom;
+    const Layout l0 = c->lay;
+    const Buffers b0 = c->buf;
+    const fn_mesh *mesh0 = c->mesh;
+    c->ws = ptr;
+    c->ws_bytes = (size_t)FN_NOALLOC_SCRATCH_BYTES;
+    // the plan tables sit at size-independent offsets: the ones the last call on this device
+    // built are reused when the parameters are the same
+    c->plan_ready = g_noalloc_plan_ok[dev] && std::memcmp(&g_noalloc_prm[dev], &c->prm, sizeof(fn_params)) == 0;
+    g_noalloc_plan_ok[dev] = false;
+    rc = set_geometry_impl(c, n_tgt, tgt_xy, n_src, src_xy, src_w, n_surf);
+    if (c->plan_ready) {
+        g_noalloc_prm[dev] = c->prm;
+        g_noalloc_plan_ok[dev] = true;
+    }
+    if (rc == FN_OK) rc = fn_set_charges(c, q);
+    if (rc == FN_OK) rc = eval_impl(c, phi, H, c->stream);
+    c->ws = ws0;
+    c->ws_bytes = wsb0;
+    c->plan_ready = plan0;
+    c->geom_ready = geom0;
+    c->charges_ready = charges0;
+    c->geom = g0;
+    c->lay = l0;
+    c->buf = b0;
+    c->mesh = mesh0;
+    return rc;
+}
