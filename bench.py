@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the forward and the H adjoint one after the other on one stream instead of "
                          "at the same time (fn_eval_with_H_adjoint)")
+    ap.add_argument("--shapes", type=str, default=None,
+                    help="kernel work shapes as JSON (fn_set_shapes fields), e.g. '{\"spread_groups\": 1}'; "
+                         "default: the autotuner's cache entry for this workload, else the library defaults")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one elementwise kernel over 256 MiB (read and write) before the timed region, "
                          "as the byte-counter calibration for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")

@@ -201,6 +201,27 @@ int fn_eval_with_H_adjoint(fn_ctx *ctx, double *phi, double *H, const double *V,
 
 int fn_get_info(const fn_ctx *ctx, fn_info *info);
 
+/* Work shapes of the kernels: the knobs of the autotuner (paper_0807_2387_amd.tune), which
+ * times candidates on the caller's own data and keeps the fastest per (grid, window, degree,
+ * precision, points per cell, GPU architecture).  They change speed only; results change at
+ * most by rounding (a different summation order).  A 0 field keeps the library default.
+ *   spread_groups   FP32 spread: the 2m x 2m footprint of a cell's points is summed in
+ *                   registers in this many groups of whole row pairs (1..3; at most 144
+ *                   sums per group); default 1 for m <= 4, 2 for m <= 6, else 3.
+ *   near_*_bx, _by  near-field home block of the volume sources, cells: 16 x 16, 32 x 8 or
+ *                   64 x 4 (default 32 x 8), forward (targets home) and adjoint (sources home)
+ *   near_*_cap      points of the other set staged per LDS chunk, a multiple of 64 in
+ *                   [128, 2048] (default 1024 forward, 512 adjoint)
+ * FN_E_INVAL for an unsupported value (nothing is changed then). */
+typedef struct fn_shapes {
+    int32_t spread_groups;
+    int32_t near_fwd_bx, near_fwd_by, near_fwd_cap;
+    int32_t near_adj_bx, near_adj_by, near_adj_cap;
+    int32_t reserved;
+} fn_shapes;
+int fn_set_shapes(fn_ctx *ctx, const fn_shapes *shapes);
+int fn_get_shapes(const fn_ctx *ctx, fn_shapes *shapes);   /* the shapes in effect */
+
 /* For callers that cannot allocate device memory (code under graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): fn_set_geometry_split + fn_set_charges + fn_eval
  * in one call whose workspace is a library-owned static device buffer of
@@ -309,6 +330,30 @@ int fn_bind_mesh(fn_ctx *ctx, fn_mesh *mesh);
  * as in fn_eval_with_H_adjoint (V needs only M), except under graph capture before
  * that call has created its stream: then one after the other. */
 int fn_energy(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *grad);
+
+/* Outputs at the quadrature points (the Discretization section's charges sit there).
+ * fn_bind_mesh_sources: the mesh's quadrature points are both the targets and the sources
+ * of the context, all in one source class (every source takes the kernel regularized at
+ * eps_I; eps_S is not used): the fast potential matrix is then symmetric like the exact
+ * one.  The potential of eq. (2) at a point leaves that point's own charge out, like any
+ * pair at distance 0.  The context's workspace must hold fn_workspace_size(S, S).
+ * fn_energy_charge: with q = C M and s = w q,
+ *     phi_j = sum_{k != j} s_k G(r_j - r_k)        -> phi_s [S] (may be NULL)
+ *     E_q   = 1/2 sum_j s_j phi_j                   -> *E (one device double)
+ *     grad  = dE_q/dM = C^T (w phi)                 -> grad [n_nodes][2] (may be NULL)
+ * E_q is the energy of the charges in their own potential (1/2 int rho phi + 1/2 oint
+ * sigma phi by the same quadrature, mu0 = 1).  The potential matrix between distinct
+ * points is symmetric (the fast one too, with one source class), so the gradient needs no
+ * adjoint evaluation.  Runs on the context's stream; needs fn_bind_mesh_sources(ctx,
+ * mesh) after the last fn_mesh_set. */
+int fn_bind_mesh_sources(fn_ctx *ctx, fn_mesh *mesh);
+int fn_energy_charge(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *grad, double *phi_s);
+
+/* The field of the P1 interpolant of a nodal potential phi [n_nodes] (e.g. phi of eq. (2)
+ * at the nodes): H_T = -sum_k phi_{i_k} grad(lambda_k) per triangle -> H_tri [n_tris][2],
+ * and its lumped projection H_i = (1/l_i) sum_{T at i} (|T|/3) H_T -> H_node [n_nodes][2]
+ * (either may be NULL, not both).  FP64, fixed summation order, on the mesh's stream. */
+int fn_mesh_p1_gradient(fn_mesh *mesh, const double *phi, double *H_tri, double *H_node);
 
 /* Message of the last error on this mesh (or of the last failed fn_mesh_create
  * when mesh is NULL). */

@@ -198,6 +198,34 @@ class Solver:
         self._mesh = mesh
         return self
 
+    def bind_mesh_sources(self, mesh):
+        """Targets = sources = the mesh's quadrature points (fn_bind_mesh_sources)."""
+        torch = _torch()
+        L = _lib.lib()
+        need = self.workspace_bytes(mesh.n_sources, mesh.n_sources)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._check(L.fn_set_workspace(self._ctx, ctypes.c_void_p(self._ws.data_ptr()), ctypes.c_size_t(need)))
+        self._check(L.fn_bind_mesh_sources(self._ctx, mesh._mesh))
+        self.n_tgt = self.n_src = mesh.n_sources
+        self._mesh = mesh
+        return self
+
+    def energy_charge(self, M, grad=True):
+        """Charge-form energy E_q = 1/2 sum_j s_j phi_j (0-d tensor), dE_q/dM [n_nodes, 2] if grad,
+        and phi at the quadrature points [S] (fn_energy_charge; needs bind_mesh_sources)."""
+        torch = _torch()
+        mesh = self._mesh
+        E = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty(mesh.n_nodes, 2, dtype=torch.float64, device=self.device) if grad else None
+        phi = torch.empty(mesh.n_sources, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_energy_charge(self._ctx, mesh._mesh, _dev_ptr(M, "M", (2,)),
+                                                ctypes.c_void_p(E.data_ptr()),
+                                                _dev_ptr(g, "grad", (2,)) if g is not None else None,
+                                                _dev_ptr(phi, "phi_s")))
+        return E, g, phi
+
     def energy(self, M, grad=True):
         """E = -1/2 sum_i l_i M_i . H_i (0-d tensor) and, if grad, dE/dM [n_nodes, 2] (fn_energy)."""
         torch = _torch()
@@ -207,6 +235,23 @@ class Solver:
         self._check(_lib.lib().fn_energy(self._ctx, mesh._mesh, _dev_ptr(M, "M", (2,)), ctypes.c_void_p(E.data_ptr()),
                                          _dev_ptr(g, "grad", (2,)) if g is not None else None))
         return E, g
+
+    SHAPE_KEYS = ("spread_groups", "near_fwd_bx", "near_fwd_by", "near_fwd_cap", "near_adj_bx", "near_adj_by",
+                  "near_adj_cap")
+
+    def set_shapes(self, **shapes):
+        """Kernel work shapes (fn_set_shapes); unnamed fields keep the library default."""
+        bad = set(shapes) - set(self.SHAPE_KEYS)
+        if bad:
+            raise ValueError(f"unknown shape fields {sorted(bad)}")
+        sh = _lib.Shapes(**{k: int(v) for k, v in shapes.items()})
+        self._check(_lib.lib().fn_set_shapes(self._ctx, ctypes.byref(sh)))
+        return self
+
+    def shapes(self):
+        sh = _lib.Shapes()
+        self._check(_lib.lib().fn_get_shapes(self._ctx, ctypes.byref(sh)))
+        return {k: int(getattr(sh, k)) for k in self.SHAPE_KEYS}
 
     def set_profiling(self, enable=True):
         self._check(_lib.lib().fn_set_profiling(self._ctx, int(bool(enable))))
@@ -284,6 +329,16 @@ class Mesh:
         out = torch.empty(self.n_nodes, 2, dtype=torch.float64, device=self.device)
         self._check(_lib.lib().fn_mesh_charges_T(self._mesh, _dev_ptr(u, "u"), _dev_ptr(out, "out", (2,))))
         return out
+
+    def p1_gradient(self, phi):
+        """Field of the P1 interpolant of nodal phi: per triangle [T, 2] and lumped to the
+        nodes [N, 2] (fn_mesh_p1_gradient)."""
+        torch = _torch()
+        HT = torch.empty(self.n_tris, 2, dtype=torch.float64, device=self.device)
+        Hn = torch.empty(self.n_nodes, 2, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn_mesh_p1_gradient(self._mesh, _dev_ptr(phi, "phi"), _dev_ptr(HT, "H_tri", (2,)),
+                                                   _dev_ptr(Hn, "H_node", (2,))))
+        return HT, Hn
 
 
 def _params(d):

@@ -23,10 +23,10 @@ SYMBOLS = (
     "fn_set_geometry", "fn_set_geometry_split", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
     "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_eval_with_H_adjoint", "fn_eval_noalloc", "fn_get_info",
     "fn_last_error",
-    "fn_set_profiling", "fn_get_profile",
+    "fn_set_profiling", "fn_get_profile", "fn_set_shapes", "fn_get_shapes",
     "fn_mesh_create", "fn_mesh_destroy", "fn_mesh_workspace_size", "fn_mesh_set_workspace", "fn_mesh_set",
     "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
-    "fn_energy", "fn_mesh_last_error",
+    "fn_energy", "fn_bind_mesh_sources", "fn_energy_charge", "fn_mesh_p1_gradient", "fn_mesh_last_error",
     "fn_batch_create", "fn_batch_destroy", "fn_batch_workspace_size", "fn_batch_set_workspace",
     "fn_set_geometry_batch", "fn_set_geometry_batch_split", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint", "fn_batch_eval_with_H_adjoint",
     "fn_batch_eval_phi_adjoint", "fn_batch_member", "fn_batch_last_error",
@@ -52,6 +52,13 @@ class Info(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("near_pairs", ctypes.c_int64),
                 ("n_surf", ctypes.c_int64), ("near_pairs_surf", ctypes.c_int64),
                 ("near_cells_surf", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Shapes(ctypes.Structure):
+    _fields_ = [("spread_groups", ctypes.c_int32),
+                ("near_fwd_bx", ctypes.c_int32), ("near_fwd_by", ctypes.c_int32), ("near_fwd_cap", ctypes.c_int32),
+                ("near_adj_bx", ctypes.c_int32), ("near_adj_by", ctypes.c_int32), ("near_adj_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -97,6 +104,8 @@ def lib():
         "fn_last_error": ([P], ctypes.c_char_p),
         "fn_set_profiling": ([P, ctypes.c_int], ctypes.c_int),
         "fn_get_profile": ([P, ctypes.POINTER(Profile)], ctypes.c_int),
+        "fn_set_shapes": ([P, ctypes.POINTER(Shapes)], ctypes.c_int),
+        "fn_get_shapes": ([P, ctypes.POINTER(Shapes)], ctypes.c_int),
         "fn_mesh_create": ([I64, I64, I64, P, ctypes.POINTER(P)], ctypes.c_int),
         "fn_mesh_destroy": ([P], ctypes.c_int),
         "fn_mesh_workspace_size": ([P, ctypes.POINTER(SZ)], ctypes.c_int),
@@ -108,6 +117,9 @@ def lib():
         "fn_mesh_charges_T": ([P, P, P], ctypes.c_int),
         "fn_bind_mesh": ([P, P], ctypes.c_int),
         "fn_energy": ([P, P, P, P, P], ctypes.c_int),
+        "fn_bind_mesh_sources": ([P, P], ctypes.c_int),
+        "fn_energy_charge": ([P, P, P, P, P, P], ctypes.c_int),
+        "fn_mesh_p1_gradient": ([P, P, P, P], ctypes.c_int),
         "fn_mesh_last_error": ([P], ctypes.c_char_p),
         "fn_batch_create": ([I32, ctypes.POINTER(Params), P, ctypes.POINTER(P)], ctypes.c_int),
         "fn_batch_destroy": ([P], ctypes.c_int),

@@ -741,8 +741,8 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
         uint32_t cnt[2] = {0, 0};
         uint32_t *dcnt = reinterpret_cast<uint32_t *>(B.red + RED_PART);
         const uint32_t cap = (uint32_t)L.nblk_cap;
-        FN_HIP(c, launch_block_list(c->geom, B, 0, 2, g.rnear_s, 1, B.blk_fs, cap, dcnt, c->stream));
-        FN_HIP(c, launch_block_list(c->geom, B, 2, 0, g.rnear_s, 0, B.blk_as, cap, dcnt + 1, c->stream));
+        FN_HIP(c, launch_block_list(c->geom, B, NEAR_SURF_FWD, 0, 2, g.rnear_s, 1, B.blk_fs, cap, dcnt, c->stream));
+        FN_HIP(c, launch_block_list(c->geom, B, NEAR_SURF_ADJ, 2, 0, g.rnear_s, 0, B.blk_as, cap, dcnt + 1, c->stream));
         FN_HIP(c, hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
         FN_HIP(c, hipStreamSynchronize(c->stream));
         if (cnt[0] > cap || cnt[1] > cap) {
@@ -760,7 +760,8 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
             NearArgs na = near_args(c, s - 1);
             double *cnt = B.far;  // one count per source of the class
             double tot = 0.0;
-            FN_HIP(c, launch_near_adj(c->geom, B, na, s, 2, B.red + RED_SUMV, cnt, s == 2 ? B.blk_as : nullptr,
+            FN_HIP(c, launch_near_adj(c->geom, B, na, s == 2 ? NEAR_SURF_ADJ : NearShape{32, 8, 512}, s, 2,
+                                      B.red + RED_SUMV, cnt, s == 2 ? B.blk_as : nullptr,
                                       c->geom.nblk_as, c->stream));
             FN_HIP(c, launch_sum(cnt, set_size(c->geom, s), B.red + RED_SUMV, c->stream));
             FN_HIP(c, hipMemcpyAsync(&tot, B.red + RED_SUMV, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -869,7 +870,8 @@ static int eval_impl(fn_ctx *c, double *phi, double *H, hipStream_t st)
         if (set_size(g, set) == 0 && k > 0) continue;
         NearArgs na = near_args(c, k);
         const int stg = k ? FN_ST_NEAR_SURF : FN_ST_NEAR;
-        FN_STAGE(c, stg, launch_near_fwd(g, B, na, set, k > 0, B.red + RED_SUMQ, want_phi, want_h, phi, H,
+        FN_STAGE(c, stg, launch_near_fwd(g, B, na, k ? NEAR_SURF_FWD : P.near_fwd, set, k > 0, B.red + RED_SUMQ,
+                                         want_phi, want_h, phi, H,
                                          k ? B.blk_fs : nullptr, g.nblk_fs, st));
         if (want_phi && (k ? g.coincident_s : g.coincident) > 0)
             FN_STAGE(c, stg, launch_near_coincident(g, B, na, 0, set, phi, st));
@@ -953,7 +955,8 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind, hipStr
         NearArgs na = near_args(c, k);
         double *u_k = u + set_base(g, set);
         const int stg = k ? FN_ST_A_NEAR_SURF : FN_ST_A_NEAR;
-        FN_STAGE(c, stg, launch_near_adj(g, B, na, set, kind, B.red + RED_SUMV, u_k, k ? B.blk_as : nullptr,
+        FN_STAGE(c, stg, launch_near_adj(g, B, na, k ? NEAR_SURF_ADJ : P.near_adj, set, kind, B.red + RED_SUMV, u_k,
+                                         k ? B.blk_as : nullptr,
                                          g.nblk_as, st));
         if (kind == 1 && (k ? g.coincident_s : g.coincident) > 0)
             FN_STAGE(c, stg, launch_near_coincident(g, B, na, set, 0, u_k, st));
@@ -1052,6 +1055,48 @@ int fn_get_info(const fn_ctx *ctx, fn_info *info)
     info->near_pairs_surf = g.near_pairs_s;
     info->near_cells_surf = g.rnear_s;
     info->workspace_bytes = make_layout(ctx->plan, g.nt, g.ns).total;
+    return FN_OK;
+}
+
+int fn_set_shapes(fn_ctx *ctx, const fn_shapes *shapes)
+{
+    if (!ctx || !shapes) return FN_E_INVAL;
+    Plan &P = ctx->plan;
+    const int m = P.m;
+    int ng = shapes->spread_groups ? shapes->spread_groups : 0;
+    if (ng < 0 || ng > 3 || (ng && 2 * ((m + ng - 1) / ng) * (2 * m) > 144))
+        FN_SET_ERR(ctx, FN_E_INVAL, "spread_groups must be 0 or 1..3 with at most 144 sums per group");
+    auto pick = [](int32_t bx, int32_t by, int32_t cap, const NearShape &cur) {
+        NearShape s = cur;
+        if (bx || by) {
+            s.bx = bx;
+            s.by = by;
+        }
+        if (cap) s.cap = cap;
+        return s;
+    };
+    const NearShape f = pick(shapes->near_fwd_bx, shapes->near_fwd_by, shapes->near_fwd_cap, NearShape{32, 8, 1024});
+    const NearShape a = pick(shapes->near_adj_bx, shapes->near_adj_by, shapes->near_adj_cap, NearShape{32, 8, 512});
+    if (!near_shape_ok(f) || !near_shape_ok(a))
+        FN_SET_ERR(ctx, FN_E_INVAL, "near-field shapes: 16 x 16, 32 x 8 or 64 x 4 cells, capacity a multiple of 64 in [128, 2048]");
+    P.spread_ng = ng;
+    P.near_fwd = f;
+    P.near_adj = a;
+    return FN_OK;
+}
+
+int fn_get_shapes(const fn_ctx *ctx, fn_shapes *shapes)
+{
+    if (!ctx || !shapes) return FN_E_INVAL;
+    const Plan &P = ctx->plan;
+    std::memset(shapes, 0, sizeof(*shapes));
+    shapes->spread_groups = P.spread_ng ? P.spread_ng : spread_default_groups(P.m);
+    shapes->near_fwd_bx = P.near_fwd.bx;
+    shapes->near_fwd_by = P.near_fwd.by;
+    shapes->near_fwd_cap = P.near_fwd.cap;
+    shapes->near_adj_bx = P.near_adj.bx;
+    shapes->near_adj_by = P.near_adj.by;
+    shapes->near_adj_cap = P.near_adj.cap;
     return FN_OK;
 }
 

@@ -253,6 +253,68 @@ __global__ void k_half_neg(const double *__restrict__ sum, double *__restrict__ 
     if (threadIdx.x == 0 && blockIdx.x == 0) E[0] = -0.5 * sum[0];
 }
 
+__global__ void k_half(const double *__restrict__ sum, double *__restrict__ E)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) E[0] = 0.5 * sum[0];
+}
+
+// Charge form at the quadrature points: e_j = w_j q_j phi_j (summed for E_q = 1/2 sum e_j)
+// and u_j = w_j phi_j (dE_q/dq_j: the potential matrix between distinct points is
+// symmetric, so the gradient with respect to M is C^T u).
+__global__ void k_charge_energy_terms(const double *__restrict__ w, const double *__restrict__ q,
+                                      const double *__restrict__ phi, int64_t S, double *__restrict__ e,
+                                      double *__restrict__ u)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= S) return;
+    const double wp = w[j] * phi[j];
+    u[j] = wp;
+    e[j] = q[j] * wp;
+}
+
+// -grad of the P1 interpolant of nodal phi on triangle t: -(phi_0 g_0 + phi_1 g_1 + phi_2 g_2)
+__device__ __forceinline__ double2 p1_grad(const double *__restrict__ phi, const int32_t *__restrict__ tris,
+                                           const double *__restrict__ tg, int64_t T, int64_t t)
+{
+    const double f0 = phi[tris[3 * t]], f1 = phi[tris[3 * t + 1]], f2 = phi[tris[3 * t + 2]];
+    const double gx = (f0 * tg[0 * T + t] + f1 * tg[2 * T + t]) + f2 * tg[4 * T + t];
+    const double gy = (f0 * tg[1 * T + t] + f1 * tg[3 * T + t]) + f2 * tg[5 * T + t];
+    return make_double2(-gx, -gy);
+}
+
+__global__ void k_p1_grad_tri(const double *__restrict__ phi, const int32_t *__restrict__ tris,
+                              const double *__restrict__ tg, int64_t T, double *__restrict__ H)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const double2 h = p1_grad(phi, tris, tg, T, t);
+    H[2 * t] = h.x;
+    H[2 * t + 1] = h.y;
+}
+
+// Lumped projection onto the nodes: H_i = (1/l_i) sum over the triangles at i of (|T|/3) H_T,
+// in the fixed order of the node's incidence list (edge slots carry no area).
+__global__ void k_p1_grad_node(const uint32_t *__restrict__ off, const uint32_t *__restrict__ slot, int64_t N,
+                               int64_t T, const double *__restrict__ phi, const int32_t *__restrict__ tris,
+                               const double *__restrict__ tg, const double *__restrict__ ell, double *__restrict__ H)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double hx = 0.0, hy = 0.0;
+    for (uint32_t k = off[i]; k < off[i + 1]; ++k) {
+        const uint32_t s = slot[k];
+        if (s >= 3 * T) continue;
+        const int64_t t = s / 3;
+        const double a3 = tg[6 * T + t] / 3.0;
+        const double2 h = p1_grad(phi, tris, tg, T, t);
+        hx += a3 * h.x;
+        hy += a3 * h.y;
+    }
+    const double l = ell[i];
+    H[2 * i] = l > 0.0 ? hx / l : 0.0;
+    H[2 * i + 1] = l > 0.0 ? hy / l : 0.0;
+}
+
 inline int nb_of(int64_t n) { return (int)((n + FB - 1) / FB); }
 inline int nb_grid(int64_t n) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + FB - 1) / FB)); }
 
@@ -267,6 +329,7 @@ using namespace fn;
 struct MeshBuf {
     double *nodes = nullptr, *tg = nullptr, *eg = nullptr, *ell = nullptr, *x = nullptr, *w = nullptr;
     double *q = nullptr, *H = nullptr, *V = nullptr, *u = nullptr, *e = nullptr, *red = nullptr;
+    double *es = nullptr, *phis = nullptr;  // charge form: terms w q phi, potential at the sources
     int32_t *tris = nullptr, *bedges = nullptr;
     uint32_t *off = nullptr, *slot = nullptr, *key = nullptr, *skey = nullptr, *sval = nullptr, *hist = nullptr;
 };
@@ -315,6 +378,8 @@ static size_t mesh_layout(const fn_mesh *m, MeshBuf *b, char *base)
     t.H = (double *)take(16 * N);
     t.V = (double *)take(16 * N);
     t.e = (double *)take(8 * N);
+    t.es = (double *)take(8 * S);
+    t.phis = (double *)take(8 * S);
     t.red = (double *)take(8 * MESH_RED);
     if (b) *b = t;
     return o;
@@ -537,6 +602,81 @@ int fn_bind_mesh(fn_ctx *ctx, fn_mesh *mesh)
     if (rc) return rc;
     ctx->mesh = mesh;
     ctx->mesh_stamp = mesh->stamp;
+    ctx->mesh_at_sources = false;
+    return FN_OK;
+}
+
+int fn_bind_mesh_sources(fn_ctx *ctx, fn_mesh *mesh)
+{
+    if (!ctx || !mesh) return FN_E_INVAL;
+    if (!mesh->ready) {
+        ctx->err = "fn_mesh_set must succeed before fn_bind_mesh_sources";
+        return FN_E_STATE;
+    }
+    if (mesh->device != ctx->device) {
+        ctx->err = "mesh and context live on different devices";
+        return FN_E_INVAL;
+    }
+    ctx->mesh = nullptr;
+    // targets = sources = the quadrature points, one source class: every source takes the
+    // kernel regularized at eps_I, so the fast potential matrix is symmetric like the exact
+    // one (with the boundary points as a class of their own, A[i][j] = K_{class of j} would
+    // not be) and C^T (w phi) is the exact gradient of the energy evaluated; the potential
+    // (unlike the field) of line charges converges at the volume radius too
+    int rc = fn_set_geometry(ctx, mesh->S, mesh->b.x, mesh->S, mesh->b.x, mesh->b.w);
+    if (rc) return rc;
+    ctx->mesh = mesh;
+    ctx->mesh_stamp = mesh->stamp;
+    ctx->mesh_at_sources = true;
+    return FN_OK;
+}
+
+int fn_energy_charge(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *grad, double *phi_s)
+{
+    if (!ctx || !mesh) return FN_E_INVAL;
+    if (!M || !E) {
+        ctx->err = "NULL M or E";
+        return FN_E_INVAL;
+    }
+    if (ctx->mesh != mesh || !ctx->mesh_at_sources || ctx->mesh_stamp != mesh->stamp || !mesh->ready ||
+        !ctx->geom_ready) {
+        ctx->err = "fn_bind_mesh_sources(ctx, mesh) must succeed after the last fn_mesh_set and fn_set_geometry";
+        return FN_E_STATE;
+    }
+    hipStream_t st = ctx->stream;
+    const MeshBuf &b = mesh->b;
+    int rc = ctx_hip(ctx, launch_charges(mesh, M, b.q, st));
+    if (rc) return rc;
+    rc = fn_set_charges(ctx, b.q);
+    if (rc) return rc;
+    double *phi = phi_s ? phi_s : b.phis;
+    rc = fn_eval_phi(ctx, phi);
+    if (rc) return rc;
+    k_charge_energy_terms<<<nb_of(mesh->S), FB, 0, st>>>(b.w, b.q, phi, mesh->S, b.es, b.u);
+    rc = ctx_hip(ctx, hipGetLastError());
+    if (rc) return rc;
+    rc = ctx_hip(ctx, launch_sum(b.es, mesh->S, b.red, st));
+    if (rc) return rc;
+    k_half<<<1, 64, 0, st>>>(b.red, E);
+    rc = ctx_hip(ctx, hipGetLastError());
+    if (rc || !grad) return rc;
+    k_charges_T<false><<<nb_of(mesh->N), FB, 0, st>>>(b.off, b.slot, mesh->N, mesh->T, mesh->E, b.tg, b.eg, b.u,
+                                                      nullptr, nullptr, grad);
+    return ctx_hip(ctx, hipGetLastError());
+}
+
+int fn_mesh_p1_gradient(fn_mesh *mesh, const double *phi, double *H_tri, double *H_node)
+{
+    if (!mesh) return FN_E_INVAL;
+    int rc = mesh_ready(mesh);
+    if (rc) return rc;
+    if (!phi || (!H_tri && !H_node)) MESH_ERR(mesh, FN_E_INVAL, "NULL phi, or both outputs NULL");
+    const MeshBuf &b = mesh->b;
+    if (H_tri) k_p1_grad_tri<<<nb_of(mesh->T), FB, 0, mesh->stream>>>(phi, b.tris, b.tg, mesh->T, H_tri);
+    if (H_node)
+        k_p1_grad_node<<<nb_of(mesh->N), FB, 0, mesh->stream>>>(b.off, b.slot, mesh->N, mesh->T, phi, b.tris, b.tg,
+                                                                b.ell, H_node);
+    MESH_HIP(mesh, hipGetLastError());
     return FN_OK;
 }
 
@@ -547,7 +687,8 @@ int fn_energy(fn_ctx *ctx, fn_mesh *mesh, const double *M, double *E, double *gr
         ctx->err = "NULL M or E";
         return FN_E_INVAL;
     }
-    if (ctx->mesh != mesh || ctx->mesh_stamp != mesh->stamp || !mesh->ready || !ctx->geom_ready) {
+    if (ctx->mesh != mesh || ctx->mesh_at_sources || ctx->mesh_stamp != mesh->stamp || !mesh->ready ||
+        !ctx->geom_ready) {
         ctx->err = "fn_bind_mesh(ctx, mesh) must succeed after the last fn_mesh_set and fn_set_geometry";
         return FN_E_STATE;
     }

@@ -46,6 +46,16 @@ struct WinPoly {
     float c[MAXM][WPD + 1];
 };
 
+// Near-field work shape: home blocks of bx x by cells (bx by = 256: 16 x 16, 32 x 8 or
+// 64 x 4) and the staging capacity in points per LDS chunk (a multiple of 64 in
+// [128, 2048]).
+struct NearShape {
+    int bx = 32, by = 8, cap = 1024;
+};
+// the sparse surface class keeps one shape (its block lists are built at set-up)
+constexpr NearShape NEAR_SURF_FWD{32, 8, 512};
+constexpr NearShape NEAR_SURF_ADJ{32, 8, 1024};
+
 struct Plan {
     int G = 0, n = 0, m = 0, p = 0, log2G = 0;
     int precision = FN_FP32_MIXED;
@@ -58,6 +68,9 @@ struct Plan {
     double aS[MAXP] = {0};           // the same at eps_S (surface sources)
     std::vector<double> cB;          // boundary polynomial in t = (r - r_B)/eps_B
     std::vector<double> psihat;      // window transform at l/G, l = 0..n/2
+    int spread_ng = 0;               // row groups of the FP32 spread footprint (0: spread_default_groups)
+    NearShape near_fwd{32, 8, 1024}; // near-field shape of the forward volume-class kernel
+    NearShape near_adj{32, 8, 512};  // ... and of the adjoint one
     // FFT twiddles e^{-2 pi i k/N} computed at fn_create: length G in the grid precision
     // (float2 or double2 pairs as consecutive values) and length n in FP64 (plan transform)
     std::vector<double> twG64;       // [G][2], FP64 path
@@ -89,6 +102,11 @@ struct Geom {
 // share the source arrays: set 2 starts at source index set_base(g, 2).
 inline int64_t set_size(const Geom &g, int s) { return s == 0 ? g.nt : (s == 1 ? g.ns - g.nsurf : g.nsurf); }
 inline int64_t set_base(const Geom &g, int s) { return s == 2 ? g.ns - g.nsurf : 0; }
+
+// Row groups of the FP32 spread's register footprint for window half-width m: every
+// group holds whole row pairs, at most 72 FP32 sums per group by default (one group of
+// 4 m^2 sums at m <= 4).
+inline int spread_default_groups(int m) { return m <= 4 ? 1 : (m <= 6 ? 2 : 3); }
 
 // Device arrays carved out of the caller's workspace.
 struct Buffers {
@@ -169,6 +187,7 @@ struct fn_ctx {
     bool charges_ready = false;
     const fn_mesh *mesh = nullptr;   // mesh whose nodes and sources are the geometry (fn_bind_mesh)
     uint64_t mesh_stamp = 0;
+    bool mesh_at_sources = false;    // fn_bind_mesh_sources: targets are the mesh's quadrature points
     std::string err;
 };
 
@@ -271,21 +290,24 @@ struct NearArgs {
 };
 // forward: targets against source set in_set; accum = 0 writes far + near (+ the
 // scale term of all charges), accum = 1 adds the near part only
-hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, int in_set, int accum,
-                           const double *sum_s, int want_phi, int want_h, double *phi, double *H,
+hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, const NearShape &sh, int in_set,
+                           int accum, const double *sum_s, int want_phi, int want_h, double *phi, double *H,
                            const uint32_t *blocks, int nblocks, hipStream_t st);
 // adjoint: source set out_set against the targets; u is that set's part of the output
-hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int kind,
-                           const double *sum_v, double *u, const uint32_t *blocks, int nblocks, hipStream_t st);
+hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, const NearShape &sh, int out_set,
+                           int kind, const double *sum_v, double *u, const uint32_t *blocks, int nblocks,
+                           hipStream_t st);
 // The near field's home blocks (NBX x NBY cells) of the geometry, and the list of those with
 // home points of out_set (and, if need_in, points of in_set within R cells): the sparse
 // surface class runs only over these.  *count (device) receives the list length.
-// near_blocks_bound(emax): the block count of any window of at most emax x emax cells (the
-// capacity of the lists).  Entries beyond cap are counted in *count but not written.
-int near_blocks(const Geom &g);
+// near_blocks_bound(emax): the block count of any window of at most emax x emax cells
+// for any allowed shape (the capacity of the lists).  Entries beyond cap are counted in
+// *count but not written.
+int near_blocks(const Geom &g, const NearShape &sh);
+bool near_shape_ok(const NearShape &sh);
 int64_t near_blocks_bound(int64_t emax);
-hipError_t launch_block_list(const Geom &g, const Buffers &b, int out_set, int in_set, int R, int need_in,
-                             uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t st);
+hipError_t launch_block_list(const Geom &g, const Buffers &b, const NearShape &sh, int out_set, int in_set, int R,
+                             int need_in, uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t st);
 hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int in_set,
                                   double *out, hipStream_t st);
 hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, double *cnt, hipStream_t st);

@@ -41,27 +41,23 @@
 // a branch-free pair body (two independent dependency chains per lane).
 #include "fn_internal.h"
 
+#include <algorithm>
+
 namespace fn {
 
 namespace {
 
 constexpr double INV_4PI = 0.07957747154594766788444188168625718;
-// Home blocks are wider than tall: the 64 home points of a wave (cell order) then
+// The home block shape (bx x by cells, bx by = 256) and the staging capacity are
+// run-time values (NearShape, chosen per direction by the plan or the autotuner).
+// Wider than tall is the usual winner: the 64 home points of a wave (cell order) then
 // mostly share one home row, so their row windows have the same vertical gaps and
 // similar trip counts (measured: 16 x 16 -> 32 x 8 cut the forward near field by 7%
 // and the adjoint by 9%, at 2.0 points per cell and a radius of 5 cells).
-#ifndef FN_NEAR_NBX
-#define FN_NEAR_NBX 32
-#endif
-#ifndef FN_NEAR_NBY
-#define FN_NEAR_NBY 8
-#endif
-constexpr int NBX = FN_NEAR_NBX;  // home block width, cells
-constexpr int NBY = FN_NEAR_NBY;  // home block height, cells
-constexpr int NSEG = NBY;         // home row segments per block
 constexpr int NTH = 256;         // threads per block
+constexpr int NSEG_MAX = 16;     // home row segments per block (by), at most
 constexpr int MAXRN = 32;        // largest near radius in cells
-constexpr int MAXROWS = NBY + 2 * MAXRN + 2;
+constexpr int MAXROWS = NSEG_MAX + 2 * MAXRN + 2;
 
 enum { MODE_FWD_BOTH = 0, MODE_ADJ_H = 1, MODE_ADJ_PHI = 2, MODE_COUNT = 3, MODE_FWD_PHI = 4, MODE_FWD_H = 5 };
 
@@ -81,6 +77,8 @@ struct NearSets {
     const uint32_t *cs_in;
     const double *pay;            // fwd: s [n_in]; adj H: V [2][n_in]; adj phi: v [n_in]
     int Ex, Ey, nbx;
+    int bx, by;                   // home block shape, cells
+    uint32_t cap;                 // staging capacity, points per LDS chunk
     int accum;                    // forward only: add the near part to phi / H instead of writing far + near
     const uint32_t *blocks;       // home blocks to run (block i of the launch is blocks[i]); NULL: all
 };
@@ -215,7 +213,14 @@ __device__ __forceinline__ int find_seg(const uint32_t *pre, int nseg, uint32_t 
     return lo;
 }
 
-template <int MODE, int CAP, int P, bool F32>
+// Dynamic LDS of k_near: staged in-cell fractions (double2), payloads [PAY][cap] (double)
+// and, in the FP64 path, cell column offsets (uint16).
+inline size_t near_lds_bytes(uint32_t cap, int pay, bool f32)
+{
+    return (size_t)cap * (sizeof(double2) + pay * sizeof(double)) + (f32 ? 0 : (size_t)cap * sizeof(uint16_t));
+}
+
+template <int MODE, int P, bool F32>
 __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const double *__restrict__ sum_in,
                                               double *__restrict__ out0, double *__restrict__ out1)
 {
@@ -224,13 +229,17 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
     constexpr bool WANT_H = MODE == MODE_FWD_BOTH || MODE == MODE_FWD_H;
     constexpr int PAY = MODE == MODE_ADJ_H ? 2 : 1;
     constexpr int KIND = MODE == MODE_ADJ_H ? 3 : (WANT_PHI && WANT_H ? 0 : (WANT_H ? 1 : 2));
-    __shared__ double2 sxy[CAP];     // in-cell fractions
-    __shared__ uint16_t scx[F32 ? 1 : CAP];  // cell column offset from the region origin (FP64 path)
-    __shared__ double spay[PAY][CAP];
-    __shared__ uint32_t hpre[NSEG + 1], hstart[NSEG];       // home row segments
-    __shared__ uint32_t ipre[MAXROWS + 1], istart[MAXROWS]; // input rows
+    const uint32_t CAP = S.cap;
+    extern __shared__ double2 near_lds[];
+    double2 *sxy = near_lds;                                            // in-cell fractions [CAP]
+    double *spay0 = reinterpret_cast<double *>(near_lds + CAP);         // payloads [PAY][CAP]
+    double *spay1 = spay0 + (PAY - 1) * CAP;
+    uint16_t *scx = reinterpret_cast<uint16_t *>(spay0 + PAY * CAP);    // cell column offsets (FP64 path)
+    __shared__ uint32_t hpre[NSEG_MAX + 1], hstart[NSEG_MAX];  // home row segments
+    __shared__ uint32_t ipre[MAXROWS + 1], istart[MAXROWS];    // input rows
 
     const int Ex = S.Ex, Ey = S.Ey, R = na.rnear;
+    const int NBX = S.bx, NBY = S.by, NSEG = S.by;
     const int bid = S.blocks ? (int)S.blocks[blockIdx.x] : (int)blockIdx.x;
     const int bx = bid % S.nbx, by = bid / S.nbx;
     const int hx0 = bx * NBX, hy0 = by * NBY;
@@ -292,7 +301,7 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
         const int hcx = cx - ix0, hcy = cy - iy0;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (uint32_t c_lo = 0; c_lo < nin; c_lo += CAP) {
-            const uint32_t c_hi = min(nin, c_lo + (uint32_t)CAP);
+            const uint32_t c_hi = min(nin, c_lo + CAP);
             __syncthreads();
             for (uint32_t kk = c_lo + tid; kk < c_hi; kk += NTH) {
                 const int r = find_seg(ipre, nirow, kk);
@@ -308,8 +317,8 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
                     sxy[kk - c_lo] = make_double2(S.f_in[j], S.f_in[S.n_in + j]);
                     scx[kk - c_lo] = (uint16_t)qcx;
                 }
-                spay[0][kk - c_lo] = S.pay[j];
-                if (PAY == 2) spay[PAY - 1][kk - c_lo] = S.pay[S.n_in + j];
+                spay0[kk - c_lo] = S.pay[j];
+                if (PAY == 2) spay1[kk - c_lo] = S.pay[S.n_in + j];
             }
             __syncthreads();
             if (!valid) continue;
@@ -353,8 +362,8 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
                 // home minus staged: target minus source (forward), source minus target (adjoint)
                 if (F32) {
                     const double2 *pq = sxy + lo;
-                    const double *pw0 = spay[0] + lo;
-                    const double *pw1 = spay[PAY - 1] + lo;
+                    const double *pw0 = spay0 + lo;
+                    const double *pw1 = spay1 + lo;
                     uint32_t n = hi > lo ? hi - lo : 0;
                     for (; n >= 2; n -= 2, pq += 2, pw0 += 2, pw1 += 2) {
                         const double2 q0 = pq[0], q1 = pq[1];
@@ -372,8 +381,8 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
                 }
                 const double2 *pq = sxy + lo;
                 const uint16_t *pc = scx + lo;
-                const double *pw0 = spay[0] + lo;
-                const double *pw1 = spay[PAY - 1] + lo;
+                const double *pw0 = spay0 + lo;
+                const double *pw1 = spay1 + lo;
                 uint32_t n = hi > lo ? hi - lo : 0;
                 for (; n >= 2; n -= 2, pq += 2, pc += 2, pw0 += 2, pw1 += 2) {
                     const double2 q0 = pq[0], q1 = pq[1];
@@ -454,40 +463,29 @@ __global__ void __launch_bounds__(256) k_coincident_count(NearSets S, double *__
     cnt[gi] = c;
 }
 
-// Staging capacities (points per LDS chunk): smaller chunks keep more blocks per CU,
-// larger ones need fewer chunk passes; measured best with 32 x 8 home blocks at a near
-// radius of 5 cells and about 2.0 points per cell.
-#ifndef FN_NEAR_CAP_FWD
-#define FN_NEAR_CAP_FWD 1024
-#endif
-#ifndef FN_NEAR_CAP_ADJ
-#define FN_NEAR_CAP_ADJ 512
-#endif
-constexpr int CAP_FWD = FN_NEAR_CAP_FWD;
-constexpr int CAP_ADJ = FN_NEAR_CAP_ADJ;
-// surface-source class (a thin strip of sources): forward blocks stage few sources,
-// adjoint blocks (home = surface points) stage the dense targets around them
-constexpr int CAP_FWD_S = 512;
-constexpr int CAP_ADJ_S = 1024;
-
-template <int MODE, int CAP, int P>
+template <int MODE, int P>
 hipError_t launch_p(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum, double *o0,
                     double *o1)
 {
+    constexpr int PAY = MODE == MODE_ADJ_H ? 2 : 1;
+    const size_t lds = near_lds_bytes(S.cap, PAY, na.f32 != 0);
+    const void *k = na.f32 ? (const void *)k_near<MODE, P, true> : (const void *)k_near<MODE, P, false>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     if (na.f32)
-        k_near<MODE, CAP, P, true><<<nblk, NTH, 0, st>>>(S, na, sum, o0, o1);
+        k_near<MODE, P, true><<<nblk, NTH, lds, st>>>(S, na, sum, o0, o1);
     else
-        k_near<MODE, CAP, P, false><<<nblk, NTH, 0, st>>>(S, na, sum, o0, o1);
+        k_near<MODE, P, false><<<nblk, NTH, lds, st>>>(S, na, sum, o0, o1);
     return hipGetLastError();
 }
 
-template <int MODE, int CAP>
+template <int MODE>
 hipError_t launch_mode(int nblk, hipStream_t st, const NearSets &S, const NearArgs &na, const double *sum, double *o0,
                        double *o1)
 {
     switch (na.p) {
 #define FN_NEAR_CASE(PP) \
-    case PP: return launch_p<MODE, CAP, PP>(nblk, st, S, na, sum, o0, o1);
+    case PP: return launch_p<MODE, PP>(nblk, st, S, na, sum, o0, o1);
     FN_NEAR_CASE(1) FN_NEAR_CASE(2) FN_NEAR_CASE(3) FN_NEAR_CASE(4) FN_NEAR_CASE(5) FN_NEAR_CASE(6)
     FN_NEAR_CASE(7) FN_NEAR_CASE(8) FN_NEAR_CASE(9) FN_NEAR_CASE(10) FN_NEAR_CASE(11) FN_NEAR_CASE(12)
 #undef FN_NEAR_CASE
@@ -498,7 +496,7 @@ hipError_t launch_mode(int nblk, hipStream_t st, const NearSets &S, const NearAr
 // Home set out_set against input set in_set (targets against a source set, or a
 // source set against the targets).  The sorted arrays of a source set start at its
 // base within the source arrays; far-field results follow the home set's order.
-NearSets make_sets(const Geom &g, const Buffers &b, int out_set, int in_set)
+NearSets make_sets(const Geom &g, const Buffers &b, int out_set, int in_set, const NearShape &sh)
 {
     NearSets S{};
     S.n_out = set_size(g, out_set);
@@ -515,7 +513,10 @@ NearSets make_sets(const Geom &g, const Buffers &b, int out_set, int in_set)
     S.pay = out_set ? b.aval64 : b.val64 + set_base(g, in_set);
     S.Ex = g.ext[0];
     S.Ey = g.ext[1];
-    S.nbx = (g.ext[0] + NBX - 1) / NBX;
+    S.bx = sh.bx;
+    S.by = sh.by;
+    S.cap = (uint32_t)sh.cap;
+    S.nbx = (g.ext[0] + sh.bx - 1) / sh.bx;
     S.accum = 0;
     S.blocks = nullptr;
     return S;
@@ -534,6 +535,7 @@ __global__ void k_block_list(NearSets S, int nblk, int R, int need_in, uint32_t 
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblk) return;
+    const int NBX = S.bx, NBY = S.by;
     const int bx = b % S.nbx, by = b / S.nbx;
     const int hx0 = bx * NBX, hy0 = by * NBY;
     const int hx1 = min(hx0 + NBX, S.Ex), hy1 = min(hy0 + NBY, S.Ey);
@@ -570,7 +572,7 @@ hipError_t launch_near_coincident(const Geom &g, const Buffers &b, const NearArg
                                   double *out, hipStream_t st)
 {
     if (set_size(g, out_set) == 0 || set_size(g, in_set) == 0) return hipSuccess;
-    NearSets S = make_sets(g, b, out_set, in_set);
+    NearSets S = make_sets(g, b, out_set, in_set, NearShape{});
     switch (na.p) {
 #define FN_CO_CASE(PP) \
     case PP: return coincident_p<PP>(S, na, out_set != 0, out, st);
@@ -586,60 +588,76 @@ hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, 
 {
     if (g.nt == 0) return hipSuccess;
     if (set_size(g, in_set) == 0) return launch_fill(cnt, g.nt, 0.0, st);
-    const NearSets S = make_sets(g, b, 0, in_set);
+    const NearSets S = make_sets(g, b, 0, in_set, NearShape{});
     k_coincident_count<<<(int)((g.nt + 255) / 256), 256, 0, st>>>(S, cnt);
     return hipGetLastError();
 }
 
-int near_blocks(const Geom &g) { return ((g.ext[0] + NBX - 1) / NBX) * ((g.ext[1] + NBY - 1) / NBY); }
-
-int64_t near_blocks_bound(int64_t emax) { return ((emax + NBX - 1) / NBX) * ((emax + NBY - 1) / NBY); }
-
-hipError_t launch_block_list(const Geom &g, const Buffers &b, int out_set, int in_set, int R, int need_in,
-                             uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t st)
+int near_blocks(const Geom &g, const NearShape &sh)
 {
-    const int nblk = near_blocks(g);
-    const NearSets S = make_sets(g, b, out_set, in_set);
+    return ((g.ext[0] + sh.bx - 1) / sh.bx) * ((g.ext[1] + sh.by - 1) / sh.by);
+}
+
+bool near_shape_ok(const NearShape &sh)
+{
+    const bool dims = (sh.bx == 16 && sh.by == 16) || (sh.bx == 32 && sh.by == 8) || (sh.bx == 64 && sh.by == 4);
+    return dims && sh.cap >= 128 && sh.cap <= 2048 && sh.cap % 64 == 0;
+}
+
+int64_t near_blocks_bound(int64_t emax)
+{
+    // the largest count over the allowed home block shapes
+    const int dims[3][2] = {{16, 16}, {32, 8}, {64, 4}};
+    int64_t best = 0;
+    for (const auto &d : dims) best = std::max<int64_t>(best, ((emax + d[0] - 1) / d[0]) * ((emax + d[1] - 1) / d[1]));
+    return best;
+}
+
+hipError_t launch_block_list(const Geom &g, const Buffers &b, const NearShape &sh, int out_set, int in_set, int R,
+                             int need_in, uint32_t *list, uint32_t cap, uint32_t *count, hipStream_t st)
+{
+    const int nblk = near_blocks(g, sh);
+    const NearSets S = make_sets(g, b, out_set, in_set, sh);
     k_fill_u32<<<1, 1, 0, st>>>(count, 0u);
     k_block_list<<<(nblk + 255) / 256, 256, 0, st>>>(S, nblk, R, need_in, cap, list, count);
     return hipGetLastError();
 }
 
-hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, int in_set, int accum,
-                           const double *sum_s, int want_phi, int want_h, double *phi, double *H,
+hipError_t launch_near_fwd(const Geom &g, const Buffers &b, const NearArgs &na, const NearShape &sh, int in_set,
+                           int accum, const double *sum_s, int want_phi, int want_h, double *phi, double *H,
                            const uint32_t *blocks, int nblocks, hipStream_t st)
 {
     if (g.nt == 0) return hipSuccess;
-    NearSets S = make_sets(g, b, 0, in_set);
+    if (!near_shape_ok(sh)) return hipErrorInvalidValue;
+    NearSets S = make_sets(g, b, 0, in_set, sh);
     S.accum = accum;
     S.blocks = blocks;
-    const int nblk = blocks ? nblocks : near_blocks(g);
+    const int nblk = blocks ? nblocks : near_blocks(g, sh);
     if (nblk == 0) return hipSuccess;
-    if (in_set == 2) {
-        if (want_phi && want_h) return launch_mode<MODE_FWD_BOTH, CAP_FWD_S>(nblk, st, S, na, sum_s, phi, H);
-        if (want_phi) return launch_mode<MODE_FWD_PHI, CAP_FWD_S>(nblk, st, S, na, sum_s, phi, H);
-        return launch_mode<MODE_FWD_H, CAP_FWD_S>(nblk, st, S, na, sum_s, phi, H);
-    }
-    if (want_phi && want_h) return launch_mode<MODE_FWD_BOTH, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
-    if (want_phi) return launch_mode<MODE_FWD_PHI, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
-    return launch_mode<MODE_FWD_H, CAP_FWD>(nblk, st, S, na, sum_s, phi, H);
+    if (want_phi && want_h) return launch_mode<MODE_FWD_BOTH>(nblk, st, S, na, sum_s, phi, H);
+    if (want_phi) return launch_mode<MODE_FWD_PHI>(nblk, st, S, na, sum_s, phi, H);
+    return launch_mode<MODE_FWD_H>(nblk, st, S, na, sum_s, phi, H);
 }
 
 // kind 0: H^T (V), kind 1: phi^T (v), kind 2: count pairs closer than the class radius
 // per source.  u is the part of the output that belongs to source set out_set.
-hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, int out_set, int kind,
-                           const double *sum_v, double *u, const uint32_t *blocks, int nblocks, hipStream_t st)
+hipError_t launch_near_adj(const Geom &g, const Buffers &b, const NearArgs &na, const NearShape &sh, int out_set,
+                           int kind, const double *sum_v, double *u, const uint32_t *blocks, int nblocks,
+                           hipStream_t st)
 {
     if (set_size(g, out_set) == 0) return hipSuccess;
-    NearSets S = make_sets(g, b, out_set, 0);
+    if (!near_shape_ok(sh)) return hipErrorInvalidValue;
+    NearSets S = make_sets(g, b, out_set, 0, sh);
     S.blocks = blocks;
-    const int nblk = blocks ? nblocks : near_blocks(g);
+    const int nblk = blocks ? nblocks : near_blocks(g, sh);
     if (nblk == 0) return hipSuccess;
-    if (out_set == 2 && kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ_S>(nblk, st, S, na, sum_v, u, nullptr);
-    if (out_set == 2 && kind == 1) return launch_mode<MODE_ADJ_PHI, CAP_ADJ_S>(nblk, st, S, na, sum_v, u, nullptr);
-    if (kind == 0) return launch_mode<MODE_ADJ_H, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
-    if (kind == 1) return launch_mode<MODE_ADJ_PHI, CAP_ADJ>(nblk, st, S, na, sum_v, u, nullptr);
-    k_near<MODE_COUNT, CAP_ADJ, 1, false><<<nblk, NTH, 0, st>>>(S, na, sum_v, u, nullptr);
+    if (kind == 0) return launch_mode<MODE_ADJ_H>(nblk, st, S, na, sum_v, u, nullptr);
+    if (kind == 1) return launch_mode<MODE_ADJ_PHI>(nblk, st, S, na, sum_v, u, nullptr);
+    const size_t lds = near_lds_bytes(S.cap, 1, false);
+    hipError_t e = hipFuncSetAttribute((const void *)k_near<MODE_COUNT, 1, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_near<MODE_COUNT, 1, false><<<nblk, NTH, lds, st>>>(S, na, sum_v, u, nullptr);
     return hipGetLastError();
 }
 

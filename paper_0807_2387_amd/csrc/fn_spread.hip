@@ -168,23 +168,35 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread(const uint32_t *__restrict
         }
 }
 
+// Taps a and 2m-1-a (a < m) of the FP32 tap polynomials at u = 2f - 1, v = u^2.
+__device__ __forceinline__ void tap_pair(const WinPoly &wp, int a, float u, float v, float &lo, float &hi)
+{
+    const float e = fmaf(fmaf(fmaf(wp.c[a][3], v, wp.c[a][2]), v, wp.c[a][1]), v, wp.c[a][0]);
+    const float o = fmaf(fmaf(fmaf(wp.c[a][7], v, wp.c[a][6]), v, wp.c[a][5]), v, wp.c[a][4]);
+    lo = fmaf(u, o, e);
+    hi = fmaf(-u, o, e);
+}
+
 // Mixed-precision spread, one thread per grid cell: the points of a cell share one
 // 2m x 2m footprint, so their window products are summed in FP32 registers (a
-// handful of terms) and added to the wave's FP64 accumulator once per cell; the
-// footprint is done in row groups of at most 72 accumulators.  The lanes of a
-// wave hold consecutive cells of a tile row, so every LDS atomic instruction
-// touches consecutive addresses.  Same accumulator layout and fixed per-wave
-// summation order as k_spread.
-template <int M2>
+// handful of terms) and added to the wave's FP64 accumulator once per cell.  The
+// footprint's rows are taken in NG groups, each holding whole row pairs (a, 2m-1-a):
+// a pair of y taps comes from one even/odd polynomial pair, so every y tap is evaluated
+// once per point whatever NG is; the x taps are evaluated once per group.  NG = 1 keeps
+// all 4m^2 sums in registers.  The lanes of a wave hold consecutive cells of a tile row,
+// so every LDS atomic instruction touches consecutive addresses.  Same accumulator layout
+// and fixed per-wave summation order as k_spread.
+template <int M2, int NG>
 __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restrict__ fr32,
                                                             const float *__restrict__ val, int64_t N,
                                                             const uint32_t *__restrict__ cstart, int Ex, int Ey,
                                                             int ntx, int nty, double *__restrict__ ptile,
                                                             const WinPoly wp)
 {
+    constexpr int m = M2 / 2;
     constexpr int PT = TILE + M2 - 1;
     constexpr int PT2 = PT * PT;
-    constexpr int RG = (72 / M2) < M2 ? (72 / M2) : M2;
+    constexpr int PPG = (m + NG - 1) / NG;  // row pairs per group
     extern __shared__ double acc[];  // [SPREAD_WAVES][PT2]
     // one block per (field, tile): a block's LDS holds one field, so a two-field
     // spread keeps the occupancy of a one-field one
@@ -233,30 +245,42 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
         for (uint32_t i0 = s0; i0 < s1; i0 += SPREAD_FLUSH) {
             const uint32_t i1 = min(s1, i0 + SPREAD_FLUSH);
 #pragma unroll
-            for (int g0 = 0; g0 < M2; g0 += RG) {
-                float r[RG][M2];
+            for (int g = 0; g < NG; ++g) {
+                const int a0 = g * PPG;  // first row pair of the group
+                // r[2k] is row a0 + k, r[2k + 1] is row 2m - 1 - (a0 + k)
+                float r[2 * PPG][M2];
 #pragma unroll
-                for (int bb = 0; bb < RG; ++bb)
+                for (int k = 0; k < 2 * PPG; ++k)
 #pragma unroll
-                    for (int a = 0; a < M2; ++a) r[bb][a] = 0.f;
+                    for (int a = 0; a < M2; ++a) r[k][a] = 0.f;
                 for (uint32_t i = i0; i < i1; ++i) {
                     const float v = fval[i];
-                    float wx[M2], wy[M2];
+                    float wx[M2];
                     taps<float, M2>(wp, fr32[i], 0.f, 0.f, 0.f, wx);
-                    taps<float, M2>(wp, fr32[N + i], 0.f, 0.f, 0.f, wy);
+                    const float uy = fmaf(2.0f, fr32[N + i], -1.0f), vy2 = uy * uy;
 #pragma unroll
-                    for (int bb = 0; bb < RG; ++bb) {
-                        const float vy = g0 + bb < M2 ? v * wy[g0 + bb < M2 ? g0 + bb : 0] : 0.f;
+                    for (int k = 0; k < PPG; ++k) {
+                        if (a0 + k >= m) break;
+                        float ylo, yhi;
+                        tap_pair(wp, a0 + k, uy, vy2, ylo, yhi);
+                        const float vl = v * ylo, vh = v * yhi;
 #pragma unroll
-                        for (int a = 0; a < M2; ++a) r[bb][a] = fmaf(vy, wx[a], r[bb][a]);
+                        for (int a = 0; a < M2; ++a) {
+                            r[2 * k][a] = fmaf(vl, wx[a], r[2 * k][a]);
+                            r[2 * k + 1][a] = fmaf(vh, wx[a], r[2 * k + 1][a]);
+                        }
                     }
                 }
-                double *af = myacc + (ly + g0) * PT + lx;
 #pragma unroll
-                for (int bb = 0; bb < RG; ++bb)
-                    if (g0 + bb < M2)
+                for (int k = 0; k < PPG; ++k) {
+                    if (a0 + k >= m) break;
+                    double *alo = myacc + (ly + a0 + k) * PT + lx;
+                    double *ahi = myacc + (ly + M2 - 1 - (a0 + k)) * PT + lx;
 #pragma unroll
-                        for (int a = 0; a < M2; ++a) atomicAdd(af + bb * PT + a, (double)r[bb][a]);
+                    for (int a = 0; a < M2; ++a) atomicAdd(alo + a, (double)r[2 * k][a]);
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) atomicAdd(ahi + a, (double)r[2 * k + 1][a]);
+                }
             }
         }
     }
@@ -437,6 +461,17 @@ __global__ void __launch_bounds__(SUMB) k_sum_partial(const double *__restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// k_spread_cells<M2, NG> when a group holds at most 144 register sums (else NULL, and the
+// variant is not instantiated)
+using SpreadCellsKernel = void (*)(const float *, const float *, int64_t, const uint32_t *, int, int, int, int,
+                                   double *, const WinPoly);
+template <int M2, int NG>
+SpreadCellsKernel spread_cells_kernel()
+{
+    if constexpr (2 * ((M2 / 2 + NG - 1) / NG) * M2 <= 144) return k_spread_cells<M2, NG>;
+    else return nullptr;
+}
+
 template <typename R, int M2>
 hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
                     double *ptile, hipStream_t st)
@@ -447,7 +482,12 @@ hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, con
     const int64_t N = set_size(g, set);
 #if FN_SPREAD_CELLS
     if (std::is_same<R, float>::value) {
-        auto kc = k_spread_cells<M2>;
+        // row groups of the register footprint (at most 144 sums per group)
+        const int ng = P.spread_ng ? P.spread_ng : spread_default_groups(M2 / 2);
+        const SpreadCellsKernel kc = ng == 1 ? spread_cells_kernel<M2, 1>()
+                                             : (ng == 2 ? spread_cells_kernel<M2, 2>()
+                                                        : (ng == 3 ? spread_cells_kernel<M2, 3>() : nullptr));
+        if (!kc) return hipErrorInvalidValue;
         const size_t lds1 = (size_t)SPREAD_WAVES * PT * PT * sizeof(double);
         hipError_t e = hipFuncSetAttribute((const void *)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
         if (e != hipSuccess) return e;
