@@ -11,7 +11,7 @@ Workload (default): rounded square of side 4 (corner radius 1/2), about 2^24
 jittered-lattice targets and 2^24 + 31k sources (cell points with charge
 -div M, boundary Gauss points with M.n), M a unit field whose angle is a sum of
 32 random cosine modes; FP32-mixed path, FFT grid 8192^2, bandwidth n = 6144,
-Kaiser-Bessel m = 6, regularization degree p = 5; the volume sources use the
+Kaiser-Bessel m = 5, regularization degree p = 5; the volume sources use the
 near radius eps_I = 3.25/n, the 31k boundary Gauss points (surface sources) their
 own eps_S = 11/n (fn_set_geometry_split); boundary regularization zone eps_B = 1/32
 (the torus map scales the workload to a distance of at most 1/2 - eps_B).
@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 24, help="about this many targets (and sources)")
     ap.add_argument("--grid", type=int, default=8192)
-    ap.add_argument("--m", type=int, default=6)
+    ap.add_argument("--m", type=int, default=5)
     ap.add_argument("--p", type=int, default=5)
     ap.add_argument("--c", type=float, default=3.25,
                     help="eps_I = c / n for the volume sources (all sources when --cs 0)")
@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--shapes", type=str, default=None,
                     help="kernel work shapes as JSON (fn_set_shapes fields), e.g. '{\"spread_groups\": 1}'; "
                          "default: the autotuner's cache entry for this workload, else the library defaults")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default shapes instead of the autotuner's (cached, or tuned before the timed region)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one elementwise kernel over 256 MiB (read and write) before the timed region, "
                          "as the byte-counter calibration for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
@@ -116,6 +118,18 @@ def main():
         S.set_geometry(ty, tx, tw, n_surf=n_surf)
         torch.cuda.synchronize()
         t_geom = time.perf_counter() - g0
+        # kernel work shapes: given, or the autotuner's (a cache hit, or a search on this data
+        # before the timed region)
+        tune_rec = {"source": "library defaults"}
+        if args.shapes:
+            S.set_shapes(**json.loads(args.shapes))
+            tune_rec = {"source": "--shapes"}
+        elif not args.no_tune:
+            from paper_0807_2387_amd import tune
+            t1 = time.perf_counter()
+            _, key, now = tune.apply(S, tq, tV, log=log)
+            tune_rec = {"source": "autotuner, searched now" if now else "autotuner cache", "key": key,
+                        "search_s": round(time.perf_counter() - t1, 2) if now else 0.0}
         phi = torch.empty(nt, dtype=torch.float64, device=dev)
         H = torch.empty(nt, 2, dtype=torch.float64, device=dev)
         u = torch.empty(ns, dtype=torch.float64, device=dev)
@@ -148,7 +162,8 @@ def main():
         if profile:
             S.set_profiling(False)
         info = S.info()
-        return dict(sec=el / steps, t_geom=t_geom, prof=prof, info=info, phi=phi, H=H, u=u, S=S)
+        return dict(sec=el / steps, t_geom=t_geom, prof=prof, info=info, phi=phi, H=H, u=u, S=S,
+                    shapes=S.shapes(), tune=tune_rec)
 
     r = run(fn.FN_FP32_MIXED, args.steps, args.warmup, True)
     ms = r["sec"] * 1e3
@@ -177,7 +192,9 @@ def main():
                    "eps_I": eps_I, "eps_S": eps_S, "n_surf": n_surf, "precision": "fp32_mixed",
                    "eps_B": args.eps_b,
                    "overlap": not args.no_overlap,
-                   "parallelism": "single_gpu"},
+                   "parallelism": "single_gpu",
+                   "near_field": "FP64 offsets, polynomial and sums; FP32 ln x and 1/x per pair",
+                   "shapes": r["shapes"], "shapes_from": r["tune"]},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "stage_spans_overlap": not args.no_overlap,
         "set_geometry_ms": r["t_geom"] * 1e3,

@@ -237,7 +237,7 @@ class Solver:
         return E, g
 
     SHAPE_KEYS = ("spread_groups", "near_fwd_bx", "near_fwd_by", "near_fwd_cap", "near_adj_bx", "near_adj_by",
-                  "near_adj_cap")
+                  "near_adj_cap", "tile")
 
     def set_shapes(self, **shapes):
         """Kernel work shapes (fn_set_shapes); unnamed fields keep the library default."""

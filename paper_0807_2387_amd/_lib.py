@@ -58,7 +58,7 @@ class Shapes(ctypes.Structure):
     _fields_ = [("spread_groups", ctypes.c_int32),
                 ("near_fwd_bx", ctypes.c_int32), ("near_fwd_by", ctypes.c_int32), ("near_fwd_cap", ctypes.c_int32),
                 ("near_adj_bx", ctypes.c_int32), ("near_adj_by", ctypes.c_int32), ("near_adj_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("tile", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):

@@ -226,8 +226,12 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
     L.emax = P.G / 2 + 2 * P.m + 4;
     L.ldS = (L.emax + 63) / 64 * 64;
     const int64_t ncell = L.emax * L.emax;
-    const int64_t tiles1 = (L.emax + TILE - 1) / TILE;
-    const int64_t PT = TILE + 2 * P.m - 1;
+    // padded tile partial sums: the larger of the two tile edges' layouts
+    int64_t ptile_cells = 0;
+    for (int t = TILE_MIN; t <= TILE_MAX; t *= 2) {
+        const int64_t nt1 = (L.emax + t - 1) / t, pt = t + 2 * P.m - 1;
+        ptile_cells = std::max(ptile_cells, nt1 * nt1 * pt * pt);
+    }
     const int64_t nmax = std::max<int64_t>(std::max(nt, ns), 1);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -254,7 +258,7 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
     L.off_val64 = take(N[1] * 8);
     L.off_aval = take(2 * N[0] * rs);
     L.off_aval64 = take(2 * N[0] * 8);
-    L.off_ptile = take((size_t)2 * tiles1 * tiles1 * PT * PT * 8);
+    L.off_ptile = take((size_t)2 * ptile_cells * 8);
     L.off_grid = take((size_t)3 * ncell * rs);
     // spectra: 2 fields each for input and output; the region also hosts the
     // n x n FP64 complex scratch of the plan FFT
@@ -267,7 +271,7 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
     L.off_grid_a = take((size_t)3 * ncell * rs);
     L.off_spec_a = take(specb);
     L.off_spec2_a = take(specb);
-    L.off_ptile_a = take((size_t)2 * tiles1 * tiles1 * PT * PT * 8);
+    L.off_ptile_a = take((size_t)2 * ptile_cells * 8);
     L.off_far_a = take((size_t)nmax * 8);  // the adjoint gathers one field
     L.off_red = take(16384 * 8);  // see the RED_* slots below
     L.nblk_cap = near_blocks_bound(L.emax);  // near-field home blocks of the largest window
@@ -711,7 +715,7 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
         g.ext[d] = whi - wlo;
         if (g.ext[d] > L.emax || wlo < 0 || whi > P.G)
             FN_SET_ERR(c, FN_E_DEVICE, "internal: data window exceeds its bound");
-        g.ntile[d] = (g.ext[d] + TILE - 1) / TILE;
+        g.ntile[d] = (g.ext[d] + P.tile - 1) / P.tile;
     }
     g.rnear = (int)std::ceil(P.eps_I * P.G);
     // a second source class only when the plan has a surface radius
@@ -853,11 +857,11 @@ static int eval_impl(fn_ctx *c, double *phi, double *H, hipStream_t st)
     // with surface sources the two classes are spread as two fields and meet in the
     // column pass, each times its own multiplier table: sum_k W_k F_k
     const int ncls = g.nsurf > 0 ? 2 : 1;
-    const size_t tfield = (size_t)g.ntile[0] * g.ntile[1] * (TILE + 2 * P.m - 1) * (TILE + 2 * P.m - 1);
+    const size_t tfield = (size_t)g.ntile[0] * g.ntile[1] * (P.tile + 2 * P.m - 1) * (P.tile + 2 * P.m - 1);
     const char *val_s = static_cast<const char *>(B.val) + set_base(g, 2) * rs;
     FN_STAGE(c, FN_ST_SPREAD, launch_spread(prec, P, g, 1, B, B.val, 1, B.ptile, st));
     if (ncls == 2) FN_STAGE(c, FN_ST_SPREAD, launch_spread(prec, P, g, 2, B, val_s, 1, B.ptile + tfield, st));
-    FN_STAGE(c, FN_ST_FOLD, launch_fold(prec, g, P.m, B.ptile, ncls, B.grid, fstride, st));
+    FN_STAGE(c, FN_ST_FOLD, launch_fold(prec, g, P.m, P.tile, B.ptile, ncls, B.grid, fstride, st));
     FN_STAGE(c, FN_ST_ROWS_FWD, launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], ncls, B.spec,
                                                 ldS, sfstride, B.tw, st));
     FN_STAGE(c, FN_ST_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1], COL_FWD,
@@ -934,7 +938,7 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind, hipStr
                                                   kind == 1 ? B.red + RED_VPART : nullptr, &nbv, st));
     if (kind == 1) FN_STAGE(c, FN_ST_A_VALUES, launch_sum_partials(B.red + RED_VPART, nbv, B.red + RED_SUMV, st));
     FN_STAGE(c, FN_ST_A_SPREAD, launch_spread(prec, P, g, 0, B, B.aval, nf, B.ptile, st));
-    FN_STAGE(c, FN_ST_A_FOLD, launch_fold(prec, g, P.m, B.ptile, nf, B.grid, fstride, st));
+    FN_STAGE(c, FN_ST_A_FOLD, launch_fold(prec, g, P.m, P.tile, B.ptile, nf, B.grid, fstride, st));
     FN_STAGE(c, FN_ST_A_ROWS_FWD,
              launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], nf, B.spec, ldS, sfstride, B.tw, st));
     FN_STAGE(c, FN_ST_A_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
@@ -1079,9 +1083,13 @@ int fn_set_shapes(fn_ctx *ctx, const fn_shapes *shapes)
     const NearShape a = pick(shapes->near_adj_bx, shapes->near_adj_by, shapes->near_adj_cap, NearShape{32, 8, 512});
     if (!near_shape_ok(f) || !near_shape_ok(a))
         FN_SET_ERR(ctx, FN_E_INVAL, "near-field shapes: 16 x 16, 32 x 8 or 64 x 4 cells, capacity a multiple of 64 in [128, 2048]");
+    const int tile = shapes->tile ? shapes->tile : 32;
+    if (tile != 16 && tile != 32) FN_SET_ERR(ctx, FN_E_INVAL, "tile must be 0, 16 or 32");
     P.spread_ng = ng;
     P.near_fwd = f;
     P.near_adj = a;
+    P.tile = tile;
+    for (int d = 0; d < 2; ++d) ctx->geom.ntile[d] = (ctx->geom.ext[d] + tile - 1) / tile;
     return FN_OK;
 }
 
@@ -1097,6 +1105,7 @@ int fn_get_shapes(const fn_ctx *ctx, fn_shapes *shapes)
     shapes->near_adj_bx = P.near_adj.bx;
     shapes->near_adj_by = P.near_adj.by;
     shapes->near_adj_cap = P.near_adj.cap;
+    shapes->tile = P.tile;
     return FN_OK;
 }
 

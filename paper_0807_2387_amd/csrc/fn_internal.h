@@ -12,7 +12,8 @@
 
 namespace fn {
 
-constexpr int TILE = 32;        // spread / gather tile edge in grid cells
+constexpr int TILE_MIN = 16;    // spread / gather tile edges in grid cells: 16 or 32 (Plan::tile)
+constexpr int TILE_MAX = 32;
 constexpr int MAXM = 8;         // largest window half-width
 constexpr int MAXP = 12;        // largest regularization degree
 constexpr int FFT_EPT = 8;      // complex elements held per thread in the LDS FFT
@@ -69,6 +70,7 @@ struct Plan {
     std::vector<double> cB;          // boundary polynomial in t = (r - r_B)/eps_B
     std::vector<double> psihat;      // window transform at l/G, l = 0..n/2
     int spread_ng = 0;               // row groups of the FP32 spread footprint (0: spread_default_groups)
+    int tile = 32;                   // spread / gather tile edge, cells (16 or 32)
     NearShape near_fwd{32, 8, 1024}; // near-field shape of the forward volume-class kernel
     NearShape near_adj{32, 8, 512};  // ... and of the adjoint one
     // FFT twiddles e^{-2 pi i k/N} computed at fn_create: length G in the grid precision
@@ -85,7 +87,7 @@ struct Geom {
     double s = 0;
     int32_t wlo[2] = {0, 0};
     int32_t ext[2] = {0, 0};         // window extent (cells) x, y
-    int32_t ntile[2] = {0, 0};       // TILE tiles per dim
+    int32_t ntile[2] = {0, 0};       // spread / gather tiles per dim (of the plan's tile edge)
     int32_t rnear = 0;               // near radius in cells
     int64_t near_pairs = 0;          // pairs closer than eps_I
     int64_t coincident = 0;          // (target, source) pairs at exactly the same position
@@ -106,7 +108,7 @@ inline int64_t set_base(const Geom &g, int s) { return s == 2 ? g.ns - g.nsurf :
 // Row groups of the FP32 spread's register footprint for window half-width m: every
 // group holds whole row pairs, at most 72 FP32 sums per group by default (one group of
 // 4 m^2 sums at m <= 4).
-inline int spread_default_groups(int m) { return m <= 4 ? 1 : (m <= 6 ? 2 : 3); }
+inline int spread_default_groups(int m) { return m <= 5 ? 1 : (m <= 6 ? 2 : 3); }
 
 // Device arrays carved out of the caller's workspace.
 struct Buffers {
@@ -247,7 +249,7 @@ hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 // spread / fold / gather
 hipError_t launch_spread(int precision, const Plan &P, const Geom &g, int set, const Buffers &b,
                          const void *val, int nfield, double *ptile, hipStream_t st);
-hipError_t launch_fold(int precision, const Geom &g, int m, const double *ptile, int nfield, void *grid,
+hipError_t launch_fold(int precision, const Geom &g, int m, int tile, const double *ptile, int nfield, void *grid,
                        int64_t fstride, hipStream_t st);
 hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, const Buffers &b,
                          const void *grid, int nfield, int64_t fstride, double *far, int64_t farstride,

@@ -9,8 +9,9 @@
 // which equals sinh(b z) / (pi z I0(m b)); zero for |t| >= m.  A point with grid
 // coordinate u has taps k = floor(u) - m + 1 + a, a = 0..2m-1, at t = u - k.
 //
-// Spread: one workgroup per TILE x TILE tile of base cells.  Every wave owns a
-// private FP64 accumulator for the padded tile (TILE + 2m - 1 cells a side) in
+// Spread: one workgroup per T x T tile of base cells (T = 16 or 32, a run-time shape:
+// smaller tiles make more workgroups for small grids).  Every wave owns a
+// private FP64 accumulator for the padded tile (T + 2m - 1 cells a side) in
 // LDS; the window products (FP32 or FP64) are added with LDS atomics that only
 // that wave touches, so the summation order is fixed and no global atomics are
 // used.  The wave copies are summed in a fixed order into a per-tile buffer, and
@@ -80,17 +81,19 @@ template <> __device__ __forceinline__ double frac_of<double>(const float *, con
     return f64[i];
 }
 
-// rows [y0, y0 + TILE) x cells [x0, x1) of a cell-sorted point set: per-row start and prefix
+// rows [y0, y0 + TL) x cells [x0, x1) of a cell-sorted point set: per-row start and prefix
+template <int TL>
 struct TileRows {
-    uint32_t start[TILE];
-    uint32_t pre[TILE + 1];
+    uint32_t start[TL];
+    uint32_t pre[TL + 1];
 };
 
-__device__ __forceinline__ void tile_rows(TileRows &tr, const uint32_t *__restrict__ cstart, int Ex, int Ey,
+template <int TL>
+__device__ __forceinline__ void tile_rows(TileRows<TL> &tr, const uint32_t *__restrict__ cstart, int Ex, int Ey,
                                           int x0, int y0)
 {
-    const int x1 = min(x0 + TILE, Ex);
-    if (threadIdx.x < TILE) {
+    const int x1 = min(x0 + TL, Ex);
+    if (threadIdx.x < TL) {
         const int y = y0 + threadIdx.x;
         uint32_t s = 0, e = 0;
         if (y < Ey) {
@@ -103,14 +106,15 @@ __device__ __forceinline__ void tile_rows(TileRows &tr, const uint32_t *__restri
     __syncthreads();
     if (threadIdx.x == 0) {
         tr.pre[0] = 0;
-        for (int r = 1; r <= TILE; ++r) tr.pre[r] += tr.pre[r - 1];
+        for (int r = 1; r <= TL; ++r) tr.pre[r] += tr.pre[r - 1];
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ int64_t tile_point(const TileRows &tr, uint32_t k)
+template <int TL>
+__device__ __forceinline__ int64_t tile_point(const TileRows<TL> &tr, uint32_t k)
 {
-    int lo = 0, hi = TILE - 1;  // largest r with pre[r] <= k
+    int lo = 0, hi = TL - 1;  // largest r with pre[r] <= k
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (tr.pre[mid] <= k) lo = mid; else hi = mid - 1;
@@ -118,7 +122,7 @@ __device__ __forceinline__ int64_t tile_point(const TileRows &tr, uint32_t k)
     return (int64_t)tr.start[lo] + (k - tr.pre[lo]);
 }
 
-template <typename R, int M2>
+template <typename R, int M2, int TL>
 __global__ void __launch_bounds__(SPREAD_NT) k_spread(const uint32_t *__restrict__ key, const float *__restrict__ fr32,
                                                       const double *__restrict__ fr64, const R *__restrict__ val,
                                                       int64_t N, const uint32_t *__restrict__ cstart, int Ex, int Ey,
@@ -126,17 +130,17 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread(const uint32_t *__restrict
                                                       double *__restrict__ ptile, const WinPoly wp)
 {
     constexpr int m = M2 / 2;
-    constexpr int PT = TILE + M2 - 1;
+    constexpr int PT = TL + M2 - 1;
     constexpr int PT2 = PT * PT;
     extern __shared__ double acc[];  // [SPREAD_WAVES][nfield][PT2]
-    __shared__ TileRows tr;
+    __shared__ TileRows<TL> tr;
     const int tile = blockIdx.x;
     const int tx = tile % ntx, ty = tile / ntx;
-    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int x0 = tx * TL, y0 = ty * TL;
     const int wv = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < SPREAD_WAVES * nfield * PT2; i += SPREAD_NT) acc[i] = 0.0;
     tile_rows(tr, cstart, Ex, Ey, x0, y0);
-    const uint32_t P = tr.pre[TILE];
+    const uint32_t P = tr.pre[TL];
     double *myacc = acc + (int64_t)wv * nfield * PT2;
     const R rm = (R)m, rb = (R)b, rw = (R)wnorm;
     for (uint32_t k = threadIdx.x; k < P; k += SPREAD_NT) {
@@ -186,7 +190,7 @@ __device__ __forceinline__ void tap_pair(const WinPoly &wp, int a, float u, floa
 // all 4m^2 sums in registers.  The lanes of a wave hold consecutive cells of a tile row,
 // so every LDS atomic instruction touches consecutive addresses.  Same accumulator layout
 // and fixed per-wave summation order as k_spread.
-template <int M2, int NG>
+template <int M2, int NG, int TL>
 __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restrict__ fr32,
                                                             const float *__restrict__ val, int64_t N,
                                                             const uint32_t *__restrict__ cstart, int Ex, int Ey,
@@ -194,7 +198,7 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
                                                             const WinPoly wp)
 {
     constexpr int m = M2 / 2;
-    constexpr int PT = TILE + M2 - 1;
+    constexpr int PT = TL + M2 - 1;
     constexpr int PT2 = PT * PT;
     constexpr int PPG = (m + NG - 1) / NG;  // row pairs per group
     extern __shared__ double acc[];  // [SPREAD_WAVES][PT2]
@@ -204,15 +208,15 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
     const int f = blockIdx.x / ntiles;
     const int tile = blockIdx.x - f * ntiles;
     const int tx = tile % ntx, ty = tile / ntx;
-    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int x0 = tx * TL, y0 = ty * TL;
     const int wv = threadIdx.x >> 6;
     // an empty tile (a sparse point set) only writes its zero partial sums
     __shared__ int tile_pts;
     if (threadIdx.x == 0) tile_pts = 0;
     __syncthreads();
-    if (threadIdx.x < TILE && y0 + (int)threadIdx.x < Ey && x0 < Ex) {
+    if (threadIdx.x < TL && y0 + (int)threadIdx.x < Ey && x0 < Ex) {
         const int64_t rb = (int64_t)(y0 + threadIdx.x) * Ex;
-        if (cstart[rb + min(x0 + TILE, Ex)] != cstart[rb + x0]) atomicOr(&tile_pts, 1);
+        if (cstart[rb + min(x0 + TL, Ex)] != cstart[rb + x0]) atomicOr(&tile_pts, 1);
     }
     __syncthreads();
     if (tile_pts == 0) {  // uniform
@@ -225,9 +229,9 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
     const float *fval = val + (int64_t)f * N;
     // point range of cell c of the tile (empty outside the grid)
     auto cell_range = [&](int c, uint32_t &a, uint32_t &b) {
-        const int gx = x0 + c % TILE, gy = y0 + c / TILE;
+        const int gx = x0 + c % TL, gy = y0 + c / TL;
         a = b = 0;
-        if (c < TILE * TILE && gx < Ex && gy < Ey) {
+        if (c < TL * TL && gx < Ex && gy < Ey) {
             const int64_t cell = (int64_t)gy * Ex + gx;
             a = cstart[cell];
             b = cstart[cell + 1];
@@ -235,8 +239,8 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
     };
     uint32_t n0, n1;
     cell_range(threadIdx.x, n0, n1);
-    for (int c = threadIdx.x; c < TILE * TILE; c += SPREAD_NT) {
-        const int lx = c % TILE, ly = c / TILE;
+    for (int c = threadIdx.x; c < TL * TL; c += SPREAD_NT) {
+        const int lx = c % TL, ly = c / TL;
         const uint32_t s0 = n0, s1 = n1;
         cell_range(c + SPREAD_NT, n0, n1);  // the next cell's range loads while this one runs
         if (s0 == s1) continue;
@@ -293,7 +297,7 @@ __global__ void __launch_bounds__(SPREAD_NT) k_spread_cells(const float *__restr
 }
 
 template <typename R>
-__global__ void k_fold(const double *__restrict__ ptile, int Ex, int Ey, int ntx, int nty, int PT, int nfield,
+__global__ void k_fold(const double *__restrict__ ptile, int Ex, int Ey, int ntx, int nty, int TILE, int PT, int nfield,
                        R *__restrict__ grid, int64_t fstride)
 {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -312,7 +316,7 @@ __global__ void k_fold(const double *__restrict__ ptile, int Ex, int Ey, int ntx
     }
 }
 
-template <typename R, int M2>
+template <typename R, int M2, int TL>
 __global__ void __launch_bounds__(256) k_gather(const uint32_t *__restrict__ key, const float *__restrict__ fr32,
                                                 const double *__restrict__ fr64, int64_t N,
                                                 const uint32_t *__restrict__ cstart, int Ex, int Ey, int ntx,
@@ -321,16 +325,16 @@ __global__ void __launch_bounds__(256) k_gather(const uint32_t *__restrict__ key
                                                 int64_t farstride, const WinPoly wp)
 {
     constexpr int m = M2 / 2;
-    constexpr int PT = TILE + M2 - 1;
+    constexpr int PT = TL + M2 - 1;
     constexpr int PT2 = PT * PT;
     extern __shared__ char smem_g[];
     R *L = reinterpret_cast<R *>(smem_g);  // [nfield][PT2]
-    __shared__ TileRows tr;
+    __shared__ TileRows<TL> tr;
     const int tile = blockIdx.x;
     const int tx = tile % ntx, ty = tile / ntx;
-    const int x0 = tx * TILE, y0 = ty * TILE;
+    const int x0 = tx * TL, y0 = ty * TL;
     tile_rows(tr, cstart, Ex, Ey, x0, y0);
-    const uint32_t P = tr.pre[TILE];
+    const uint32_t P = tr.pre[TL];
     if (P == 0) return;  // uniform across the block
     for (int f = 0; f < nfield; ++f)
         for (int c = threadIdx.x; c < PT2; c += blockDim.x) {
@@ -461,76 +465,103 @@ __global__ void __launch_bounds__(SUMB) k_sum_partial(const double *__restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// k_spread_cells<M2, NG> when a group holds at most 144 register sums (else NULL, and the
-// variant is not instantiated)
+// k_spread_cells<M2, NG, TL> when a group holds at most 144 register sums (else NULL, and
+// the variant is not instantiated)
 using SpreadCellsKernel = void (*)(const float *, const float *, int64_t, const uint32_t *, int, int, int, int,
                                    double *, const WinPoly);
-template <int M2, int NG>
+template <int M2, int NG, int TL>
 SpreadCellsKernel spread_cells_kernel()
 {
-    if constexpr (2 * ((M2 / 2 + NG - 1) / NG) * M2 <= 144) return k_spread_cells<M2, NG>;
+    if constexpr (2 * ((M2 / 2 + NG - 1) / NG) * M2 <= 144) return k_spread_cells<M2, NG, TL>;
     else return nullptr;
 }
 
-template <typename R, int M2>
+template <typename R, int M2, int TL>
 hipError_t spread_t(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
                     double *ptile, hipStream_t st)
 {
-    constexpr int PT = TILE + M2 - 1;
-    const int ntiles = g.ntile[0] * g.ntile[1];
+    constexpr int PT = TL + M2 - 1;
+    const int ntx = (g.ext[0] + TL - 1) / TL, nty = (g.ext[1] + TL - 1) / TL;
+    const int ntiles = ntx * nty;
     const size_t lds = (size_t)SPREAD_WAVES * nfield * PT * PT * sizeof(double);
     const int64_t N = set_size(g, set);
 #if FN_SPREAD_CELLS
     if (std::is_same<R, float>::value) {
         // row groups of the register footprint (at most 144 sums per group)
         const int ng = P.spread_ng ? P.spread_ng : spread_default_groups(M2 / 2);
-        const SpreadCellsKernel kc = ng == 1 ? spread_cells_kernel<M2, 1>()
-                                             : (ng == 2 ? spread_cells_kernel<M2, 2>()
-                                                        : (ng == 3 ? spread_cells_kernel<M2, 3>() : nullptr));
+        const SpreadCellsKernel kc = ng == 1 ? spread_cells_kernel<M2, 1, TL>()
+                                             : (ng == 2 ? spread_cells_kernel<M2, 2, TL>()
+                                                        : (ng == 3 ? spread_cells_kernel<M2, 3, TL>() : nullptr));
         if (!kc) return hipErrorInvalidValue;
         const size_t lds1 = (size_t)SPREAD_WAVES * PT * PT * sizeof(double);
         hipError_t e = hipFuncSetAttribute((const void *)kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
         if (e != hipSuccess) return e;
         kc<<<ntiles * nfield, SPREAD_NT, lds1, st>>>(b.fr32[set], (const float *)val, N, b.cstart[set], g.ext[0],
-                                                     g.ext[1], g.ntile[0], g.ntile[1], ptile, P.wpoly);
+                                                     g.ext[1], ntx, nty, ptile, P.wpoly);
         return hipGetLastError();
     }
 #endif
-    auto kern = k_spread<R, M2>;
+    auto kern = k_spread<R, M2, TL>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     kern<<<ntiles, SPREAD_NT, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], (const R *)val, N,
-                                         b.cstart[set], g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], P.kb_b,
+                                         b.cstart[set], g.ext[0], g.ext[1], ntx, nty, P.kb_b,
                                          P.win_norm, nfield, ptile, P.wpoly);
     return hipGetLastError();
 }
 
-template <typename R, int M2>
+template <typename R, int M2, int TL>
 hipError_t gather_t(const Plan &P, const Geom &g, int set, const Buffers &b, const void *grid, int nfield,
                     int64_t fstride, double *far, int64_t farstride, hipStream_t st)
 {
-    constexpr int PT = TILE + M2 - 1;
-    const int ntiles = g.ntile[0] * g.ntile[1];
+    constexpr int PT = TL + M2 - 1;
+    const int ntx = (g.ext[0] + TL - 1) / TL, nty = (g.ext[1] + TL - 1) / TL;
+    const int ntiles = ntx * nty;
     const size_t lds = (size_t)nfield * PT * PT * sizeof(R);
     const int64_t N = set_size(g, set);
-    k_gather<R, M2><<<ntiles, 256, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], N, b.cstart[set], g.ext[0],
-                                             g.ext[1], g.ntile[0], P.kb_b, P.win_norm, (const R *)grid,
-                                             fstride, nfield, far, farstride, P.wpoly);
+    k_gather<R, M2, TL><<<ntiles, 256, lds, st>>>(b.key[set], b.fr32[set], b.fr64[set], N, b.cstart[set], g.ext[0],
+                                                 g.ext[1], ntx, P.kb_b, P.win_norm, (const R *)grid,
+                                                 fstride, nfield, far, farstride, P.wpoly);
     return hipGetLastError();
+}
+
+template <typename R, int TL>
+hipError_t spread_mt(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
+                     double *ptile, hipStream_t st)
+{
+    switch (P.m) {
+    case 2: return spread_t<R, 4, TL>(P, g, set, b, val, nfield, ptile, st);
+    case 3: return spread_t<R, 6, TL>(P, g, set, b, val, nfield, ptile, st);
+    case 4: return spread_t<R, 8, TL>(P, g, set, b, val, nfield, ptile, st);
+    case 5: return spread_t<R, 10, TL>(P, g, set, b, val, nfield, ptile, st);
+    case 6: return spread_t<R, 12, TL>(P, g, set, b, val, nfield, ptile, st);
+    case 7: return spread_t<R, 14, TL>(P, g, set, b, val, nfield, ptile, st);
+    case 8: return spread_t<R, 16, TL>(P, g, set, b, val, nfield, ptile, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename R>
 hipError_t spread_m(const Plan &P, const Geom &g, int set, const Buffers &b, const void *val, int nfield,
                     double *ptile, hipStream_t st)
 {
+    if (P.tile == 16) return spread_mt<R, 16>(P, g, set, b, val, nfield, ptile, st);
+    if (P.tile == 32) return spread_mt<R, 32>(P, g, set, b, val, nfield, ptile, st);
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int TL>
+hipError_t gather_mt(const Plan &P, const Geom &g, int set, const Buffers &b, const void *grid, int nfield,
+                     int64_t fstride, double *far, int64_t farstride, hipStream_t st)
+{
     switch (P.m) {
-    case 2: return spread_t<R, 4>(P, g, set, b, val, nfield, ptile, st);
-    case 3: return spread_t<R, 6>(P, g, set, b, val, nfield, ptile, st);
-    case 4: return spread_t<R, 8>(P, g, set, b, val, nfield, ptile, st);
-    case 5: return spread_t<R, 10>(P, g, set, b, val, nfield, ptile, st);
-    case 6: return spread_t<R, 12>(P, g, set, b, val, nfield, ptile, st);
-    case 7: return spread_t<R, 14>(P, g, set, b, val, nfield, ptile, st);
-    case 8: return spread_t<R, 16>(P, g, set, b, val, nfield, ptile, st);
+    case 2: return gather_t<R, 4, TL>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 3: return gather_t<R, 6, TL>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 4: return gather_t<R, 8, TL>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 5: return gather_t<R, 10, TL>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 6: return gather_t<R, 12, TL>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 7: return gather_t<R, 14, TL>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    case 8: return gather_t<R, 16, TL>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -539,16 +570,9 @@ template <typename R>
 hipError_t gather_m(const Plan &P, const Geom &g, int set, const Buffers &b, const void *grid, int nfield, int64_t fstride,
                     double *far, int64_t farstride, hipStream_t st)
 {
-    switch (P.m) {
-    case 2: return gather_t<R, 4>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
-    case 3: return gather_t<R, 6>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
-    case 4: return gather_t<R, 8>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
-    case 5: return gather_t<R, 10>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
-    case 6: return gather_t<R, 12>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
-    case 7: return gather_t<R, 14>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
-    case 8: return gather_t<R, 16>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (P.tile == 16) return gather_mt<R, 16>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    if (P.tile == 32) return gather_mt<R, 32>(P, g, set, b, grid, nfield, fstride, far, farstride, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -562,17 +586,18 @@ hipError_t launch_spread(int precision, const Plan &P, const Geom &g, int set, c
                                 : spread_m<float>(P, g, set, b, val, nfield, ptile, st);
 }
 
-hipError_t launch_fold(int precision, const Geom &g, int m, const double *ptile, int nfield, void *grid,
+hipError_t launch_fold(int precision, const Geom &g, int m, int tile, const double *ptile, int nfield, void *grid,
                        int64_t fstride, hipStream_t st)
 {
     const int64_t tot = (int64_t)g.ext[0] * g.ext[1];
     const int nb = (int)((tot + 255) / 256);
-    const int PT = TILE + 2 * m - 1;
+    const int PT = tile + 2 * m - 1;
+    const int ntx = (g.ext[0] + tile - 1) / tile, nty = (g.ext[1] + tile - 1) / tile;
     if (precision == FN_FP64)
-        k_fold<double><<<nb, 256, 0, st>>>(ptile, g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], PT, nfield,
+        k_fold<double><<<nb, 256, 0, st>>>(ptile, g.ext[0], g.ext[1], ntx, nty, tile, PT, nfield,
                                            (double *)grid, fstride);
     else
-        k_fold<float><<<nb, 256, 0, st>>>(ptile, g.ext[0], g.ext[1], g.ntile[0], g.ntile[1], PT, nfield,
+        k_fold<float><<<nb, 256, 0, st>>>(ptile, g.ext[0], g.ext[1], ntx, nty, tile, PT, nfield,
                                           (float *)grid, fstride);
     return hipGetLastError();
 }

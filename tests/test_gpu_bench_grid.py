@@ -1,8 +1,9 @@
 """Parity with the step-by-step oracle (O2) at the grid sizes the bench runs, through the C-ABI.
 
 The small parity cases stop at G = 512, where an FFT block holds several short lines.  These
-cases run the shapes of the timed configuration itself: G = 2048 and G = 8192 (one line of
-G points per FFT block), bandwidth 3G/4, m = 6, p = 5, n eps_I = 3.25 for the volume
+cases run the shapes of the timed configuration itself: G = 2048 (m = 6) and G = 8192 (one
+line of G points per FFT block; the bench's m = 5 and the autotuner's kernel shapes),
+bandwidth 3G/4, p = 5, n eps_I = 3.25 for the volume
 sources and n eps_S = 11 for the boundary Gauss points, eps_B = 1/32, two source classes,
 forward and H adjoint in one overlapped call (as timed) plus the phi adjoint.  The points
 are the bench workload's recipe (rounded square, jittered lattice, boundary Gauss points)
@@ -23,8 +24,8 @@ from tests.conftest import max_rel, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
-# name, lattice points, G, seed
-GRIDS = [("G2048", 60_000, 2048, 91), ("G8192", 150_000, 8192, 92)]
+# name, lattice points, G, window half-width m, seed, tuned shapes
+GRIDS = [("G2048", 60_000, 2048, 6, 91, False), ("G8192", 150_000, 8192, 5, 92, True)]
 P_DEG, C_VOL, C_SURF, EPS_B = 5, 3.25, 11.0, 1.0 / 32.0
 
 
@@ -48,7 +49,7 @@ def dev(torch, a):
 _CACHE = {}
 
 
-def expected(name, N, G, seed):
+def expected(name, N, G, m, seed):
     """Inputs and the O2 outputs of one grid case (computed once per module)."""
     if name in _CACHE:
         return _CACHE[name]
@@ -60,8 +61,8 @@ def expected(name, N, G, seed):
     V = rng.standard_normal((len(y), 2))
     v = rng.standard_normal(len(y))
     band = 3 * G // 4
-    pv = fs.Params(G=G, m=6, p=P_DEG, eps_I=C_VOL / band, band=band, eps_B=EPS_B)
-    ps = fs.Params(G=G, m=6, p=P_DEG, eps_I=C_SURF / band, band=band, eps_B=EPS_B)
+    pv = fs.Params(G=G, m=m, p=P_DEG, eps_I=C_VOL / band, band=band, eps_B=EPS_B)
+    ps = fs.Params(G=G, m=m, p=P_DEG, eps_I=C_SURF / band, band=band, eps_B=EPS_B)
     out = []
     phi, H = 0.0, 0.0
     for sl, prm, other in ((slice(0, ns1), pv, slice(ns1, None)), (slice(ns1, None), ps, slice(0, ns1))):
@@ -79,16 +80,21 @@ def expected(name, N, G, seed):
 
 @pytest.mark.parametrize("case", GRIDS, ids=[c[0] for c in GRIDS])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_bench_grid_matches_step_by_step_oracle(torch, fn, case, precision):
-    name, N, G, seed = case
-    print(f"bench-grid case {name} {precision}: oracle", flush=True)
-    e = expected(name, N, G, seed)
+def test_bench_grid_matches_step_by_step_oracle(torch, fn, case, precision, tmp_path, monkeypatch):
+    name, N, G, m, seed, tuned = case
+    print(f"bench-grid case {name} m={m} {precision}: oracle", flush=True)
+    e = expected(name, N, G, m, seed)
     print(f"  {len(e['y'])} targets, {len(e['x'])} sources ({len(e['x']) - e['ns1']} surface); GPU", flush=True)
     P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
     band = e["band"]
-    S = fn.Solver(grid=G, m=6, p=P_DEG, eps_I=C_VOL / band, eps_S=C_SURF / band, eps_B=EPS_B, n=band,
+    S = fn.Solver(grid=G, m=m, p=P_DEG, eps_I=C_VOL / band, eps_S=C_SURF / band, eps_B=EPS_B, n=band,
                   precision=P)
     S.set_geometry(dev(torch, e["y"]), dev(torch, e["x"]), dev(torch, e["w"]), n_surf=len(e["x"]) - e["ns1"])
+    if tuned:  # the autotuner's shapes, as the bench runs them (searched here on this data)
+        from paper_0807_2387_amd import tune
+        monkeypatch.setenv("FEMNFFT_TUNE_CACHE", str(tmp_path / "tune.json"))
+        shapes, _, _ = tune.apply(S, dev(torch, e["q"]), dev(torch, e["V"]), reps=2)
+        print(f"  tuned shapes {shapes}", flush=True)
     info = S.info()
     # the data window of the timed configuration (about 0.36 G cells) and the FFT size
     assert 0.3 * G < info["win_ext"][0] < 0.4 * G, info["win_ext"]
