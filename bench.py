@@ -150,37 +150,53 @@ def main():
             torch.add(src, 1.0, out=dst)
             del src, dst
         torch.cuda.synchronize()
-        if profile:
-            S.set_profiling(True)
-        torch.cuda.synchronize()
         a = time.perf_counter()
         for _ in range(steps):
             step()
         torch.cuda.synchronize()
         el = time.perf_counter() - a
-        prof = S.profile() if profile else None
+        prof = None
         if profile:
+            # kernel durations: HIP events around every stage, recorded on the stream the
+            # stage runs on, over `steps` steps with the two directions one after the other
+            # (with the directions overlapped an event span would also hold the wait for CUs
+            # that the other direction's kernels occupy)
+            S.set_profiling(True)
+            for _ in range(steps):
+                S.set_charges(tq)
+                S.eval(out_phi=phi, out_H=H)
+                S.adjoint_H(tV, out=u)
+            torch.cuda.synchronize()
+            prof = S.profile()
             S.set_profiling(False)
         info = S.info()
         return dict(sec=el / steps, t_geom=t_geom, prof=prof, info=info, phi=phi, H=H, u=u, S=S,
                     shapes=S.shapes(), tune=tune_rec)
 
     r = run(fn.FN_FP32_MIXED, args.steps, args.warmup, True)
+    r["info"]["tile"] = r["shapes"]["tile"]
     ms = r["sec"] * 1e3
     value = (nt + ns) / r["sec"]
     log(f"FP32-mixed: {ms:.3f} ms/step, {value:.4e} points/s, set_geometry {r['t_geom'] * 1e3:.1f} ms")
     stages = {k: v[0] / max(args.steps, 1) for k, v in r["prof"].items() if v[1]}
+    log(f"  kernel time per step, the two directions one after the other: {sum(stages.values()):.3f} ms")
     for k, v in sorted(stages.items(), key=lambda kv: -kv[1]):
         log(f"  {k:12s} {v:9.3f} ms/step")
 
-    # dominant kernel and its roofline: the near field, which holds most of the step's
-    # arithmetic.  With the two directions overlapped, a grid stage of one direction that
-    # is queued behind the other's near field waits for free CUs inside its event span, so
-    # spans are not ranked when overlapped.
-    dom = max(stages, key=stages.get) if args.no_overlap else max(("near", "a_near"), key=lambda k: stages.get(k, 0))
-    dom_ms = stages[dom]
-    calls = r["prof"][dom][1] / max(args.steps, 1)
-    roof = roofline(dom, dom_ms / calls, calls, args, r["info"], nt, ns)
+    # dominant kernel (the largest kernel time per step) and the roofline of every stage
+    dom = max(stages, key=stages.get)
+    per_launch = lambda k: stages[k] / (r["prof"][k][1] / max(args.steps, 1))
+    roof = roofline(dom, per_launch(dom), None, args, r["info"], nt, ns)
+    roof_stages = {k: {kk: vv for kk, vv in roofline(k, per_launch(k), None, args, r["info"], nt, ns).items()
+                       if kk in ("bound", "achieved", "unit", "frac", "ms_per_launch")}
+                   for k in stages if k not in ("near_surf", "a_near_surf")}
+    sg = [k for k in ("spread", "gather", "a_spread", "a_gather") if k in stages]
+    sg_bytes = sum(roofline(k, per_launch(k), None, args, r["info"], nt, ns)["algorithmic_bytes_per_launch"]
+                   * r["prof"][k][1] / max(args.steps, 1) for k in sg)
+    sg_ms = sum(stages[k] for k in sg)
+    spread_gather = {"stages": sg, "algorithmic_bytes_per_step": sg_bytes, "ms_per_step": sg_ms,
+                     "achieved": sg_bytes / (sg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sg_bytes / (sg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     out = {
         "metric": "source+target points/s for forward+adjoint fast summation at <=1e-6 rel L2 vs FP64",
@@ -196,9 +212,11 @@ def main():
                    "near_field": "FP64 offsets, polynomial and sums; FP32 ln x and 1/x per pair",
                    "shapes": r["shapes"], "shapes_from": r["tune"]},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
-        "stage_spans_overlap": not args.no_overlap,
+        "stages_ms_from": "HIP events per stage on its stream, the two directions one after the other",
         "set_geometry_ms": r["t_geom"] * 1e3,
         "roofline": roof,
+        "roofline_stages": roof_stages,
+        "spread_gather_hbm": spread_gather,
     }
 
     if not args.no_cpu:
@@ -270,6 +288,18 @@ def roofline(stage, ms_per_launch, calls, args, info, nt, ns):
     elif stage in ("rows_inv", "a_rows_inv"):
         nin, nout = (2, 3) if stage == "rows_inv" else (1, 1)
         byts = nin * (nh + 1) * ey * 8 + nout * cells * 4
+    elif stage == "charges":
+        byts = ns * 32          # permutation 4, charge 8, weight 8 in; FP32 and FP64 values out
+    elif stage == "a_values":
+        byts = nt * 44          # permutation 4, V 16 in; FP32 and FP64 pairs out
+    elif stage in ("fold", "a_fold"):
+        nf = 2 if args.cs else 1
+        if stage == "a_fold":
+            nf = 2
+        t = 32 if not info.get("tile") else info["tile"]
+        pt = t + 2 * m - 1
+        ntl = -(-ex // t) * -(-ey // t)
+        byts = nf * (ntl * pt * pt * 8 + cells * 4)  # padded tile sums in, grid out
     else:
         byts = (nt + ns) * 16
     ach = byts / sec / 1e9

@@ -130,6 +130,16 @@ int fn_params_default(fn_params *p, int32_t grid);
  * in total, where the boundary-layer error of H is a larger share. */
 int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p);
 
+/* Parameters for forward and adjoint outputs (phi, H, H^T) on FEM meshes whose last n_surf
+ * sources are boundary-edge points (fn_set_geometry_split): as fn_params_auto, but from
+ * 2^16 points on the boundary points take their own radius eps_S = 11/n and the volume
+ * sources p = 8, eps_I = 5/n -- about 2.5x fewer near-field pairs than eps_I = 8/n, at a
+ * relative L2 error of phi, H and H^T within about 4e-7 of the exact sum on meshes of 10k
+ * nodes and up.  The energy gradient C^T A^T (l M) magnifies the error of small radii (a
+ * discrete divergence): fn_params_auto is the rule for fn_energy.  n_surf = 0 or fewer
+ * than 2^16 points: fn_params_auto. */
+int fn_params_auto_split(int64_t n_tgt, int64_t n_src, int64_t n_surf, int32_t precision, fn_params *p);
+
 /* Create a context bound to the current device and to the HIP stream
  * `stream` (hipStream_t, may be NULL for the null stream).  Validates the
  * parameters and prepares the host-side plan (regularization polynomials,
@@ -212,12 +222,14 @@ int fn_get_info(const fn_ctx *ctx, fn_info *info);
  *                   64 x 4 (default 32 x 8), forward (targets home) and adjoint (sources home)
  *   near_*_cap      points of the other set staged per LDS chunk, a multiple of 64 in
  *                   [128, 2048] (default 1024 forward, 512 adjoint)
+ *   tile            spread and gather tile edge, cells: 16 or 32 (default 32); smaller tiles
+ *                   give small grids more workgroups
  * FN_E_INVAL for an unsupported value (nothing is changed then). */
 typedef struct fn_shapes {
     int32_t spread_groups;
     int32_t near_fwd_bx, near_fwd_by, near_fwd_cap;
     int32_t near_adj_bx, near_adj_by, near_adj_cap;
-    int32_t reserved;
+    int32_t tile;
 } fn_shapes;
 int fn_set_shapes(fn_ctx *ctx, const fn_shapes *shapes);
 int fn_get_shapes(const fn_ctx *ctx, fn_shapes *shapes);   /* the shapes in effect */
@@ -361,12 +373,19 @@ const char *fn_mesh_last_error(const fn_mesh *mesh);
 
 /*
  * Batches: B independent problems (e.g. one per mesh) in one object, each with
- * its own parameters (typically its own grid), evaluated on one stream.  Inputs
- * and outputs are the members' arrays concatenated; tgt_off / src_off are HOST
- * arrays of B + 1 offsets (0 = tgt_off[0] <= tgt_off[1] <= ...), in points.  Each
- * member needs at least one point.  Member b's targets are
- * tgt_xy[tgt_off[b] .. tgt_off[b+1]) and so on; phi, H, q, V, v, u likewise.
- * The workspace is one caller buffer carved into the members' workspaces.
+ * its own parameters (typically its own grid).  Inputs and outputs are the members'
+ * arrays concatenated; tgt_off / src_off are HOST arrays of B + 1 offsets
+ * (0 = tgt_off[0] <= tgt_off[1] <= ...), in points.  Each member needs at least one
+ * point.  Member b's targets are tgt_xy[tgt_off[b] .. tgt_off[b+1]) and so on; phi, H,
+ * q, V, v, u likewise.  The workspace is one caller buffer carved into the members'
+ * workspaces.  Every evaluation call is ordered on the batch stream; inside it the
+ * members' tasks (forwards and adjoints) run over the batch's lanes: streams it owns
+ * (default priority, created by the first evaluation or fn_batch_set_lanes, freed by
+ * fn_batch_destroy), forked from the batch stream with one event and joined back, the
+ * tasks given to the lanes longest first by a cost model (near-field pairs, points, grid
+ * cells) so that small members' kernels run side by side.  A batch evaluation records
+ * into one graph once the lanes exist (FN_E_STATE if the first evaluation is captured).
+ * Evaluation arguments are checked for the whole batch before anything is enqueued.
  */
 typedef struct fn_batch fn_batch;
 int fn_batch_create(int32_t count, const fn_params *params /* [count] */, void *stream, fn_batch **out);
@@ -380,16 +399,18 @@ int fn_set_geometry_batch(fn_batch *batch, const int64_t *tgt_off, const double 
 int fn_set_geometry_batch_split(fn_batch *batch, const int64_t *tgt_off, const double *tgt_xy,
                                 const int64_t *src_off, const double *src_xy, const double *src_w,
                                 const int64_t *n_surf);
+/* Number of lanes (streams) an evaluation spreads the members' tasks over, 1..8 (default
+ * 4, the hardware queues a process gets by default); creates them now.  Not during capture. */
+int fn_batch_set_lanes(fn_batch *batch, int32_t lanes);
 int fn_batch_set_charges(fn_batch *batch, const double *q);
 int fn_batch_eval(fn_batch *batch, double *phi, double *H);        /* either may be NULL, not both */
 int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u);
 /* fn_batch_eval(batch, phi, H) and fn_batch_eval_H_adjoint(batch, V, u) in one call, as
  * fn_eval_with_H_adjoint does for one context (phi and H = -grad phi of eq. (2), and the
- * transpose of the H map): every member's adjoint on a second stream the batch owns
- * (created on the first call, default priority, freed by fn_batch_destroy), its forward
- * on the batch stream, with one fork and one join for the whole batch.  Capturable once
- * it has run once (FN_E_STATE if the first call is made under capture); outputs must not
- * overlap each other or the inputs; results equal those of the two calls. */
+ * transpose of the H map): every member's forward and adjoint are tasks of one schedule
+ * over the lanes (a member's two directions use separate scratch and may run at the same
+ * time).  Outputs must not overlap each other or the inputs; results equal those of the
+ * two calls. */
 int fn_batch_eval_with_H_adjoint(fn_batch *batch, double *phi, double *H, const double *V, double *u);
 int fn_batch_eval_phi_adjoint(fn_batch *batch, const double *v, double *u);
 int fn_batch_member(fn_batch *batch, int32_t i, fn_ctx **out);    /* borrow member i's context */

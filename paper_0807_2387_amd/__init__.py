@@ -34,7 +34,8 @@ import ctypes
 from . import _lib
 from ._lib import FN_FP32_MIXED, FN_FP64, FemNfftError  # noqa: F401
 
-__all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params", "FN_FP64", "FN_FP32_MIXED",
+__all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params", "auto_params_split",
+           "FN_FP64", "FN_FP32_MIXED",
            "FemNfftError"]
 
 
@@ -49,6 +50,15 @@ def auto_params(n_tgt, n_src, precision=FN_FP32_MIXED):
     """Grid and regularization for a problem size (fn_params_auto)."""
     p = _lib.Params()
     _lib.check(_lib.lib().fn_params_auto(int(n_tgt), int(n_src), int(precision), ctypes.byref(p)))
+    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n,
+                eps_S=p.eps_S)
+
+
+def auto_params_split(n_tgt, n_src, n_surf, precision=FN_FP32_MIXED):
+    """Grid and regularization for forward/adjoint outputs on FEM meshes whose last n_surf
+    sources are boundary points (fn_params_auto_split)."""
+    p = _lib.Params()
+    _lib.check(_lib.lib().fn_params_auto_split(int(n_tgt), int(n_src), int(n_surf), int(precision), ctypes.byref(p)))
     return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n,
                 eps_S=p.eps_S)
 
@@ -350,8 +360,9 @@ def _params(d):
 
 
 class Batch:
-    """Independent problems evaluated on one stream (fn_batch_*): members' arrays are
-    concatenated; offsets are host sequences of B + 1 point counts (CSR)."""
+    """Independent problems (fn_batch_*): members' arrays are concatenated; offsets are host
+    sequences of B + 1 point counts (CSR).  Calls are ordered on one stream; inside an
+    evaluation the members' tasks run over a few lanes (set_lanes)."""
 
     def __init__(self, params, stream=None):
         torch = _torch()
@@ -399,6 +410,11 @@ class Batch:
         self.n_tgt, self.n_src = int(tgt_off[-1]), int(src_off[-1])
         return self
 
+    def set_lanes(self, lanes):
+        """Streams an evaluation spreads the members' tasks over (fn_batch_set_lanes)."""
+        self._check(_lib.lib().fn_batch_set_lanes(self._b, int(lanes)))
+        return self
+
     def set_charges(self, q):
         self._check(_lib.lib().fn_batch_set_charges(self._b, _dev_ptr(q, "q")))
         return self
@@ -417,8 +433,8 @@ class Batch:
         return u
 
     def eval_with_H_adjoint(self, V, out_phi=None, out_H=None, out_u=None):
-        """phi, H = eval() and u = adjoint_H(V) in one call that runs the two at once on
-        two streams (fn_batch_eval_with_H_adjoint); returns (phi, H, u)."""
+        """phi, H = eval() and u = adjoint_H(V) in one call, every member's two directions
+        in one schedule over the lanes (fn_batch_eval_with_H_adjoint); returns (phi, H, u)."""
         torch = _torch()
         p = out_phi if out_phi is not None else torch.empty(self.n_tgt, dtype=torch.float64, device=self.device)
         h = out_H if out_H is not None else torch.empty(self.n_tgt, 2, dtype=torch.float64, device=self.device)
@@ -426,19 +442,6 @@ class Batch:
         self._check(_lib.lib().fn_batch_eval_with_H_adjoint(self._b, _dev_ptr(p, "phi"), _dev_ptr(h, "H", (2,)),
                                                             _dev_ptr(V, "V", (2,)), _dev_ptr(u, "u")))
         return p, h, u
-
-    def eval_noalloc(self, tgt_xy, src_xy, src_w, q, out_phi, out_H, n_surf=0):
-        """fn_eval_noalloc: geometry + charges + eval on the library's static scratch (no
-        device allocation; the outputs are the caller's tensors).  The context's own
-        workspace and state are untouched."""
-        nt, ns = int(tgt_xy.shape[0]), int(src_xy.shape[0])
-        self._check(_lib.lib().fn_eval_noalloc(
-            self._ctx, nt, _dev_ptr(tgt_xy, "tgt_xy", (2,)) if nt else None, ns,
-            _dev_ptr(src_xy, "src_xy", (2,)) if ns else None, _dev_ptr(src_w, "src_w") if ns else None,
-            int(n_surf), _dev_ptr(q, "q") if ns else None,
-            _dev_ptr(out_phi, "phi") if out_phi is not None else None,
-            _dev_ptr(out_H, "H", (2,)) if out_H is not None else None))
-        return out_phi, out_H
 
     def adjoint_phi(self, v, out=None):
         torch = _torch()

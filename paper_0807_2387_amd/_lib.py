@@ -19,7 +19,7 @@ ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: 
 
 # exported C-ABI symbols (include/femnfft.h)
 SYMBOLS = (
-    "fn_params_default", "fn_params_auto", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
+    "fn_params_default", "fn_params_auto", "fn_params_auto_split", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
     "fn_set_geometry", "fn_set_geometry_split", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
     "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_eval_with_H_adjoint", "fn_eval_noalloc", "fn_get_info",
     "fn_last_error",
@@ -28,7 +28,7 @@ SYMBOLS = (
     "fn_mesh_sources", "fn_mesh_lumped_mass", "fn_mesh_charges", "fn_mesh_charges_T", "fn_bind_mesh",
     "fn_energy", "fn_bind_mesh_sources", "fn_energy_charge", "fn_mesh_p1_gradient", "fn_mesh_last_error",
     "fn_batch_create", "fn_batch_destroy", "fn_batch_workspace_size", "fn_batch_set_workspace",
-    "fn_set_geometry_batch", "fn_set_geometry_batch_split", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint", "fn_batch_eval_with_H_adjoint",
+    "fn_set_geometry_batch", "fn_set_geometry_batch_split", "fn_batch_set_lanes", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint", "fn_batch_eval_with_H_adjoint",
     "fn_batch_eval_phi_adjoint", "fn_batch_member", "fn_batch_last_error",
     "fn_graph_begin", "fn_graph_end", "fn_graph_launch", "fn_graph_destroy", "fn_graph_last_error",
 )
@@ -86,6 +86,7 @@ def lib():
     sig = {
         "fn_params_default": ([ctypes.POINTER(Params), I32], ctypes.c_int),
         "fn_params_auto": ([I64, I64, I32, ctypes.POINTER(Params)], ctypes.c_int),
+        "fn_params_auto_split": ([I64, I64, I64, I32, ctypes.POINTER(Params)], ctypes.c_int),
         "fn_create": ([ctypes.POINTER(Params), P, ctypes.POINTER(P)], ctypes.c_int),
         "fn_destroy": ([P], ctypes.c_int),
         "fn_workspace_size": ([P, I64, I64, ctypes.POINTER(SZ)], ctypes.c_int),
@@ -128,6 +129,7 @@ def lib():
         "fn_set_geometry_batch": ([P, ctypes.POINTER(I64), P, ctypes.POINTER(I64), P, P], ctypes.c_int),
         "fn_set_geometry_batch_split": ([P, ctypes.POINTER(I64), P, ctypes.POINTER(I64), P, P, ctypes.POINTER(I64)],
                                         ctypes.c_int),
+        "fn_batch_set_lanes": ([P, I32], ctypes.c_int),
         "fn_batch_set_charges": ([P, P], ctypes.c_int),
         "fn_batch_eval": ([P, P, P], ctypes.c_int),
         "fn_batch_eval_H_adjoint": ([P, P, P], ctypes.c_int),

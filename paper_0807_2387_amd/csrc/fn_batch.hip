@@ -1,15 +1,21 @@
 // Batches of independent point sets (one mesh each) and HIP-graph capture of
 // evaluation sequences.
 //
-// A batch holds one context per member, all on the batch's stream, with their
-// workspaces carved from one caller buffer; inputs and outputs are the members'
-// arrays concatenated (CSR offsets).  Members may use different parameters (the
-// grid is normally chosen per member from its size).  Every member call is
-// enqueued on the one stream, so a whole batch evaluation can be captured into
-// a single graph and replayed with one launch (fn_graph_*), which removes the
-// per-kernel launch cost that dominates small members.
+// A batch holds one context per member with their workspaces carved from one
+// caller buffer; inputs and outputs are the members' arrays concatenated (CSR
+// offsets).  Members may use different parameters (the grid is normally chosen per
+// member from its size).  An evaluation is a set of tasks (a member's forward, its H
+// adjoint or its phi adjoint; a member's forward and adjoints use separate scratch)
+// spread over a few lanes -- streams the batch owns, forked from the batch stream with
+// one event and joined back with one event per lane -- by longest-processing-time
+// first on a cost model (near-field pairs, points, grid cells), so the kernels of small
+// members run side by side instead of leaving most CUs idle one after the other.  The
+// call stays ordered on the batch stream, and a whole batch evaluation records into a
+// single graph (fn_graph_*) once the lanes exist.
 #include "fn_internal.h"
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -17,8 +23,10 @@
 
 struct fn_batch {
     hipStream_t stream = nullptr;
-    hipStream_t stream2 = nullptr;  // second stream of fn_batch_eval_with_H_adjoint (created on first use)
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int nlanes = 4;                    // lanes of an evaluation (fn_batch_set_lanes)
+    std::vector<hipStream_t> lanes;    // created on the first evaluation, default priority
+    std::vector<hipEvent_t> lane_ev;   // join event per lane
+    hipEvent_t ev_fork = nullptr;
     std::vector<fn_ctx *> ctx;
     std::vector<int64_t> toff, soff;  // host copies of the offsets of the last geometry
     std::vector<size_t> wsoff;        // workspace offset of each member
@@ -99,12 +107,12 @@ int fn_batch_destroy(fn_batch *batch)
 {
     if (batch) {
         for (fn_ctx *c : batch->ctx) fn_destroy(c);
-        if (batch->stream2) {
-            hipStreamSynchronize(batch->stream2);
-            hipStreamDestroy(batch->stream2);
+        for (hipStream_t l : batch->lanes) {
+            hipStreamSynchronize(l);
+            hipStreamDestroy(l);
         }
+        for (hipEvent_t e : batch->lane_ev) hipEventDestroy(e);
         if (batch->ev_fork) hipEventDestroy(batch->ev_fork);
-        if (batch->ev_join) hipEventDestroy(batch->ev_join);
     }
     delete batch;
     return FN_OK;
@@ -176,30 +184,151 @@ int fn_batch_set_charges(fn_batch *batch, const double *q)
     return FN_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+enum { TASK_FWD = 0, TASK_ADJ_H = 1, TASK_ADJ_PHI = 2 };
+struct Task {
+    int member, kind;
+    double cost;
+};
+
+// Relative cost of a member's task: near-field pairs (the dominant work), points through
+// spread and gather, grid cells through the FFT passes.
+double task_cost(const fn_ctx *c, int kind)
+{
+    const double pairs = (double)c->geom.near_pairs + (double)c->geom.near_pairs_s;
+    const double pts = (double)c->geom.nt + (double)c->geom.ns;
+    const double G = c->plan.G, cells = (double)c->geom.ext[0] * c->geom.ext[1];
+    const double lg = std::log2(G);
+    return (kind == TASK_FWD ? 1.5 : 1.0) * pairs + 150.0 * pts + 60.0 * (cells + 0.5 * G * G / 4 * lg / 13.0);
+}
+
+// The lanes exist (created all or none, outside capture)
+int ensure_lanes(fn_batch *b)
+{
+    if ((int)b->lanes.size() == b->nlanes && b->ev_fork) return FN_OK;
+    if (stream_capturing(b->stream))
+        BATCH_ERR(b, FN_E_STATE, "evaluate the batch once before capturing it (the first evaluation creates its lanes)");
+    for (hipStream_t l : b->lanes) {
+        hipStreamSynchronize(l);
+        hipStreamDestroy(l);
+    }
+    for (hipEvent_t e : b->lane_ev) hipEventDestroy(e);
+    b->lanes.clear();
+    b->lane_ev.clear();
+    hipError_t e = hipSuccess;
+    if (!b->ev_fork) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    for (int l = 0; l < b->nlanes && e == hipSuccess; ++l) {
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (s) b->lanes.push_back(s);
+        if (ev) b->lane_ev.push_back(ev);
+    }
+    if (e != hipSuccess || (int)b->lanes.size() != b->nlanes || (int)b->lane_ev.size() != b->nlanes) {
+        for (hipStream_t l : b->lanes) hipStreamDestroy(l);
+        for (hipEvent_t ev : b->lane_ev) hipEventDestroy(ev);
+        b->lanes.clear();
+        b->lane_ev.clear();
+        BATCH_ERR(b, FN_E_DEVICE, std::string("creating the batch lanes: ") + hipGetErrorString(e));
+    }
+    return FN_OK;
+}
+
+// Enqueue the tasks over the lanes (longest first, each to the least loaded lane), forked
+// from and joined back into the batch stream.  Arguments were checked by the caller.
+int run_tasks(fn_batch *b, std::vector<Task> &tasks, double *phi, double *H, const double *in, int comps, double *u)
+{
+    int rc = ensure_lanes(b);
+    if (rc) return rc;
+    std::stable_sort(tasks.begin(), tasks.end(), [](const Task &x, const Task &y) { return x.cost > y.cost; });
+    hipError_t e = hipEventRecord(b->ev_fork, b->stream);
+    for (int l = 0; l < b->nlanes && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->lanes[l], b->ev_fork, 0);
+    if (e != hipSuccess) BATCH_ERR(b, FN_E_DEVICE, std::string("fork: ") + hipGetErrorString(e));
+    std::vector<double> load(b->nlanes, 0.0);
+    for (const Task &t : tasks) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[l] += t.cost;
+        fn_ctx *c = b->ctx[t.member];
+        const int64_t to = b->toff[t.member], so = b->soff[t.member];
+        if (t.kind == TASK_FWD)
+            rc = fn_internal_eval_on_stream(c, phi ? phi + to : nullptr, H ? H + 2 * to : nullptr, b->lanes[l]);
+        else if (t.kind == TASK_ADJ_H)
+            rc = fn_internal_adjoint_H_on_stream(c, in ? in + 2 * to : nullptr, u ? u + so : nullptr, b->lanes[l]);
+        else
+            rc = fn_internal_adjoint_phi_on_stream(c, in ? in + comps * to : nullptr, u ? u + so : nullptr, b->lanes[l]);
+        if (rc) {
+            rc = member_err(b, t.member, rc);
+            break;
+        }
+    }
+    // join every lane even after an error, so that the batch stream never runs ahead of it
+    hipError_t ej = hipSuccess;
+    for (int l = 0; l < b->nlanes; ++l) {
+        const hipError_t e1 = hipEventRecord(b->lane_ev[l], b->lanes[l]);
+        const hipError_t e2 = hipStreamWaitEvent(b->stream, b->lane_ev[l], 0);
+        if (ej == hipSuccess) ej = e1 != hipSuccess ? e1 : e2;
+    }
+    if (rc) return rc;
+    if (ej != hipSuccess) BATCH_ERR(b, FN_E_DEVICE, std::string("join: ") + hipGetErrorString(ej));
+    return FN_OK;
+}
+
+// Batch-wide argument checks, before anything is enqueued.
+int check_eval_args(fn_batch *b, bool fwd, bool need_phi_or_H, const void *phi, const void *H, bool adj,
+                    const void *in, const void *u)
+{
+    if (!b->geom_ready) BATCH_ERR(b, FN_E_STATE, "fn_set_geometry_batch must succeed first");
+    const size_t B = b->ctx.size();
+    const int64_t nt = b->toff[B] - b->toff[0], ns = b->soff[B] - b->soff[0];
+    if (fwd)
+        for (size_t i = 0; i < B; ++i)
+            if (!b->ctx[i]->charges_ready) {
+                b->err = "member " + std::to_string(i) + ": fn_batch_set_charges must be called before evaluation";
+                return FN_E_STATE;
+            }
+    if (fwd && need_phi_or_H && nt > 0 && !phi && !H) BATCH_ERR(b, FN_E_INVAL, "both outputs are NULL");
+    if (adj && ((nt > 0 && !in) || (ns > 0 && !u))) BATCH_ERR(b, FN_E_INVAL, "NULL input or output");
+    return FN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fn_batch_set_lanes(fn_batch *batch, int32_t lanes)
+{
+    if (!batch) return FN_E_INVAL;
+    if (lanes < 1 || lanes > 8) BATCH_ERR(batch, FN_E_INVAL, "lanes must be in [1, 8]");
+    if (stream_capturing(batch->stream)) BATCH_ERR(batch, FN_E_STATE, "not during graph capture");
+    batch->nlanes = lanes;
+    return ensure_lanes(batch);
+}
+
 int fn_batch_eval(fn_batch *batch, double *phi, double *H)
 {
     if (!batch) return FN_E_INVAL;
-    if (!batch->geom_ready) BATCH_ERR(batch, FN_E_STATE, "fn_set_geometry_batch must succeed first");
-    for (size_t i = 0; i < batch->ctx.size(); ++i) {
-        if (batch->toff[i + 1] == batch->toff[i]) continue;
-        int rc = fn_eval(batch->ctx[i], phi ? phi + batch->toff[i] : nullptr, H ? H + 2 * batch->toff[i] : nullptr);
-        if (rc) return member_err(batch, (int)i, rc);
-    }
-    return FN_OK;
+    int rc = check_eval_args(batch, true, true, phi, H, false, nullptr, nullptr);
+    if (rc) return rc;
+    std::vector<Task> tasks;
+    for (size_t i = 0; i < batch->ctx.size(); ++i)
+        if (batch->toff[i + 1] > batch->toff[i]) tasks.push_back({(int)i, TASK_FWD, task_cost(batch->ctx[i], TASK_FWD)});
+    return run_tasks(batch, tasks, phi, H, nullptr, 0, nullptr);
 }
 
 static int batch_adjoint(fn_batch *batch, const double *in, int comps, double *u, bool h)
 {
     if (!batch) return FN_E_INVAL;
-    if (!batch->geom_ready) BATCH_ERR(batch, FN_E_STATE, "fn_set_geometry_batch must succeed first");
-    for (size_t i = 0; i < batch->ctx.size(); ++i) {
-        if (batch->soff[i + 1] == batch->soff[i]) continue;
-        const double *pi = in ? in + comps * batch->toff[i] : nullptr;
-        double *pu = u ? u + batch->soff[i] : nullptr;
-        int rc = h ? fn_eval_H_adjoint(batch->ctx[i], pi, pu) : fn_eval_phi_adjoint(batch->ctx[i], pi, pu);
-        if (rc) return member_err(batch, (int)i, rc);
-    }
-    return FN_OK;
+    int rc = check_eval_args(batch, false, false, nullptr, nullptr, true, in, u);
+    if (rc) return rc;
+    std::vector<Task> tasks;
+    const int kind = h ? TASK_ADJ_H : TASK_ADJ_PHI;
+    for (size_t i = 0; i < batch->ctx.size(); ++i)
+        if (batch->soff[i + 1] > batch->soff[i]) tasks.push_back({(int)i, kind, task_cost(batch->ctx[i], kind)});
+    return run_tasks(batch, tasks, nullptr, nullptr, in, comps, u);
 }
 
 int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u) { return batch_adjoint(batch, V, 2, u, true); }
@@ -207,64 +336,16 @@ int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u) { retur
 int fn_batch_eval_with_H_adjoint(fn_batch *batch, double *phi, double *H, const double *V, double *u)
 {
     if (!batch) return FN_E_INVAL;
-    if (!batch->geom_ready) BATCH_ERR(batch, FN_E_STATE, "fn_set_geometry_batch must succeed first");
-    // every argument is checked before anything is enqueued, so that an error leaves the
-    // outputs untouched
-    {
-        const size_t B = batch->ctx.size();
-        const int64_t nt = batch->toff[B] - batch->toff[0], ns = batch->soff[B] - batch->soff[0];
-        for (size_t i = 0; i < B; ++i)
-            if (!batch->ctx[i]->charges_ready) {
-                batch->err = "member " + std::to_string(i) + ": fn_batch_set_charges must be called before evaluation";
-                return FN_E_STATE;
-            }
-        if (nt > 0 && !phi && !H) BATCH_ERR(batch, FN_E_INVAL, "both outputs are NULL");
-        if ((nt > 0 && !V) || (ns > 0 && !u)) BATCH_ERR(batch, FN_E_INVAL, "NULL input or output");
-    }
-    if (!batch->stream2) {
-        if (stream_capturing(batch->stream))
-            BATCH_ERR(batch, FN_E_STATE, "call fn_batch_eval_with_H_adjoint once before capturing it (it creates its stream)");
-        hipStream_t s2 = nullptr;
-        hipEvent_t e1 = nullptr, e2 = nullptr;
-        hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&e2, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            if (e2) hipEventDestroy(e2);
-            if (e1) hipEventDestroy(e1);
-            if (s2) hipStreamDestroy(s2);
-            BATCH_ERR(batch, FN_E_DEVICE, std::string("creating the second stream: ") + hipGetErrorString(e));
-        }
-        batch->stream2 = s2;
-        batch->ev_fork = e1;
-        batch->ev_join = e2;
-    }
-    // one fork for the whole batch: every member's adjoint on the second stream, its
-    // forward on the batch stream, one join at the end
-    hipError_t e = hipEventRecord(batch->ev_fork, batch->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(batch->stream2, batch->ev_fork, 0);
-    if (e != hipSuccess) BATCH_ERR(batch, FN_E_DEVICE, std::string("fork: ") + hipGetErrorString(e));
-    int rc = FN_OK;
-    for (size_t i = 0; i < batch->ctx.size() && rc == FN_OK; ++i) {
-        const int64_t nt = batch->toff[i + 1] - batch->toff[i], ns = batch->soff[i + 1] - batch->soff[i];
-        if (ns > 0) {
-            rc = fn_internal_adjoint_H_on_stream(batch->ctx[i], V ? V + 2 * batch->toff[i] : nullptr,
-                                                 u ? u + batch->soff[i] : nullptr, batch->stream2);
-            if (rc) rc = member_err(batch, (int)i, rc);
-        }
-        if (rc == FN_OK && nt > 0) {
-            rc = fn_internal_eval_on_stream(batch->ctx[i], phi ? phi + batch->toff[i] : nullptr,
-                                            H ? H + 2 * batch->toff[i] : nullptr, batch->stream);
-            if (rc) rc = member_err(batch, (int)i, rc);
-        }
-    }
-    // join even after an error, so that the batch stream never runs ahead of the fork
-    const hipError_t e1 = hipEventRecord(batch->ev_join, batch->stream2);
-    const hipError_t e2 = hipStreamWaitEvent(batch->stream, batch->ev_join, 0);
+    int rc = check_eval_args(batch, true, true, phi, H, true, V, u);
     if (rc) return rc;
-    if (e1 != hipSuccess || e2 != hipSuccess)
-        BATCH_ERR(batch, FN_E_DEVICE, std::string("join: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
-    return FN_OK;
+    std::vector<Task> tasks;
+    for (size_t i = 0; i < batch->ctx.size(); ++i) {
+        if (batch->soff[i + 1] > batch->soff[i])
+            tasks.push_back({(int)i, TASK_ADJ_H, task_cost(batch->ctx[i], TASK_ADJ_H)});
+        if (batch->toff[i + 1] > batch->toff[i])
+            tasks.push_back({(int)i, TASK_FWD, task_cost(batch->ctx[i], TASK_FWD)});
+    }
+    return run_tasks(batch, tasks, phi, H, V, 2, u);
 }
 
 int fn_batch_eval_phi_adjoint(fn_batch *batch, const double *v, double *u)

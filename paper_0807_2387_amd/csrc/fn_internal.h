@@ -204,6 +204,8 @@ __attribute__((visibility("hidden"))) int fn_internal_eval_on_stream(fn_ctx *c, 
                                                                      hipStream_t st);
 __attribute__((visibility("hidden"))) int fn_internal_adjoint_H_on_stream(fn_ctx *c, const double *V, double *u,
                                                                           hipStream_t st);
+__attribute__((visibility("hidden"))) int fn_internal_adjoint_phi_on_stream(fn_ctx *c, const double *v, double *u,
+                                                                            hipStream_t st);
 }
 
 // true while work issued on `st` is being captured into a graph
