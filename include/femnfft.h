@@ -130,16 +130,6 @@ int fn_params_default(fn_params *p, int32_t grid);
  * in total, where the boundary-layer error of H is a larger share. */
 int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p);
 
-/* Parameters for forward and adjoint outputs (phi, H, H^T) on FEM meshes whose last n_surf
- * sources are boundary-edge points (fn_set_geometry_split): as fn_params_auto, but from
- * 2^16 points on the boundary points take their own radius eps_S = 11/n and the volume
- * sources p = 8, eps_I = 5/n -- about 2.5x fewer near-field pairs than eps_I = 8/n, at a
- * relative L2 error of phi, H and H^T within about 4e-7 of the exact sum on meshes of 10k
- * nodes and up.  The energy gradient C^T A^T (l M) magnifies the error of small radii (a
- * discrete divergence): fn_params_auto is the rule for fn_energy.  n_surf = 0 or fewer
- * than 2^16 points: fn_params_auto. */
-int fn_params_auto_split(int64_t n_tgt, int64_t n_src, int64_t n_surf, int32_t precision, fn_params *p);
-
 /* Create a context bound to the current device and to the HIP stream
  * `stream` (hipStream_t, may be NULL for the null stream).  Validates the
  * parameters and prepares the host-side plan (regularization polynomials,

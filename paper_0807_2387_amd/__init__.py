@@ -34,7 +34,7 @@ import ctypes
 from . import _lib
 from ._lib import FN_FP32_MIXED, FN_FP64, FemNfftError  # noqa: F401
 
-__all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params", "auto_params_split",
+__all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params",
            "FN_FP64", "FN_FP32_MIXED",
            "FemNfftError"]
 
@@ -50,15 +50,6 @@ def auto_params(n_tgt, n_src, precision=FN_FP32_MIXED):
     """Grid and regularization for a problem size (fn_params_auto)."""
     p = _lib.Params()
     _lib.check(_lib.lib().fn_params_auto(int(n_tgt), int(n_src), int(precision), ctypes.byref(p)))
-    return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n,
-                eps_S=p.eps_S)
-
-
-def auto_params_split(n_tgt, n_src, n_surf, precision=FN_FP32_MIXED):
-    """Grid and regularization for forward/adjoint outputs on FEM meshes whose last n_surf
-    sources are boundary points (fn_params_auto_split)."""
-    p = _lib.Params()
-    _lib.check(_lib.lib().fn_params_auto_split(int(n_tgt), int(n_src), int(n_surf), int(precision), ctypes.byref(p)))
     return dict(grid=p.grid, m=p.m, p=p.p, eps_I=p.eps_I, eps_B=p.eps_B, precision=p.precision, n=p.n,
                 eps_S=p.eps_S)
 

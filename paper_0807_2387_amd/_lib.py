@@ -19,7 +19,7 @@ ERR_NAMES = {0: "FN_OK", 1: "FN_E_INVAL", 2: "FN_E_STATE", 3: "FN_E_DOMAIN", 4: 
 
 # exported C-ABI symbols (include/femnfft.h)
 SYMBOLS = (
-    "fn_params_default", "fn_params_auto", "fn_params_auto_split", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
+    "fn_params_default", "fn_params_auto", "fn_create", "fn_destroy", "fn_workspace_size", "fn_set_workspace",
     "fn_set_geometry", "fn_set_geometry_split", "fn_set_charges", "fn_eval", "fn_eval_phi", "fn_eval_H",
     "fn_eval_phi_adjoint", "fn_eval_H_adjoint", "fn_eval_with_H_adjoint", "fn_eval_noalloc", "fn_get_info",
     "fn_last_error",
@@ -86,7 +86,6 @@ def lib():
     sig = {
         "fn_params_default": ([ctypes.POINTER(Params), I32], ctypes.c_int),
         "fn_params_auto": ([I64, I64, I32, ctypes.POINTER(Params)], ctypes.c_int),
-        "fn_params_auto_split": ([I64, I64, I64, I32, ctypes.POINTER(Params)], ctypes.c_int),
         "fn_create": ([ctypes.POINTER(Params), P, ctypes.POINTER(P)], ctypes.c_int),
         "fn_destroy": ([P], ctypes.c_int),
         "fn_workspace_size": ([P, I64, I64, ctypes.POINTER(SZ)], ctypes.c_int),

@@ -456,20 +456,6 @@ int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p
     return FN_OK;
 }
 
-int fn_params_auto_split(int64_t n_tgt, int64_t n_src, int64_t n_surf, int32_t precision, fn_params *p)
-{
-    int rc = fn_params_auto(n_tgt, n_src, precision, p);
-    if (rc || n_surf <= 0 || n_surf > n_src || n_tgt + n_src < 65536) return rc;
-    // the boundary points at their own radius let the volume radius shrink: pairs fall
-    // with the square of the radius (measured on FEM meshes of 10k-50k nodes: phi, H and
-    // the H adjoint within 4e-7 of the direct sum at p = 8, n eps_I = 5, n eps_S = 11)
-    const double nb = p->n ? p->n : p->grid / 2;
-    p->p = 8;
-    p->eps_I = 5.0 / nb;
-    p->eps_S = 11.0 / nb;
-    return FN_OK;
-}
-
 static int validate_params(const fn_params *p, std::string &err)
 {
     if (!p) { err = "params is NULL"; return FN_E_INVAL; }
