@@ -1,7 +1,8 @@
-"""ctypes binding of oracle O1 (oracle/direct.c) -- TEST INFRASTRUCTURE ONLY.
+"""ctypes binding of oracle O1 (oracle/direct.c, 2D; oracle/direct3.c, 3D) -- TEST
+INFRASTRUCTURE ONLY.
 
-build() compiles direct.c with gcc (-O2 -fopenmp, no fast-math, no FMA
-contraction) into oracle/_o1.so.  The loader builds it on first use if absent.
+build() compiles both with gcc (-O2 -fopenmp, no fast-math, no FMA contraction) into
+oracle/_o1.so.  The loader builds it on first use if absent.
 """
 from __future__ import annotations
 
@@ -12,14 +13,14 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "direct.c")
+_SRC = [os.path.join(_HERE, "direct.c"), os.path.join(_HERE, "direct3.c")]
 _SO = os.path.join(_HERE, "_o1.so")
 _lib = None
 
 
 def build(force=True):
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-o", _SO + ".tmp", _SRC, "-lm"]
+           "-fno-fast-math", "-o", _SO + ".tmp", *_SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_SO + ".tmp", _SO)
 
@@ -37,6 +38,9 @@ def _load():
         lib.o1_adjoint.argtypes = [I64, P, I64, P, P, P, P, P]
         lib.o1_adjoint.restype = ctypes.c_int
         lib.o1_threads.restype = ctypes.c_int
+        for f in (lib.o1_3d_forward, lib.o1_3d_adjoint):
+            f.argtypes = [I64, P, I64, P, P, P, P, P]
+            f.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -78,4 +82,27 @@ def adjoint(y, x, w, v=None, V=None):
     rc = lib.o1_adjoint(len(y), _p(y), len(x), _p(x), _p(w), _p(v), _p(V), _p(u))
     if rc:
         raise ValueError("o1_adjoint: bad arguments")
+    return u
+
+
+def forward3(y, x, w, q, want_phi=True, want_H=True):
+    """3D: phi [nt], H [nt, 3] of sum_j w_j q_j G(y_i - x_j), G = 1/(4 pi r)."""
+    lib = _load()
+    y, x, w, q = _c(y), _c(x), _c(w), _c(q)
+    nt, ns = len(y), len(x)
+    phi = np.empty(nt) if want_phi else None
+    H = np.empty((nt, 3)) if want_H else None
+    if lib.o1_3d_forward(nt, _p(y), ns, _p(x), _p(w), _p(q), _p(phi), _p(H)):
+        raise ValueError("o1_3d_forward: bad arguments")
+    return phi, H
+
+
+def adjoint3(y, x, w, v=None, V=None):
+    """3D: u_j = w_j sum_i (v_i G(y_i - x_j) + V_i . (-grad G)(y_i - x_j)), G = 1/(4 pi r)."""
+    lib = _load()
+    y, x, w = _c(y), _c(x), _c(w)
+    v, V = _c(v), _c(V)
+    u = np.empty(len(x))
+    if lib.o1_3d_adjoint(len(y), _p(y), len(x), _p(x), _p(w), _p(v), _p(V), _p(u)):
+        raise ValueError("o1_3d_adjoint: bad arguments")
     return u

@@ -72,6 +72,14 @@ def ifft2(a):
     return sfft.ifft2(a, workers=_WORKERS)
 
 
+def fftn_w(a):
+    return sfft.fftn(a, workers=_WORKERS)
+
+
+def ifftn_w(a):
+    return sfft.ifftn(a, workers=_WORKERS)
+
+
 @dataclass
 class Params:
     G: int            # FFT grid per dimension (oversampled)

@@ -271,6 +271,27 @@ def random_cloud(n_tgt, n_src, seed, shape="disk", R=1.0, neutral=True):
     return y, x, w, q
 
 
+def random_cloud3(n_tgt, n_src, seed, shape="ball", R=1.0, neutral=True):
+    """3D: uniform random targets and sources in a ball or cube, positive weights,
+    charges of both signs (zero weighted sum if neutral)."""
+    rng = np.random.default_rng(seed)
+
+    def pts(n):
+        if shape == "ball":
+            v = rng.standard_normal((n, 3))
+            v /= np.linalg.norm(v, axis=1)[:, None]
+            return v * (R * rng.random(n) ** (1.0 / 3.0))[:, None]
+        return rng.uniform(-R, R, size=(n, 3))
+
+    y = pts(n_tgt)
+    x = pts(n_src)
+    w = rng.uniform(0.5, 1.5, size=n_src) / max(n_src, 1)
+    q = rng.standard_normal(n_src)
+    if neutral and n_src > 1:
+        q -= np.dot(w, q) / w.sum()
+    return y, x, w, q
+
+
 def rounded_square_cloud(N=1 << 24, side=4.0, rc=0.5, n_modes=32, kmax=4,
                          jitter=0.1, seed=SEED_BASE + 4, with_boundary=True):
     """Jittered-lattice targets and sources in a rounded square with smooth M.
