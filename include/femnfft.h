@@ -425,6 +425,36 @@ int fn_graph_launch(fn_graph *graph, void *stream);
 int fn_graph_destroy(fn_graph *graph);
 const char *fn_graph_last_error(void);
 
+/*
+ * The same fast summation in 3D: eq. (2) with the 3D Green function given with eq. (1),
+ *
+ *     phi_i = sum_j w_j q_j / (4 pi |r_i - r_j|),
+ *     H_i   = -grad phi = (1/4pi) sum_j w_j q_j (r_i - r_j) / |r_i - r_j|^3,
+ *
+ * and the transpose of the H map, u_j = w_j sum_i V_i . (r_i - r_j) / (4 pi |r_i - r_j|^3),
+ * by the NFFT method on a G^3 grid (the paper's p^3 N grid in 3D; bandwidth n = G/2), for
+ * tetrahedral FEM quadrature points or any point sets.  FP64 throughout (precision must be
+ * FN_FP64), grid G a power of two in [16, 256], eps_S = 0.  3-vectors are interleaved
+ * [n][3]; every array is a device pointer; the conventions (ordering, workspace, call order,
+ * errors, pairs at distance zero) are those of the 2D context.  The kernel's regularization
+ * near the torus boundary needs a wider zone than in 2D: eps_B = 1/8 is the tested setting.
+ */
+typedef struct fn3_ctx fn3_ctx;
+int fn3_create(const fn_params *params, void *stream, fn3_ctx **out);
+int fn3_destroy(fn3_ctx *ctx);
+int fn3_workspace_size(const fn3_ctx *ctx, int64_t n_tgt, int64_t n_src, size_t *bytes);
+int fn3_set_workspace(fn3_ctx *ctx, void *dev_ptr, size_t bytes);
+int fn3_set_geometry(fn3_ctx *ctx, int64_t n_tgt, const double *tgt_xyz, int64_t n_src, const double *src_xyz,
+                     const double *src_w);
+int fn3_set_charges(fn3_ctx *ctx, const double *q);
+int fn3_eval(fn3_ctx *ctx, double *phi, double *H);                   /* phi [n_tgt], H [n_tgt][3] */
+int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u);     /* V [n_tgt][3], u [n_src] */
+/* facts after fn3_set_geometry (host outputs, any may be NULL): point counts, torus scale s,
+ * data window extent [3] in cells, near radius in cells */
+int fn3_get_info(const fn3_ctx *ctx, int64_t *n_tgt, int64_t *n_src, double *scale, int32_t *win_ext,
+                 int32_t *near_cells);
+const char *fn3_last_error(const fn3_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,7 @@ import ctypes
 from . import _lib
 from ._lib import FN_FP32_MIXED, FN_FP64, FemNfftError  # noqa: F401
 
-__all__ = ["Solver", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params",
+__all__ = ["Solver", "Solver3", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params",
            "FN_FP64", "FN_FP32_MIXED",
            "FemNfftError"]
 
@@ -270,6 +270,80 @@ class Solver:
                     win_lo=tuple(i.win_lo), win_ext=tuple(i.win_ext), tiles=tuple(i.tiles),
                     near_cells=i.near_cells, workspace_bytes=i.workspace_bytes, near_pairs=i.near_pairs,
                     n_surf=i.n_surf, near_pairs_surf=i.near_pairs_surf, near_cells_surf=i.near_cells_surf)
+
+
+class Solver3:
+    """The 3D fast summation (fn3_*): G = 1/(4 pi r), FP64, points as [n, 3] device tensors."""
+
+    def __init__(self, grid, m=6, p=8, eps_I=None, eps_B=0.125, stream=None):
+        torch = _torch()
+        prm = _lib.Params(grid=int(grid), m=int(m), p=int(p), precision=FN_FP64,
+                          eps_I=float(eps_I if eps_I is not None else 6.0 / (grid // 2)), eps_B=float(eps_B), flags=0,
+                          n=0, eps_S=0.0)
+        self.params = prm
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        _lib.check3(_lib.lib().fn3_create(ctypes.byref(prm), ctypes.c_void_p(self._stream.cuda_stream),
+                                          ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._ws = None
+        self.n_tgt = self.n_src = 0
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx:
+            try:
+                _lib.lib().fn3_destroy(ctx)
+            except Exception:
+                pass
+            self._ctx = None
+
+    def _check(self, rc):
+        _lib.check3(rc, self._ctx)
+
+    def set_geometry(self, tgt_xyz, src_xyz, src_w):
+        torch = _torch()
+        L = _lib.lib()
+        nt, ns = int(tgt_xyz.shape[0]), int(src_xyz.shape[0])
+        need = ctypes.c_size_t()
+        self._check(L.fn3_workspace_size(self._ctx, nt, ns, ctypes.byref(need)))
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = None
+            self._ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+            self._check(L.fn3_set_workspace(self._ctx, ctypes.c_void_p(self._ws.data_ptr()), need))
+        self._check(L.fn3_set_geometry(self._ctx, nt, _dev_ptr(tgt_xyz, "tgt_xyz", (3,)) if nt else None, ns,
+                                       _dev_ptr(src_xyz, "src_xyz", (3,)) if ns else None,
+                                       _dev_ptr(src_w, "src_w") if ns else None))
+        self.n_tgt, self.n_src = nt, ns
+        self._geom_refs = (tgt_xyz, src_xyz, src_w)
+        return self
+
+    def set_charges(self, q):
+        self._q = q
+        self._check(_lib.lib().fn3_set_charges(self._ctx, _dev_ptr(q, "q") if self.n_src else None))
+        return self
+
+    def eval(self, phi=True, H=True):
+        torch = _torch()
+        p = torch.empty(self.n_tgt, dtype=torch.float64, device=self.device) if phi else None
+        h = torch.empty(self.n_tgt, 3, dtype=torch.float64, device=self.device) if H else None
+        self._check(_lib.lib().fn3_eval(self._ctx, _dev_ptr(p, "phi") if p is not None else None,
+                                        _dev_ptr(h, "H", (3,)) if h is not None else None))
+        return p, h
+
+    def adjoint_H(self, V):
+        torch = _torch()
+        u = torch.empty(self.n_src, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn3_eval_H_adjoint(self._ctx, _dev_ptr(V, "V", (3,)), _dev_ptr(u, "u")))
+        return u
+
+    def info(self):
+        nt, ns, ne, nc = ctypes.c_int64(), ctypes.c_int64(), (ctypes.c_int32 * 3)(), ctypes.c_int32()
+        sc = ctypes.c_double()
+        self._check(_lib.lib().fn3_get_info(self._ctx, ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(sc), ne,
+                                            ctypes.byref(nc)))
+        return dict(n_tgt=nt.value, n_src=ns.value, scale=sc.value, win_ext=tuple(ne), near_cells=nc.value)
 
 
 class Mesh:

@@ -31,6 +31,8 @@ SYMBOLS = (
     "fn_set_geometry_batch", "fn_set_geometry_batch_split", "fn_batch_set_lanes", "fn_batch_set_charges", "fn_batch_eval", "fn_batch_eval_H_adjoint", "fn_batch_eval_with_H_adjoint",
     "fn_batch_eval_phi_adjoint", "fn_batch_member", "fn_batch_last_error",
     "fn_graph_begin", "fn_graph_end", "fn_graph_launch", "fn_graph_destroy", "fn_graph_last_error",
+    "fn3_create", "fn3_destroy", "fn3_workspace_size", "fn3_set_workspace", "fn3_set_geometry", "fn3_set_charges",
+    "fn3_eval", "fn3_eval_H_adjoint", "fn3_get_info", "fn3_last_error",
 )
 
 STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather", "near",
@@ -141,6 +143,17 @@ def lib():
         "fn_graph_launch": ([P, P], ctypes.c_int),
         "fn_graph_destroy": ([P], ctypes.c_int),
         "fn_graph_last_error": ([], ctypes.c_char_p),
+        "fn3_create": ([ctypes.POINTER(Params), P, ctypes.POINTER(P)], ctypes.c_int),
+        "fn3_destroy": ([P], ctypes.c_int),
+        "fn3_workspace_size": ([P, I64, I64, ctypes.POINTER(SZ)], ctypes.c_int),
+        "fn3_set_workspace": ([P, P, SZ], ctypes.c_int),
+        "fn3_set_geometry": ([P, I64, P, I64, P, P], ctypes.c_int),
+        "fn3_set_charges": ([P, P], ctypes.c_int),
+        "fn3_eval": ([P, P, P], ctypes.c_int),
+        "fn3_eval_H_adjoint": ([P, P, P], ctypes.c_int),
+        "fn3_get_info": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
+        "fn3_last_error": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -171,4 +184,10 @@ def check_graph(rc):
 def check_mesh(rc, mesh=None):
     if rc != FN_OK:
         msg = lib().fn_mesh_last_error(mesh)
+        raise FemNfftError(rc, msg.decode() if msg else "")
+
+
+def check3(rc, ctx=None):
+    if rc != FN_OK:
+        msg = lib().fn3_last_error(ctx)
         raise FemNfftError(rc, msg.decode() if msg else "")

@@ -1,0 +1,1131 @@
+// The fast summation in 3D: the discrete Green sum of the paper's eq. (2) with the 3D
+// Green function given with eq. (1), G(r) = 1/(4 pi r), its field H = -grad phi and the
+// transpose of the H map, by the NFFT method of the paper's "NFFT" section (a grid of
+// about p^3 N points in 3D), FP64 throughout.
+//
+// Steps (the 2D path's, in three dimensions):
+//   torus map   c = bounding-box midpoint, D = 2 max |p - c|, s = (1/2 - eps_B)/D; for mapped
+//               points t = s (r - c), G(y - x) = s K(|t_y - t_x|), K(r) = 1/(4 pi r), so
+//               phi = s (torus sum) and H = s^2 (torus gradient sum)
+//   plan        K_R = T_I (even polynomial of degree 2p-2 matching K and p-1 derivatives at
+//               eps_I) inside eps_I, K up to 1/2 - eps_B, T_B to 1/2, constant beyond;
+//               b_l = DFT of K_R on the n^3 grid; W_l = omega_l b_l / prod_d psihat(l_d/G)^2
+//   spread      g_k = sum_j s_j prod_d psi(G t_jd - k_d), (2m)^3 taps; gathered per grid
+//               point over the points of the (2m)^3 cells that reach it (fixed order, no
+//               atomics), from per-point tap tables
+//   FFT         G^3 complex, Stockham line transforms through LDS along each axis
+//   multiply    W_l, and -2 pi i l_d W_l for the field; phi with H_z and H_x with H_y share
+//               one complex inverse transform each (real fields A + iB)
+//   gather      per target over the (2m)^3 taps of the four real grids
+//   near field  per target over the cells within eps_I: s_j (K - T_I)(r) and
+//               -s_j grad(K - T_I); a pair at distance 0 adds -s_j a_0 (the far field holds
+//               K_R(0) = a_0 for it, the exact sum leaves it out)
+//   adjoint     V spread at the targets (3 fields), sum_d 2 pi i l_d W_l F_d, inverse
+//               transform, gather at the sources, transposed near field; u = w s^2 (..)
+#include "fn_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace fn3 {
+
+using fn::MAXM;
+using fn::MAXP;
+
+constexpr double PI = 3.14159265358979323846264338327950288;
+constexpr double INV_4PI = 0.07957747154594766788444188168625718;
+constexpr int MAXG3 = 256;
+constexpr int NT = 256;
+
+struct Plan3 {
+    int G = 0, n = 0, m = 0, p = 0, log2G = 0, log2n = 0;
+    double eps_I = 0, eps_B = 0, kb_b = 0, i0mb = 0;
+    double a[MAXP] = {0};
+    std::vector<double> cB, psihat;
+    std::vector<double> twG, twn;  // [N][2] twiddles e^{-2 pi i k/N}
+};
+
+struct Geom3 {
+    int64_t nt = 0, ns = 0;
+    double c[3] = {0, 0, 0};
+    double s = 0;
+    int wlo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};
+    int rnear = 0;
+    int64_t near_pairs = 0;
+};
+
+struct Buf3 {
+    double *W = nullptr;              // [(n/2+1)^3]
+    double2 *twG = nullptr, *twn = nullptr;
+    uint32_t *key[2] = {nullptr, nullptr}, *perm[2] = {nullptr, nullptr}, *cstart[2] = {nullptr, nullptr};
+    double *fr[2] = {nullptr, nullptr};   // [3][N] in-cell fractions
+    double *taps[2] = {nullptr, nullptr}; // [N][3][2m] window taps
+    double *w = nullptr;              // sorted source weights
+    double *val = nullptr;            // s_j sorted
+    double *aval = nullptr;           // adjoint input V [3][nt] sorted
+    double2 *grid[3] = {nullptr, nullptr, nullptr};  // G^3 complex
+    double *far = nullptr;            // [4][max(nt, ns)]
+    double *red = nullptr;            // reduction scratch
+    uint32_t *skey = nullptr, *sval = nullptr, *hist = nullptr;
+};
+
+}  // namespace fn3
+
+struct fn3_ctx {
+    fn_params prm{};
+    fn3::Plan3 plan;
+    fn3::Geom3 geom;
+    fn3::Buf3 buf;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool plan_ready = false, geom_ready = false, charges_ready = false;
+    std::string err;
+};
+
+namespace fn3 {
+
+static thread_local std::string g_err3;
+
+// ------------------------------------------------------------------ host plan
+
+static double bessel_i0(double x)
+{
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 300; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+// r^q K^{(q)}(r) for K = 1/(4 pi r)
+static double K_scaled_deriv(int q, double r)
+{
+    double f = 1.0;
+    for (int i = 2; i <= q; ++i) f *= i;
+    return ((q % 2) ? -1.0 : 1.0) * f / (4.0 * PI * r);
+}
+
+static double falling(int a, int q)
+{
+    if (q > a) return 0.0;
+    double r = 1.0;
+    for (int i = 0; i < q; ++i) r *= (double)(a - i);
+    return r;
+}
+
+static bool solve(std::vector<double> A, std::vector<double> b, int n, std::vector<double> &x)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0.0) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    x.assign(n, 0.0);
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * x[k];
+        x[r] = s / A[r * n + r];
+    }
+    return true;
+}
+
+static void twiddles(int N, std::vector<double> &t)
+{
+    t.resize(2 * (size_t)N);
+    for (int k = 0; k < N; ++k) {
+        const long double a = -2.0L * (long double)PI * (long double)k / (long double)N;
+        t[2 * k] = (double)std::cos(a);
+        t[2 * k + 1] = (double)std::sin(a);
+    }
+}
+
+static bool build_plan(const fn_params &prm, Plan3 &P, std::string &err)
+{
+    P.G = prm.grid;
+    P.n = prm.n ? prm.n : prm.grid / 2;
+    P.m = prm.m;
+    P.p = prm.p;
+    P.eps_I = prm.eps_I;
+    P.eps_B = prm.eps_B;
+    while ((1 << P.log2G) < P.G) ++P.log2G;
+    while ((1 << P.log2n) < P.n) ++P.log2n;
+    P.kb_b = PI * (2.0 - (double)P.n / P.G);
+    P.i0mb = bessel_i0(P.m * P.kb_b);
+    {
+        const int p = P.p;
+        std::vector<double> A(p * p), b(p), x;
+        for (int q = 0; q < p; ++q) {
+            for (int k = 0; k < p; ++k) A[q * p + k] = falling(2 * k, q);
+            b[q] = K_scaled_deriv(q, P.eps_I);
+        }
+        if (!solve(A, b, p, x)) { err = "inner regularization system is singular"; return false; }
+        for (int k = 0; k < MAXP; ++k) P.a[k] = k < p ? x[k] : 0.0;
+    }
+    {
+        const int p = P.p;
+        const double rB = 0.5 - P.eps_B;
+        P.cB.assign(2 * p - 1, 0.0);
+        double fact = 1.0;
+        for (int q = 0; q < p; ++q) {
+            if (q > 0) fact *= q;
+            P.cB[q] = K_scaled_deriv(q, rB) * std::pow(P.eps_B / rB, q) / fact;
+        }
+        if (p > 1) {
+            const int nu = p - 1;
+            std::vector<double> A(nu * nu), b(nu), x;
+            for (int qi = 0; qi < nu; ++qi) {
+                const int q = qi + 1;
+                double rhs = 0.0;
+                for (int k = 0; k < p; ++k) rhs -= P.cB[k] * falling(k, q);
+                b[qi] = rhs;
+                for (int ki = 0; ki < nu; ++ki) A[qi * nu + ki] = falling(p + ki, q);
+            }
+            if (!solve(A, b, nu, x)) { err = "boundary regularization system is singular"; return false; }
+            for (int ki = 0; ki < nu; ++ki) P.cB[p + ki] = x[ki];
+        }
+    }
+    P.psihat.resize(P.n / 2 + 1);
+    for (int l = 0; l <= P.n / 2; ++l) {
+        const double w = 2.0 * PI * l / P.G;
+        P.psihat[l] = bessel_i0(P.m * std::sqrt(P.kb_b * P.kb_b - w * w)) / P.i0mb;
+    }
+    twiddles(P.G, P.twG);
+    twiddles(P.n, P.twn);
+    return true;
+}
+
+// ------------------------------------------------------------------ device helpers
+
+// Kaiser-Bessel window at t cells, sinh(b z)/(pi z I0(m b)) with z = sqrt(m^2 - t^2), evaluated
+// as (e^{-b t^2/(z+m)} - e^{-b(z+m)}) wnorm / z, wnorm = 1/(2 pi I0(m b) e^{-m b}) (the same
+// value: e^{b(z-m)} = e^{-b t^2/(z+m)}); zero for |t| >= m.
+__device__ __forceinline__ double kb_psi(double t, double m, double b, double wnorm)
+{
+    const double t2 = t * t;
+    const double z2 = m * m - t2;
+    if (!(z2 > 0.0)) return 0.0;
+    const double z = sqrt(z2);
+    const double zm = z + m;
+    return (exp(-b * t2 / zm) - exp(-b * zm)) * wnorm / z;
+}
+
+__device__ __forceinline__ int sfreq(int k, int N) { return k <= N / 2 ? k : k - N; }
+
+// ------------------------------------------------------------------ geometry kernels
+
+// per block: min x, y, z and max x, y, z (as negated mins), and a non-finite count
+__global__ void k3_bbox(const double *__restrict__ p, int64_t n, double *__restrict__ part)
+{
+    __shared__ double sh[7][NT];
+    double v[7] = {1e308, 1e308, 1e308, 1e308, 1e308, 1e308, 0.0};
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        for (int d = 0; d < 3; ++d) {
+            const double x = p[3 * i + d];
+            if (!isfinite(x)) { v[6] += 1.0; continue; }
+            v[d] = fmin(v[d], x);
+            v[3 + d] = fmin(v[3 + d], -x);
+        }
+    for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 7; ++k)
+                sh[k][threadIdx.x] = k < 6 ? fmin(sh[k][threadIdx.x], sh[k][threadIdx.x + h])
+                                           : sh[k][threadIdx.x] + sh[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) part[7 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k3_maxdist(const double *__restrict__ p, int64_t n, double cx, double cy, double cz,
+                           double *__restrict__ part)
+{
+    __shared__ double sh[NT];
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        const double a = p[3 * i] - cx, b = p[3 * i + 1] - cy, c = p[3 * i + 2] - cz;
+        v = fmax(v, a * a + b * b + c * c);
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k3_nonfinite(const double *__restrict__ w, int64_t n, double *__restrict__ part)
+{
+    __shared__ double sh[NT];
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        v += isfinite(w[i]) ? 0.0 : 1.0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+struct Map3 {
+    double c[3], s, G;
+    int m, wlo[3], ext[3];
+};
+
+// key = base (first tap) cell in the data window, x fastest; idx = i
+__global__ void k3_prepare(const double *__restrict__ p, int64_t n, Map3 mp, uint32_t *__restrict__ key,
+                           uint32_t *__restrict__ idx)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int half = (int)(0.5 * mp.G);
+    int b[3];
+    for (int d = 0; d < 3; ++d) {
+        const double v = (mp.s * (p[3 * i + d] - mp.c[d])) * mp.G;
+        b[d] = (int)floor(v) + half - mp.m + 1 - mp.wlo[d];
+        b[d] = min(max(b[d], 0), mp.ext[d] - 2 * mp.m);  // guards a rounding slip only
+    }
+    key[i] = ((uint32_t)b[2] * (uint32_t)mp.ext[1] + (uint32_t)b[1]) * (uint32_t)mp.ext[0] + (uint32_t)b[0];
+    idx[i] = (uint32_t)i;
+}
+
+// sorted fractions [3][n], window taps [n][3][2m] and sorted weights
+__global__ void k3_finish(const double *__restrict__ p, const double *__restrict__ w, int64_t n,
+                          const uint32_t *__restrict__ perm, Map3 mp, double kb_b, double wnorm,
+                          double *__restrict__ fr, double *__restrict__ taps, double *__restrict__ wsorted)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t i = perm[k];
+    const int M2 = 2 * mp.m;
+    for (int d = 0; d < 3; ++d) {
+        const double v = (mp.s * (p[3 * (int64_t)i + d] - mp.c[d])) * mp.G;
+        const double f = v - floor(v);
+        fr[d * n + k] = f;
+        for (int a = 0; a < M2; ++a) taps[(k * 3 + d) * M2 + a] = kb_psi(f + (double)(mp.m - 1 - a), mp.m, kb_b, wnorm);
+    }
+    if (wsorted) wsorted[k] = w[i];
+}
+
+// ------------------------------------------------------------------ plan kernels
+
+__global__ void k3_kr_samples(double2 *__restrict__ a, int n, const double *__restrict__ coef, int p,
+                              double eps_I, double eps_B, const double *__restrict__ cB, int ncB)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n3 = (int64_t)n * n * n;
+    if (idx >= n3) return;
+    const int j0 = (int)(idx % n), j1 = (int)((idx / n) % n), j2 = (int)(idx / ((int64_t)n * n));
+    const double c0 = sfreq(j0, n) == n / 2 ? -n / 2 : sfreq(j0, n);
+    const double c1 = sfreq(j1, n) == n / 2 ? -n / 2 : sfreq(j1, n);
+    const double c2 = sfreq(j2, n) == n / 2 ? -n / 2 : sfreq(j2, n);
+    const double r = sqrt(c0 * c0 + c1 * c1 + c2 * c2) / n;
+    const double rB = 0.5 - eps_B;
+    double v;
+    if (r < eps_I) {
+        const double rho2 = (r / eps_I) * (r / eps_I);
+        double acc = 0.0;
+        for (int k = p - 1; k >= 0; --k) acc = acc * rho2 + coef[k];
+        v = acc;
+    } else if (r <= rB) {
+        v = INV_4PI / r;
+    } else {
+        const double t = r > 0.5 ? 1.0 : (r - rB) / eps_B;
+        double acc = 0.0;
+        for (int k = ncB - 1; k >= 0; --k) acc = acc * t + cB[k];
+        v = acc;
+    }
+    a[idx] = make_double2(v, 0.0);
+}
+
+// W[(l0 (nh+1) + l1)(nh+1) + l2] = omega(l) Re(b_l) / prod psihat(l_d)^2 for l_d in [0, n/2];
+// bl holds n^3 b_l (unnormalized DFT of the samples)
+__global__ void k3_make_W(const double2 *__restrict__ bl, int n, const double *__restrict__ psihat,
+                          double *__restrict__ W)
+{
+    const int nh = n / 2, nh1 = nh + 1;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nh1 * nh1 * nh1) return;
+    const int l0 = (int)(idx / ((int64_t)nh1 * nh1)), l1 = (int)((idx / nh1) % nh1), l2 = (int)(idx % nh1);
+    // b_l is even in each component; sample index (l2, l1, l0) in the x-fastest layout
+    const double b = bl[((int64_t)(l0 % n) * n + (l1 % n)) * n + (l2 % n)].x / ((double)n * n * n);
+    const double om = (l0 == nh ? 0.5 : 1.0) * (l1 == nh ? 0.5 : 1.0) * (l2 == nh ? 0.5 : 1.0);
+    const double ph = psihat[l0] * psihat[l1] * psihat[l2];
+    W[idx] = om * b / (ph * ph);
+}
+
+// ------------------------------------------------------------------ FFT lines
+
+// In-place forward C2C transforms of lines of length N (a power of two, <= 256) of a
+// cube N^3 (x fastest) along `axis`; one line per block of N/2 threads, radix-2 Stockham
+// passes through LDS (ping-pong), twiddles from an FP64 table.  Inverse: conj in and out.
+__global__ void k3_lines(double2 *__restrict__ a, int N, int log2N, int axis, int inv,
+                         const double2 *__restrict__ tw)
+{
+    __shared__ double2 buf[2][MAXG3];
+    const int q = blockIdx.x;  // line index over the other two axes
+    const int64_t N1 = N, N2 = (int64_t)N * N;
+    int64_t base, stride;
+    if (axis == 0) { base = (int64_t)q * N1; stride = 1; }
+    else if (axis == 1) { base = (int64_t)(q / N) * N2 + (q % N); stride = N1; }
+    else { base = (int64_t)q; stride = N2; }
+    const int t = threadIdx.x;  // N/2 threads
+    for (int e = t; e < N; e += N / 2) {
+        double2 v = a[base + e * stride];
+        if (inv) v.y = -v.y;
+        buf[0][e] = v;
+    }
+    __syncthreads();
+    int src = 0;
+    // Stockham radix-2: at stage with half-length L (1, 2, 4, ...), butterfly j = k + L * r
+    for (int L = 1; L < N; L <<= 1) {
+        const int k = t % L, r = t / L;  // r in [0, N/(2L))
+        const double2 x0 = buf[src][k + L * r];
+        const double2 x1 = buf[src][k + L * r + N / 2];
+        const double2 w = tw[k * (N / (2 * L))];
+        const double2 y1 = make_double2(x1.x * w.x - x1.y * w.y, x1.x * w.y + x1.y * w.x);
+        buf[src ^ 1][k + 2 * L * r] = make_double2(x0.x + y1.x, x0.y + y1.y);
+        buf[src ^ 1][k + 2 * L * r + L] = make_double2(x0.x - y1.x, x0.y - y1.y);
+        src ^= 1;
+        __syncthreads();
+    }
+    for (int e = t; e < N; e += N / 2) {
+        double2 v = buf[src][e];
+        if (inv) v.y = -v.y;
+        a[base + e * stride] = v;
+    }
+}
+
+// ------------------------------------------------------------------ spread / multiply / gather
+
+// g_k for every grid point k of the data window, gathered over the base cells
+// b in [k - 2m + 1, k] of each axis (a point's taps reach k = b .. b + 2m - 1), written into the
+// G^3 complex grid at k + wlo (real part; imaginary part zero); grid points outside the window
+// are zeroed by k3_zero_outside.  nf fields of values val [f][N].  Each grid point sums its
+// points in the fixed order of the cells and of the sorted points (no atomics).
+__global__ void k3_spread(const double *__restrict__ taps, const uint32_t *__restrict__ key,
+                          const double *__restrict__ val, int64_t N, const uint32_t *__restrict__ cstart, Map3 mp,
+                          int nf, double2 *g0, double2 *g1, double2 *g2, int G)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int ex = mp.ext[0], ey = mp.ext[1], ez = mp.ext[2];
+    if (idx >= (int64_t)ex * ey * ez) return;
+    const int k0 = (int)(idx % ex), k1 = (int)((idx / ex) % ey), k2 = (int)(idx / ((int64_t)ex * ey));
+    const int M2 = 2 * mp.m;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int b0lo = max(k0 - M2 + 1, 0), b1lo = max(k1 - M2 + 1, 0), b2lo = max(k2 - M2 + 1, 0);
+    const int b0hi = min(k0, ex - M2), b1hi = min(k1, ey - M2), b2hi = min(k2, ez - M2);
+    if (b0lo <= b0hi)
+        for (int b2 = b2lo; b2 <= b2hi; ++b2)
+            for (int b1 = b1lo; b1 <= b1hi; ++b1) {
+                const int64_t row = ((int64_t)b2 * ey + b1) * ex;
+                const uint32_t j0 = cstart[row + b0lo], j1 = cstart[row + b0hi + 1];
+                for (uint32_t j = j0; j < j1; ++j) {
+                    const int b0 = (int)(key[j] % (uint32_t)ex);
+                    const double *tp = taps + (int64_t)j * 3 * M2;
+                    const double w = tp[k0 - b0] * tp[M2 + (k1 - b1)] * tp[2 * M2 + (k2 - b2)];
+                    for (int f = 0; f < nf; ++f) acc[f] += val[f * N + j] * w;
+                }
+            }
+    const int64_t o = ((int64_t)(k2 + mp.wlo[2]) * G + (k1 + mp.wlo[1])) * G + (k0 + mp.wlo[0]);
+    double2 *gs[3] = {g0, g1, g2};
+    for (int f = 0; f < nf; ++f) gs[f][o] = make_double2(acc[f], 0.0);
+}
+
+// zero the grid outside the data window
+__global__ void k3_zero_outside(double2 *g0, double2 *g1, double2 *g2, int nf, int G, Map3 mp)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * G * G) return;
+    const int x = (int)(idx % G), y = (int)((idx / G) % G), z = (int)(idx / ((int64_t)G * G));
+    const bool in = x >= mp.wlo[0] && x < mp.wlo[0] + mp.ext[0] && y >= mp.wlo[1] && y < mp.wlo[1] + mp.ext[1] &&
+                    z >= mp.wlo[2] && z < mp.wlo[2] + mp.ext[2];
+    if (in) return;
+    double2 *gs[3] = {g0, g1, g2};
+    for (int f = 0; f < nf; ++f) gs[f][idx] = make_double2(0.0, 0.0);
+}
+
+__device__ __forceinline__ double w_at(const double *__restrict__ W, int nh, int l0, int l1, int l2)
+{
+    const int a0 = abs(l0), a1 = abs(l1), a2 = abs(l2);
+    if (a0 > nh || a1 > nh || a2 > nh) return 0.0;
+    return W[((int64_t)a0 * (nh + 1) + a1) * (nh + 1) + a2];
+}
+
+// forward multiply: F -> T1 = W F + i (-2 pi i l_z W F) (phi + i H_z), T2 = (-2 pi i l_x W F) + i (-2 pi i l_y W F)
+__global__ void k3_mul_fwd(const double2 *__restrict__ F, double2 *__restrict__ T1, double2 *__restrict__ T2, int G,
+                           int nh, const double *__restrict__ W)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * G * G) return;
+    const int lx = sfreq((int)(idx % G), G), ly = sfreq((int)((idx / G) % G), G), lz = sfreq((int)(idx / ((int64_t)G * G)), G);
+    const double wv = w_at(W, nh, lz, ly, lx);
+    const double2 f = make_double2(wv * F[idx].x, wv * F[idx].y);
+    const double tp = 2.0 * PI;
+    // (-2 pi i l) f = (2 pi l f.y, -2 pi l f.x)
+    const double2 hx = make_double2(tp * lx * f.y, -tp * lx * f.x);
+    const double2 hy = make_double2(tp * ly * f.y, -tp * ly * f.x);
+    const double2 hz = make_double2(tp * lz * f.y, -tp * lz * f.x);
+    T1[idx] = make_double2(f.x - hz.y, f.y + hz.x);   // f + i hz
+    T2[idx] = make_double2(hx.x - hy.y, hx.y + hy.x); // hx + i hy
+}
+
+// adjoint multiply: T = sum_d (2 pi i l_d) W F_d
+__global__ void k3_mul_adj(const double2 *F0, const double2 *F1, const double2 *F2, double2 *T, int G, int nh,
+                           const double *__restrict__ W)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * G * G) return;
+    const int lx = sfreq((int)(idx % G), G), ly = sfreq((int)((idx / G) % G), G), lz = sfreq((int)(idx / ((int64_t)G * G)), G);
+    const double wv = w_at(W, nh, lz, ly, lx) * 2.0 * PI;
+    // (i l) f = (-l f.y, l f.x)
+    const double2 a = F0[idx], b = F1[idx], c = F2[idx];
+    const double sx = -(lx * a.y + ly * b.y + lz * c.y), sy = lx * a.x + ly * b.x + lz * c.x;
+    T[idx] = make_double2(wv * sx, wv * sy);
+}
+
+// far values at points of a set: sums over the (2m)^3 taps of real grid fields, the real and
+// imaginary parts of up to two complex grids.  nout = 1: out[k] = re A; nout = 4 (forward):
+// A = phi + i H_z, B = H_x + i H_y -> out[f][k] for f = phi, H_x, H_y, H_z.
+__global__ void k3_gather(const double *__restrict__ taps, const uint32_t *__restrict__ key, int64_t N, Map3 mp,
+                          const double2 *__restrict__ A, const double2 *__restrict__ B, int nout, int G,
+                          double *__restrict__ out)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int M2 = 2 * mp.m;
+    const uint32_t kk = key[k];
+    const int b0 = (int)(kk % (uint32_t)mp.ext[0]), b1 = (int)((kk / (uint32_t)mp.ext[0]) % (uint32_t)mp.ext[1]);
+    const int b2 = (int)(kk / ((uint32_t)mp.ext[0] * (uint32_t)mp.ext[1]));
+    const double *tp = taps + k * 3 * M2;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < M2; ++c) {
+        const int z = b2 + c + mp.wlo[2];
+        for (int b = 0; b < M2; ++b) {
+            const int y = b1 + b + mp.wlo[1];
+            const double wyz = tp[M2 + b] * tp[2 * M2 + c];
+            const int64_t row = ((int64_t)z * G + y) * G + (b0 + mp.wlo[0]);
+            for (int a = 0; a < M2; ++a) {
+                const double w = tp[a] * wyz;
+                const double2 u = A[row + a];
+                acc[0] += w * u.x;
+                if (nout > 2) acc[1] += w * u.y;
+                if (nout > 2) {
+                    const double2 v = B[row + a];
+                    acc[2] += w * v.x;
+                    acc[3] += w * v.y;
+                }
+            }
+        }
+    }
+    if (nout == 4) {
+        out[k] = acc[0];
+        out[N + k] = acc[2];
+        out[2 * N + k] = acc[3];
+        out[3 * N + k] = acc[1];
+    } else {
+        out[k] = acc[0];
+    }
+}
+
+// ------------------------------------------------------------------ near field + final
+
+struct Near3 {
+    double e2g, invG, a[MAXP], da[MAXP];  // e2g = (eps_I G)^2; T_I coefficients, (k+1) a_{k+1}
+    int p, R;
+    double s;
+};
+
+// (K - T_I) and f with -grad(K - T_I)(d) = f d, d in torus units, r2 = |d|^2 > 0; e2 = eps_I^2.
+// T_I(r) = sum_k a_k x^k with x = (r/eps_I)^2, so T_I'(r)/r = (2/e2) sum_k da_k x^k.
+__device__ __forceinline__ void near_k(const Near3 &nr, double r2, double e2, double &kphi, double &f)
+{
+    const double x = r2 / e2;
+    double t = nr.a[nr.p - 1];
+    for (int k = nr.p - 2; k >= 0; --k) t = t * x + nr.a[k];
+    double d = 0.0;
+    for (int k = nr.p - 2; k >= 0; --k) d = d * x + nr.da[k];
+    const double r = sqrt(r2);
+    kphi = INV_4PI / r - t;
+    f = INV_4PI / (r2 * r) + 2.0 * d / e2;
+}
+
+// Forward (targets home, sources in): phi_i = s (far + near), H_i = s^2 (far + near), caller order.
+// Adjoint (sources home, targets in, payload V [3][nt]): u_j = w_j s^2 (far - near_dot) (the pair
+// offset is source minus target there).
+template <bool ADJ>
+__global__ void k3_near(const double *__restrict__ fr_out, const uint32_t *__restrict__ key_out,
+                        const uint32_t *__restrict__ perm_out, int64_t n_out, const double *__restrict__ fr_in,
+                        const uint32_t *__restrict__ key_in, const uint32_t *__restrict__ cs_in, int64_t n_in,
+                        const double *__restrict__ pay, Map3 mp, Near3 nr, const double *__restrict__ far,
+                        const double *__restrict__ w_out, double *__restrict__ o_phi, double *__restrict__ o_H)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_out) return;
+    const int ex = mp.ext[0], ey = mp.ext[1], ez = mp.ext[2];
+    const uint32_t kk = key_out[i];
+    const int c0 = (int)(kk % (uint32_t)ex), c1 = (int)((kk / (uint32_t)ex) % (uint32_t)ey);
+    const int c2 = (int)(kk / ((uint32_t)ex * (uint32_t)ey));
+    const double f0 = fr_out[i], f1 = fr_out[n_out + i], f2 = fr_out[2 * n_out + i];
+    const double e2 = nr.e2g;  // in grid units^2
+    const int R = nr.R;
+    double ap = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int z = max(c2 - R, 0); z <= min(c2 + R, ez - 1); ++z) {
+        const double gz = z < c2 ? (double)(c2 - z - 1) + f2 : (z > c2 ? (double)(z - c2) - f2 : 0.0);
+        if (gz * gz >= e2) continue;
+        for (int y = max(c1 - R, 0); y <= min(c1 + R, ey - 1); ++y) {
+            const double gy = y < c1 ? (double)(c1 - y - 1) + f1 : (y > c1 ? (double)(y - c1) - f1 : 0.0);
+            const double h2 = e2 - gz * gz - gy * gy;
+            if (h2 <= 0.0) continue;
+            const double wdt = sqrt(h2) + 1e-9;
+            const int x0 = max((int)floor((double)c0 + f0 - wdt), 0);
+            const int x1 = min((int)floor((double)c0 + f0 + wdt), ex - 1);
+            if (x0 > x1) continue;
+            const int64_t row = ((int64_t)z * ey + y) * ex;
+            for (uint32_t j = cs_in[row + x0]; j < cs_in[row + x1 + 1]; ++j) {
+                const uint32_t kj = key_in[j];
+                const int j0 = (int)(kj % (uint32_t)ex);
+                // offset home minus staged, grid units
+                const double d0 = (double)(c0 - j0) + (f0 - fr_in[j]);
+                const double d1 = (double)(c1 - y) + (f1 - fr_in[n_in + j]);
+                const double d2 = (double)(c2 - z) + (f2 - fr_in[2 * n_in + j]);
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                if (r2 >= e2) continue;
+                if (r2 == 0.0) {  // not part of the exact sum: remove the far field's K_R(0) = a_0
+                    if (!ADJ) ap -= nr.a[0] * pay[j];
+                    continue;
+                }
+                double kphi, f;
+                // torus units: d / G, r2 / G^2
+                near_k(nr, r2 * nr.invG * nr.invG, e2 * nr.invG * nr.invG, kphi, f);
+                const double t0 = d0 * nr.invG, t1 = d1 * nr.invG, t2 = d2 * nr.invG;
+                if (!ADJ) {
+                    const double sj = pay[j];
+                    ap += sj * kphi;
+                    a0 += sj * f * t0;
+                    a1 += sj * f * t1;
+                    a2 += sj * f * t2;
+                } else {
+                    // pair offset here is source minus target: -grad G at (target - source)
+                    ap -= f * (pay[j] * t0 + pay[n_in + j] * t1 + pay[2 * n_in + j] * t2);
+                }
+            }
+        }
+    }
+    const uint32_t o = perm_out[i];
+    if (!ADJ) {
+        if (o_phi) o_phi[o] = nr.s * (far[i] + ap);
+        if (o_H) {
+            const double s2 = nr.s * nr.s;
+            o_H[3 * (int64_t)o] = s2 * (far[n_out + i] + a0);
+            o_H[3 * (int64_t)o + 1] = s2 * (far[2 * n_out + i] + a1);
+            o_H[3 * (int64_t)o + 2] = s2 * (far[3 * n_out + i] + a2);
+        }
+    } else {
+        o_phi[o] = w_out[i] * nr.s * nr.s * (far[i] + ap);
+    }
+}
+
+// values in sorted order: out[f][k] = (w_k) in[perm_k][f] (w NULL: 1), nf components per point
+__global__ void k3_values(const double *__restrict__ in, const double *__restrict__ w, const uint32_t *__restrict__ perm,
+                          int64_t n, int nf, double *__restrict__ out)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t i = perm[k];
+    for (int f = 0; f < nf; ++f) out[f * n + k] = (w ? w[k] : 1.0) * in[(int64_t)i * nf + f];
+}
+
+__global__ void k3_fill(double *p, int64_t n, double v)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+inline int nbk(int64_t n) { return (int)std::max<int64_t>(1, (n + NT - 1) / NT); }
+
+}  // namespace fn3
+
+using namespace fn3;
+
+#define F3_ERR(c, code, msg) \
+    do {                     \
+        (c)->err = (msg);    \
+        return (code);       \
+    } while (0)
+#define F3_HIP(c, call)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            (c)->err = std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_);   \
+            return FN_E_DEVICE;                                                               \
+        }                                                                                     \
+    } while (0)
+#define F3_LAUNCH(c) F3_HIP(c, hipGetLastError())
+
+namespace {
+
+struct Layout3 {
+    size_t total = 0, off_W = 0, off_twG = 0, off_twn = 0, off_key[2] = {0, 0}, off_perm[2] = {0, 0},
+           off_cs[2] = {0, 0}, off_fr[2] = {0, 0}, off_taps[2] = {0, 0}, off_w = 0, off_val = 0, off_aval = 0,
+           off_grid[3] = {0, 0, 0},
+           off_far = 0, off_red = 0, off_skey = 0, off_sval = 0, off_hist = 0;
+    int64_t emax = 0;
+};
+
+Layout3 layout3(const Plan3 &P, int64_t nt, int64_t ns)
+{
+    Layout3 L;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t r = o;
+        o = (o + b + 255) & ~(size_t)255;
+        return r;
+    };
+    const int nh1 = P.n / 2 + 1;
+    L.emax = P.G / 2 + 2 * P.m + 4;
+    const int64_t ncell = L.emax * L.emax * L.emax;
+    const int64_t N[2] = {std::max<int64_t>(nt, 1), std::max<int64_t>(ns, 1)};
+    const int64_t nmax = std::max(N[0], N[1]);
+    const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    L.off_W = take((size_t)nh1 * nh1 * nh1 * 8);
+    L.off_twG = take((size_t)P.G * 16);
+    L.off_twn = take((size_t)P.n * 16);
+    for (int s = 0; s < 2; ++s) {
+        L.off_key[s] = take(N[s] * 4);
+        L.off_perm[s] = take(N[s] * 4);
+        L.off_cs[s] = take((size_t)(ncell + 1) * 4);
+        L.off_fr[s] = take(N[s] * 24);
+        L.off_taps[s] = take(N[s] * 3 * 2 * P.m * 8);
+    }
+    L.off_w = take(N[1] * 8);
+    L.off_val = take(N[1] * 8);
+    L.off_aval = take(3 * N[0] * 8);
+    // three G^3 complex grids; they also hold the n^3 plan transform (n <= 3G/4 < G)
+    for (int g = 0; g < 3; ++g) L.off_grid[g] = take((size_t)G3 * 16);
+    L.off_far = take(4 * nmax * 8);
+    L.off_red = take(8192 * 8);
+    L.off_skey = take(nmax * 4);
+    L.off_sval = take(nmax * 4);
+    L.off_hist = take((size_t)256 * ((nmax + 4095) / 4096) * 4);
+    L.total = o;
+    return L;
+}
+
+void bind3(fn3_ctx *c, const Layout3 &L)
+{
+    char *b = static_cast<char *>(c->ws);
+    Buf3 &B = c->buf;
+    B.W = reinterpret_cast<double *>(b + L.off_W);
+    B.twG = reinterpret_cast<double2 *>(b + L.off_twG);
+    B.twn = reinterpret_cast<double2 *>(b + L.off_twn);
+    for (int s = 0; s < 2; ++s) {
+        B.key[s] = reinterpret_cast<uint32_t *>(b + L.off_key[s]);
+        B.perm[s] = reinterpret_cast<uint32_t *>(b + L.off_perm[s]);
+        B.cstart[s] = reinterpret_cast<uint32_t *>(b + L.off_cs[s]);
+        B.fr[s] = reinterpret_cast<double *>(b + L.off_fr[s]);
+        B.taps[s] = reinterpret_cast<double *>(b + L.off_taps[s]);
+    }
+    B.w = reinterpret_cast<double *>(b + L.off_w);
+    B.val = reinterpret_cast<double *>(b + L.off_val);
+    B.aval = reinterpret_cast<double *>(b + L.off_aval);
+    for (int g = 0; g < 3; ++g) B.grid[g] = reinterpret_cast<double2 *>(b + L.off_grid[g]);
+    B.far = reinterpret_cast<double *>(b + L.off_far);
+    B.red = reinterpret_cast<double *>(b + L.off_red);
+    B.skey = reinterpret_cast<uint32_t *>(b + L.off_skey);
+    B.sval = reinterpret_cast<uint32_t *>(b + L.off_sval);
+    B.hist = reinterpret_cast<uint32_t *>(b + L.off_hist);
+}
+
+// 3D transform of a cube of N^3 complex values (N <= 256)
+int fft3(fn3_ctx *c, double2 *a, int N, int log2N, int inv, const double2 *tw)
+{
+    for (int axis = 0; axis < 3; ++axis) {
+        k3_lines<<<N * N, N / 2, 0, c->stream>>>(a, N, log2N, axis, inv, tw);
+        F3_LAUNCH(c);
+    }
+    return FN_OK;
+}
+
+int build_plan3(fn3_ctx *c)
+{
+    const Plan3 &P = c->plan;
+    Buf3 &B = c->buf;
+    hipStream_t st = c->stream;
+    F3_HIP(c, hipMemcpyAsync(B.twG, P.twG.data(), P.twG.size() * 8, hipMemcpyHostToDevice, st));
+    F3_HIP(c, hipMemcpyAsync(B.twn, P.twn.data(), P.twn.size() * 8, hipMemcpyHostToDevice, st));
+    double *coef = B.red, *cB = B.red + 32, *psi = B.red + 128;
+    F3_HIP(c, hipMemcpyAsync(coef, P.a, sizeof(double) * MAXP, hipMemcpyHostToDevice, st));
+    F3_HIP(c, hipMemcpyAsync(cB, P.cB.data(), sizeof(double) * P.cB.size(), hipMemcpyHostToDevice, st));
+    F3_HIP(c, hipMemcpyAsync(psi, P.psihat.data(), sizeof(double) * P.psihat.size(), hipMemcpyHostToDevice, st));
+    const int64_t n3 = (int64_t)P.n * P.n * P.n;
+    double2 *scr = B.grid[0];
+    k3_kr_samples<<<nbk(n3), NT, 0, st>>>(scr, P.n, coef, P.p, P.eps_I, P.eps_B, cB, (int)P.cB.size());
+    F3_LAUNCH(c);
+    int rc = fft3(c, scr, P.n, P.log2n, 0, B.twn);
+    if (rc) return rc;
+    const int64_t nh1 = P.n / 2 + 1;
+    k3_make_W<<<nbk(nh1 * nh1 * nh1), NT, 0, st>>>(scr, P.n, psi, B.W);
+    F3_LAUNCH(c);
+    F3_HIP(c, hipStreamSynchronize(st));
+    c->plan_ready = true;
+    return FN_OK;
+}
+
+Map3 map_of(const fn3_ctx *c)
+{
+    Map3 mp;
+    for (int d = 0; d < 3; ++d) {
+        mp.c[d] = c->geom.c[d];
+        mp.wlo[d] = c->geom.wlo[d];
+        mp.ext[d] = c->geom.ext[d];
+    }
+    mp.s = c->geom.s;
+    mp.G = c->plan.G;
+    mp.m = c->plan.m;
+    return mp;
+}
+
+Near3 near_of(const fn3_ctx *c)
+{
+    Near3 nr{};
+    const Plan3 &P = c->plan;
+    const double eg = P.eps_I * P.G;
+    nr.e2g = eg * eg;
+    nr.invG = 1.0 / P.G;
+    for (int k = 0; k < MAXP; ++k) nr.a[k] = P.a[k];
+    for (int k = 0; k + 1 < MAXP; ++k) nr.da[k] = (k + 1) * P.a[k + 1];
+    nr.p = P.p;
+    nr.R = c->geom.rnear;
+    nr.s = c->geom.s;
+    return nr;
+}
+
+int check_dev(fn3_ctx *c)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) F3_ERR(c, FN_E_DEVICE, std::string("pending HIP error: ") + hipGetErrorString(e));
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+        if (hipSetDevice(c->device) != hipSuccess) F3_ERR(c, FN_E_DEVICE, "cannot select the context's device");
+    return FN_OK;
+}
+
+// spread nf value fields of set `set` into grids, zero outside the window, forward FFT each
+int spread_fft(fn3_ctx *c, int set, const double *val, int64_t N, int nf)
+{
+    const Plan3 &P = c->plan;
+    Buf3 &B = c->buf;
+    const Map3 mp = map_of(c);
+    const int64_t cells = (int64_t)mp.ext[0] * mp.ext[1] * mp.ext[2];
+    const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    k3_zero_outside<<<nbk(G3), NT, 0, c->stream>>>(B.grid[0], B.grid[1], B.grid[2], nf, P.G, mp);
+    F3_LAUNCH(c);
+    k3_spread<<<nbk(cells), NT, 0, c->stream>>>(B.taps[set], B.key[set], val, N, B.cstart[set], mp, nf, B.grid[0],
+                                                 B.grid[1], B.grid[2], P.G);
+    F3_LAUNCH(c);
+    for (int f = 0; f < nf; ++f) {
+        int rc = fft3(c, B.grid[f], P.G, P.log2G, 0, B.twG);
+        if (rc) return rc;
+    }
+    return FN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fn3_create(const fn_params *params, void *stream, fn3_ctx **out)
+{
+    if (!out) { g_err3 = "out is NULL"; return FN_E_INVAL; }
+    *out = nullptr;
+    if (!params) { g_err3 = "params is NULL"; return FN_E_INVAL; }
+    const fn_params &p = *params;
+    const int G = p.grid;
+    if (G < 16 || G > MAXG3 || (G & (G - 1))) { g_err3 = "grid must be a power of two in [16, 256]"; return FN_E_INVAL; }
+    if (p.m < 2 || p.m > MAXM) { g_err3 = "m must be in [2, 8]"; return FN_E_INVAL; }
+    // the data window spans cells [G/4 - m, 3G/4 + m + 1] of each axis: it must fit the grid
+    if (p.m > G / 4 - 1) { g_err3 = "m must be at most grid/4 - 1"; return FN_E_INVAL; }
+    if (p.p < 1 || p.p > MAXP) { g_err3 = "p must be in [1, 12]"; return FN_E_INVAL; }
+    if (!(p.eps_B > 0.0) || !(p.eps_B < 0.25)) { g_err3 = "eps_B must be in (0, 1/4)"; return FN_E_INVAL; }
+    if (!(p.eps_I > 0.0) || !(p.eps_I * G <= 32.0) || !(p.eps_I < 0.5 - p.eps_B)) {
+        g_err3 = "eps_I must be positive, eps_I*grid <= 32 and eps_I < 1/2 - eps_B";
+        return FN_E_INVAL;
+    }
+    if (p.precision != FN_FP64) { g_err3 = "the 3D path computes in FP64 only (precision FN_FP64)"; return FN_E_UNSUPPORTED; }
+    if (p.eps_S != 0.0 || p.flags != 0) { g_err3 = "eps_S and flags must be 0 in 3D"; return FN_E_UNSUPPORTED; }
+    if (p.n != 0 && (p.n != G / 2)) { g_err3 = "the 3D path uses the bandwidth n = G/2 (n must be 0)"; return FN_E_UNSUPPORTED; }
+    fn3_ctx *c = new (std::nothrow) fn3_ctx();
+    if (!c) { g_err3 = "out of host memory"; return FN_E_NOMEM; }
+    c->prm = p;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; g_err3 = "no HIP device"; return FN_E_DEVICE; }
+    std::string err;
+    if (!build_plan(p, c->plan, err)) { delete c; g_err3 = err; return FN_E_INVAL; }
+    *out = c;
+    return FN_OK;
+}
+
+int fn3_destroy(fn3_ctx *ctx)
+{
+    delete ctx;
+    return FN_OK;
+}
+
+int fn3_workspace_size(const fn3_ctx *ctx, int64_t n_tgt, int64_t n_src, size_t *bytes)
+{
+    if (!ctx || !bytes || n_tgt < 0 || n_src < 0 || n_tgt > (int64_t)UINT32_MAX / 2 || n_src > (int64_t)UINT32_MAX / 2)
+        return FN_E_INVAL;
+    *bytes = layout3(ctx->plan, n_tgt, n_src).total;
+    return FN_OK;
+}
+
+int fn3_set_workspace(fn3_ctx *ctx, void *dev_ptr, size_t bytes)
+{
+    if (!ctx) return FN_E_INVAL;
+    if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) F3_ERR(ctx, FN_E_INVAL, "workspace must be non-NULL and 256-byte aligned");
+    ctx->ws = dev_ptr;
+    ctx->ws_bytes = bytes;
+    ctx->plan_ready = ctx->geom_ready = ctx->charges_ready = false;
+    return FN_OK;
+}
+
+int fn3_set_geometry(fn3_ctx *ctx, int64_t n_tgt, const double *tgt_xyz, int64_t n_src, const double *src_xyz,
+                     const double *src_w)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn3_ctx *c = ctx;
+    if (!c->ws) F3_ERR(c, FN_E_STATE, "fn3_set_workspace must be called before fn3_set_geometry");
+    if (n_tgt < 0 || n_src < 0 || n_tgt + n_src < 1 || n_tgt > (int64_t)UINT32_MAX / 2 || n_src > (int64_t)UINT32_MAX / 2)
+        F3_ERR(c, FN_E_INVAL, "need n_tgt, n_src >= 0, n_tgt + n_src >= 1, both < 2^31");
+    if ((n_tgt > 0 && !tgt_xyz) || (n_src > 0 && (!src_xyz || !src_w))) F3_ERR(c, FN_E_INVAL, "NULL point or weight array");
+    if (stream_capturing(c->stream)) F3_ERR(c, FN_E_STATE, "fn3_set_geometry waits for the device: not during graph capture");
+    int rc = check_dev(c);
+    if (rc) return rc;
+    c->geom_ready = c->charges_ready = false;
+    const Layout3 L = layout3(c->plan, n_tgt, n_src);
+    if (L.total > c->ws_bytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "workspace too small: %zu bytes needed, %zu given", L.total, c->ws_bytes);
+        F3_ERR(c, FN_E_NOMEM, msg);
+    }
+    bind3(c, L);
+    if (!c->plan_ready) {
+        rc = build_plan3(c);
+        if (rc) return rc;
+    }
+    Buf3 &B = c->buf;
+    const Plan3 &P = c->plan;
+    hipStream_t st = c->stream;
+    // bounding box and non-finite inputs
+    double lo[3] = {1e308, 1e308, 1e308}, hi[3] = {-1e308, -1e308, -1e308}, bad = 0.0;
+    const double *pts[2] = {tgt_xyz, src_xyz};
+    const int64_t cnt[2] = {n_tgt, n_src};
+    double h[7 * 256];
+    for (int s = 0; s < 2; ++s) {
+        if (cnt[s] == 0) continue;
+        const int nb = (int)std::min<int64_t>(256, (cnt[s] + NT - 1) / NT);
+        k3_bbox<<<nb, NT, 0, st>>>(pts[s], cnt[s], B.red);
+        F3_LAUNCH(c);
+        F3_HIP(c, hipMemcpyAsync(h, B.red, sizeof(double) * 7 * nb, hipMemcpyDeviceToHost, st));
+        F3_HIP(c, hipStreamSynchronize(st));
+        for (int b = 0; b < nb; ++b) {
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], h[7 * b + d]);
+                hi[d] = std::max(hi[d], -h[7 * b + 3 + d]);
+            }
+            bad += h[7 * b + 6];
+        }
+    }
+    if (n_src > 0) {
+        const int nb = (int)std::min<int64_t>(256, (n_src + NT - 1) / NT);
+        k3_nonfinite<<<nb, NT, 0, st>>>(src_w, n_src, B.red);
+        F3_LAUNCH(c);
+        F3_HIP(c, hipMemcpyAsync(h, B.red, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+        F3_HIP(c, hipStreamSynchronize(st));
+        for (int b = 0; b < nb; ++b) bad += h[b];
+    }
+    if (bad > 0.0) F3_ERR(c, FN_E_INVAL, "non-finite coordinate or weight");
+    Geom3 g;
+    g.nt = n_tgt;
+    g.ns = n_src;
+    for (int d = 0; d < 3; ++d) g.c[d] = 0.5 * (lo[d] + hi[d]);
+    double m2 = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        if (cnt[s] == 0) continue;
+        const int nb = (int)std::min<int64_t>(256, (cnt[s] + NT - 1) / NT);
+        k3_maxdist<<<nb, NT, 0, st>>>(pts[s], cnt[s], g.c[0], g.c[1], g.c[2], B.red);
+        F3_LAUNCH(c);
+        F3_HIP(c, hipMemcpyAsync(h, B.red, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+        F3_HIP(c, hipStreamSynchronize(st));
+        for (int b = 0; b < nb; ++b) m2 = std::max(m2, h[b]);
+    }
+    const double D = 2.0 * std::sqrt(m2);
+    if (!(D > 0.0) || !std::isfinite(D)) F3_ERR(c, FN_E_DOMAIN, "all points coincide");
+    g.s = (0.5 - P.eps_B) / D;
+    for (int d = 0; d < 3; ++d) {
+        const double umin = (g.s * (lo[d] - g.c[d])) * P.G + 0.5 * P.G;
+        const double umax = (g.s * (hi[d] - g.c[d])) * P.G + 0.5 * P.G;
+        g.wlo[d] = (int)std::floor(umin) - P.m;
+        const int whi = (int)std::floor(umax) + P.m + 2;
+        g.ext[d] = whi - g.wlo[d];
+        if (g.ext[d] > L.emax || g.wlo[d] < 0 || whi > P.G) F3_ERR(c, FN_E_DEVICE, "internal: data window exceeds its bound");
+    }
+    g.rnear = (int)std::ceil(P.eps_I * P.G);
+    c->geom = g;
+    const Map3 mp = map_of(c);
+    const int64_t ncell = (int64_t)g.ext[0] * g.ext[1] * g.ext[2];
+    int keybits = 1;
+    while (((int64_t)1 << keybits) < ncell) ++keybits;
+    const double wnorm = 1.0 / (2.0 * PI * P.i0mb * std::exp(-P.m * P.kb_b));
+    for (int s = 0; s < 2; ++s) {
+        const int64_t n = cnt[s];
+        if (n > 0) {
+            k3_prepare<<<nbk(n), NT, 0, st>>>(pts[s], n, mp, B.key[s], B.perm[s]);
+            F3_LAUNCH(c);
+            F3_HIP(c, fn::radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, n, keybits, st));
+            k3_finish<<<nbk(n), NT, 0, st>>>(pts[s], s ? src_w : nullptr, n, B.perm[s], mp, P.kb_b, wnorm, B.fr[s],
+                                               B.taps[s], s ? B.w : nullptr);
+            F3_LAUNCH(c);
+        }
+        F3_HIP(c, fn::launch_cellstart(B.key[s], n, ncell, B.cstart[s], st));
+    }
+    F3_HIP(c, hipStreamSynchronize(st));
+    c->geom_ready = true;
+    return FN_OK;
+}
+
+int fn3_set_charges(fn3_ctx *ctx, const double *q)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn3_ctx *c = ctx;
+    if (!c->geom_ready) F3_ERR(c, FN_E_STATE, "fn3_set_geometry must succeed before fn3_set_charges");
+    if (c->geom.ns > 0 && !q) F3_ERR(c, FN_E_INVAL, "q is NULL");
+    int rc = check_dev(c);
+    if (rc) return rc;
+    if (c->geom.ns > 0) {
+        k3_values<<<nbk(c->geom.ns), NT, 0, c->stream>>>(q, c->buf.w, c->buf.perm[1], c->geom.ns, 1, c->buf.val);
+        F3_LAUNCH(c);
+    }
+    c->charges_ready = true;
+    return FN_OK;
+}
+
+int fn3_eval(fn3_ctx *ctx, double *phi, double *H)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn3_ctx *c = ctx;
+    if (!c->charges_ready) F3_ERR(c, FN_E_STATE, "fn3_set_charges must be called before fn3_eval");
+    const Geom3 &g = c->geom;
+    if (g.nt > 0 && !phi && !H) F3_ERR(c, FN_E_INVAL, "both outputs are NULL");
+    int rc = check_dev(c);
+    if (rc) return rc;
+    if (g.nt == 0) return FN_OK;
+    hipStream_t st = c->stream;
+    Buf3 &B = c->buf;
+    const Plan3 &P = c->plan;
+    if (g.ns == 0) {
+        if (phi) k3_fill<<<nbk(g.nt), NT, 0, st>>>(phi, g.nt, 0.0);
+        if (H) k3_fill<<<nbk(3 * g.nt), NT, 0, st>>>(H, 3 * g.nt, 0.0);
+        F3_LAUNCH(c);
+        return FN_OK;
+    }
+    rc = spread_fft(c, 1, B.val, g.ns, 1);
+    if (rc) return rc;
+    const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    k3_mul_fwd<<<nbk(G3), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], P.G, P.n / 2, B.W);
+    F3_LAUNCH(c);
+    for (int f = 1; f <= 2; ++f) {
+        rc = fft3(c, B.grid[f], P.G, P.log2G, 1, B.twG);
+        if (rc) return rc;
+    }
+    const Map3 mp = map_of(c);
+    // far: phi (re T1), H_z (im T1), H_x (re T2), H_y (im T2) -> far[0..3] as phi, Hx, Hy, Hz
+    double *far = B.far;  // [4][nt]: phi, H_x, H_y, H_z
+    k3_gather<<<nbk(g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
+    F3_LAUNCH(c);
+    k3_near<false><<<nbk(g.nt), NT, 0, st>>>(B.fr[0], B.key[0], B.perm[0], g.nt, B.fr[1], B.key[1], B.cstart[1], g.ns,
+                                              B.val, mp, near_of(c), far, nullptr, phi, H);
+    F3_LAUNCH(c);
+    return FN_OK;
+}
+
+int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u)
+{
+    if (!ctx) return FN_E_INVAL;
+    fn3_ctx *c = ctx;
+    if (!c->geom_ready) F3_ERR(c, FN_E_STATE, "fn3_set_geometry must succeed before fn3_eval_H_adjoint");
+    const Geom3 &g = c->geom;
+    if ((g.nt > 0 && !V) || (g.ns > 0 && !u)) F3_ERR(c, FN_E_INVAL, "NULL input or output");
+    int rc = check_dev(c);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    Buf3 &B = c->buf;
+    const Plan3 &P = c->plan;
+    if (g.ns == 0) return FN_OK;
+    if (g.nt == 0) {
+        k3_fill<<<nbk(g.ns), NT, 0, st>>>(u, g.ns, 0.0);
+        F3_LAUNCH(c);
+        return FN_OK;
+    }
+    k3_values<<<nbk(g.nt), NT, 0, st>>>(V, nullptr, B.perm[0], g.nt, 3, B.aval);
+    F3_LAUNCH(c);
+    rc = spread_fft(c, 0, B.aval, g.nt, 3);
+    if (rc) return rc;
+    const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    // T = sum_d 2 pi i l_d W F_d into grid 0 (in place: each element reads its own F values)
+    k3_mul_adj<<<nbk(G3), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], B.grid[0], P.G, P.n / 2, B.W);
+    F3_LAUNCH(c);
+    rc = fft3(c, B.grid[0], P.G, P.log2G, 1, B.twG);
+    if (rc) return rc;
+    const Map3 mp = map_of(c);
+    k3_gather<<<nbk(g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
+    F3_LAUNCH(c);
+    k3_near<true><<<nbk(g.ns), NT, 0, st>>>(B.fr[1], B.key[1], B.perm[1], g.ns, B.fr[0], B.key[0], B.cstart[0], g.nt,
+                                             B.aval, mp, near_of(c), B.far, B.w, u, nullptr);
+    F3_LAUNCH(c);
+    return FN_OK;
+}
+
+int fn3_get_info(const fn3_ctx *ctx, int64_t *n_tgt, int64_t *n_src, double *scale, int32_t *win_ext, int32_t *near_cells)
+{
+    if (!ctx) return FN_E_INVAL;
+    if (n_tgt) *n_tgt = ctx->geom.nt;
+    if (n_src) *n_src = ctx->geom.ns;
+    if (scale) *scale = ctx->geom.s;
+    if (win_ext)
+        for (int d = 0; d < 3; ++d) win_ext[d] = ctx->geom.ext[d];
+    if (near_cells) *near_cells = ctx->geom.rnear;
+    return FN_OK;
+}
+
+const char *fn3_last_error(const fn3_ctx *ctx)
+{
+    if (!ctx) return g_err3.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

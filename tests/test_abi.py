@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "femnfft.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fn_[A-Za-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fn3?_[A-Za-z_0-9]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():

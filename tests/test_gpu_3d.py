@@ -1,0 +1,129 @@
+"""The 3D fast summation (fn3_*, G = 1/(4 pi r)) through the C-ABI against the 3D oracles.
+
+  * parity with the step-by-step oracle O2 (oracle.fastsum3) element by element: phi, H and
+    the H adjoint, FP64, bound 1e-10 (relative L2 and per element, tests.conftest.parity_err),
+    on ball and cube clouds at G = 32, 64, 128 (several cells per near radius, ragged point
+    counts, targets coinciding with sources);
+  * accuracy against the direct sum O1 at the tested parameters (the oracle's own bounds);
+  * empty source or target sets, degenerate geometry and the parameter checks.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct
+from oracle import fastsum3 as f3
+from tests.conftest import max_rel, parity_err, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def fn():
+    import paper_0807_2387_amd as _fn
+    return _fn
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+# name, n_tgt, n_src, shape, G, m, p, n eps_I, seed, coincident targets
+CASES = [
+    ("G32-ball", 701, 903, "ball", 32, 5, 5, 4, 31, 0),
+    ("G64-cube", 2999, 4001, "cube", 64, 6, 6, 5, 32, 50),
+    ("G128-ball", 9001, 12003, "ball", 128, 7, 8, 8, 33, 100),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_3d_matches_step_by_step_oracle(torch, fn, case):
+    name, nt, ns, shape, G, m, p, c, seed, nco = case
+    print(f"3D case {name}: oracle", flush=True)
+    y, x, w, q = synth.random_cloud3(nt, ns, seed, shape=shape)
+    y[:nco] = x[:nco]
+    prm = f3.Params3(G=G, m=m, p=p, eps_I=c / (G // 2), eps_B=1 / 8)
+    F = f3.FastSum3(y, x, w, prm)
+    rng = np.random.default_rng(seed + 1)
+    V = rng.standard_normal((nt, 3))
+    ref = dict(phi=None, H=None)
+    ref["phi"], ref["H"] = F.forward(q)
+    ref["HT"] = F.adjoint_H(V)
+    del F
+    print("  GPU", flush=True)
+    S = fn.Solver3(grid=G, m=m, p=p, eps_I=c / (G // 2), eps_B=1 / 8)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
+    info = S.info()
+    assert info["near_cells"] == int(np.ceil(c * 2)) and abs(info["scale"] - f3.torus_map(y, x, 1 / 8)[1]) < 1e-15
+    S.set_charges(dev(torch, q))
+    phi, H = S.eval()
+    u = S.adjoint_H(dev(torch, V))
+    torch.cuda.synchronize()
+    got = dict(phi=phi.cpu().numpy(), H=H.cpu().numpy(), HT=u.cpu().numpy())
+    errs = {k: (rel_l2(got[k], ref[k]), max_rel(got[k], ref[k])) for k in got}
+    print("  rel L2, per-element max:", {k: f"{a:.2e}, {b:.2e}" for k, (a, b) in errs.items()}, flush=True)
+    assert max(parity_err(got[k], ref[k]) for k in got) < 1e-10, errs
+    # phi only and H only give the same values
+    p2, _ = S.eval(H=False)
+    _, H2 = S.eval(phi=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(p2.cpu().numpy(), got["phi"]) and np.array_equal(H2.cpu().numpy(), got["H"])
+
+
+def test_3d_accuracy_against_the_direct_sum(torch, fn):
+    y, x, w, q = synth.random_cloud3(3000, 4000, 41)
+    S = fn.Solver3(grid=128, m=8, p=8, eps_I=8 / 64, eps_B=1 / 8)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
+    S.set_charges(dev(torch, q))
+    phi, H = S.eval()
+    V = np.random.default_rng(42).standard_normal((len(y), 3))
+    u = S.adjoint_H(dev(torch, V))
+    torch.cuda.synchronize()
+    phi1, H1 = direct.forward3(y, x, w, q)
+    u1 = direct.adjoint3(y, x, w, V=V)
+    e = (rel_l2(phi.cpu().numpy(), phi1), rel_l2(H.cpu().numpy(), H1), rel_l2(u.cpu().numpy(), u1))
+    print("3D vs direct sum (rel L2 phi, H, H^T):", [f"{v:.2e}" for v in e], flush=True)
+    assert max(e) < 1e-6, e
+
+
+def test_3d_empty_sets_and_errors(torch, fn):
+    y, x, w, q = synth.random_cloud3(50, 60, 43)
+    # no sources: zero outputs; no targets: nothing to do, the adjoint is zero
+    S = fn.Solver3(grid=32, m=4, p=4, eps_I=3 / 16)
+    S.set_geometry(dev(torch, y), dev(torch, x[:0]), dev(torch, w[:0]))
+    S.set_charges(dev(torch, q[:0]))
+    phi, H = S.eval()
+    torch.cuda.synchronize()
+    assert not phi.cpu().numpy().any() and not H.cpu().numpy().any()
+    S.set_geometry(dev(torch, y[:0]), dev(torch, x), dev(torch, w))
+    S.set_charges(dev(torch, q))
+    phi, H = S.eval()
+    u = S.adjoint_H(dev(torch, np.zeros((0, 3))))
+    torch.cuda.synchronize()
+    assert phi.numel() == 0 and not u.cpu().numpy().any()
+    # one target, one source
+    S.set_geometry(dev(torch, y[:1]), dev(torch, x[:1]), dev(torch, w[:1]))
+    S.set_charges(dev(torch, q[:1]))
+    phi, H = S.eval()
+    torch.cuda.synchronize()
+    p1, H1 = direct.forward3(y[:1], x[:1], w[:1], q[:1])
+    assert abs(phi.item() - p1[0]) < 1e-3 * abs(p1[0])
+    # every point at one place
+    with pytest.raises(fn.FemNfftError, match="coincide"):
+        S.set_geometry(dev(torch, np.zeros((3, 3))), dev(torch, np.zeros((2, 3))), dev(torch, np.ones(2)))
+    # non-finite input
+    bad = x.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(fn.FemNfftError, match="non-finite"):
+        S.set_geometry(dev(torch, y), dev(torch, bad), dev(torch, w))
+    # parameters the 3D path does not take
+    for kw, msg in ((dict(grid=48), "power of two"), (dict(grid=16, m=4), "grid/4"), (dict(grid=512), "power of two")):
+        with pytest.raises(fn.FemNfftError, match=msg):
+            fn.Solver3(**dict(dict(m=3, p=4, eps_I=0.1), **kw))
