@@ -69,6 +69,14 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one elementwise kernel over 256 MiB (read and write) before the timed region, "
                          "as the byte-counter calibration for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--workload", choices=("square2d", "ball3d"), default="square2d",
+                    help="square2d: the 2D rounded square (default); ball3d: the 3D path (fn3_*, G = 1/(4 pi r)) "
+                         "on a ball lattice, options --K, --grid3, --m3, --p3, --c3")
+    ap.add_argument("--K", type=int, default=64, help="ball3d: lattice cells across the ball")
+    ap.add_argument("--grid3", type=int, default=256)
+    ap.add_argument("--m3", type=int, default=6)
+    ap.add_argument("--p3", type=int, default=6)
+    ap.add_argument("--c3", type=float, default=5.0, help="ball3d: eps_I = c3 / (grid3/2)")
     return ap.parse_args()
 
 
@@ -93,6 +101,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "ball3d":
+        return main_3d(args, torch, synth, fn, dev)
     t0 = time.time()
     d = synth.rounded_square_cloud(N=args.n, seed=synth.SEED_BASE + 4)
     y, x, w, q = d["y"], d["x"], d["w"], d["q"]
@@ -386,6 +396,146 @@ def accuracy_and_cpu(d, r, args, nt, ns):
                      f"{t_f + t_a:.1f} s of CPU work"}
     log(f"vs O1 (sampled): {err}; CPU oracle {cpu['value']:.3e} points/s on {cpu['cores']} threads")
     return err, cpu
+
+
+# ---------------------------------------------------------------------------- 3D path
+
+def near3_flops_per_pair(stage, p):
+    """3D near field, FP64 flops per interacting pair (FMA = 2; sqrt, division = 1 each):
+    forward: offsets 6, r^2 5, x 1, T_I and T_I'/r by Horner 2(p-1) + 2(p-2), sqrt 1, 1/r 1,
+    phi share 2, field factor 4, phi sum 2, H sums 7; adjoint: offsets 6, r^2 5, x 1,
+    T_I'/r 2(p-2), sqrt 1, field factor 5, V.d 5, sum 2."""
+    if stage == "near":
+        return 6 + 5 + 1 + 2 * (p - 1) + 2 * (p - 2) + 1 + 1 + 2 + 4 + 2 + 7
+    return 6 + 5 + 1 + 2 * (p - 2) + 1 + 5 + 5 + 2
+
+
+def roofline3(stage, ms_per_launch, G, m, p, info, nt, ns, pairs):
+    """Roofline of one 3D stage: algorithmic HBM bytes (points' cell, fractions and values once,
+    every grid value read and written once per pass), or near-field flops, per launch."""
+    sec = ms_per_launch * 1e-3
+    G3 = G ** 3 * 16
+    win = int(np.prod(info["win_ext"])) * 16
+    if stage in ("near", "a_near"):
+        fl = near3_flops_per_pair(stage, p)
+        ach = pairs[stage] * fl / sec / 1e12
+        return {"kernel": stage, "bound": "alu", "achieved": ach, "peak": FP64_VEC_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_VEC_TFLOPS, "traffic": None, "ms_per_launch": ms_per_launch,
+                "pairs_per_launch": pairs[stage], "flops_per_pair": fl}
+    byts = {
+        "charges": ns * 28, "a_values": nt * 52,
+        "spread": ns * 36 + G3, "a_spread": nt * 52 + 3 * G3,
+        "fft": 6 * G3, "a_fft": 18 * G3,
+        "multiply": 3 * G3, "a_multiply": 4 * G3,
+        "ifft": 12 * G3, "a_ifft": 6 * G3,
+        "gather": nt * 60 + 2 * win, "a_gather": ns * 36 + win,
+    }[stage]
+    ach = byts / sec / 1e9
+    return {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "ms_per_launch": ms_per_launch,
+            "algorithmic_bytes_per_launch": byts}
+
+
+def main_3d(args, torch, synth, fn, dev):
+    """The 3D fast summation on a ball lattice: one step = set_charges + eval (phi, H) + H
+    adjoint, FP64, inputs resident before the timed region."""
+    from scipy.spatial import cKDTree
+    G, m, p = args.grid3, args.m3, args.p3
+    eps_I, eps_B = args.c3 / (G // 2), 1.0 / 8.0
+    d = synth.ball_lattice3(K=args.K)
+    y, x, w, q, V = d["y"], d["x"], d["w"], d["q"], d["V"]
+    nt, ns = len(y), len(x)
+    log(f"3D workload: {nt} targets, {ns} sources; G = {G}, m = {m}, p = {p}, eps_I = {eps_I:.5f}")
+    tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ty, tx, tw, tq, tV = tt(y), tt(x), tt(w), tt(q), tt(V)
+    S = fn.Solver3(grid=G, m=m, p=p, eps_I=eps_I, eps_B=eps_B)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    S.set_geometry(ty, tx, tw)
+    torch.cuda.synchronize()
+    t_geom = time.perf_counter() - g0
+    info = S.info()
+    phi = torch.empty(nt, dtype=torch.float64, device=dev)
+    H = torch.empty(nt, 3, dtype=torch.float64, device=dev)
+    u = torch.empty(ns, dtype=torch.float64, device=dev)
+
+    def step():
+        S.set_charges(tq)
+        S.eval(out_phi=phi, out_H=H)
+        S.adjoint_H(tV, out=u)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - a) / args.steps
+    # stage times: HIP events recorded on the context's stream around every stage
+    S.set_profiling(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = S.profile()
+    S.set_profiling(False)
+    stages = {k: v[0] / args.steps for k, v in prof.items() if v[1]}
+    per_launch = {k: prof[k][0] / prof[k][1] for k in stages}
+    # in-zone pairs (|t_y - t_x| < eps_I in torus units, i.e. eps_I / s physically)
+    r_phys = eps_I / info["scale"]
+    tree = cKDTree(x)
+    npairs = int(tree.query_ball_point(y, r_phys, return_length=True).sum())
+    pairs = {"near": npairs, "a_near": npairs}  # the adjoint visits the same pairs from the sources
+    ms = sec * 1e3
+    value = (nt + ns) / sec
+    log(f"3D: {ms:.3f} ms/step, {value:.4e} points/s, set_geometry {t_geom * 1e3:.1f} ms, "
+        f"{pairs['near']} near pairs")
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]):
+        log(f"  {k:12s} {v:9.3f} ms/step")
+    dom = max(stages, key=stages.get)
+    roof = roofline3(dom, per_launch[dom], G, m, p, info, nt, ns, pairs)
+    roof_stages = {k: {kk: vv for kk, vv in roofline3(k, per_launch[k], G, m, p, info, nt, ns, pairs).items()
+                       if kk in ("bound", "achieved", "unit", "frac", "ms_per_launch")} for k in stages}
+    out = {
+        "metric": "source+target points/s for 3D forward+adjoint fast summation (G = 1/(4 pi r), FP64)",
+        "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"ball radius 1, lattice K = {args.K}: jittered nodes as targets, "
+                               f"4 random points per lattice cell as sources, smooth random charges",
+                   "n_tgt": nt, "n_src": ns, "grid": G, "bandwidth": G // 2, "m": m, "p": p, "eps_I": eps_I,
+                   "eps_B": eps_B, "precision": "fp64", "parallelism": "single_gpu"},
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "stages_ms_from": "HIP events per stage on the context's stream (one stream, stages in order)",
+        "set_geometry_ms": t_geom * 1e3,
+        "roofline": roof,
+        "roofline_stages": roof_stages,
+    }
+    if not args.no_cpu:
+        from oracle import direct
+        rng = np.random.default_rng(321)
+        it = np.sort(rng.choice(nt, min(args.samples, nt), replace=False))
+        js = np.sort(rng.choice(ns, min(args.samples, ns), replace=False))
+        a = time.perf_counter()
+        phi1, H1 = direct.forward3(y[it], x, w, q)
+        t_f = time.perf_counter() - a
+        a = time.perf_counter()
+        u1 = direct.adjoint3(y, x[js], w[js], V=V)
+        t_a = time.perf_counter() - a
+        rel = lambda g, r: float(np.linalg.norm(g - r) / np.linalg.norm(r))
+        out["rel_l2_vs_fp64_oracle"] = {"phi": rel(phi.cpu().numpy()[it], phi1), "H": rel(H.cpu().numpy()[it], H1),
+                                        "HT": rel(u.cpu().numpy()[js], u1),
+                                        "samples": f"{len(it)} targets and {len(js)} sources, uniform"}
+        t_full = t_f * nt / len(it) + t_a * ns / len(js)
+        out["cpu_baseline"] = {"value": (nt + ns) / t_full, "unit": "points/s", "cores": direct.threads(),
+                               "kind": "oracle",
+                               "sample": f"O1 direct FP64 3D sum for {len(it)} targets x {ns} sources (phi, H) and "
+                                         f"{len(js)} sources x {nt} targets (H adjoint), extrapolated linearly; "
+                                         f"{t_f + t_a:.1f} s of CPU work"}
+        log(f"vs O1 (sampled): {out['rel_l2_vs_fp64_oracle']}")
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -434,7 +434,7 @@ const char *fn_graph_last_error(void);
  * and the transpose of the H map, u_j = w_j sum_i V_i . (r_i - r_j) / (4 pi |r_i - r_j|^3),
  * by the NFFT method on a G^3 grid (the paper's p^3 N grid in 3D; bandwidth n = G/2), for
  * tetrahedral FEM quadrature points or any point sets.  FP64 throughout (precision must be
- * FN_FP64), grid G a power of two in [16, 256], eps_S = 0.  3-vectors are interleaved
+ * FN_FP64), grid G a power of two in [16, 256], m <= G/4 - 1, eps_S = 0.  3-vectors are interleaved
  * [n][3]; every array is a device pointer; the conventions (ordering, workspace, call order,
  * errors, pairs at distance zero) are those of the 2D context.  The kernel's regularization
  * near the torus boundary needs a wider zone than in 2D: eps_B = 1/8 is the tested setting.
@@ -453,6 +453,17 @@ int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u);     /* V [n_tg
  * data window extent [3] in cells, near radius in cells */
 int fn3_get_info(const fn3_ctx *ctx, int64_t *n_tgt, int64_t *n_src, double *scale, int32_t *win_ext,
                  int32_t *near_cells);
+/* Stage timing of the 3D context (the 2D context's fn_set_profiling / fn_get_profile
+ * conventions; at most 4096 stages between two fn3_get_profile calls), filling the
+ * first FN3_NUM_STAGES entries of an fn_profile with these stages: */
+enum {
+    FN3_ST_CHARGES = 0, FN3_ST_SPREAD, FN3_ST_FFT, FN3_ST_MULTIPLY, FN3_ST_IFFT, FN3_ST_GATHER, FN3_ST_NEAR,
+    FN3_ST_A_VALUES, FN3_ST_A_SPREAD, FN3_ST_A_FFT, FN3_ST_A_MULTIPLY, FN3_ST_A_IFFT, FN3_ST_A_GATHER,
+    FN3_ST_A_NEAR,
+    FN3_NUM_STAGES
+};
+int fn3_set_profiling(fn3_ctx *ctx, int enable);
+int fn3_get_profile(fn3_ctx *ctx, fn_profile *out);
 const char *fn3_last_error(const fn3_ctx *ctx);
 
 #ifdef __cplusplus

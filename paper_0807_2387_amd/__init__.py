@@ -306,6 +306,8 @@ class Solver3:
         torch = _torch()
         L = _lib.lib()
         nt, ns = int(tgt_xyz.shape[0]), int(src_xyz.shape[0])
+        if src_w.dim() != 1 or src_w.shape[0] != ns:
+            raise ValueError(f"src_w must have shape [{ns}]")
         need = ctypes.c_size_t()
         self._check(L.fn3_workspace_size(self._ctx, nt, ns, ctypes.byref(need)))
         if self._ws is None or self._ws.numel() < need.value:
@@ -320,23 +322,45 @@ class Solver3:
         return self
 
     def set_charges(self, q):
+        if q.dim() != 1 or q.shape[0] != self.n_src:
+            raise ValueError(f"q must have shape [{self.n_src}]")
         self._q = q
         self._check(_lib.lib().fn3_set_charges(self._ctx, _dev_ptr(q, "q") if self.n_src else None))
         return self
 
-    def eval(self, phi=True, H=True):
+    def eval(self, phi=True, H=True, out_phi=None, out_H=None):
+        """phi [n_tgt] and H [n_tgt, 3] (either may be skipped); out_* are optional preallocated outputs."""
         torch = _torch()
-        p = torch.empty(self.n_tgt, dtype=torch.float64, device=self.device) if phi else None
-        h = torch.empty(self.n_tgt, 3, dtype=torch.float64, device=self.device) if H else None
+        for t, nm in ((out_phi, "out_phi"), (out_H, "out_H")):
+            if t is not None and (t.dim() < 1 or t.shape[0] != self.n_tgt):
+                raise ValueError(f"{nm} must have {self.n_tgt} rows")
+        p = (out_phi if out_phi is not None else torch.empty(self.n_tgt, dtype=torch.float64, device=self.device)) \
+            if phi else None
+        h = (out_H if out_H is not None else torch.empty(self.n_tgt, 3, dtype=torch.float64, device=self.device)) \
+            if H else None
         self._check(_lib.lib().fn3_eval(self._ctx, _dev_ptr(p, "phi") if p is not None else None,
                                         _dev_ptr(h, "H", (3,)) if h is not None else None))
         return p, h
 
-    def adjoint_H(self, V):
+    def adjoint_H(self, V, out=None):
+        """u [n_src] = the transpose of the H map applied to V [n_tgt, 3]."""
         torch = _torch()
-        u = torch.empty(self.n_src, dtype=torch.float64, device=self.device)
+        if V.dim() != 2 or V.shape[0] != self.n_tgt:
+            raise ValueError(f"V must have shape [{self.n_tgt}, 3]")
+        if out is not None and (out.dim() != 1 or out.shape[0] != self.n_src):
+            raise ValueError(f"out must have shape [{self.n_src}]")
+        u = out if out is not None else torch.empty(self.n_src, dtype=torch.float64, device=self.device)
         self._check(_lib.lib().fn3_eval_H_adjoint(self._ctx, _dev_ptr(V, "V", (3,)), _dev_ptr(u, "u")))
         return u
+
+    def set_profiling(self, enable=True):
+        self._check(_lib.lib().fn3_set_profiling(self._ctx, int(bool(enable))))
+
+    def profile(self):
+        """Per-stage event time (ms) and launch counts since profiling was enabled."""
+        pr = _lib.Profile()
+        self._check(_lib.lib().fn3_get_profile(self._ctx, ctypes.byref(pr)))
+        return {name: (pr.ms[i], pr.count[i]) for i, name in enumerate(_lib.STAGES3)}
 
     def info(self):
         nt, ns, ne, nc = ctypes.c_int64(), ctypes.c_int64(), (ctypes.c_int32 * 3)(), ctypes.c_int32()

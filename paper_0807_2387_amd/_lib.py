@@ -32,12 +32,14 @@ SYMBOLS = (
     "fn_batch_eval_phi_adjoint", "fn_batch_member", "fn_batch_last_error",
     "fn_graph_begin", "fn_graph_end", "fn_graph_launch", "fn_graph_destroy", "fn_graph_last_error",
     "fn3_create", "fn3_destroy", "fn3_workspace_size", "fn3_set_workspace", "fn3_set_geometry", "fn3_set_charges",
-    "fn3_eval", "fn3_eval_H_adjoint", "fn3_get_info", "fn3_last_error",
+    "fn3_eval", "fn3_eval_H_adjoint", "fn3_get_info", "fn3_set_profiling", "fn3_get_profile", "fn3_last_error",
 )
 
 STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather", "near",
           "a_values", "a_spread", "a_fold", "a_rows_fwd", "a_cols", "a_rows_inv", "a_gather", "a_near",
           "near_surf", "a_near_surf")
+STAGES3 = ("charges", "spread", "fft", "multiply", "ifft", "gather", "near",
+           "a_values", "a_spread", "a_fft", "a_multiply", "a_ifft", "a_gather", "a_near")
 
 
 class Params(ctypes.Structure):
@@ -153,6 +155,8 @@ def lib():
         "fn3_eval_H_adjoint": ([P, P, P], ctypes.c_int),
         "fn3_get_info": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
+        "fn3_set_profiling": ([P, ctypes.c_int], ctypes.c_int),
+        "fn3_get_profile": ([P, ctypes.POINTER(Profile)], ctypes.c_int),
         "fn3_last_error": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():

@@ -87,6 +87,12 @@ struct fn3_ctx {
     size_t ws_bytes = 0;
     bool plan_ready = false, geom_ready = false, charges_ready = false;
     std::string err;
+    // stage timing (fn3_set_profiling): event pairs recorded on the stream around each stage
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_stage;
+    size_t prof_next = 0;
+    fn_profile prof{};
 };
 
 namespace fn3 {
@@ -688,6 +694,26 @@ using namespace fn3;
 
 namespace {
 
+constexpr size_t PROF3_MAX = 4096;
+
+int prof3_begin(fn3_ctx *c, int st)
+{
+    if (!c->prof_on || stream_capturing(c->stream)) return -1;
+    if (c->prof_next >= PROF3_MAX) {
+        c->prof.dropped += 1;
+        return -1;
+    }
+    const size_t i = c->prof_next++;
+    c->prof_stage[i] = st;
+    hipEventRecord(c->prof_ev[2 * i], c->stream);
+    return (int)i;
+}
+
+void prof3_end(fn3_ctx *c, int i)
+{
+    if (i >= 0) hipEventRecord(c->prof_ev[2 * i + 1], c->stream);
+}
+
 struct Layout3 {
     size_t total = 0, off_W = 0, off_twG = 0, off_twn = 0, off_key[2] = {0, 0}, off_perm[2] = {0, 0},
            off_cs[2] = {0, 0}, off_fr[2] = {0, 0}, off_taps[2] = {0, 0}, off_w = 0, off_val = 0, off_aval = 0,
@@ -834,23 +860,28 @@ int check_dev(fn3_ctx *c)
     return FN_OK;
 }
 
-// spread nf value fields of set `set` into grids, zero outside the window, forward FFT each
-int spread_fft(fn3_ctx *c, int set, const double *val, int64_t N, int nf)
+// spread nf value fields of set `set` into grids, zero outside the window (stage st_spread),
+// forward FFT each (stage st_fft)
+int spread_fft(fn3_ctx *c, int set, const double *val, int64_t N, int nf, int st_spread, int st_fft)
 {
     const Plan3 &P = c->plan;
     Buf3 &B = c->buf;
     const Map3 mp = map_of(c);
     const int64_t cells = (int64_t)mp.ext[0] * mp.ext[1] * mp.ext[2];
     const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    int pi = prof3_begin(c, st_spread);
     k3_zero_outside<<<nbk(G3), NT, 0, c->stream>>>(B.grid[0], B.grid[1], B.grid[2], nf, P.G, mp);
     F3_LAUNCH(c);
     k3_spread<<<nbk(cells), NT, 0, c->stream>>>(B.taps[set], B.key[set], val, N, B.cstart[set], mp, nf, B.grid[0],
                                                  B.grid[1], B.grid[2], P.G);
     F3_LAUNCH(c);
+    prof3_end(c, pi);
+    pi = prof3_begin(c, st_fft);
     for (int f = 0; f < nf; ++f) {
         int rc = fft3(c, B.grid[f], P.G, P.log2G, 0, B.twG);
         if (rc) return rc;
     }
+    prof3_end(c, pi);
     return FN_OK;
 }
 
@@ -891,6 +922,8 @@ int fn3_create(const fn_params *params, void *stream, fn3_ctx **out)
 
 int fn3_destroy(fn3_ctx *ctx)
 {
+    if (ctx)
+        for (auto &e : ctx->prof_ev) hipEventDestroy(e);
     delete ctx;
     return FN_OK;
 }
@@ -1027,8 +1060,10 @@ int fn3_set_charges(fn3_ctx *ctx, const double *q)
     int rc = check_dev(c);
     if (rc) return rc;
     if (c->geom.ns > 0) {
+        const int pi = prof3_begin(c, FN3_ST_CHARGES);
         k3_values<<<nbk(c->geom.ns), NT, 0, c->stream>>>(q, c->buf.w, c->buf.perm[1], c->geom.ns, 1, c->buf.val);
         F3_LAUNCH(c);
+        prof3_end(c, pi);
     }
     c->charges_ready = true;
     return FN_OK;
@@ -1053,23 +1088,31 @@ int fn3_eval(fn3_ctx *ctx, double *phi, double *H)
         F3_LAUNCH(c);
         return FN_OK;
     }
-    rc = spread_fft(c, 1, B.val, g.ns, 1);
+    rc = spread_fft(c, 1, B.val, g.ns, 1, FN3_ST_SPREAD, FN3_ST_FFT);
     if (rc) return rc;
     const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    int pi = prof3_begin(c, FN3_ST_MULTIPLY);
     k3_mul_fwd<<<nbk(G3), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], P.G, P.n / 2, B.W);
     F3_LAUNCH(c);
+    prof3_end(c, pi);
+    pi = prof3_begin(c, FN3_ST_IFFT);
     for (int f = 1; f <= 2; ++f) {
         rc = fft3(c, B.grid[f], P.G, P.log2G, 1, B.twG);
         if (rc) return rc;
     }
+    prof3_end(c, pi);
     const Map3 mp = map_of(c);
     // far: phi (re T1), H_z (im T1), H_x (re T2), H_y (im T2) -> far[0..3] as phi, Hx, Hy, Hz
     double *far = B.far;  // [4][nt]: phi, H_x, H_y, H_z
+    pi = prof3_begin(c, FN3_ST_GATHER);
     k3_gather<<<nbk(g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
     F3_LAUNCH(c);
+    prof3_end(c, pi);
+    pi = prof3_begin(c, FN3_ST_NEAR);
     k3_near<false><<<nbk(g.nt), NT, 0, st>>>(B.fr[0], B.key[0], B.perm[0], g.nt, B.fr[1], B.key[1], B.cstart[1], g.ns,
                                               B.val, mp, near_of(c), far, nullptr, phi, H);
     F3_LAUNCH(c);
+    prof3_end(c, pi);
     return FN_OK;
 }
 
@@ -1091,22 +1134,32 @@ int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u)
         F3_LAUNCH(c);
         return FN_OK;
     }
+    int pi = prof3_begin(c, FN3_ST_A_VALUES);
     k3_values<<<nbk(g.nt), NT, 0, st>>>(V, nullptr, B.perm[0], g.nt, 3, B.aval);
     F3_LAUNCH(c);
-    rc = spread_fft(c, 0, B.aval, g.nt, 3);
+    prof3_end(c, pi);
+    rc = spread_fft(c, 0, B.aval, g.nt, 3, FN3_ST_A_SPREAD, FN3_ST_A_FFT);
     if (rc) return rc;
     const int64_t G3 = (int64_t)P.G * P.G * P.G;
     // T = sum_d 2 pi i l_d W F_d into grid 0 (in place: each element reads its own F values)
+    pi = prof3_begin(c, FN3_ST_A_MULTIPLY);
     k3_mul_adj<<<nbk(G3), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], B.grid[0], P.G, P.n / 2, B.W);
     F3_LAUNCH(c);
+    prof3_end(c, pi);
+    pi = prof3_begin(c, FN3_ST_A_IFFT);
     rc = fft3(c, B.grid[0], P.G, P.log2G, 1, B.twG);
     if (rc) return rc;
+    prof3_end(c, pi);
     const Map3 mp = map_of(c);
+    pi = prof3_begin(c, FN3_ST_A_GATHER);
     k3_gather<<<nbk(g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
     F3_LAUNCH(c);
+    prof3_end(c, pi);
+    pi = prof3_begin(c, FN3_ST_A_NEAR);
     k3_near<true><<<nbk(g.ns), NT, 0, st>>>(B.fr[1], B.key[1], B.perm[1], g.ns, B.fr[0], B.key[0], B.cstart[0], g.nt,
                                              B.aval, mp, near_of(c), B.far, B.w, u, nullptr);
     F3_LAUNCH(c);
+    prof3_end(c, pi);
     return FN_OK;
 }
 
@@ -1119,6 +1172,46 @@ int fn3_get_info(const fn3_ctx *ctx, int64_t *n_tgt, int64_t *n_src, double *sca
     if (win_ext)
         for (int d = 0; d < 3; ++d) win_ext[d] = ctx->geom.ext[d];
     if (near_cells) *near_cells = ctx->geom.rnear;
+    return FN_OK;
+}
+
+int fn3_set_profiling(fn3_ctx *ctx, int enable)
+{
+    if (!ctx) return FN_E_INVAL;
+    if (enable && ctx->prof_ev.empty()) {
+        ctx->prof_ev.assign(2 * PROF3_MAX, nullptr);
+        ctx->prof_stage.assign(PROF3_MAX, 0);
+        for (auto &e : ctx->prof_ev) {
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) {
+                for (auto &f : ctx->prof_ev)
+                    if (f) hipEventDestroy(f);
+                ctx->prof_ev.clear();
+                F3_ERR(ctx, FN_E_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(r));
+            }
+        }
+    }
+    ctx->prof_on = enable != 0;
+    if (enable) {
+        std::memset(&ctx->prof, 0, sizeof(ctx->prof));
+        ctx->prof_next = 0;
+    }
+    return FN_OK;
+}
+
+int fn3_get_profile(fn3_ctx *ctx, fn_profile *out)
+{
+    if (!ctx || !out) return FN_E_INVAL;
+    if (stream_capturing(ctx->stream)) F3_ERR(ctx, FN_E_STATE, "fn3_get_profile waits for the device: not during graph capture");
+    for (size_t i = 0; i < ctx->prof_next; ++i) {
+        F3_HIP(ctx, hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
+        float ms = 0.f;
+        F3_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+        ctx->prof.ms[ctx->prof_stage[i]] += ms;
+        ctx->prof.count[ctx->prof_stage[i]] += 1;
+    }
+    ctx->prof_next = 0;
+    *out = ctx->prof;
     return FN_OK;
 }
 

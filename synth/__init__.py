@@ -1,10 +1,15 @@
 """Seeded synthetic workloads for the FEM-NFFT fast summation.
 
-This module only builds inputs: point sets, 2D triangle meshes, boundary edge
-lists and magnetization fields, all from seeded random generators.  It holds
-none of the method's arithmetic (no Green function, no quadrature rule, no
-charge formula, no window, no FFT), so that the CPU oracle and the GPU path can
-both be fed from it without sharing any code with each other.
+This module only builds inputs: point sets (2D and 3D), 2D triangle meshes,
+boundary edge lists and magnetization fields, all from seeded random
+generators.  It holds none of the fast summation's arithmetic (no Green
+function, no regularization, no window, no FFT, no near-field correction), so
+that the CPU oracle and the GPU path can both be fed from it without sharing any
+code with each other.  Two point-cloud workloads carry their own charges: the
+rounded-square cloud writes -div M analytically at its cell points and M.n at
+2-point Gauss points of its boundary, the 3D ball lattice a smooth random field.
+Both paths take those charges as plain inputs; the FEM charge operators under
+test (oracle/fem.py and the library's mesh calls) are separate code.
 
 Mesh conventions shared by every consumer:
   nodes  float64 [N, 2]
@@ -290,6 +295,44 @@ def random_cloud3(n_tgt, n_src, seed, shape="ball", R=1.0, neutral=True):
     if neutral and n_src > 1:
         q -= np.dot(w, q) / w.sum()
     return y, x, w, q
+
+
+def _smooth3(rng, pts, n_modes, kmax, L):
+    """A smooth random scalar field on 3D points: a sum of cosine modes of wavelength >= L/kmax."""
+    ks = rng.integers(-kmax, kmax + 1, size=(n_modes, 3)).astype(np.float64)
+    ph = rng.uniform(0.0, 2 * np.pi, n_modes)
+    amp = rng.standard_normal(n_modes) / np.sqrt(n_modes)
+    out = np.zeros(len(pts))
+    for k, f, a in zip(ks, ph, amp):
+        out += a * np.cos(2 * np.pi * (pts @ k) / L + f)
+    return out
+
+
+def ball_lattice3(K=64, R=1.0, spc=4, jitter=0.1, n_modes=16, kmax=3, seed=SEED_BASE + 5):
+    """3D workload: a ball of radius R on a lattice of spacing h = 2R/K.  Targets: the lattice
+    nodes inside the ball, interior ones jittered by up to jitter*h per axis (mesh-node-like);
+    sources: spc uniform random points in every lattice cell whose centre lies inside the ball
+    (quadrature-point-like), weight h^3/spc; charges a smooth random field with zero weighted
+    sum; V a smooth random 3-vector field times h^3 (an adjoint input like l_i M_i)."""
+    rng = np.random.default_rng(seed)
+    h = 2.0 * R / K
+    g = np.arange(K + 1) * h - R
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    nodes = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    r = np.linalg.norm(nodes, axis=1)
+    nodes = nodes[r <= R]
+    inner = np.linalg.norm(nodes, axis=1) <= R - 1.75 * h
+    nodes[inner] += rng.uniform(-jitter * h, jitter * h, size=(int(inner.sum()), 3))
+    c = np.arange(K) * h - R + 0.5 * h
+    CX, CY, CZ = np.meshgrid(c, c, c, indexing="ij")
+    cent = np.stack([CX.ravel(), CY.ravel(), CZ.ravel()], axis=1)
+    cent = cent[np.linalg.norm(cent, axis=1) <= R]
+    x = (np.repeat(cent, spc, axis=0) + rng.uniform(-0.5 * h, 0.5 * h, size=(len(cent) * spc, 3)))
+    w = np.full(len(x), h ** 3 / spc)
+    q = _smooth3(rng, x, n_modes, kmax, 2 * R)
+    q -= np.dot(w, q) / w.sum()
+    V = np.stack([_smooth3(rng, nodes, n_modes, kmax, 2 * R) for _ in range(3)], axis=1) * h ** 3
+    return dict(y=nodes, x=x, w=w, q=q, V=V, h=h)
 
 
 def rounded_square_cloud(N=1 << 24, side=4.0, rc=0.5, n_modes=32, kmax=4,
