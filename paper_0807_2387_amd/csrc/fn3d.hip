@@ -22,7 +22,7 @@
 //               K_R(0) = a_0 for it, the exact sum leaves it out)
 //   adjoint     V spread at the targets (3 fields), sum_d 2 pi i l_d W_l F_d, inverse
 //               transform, gather at the sources, transposed near field; u = w s^2 (..)
-#include "fn_internal.h"
+#include "fn_fft_dev.h"
 
 #include <algorithm>
 #include <cmath>
@@ -34,6 +34,7 @@
 
 namespace fn3 {
 
+using fn::FFT_EPT;
 using fn::MAXM;
 using fn::MAXP;
 
@@ -71,6 +72,7 @@ struct Buf3 {
     double2 *grid[3] = {nullptr, nullptr, nullptr};  // G^3 complex
     double *far = nullptr;            // [4][max(nt, ns)]
     double *red = nullptr;            // reduction scratch
+    double *tiles = nullptr;          // spread tile footprints [tile][F^3]
     uint32_t *skey = nullptr, *sval = nullptr, *hist = nullptr;
 };
 
@@ -383,177 +385,259 @@ __global__ void k3_make_W(const double2 *__restrict__ bl, int n, const double *_
     W[idx] = om * b / (ph * ph);
 }
 
-// ------------------------------------------------------------------ FFT lines
+// ------------------------------------------------------------------ FFT passes
 
-// In-place forward C2C transforms of lines of length N (a power of two, <= 256) of a
-// cube N^3 (x fastest) along `axis`; one line per block of N/2 threads, radix-2 Stockham
-// passes through LDS (ping-pong), twiddles from an FP64 table.  Inverse: conj in and out.
-__global__ void k3_lines(double2 *__restrict__ a, int N, int log2N, int axis, int inv,
-                         const double2 *__restrict__ tw)
+// A set of indices along one axis of the G grid: an interval [lo, lo + len) (the data
+// window), the band {0..nh} U {G-nh..G-1} (the frequencies the multiplier keeps), or all.
+struct Set3 {
+    int kind;  // 0 interval, 1 band, 2 all
+    int lo, len;
+};
+
+__device__ __forceinline__ int set_count(const Set3 &s, int N, int nh)
 {
-    __shared__ double2 buf[2][MAXG3];
-    const int q = blockIdx.x;  // line index over the other two axes
+    return s.kind == 0 ? s.len : (s.kind == 1 ? 2 * nh + 1 : N);
+}
+__device__ __forceinline__ int set_at(const Set3 &s, int i, int N, int nh)
+{
+    return s.kind == 0 ? s.lo + i : (s.kind == 1 ? (i <= nh ? i : N - 2 * nh - 1 + i) : i);
+}
+__device__ __forceinline__ bool set_has(const Set3 &s, int e, int N, int nh)
+{
+    return s.kind == 0 ? (unsigned)(e - s.lo) < (unsigned)s.len : (s.kind == 1 ? (e <= nh || e >= N - nh) : true);
+}
+
+// One pass of line transforms along `axis` of an N^3 complex cube (x fastest), in place:
+// the lines are those whose other two coordinates lie in su (the faster of the two axes)
+// x sv; elements outside `ld` are read as zero, and only elements in `stv` are written
+// back.  Forward C2C; inverse as conj(FFT(conj(.))).  A block holds PER lines (one set of
+// NT = N/FFT_EPT threads each) with consecutive su coordinates, so for axes 1 and 2 the
+// PER lines' elements at one position are adjacent in memory and the copies coalesce.
+__global__ void __launch_bounds__(512) k3_pass(double2 *__restrict__ a, int N, int log2N, int axis, int inv, int nh,
+                                               Set3 su, Set3 sv, Set3 ld, Set3 stv, const double2 *__restrict__ tw)
+{
+    using namespace fn::fftd;
+    extern __shared__ double2 sh3[];
+    const int NT = N / FFT_EPT, PER = blockDim.x / NT;
+    const int cu = set_count(su, N, nh);
+    const int iv = blockIdx.y;
+    const int iu0 = blockIdx.x * PER;
+    const int v = set_at(sv, iv, N, nh);
     const int64_t N1 = N, N2 = (int64_t)N * N;
-    int64_t base, stride;
-    if (axis == 0) { base = (int64_t)q * N1; stride = 1; }
-    else if (axis == 1) { base = (int64_t)(q / N) * N2 + (q % N); stride = N1; }
-    else { base = (int64_t)q; stride = N2; }
-    const int t = threadIdx.x;  // N/2 threads
-    for (int e = t; e < N; e += N / 2) {
-        double2 v = a[base + e * stride];
-        if (inv) v.y = -v.y;
-        buf[0][e] = v;
+    // element e of line u: base(u) + e * stride
+    int64_t stride;
+    if (axis == 0) stride = 1;
+    else if (axis == 1) stride = N1;
+    else stride = N2;
+    auto base = [&](int u) -> int64_t {
+        if (axis == 0) return (int64_t)v * N2 + (int64_t)u * N1;  // line (y = u, z = v)
+        if (axis == 1) return (int64_t)v * N2 + u;                // line (x = u, z = v)
+        return (int64_t)v * N1 + u;                               // line (x = u, y = v)
+    };
+    const int nl = min(PER, cu - iu0);
+    const int LS = lp(N) + 1;  // line stride in LDS: the +1 spreads the PER lines of a transposed copy over the banks
+    // copy in: axis 0 with the element index fastest, axes 1 and 2 with the line index fastest
+    for (int t = threadIdx.x; t < PER * N; t += blockDim.x) {
+        int li, e;
+        if (axis == 0) { li = t / N; e = t % N; }
+        else { li = t % PER; e = t / PER; }
+        double2 val = make_double2(0.0, 0.0);
+        if (li < nl && set_has(ld, e, N, nh)) {
+            val = a[base(set_at(su, iu0 + li, N, nh)) + e * stride];
+            if (inv) val.y = -val.y;
+        }
+        sh3[(int64_t)li * LS + lp(e)] = val;
     }
     __syncthreads();
-    int src = 0;
-    // Stockham radix-2: at stage with half-length L (1, 2, 4, ...), butterfly j = k + L * r
-    for (int L = 1; L < N; L <<= 1) {
-        const int k = t % L, r = t / L;  // r in [0, N/(2L))
-        const double2 x0 = buf[src][k + L * r];
-        const double2 x1 = buf[src][k + L * r + N / 2];
-        const double2 w = tw[k * (N / (2 * L))];
-        const double2 y1 = make_double2(x1.x * w.x - x1.y * w.y, x1.x * w.y + x1.y * w.x);
-        buf[src ^ 1][k + 2 * L * r] = make_double2(x0.x + y1.x, x0.y + y1.y);
-        buf[src ^ 1][k + 2 * L * r + L] = make_double2(x0.x - y1.x, x0.y - y1.y);
-        src ^= 1;
-        __syncthreads();
-    }
-    for (int e = t; e < N; e += N / 2) {
-        double2 v = buf[src][e];
-        if (inv) v.y = -v.y;
-        a[base + e * stride] = v;
+    const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
+    fft_line(sh3 + (int64_t)li * LS, N, log2N, lt, NT, tw);
+    for (int t = threadIdx.x; t < PER * N; t += blockDim.x) {
+        int l2, e;
+        if (axis == 0) { l2 = t / N; e = t % N; }
+        else { l2 = t % PER; e = t / PER; }
+        if (l2 < nl && set_has(stv, e, N, nh)) {
+            double2 val = sh3[(int64_t)l2 * LS + lp(e)];
+            if (inv) val.y = -val.y;
+            a[base(set_at(su, iu0 + l2, N, nh)) + e * stride] = val;
+        }
     }
 }
 
 // ------------------------------------------------------------------ spread / multiply / gather
 
-// g_k for every grid point k of the data window, gathered over the base cells
-// b in [k - 2m + 1, k] of each axis (a point's taps reach k = b .. b + 2m - 1), written into the
-// G^3 complex grid at k + wlo (real part; imaginary part zero); grid points outside the window
-// are zeroed by k3_zero_outside.  nf fields of values val [f][N].  Each grid point sums its
-// points in the fixed order of the cells and of the sorted points (no atomics).
-__global__ void k3_spread(const double *__restrict__ taps, const uint32_t *__restrict__ key,
-                          const double *__restrict__ val, int64_t N, const uint32_t *__restrict__ cstart, Map3 mp,
-                          int nf, double2 *g0, double2 *g1, double2 *g2, int G)
+// Spread, one field.  One wave per tile of ST^3 base cells (a point's base cell is its first
+// tap cell); the tile's footprint of F^3 grid points, F = ST + 2m - 1, is accumulated in LDS:
+// the wave takes the tile's points one after the other in sorted order, its lanes the (a, b)
+// taps of a point (distinct LDS addresses), each looping over the 2m taps c.  Every LDS value
+// is thus summed in a fixed order, and the footprint is written to the tile's own slot of
+// tileout [tile][F^3]; k3_fold adds the overlapping footprints.  No atomics.
+constexpr int ST = 4;
+
+__global__ void __launch_bounds__(64) k3_spread_tile(const double *__restrict__ taps, const uint32_t *__restrict__ key,
+                                                     const uint32_t *__restrict__ cstart, const double *__restrict__ val,
+                                                     Map3 mp, int ntx, int nty, double *__restrict__ tileout)
+{
+    extern __shared__ double acc[];
+    const int M2 = 2 * mp.m, F = ST + M2 - 1, F2 = F * F, F3 = F2 * F;
+    const int t = blockIdx.x, tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    const int ex = mp.ext[0], ey = mp.ext[1];
+    const int nbx = ex - M2 + 1, nby = ey - M2 + 1, nbz = mp.ext[2] - M2 + 1;
+    const int x0 = tx * ST, y0 = ty * ST, z0 = tz * ST;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < F3; i += 64) acc[i] = 0.0;
+    // this lane's (a, b) taps: e = lane + 64 r < (2m)^2 <= 256
+    int ne = 0, ea[4], eb[4];
+    for (int e = lane; e < M2 * M2; e += 64) {
+        ea[ne] = e % M2;
+        eb[ne] = e / M2;
+        ++ne;
+    }
+    __syncthreads();
+    const int x1 = min(x0 + ST, nbx);
+    for (int dz = 0; dz < ST && z0 + dz < nbz; ++dz)
+        for (int dy = 0; dy < ST && y0 + dy < nby; ++dy) {
+            const int64_t row = ((int64_t)(z0 + dz) * ey + (y0 + dy)) * ex;
+            const uint32_t j0 = cstart[row + x0], j1 = cstart[row + x1];
+            for (uint32_t j = j0; j < j1; ++j) {
+                const int lx = (int)(key[j] - (uint32_t)row) - x0;
+                const double *tp = taps + (int64_t)j * 3 * M2;
+                const double v = val[j];
+                for (int r = 0; r < ne; ++r) {
+                    const int aa = ea[r], bb = eb[r];
+                    const double wab = tp[aa] * tp[M2 + bb] * v;
+                    double *ap = acc + (dz * F + dy + bb) * F + lx + aa;
+                    for (int c = 0; c < M2; ++c) ap[c * F2] += wab * tp[2 * M2 + c];
+                }
+            }
+        }
+    __syncthreads();
+    double *o = tileout + (int64_t)t * F3;
+    for (int i = lane; i < F3; i += 64) o[i] = acc[i];
+}
+
+// Grid value at every data-window point: the sum of the footprints of the tiles that reach
+// it, in tile order, written (value, 0) into the G^3 grid at the window offset.
+__global__ void k3_fold(const double *__restrict__ tileout, Map3 mp, int ntx, int nty, int ntz, int G,
+                        double2 *__restrict__ g)
 {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int ex = mp.ext[0], ey = mp.ext[1], ez = mp.ext[2];
     if (idx >= (int64_t)ex * ey * ez) return;
-    const int k0 = (int)(idx % ex), k1 = (int)((idx / ex) % ey), k2 = (int)(idx / ((int64_t)ex * ey));
-    const int M2 = 2 * mp.m;
-    double acc[3] = {0.0, 0.0, 0.0};
-    const int b0lo = max(k0 - M2 + 1, 0), b1lo = max(k1 - M2 + 1, 0), b2lo = max(k2 - M2 + 1, 0);
-    const int b0hi = min(k0, ex - M2), b1hi = min(k1, ey - M2), b2hi = min(k2, ez - M2);
-    if (b0lo <= b0hi)
-        for (int b2 = b2lo; b2 <= b2hi; ++b2)
-            for (int b1 = b1lo; b1 <= b1hi; ++b1) {
-                const int64_t row = ((int64_t)b2 * ey + b1) * ex;
-                const uint32_t j0 = cstart[row + b0lo], j1 = cstart[row + b0hi + 1];
-                for (uint32_t j = j0; j < j1; ++j) {
-                    const int b0 = (int)(key[j] % (uint32_t)ex);
-                    const double *tp = taps + (int64_t)j * 3 * M2;
-                    const double w = tp[k0 - b0] * tp[M2 + (k1 - b1)] * tp[2 * M2 + (k2 - b2)];
-                    for (int f = 0; f < nf; ++f) acc[f] += val[f * N + j] * w;
-                }
-            }
-    const int64_t o = ((int64_t)(k2 + mp.wlo[2]) * G + (k1 + mp.wlo[1])) * G + (k0 + mp.wlo[0]);
-    double2 *gs[3] = {g0, g1, g2};
-    for (int f = 0; f < nf; ++f) gs[f][o] = make_double2(acc[f], 0.0);
+    const int kx = (int)(idx % ex), ky = (int)((idx / ex) % ey), kz = (int)(idx / ((int64_t)ex * ey));
+    const int F = ST + 2 * mp.m - 1, F2 = F * F, F3 = F2 * F;
+    // tiles t with t ST <= k <= t ST + F - 1: t from ceil((k - F + 1) / ST) (at least 0) to k / ST
+    auto lo = [&](int k) { return k - F + 1 <= 0 ? 0 : (k - F + ST) / ST; };
+    const int txl = lo(kx), tyl = lo(ky), tzl = lo(kz);
+    const int txh = min(ntx - 1, kx / ST), tyh = min(nty - 1, ky / ST), tzh = min(ntz - 1, kz / ST);
+    double s = 0.0;
+    for (int tz = tzl; tz <= tzh; ++tz)
+        for (int ty = tyl; ty <= tyh; ++ty) {
+            const int64_t tb = ((int64_t)tz * nty + ty) * ntx;
+            const int oz = kz - tz * ST, oy = ky - ty * ST;
+            for (int tx = txl; tx <= txh; ++tx) s += tileout[(tb + tx) * F3 + (oz * F + oy) * F + (kx - tx * ST)];
+        }
+    g[((int64_t)(kz + mp.wlo[2]) * G + (ky + mp.wlo[1])) * G + (kx + mp.wlo[0])] = make_double2(s, 0.0);
 }
 
-// zero the grid outside the data window
-__global__ void k3_zero_outside(double2 *g0, double2 *g1, double2 *g2, int nf, int G, Map3 mp)
+__device__ __forceinline__ int w_idx(int nh, int a0, int a1, int a2)
 {
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)G * G * G) return;
-    const int x = (int)(idx % G), y = (int)((idx / G) % G), z = (int)(idx / ((int64_t)G * G));
-    const bool in = x >= mp.wlo[0] && x < mp.wlo[0] + mp.ext[0] && y >= mp.wlo[1] && y < mp.wlo[1] + mp.ext[1] &&
-                    z >= mp.wlo[2] && z < mp.wlo[2] + mp.ext[2];
-    if (in) return;
-    double2 *gs[3] = {g0, g1, g2};
-    for (int f = 0; f < nf; ++f) gs[f][idx] = make_double2(0.0, 0.0);
+    return (a0 * (nh + 1) + a1) * (nh + 1) + a2;
 }
 
-__device__ __forceinline__ double w_at(const double *__restrict__ W, int nh, int l0, int l1, int l2)
-{
-    const int a0 = abs(l0), a1 = abs(l1), a2 = abs(l2);
-    if (a0 > nh || a1 > nh || a2 > nh) return 0.0;
-    return W[((int64_t)a0 * (nh + 1) + a1) * (nh + 1) + a2];
-}
-
-// forward multiply: F -> T1 = W F + i (-2 pi i l_z W F) (phi + i H_z), T2 = (-2 pi i l_x W F) + i (-2 pi i l_y W F)
+// forward multiply over the band^3 frequencies only (the inverse passes read nothing else):
+// T1 = W F + i (-2 pi i l_z W F) (phi + i H_z), T2 = (-2 pi i l_x W F) + i (-2 pi i l_y W F)
 __global__ void k3_mul_fwd(const double2 *__restrict__ F, double2 *__restrict__ T1, double2 *__restrict__ T2, int G,
                            int nh, const double *__restrict__ W)
 {
+    const int cb = 2 * nh + 1;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)G * G * G) return;
-    const int lx = sfreq((int)(idx % G), G), ly = sfreq((int)((idx / G) % G), G), lz = sfreq((int)(idx / ((int64_t)G * G)), G);
-    const double wv = w_at(W, nh, lz, ly, lx);
-    const double2 f = make_double2(wv * F[idx].x, wv * F[idx].y);
+    if (idx >= (int64_t)cb * cb * cb) return;
+    const int ix = (int)(idx % cb), iy = (int)((idx / cb) % cb), iz = (int)(idx / ((int64_t)cb * cb));
+    const int lx = ix <= nh ? ix : ix - cb, ly = iy <= nh ? iy : iy - cb, lz = iz <= nh ? iz : iz - cb;
+    const int64_t o = ((int64_t)(lz < 0 ? lz + G : lz) * G + (ly < 0 ? ly + G : ly)) * G + (lx < 0 ? lx + G : lx);
+    const double wv = W[w_idx(nh, abs(lz), abs(ly), abs(lx))];
+    const double2 f = make_double2(wv * F[o].x, wv * F[o].y);
     const double tp = 2.0 * PI;
     // (-2 pi i l) f = (2 pi l f.y, -2 pi l f.x)
     const double2 hx = make_double2(tp * lx * f.y, -tp * lx * f.x);
     const double2 hy = make_double2(tp * ly * f.y, -tp * ly * f.x);
     const double2 hz = make_double2(tp * lz * f.y, -tp * lz * f.x);
-    T1[idx] = make_double2(f.x - hz.y, f.y + hz.x);   // f + i hz
-    T2[idx] = make_double2(hx.x - hy.y, hx.y + hy.x); // hx + i hy
+    T1[o] = make_double2(f.x - hz.y, f.y + hz.x);   // f + i hz
+    T2[o] = make_double2(hx.x - hy.y, hx.y + hy.x); // hx + i hy
 }
 
-// adjoint multiply: T = sum_d (2 pi i l_d) W F_d
+// adjoint multiply over the band^3 frequencies: T = sum_d (2 pi i l_d) W F_d (T may be F0)
 __global__ void k3_mul_adj(const double2 *F0, const double2 *F1, const double2 *F2, double2 *T, int G, int nh,
                            const double *__restrict__ W)
 {
+    const int cb = 2 * nh + 1;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)G * G * G) return;
-    const int lx = sfreq((int)(idx % G), G), ly = sfreq((int)((idx / G) % G), G), lz = sfreq((int)(idx / ((int64_t)G * G)), G);
-    const double wv = w_at(W, nh, lz, ly, lx) * 2.0 * PI;
+    if (idx >= (int64_t)cb * cb * cb) return;
+    const int ix = (int)(idx % cb), iy = (int)((idx / cb) % cb), iz = (int)(idx / ((int64_t)cb * cb));
+    const int lx = ix <= nh ? ix : ix - cb, ly = iy <= nh ? iy : iy - cb, lz = iz <= nh ? iz : iz - cb;
+    const int64_t o = ((int64_t)(lz < 0 ? lz + G : lz) * G + (ly < 0 ? ly + G : ly)) * G + (lx < 0 ? lx + G : lx);
+    const double wv = W[w_idx(nh, abs(lz), abs(ly), abs(lx))] * 2.0 * PI;
     // (i l) f = (-l f.y, l f.x)
-    const double2 a = F0[idx], b = F1[idx], c = F2[idx];
+    const double2 a = F0[o], b = F1[o], c = F2[o];
     const double sx = -(lx * a.y + ly * b.y + lz * c.y), sy = lx * a.x + ly * b.x + lz * c.x;
-    T[idx] = make_double2(wv * sx, wv * sy);
+    T[o] = make_double2(wv * sx, wv * sy);
 }
 
-// far values at points of a set: sums over the (2m)^3 taps of real grid fields, the real and
-// imaginary parts of up to two complex grids.  nout = 1: out[k] = re A; nout = 4 (forward):
-// A = phi + i H_z, B = H_x + i H_y -> out[f][k] for f = phi, H_x, H_y, H_z.
-__global__ void k3_gather(const double *__restrict__ taps, const uint32_t *__restrict__ key, int64_t N, Map3 mp,
-                          const double2 *__restrict__ A, const double2 *__restrict__ B, int nout, int G,
-                          double *__restrict__ out)
+// Far values at the points of a set, 16 lanes per point: lane a takes the x tap a (a < 2m),
+// every lane loops over the (b, c) taps, reading 2m consecutive grid values per row across
+// the point's lanes; the 16 partial sums are then added by a butterfly within the group (a
+// fixed order).  nout = 1: out[k] = re A; nout = 4 (forward): A = phi + i H_z,
+// B = H_x + i H_y -> out[f][k] for f = phi, H_x, H_y, H_z.
+__global__ void __launch_bounds__(256) k3_gather(const double *__restrict__ taps, const uint32_t *__restrict__ key,
+                                                 int64_t N, Map3 mp, const double2 *__restrict__ A,
+                                                 const double2 *__restrict__ B, int nout, int G, double *__restrict__ out)
 {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= N) return;
+    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
+    const int a = threadIdx.x & 15;
+    if (k >= N) return;  // the whole group of 16 leaves together
     const int M2 = 2 * mp.m;
+    const bool act = a < M2;
     const uint32_t kk = key[k];
     const int b0 = (int)(kk % (uint32_t)mp.ext[0]), b1 = (int)((kk / (uint32_t)mp.ext[0]) % (uint32_t)mp.ext[1]);
     const int b2 = (int)(kk / ((uint32_t)mp.ext[0] * (uint32_t)mp.ext[1]));
     const double *tp = taps + k * 3 * M2;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = 0; c < M2; ++c) {
-        const int z = b2 + c + mp.wlo[2];
-        for (int b = 0; b < M2; ++b) {
-            const int y = b1 + b + mp.wlo[1];
-            const double wyz = tp[M2 + b] * tp[2 * M2 + c];
-            const int64_t row = ((int64_t)z * G + y) * G + (b0 + mp.wlo[0]);
-            for (int a = 0; a < M2; ++a) {
-                const double w = tp[a] * wyz;
-                const double2 u = A[row + a];
-                acc[0] += w * u.x;
-                if (nout > 2) acc[1] += w * u.y;
-                if (nout > 2) {
-                    const double2 v = B[row + a];
-                    acc[2] += w * v.x;
-                    acc[3] += w * v.y;
+    const double txa = act ? tp[a] : 0.0;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    if (act) {
+        const int64_t xo = (int64_t)b0 + mp.wlo[0] + a;
+        for (int c = 0; c < M2; ++c) {
+            const double wz = txa * tp[2 * M2 + c];
+            const int64_t zrow = ((int64_t)(b2 + c + mp.wlo[2]) * G + (b1 + mp.wlo[1])) * G + xo;
+            for (int b = 0; b < M2; ++b) {
+                const double w = wz * tp[M2 + b];
+                const int64_t o = zrow + (int64_t)b * G;
+                const double2 u = A[o];
+                acc0 += w * u.x;
+                if (nout == 4) {
+                    acc1 += w * u.y;
+                    const double2 v = B[o];
+                    acc2 += w * v.x;
+                    acc3 += w * v.y;
                 }
             }
         }
     }
+    for (int s = 8; s > 0; s >>= 1) {
+        acc0 += __shfl_xor(acc0, s, 16);
+        if (nout == 4) {
+            acc1 += __shfl_xor(acc1, s, 16);
+            acc2 += __shfl_xor(acc2, s, 16);
+            acc3 += __shfl_xor(acc3, s, 16);
+        }
+    }
+    if (a != 0) return;
     if (nout == 4) {
-        out[k] = acc[0];
-        out[N + k] = acc[2];
-        out[2 * N + k] = acc[3];
-        out[3 * N + k] = acc[1];
+        out[k] = acc0;
+        out[N + k] = acc2;
+        out[2 * N + k] = acc3;
+        out[3 * N + k] = acc1;
     } else {
-        out[k] = acc[0];
+        out[k] = acc0;
     }
 }
 
@@ -718,7 +802,7 @@ struct Layout3 {
     size_t total = 0, off_W = 0, off_twG = 0, off_twn = 0, off_key[2] = {0, 0}, off_perm[2] = {0, 0},
            off_cs[2] = {0, 0}, off_fr[2] = {0, 0}, off_taps[2] = {0, 0}, off_w = 0, off_val = 0, off_aval = 0,
            off_grid[3] = {0, 0, 0},
-           off_far = 0, off_red = 0, off_skey = 0, off_sval = 0, off_hist = 0;
+           off_far = 0, off_red = 0, off_skey = 0, off_sval = 0, off_hist = 0, off_tiles = 0;
     int64_t emax = 0;
 };
 
@@ -732,7 +816,8 @@ Layout3 layout3(const Plan3 &P, int64_t nt, int64_t ns)
         return r;
     };
     const int nh1 = P.n / 2 + 1;
-    L.emax = P.G / 2 + 2 * P.m + 4;
+    // data window extent per axis: at most floor((1/2 - eps_B) G) + 2m + 3 cells
+    L.emax = (int64_t)std::floor((0.5 - P.eps_B) * P.G) + 2 * P.m + 4;
     const int64_t ncell = L.emax * L.emax * L.emax;
     const int64_t N[2] = {std::max<int64_t>(nt, 1), std::max<int64_t>(ns, 1)};
     const int64_t nmax = std::max(N[0], N[1]);
@@ -757,6 +842,10 @@ Layout3 layout3(const Plan3 &P, int64_t nt, int64_t ns)
     L.off_skey = take(nmax * 4);
     L.off_sval = take(nmax * 4);
     L.off_hist = take((size_t)256 * ((nmax + 4095) / 4096) * 4);
+    {  // spread tile footprints, one field
+        const int64_t nt1 = (L.emax - 2 * P.m + 1 + ST - 1) / ST, F = ST + 2 * P.m - 1;
+        L.off_tiles = take((size_t)(nt1 * nt1 * nt1) * (size_t)(F * F * F) * 8);
+    }
     L.total = o;
     return L;
 }
@@ -784,16 +873,57 @@ void bind3(fn3_ctx *c, const Layout3 &L)
     B.skey = reinterpret_cast<uint32_t *>(b + L.off_skey);
     B.sval = reinterpret_cast<uint32_t *>(b + L.off_sval);
     B.hist = reinterpret_cast<uint32_t *>(b + L.off_hist);
+    B.tiles = reinterpret_cast<double *>(b + L.off_tiles);
 }
 
-// 3D transform of a cube of N^3 complex values (N <= 256)
-int fft3(fn3_ctx *c, double2 *a, int N, int log2N, int inv, const double2 *tw)
+constexpr int PASS_THREADS = 512;
+constexpr size_t PASS_LDS = (size_t)80 << 10;
+
+Set3 s_int(int lo, int len) { return Set3{0, lo, len}; }
+Set3 s_band() { return Set3{1, 0, 0}; }
+Set3 s_all() { return Set3{2, 0, 0}; }
+
+int pass3(fn3_ctx *c, double2 *a, int N, int log2N, int axis, int inv, int nh, Set3 su, Set3 sv, Set3 ld, Set3 stv,
+          const double2 *tw)
 {
-    for (int axis = 0; axis < 3; ++axis) {
-        k3_lines<<<N * N, N / 2, 0, c->stream>>>(a, N, log2N, axis, inv, tw);
-        F3_LAUNCH(c);
-    }
+    auto count = [&](const Set3 &s) { return s.kind == 0 ? s.len : (s.kind == 1 ? 2 * nh + 1 : N); };
+    const int NT = N / FFT_EPT, PER = PASS_THREADS / NT;
+    const size_t lds = (size_t)PER * (fn::fftd::lp(N) + 1) * sizeof(double2);
+    if (lds > PASS_LDS) F3_ERR(c, FN_E_DEVICE, "internal: line pass LDS");
+    const int cu = count(su), cv = count(sv);
+    if (cu <= 0 || cv <= 0) return FN_OK;
+    dim3 grid((cu + PER - 1) / PER, cv);
+    k3_pass<<<grid, PASS_THREADS, lds, c->stream>>>(a, N, log2N, axis, inv, nh, su, sv, ld, stv, tw);
+    F3_LAUNCH(c);
     return FN_OK;
+}
+
+// Forward transform of a grid that is zero outside the data window, keeping the band^3
+// frequencies only: x lines of the window's (y, z) rows, then y lines of the band's x
+// columns in the window's z planes, then z lines of band x band.
+int fft3_fwd(fn3_ctx *c, double2 *a)
+{
+    const Plan3 &P = c->plan;
+    const Geom3 &g = c->geom;
+    const int nh = P.n / 2;
+    const Set3 wx = s_int(g.wlo[0], g.ext[0]), wy = s_int(g.wlo[1], g.ext[1]), wz = s_int(g.wlo[2], g.ext[2]);
+    int rc = pass3(c, a, P.G, P.log2G, 0, 0, nh, wy, wz, wx, s_band(), c->buf.twG);
+    if (!rc) rc = pass3(c, a, P.G, P.log2G, 1, 0, nh, s_band(), wz, wy, s_band(), c->buf.twG);
+    if (!rc) rc = pass3(c, a, P.G, P.log2G, 2, 0, nh, s_band(), s_band(), wz, s_band(), c->buf.twG);
+    return rc;
+}
+
+// Inverse transform of a spectrum that is zero outside band^3, computing the data window only.
+int fft3_inv(fn3_ctx *c, double2 *a)
+{
+    const Plan3 &P = c->plan;
+    const Geom3 &g = c->geom;
+    const int nh = P.n / 2;
+    const Set3 wx = s_int(g.wlo[0], g.ext[0]), wy = s_int(g.wlo[1], g.ext[1]), wz = s_int(g.wlo[2], g.ext[2]);
+    int rc = pass3(c, a, P.G, P.log2G, 2, 1, nh, s_band(), s_band(), s_band(), wz, c->buf.twG);
+    if (!rc) rc = pass3(c, a, P.G, P.log2G, 1, 1, nh, s_band(), wz, s_band(), wy, c->buf.twG);
+    if (!rc) rc = pass3(c, a, P.G, P.log2G, 0, 1, nh, wy, wz, s_band(), wx, c->buf.twG);
+    return rc;
 }
 
 int build_plan3(fn3_ctx *c)
@@ -801,6 +931,7 @@ int build_plan3(fn3_ctx *c)
     const Plan3 &P = c->plan;
     Buf3 &B = c->buf;
     hipStream_t st = c->stream;
+    F3_HIP(c, hipFuncSetAttribute((const void *)k3_pass, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PASS_LDS));
     F3_HIP(c, hipMemcpyAsync(B.twG, P.twG.data(), P.twG.size() * 8, hipMemcpyHostToDevice, st));
     F3_HIP(c, hipMemcpyAsync(B.twn, P.twn.data(), P.twn.size() * 8, hipMemcpyHostToDevice, st));
     double *coef = B.red, *cB = B.red + 32, *psi = B.red + 128;
@@ -811,7 +942,9 @@ int build_plan3(fn3_ctx *c)
     double2 *scr = B.grid[0];
     k3_kr_samples<<<nbk(n3), NT, 0, st>>>(scr, P.n, coef, P.p, P.eps_I, P.eps_B, cB, (int)P.cB.size());
     F3_LAUNCH(c);
-    int rc = fft3(c, scr, P.n, P.log2n, 0, B.twn);
+    int rc = FN_OK;
+    for (int axis = 0; axis < 3 && !rc; ++axis)
+        rc = pass3(c, scr, P.n, P.log2n, axis, 0, 0, s_all(), s_all(), s_all(), s_all(), B.twn);
     if (rc) return rc;
     const int64_t nh1 = P.n / 2 + 1;
     k3_make_W<<<nbk(nh1 * nh1 * nh1), NT, 0, st>>>(scr, P.n, psi, B.W);
@@ -860,25 +993,30 @@ int check_dev(fn3_ctx *c)
     return FN_OK;
 }
 
-// spread nf value fields of set `set` into grids, zero outside the window (stage st_spread),
-// forward FFT each (stage st_fft)
+// spread nf value fields of set `set` (val [f][N]) into grids 0..nf-1 over the data window
+// (stage st_spread), then transform each (stage st_fft)
 int spread_fft(fn3_ctx *c, int set, const double *val, int64_t N, int nf, int st_spread, int st_fft)
 {
     const Plan3 &P = c->plan;
     Buf3 &B = c->buf;
     const Map3 mp = map_of(c);
+    const int M2 = 2 * P.m, F = ST + M2 - 1;
+    int nt[3];
+    for (int d = 0; d < 3; ++d) nt[d] = (mp.ext[d] - M2 + 1 + ST - 1) / ST;
+    const int ntiles = nt[0] * nt[1] * nt[2];
     const int64_t cells = (int64_t)mp.ext[0] * mp.ext[1] * mp.ext[2];
-    const int64_t G3 = (int64_t)P.G * P.G * P.G;
     int pi = prof3_begin(c, st_spread);
-    k3_zero_outside<<<nbk(G3), NT, 0, c->stream>>>(B.grid[0], B.grid[1], B.grid[2], nf, P.G, mp);
-    F3_LAUNCH(c);
-    k3_spread<<<nbk(cells), NT, 0, c->stream>>>(B.taps[set], B.key[set], val, N, B.cstart[set], mp, nf, B.grid[0],
-                                                 B.grid[1], B.grid[2], P.G);
-    F3_LAUNCH(c);
+    for (int f = 0; f < nf; ++f) {
+        k3_spread_tile<<<ntiles, 64, (size_t)F * F * F * sizeof(double), c->stream>>>(
+            B.taps[set], B.key[set], B.cstart[set], val + (int64_t)f * N, mp, nt[0], nt[1], B.tiles);
+        F3_LAUNCH(c);
+        k3_fold<<<nbk(cells), NT, 0, c->stream>>>(B.tiles, mp, nt[0], nt[1], nt[2], P.G, B.grid[f]);
+        F3_LAUNCH(c);
+    }
     prof3_end(c, pi);
     pi = prof3_begin(c, st_fft);
     for (int f = 0; f < nf; ++f) {
-        int rc = fft3(c, B.grid[f], P.G, P.log2G, 0, B.twG);
+        int rc = fft3_fwd(c, B.grid[f]);
         if (rc) return rc;
     }
     prof3_end(c, pi);
@@ -1090,14 +1228,14 @@ int fn3_eval(fn3_ctx *ctx, double *phi, double *H)
     }
     rc = spread_fft(c, 1, B.val, g.ns, 1, FN3_ST_SPREAD, FN3_ST_FFT);
     if (rc) return rc;
-    const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    const int64_t cb = P.n / 2 * 2 + 1, nband = cb * cb * cb;
     int pi = prof3_begin(c, FN3_ST_MULTIPLY);
-    k3_mul_fwd<<<nbk(G3), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], P.G, P.n / 2, B.W);
+    k3_mul_fwd<<<nbk(nband), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], P.G, P.n / 2, B.W);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_IFFT);
     for (int f = 1; f <= 2; ++f) {
-        rc = fft3(c, B.grid[f], P.G, P.log2G, 1, B.twG);
+        rc = fft3_inv(c, B.grid[f]);
         if (rc) return rc;
     }
     prof3_end(c, pi);
@@ -1105,7 +1243,7 @@ int fn3_eval(fn3_ctx *ctx, double *phi, double *H)
     // far: phi (re T1), H_z (im T1), H_x (re T2), H_y (im T2) -> far[0..3] as phi, Hx, Hy, Hz
     double *far = B.far;  // [4][nt]: phi, H_x, H_y, H_z
     pi = prof3_begin(c, FN3_ST_GATHER);
-    k3_gather<<<nbk(g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
+    k3_gather<<<nbk(16 * g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_NEAR);
@@ -1140,19 +1278,19 @@ int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u)
     prof3_end(c, pi);
     rc = spread_fft(c, 0, B.aval, g.nt, 3, FN3_ST_A_SPREAD, FN3_ST_A_FFT);
     if (rc) return rc;
-    const int64_t G3 = (int64_t)P.G * P.G * P.G;
+    const int64_t cb = P.n / 2 * 2 + 1, nband = cb * cb * cb;
     // T = sum_d 2 pi i l_d W F_d into grid 0 (in place: each element reads its own F values)
     pi = prof3_begin(c, FN3_ST_A_MULTIPLY);
-    k3_mul_adj<<<nbk(G3), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], B.grid[0], P.G, P.n / 2, B.W);
+    k3_mul_adj<<<nbk(nband), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], B.grid[0], P.G, P.n / 2, B.W);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_A_IFFT);
-    rc = fft3(c, B.grid[0], P.G, P.log2G, 1, B.twG);
+    rc = fft3_inv(c, B.grid[0]);
     if (rc) return rc;
     prof3_end(c, pi);
     const Map3 mp = map_of(c);
     pi = prof3_begin(c, FN3_ST_A_GATHER);
-    k3_gather<<<nbk(g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
+    k3_gather<<<nbk(16 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_A_NEAR);

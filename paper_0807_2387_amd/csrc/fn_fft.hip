@@ -1,12 +1,13 @@
 // 2D FFT passes of the fast summation, and the kernel's Fourier table.
 //
-// Every line transform runs in LDS as a Stockham autosort FFT: each thread
-// holds 32 complex values in registers per pass (radix-8 passes, then one
-// radix-4 or radix-2 pass), so a line of length N uses N/32 threads and a
-// 256-thread workgroup holds 8192 complex values whatever N is.  Twiddles come
-// from an FP64-generated table, never from recurrences.  Inverse transforms
-// are conj(FFT(conj(x))) and unnormalized.
-//
+// Every line transform runs in LDS as a Stockham autosort FFT (fn_fft_dev.h):
+// each thread holds FFT_EPT = 8 complex values in registers per pass (one radix-8
+// butterfly per pass, then a closing radix-4 or radix-2 pass), so a line of length N
+// uses N/8 threads; a block of at most 1024 threads holds one line at N = 8192 and
+// several shorter lines otherwise.  Twiddles come from an FP64-generated table,
+// never from recurrences.  Inverse transforms are conj(FFT(conj(x))) and
+// unnormalized.
+
 // Grid layout: the real grids hold only the data window (ext_x x ext_y cells,
 // row-major, x contiguous); everything outside it is zero and is supplied as
 // zero padding at load time.  Because sources and targets share the window
@@ -22,127 +23,13 @@
 //   rows_inv  : C2R of the half spectra (pairs of real outputs share one
 //               complex inverse FFT); H_x = C2R((-2 pi i l_x) T_phi) needs no
 //               column pass of its own because l_x is constant per column
-#include "fn_internal.h"
+#include "fn_fft_dev.h"
 
 namespace fn {
 
 namespace {
 
-template <typename C> __device__ __forceinline__ C mk(decltype(C::x) a, decltype(C::x) b)
-{
-    C r;
-    r.x = a;
-    r.y = b;
-    return r;
-}
-template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
-template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
-template <typename C> __device__ __forceinline__ C cmul(C a, C b)
-{
-    return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-template <typename C> __device__ __forceinline__ C cmi(C a) { return mk<C>(a.y, -a.x); }  // a * (-i)
-template <typename C> __device__ __forceinline__ C conjc(C a) { return mk<C>(a.x, -a.y); }
-
-template <typename C> __device__ __forceinline__ void dft2(C *v)
-{
-    C a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-}
-
-template <typename C> __device__ __forceinline__ void dft4(C &x0, C &x1, C &x2, C &x3)
-{
-    C s0 = cadd(x0, x2), s1 = csub(x0, x2), s2 = cadd(x1, x3), s3 = cmi(csub(x1, x3));
-    x0 = cadd(s0, s2);
-    x2 = csub(s0, s2);
-    x1 = cadd(s1, s3);
-    x3 = csub(s1, s3);
-}
-
-template <typename C> __device__ __forceinline__ void dft4v(C *v) { dft4(v[0], v[1], v[2], v[3]); }
-
-template <typename C> __device__ __forceinline__ void dft8(C *v)
-{
-    using R = decltype(C::x);
-    const R h = (R)0.70710678118654752440084436210485;
-    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-    dft4(e0, e1, e2, e3);
-    dft4(o0, o1, o2, o3);
-    // W^1 = (1 - i)/sqrt2, W^2 = -i, W^3 = (-1 - i)/sqrt2
-    C t1 = mk<C>(h * (o1.x + o1.y), h * (o1.y - o1.x));
-    C t2 = cmi(o2);
-    C t3 = mk<C>(h * (o3.y - o3.x), -h * (o3.x + o3.y));
-    v[0] = cadd(e0, o0);
-    v[4] = csub(e0, o0);
-    v[1] = cadd(e1, t1);
-    v[5] = csub(e1, t1);
-    v[2] = cadd(e2, t2);
-    v[6] = csub(e2, t2);
-    v[3] = cadd(e3, t3);
-    v[7] = csub(e3, t3);
-}
-
-template <int RAD, typename C> __device__ __forceinline__ void dftR(C *v)
-{
-    if (RAD == 2) dft2(v);
-    else if (RAD == 4) dft4v(v);
-    else dft8(v);
-}
-
-// A line of N elements sits in LDS with one pad slot after every 8 elements:
-// element i at lp(i).  Without it the first two radix-8 passes store 8 outputs
-// per lane at a 64-byte lane stride (16- and 8-way bank conflicts).
-__host__ __device__ constexpr int lp(int i) { return i + (i >> 3); }
-
-// One Stockham pass over a line in LDS.  NT threads, each FFT_EPT/RAD butterflies.
-// The twiddle table holds N * TWM entries (a line of a transform TWM times longer).
-template <int RAD, int TWM, typename C>
-__device__ __forceinline__ void fft_pass(C *buf, int N, int L, int lt, int NT, const C *__restrict__ tw)
-{
-    constexpr int PER = FFT_EPT / RAD;
-    const int nb = N / RAD;
-    C v[FFT_EPT];
-#pragma unroll
-    for (int c = 0; c < PER; ++c) {
-        const int j = lt + c * NT;
-#pragma unroll
-        for (int r = 0; r < RAD; ++r) v[c * RAD + r] = buf[lp(j + r * nb)];
-    }
-    __syncthreads();
-    const int stride = N / (L * RAD);
-#pragma unroll
-    for (int c = 0; c < PER; ++c) {
-        const int j = lt + c * NT;
-        const int k = j & (L - 1);
-        if (L > 1) {
-#pragma unroll
-            for (int r = 1; r < RAD; ++r) v[c * RAD + r] = cmul(v[c * RAD + r], tw[r * k * stride * TWM]);
-        }
-        dftR<RAD>(&v[c * RAD]);
-        const int o = (j - k) * RAD + k;
-#pragma unroll
-        for (int q = 0; q < RAD; ++q) buf[lp(o + q * L)] = v[c * RAD + q];
-    }
-    __syncthreads();
-}
-
-// Forward FFT of one LDS line (in place), N a power of two.  All threads of the
-// block must call it.  TWM: the twiddle table belongs to a transform TWM times
-// longer (entry TWM k is e^{-2 pi i k / N}).
-template <int TWM = 1, typename C>
-__device__ __forceinline__ void fft_line(C *buf, int N, int log2N, int lt, int NT, const C *__restrict__ tw)
-{
-    int L = 1, rem = log2N;
-    while (rem >= 3) {
-        fft_pass<8, TWM>(buf, N, L, lt, NT, tw);
-        L <<= 3;
-        rem -= 3;
-    }
-    if (rem == 2) fft_pass<4, TWM>(buf, N, L, lt, NT, tw);
-    else if (rem == 1) fft_pass<2, TWM>(buf, N, L, lt, NT, tw);
-}
+using namespace fftd;
 
 // ---------------------------------------------------------------- plan kernels
 
