@@ -64,7 +64,7 @@ struct Buf3 {
     double *W = nullptr;              // [(n/2+1)^3]
     double2 *twG = nullptr, *twn = nullptr;
     uint32_t *key[2] = {nullptr, nullptr}, *perm[2] = {nullptr, nullptr}, *cstart[2] = {nullptr, nullptr};
-    double *fr[2] = {nullptr, nullptr};   // [3][N] in-cell fractions
+    double4 *pos[2] = {nullptr, nullptr}; // [N] positions in grid units (base cell + fraction)
     double *taps[2] = {nullptr, nullptr}; // [N][3][2m] window taps
     double *w = nullptr;              // sorted source weights
     double *val = nullptr;            // s_j sorted
@@ -320,21 +320,26 @@ __global__ void k3_prepare(const double *__restrict__ p, int64_t n, Map3 mp, uin
     idx[i] = (uint32_t)i;
 }
 
-// sorted fractions [3][n], window taps [n][3][2m] and sorted weights
+// sorted positions (grid units from the data window origin: base cell + in-cell fraction per
+// axis, w unused), window taps [n][3][2m] and sorted weights
 __global__ void k3_finish(const double *__restrict__ p, const double *__restrict__ w, int64_t n,
                           const uint32_t *__restrict__ perm, Map3 mp, double kb_b, double wnorm,
-                          double *__restrict__ fr, double *__restrict__ taps, double *__restrict__ wsorted)
+                          double4 *__restrict__ pos, double *__restrict__ taps, double *__restrict__ wsorted)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     const uint32_t i = perm[k];
     const int M2 = 2 * mp.m;
+    const int half = (int)(0.5 * mp.G);
+    double q[3];
     for (int d = 0; d < 3; ++d) {
         const double v = (mp.s * (p[3 * (int64_t)i + d] - mp.c[d])) * mp.G;
-        const double f = v - floor(v);
-        fr[d * n + k] = f;
+        const double fl = floor(v);
+        const double f = v - fl;
+        q[d] = (fl + (double)(half - mp.m + 1 - mp.wlo[d])) + f;
         for (int a = 0; a < M2; ++a) taps[(k * 3 + d) * M2 + a] = kb_psi(f + (double)(mp.m - 1 - a), mp.m, kb_b, wnorm);
     }
+    pos[k] = make_double4(q[0], q[1], q[2], 0.0);
     if (wsorted) wsorted[k] = w[i];
 }
 
@@ -644,99 +649,263 @@ __global__ void __launch_bounds__(256) k3_gather(const double *__restrict__ taps
 // ------------------------------------------------------------------ near field + final
 
 struct Near3 {
-    double e2g, invG, a[MAXP], da[MAXP];  // e2g = (eps_I G)^2; T_I coefficients, (k+1) a_{k+1}
+    double e2g, inv_e2g;   // (eps_I G)^2 and its inverse: x = r^2 / (eps_I G)^2 with r in grid units
+    double a[MAXP], da[MAXP];  // T_I(x) = sum a_k x^k; D(x) = sum da_k x^k, da_k = (k+1) a_{k+1}
+    double cphi;           // G/(4 pi): K(r/G) = cphi / r for r in grid units
+    double cD;             // 2/((eps_I G)^2 G)
+    double G2;             // G^2: the H sums are in grid units
     int p, R;
     double s;
+    int hb[3], nh[3];      // home block edge (cells) and home block counts per axis
 };
 
-// (K - T_I) and f with -grad(K - T_I)(d) = f d, d in torus units, r2 = |d|^2 > 0; e2 = eps_I^2.
-// T_I(r) = sum_k a_k x^k with x = (r/eps_I)^2, so T_I'(r)/r = (2/e2) sum_k da_k x^k.
-__device__ __forceinline__ void near_k(const Near3 &nr, double r2, double e2, double &kphi, double &f)
+// Near field.  One block of NB threads per home block of hb[0] x hb[1] x hb[2] base cells
+// of the output ("home") set.  The cells of the input set that can hold a point within
+// eps_I of the home block form, per (z, y) row, one run of cells, hence one contiguous run
+// of sorted points; the runs are concatenated (block prefix sum) and the block's threads
+// take the candidates of the concatenation one each (coalesced loads), each against the
+// home points of the block, KC at a time (positions in registers), with per-home-point
+// partial sums in registers.  The partial sums are added over the block in a fixed order
+// (wave butterflies, then the waves in order), so the result does not depend on timing.
+// Positions are in grid units relative to the data window: base cell + in-cell fraction.
+// Per pair (r = |d| in grid units, x = r^2/(eps_I G)^2, zone r < eps_I G):
+//   phi += s_j (cphi/r - T_I(x)),    H-sum += s_j (1/(4 pi r^3) + cD D(x)) d
+// (H = s^2 (far + G^2 H-sum)); a pair at distance 0 adds -s_j a_0 to phi instead.  The
+// adjoint (home = sources, input = targets with payload V) adds -(1/(4 pi r^3) + cD D(x)) V.d.
+// 1/r: hardware reciprocal square root estimate and two Newton steps.
+constexpr int NB = 256;
+constexpr int KC = 8;
+
+__device__ __forceinline__ double rsqrt64(double x)
 {
-    const double x = r2 / e2;
-    double t = nr.a[nr.p - 1];
-    for (int k = nr.p - 2; k >= 0; --k) t = t * x + nr.a[k];
-    double d = 0.0;
-    for (int k = nr.p - 2; k >= 0; --k) d = d * x + nr.da[k];
-    const double r = sqrt(r2);
-    kphi = INV_4PI / r - t;
-    f = INV_4PI / (r2 * r) + 2.0 * d / e2;
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
-// Forward (targets home, sources in): phi_i = s (far + near), H_i = s^2 (far + near), caller order.
-// Adjoint (sources home, targets in, payload V [3][nt]): u_j = w_j s^2 (far - near_dot) (the pair
-// offset is source minus target there).
-template <bool ADJ>
-__global__ void k3_near(const double *__restrict__ fr_out, const uint32_t *__restrict__ key_out,
-                        const uint32_t *__restrict__ perm_out, int64_t n_out, const double *__restrict__ fr_in,
-                        const uint32_t *__restrict__ key_in, const uint32_t *__restrict__ cs_in, int64_t n_in,
-                        const double *__restrict__ pay, Map3 mp, Near3 nr, const double *__restrict__ far,
-                        const double *__restrict__ w_out, double *__restrict__ o_phi, double *__restrict__ o_H)
+// exclusive prefix over the block (NB threads); returns the prefix of v, *total the sum
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *sh, uint32_t *total)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n_out) return;
-    const int ex = mp.ext[0], ey = mp.ext[1], ez = mp.ext[2];
-    const uint32_t kk = key_out[i];
-    const int c0 = (int)(kk % (uint32_t)ex), c1 = (int)((kk / (uint32_t)ex) % (uint32_t)ey);
-    const int c2 = (int)(kk / ((uint32_t)ex * (uint32_t)ey));
-    const double f0 = fr_out[i], f1 = fr_out[n_out + i], f2 = fr_out[2 * n_out + i];
-    const double e2 = nr.e2g;  // in grid units^2
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < NB; off <<= 1) {
+        const uint32_t o = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    const uint32_t incl = sh[t];
+    *total = sh[NB - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <bool ADJ, int P>
+__global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_out, const uint32_t *__restrict__ cs_out,
+                                              const uint32_t *__restrict__ perm_out, int64_t n_out,
+                                              const double4 *__restrict__ pos_in, const uint32_t *__restrict__ cs_in,
+                                              const double *__restrict__ pay, int64_t n_in, Map3 mp, Near3 nr,
+                                              const double *__restrict__ far, const double *__restrict__ w_out,
+                                              double *__restrict__ o_phi, double *__restrict__ o_H)
+{
+    extern __shared__ uint32_t nsh[];
+    constexpr int NV = ADJ ? 1 : 4;
+    const int ex = mp.ext[0], ey = mp.ext[1];
+    const int M2 = 2 * mp.m;
+    const int nbx = ex - M2 + 1, nby = ey - M2 + 1, nbz = mp.ext[2] - M2 + 1;
+    const int b = blockIdx.x;
+    const int hx0 = (b % nr.nh[0]) * nr.hb[0], hy0 = ((b / nr.nh[0]) % nr.nh[1]) * nr.hb[1];
+    const int hz0 = (b / (nr.nh[0] * nr.nh[1])) * nr.hb[2];
+    const int hx1 = min(hx0 + nr.hb[0], nbx);
     const int R = nr.R;
-    double ap = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int z = max(c2 - R, 0); z <= min(c2 + R, ez - 1); ++z) {
-        const double gz = z < c2 ? (double)(c2 - z - 1) + f2 : (z > c2 ? (double)(z - c2) - f2 : 0.0);
-        if (gz * gz >= e2) continue;
-        for (int y = max(c1 - R, 0); y <= min(c1 + R, ey - 1); ++y) {
-            const double gy = y < c1 ? (double)(c1 - y - 1) + f1 : (y > c1 ? (double)(y - c1) - f1 : 0.0);
-            const double h2 = e2 - gz * gz - gy * gy;
-            if (h2 <= 0.0) continue;
-            const double wdt = sqrt(h2) + 1e-9;
-            const int x0 = max((int)floor((double)c0 + f0 - wdt), 0);
-            const int x1 = min((int)floor((double)c0 + f0 + wdt), ex - 1);
-            if (x0 > x1) continue;
-            const int64_t row = ((int64_t)z * ey + y) * ex;
-            for (uint32_t j = cs_in[row + x0]; j < cs_in[row + x1 + 1]; ++j) {
-                const uint32_t kj = key_in[j];
-                const int j0 = (int)(kj % (uint32_t)ex);
-                // offset home minus staged, grid units
-                const double d0 = (double)(c0 - j0) + (f0 - fr_in[j]);
-                const double d1 = (double)(c1 - y) + (f1 - fr_in[n_in + j]);
-                const double d2 = (double)(c2 - z) + (f2 - fr_in[2 * n_in + j]);
-                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                if (r2 >= e2) continue;
-                if (r2 == 0.0) {  // not part of the exact sum: remove the far field's K_R(0) = a_0
-                    if (!ADJ) ap -= nr.a[0] * pay[j];
-                    continue;
+    const int zlo = max(hz0 - R, 0), zhi = min(hz0 + nr.hb[2] - 1 + R, nbz - 1);
+    const int ylo = max(hy0 - R, 0), yhi = min(hy0 + nr.hb[1] - 1 + R, nby - 1);
+    const int nyr = yhi - ylo + 1, nrows = (zhi - zlo + 1) * nyr;
+    // LDS: scan scratch [NB], home segments, row starts and prefixes [nrows + 1], home chunk, reduction
+    uint32_t *scan = nsh;
+    uint32_t *hseg = scan + NB;                   // [8] starts, [9] prefixes
+    uint32_t *hpre = hseg + 8;
+    uint32_t *rstart = hpre + 9;
+    uint32_t *rpre = rstart + nrows;
+    double *red = reinterpret_cast<double *>(nsh + ((NB + 17 + 2 * nrows + 1 + 1) & ~1));  // [NB/64][KC][NV]
+    const int t = threadIdx.x;
+
+    // home points: one run per home row (at most 8 rows: hb[1] hb[2] <= 8)
+    const int nseg = nr.hb[1] * nr.hb[2];
+    if (t < nseg) {
+        const int y = hy0 + t % nr.hb[1], z = hz0 + t / nr.hb[1];
+        uint32_t s0 = 0, cnt = 0;
+        if (y < nby && z < nbz) {
+            const int64_t rb = ((int64_t)z * ey + y) * ex;
+            s0 = cs_out[rb + hx0];
+            cnt = cs_out[rb + hx1] - s0;
+        }
+        hseg[t] = s0;
+        hpre[t + 1] = cnt;
+    }
+    __syncthreads();
+    if (t == 0) {
+        hpre[0] = 0;
+        for (int s = 1; s <= nseg; ++s) hpre[s] += hpre[s - 1];
+    }
+    __syncthreads();
+    const uint32_t nhome = hpre[nseg];
+    if (nhome == 0) return;  // uniform
+
+    // candidate runs per input row (z, y): cells whose x extent meets [hx0 - w, hx1 + w]
+    const double e2 = nr.e2g;
+    const int per = (nrows + NB - 1) / NB;
+    uint32_t mysum = 0;
+    for (int r = t * per; r < min(nrows, (t + 1) * per); ++r) {
+        const int z = zlo + r / nyr, y = ylo + r % nyr;
+        const double gz = z >= hz0 + nr.hb[2] ? (double)(z - hz0 - nr.hb[2]) : (z + 1 <= hz0 ? (double)(hz0 - z - 1) : 0.0);
+        const double gy = y >= hy0 + nr.hb[1] ? (double)(y - hy0 - nr.hb[1]) : (y + 1 <= hy0 ? (double)(hy0 - y - 1) : 0.0);
+        const double h2 = e2 - gz * gz - gy * gy;
+        uint32_t s0 = 0, cnt = 0;
+        if (h2 > 0.0) {
+            const double w = sqrt(h2);
+            const int xa = max((int)floor((double)hx0 - w), 0);
+            const int xb = min((int)floor((double)hx1 + w), nbx - 1);
+            if (xa <= xb) {
+                const int64_t rb = ((int64_t)z * ey + y) * ex;
+                s0 = cs_in[rb + xa];
+                cnt = cs_in[rb + xb + 1] - s0;
+            }
+        }
+        rstart[r] = s0;
+        rpre[r] = cnt;
+        mysum += cnt;
+    }
+    uint32_t total;
+    uint32_t run = block_scan(mysum, scan, &total);
+    for (int r = t * per; r < min(nrows, (t + 1) * per); ++r) {
+        const uint32_t cnt = rpre[r];
+        rpre[r] = run;
+        run += cnt;
+    }
+    if (t == 0) rpre[nrows] = total;
+    __syncthreads();
+
+    const double a0 = nr.a[0];
+    for (uint32_t kc0 = 0; kc0 < nhome; kc0 += KC) {
+        // this chunk's home positions (a far sentinel for empty slots never enters the zone)
+        double hx[KC], hy[KC], hz[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const uint32_t kk = kc0 + k;
+            hx[k] = hy[k] = hz[k] = 1e30;
+            if (kk < nhome) {
+                int s = 0;
+                while (s + 1 < nseg && hpre[s + 1] <= kk) ++s;
+                const double4 h = pos_out[hseg[s] + (kk - hpre[s])];
+                hx[k] = h.x;
+                hy[k] = h.y;
+                hz[k] = h.z;
+            }
+        }
+        double acc[KC][NV];
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[k][v] = 0.0;
+        for (uint32_t idx = t; idx < total; idx += NB) {
+            int lo = 0, hi = nrows - 1;  // largest row with rpre <= idx (a non-empty row)
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rpre[mid] <= idx) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t j = rstart[lo] + (idx - rpre[lo]);
+            const double4 q = pos_in[j];
+            double w0, w1 = 0.0, w2 = 0.0;
+            if (ADJ) {
+                w0 = pay[j];
+                w1 = pay[n_in + j];
+                w2 = pay[2 * n_in + j];
+            } else {
+                w0 = pay[j];
+            }
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const double dx = hx[k] - q.x, dy = hy[k] - q.y, dz = hz[k] - q.z;
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const bool inz = r2 < e2;
+                const bool pos = r2 > 0.0;
+                // x is capped at the zone edge so that pairs outside (and the sentinel) stay finite;
+                // their terms are masked below
+                const double x = fmin(r2 * nr.inv_e2g, 1.0);
+                const double ri = rsqrt64(fmax(r2, 1e-200));
+                double d = 0.0;
+                if (P >= 2) {
+                    d = nr.da[P - 2];
+#pragma unroll
+                    for (int i = P - 3; i >= 0; --i) d = fma(d, x, nr.da[i]);
                 }
-                double kphi, f;
-                // torus units: d / G, r2 / G^2
-                near_k(nr, r2 * nr.invG * nr.invG, e2 * nr.invG * nr.invG, kphi, f);
-                const double t0 = d0 * nr.invG, t1 = d1 * nr.invG, t2 = d2 * nr.invG;
+                const double g = fma(INV_4PI * ri, ri * ri, nr.cD * d);
                 if (!ADJ) {
-                    const double sj = pay[j];
-                    ap += sj * kphi;
-                    a0 += sj * f * t0;
-                    a1 += sj * f * t1;
-                    a2 += sj * f * t2;
+                    double tt = nr.a[P - 1];
+#pragma unroll
+                    for (int i = P - 2; i >= 0; --i) tt = fma(tt, x, nr.a[i]);
+                    const double ph = pos ? fma(nr.cphi, ri, -tt) : -a0;
+                    const double sp = inz ? w0 : 0.0;
+                    const double sh = (inz && pos) ? w0 * g : 0.0;
+                    acc[k][0] = fma(sp, ph, acc[k][0]);
+                    acc[k][1] = fma(sh, dx, acc[k][1]);
+                    acc[k][2] = fma(sh, dy, acc[k][2]);
+                    acc[k][3] = fma(sh, dz, acc[k][3]);
                 } else {
-                    // pair offset here is source minus target: -grad G at (target - source)
-                    ap -= f * (pay[j] * t0 + pay[n_in + j] * t1 + pay[2 * n_in + j] * t2);
+                    const double gm = (inz && pos) ? g : 0.0;
+                    acc[k][0] = fma(-gm, fma(w0, dx, fma(w1, dy, w2 * dz)), acc[k][0]);
                 }
             }
         }
-    }
-    const uint32_t o = perm_out[i];
-    if (!ADJ) {
-        if (o_phi) o_phi[o] = nr.s * (far[i] + ap);
-        if (o_H) {
-            const double s2 = nr.s * nr.s;
-            o_H[3 * (int64_t)o] = s2 * (far[n_out + i] + a0);
-            o_H[3 * (int64_t)o + 1] = s2 * (far[2 * n_out + i] + a1);
-            o_H[3 * (int64_t)o + 2] = s2 * (far[3 * n_out + i] + a2);
+        // block sums in a fixed order: butterflies within each wave, then the waves in order
+        const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double s = acc[k][v];
+                for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+                if (lane == 0) red[(wv * KC + k) * NV + v] = s;
+            }
+        __syncthreads();
+        if (t < KC) {
+            const uint32_t kk = kc0 + t;
+            if (kk < nhome) {
+                double sv[NV];
+                for (int v = 0; v < NV; ++v) {
+                    double s = 0.0;
+                    for (int w = 0; w < NB / 64; ++w) s += red[(w * KC + t) * NV + v];
+                    sv[v] = s;
+                }
+                int s = 0;
+                while (s + 1 < nseg && hpre[s + 1] <= kk) ++s;
+                const uint32_t i = hseg[s] + (kk - hpre[s]);
+                const uint32_t o = perm_out[i];
+                const double s1 = nr.s, s2 = s1 * s1, G2 = nr.G2;
+                if (!ADJ) {
+                    if (o_phi) o_phi[o] = s1 * (far[i] + sv[0]);
+                    if (o_H) {
+                        o_H[3 * (int64_t)o] = s2 * fma(G2, sv[1], far[n_out + i]);
+                        o_H[3 * (int64_t)o + 1] = s2 * fma(G2, sv[2], far[2 * n_out + i]);
+                        o_H[3 * (int64_t)o + 2] = s2 * fma(G2, sv[3], far[3 * n_out + i]);
+                    }
+                } else {
+                    o_phi[o] = w_out[i] * s2 * fma(G2, sv[0], far[i]);
+                }
+            }
         }
-    } else {
-        o_phi[o] = w_out[i] * nr.s * nr.s * (far[i] + ap);
+        __syncthreads();
     }
+}
+
+inline size_t near3_lds_bytes(int nrows)
+{
+    const size_t words = ((size_t)NB + 17 + 2 * (size_t)nrows + 1 + 1) & ~(size_t)1;
+    return words * 4 + (size_t)(NB / 64) * KC * 4 * sizeof(double);
 }
 
 // values in sorted order: out[f][k] = (w_k) in[perm_k][f] (w NULL: 1), nf components per point
@@ -829,7 +998,7 @@ Layout3 layout3(const Plan3 &P, int64_t nt, int64_t ns)
         L.off_key[s] = take(N[s] * 4);
         L.off_perm[s] = take(N[s] * 4);
         L.off_cs[s] = take((size_t)(ncell + 1) * 4);
-        L.off_fr[s] = take(N[s] * 24);
+        L.off_fr[s] = take(N[s] * 32);
         L.off_taps[s] = take(N[s] * 3 * 2 * P.m * 8);
     }
     L.off_w = take(N[1] * 8);
@@ -861,7 +1030,7 @@ void bind3(fn3_ctx *c, const Layout3 &L)
         B.key[s] = reinterpret_cast<uint32_t *>(b + L.off_key[s]);
         B.perm[s] = reinterpret_cast<uint32_t *>(b + L.off_perm[s]);
         B.cstart[s] = reinterpret_cast<uint32_t *>(b + L.off_cs[s]);
-        B.fr[s] = reinterpret_cast<double *>(b + L.off_fr[s]);
+        B.pos[s] = reinterpret_cast<double4 *>(b + L.off_fr[s]);
         B.taps[s] = reinterpret_cast<double *>(b + L.off_taps[s]);
     }
     B.w = reinterpret_cast<double *>(b + L.off_w);
@@ -968,19 +1137,83 @@ Map3 map_of(const fn3_ctx *c)
     return mp;
 }
 
-Near3 near_of(const fn3_ctx *c)
+// Near-field constants; home blocks sized for about 8 home points each (one register chunk),
+// from the density the home set would have if it filled the ball the torus map allows.
+Near3 near_of(const fn3_ctx *c, bool adj)
 {
     Near3 nr{};
     const Plan3 &P = c->plan;
+    const Geom3 &g = c->geom;
     const double eg = P.eps_I * P.G;
     nr.e2g = eg * eg;
-    nr.invG = 1.0 / P.G;
+    nr.inv_e2g = 1.0 / nr.e2g;
     for (int k = 0; k < MAXP; ++k) nr.a[k] = P.a[k];
     for (int k = 0; k + 1 < MAXP; ++k) nr.da[k] = (k + 1) * P.a[k + 1];
+    nr.cphi = P.G * INV_4PI;
+    nr.cD = 2.0 / (nr.e2g * P.G);
+    nr.G2 = (double)P.G * P.G;
     nr.p = P.p;
-    nr.R = c->geom.rnear;
-    nr.s = c->geom.s;
+    nr.R = g.rnear;
+    nr.s = g.s;
+    const double dia = (0.5 - P.eps_B) * P.G;
+    const double ppc = (double)(adj ? g.ns : g.nt) / std::max(1.0, PI / 6.0 * dia * dia * dia);
+    static const int shapes[5][3] = {{2, 2, 1}, {2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {8, 4, 2}};
+    int k = 0;
+    while (k < 4 && ppc * shapes[k][0] * shapes[k][1] * shapes[k][2] < 6.0) ++k;
+    for (int d = 0; d < 3; ++d) {
+        nr.hb[d] = shapes[k][d];
+        const int nb = g.ext[d] - 2 * P.m + 1;
+        nr.nh[d] = (nb + nr.hb[d] - 1) / nr.hb[d];
+    }
     return nr;
+}
+
+template <bool ADJ, int P>
+void near3_go(fn3_ctx *c, const Near3 &nr, int nblk, size_t lds, double *phi, double *H, double *u)
+{
+    Buf3 &B = c->buf;
+    const Geom3 &g = c->geom;
+    const Map3 mp = map_of(c);
+    if (!ADJ)
+        k3_near<false, P><<<nblk, NB, lds, c->stream>>>(B.pos[0], B.cstart[0], B.perm[0], g.nt, B.pos[1], B.cstart[1],
+                                                         B.val, g.ns, mp, nr, B.far, nullptr, phi, H);
+    else
+        k3_near<true, P><<<nblk, NB, lds, c->stream>>>(B.pos[1], B.cstart[1], B.perm[1], g.ns, B.pos[0], B.cstart[0],
+                                                        B.aval, g.nt, mp, nr, B.far, B.w, u, nullptr);
+}
+
+template <bool ADJ>
+void near3_dispatch(fn3_ctx *c, const Near3 &nr, int nblk, size_t lds, double *phi, double *H, double *u)
+{
+    switch (nr.p) {
+    case 1: near3_go<ADJ, 1>(c, nr, nblk, lds, phi, H, u); break;
+    case 2: near3_go<ADJ, 2>(c, nr, nblk, lds, phi, H, u); break;
+    case 3: near3_go<ADJ, 3>(c, nr, nblk, lds, phi, H, u); break;
+    case 4: near3_go<ADJ, 4>(c, nr, nblk, lds, phi, H, u); break;
+    case 5: near3_go<ADJ, 5>(c, nr, nblk, lds, phi, H, u); break;
+    case 6: near3_go<ADJ, 6>(c, nr, nblk, lds, phi, H, u); break;
+    case 7: near3_go<ADJ, 7>(c, nr, nblk, lds, phi, H, u); break;
+    case 8: near3_go<ADJ, 8>(c, nr, nblk, lds, phi, H, u); break;
+    case 9: near3_go<ADJ, 9>(c, nr, nblk, lds, phi, H, u); break;
+    case 10: near3_go<ADJ, 10>(c, nr, nblk, lds, phi, H, u); break;
+    case 11: near3_go<ADJ, 11>(c, nr, nblk, lds, phi, H, u); break;
+    default: near3_go<ADJ, 12>(c, nr, nblk, lds, phi, H, u); break;
+    }
+}
+
+// the near field and the final sums of one direction
+int launch_near3(fn3_ctx *c, bool adj, double *phi, double *H, double *u)
+{
+    const Near3 nr = near_of(c, adj);
+    const int64_t nblk = (int64_t)nr.nh[0] * nr.nh[1] * nr.nh[2];
+    const int nrows = (nr.hb[2] + 2 * nr.R) * (nr.hb[1] + 2 * nr.R);
+    const size_t lds = near3_lds_bytes(nrows);
+    if (nblk <= 0 || nblk > INT32_MAX || lds > 65536 || nr.hb[1] * nr.hb[2] > 8)
+        F3_ERR(c, FN_E_DEVICE, "internal: near-field launch shape");
+    if (adj) near3_dispatch<true>(c, nr, (int)nblk, lds, phi, H, u);
+    else near3_dispatch<false>(c, nr, (int)nblk, lds, phi, H, u);
+    F3_LAUNCH(c);
+    return FN_OK;
 }
 
 int check_dev(fn3_ctx *c)
@@ -1178,7 +1411,7 @@ int fn3_set_geometry(fn3_ctx *ctx, int64_t n_tgt, const double *tgt_xyz, int64_t
             k3_prepare<<<nbk(n), NT, 0, st>>>(pts[s], n, mp, B.key[s], B.perm[s]);
             F3_LAUNCH(c);
             F3_HIP(c, fn::radix_sort(B.key[s], B.perm[s], B.skey, B.sval, B.hist, n, keybits, st));
-            k3_finish<<<nbk(n), NT, 0, st>>>(pts[s], s ? src_w : nullptr, n, B.perm[s], mp, P.kb_b, wnorm, B.fr[s],
+            k3_finish<<<nbk(n), NT, 0, st>>>(pts[s], s ? src_w : nullptr, n, B.perm[s], mp, P.kb_b, wnorm, B.pos[s],
                                                B.taps[s], s ? B.w : nullptr);
             F3_LAUNCH(c);
         }
@@ -1247,9 +1480,8 @@ int fn3_eval(fn3_ctx *ctx, double *phi, double *H)
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_NEAR);
-    k3_near<false><<<nbk(g.nt), NT, 0, st>>>(B.fr[0], B.key[0], B.perm[0], g.nt, B.fr[1], B.key[1], B.cstart[1], g.ns,
-                                              B.val, mp, near_of(c), far, nullptr, phi, H);
-    F3_LAUNCH(c);
+    rc = launch_near3(c, false, phi, H, nullptr);
+    if (rc) return rc;
     prof3_end(c, pi);
     return FN_OK;
 }
@@ -1294,9 +1526,8 @@ int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u)
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_A_NEAR);
-    k3_near<true><<<nbk(g.ns), NT, 0, st>>>(B.fr[1], B.key[1], B.perm[1], g.ns, B.fr[0], B.key[0], B.cstart[0], g.nt,
-                                             B.aval, mp, near_of(c), B.far, B.w, u, nullptr);
-    F3_LAUNCH(c);
+    rc = launch_near3(c, true, nullptr, nullptr, u);
+    if (rc) return rc;
     prof3_end(c, pi);
     return FN_OK;
 }
