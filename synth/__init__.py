@@ -297,6 +297,69 @@ def random_cloud3(n_tgt, n_src, seed, shape="ball", R=1.0, neutral=True):
     return y, x, w, q
 
 
+# --------------------------------------------------------------------------
+# tetrahedral meshes (3D)
+# --------------------------------------------------------------------------
+#   nodes  float64 [N, 3]
+#   tets   int32   [T, 4]   vertex indices, any orientation
+#   bfaces int32   [F, 3]   boundary triangles (a, b, c) with (b - a) x (c - a) pointing
+#                           out of the domain
+#   M      float64 [N, 3]   nodal magnetization
+
+# the six tetrahedra of a unit cube cell around its main diagonal v000 -> v111 (corner
+# k = x + 2 y + 4 z); every cell uses the same diagonal, so neighbouring cells share faces
+_KUHN = np.array([[0, 1, 3, 7], [0, 1, 5, 7], [0, 2, 3, 7], [0, 2, 6, 7], [0, 4, 5, 7], [0, 4, 6, 7]])
+
+
+def boundary_faces(nodes, tets):
+    """Faces that belong to one tetrahedron only, oriented outward (away from the fourth vertex)."""
+    tets = np.asarray(tets, np.int64)
+    loc = np.array([[1, 2, 3, 0], [0, 2, 3, 1], [0, 1, 3, 2], [0, 1, 2, 3]])  # face (3), opposite (1)
+    faces = np.concatenate([tets[:, l[:3]] for l in loc])
+    opp = np.concatenate([tets[:, l[3]] for l in loc])
+    key = np.sort(faces, axis=1)
+    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    once = cnt[inv.ravel()] == 1
+    f, d = faces[once], opp[once]
+    a, b, c = nodes[f[:, 0]], nodes[f[:, 1]], nodes[f[:, 2]]
+    flip = (np.cross(b - a, c - a) * (nodes[d] - a)).sum(1) > 0
+    f[flip] = f[flip][:, [0, 2, 1]]
+    return f.astype(np.int32)
+
+
+def cube_tet_mesh(n=8, L=1.0, jitter=0.0, seed=SEED_BASE + 6):
+    """Cube [-L/2, L/2]^3 cut into n^3 cells of six tetrahedra each; interior nodes jittered by
+    up to jitter*h per axis.  Returns nodes, tets, bfaces."""
+    rng = np.random.default_rng(seed)
+    h = L / n
+    g = np.arange(n + 1) * h - L / 2
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    nodes = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    idx = lambda i, j, k: (i * (n + 1) + j) * (n + 1) + k
+    i, j, k = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    corner = np.stack([idx(i + (c & 1), j + ((c >> 1) & 1), k + ((c >> 2) & 1)) for c in range(8)], axis=1)
+    tets = corner[:, _KUHN].reshape(-1, 4).astype(np.int32)
+    if jitter:
+        inner = np.all(np.abs(nodes) < L / 2 - 0.5 * h, axis=1)
+        nodes[inner] += rng.uniform(-jitter * h, jitter * h, size=(int(inner.sum()), 3))
+    return nodes, tets, boundary_faces(nodes, tets)
+
+
+def ball_tet_mesh(n=8, R=1.0):
+    """Ball of radius R: the cube mesh of [-1, 1]^3 pushed radially onto the ball
+    (p -> R p |p|_inf / |p|_2).  The boundary is the polyhedron of the mapped cube surface,
+    its vertices on the sphere.  The map keeps every tetrahedron's orientation but flattens
+    the cells along the cube's diagonals (smallest volume ~1e-3 of the mean at n = 16), so
+    the nodes are not jittered: a jitter of 0.1 h already inverts some of them."""
+    nodes, tets, _ = cube_tet_mesh(n=n, L=2.0)
+    r2 = np.linalg.norm(nodes, axis=1)
+    rinf = np.abs(nodes).max(axis=1)
+    sc = np.where(r2 > 0, rinf / np.where(r2 > 0, r2, 1.0), 0.0)
+    nodes = R * nodes * sc[:, None]
+    return nodes, tets, boundary_faces(nodes, tets)
+
+
 def _smooth3(rng, pts, n_modes, kmax, L):
     """A smooth random scalar field on 3D points: a sum of cosine modes of wavelength >= L/kmax."""
     ks = rng.integers(-kmax, kmax + 1, size=(n_modes, 3)).astype(np.float64)
