@@ -463,6 +463,42 @@ enum {
     FN3_NUM_STAGES
 };
 int fn3_set_profiling(fn3_ctx *ctx, int enable);
+
+/*
+ * 3D FEM front on tetrahedra (the 2D fn_mesh_* calls with tetrahedra and boundary
+ * triangles; the Discretization section's P1 interpolation of M, rho = -div M and
+ * sigma = M.n, quadrature points with weights omega_j det J):
+ *   nodes [n_nodes][3] FP64, tets [n_tets][4] int32 (any orientation), bfaces [n_bfaces][3]
+ *   int32 with (b - a) x (c - a) pointing out of the domain; M [n_nodes][3].
+ * Sources (S = 4 n_tets + 3 n_bfaces): 4 points per tetrahedron at barycentric
+ * (a, b, b, b) and permutations, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weight |T|/4,
+ * then 3 points per boundary face at (2/3, 1/6, 1/6) and permutations, weight |F|/3.
+ * q = C M: -div M_h at the volume points, M_h . n at the face points; C^T its transpose;
+ * lumped mass l_i = sum |T|/4 over the tetrahedra at node i.  Workspace, stream, error
+ * and ordering conventions are those of fn_mesh_*; fn3_mesh_set checks indices and
+ * finiteness (FN_E_INVAL) and zero-volume tetrahedra (|det J| <= 1e-12 |e1||e2||e3|) or
+ * zero-area faces (FN_E_DOMAIN), and blocks until done.
+ * fn3_bind_mesh: the mesh's nodes become the targets and its quadrature points the
+ * sources of the 3D context (fn3_set_geometry).
+ * fn3_energy: E = -1/2 sum_i l_i M_i . H_i (one device double) and, if grad is not NULL,
+ * dE/dM = -1/2 (l H + C^T A^T (l M)) [n_nodes][3], with H = A C M the 3D fast-sum field
+ * at the nodes; on the context's stream; needs fn3_bind_mesh after the last fn3_mesh_set
+ * and fn3_set_geometry (else FN_E_STATE).  fn3_bind_mesh and fn3_energy report every
+ * error, the context's included, through fn3_mesh_last_error(mesh).
+ */
+typedef struct fn3_mesh fn3_mesh;
+int fn3_mesh_create(int64_t n_nodes, int64_t n_tets, int64_t n_bfaces, void *stream, fn3_mesh **out);
+int fn3_mesh_destroy(fn3_mesh *mesh);
+int fn3_mesh_workspace_size(const fn3_mesh *mesh, size_t *bytes);
+int fn3_mesh_set_workspace(fn3_mesh *mesh, void *dev_ptr, size_t bytes);
+int fn3_mesh_set(fn3_mesh *mesh, const double *nodes, const int32_t *tets, const int32_t *bfaces);
+int fn3_mesh_sources(fn3_mesh *mesh, double *x, double *w);          /* x [S][3], w [S]; either may be NULL */
+int fn3_mesh_lumped_mass(fn3_mesh *mesh, double *ell);               /* ell [n_nodes] */
+int fn3_mesh_charges(fn3_mesh *mesh, const double *M, double *q);    /* M [n_nodes][3] -> q [S] */
+int fn3_mesh_charges_T(fn3_mesh *mesh, const double *u, double *out);/* u [S] -> out [n_nodes][3] */
+int fn3_bind_mesh(fn3_ctx *ctx, fn3_mesh *mesh);
+int fn3_energy(fn3_ctx *ctx, fn3_mesh *mesh, const double *M, double *E, double *grad);
+const char *fn3_mesh_last_error(const fn3_mesh *mesh);
 int fn3_get_profile(fn3_ctx *ctx, fn_profile *out);
 const char *fn3_last_error(const fn3_ctx *ctx);
 

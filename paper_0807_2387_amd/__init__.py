@@ -34,7 +34,7 @@ import ctypes
 from . import _lib
 from ._lib import FN_FP32_MIXED, FN_FP64, FemNfftError  # noqa: F401
 
-__all__ = ["Solver", "Solver3", "Mesh", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params",
+__all__ = ["Solver", "Solver3", "Mesh", "Mesh3", "Batch", "Graph", "DemagEnergy", "default_params", "auto_params",
            "FN_FP64", "FN_FP32_MIXED",
            "FemNfftError"]
 
@@ -308,18 +308,23 @@ class Solver3:
         nt, ns = int(tgt_xyz.shape[0]), int(src_xyz.shape[0])
         if src_w.dim() != 1 or src_w.shape[0] != ns:
             raise ValueError(f"src_w must have shape [{ns}]")
-        need = ctypes.c_size_t()
-        self._check(L.fn3_workspace_size(self._ctx, nt, ns, ctypes.byref(need)))
-        if self._ws is None or self._ws.numel() < need.value:
-            self._ws = None
-            self._ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
-            self._check(L.fn3_set_workspace(self._ctx, ctypes.c_void_p(self._ws.data_ptr()), need))
+        self._ensure_ws(nt, ns)
         self._check(L.fn3_set_geometry(self._ctx, nt, _dev_ptr(tgt_xyz, "tgt_xyz", (3,)) if nt else None, ns,
                                        _dev_ptr(src_xyz, "src_xyz", (3,)) if ns else None,
                                        _dev_ptr(src_w, "src_w") if ns else None))
         self.n_tgt, self.n_src = nt, ns
         self._geom_refs = (tgt_xyz, src_xyz, src_w)
         return self
+
+    def _ensure_ws(self, nt, ns):
+        torch = _torch()
+        L = _lib.lib()
+        need = ctypes.c_size_t()
+        self._check(L.fn3_workspace_size(self._ctx, nt, ns, ctypes.byref(need)))
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = None
+            self._ws = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+            self._check(L.fn3_set_workspace(self._ctx, ctypes.c_void_p(self._ws.data_ptr()), need))
 
     def set_charges(self, q):
         if q.dim() != 1 or q.shape[0] != self.n_src:
@@ -438,6 +443,89 @@ class Mesh:
         self._check(_lib.lib().fn_mesh_p1_gradient(self._mesh, _dev_ptr(phi, "phi"), _dev_ptr(HT, "H_tri", (2,)),
                                                    _dev_ptr(Hn, "H_node", (2,))))
         return HT, Hn
+
+
+class Mesh3:
+    """A P1 tetrahedral mesh on the device (fn3_mesh_*): nodes [N, 3] float64, tets [T, 4] int32,
+    bfaces [F, 3] int32 with (b - a) x (c - a) pointing out of the domain."""
+
+    def __init__(self, nodes, tets, bfaces, stream=None):
+        torch = _torch()
+        L = _lib.lib()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n_nodes, self.n_tets, self.n_bfaces = int(nodes.shape[0]), int(tets.shape[0]), int(bfaces.shape[0])
+        self.n_sources = 4 * self.n_tets + 3 * self.n_bfaces
+        m = ctypes.c_void_p()
+        _lib.check_mesh3(L.fn3_mesh_create(self.n_nodes, self.n_tets, self.n_bfaces,
+                                           ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(m)))
+        self._mesh = m
+        b = ctypes.c_size_t()
+        self._check(L.fn3_mesh_workspace_size(m, ctypes.byref(b)))
+        self._ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        self._check(L.fn3_mesh_set_workspace(m, ctypes.c_void_p(self._ws.data_ptr()), b))
+        self._check(L.fn3_mesh_set(m, _dev_ptr(nodes, "nodes", (3,)), _dev_ptr(tets, "tets", (4,), torch.int32),
+                                   _dev_ptr(bfaces, "bfaces", (3,), torch.int32) if self.n_bfaces else None))
+
+    def __del__(self):
+        m = getattr(self, "_mesh", None)
+        if m:
+            try:
+                _lib.lib().fn3_mesh_destroy(m)
+            except Exception:
+                pass
+            self._mesh = None
+
+    def _check(self, rc):
+        _lib.check_mesh3(rc, self._mesh)
+
+    def sources(self):
+        torch = _torch()
+        x = torch.empty(self.n_sources, 3, dtype=torch.float64, device=self.device)
+        w = torch.empty(self.n_sources, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn3_mesh_sources(self._mesh, _dev_ptr(x, "x", (3,)), _dev_ptr(w, "w")))
+        return x, w
+
+    def lumped_mass(self):
+        torch = _torch()
+        ell = torch.empty(self.n_nodes, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn3_mesh_lumped_mass(self._mesh, _dev_ptr(ell, "ell")))
+        return ell
+
+    def charges(self, M):
+        torch = _torch()
+        if M.dim() != 2 or M.shape[0] != self.n_nodes:
+            raise ValueError(f"M must have shape [{self.n_nodes}, 3]")
+        q = torch.empty(self.n_sources, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn3_mesh_charges(self._mesh, _dev_ptr(M, "M", (3,)), _dev_ptr(q, "q")))
+        return q
+
+    def charges_T(self, u):
+        torch = _torch()
+        if u.dim() != 1 or u.shape[0] != self.n_sources:
+            raise ValueError(f"u must have shape [{self.n_sources}]")
+        out = torch.empty(self.n_nodes, 3, dtype=torch.float64, device=self.device)
+        self._check(_lib.lib().fn3_mesh_charges_T(self._mesh, _dev_ptr(u, "u"), _dev_ptr(out, "out", (3,))))
+        return out
+
+    def bind(self, solver):
+        """Targets = this mesh's nodes, sources = its quadrature points, on the 3D solver."""
+        solver._ensure_ws(self.n_nodes, self.n_sources)
+        self._check(_lib.lib().fn3_bind_mesh(solver._ctx, self._mesh))
+        solver.n_tgt, solver.n_src = self.n_nodes, self.n_sources
+        solver._geom_refs = (self,)
+        return solver
+
+    def energy(self, solver, M, grad=True):
+        """E (a device scalar) and dE/dM [N, 3] (or None) of nodal M through the bound 3D solver."""
+        torch = _torch()
+        if M.dim() != 2 or M.shape[0] != self.n_nodes:
+            raise ValueError(f"M must have shape [{self.n_nodes}, 3]")
+        E = torch.empty((), dtype=torch.float64, device=self.device)
+        g = torch.empty(self.n_nodes, 3, dtype=torch.float64, device=self.device) if grad else None
+        self._check(_lib.lib().fn3_energy(solver._ctx, self._mesh, _dev_ptr(M, "M", (3,)), _dev_ptr(E, "E"),
+                                          _dev_ptr(g, "grad", (3,)) if g is not None else None))
+        return E, g
 
 
 def _params(d):

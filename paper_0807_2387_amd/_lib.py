@@ -33,6 +33,9 @@ SYMBOLS = (
     "fn_graph_begin", "fn_graph_end", "fn_graph_launch", "fn_graph_destroy", "fn_graph_last_error",
     "fn3_create", "fn3_destroy", "fn3_workspace_size", "fn3_set_workspace", "fn3_set_geometry", "fn3_set_charges",
     "fn3_eval", "fn3_eval_H_adjoint", "fn3_get_info", "fn3_set_profiling", "fn3_get_profile", "fn3_last_error",
+    "fn3_mesh_create", "fn3_mesh_destroy", "fn3_mesh_workspace_size", "fn3_mesh_set_workspace", "fn3_mesh_set",
+    "fn3_mesh_sources", "fn3_mesh_lumped_mass", "fn3_mesh_charges", "fn3_mesh_charges_T", "fn3_bind_mesh",
+    "fn3_energy", "fn3_mesh_last_error",
 )
 
 STAGES = ("charges", "spread", "fold", "rows_fwd", "cols", "rows_inv", "gather", "near",
@@ -158,6 +161,18 @@ def lib():
         "fn3_set_profiling": ([P, ctypes.c_int], ctypes.c_int),
         "fn3_get_profile": ([P, ctypes.POINTER(Profile)], ctypes.c_int),
         "fn3_last_error": ([P], ctypes.c_char_p),
+        "fn3_mesh_create": ([I64, I64, I64, P, ctypes.POINTER(P)], ctypes.c_int),
+        "fn3_mesh_destroy": ([P], ctypes.c_int),
+        "fn3_mesh_workspace_size": ([P, ctypes.POINTER(SZ)], ctypes.c_int),
+        "fn3_mesh_set_workspace": ([P, P, SZ], ctypes.c_int),
+        "fn3_mesh_set": ([P, P, P, P], ctypes.c_int),
+        "fn3_mesh_sources": ([P, P, P], ctypes.c_int),
+        "fn3_mesh_lumped_mass": ([P, P], ctypes.c_int),
+        "fn3_mesh_charges": ([P, P, P], ctypes.c_int),
+        "fn3_mesh_charges_T": ([P, P, P], ctypes.c_int),
+        "fn3_bind_mesh": ([P, P], ctypes.c_int),
+        "fn3_energy": ([P, P, P, P, P], ctypes.c_int),
+        "fn3_mesh_last_error": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -188,6 +203,12 @@ def check_graph(rc):
 def check_mesh(rc, mesh=None):
     if rc != FN_OK:
         msg = lib().fn_mesh_last_error(mesh)
+        raise FemNfftError(rc, msg.decode() if msg else "")
+
+
+def check_mesh3(rc, mesh=None):
+    if rc != FN_OK:
+        msg = lib().fn3_mesh_last_error(mesh)
         raise FemNfftError(rc, msg.decode() if msg else "")
 
 

@@ -88,6 +88,7 @@ struct fn3_ctx {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bool plan_ready = false, geom_ready = false, charges_ready = false;
+    uint64_t geom_gen = 0;  // successful fn3_set_geometry calls
     std::string err;
     // stage timing (fn3_set_profiling): event pairs recorded on the stream around each stage
     bool prof_on = false;
@@ -1419,6 +1420,7 @@ int fn3_set_geometry(fn3_ctx *ctx, int64_t n_tgt, const double *tgt_xyz, int64_t
     }
     F3_HIP(c, hipStreamSynchronize(st));
     c->geom_ready = true;
+    c->geom_gen++;
     return FN_OK;
 }
 
@@ -1583,6 +1585,10 @@ int fn3_get_profile(fn3_ctx *ctx, fn_profile *out)
     *out = ctx->prof;
     return FN_OK;
 }
+
+int fn3_internal_device(const fn3_ctx *c) { return c->device; }
+void *fn3_internal_stream(const fn3_ctx *c) { return c->stream; }
+uint64_t fn3_internal_geom_gen(const fn3_ctx *c) { return c->geom_gen; }
 
 const char *fn3_last_error(const fn3_ctx *ctx)
 {

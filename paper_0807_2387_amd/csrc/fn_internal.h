@@ -206,6 +206,11 @@ __attribute__((visibility("hidden"))) int fn_internal_adjoint_H_on_stream(fn_ctx
                                                                           hipStream_t st);
 __attribute__((visibility("hidden"))) int fn_internal_adjoint_phi_on_stream(fn_ctx *c, const double *v, double *u,
                                                                             hipStream_t st);
+// the 3D context's device, stream and geometry generation (incremented by every successful
+// fn3_set_geometry), for the 3D FEM front
+__attribute__((visibility("hidden"))) int fn3_internal_device(const fn3_ctx *c);
+__attribute__((visibility("hidden"))) void *fn3_internal_stream(const fn3_ctx *c);
+__attribute__((visibility("hidden"))) uint64_t fn3_internal_geom_gen(const fn3_ctx *c);
 }
 
 // true while work issued on `st` is being captured into a graph

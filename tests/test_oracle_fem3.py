@@ -8,7 +8,8 @@
     against numerical quadrature) converging as the mesh is refined, the field -M/3 at
     the centre;
   * a uniformly magnetized ball: potential M.r/3 and field -M/3 inside, approached at
-    second order as the mesh is refined (the boundary is a polyhedron).
+    second order as the mesh is refined (the boundary is a polyhedron); its lumped
+    energy tends to V M^2 / 6 at first order.
 """
 import numpy as np
 import pytest
@@ -116,3 +117,20 @@ def test_uniform_ball_potential_and_field():
         eh.append(np.abs(H - np.array([-1 / 3, 0.0, 0.0])).max())
     assert ep[0] > 2.5 * ep[1] > 2.5 * 2.5 * ep[2] and ep[2] < 1e-4, ep
     assert eh[0] > 2.5 * eh[1] > 2.5 * 2.5 * eh[2] and eh[2] < 5e-4, eh
+
+
+def test_uniform_ball_lumped_energy_converges_at_first_order():
+    """E = -1/2 sum l_i M_i.H_i of the uniformly magnetized ball tends to V M^2 / 6 (H = -M/3
+    inside); the boundary nodes, where H is the average of the inner and outer fields, make
+    the lumped sum's error first order in h: (E/(V/6) - 1) n is constant."""
+    devs = []
+    for n in (8, 12, 16):
+        nodes, tets, bf = synth.ball_tet_mesh(n=n)
+        M = np.zeros((len(nodes), 3))
+        M[:, 2] = 1.0
+        x, w = fem3.sources(nodes, tets, bf)
+        q = fem3.charges(nodes, tets, bf, M)
+        _, H = direct.forward3(nodes, x, w, q, want_phi=False)
+        ell = fem3.lumped_mass(nodes, tets)
+        devs.append((fem3.energy(M, H, ell) / (ell.sum() / 6) - 1) * n)
+    assert all(d < 0 for d in devs) and max(devs) / min(devs) < 1.03, devs
