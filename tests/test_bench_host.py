@@ -53,3 +53,20 @@ def test_counter_traffic_only_for_the_setting_it_was_taken_on():
     assert bench.counter_traffic("k_near<0", args[0], args[1], args[2] * 2, args[3]) is None
     assert bench.counter_traffic("k_near<0", args[0], args[1], args[2], args[3] // 2) is None
     assert bench.counter_traffic("k_near<0", args[0] // 2, args[1], args[2], args[3]) is None
+
+
+def test_3d_near_flop_accounting_and_roofline_record():
+    # forward: offsets 6, r^2 5, x 1, T and D by Horner 2(p-1) + 2(p-2), sqrt 1, 1/r 1,
+    # phi share 2, field factor 4, phi sum 2, H sums 7
+    assert bench.near3_flops_per_pair("near", 6) == 6 + 5 + 1 + 10 + 8 + 1 + 1 + 2 + 4 + 2 + 7
+    # adjoint: offsets 6, r^2 5, x 1, D 2(p-2), sqrt 1, field factor 5, V.d 5, sum 2
+    assert bench.near3_flops_per_pair("a_near", 6) == 6 + 5 + 1 + 8 + 1 + 5 + 5 + 2
+    info = {"win_ext": (110, 110, 110)}
+    pairs = {"near": 10 ** 9, "a_near": 10 ** 9}
+    r = bench.roofline3("near", 2.0, 256, 6, 6, info, 1000, 4000, pairs)
+    assert r["bound"] == "alu" and abs(r["achieved"] - 1e9 * 47 / 2e-3 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / bench.FP64_VEC_TFLOPS) < 1e-15
+    # a grid pass: every value read and written once per axis pass, 3 passes
+    r = bench.roofline3("fft", 1.0, 256, 6, 6, info, 1000, 4000, pairs)
+    assert r["algorithmic_bytes_per_launch"] == 6 * 256 ** 3 * 16
+    assert r["bound"] == "hbm" and abs(r["achieved"] - 6 * 256 ** 3 * 16 / 1e-3 / 1e9) < 1e-6

@@ -127,3 +127,20 @@ def test_3d_empty_sets_and_errors(torch, fn):
     for kw, msg in ((dict(grid=48), "power of two"), (dict(grid=16, m=4), "grid/4"), (dict(grid=512), "power of two")):
         with pytest.raises(fn.FemNfftError, match=msg):
             fn.Solver3(**dict(dict(m=3, p=4, eps_I=0.1), **kw))
+
+
+def test_3d_stage_profile_records_every_stage(torch, fn):
+    y, x, w, q = synth.random_cloud3(2000, 3000, 44)
+    S = fn.Solver3(grid=64, m=6, p=6, eps_I=5 / 32, eps_B=1 / 8)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
+    V = dev(torch, np.random.default_rng(45).standard_normal((len(y), 3)))
+    S.set_profiling(True)
+    for _ in range(2):
+        S.set_charges(dev(torch, q))
+        S.eval()
+        S.adjoint_H(V)
+    torch.cuda.synchronize()
+    prof = S.profile()
+    S.set_profiling(False)
+    print({k: f"{v[0]:.3f} ms x {v[1]}" for k, v in prof.items()}, flush=True)
+    assert all(n == 2 and ms > 0 for ms, n in prof.values()), prof
