@@ -471,17 +471,22 @@ __global__ void __launch_bounds__(512) k3_pass(double2 *__restrict__ a, int N, i
 
 // ------------------------------------------------------------------ spread / multiply / gather
 
-// Spread, one field.  One wave per tile of ST^3 base cells (a point's base cell is its first
-// tap cell); the tile's footprint of F^3 grid points, F = ST + 2m - 1, is accumulated in LDS:
-// the wave takes the tile's points one after the other in sorted order, its lanes the (a, b)
-// taps of a point (distinct LDS addresses), each looping over the 2m taps c.  Every LDS value
-// is thus summed in a fixed order, and the footprint is written to the tile's own slot of
-// tileout [tile][F^3]; k3_fold adds the overlapping footprints.  No atomics.
-constexpr int ST = 4;
+// Spread, one field.  One block of SW waves per tile of ST^3 base cells (a point's base cell
+// is its first tap cell); the tile's footprint of F^3 grid points, F = ST + 2m - 1, is
+// accumulated in LDS.  The footprint's z planes are split among the waves (wave w owns a
+// contiguous range of planes); every wave takes the tile's points one after the other in
+// sorted order, its lanes the point's (a, b) taps, each lane adding the taps c whose plane
+// lies in the wave's range.  Each LDS value is thus updated by one wave only, in a fixed
+// order of points (no atomics, no races), and the footprint is written to the tile's own
+// slot of tileout [tile][F^3]; k3_fold adds the overlapping footprints.
+constexpr int ST = 6;
+constexpr int SW = 4;
 
-__global__ void __launch_bounds__(64) k3_spread_tile(const double *__restrict__ taps, const uint32_t *__restrict__ key,
-                                                     const uint32_t *__restrict__ cstart, const double *__restrict__ val,
-                                                     Map3 mp, int ntx, int nty, double *__restrict__ tileout)
+__global__ void __launch_bounds__(64 * SW) k3_spread_tile(const double *__restrict__ taps,
+                                                          const uint32_t *__restrict__ key,
+                                                          const uint32_t *__restrict__ cstart,
+                                                          const double *__restrict__ val, Map3 mp, int ntx, int nty,
+                                                          double *__restrict__ tileout)
 {
     extern __shared__ double acc[];
     const int M2 = 2 * mp.m, F = ST + M2 - 1, F2 = F * F, F3 = F2 * F;
@@ -489,8 +494,9 @@ __global__ void __launch_bounds__(64) k3_spread_tile(const double *__restrict__ 
     const int ex = mp.ext[0], ey = mp.ext[1];
     const int nbx = ex - M2 + 1, nby = ey - M2 + 1, nbz = mp.ext[2] - M2 + 1;
     const int x0 = tx * ST, y0 = ty * ST, z0 = tz * ST;
-    const int lane = threadIdx.x;
-    for (int i = lane; i < F3; i += 64) acc[i] = 0.0;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int pz0 = (wv * F) / SW, pz1 = ((wv + 1) * F) / SW;  // this wave's footprint planes
+    for (int i = threadIdx.x; i < F3; i += 64 * SW) acc[i] = 0.0;
     // this lane's (a, b) taps: e = lane + 64 r < (2m)^2 <= 256
     int ne = 0, ea[4], eb[4];
     for (int e = lane; e < M2 * M2; e += 64) {
@@ -500,7 +506,10 @@ __global__ void __launch_bounds__(64) k3_spread_tile(const double *__restrict__ 
     }
     __syncthreads();
     const int x1 = min(x0 + ST, nbx);
-    for (int dz = 0; dz < ST && z0 + dz < nbz; ++dz)
+    constexpr int CMAX = 2 * MAXM / SW + 2;  // planes per wave: at most ceil((ST + 2m - 1)/SW)
+    for (int dz = 0; dz < ST && z0 + dz < nbz; ++dz) {
+        const int c0 = max(0, pz0 - dz), c1 = min(M2, pz1 - dz);  // taps c landing in the wave's planes
+        if (c0 >= c1) continue;                                   // uniform over the wave
         for (int dy = 0; dy < ST && y0 + dy < nby; ++dy) {
             const int64_t row = ((int64_t)(z0 + dz) * ey + (y0 + dy)) * ex;
             const uint32_t j0 = cstart[row + x0], j1 = cstart[row + x1];
@@ -508,17 +517,27 @@ __global__ void __launch_bounds__(64) k3_spread_tile(const double *__restrict__ 
                 const int lx = (int)(key[j] - (uint32_t)row) - x0;
                 const double *tp = taps + (int64_t)j * 3 * M2;
                 const double v = val[j];
+                double tzc[CMAX];
+#pragma unroll
+                for (int k = 0; k < CMAX; ++k) tzc[k] = c0 + k < c1 ? tp[2 * M2 + c0 + k] : 0.0;
                 for (int r = 0; r < ne; ++r) {
                     const int aa = ea[r], bb = eb[r];
                     const double wab = tp[aa] * tp[M2 + bb] * v;
-                    double *ap = acc + (dz * F + dy + bb) * F + lx + aa;
-                    for (int c = 0; c < M2; ++c) ap[c * F2] += wab * tp[2 * M2 + c];
+                    double *ap = acc + ((dz + c0) * F + dy + bb) * F + lx + aa;
+                    double cur[CMAX];
+#pragma unroll
+                    for (int k = 0; k < CMAX; ++k)
+                        if (c0 + k < c1) cur[k] = ap[k * F2];
+#pragma unroll
+                    for (int k = 0; k < CMAX; ++k)
+                        if (c0 + k < c1) ap[k * F2] = fma(wab, tzc[k], cur[k]);
                 }
             }
         }
+    }
     __syncthreads();
     double *o = tileout + (int64_t)t * F3;
-    for (int i = lane; i < F3; i += 64) o[i] = acc[i];
+    for (int i = threadIdx.x; i < F3; i += 64 * SW) o[i] = acc[i];
 }
 
 // Grid value at every data-window point: the sum of the footprints of the tiles that reach
@@ -614,17 +633,21 @@ __global__ void __launch_bounds__(256) k3_gather(const double *__restrict__ taps
         for (int c = 0; c < M2; ++c) {
             const double wz = txa * tp[2 * M2 + c];
             const int64_t zrow = ((int64_t)(b2 + c + mp.wlo[2]) * G + (b1 + mp.wlo[1])) * G + xo;
-            for (int b = 0; b < M2; ++b) {
-                const double w = wz * tp[M2 + b];
+            for (int b = 0; b < M2; b += 2) {  // 2m is even: two rows per trip, loads first
+                const double w0 = wz * tp[M2 + b], w1 = wz * tp[M2 + b + 1];
                 const int64_t o = zrow + (int64_t)b * G;
-                const double2 u = A[o];
-                acc0 += w * u.x;
+                const double2 u0 = A[o], u1 = A[o + G];
                 if (nout == 4) {
-                    acc1 += w * u.y;
-                    const double2 v = B[o];
-                    acc2 += w * v.x;
-                    acc3 += w * v.y;
+                    const double2 v0 = B[o], v1 = B[o + G];
+                    acc1 = fma(w0, u0.y, acc1);
+                    acc2 = fma(w0, v0.x, acc2);
+                    acc3 = fma(w0, v0.y, acc3);
+                    acc1 = fma(w1, u1.y, acc1);
+                    acc2 = fma(w1, v1.x, acc2);
+                    acc3 = fma(w1, v1.y, acc3);
                 }
+                acc0 = fma(w0, u0.x, acc0);
+                acc0 = fma(w1, u1.x, acc0);
             }
         }
     }
@@ -792,6 +815,7 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
 
     const double a0 = nr.a[0];
     for (uint32_t kc0 = 0; kc0 < nhome; kc0 += KC) {
+        const int kn = (int)min((uint32_t)KC, nhome - kc0);  // home points in this chunk (block-uniform)
         // this chunk's home positions (a far sentinel for empty slots never enters the zone)
         double hx[KC], hy[KC], hz[KC];
 #pragma unroll
@@ -830,6 +854,7 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
             }
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
+                if (k >= kn) break;  // uniform: a short last chunk costs only its own pairs
                 const double dx = hx[k] - q.x, dy = hy[k] - q.y, dz = hz[k] - q.z;
                 const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                 const bool inz = r2 < e2;
@@ -1102,6 +1127,11 @@ int build_plan3(fn3_ctx *c)
     Buf3 &B = c->buf;
     hipStream_t st = c->stream;
     F3_HIP(c, hipFuncSetAttribute((const void *)k3_pass, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PASS_LDS));
+    {
+        const int F = ST + 2 * MAXM - 1;
+        F3_HIP(c, hipFuncSetAttribute((const void *)k3_spread_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      F * F * F * (int)sizeof(double)));
+    }
     F3_HIP(c, hipMemcpyAsync(B.twG, P.twG.data(), P.twG.size() * 8, hipMemcpyHostToDevice, st));
     F3_HIP(c, hipMemcpyAsync(B.twn, P.twn.data(), P.twn.size() * 8, hipMemcpyHostToDevice, st));
     double *coef = B.red, *cB = B.red + 32, *psi = B.red + 128;
@@ -1138,7 +1168,7 @@ Map3 map_of(const fn3_ctx *c)
     return mp;
 }
 
-// Near-field constants; home blocks sized for about 8 home points each (one register chunk),
+// Near-field constants; home blocks sized for about 4-8 home points each (a register chunk),
 // from the density the home set would have if it filled the ball the torus map allows.
 Near3 near_of(const fn3_ctx *c, bool adj)
 {
@@ -1160,7 +1190,7 @@ Near3 near_of(const fn3_ctx *c, bool adj)
     const double ppc = (double)(adj ? g.ns : g.nt) / std::max(1.0, PI / 6.0 * dia * dia * dia);
     static const int shapes[5][3] = {{2, 2, 1}, {2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {8, 4, 2}};
     int k = 0;
-    while (k < 4 && ppc * shapes[k][0] * shapes[k][1] * shapes[k][2] < 6.0) ++k;
+    while (k < 4 && ppc * shapes[k][0] * shapes[k][1] * shapes[k][2] < 4.0) ++k;
     for (int d = 0; d < 3; ++d) {
         nr.hb[d] = shapes[k][d];
         const int nb = g.ext[d] - 2 * P.m + 1;
@@ -1241,7 +1271,7 @@ int spread_fft(fn3_ctx *c, int set, const double *val, int64_t N, int nf, int st
     const int64_t cells = (int64_t)mp.ext[0] * mp.ext[1] * mp.ext[2];
     int pi = prof3_begin(c, st_spread);
     for (int f = 0; f < nf; ++f) {
-        k3_spread_tile<<<ntiles, 64, (size_t)F * F * F * sizeof(double), c->stream>>>(
+        k3_spread_tile<<<ntiles, 64 * SW, (size_t)F * F * F * sizeof(double), c->stream>>>(
             B.taps[set], B.key[set], B.cstart[set], val + (int64_t)f * N, mp, nt[0], nt[1], B.tiles);
         F3_LAUNCH(c);
         k3_fold<<<nbk(cells), NT, 0, c->stream>>>(B.tiles, mp, nt[0], nt[1], nt[2], P.G, B.grid[f]);
