@@ -410,12 +410,25 @@ def near3_flops_per_pair(stage, p):
     return 6 + 5 + 1 + 2 * (p - 2) + 1 + 5 + 5 + 2
 
 
+def fft3_bytes(G, ext, forward):
+    """Bytes the pruned 3D transform must move: each pass reads the elements its lines hold
+    (the data window or the band |l| <= n/2, n = G/2) and writes the ones the next step keeps."""
+    nb = 2 * (G // 4) + 1
+    ex, ey, ez = ext
+    if forward:  # x lines of the window's rows, y lines of band x window-z, z lines of band x band
+        el = ey * ez * (ex + nb) + nb * ez * (ey + nb) + nb * nb * (ez + nb)
+    else:        # z lines of band x band, y lines of band x window-z, x lines of the window's rows
+        el = nb * nb * (nb + ez) + nb * ez * (nb + ey) + ey * ez * (nb + ex)
+    return el * 16
+
+
 def roofline3(stage, ms_per_launch, G, m, p, info, nt, ns, pairs):
     """Roofline of one 3D stage: algorithmic HBM bytes (points' cell, fractions and values once,
-    every grid value read and written once per pass), or near-field flops, per launch."""
+    every grid value a pass needs read and written once), or near-field flops, per launch."""
     sec = ms_per_launch * 1e-3
-    G3 = G ** 3 * 16
-    win = int(np.prod(info["win_ext"])) * 16
+    ext = tuple(info["win_ext"])
+    win = int(np.prod(ext)) * 16
+    band3 = (2 * (G // 4) + 1) ** 3 * 16
     if stage in ("near", "a_near"):
         fl = near3_flops_per_pair(stage, p)
         ach = pairs[stage] * fl / sec / 1e12
@@ -424,10 +437,10 @@ def roofline3(stage, ms_per_launch, G, m, p, info, nt, ns, pairs):
                 "pairs_per_launch": pairs[stage], "flops_per_pair": fl}
     byts = {
         "charges": ns * 28, "a_values": nt * 52,
-        "spread": ns * 36 + G3, "a_spread": nt * 52 + 3 * G3,
-        "fft": 6 * G3, "a_fft": 18 * G3,
-        "multiply": 3 * G3, "a_multiply": 4 * G3,
-        "ifft": 12 * G3, "a_ifft": 6 * G3,
+        "spread": ns * 36 + win, "a_spread": nt * 60 + 3 * win,
+        "fft": fft3_bytes(G, ext, True), "a_fft": 3 * fft3_bytes(G, ext, True),
+        "multiply": 3 * band3, "a_multiply": 4 * band3,
+        "ifft": 2 * fft3_bytes(G, ext, False), "a_ifft": fft3_bytes(G, ext, False),
         "gather": nt * 60 + 2 * win, "a_gather": ns * 36 + win,
     }[stage]
     ach = byts / sec / 1e9

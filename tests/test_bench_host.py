@@ -66,7 +66,12 @@ def test_3d_near_flop_accounting_and_roofline_record():
     r = bench.roofline3("near", 2.0, 256, 6, 6, info, 1000, 4000, pairs)
     assert r["bound"] == "alu" and abs(r["achieved"] - 1e9 * 47 / 2e-3 / 1e12) < 1e-9
     assert abs(r["frac"] - r["achieved"] / bench.FP64_VEC_TFLOPS) < 1e-15
-    # a grid pass: every value read and written once per axis pass, 3 passes
+    # the pruned transform: window rows in, band out, per pass
+    nb = 2 * 64 + 1
+    fwd = (110 * 110 * (110 + nb) + nb * 110 * (110 + nb) + nb * nb * (110 + nb)) * 16
     r = bench.roofline3("fft", 1.0, 256, 6, 6, info, 1000, 4000, pairs)
-    assert r["algorithmic_bytes_per_launch"] == 6 * 256 ** 3 * 16
-    assert r["bound"] == "hbm" and abs(r["achieved"] - 6 * 256 ** 3 * 16 / 1e-3 / 1e9) < 1e-6
+    assert r["algorithmic_bytes_per_launch"] == fwd
+    assert r["bound"] == "hbm" and abs(r["achieved"] - fwd / 1e-3 / 1e9) < 1e-6
+    # an unpruned transform of the whole cube would move 6 G^3 complex values: far more
+    assert fwd < 6 * 256 ** 3 * 16 / 4
+    assert bench.fft3_bytes(256, (110, 110, 110), False) == fwd
