@@ -233,6 +233,7 @@ def main():
         err, cpu = accuracy_and_cpu(d, r, args, nt, ns)
         out["rel_l2_vs_fp64_oracle"] = err
         out["cpu_baseline"] = cpu
+        out["cpu_fastsum"] = cpu_fastsum(args)
     else:
         out["cpu_baseline"] = None
 
@@ -396,6 +397,42 @@ def accuracy_and_cpu(d, r, args, nt, ns):
                      f"{t_f + t_a:.1f} s of CPU work"}
     log(f"vs O1 (sampled): {err}; CPU oracle {cpu['value']:.3e} points/s on {cpu['cores']} threads")
     return err, cpu
+
+
+def cpu_fastsum(args):
+    """The step-by-step fast-summation oracle (O2, numpy/scipy FP64) timed on the host on the
+    same workload recipe at 1/64 of the points (2^18 + 2^18), the grid scaled with sqrt(N)
+    (G/8 = 1024, bandwidth 3G/4, the same m, p, n eps_I, n eps_S and eps_B): a fair N log N CPU
+    figure beside the O(N^2) direct sum.  The construction (window matrices, near-pair search,
+    the counterpart of set_geometry) is not timed; forward (phi, H) + H adjoint is."""
+    import synth
+    from oracle import fastsum as fs
+    n = args.n // 64
+    G = max(64, args.grid // 8)
+    band = 3 * G // 4
+    d = synth.rounded_square_cloud(N=n, seed=synth.SEED_BASE + 4)
+    y, x, w, q = d["y"], d["x"], d["w"], d["q"]
+    V = (d["h"] ** 2) * d["M_tgt"]
+    ns1 = int(np.sum(w == d["h"] ** 2))
+    parts = ((slice(0, ns1), args.c, slice(ns1, None)), (slice(ns1, None), args.cs, slice(0, ns1)))
+    t_set, t_run = 0.0, 0.0
+    for sl, c, other in parts:
+        prm = fs.Params(G=G, m=args.m, p=args.p, eps_I=c / band, band=band, eps_B=args.eps_b)
+        a = time.perf_counter()
+        F = fs.FastSum(y, x[sl], w[sl], prm, map_with=x[other])
+        t_set += time.perf_counter() - a
+        a = time.perf_counter()
+        F.forward(q[sl])
+        F.adjoint_H(V)
+        t_run += time.perf_counter() - a
+        del F
+    npts = len(y) + len(x)
+    rec = {"value": npts / t_run, "unit": "points/s", "cores": fs._WORKERS, "kind": "oracle O2 (fast sum)",
+           "sample": f"forward + H adjoint of {len(y)} targets and {len(x)} sources (the workload recipe at 1/64 "
+                     f"of the points), G = {G}, n = {band}; {t_run:.1f} s (construction {t_set:.1f} s, not timed); "
+                     f"the FFTs use {fs._WORKERS} threads, the sparse window products and the near field one"}
+    log(f"CPU fast sum (O2): {rec['value']:.3e} points/s ({rec['sample']})")
+    return rec
 
 
 # ---------------------------------------------------------------------------- 3D path
