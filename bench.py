@@ -69,9 +69,12 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one elementwise kernel over 256 MiB (read and write) before the timed region, "
                          "as the byte-counter calibration for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
-    ap.add_argument("--workload", choices=("square2d", "ball3d"), default="square2d",
+    ap.add_argument("--workload", choices=("square2d", "ball3d", "disk_c1", "ellipse_c2", "batch_c3", "annulus_c4"),
+                    default="square2d",
                     help="square2d: the 2D rounded square (default); ball3d: the 3D path (fn3_*, G = 1/(4 pi r)) "
-                         "on a ball lattice, options --K, --grid3, --m3, --p3, --c3")
+                         "on a ball lattice, options --K, --grid3, --m3, --p3, --c3; disk_c1, ellipse_c2, batch_c3, "
+                         "annulus_c4: the other configurations (a disk of 2k nodes, an ellipse of 50k nodes, a batch "
+                         "of 64 meshes, an annulus of 1M nodes), each through the GPU FEM front")
     ap.add_argument("--K", type=int, default=64, help="ball3d: lattice cells across the ball")
     ap.add_argument("--grid3", type=int, default=256)
     ap.add_argument("--m3", type=int, default=6)
@@ -103,6 +106,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "ball3d":
         return main_3d(args, torch, synth, fn, dev)
+    if args.workload != "square2d":
+        return main_configs(args, torch, synth, fn, dev)
     t0 = time.time()
     d = synth.rounded_square_cloud(N=args.n, seed=synth.SEED_BASE + 4)
     y, x, w, q = d["y"], d["x"], d["w"], d["q"]
@@ -433,6 +438,154 @@ def cpu_fastsum(args):
                      f"the FFTs use {fs._WORKERS} threads, the sparse window products and the near field one"}
     log(f"CPU fast sum (O2): {rec['value']:.3e} points/s ({rec['sample']})")
     return rec
+
+
+# ---------------------------------------------------------------------------- other configurations
+
+def _timed(torch, f, steps, warmup):
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(steps):
+        f()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - a) / steps
+
+
+def main_configs(args, torch, synth, fn, dev):
+    """The smaller configurations, every step through the library's GPU FEM front:
+    disk_c1    disk of ~2k nodes, uniform M = (1, 0) (surface charges only), FP64, G = 64, m = 4,
+               eps_I = 4/64; step = set_charges + phi, H + H adjoint (V = l M)
+    ellipse_c2 ellipse a = 2, b = 1, 50k nodes, vortex M with 8 random modes, G = 512 (the
+               library's defaults for it), FP32-mixed and FP64; the same step
+    batch_c3   64 meshes of 5k-200k nodes in one batch (fn_params_auto per member, FP32-mixed),
+               4 lanes, forward and H adjoint at once, replayed from a HIP graph
+    annulus_c4 annulus of 1M nodes, smooth M, fn_params_auto, FP32-mixed; step = energy and
+               gradient (set charges, H and the H adjoint at once, C^T)
+    Prints one JSON line per precision (rank 0); value = (nodes + quadrature points)/s."""
+    tt = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a)).to(dt or torch.float64).to(dev)
+    out_lines = []
+
+    def mesh_of(d):
+        return fn.Mesh(tt(d["nodes"]), tt(d["tris"], torch.int32), tt(d["bedges"], torch.int32))
+
+    def record(name, precision, ms, npts, cfg, extra=None):
+        rec = {"metric": f"{name}: nodes + quadrature points per second, one step", "value": npts / (ms * 1e-3),
+               "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64" if precision == fn.FN_FP64 else "f32+f64", "data": "synthetic", "config": cfg}
+        rec.update(extra or {})
+        out_lines.append(rec)
+        log(f"{name} ({rec['dtype']}): {ms:.3f} ms per step, {rec['value']:.3e} points/s")
+
+    if args.workload in ("disk_c1", "ellipse_c2"):
+        d = synth.workload_disk_c1() if args.workload == "disk_c1" else synth.workload_ellipse_c2()
+        mesh = mesh_of(d)
+        Md = tt(d["M"])
+        q = mesh.charges(Md)
+        V = mesh.lumped_mass()[:, None] * Md
+        nt, ns = mesh.n_nodes, mesh.n_sources
+        precs = (fn.FN_FP64,) if args.workload == "disk_c1" else (fn.FN_FP32_MIXED, fn.FN_FP64)
+        for P in precs:
+            if args.workload == "disk_c1":
+                S = fn.Solver(grid=64, m=4, eps_I=4 / 64, precision=P)
+                cfg = {"workload": "disk radius 1, 30 polar rings, 128 boundary edges, M = (1, 0)", "grid": 64,
+                       "m": 4, "eps_I": 4 / 64, "n_nodes": nt, "n_src": ns}
+            else:
+                S = fn.Solver(grid=512, precision=P)
+                cfg = {"workload": "ellipse a = 2, b = 1, vortex M + 8 modes", "grid": 512, "n_nodes": nt,
+                       "n_src": ns, "params": "library defaults for G = 512"}
+            S.bind_mesh(mesh)
+            phi = torch.empty(nt, dtype=torch.float64, device=dev)
+            H = torch.empty(nt, 2, dtype=torch.float64, device=dev)
+            u = torch.empty(ns, dtype=torch.float64, device=dev)
+
+            def step():
+                S.set_charges(q)
+                S.eval_with_H_adjoint(V, out_phi=phi, out_H=H, out_u=u)
+
+            ms = _timed(torch, step, args.steps, args.warmup) * 1e3
+            extra = {}
+            if not args.no_cpu:
+                extra = _configs_vs_direct(d, phi, H, u, args)
+            record(args.workload, P, ms, nt + ns, cfg, extra)
+            del S
+    elif args.workload == "annulus_c4":
+        d = synth.workload_annulus_c4()
+        mesh = mesh_of(d)
+        Md = tt(d["M"])
+        a = fn.auto_params(mesh.n_nodes, mesh.n_sources, fn.FN_FP32_MIXED)
+        S = fn.Solver(grid=a["grid"], m=a["m"], p=a["p"], eps_I=a["eps_I"], eps_B=a["eps_B"], n=a["n"],
+                      eps_S=a["eps_S"], precision=fn.FN_FP32_MIXED)
+        S.bind_mesh(mesh)
+        ms = _timed(torch, lambda: S.energy(Md), args.steps, args.warmup) * 1e3
+        record("annulus_c4", fn.FN_FP32_MIXED, ms, mesh.n_nodes + mesh.n_sources,
+               {"workload": "annulus r in [0.5, 1], smooth M, energy and gradient", "n_nodes": mesh.n_nodes,
+                "n_src": mesh.n_sources, "grid": a["grid"], "params": "fn_params_auto"})
+    else:  # batch_c3
+        meshes = synth.batch_meshes()
+        xs, ws, qs, Vs, ys = [], [], [], [], []
+        for m in meshes:
+            me = mesh_of(m)
+            x, w = me.sources()
+            Md = tt(m["M"])
+            ys.append(tt(m["nodes"]))
+            xs.append(x), ws.append(w), qs.append(me.charges(Md)), Vs.append(me.lumped_mass()[:, None] * Md)
+        toff = np.cumsum([0] + [len(y) for y in ys])
+        soff = np.cumsum([0] + [len(x) for x in xs])
+        Y, X, W, Q, V = (torch.cat(a) for a in (ys, xs, ws, qs, Vs))
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            B = fn.Batch([fn.auto_params(len(y), len(x), fn.FN_FP32_MIXED) for y, x in zip(ys, xs)])
+            B.set_geometry(toff, Y, soff, X, W)
+            phi = torch.empty(len(Y), dtype=torch.float64, device=dev)
+            H = torch.empty(len(Y), 2, dtype=torch.float64, device=dev)
+            u = torch.empty(len(X), dtype=torch.float64, device=dev)
+
+            def step():
+                B.set_charges(Q)
+                B.eval_with_H_adjoint(V, out_phi=phi, out_H=H, out_u=u)
+
+            step()
+            st.synchronize()
+            g = fn.Graph()
+            with g.capture(st):
+                step()
+            st.synchronize()
+            ms = _timed(torch, lambda: g.launch(st), args.steps, args.warmup) * 1e3
+        record("batch_c3", fn.FN_FP32_MIXED, ms, len(Y) + len(X),
+               {"workload": "64 meshes, 5k-200k nodes (disks, ellipses, annuli, rounded rectangles)",
+                "n_nodes": len(Y), "n_src": len(X), "lanes": 4, "graph": True, "params": "fn_params_auto per member"})
+    for rec in out_lines:
+        print(json.dumps(rec), flush=True)
+
+
+def _configs_vs_direct(d, phi, H, u, args):
+    """The step's outputs against the FP64 direct sum (O1) on the oracle's own FEM sources, at
+    up to --samples targets and sources, and the direct sum's own rate (CPU leg only)."""
+    from oracle import direct, fem
+    nodes, tris, bedges, M = d["nodes"], d["tris"], d["bedges"], d["M"]
+    x, w = fem.sources(nodes, tris, bedges)
+    q = fem.charges(nodes, tris, bedges, M)
+    V = fem.lumped_mass(nodes, tris)[:, None] * M
+    rng = np.random.default_rng(7)
+    it = np.sort(rng.choice(len(nodes), min(args.samples, len(nodes)), replace=False))
+    js = np.sort(rng.choice(len(x), min(args.samples, len(x)), replace=False))
+    a = time.perf_counter()
+    phi1, H1 = direct.forward(nodes[it], x, w, q)
+    t_f = time.perf_counter() - a
+    a = time.perf_counter()
+    u1 = direct.adjoint(nodes, x[js], w[js], V=V)
+    t_a = time.perf_counter() - a
+    rel = lambda g, r: float(np.linalg.norm(g - r) / np.linalg.norm(r))
+    err = {"phi": rel(phi.cpu().numpy()[it], phi1), "H": rel(H.cpu().numpy()[it], H1),
+           "HT": rel(u.cpu().numpy()[js], u1), "samples": f"{len(it)} nodes and {len(js)} sources"}
+    t_full = t_f * len(nodes) / len(it) + t_a * len(x) / len(js)
+    cpu = {"value": (len(nodes) + len(x)) / t_full, "unit": "points/s", "cores": direct.threads(), "kind": "oracle",
+           "sample": f"O1 direct FP64 sum on {len(it)} nodes and {len(js)} sources, extrapolated linearly"}
+    log(f"  vs O1: {err}")
+    return {"rel_l2_vs_fp64_oracle": err, "cpu_baseline": cpu}
 
 
 # ---------------------------------------------------------------------------- 3D path
