@@ -37,6 +37,14 @@
  *   - A context is not thread-safe; use one context per stream.
  *   - Every function returns FN_OK (0) or an FN_E_* code; fn_last_error()
  *     gives a message.  No C++ exception crosses this interface.
+ *   - Debug checks: with the environment variable FEMNFFT_DEBUG_CHECKS set to a
+ *     value other than "0" when fn_create / fn3_create runs, fn_set_geometry and
+ *     fn3_set_geometry validate every binned point set on the device (keys sorted
+ *     and inside the cell table, cell starts consistent with the keys, cell
+ *     fractions in [0, 1] in 2D, packed positions inside their key's cell in 3D,
+ *     the sort permutation a permutation) and return FN_E_DEVICE with the count of
+ *     violations in the message.  The checks wait for the stream; results are the
+ *     same bit for bit with and without them.
  */
 #ifndef FEMNFFT_H
 #define FEMNFFT_H

@@ -89,6 +89,7 @@ struct fn3_ctx {
     size_t ws_bytes = 0;
     bool plan_ready = false, geom_ready = false, charges_ready = false;
     uint64_t geom_gen = 0;  // successful fn3_set_geometry calls
+    bool debug_checks = false;  // FEMNFFT_DEBUG_CHECKS: validate the binning after fn3_set_geometry
     std::string err;
     // stage timing (fn3_set_profiling): event pairs recorded on the stream around each stage
     bool prof_on = false;
@@ -944,6 +945,49 @@ __global__ void k3_values(const double *__restrict__ in, const double *__restric
     for (int f = 0; f < nf; ++f) out[f * n + k] = (w ? w[k] : 1.0) * in[(int64_t)i * nf + f];
 }
 
+// Debug validation of one binned set (FEMNFFT_DEBUG_CHECKS): keys sorted and inside the cell
+// table, cell starts consistent with the keys, each packed position inside its key's cell
+// (closed: base cell + fraction may round up to the next integer),
+// perm a permutation of [0, n) (cnt: n counters, zeroed by the caller's k3_zero32)
+__global__ void k3_zero32(uint32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k3_check_bins(const uint32_t *__restrict__ key, const uint32_t *__restrict__ perm,
+                              const uint32_t *__restrict__ cstart, const double4 *__restrict__ pos, int64_t n,
+                              int ex, int ey, int64_t ncell, uint32_t *__restrict__ cnt, uint32_t *__restrict__ bad)
+{
+    uint32_t v = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t kk = key[k];
+        if ((int64_t)kk >= ncell) {
+            ++v;
+        } else {
+            if ((int64_t)cstart[kk] > k || (int64_t)cstart[kk + 1] <= k) ++v;
+            const double4 q = pos[k];
+            const int b0 = (int)(kk % (uint32_t)ex), b1 = (int)((kk / (uint32_t)ex) % (uint32_t)ey);
+            const int b2 = (int)(kk / ((uint32_t)ex * (uint32_t)ey));
+            // base cell + fraction may round up to the next integer: the cell's closed extent
+            if (!(q.x >= b0 && q.x <= b0 + 1 && q.y >= b1 && q.y <= b1 + 1 && q.z >= b2 && q.z <= b2 + 1)) ++v;
+        }
+        if (k + 1 < n && key[k + 1] < kk) ++v;
+        const uint32_t i = perm[k];
+        if ((int64_t)i >= n) ++v;
+        else atomicAdd(&cnt[i], 1u);
+    }
+    if (v) atomicAdd(bad, v);
+}
+
+__global__ void k3_check_perm(const uint32_t *__restrict__ cnt, int64_t n, uint32_t *__restrict__ bad)
+{
+    uint32_t v = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v += cnt[i] != 1u ? 1u : 0u;
+    if (v) atomicAdd(bad, v);
+}
+
 __global__ void k3_fill(double *p, int64_t n, double v)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1315,6 +1359,7 @@ int fn3_create(const fn_params *params, void *stream, fn3_ctx **out)
     if (!c) { g_err3 = "out of host memory"; return FN_E_NOMEM; }
     c->prm = p;
     c->stream = static_cast<hipStream_t>(stream);
+    c->debug_checks = fn::debug_checks_from_env();
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; g_err3 = "no HIP device"; return FN_E_DEVICE; }
     std::string err;
     if (!build_plan(p, c->plan, err)) { delete c; g_err3 = err; return FN_E_INVAL; }
@@ -1447,6 +1492,28 @@ int fn3_set_geometry(fn3_ctx *ctx, int64_t n_tgt, const double *tgt_xyz, int64_t
             F3_LAUNCH(c);
         }
         F3_HIP(c, fn::launch_cellstart(B.key[s], n, ncell, B.cstart[s], st));
+        if (c->debug_checks) {  // the sort's scratch keys serve as the permutation counters
+            uint32_t bad = 0;
+            uint32_t *dbad = reinterpret_cast<uint32_t *>(B.red + 1024);
+            const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + NT - 1) / NT));
+            k3_zero32<<<nb, NT, 0, st>>>(B.skey, n);
+            k3_zero32<<<1, 64, 0, st>>>(dbad, 1);
+            F3_LAUNCH(c);
+            if (n > 0) {
+                k3_check_bins<<<nb, NT, 0, st>>>(B.key[s], B.perm[s], B.cstart[s], B.pos[s], n, g.ext[0], g.ext[1],
+                                                  ncell, B.skey, dbad);
+                k3_check_perm<<<nb, NT, 0, st>>>(B.skey, n, dbad);
+                F3_LAUNCH(c);
+            }
+            F3_HIP(c, hipMemcpyAsync(&bad, dbad, sizeof(bad), hipMemcpyDeviceToHost, st));
+            F3_HIP(c, hipStreamSynchronize(st));
+            if (bad) {
+                char msg[160];
+                std::snprintf(msg, sizeof msg, "debug check: %u violations in the binning of point set %d "
+                              "(keys, cell starts, positions or permutation)", bad, s);
+                F3_ERR(c, FN_E_DEVICE, msg);
+            }
+        }
     }
     F3_HIP(c, hipStreamSynchronize(st));
     c->geom_ready = true;

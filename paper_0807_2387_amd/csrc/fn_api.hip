@@ -497,6 +497,7 @@ int fn_create(const fn_params *params, void *stream, fn_ctx **out)
     c->prm = *params;
     c->stream = static_cast<hipStream_t>(stream);
     c->cur = c->stream;
+    c->debug_checks = debug_checks_from_env();
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         g_create_err = "no HIP device";
@@ -738,6 +739,20 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
                                            P.G, B.fr32[s], B.fr64[s], s ? B.w + base : nullptr, c->stream));
         }
         FN_HIP(c, launch_cellstart(B.key[s], n, ncell, B.cstart[s], c->stream));
+        if (c->debug_checks) {  // the sort's scratch keys serve as the permutation counters
+            uint32_t bad = 0;
+            uint32_t *dbad = reinterpret_cast<uint32_t *>(B.red + RED_PART);
+            FN_HIP(c, launch_check_bins(B.key[s], B.perm[s], B.cstart[s], B.fr32[s], B.fr64[s], n, ncell, B.skey,
+                                        dbad, c->stream));
+            FN_HIP(c, hipMemcpyAsync(&bad, dbad, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+            FN_HIP(c, hipStreamSynchronize(c->stream));
+            if (bad) {
+                char msg[160];
+                std::snprintf(msg, sizeof msg, "debug check: %u violations in the binning of point set %d "
+                              "(keys, cell starts, fractions or permutation)", bad, s);
+                FN_SET_ERR(c, FN_E_DEVICE, msg);
+            }
+        }
     }
     FN_HIP(c, hipStreamSynchronize(c->stream));
     c->geom = g;

@@ -11,7 +11,10 @@
 // to the last bit of the fraction.
 #include "fn_internal.h"
 
+#include <algorithm>
 #include <cfloat>
+#include <cstdlib>
+#include <cstring>
 
 namespace fn {
 
@@ -253,6 +256,64 @@ hipError_t launch_finish_points(const double *xy, const double *w, int64_t n, co
     int nb = (int)((n + 255) / 256);
     k_finish_points<<<nb, 256, 0, st>>>(xy, w, n, perm, cx, cy, s, (double)G, fr32, fr64, wsorted);
     return hipGetLastError();
+}
+
+__global__ void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_check_bins(const uint32_t *__restrict__ key, const uint32_t *__restrict__ perm,
+                             const uint32_t *__restrict__ cstart, const float *__restrict__ fr32,
+                             const double *__restrict__ fr64, int64_t n, int64_t ncell, uint32_t *__restrict__ cnt,
+                             uint32_t *__restrict__ bad)
+{
+    uint32_t v = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t kk = key[k];
+        if ((int64_t)kk >= ncell) ++v;
+        else if ((int64_t)cstart[kk] > k || (int64_t)cstart[kk + 1] <= k) ++v;
+        if (k + 1 < n && key[k + 1] < kk) ++v;
+        for (int d = 0; d < 2; ++d) {
+            const double f = fr64[d * n + k];
+            const float g = fr32[d * n + k];
+            if (!(f >= 0.0 && f < 1.0)) ++v;
+            if (!(g >= 0.0f && g <= 1.0f)) ++v;
+        }
+        const uint32_t i = perm[k];
+        if ((int64_t)i >= n) ++v;
+        else atomicAdd(&cnt[i], 1u);
+    }
+    if (v) atomicAdd(bad, v);
+}
+
+__global__ void k_check_perm(const uint32_t *__restrict__ cnt, int64_t n, uint32_t *__restrict__ bad)
+{
+    uint32_t v = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v += cnt[i] != 1u ? 1u : 0u;
+    if (v) atomicAdd(bad, v);
+}
+
+hipError_t launch_check_bins(const uint32_t *key, const uint32_t *perm, const uint32_t *cstart, const float *fr32,
+                             const double *fr64, int64_t n, int64_t ncell, uint32_t *cnt, uint32_t *bad,
+                             hipStream_t st)
+{
+    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+    k_zero_u32<<<nb, 256, 0, st>>>(cnt, n);
+    k_zero_u32<<<1, 64, 0, st>>>(bad, 1);
+    if (n > 0) {
+        k_check_bins<<<nb, 256, 0, st>>>(key, perm, cstart, fr32, fr64, n, ncell, cnt, bad);
+        k_check_perm<<<nb, 256, 0, st>>>(cnt, n, bad);
+    }
+    return hipGetLastError();
+}
+
+bool debug_checks_from_env()
+{
+    const char *e = std::getenv("FEMNFFT_DEBUG_CHECKS");
+    return e && *e && std::strcmp(e, "0") != 0;
 }
 
 hipError_t launch_cellstart(const uint32_t *key, int64_t n, int64_t ncell, uint32_t *cstart,

@@ -175,6 +175,7 @@ struct fn_ctx {
     hipStream_t stream2 = nullptr;   // second stream of fn_eval_with_H_adjoint (created on first use)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
+    bool debug_checks = false;       // FEMNFFT_DEBUG_CHECKS: validate the binning after set_geometry
     void *ws = nullptr;
     size_t ws_bytes = 0;
     int64_t ws_nt = 0, ws_ns = 0;    // sizes the workspace was laid out for
@@ -236,6 +237,14 @@ hipError_t radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *va
 hipError_t launch_finish_points(const double *xy, const double *w, int64_t n, const uint32_t *perm,
                                 double cx, double cy, double s, int G, float *fr32, double *fr64,
                                 double *wsorted, hipStream_t st);
+// Debug validation of one binned point set (FEMNFFT_DEBUG_CHECKS): keys sorted and inside the
+// cell table, cell starts consistent with the keys, fractions in [0, 1], perm a permutation of
+// [0, n) (cnt: n scratch counters).  Adds the number of violations to *bad (zeroed here).
+hipError_t launch_check_bins(const uint32_t *key, const uint32_t *perm, const uint32_t *cstart, const float *fr32,
+                             const double *fr64, int64_t n, int64_t ncell, uint32_t *cnt, uint32_t *bad,
+                             hipStream_t st);
+// true when FEMNFFT_DEBUG_CHECKS is set to anything but "" or "0"
+bool debug_checks_from_env();
 hipError_t launch_cellstart(const uint32_t *key, int64_t n, int64_t ncell, uint32_t *cstart,
                             hipStream_t st);
 // plan
