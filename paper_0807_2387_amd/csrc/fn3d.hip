@@ -48,7 +48,7 @@ struct Plan3 {
     double eps_I = 0, eps_B = 0, kb_b = 0, i0mb = 0;
     double a[MAXP] = {0};
     std::vector<double> cB, psihat;
-    std::vector<double> twG, twn;  // [N][2] twiddles e^{-2 pi i k/N}
+    std::vector<double> twG, twn;  // pass-ordered twiddles of G- and n-point lines (staged_twiddles)
 };
 
 struct Geom3 {
@@ -159,15 +159,6 @@ static bool solve(std::vector<double> A, std::vector<double> b, int n, std::vect
     return true;
 }
 
-static void twiddles(int N, std::vector<double> &t)
-{
-    t.resize(2 * (size_t)N);
-    for (int k = 0; k < N; ++k) {
-        const long double a = -2.0L * (long double)PI * (long double)k / (long double)N;
-        t[2 * k] = (double)std::cos(a);
-        t[2 * k + 1] = (double)std::sin(a);
-    }
-}
 
 static bool build_plan(const fn_params &prm, Plan3 &P, std::string &err)
 {
@@ -219,8 +210,8 @@ static bool build_plan(const fn_params &prm, Plan3 &P, std::string &err)
         const double w = 2.0 * PI * l / P.G;
         P.psihat[l] = bessel_i0(P.m * std::sqrt(P.kb_b * P.kb_b - w * w)) / P.i0mb;
     }
-    twiddles(P.G, P.twG);
-    twiddles(P.n, P.twn);
+    fn::staged_twiddles(P.G, P.twG);  // pass-ordered tables of the G- and n-point lines
+    fn::staged_twiddles(P.n, P.twn);
     return true;
 }
 
@@ -457,7 +448,7 @@ __global__ void __launch_bounds__(512) k3_pass(double2 *__restrict__ a, int N, i
     }
     __syncthreads();
     const int li = threadIdx.x / NT, lt = threadIdx.x % NT;
-    fft_line(sh3 + (int64_t)li * LS, N, log2N, lt, NT, tw);
+    fft_line_st(sh3 + (int64_t)li * LS, N, log2N, lt, NT, tw);
     for (int t = threadIdx.x; t < PER * N; t += blockDim.x) {
         int l2, e;
         if (axis == 0) { l2 = t / N; e = t % N; }

@@ -40,6 +40,28 @@ void twiddles(int N, std::vector<double> &re, std::vector<double> &im)
     }
 }
 
+void staged_twiddles(int N, std::vector<double> &t)
+{
+    t.assign(2 * (size_t)std::max(N - 8, 1), 0.0);
+    int L = 1, rem = 0;
+    while ((1 << rem) < N) ++rem;
+    auto put = [&](int L, int rad) {
+        for (int r = 1; r < rad; ++r)
+            for (int k = 0; k < L; ++k) {
+                const size_t i = (size_t)(L - 8) + (size_t)(r - 1) * L + k;
+                const long double a = -2.0L * (long double)PI * (long double)r * k / ((long double)L * rad);
+                t[2 * i] = (double)std::cos(a);
+                t[2 * i + 1] = (double)std::sin(a);
+            }
+    };
+    while (rem >= 3) {
+        if (L > 1) put(L, 8);
+        L <<= 3;
+        rem -= 3;
+    }
+    if (rem >= 1 && L > 1) put(L, 1 << rem);
+}
+
 // r^q K^{(q)}(r) for K(r) = -(1/2pi) ln r.
 static double K_scaled_deriv(int q, double r)
 {
@@ -183,14 +205,13 @@ static bool build_host_plan(const fn_params &prm, Plan &P, std::string &err)
         }
     }
     {
-        std::vector<double> re, im;
-        twiddles(P.G, re, im);
+        std::vector<double> st, re, im;
+        staged_twiddles(P.G, st);
         if (P.precision == FN_FP64) {
-            P.twG64.resize(2 * (size_t)P.G);
-            for (int k = 0; k < P.G; ++k) P.twG64[2 * k] = re[k], P.twG64[2 * k + 1] = im[k];
+            P.twG64 = st;
         } else {
-            P.twG32.resize(2 * (size_t)P.G);
-            for (int k = 0; k < P.G; ++k) P.twG32[2 * k] = (float)re[k], P.twG32[2 * k + 1] = (float)im[k];
+            P.twG32.resize(st.size());
+            for (size_t k = 0; k < st.size(); ++k) P.twG32[k] = (float)st[k];
         }
         twiddles(P.n, re, im);
         P.twn.resize(2 * (size_t)P.n);

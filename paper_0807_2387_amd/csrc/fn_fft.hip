@@ -149,13 +149,23 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_fwd(const R *__rest
         ra = q < Ey ? grid + (int64_t)q * Ex : nullptr;
         rb = q < Ey ? grid + fstride + (int64_t)q * Ex : nullptr;
     }
-    for (int e = lt; e < G; e += NT) {
+    C v[FFT_EPT];
+#pragma unroll
+    for (int i = 0; i < FFT_EPT; ++i) {
+        const int e = lt + i * NT;
         R a = (ra && e < Ex) ? ra[e] : (R)0;
         R b = (rb && e < Ex) ? rb[e] : (R)0;
-        buf[lp(e)] = mk<C>(a, b);
+        v[i] = mk<C>(a, b);
+    }
+    fft_line_reg(v, buf, G, log2G, lt, NT, tw);
+    __syncthreads();  // the last pass's reads of buf are done
+    {
+        C *dst = buf + lp(opaque(lt));  // lp(lt + i NT) = lp(lt) + i lp(NT): NT is a multiple of 8
+        const int snt = lp(NT);
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) dst[i * snt] = v[i];
     }
     __syncthreads();
-    fft_line(buf, G, log2G, lt, NT, tw);
     C *sa = spec;
     C *sb = (nfield == 1) ? spec : spec + sfstride;
     for (int l = lt; l <= nh; l += NT) {
@@ -167,14 +177,19 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_fwd(const R *__rest
     }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(1024) k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
-                                               cplx<R> *__restrict__ out, int64_t ofstride, int64_t ldS,
-                                               int Ey, int mode, int nclass, int hy, int G, int log2G, int nh,
-                                               const R *__restrict__ W0, const R *__restrict__ W1,
-                                               const cplx<R> *__restrict__ tw)
+// Column pass: per l_x, the forward FFTs of the class columns, the multiply, and the
+// inverse FFTs of the outputs.  The columns enter and leave through registers (thread
+// lt holds y = lt + i NT), and so do the products between the forward and the inverse
+// transforms: fft_line_reg keeps exactly those positions in registers.
+template <typename R, int mode>
+__global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
+                                                             cplx<R> *__restrict__ out, int64_t ofstride,
+                                                             int64_t ldS, int Ey, int nclass, int hy,
+                                                             int G, int log2G, int nh, const R *__restrict__ W0,
+                                                             const R *__restrict__ W1, const cplx<R> *__restrict__ tw)
 {
     using C = cplx<R>;
+    static_assert(FFT_EPT == 8, "fft_line_reg works on radix-8 first passes");
     extern __shared__ char smem_c[];
     C *sh = reinterpret_cast<C *>(smem_c);
     const int NT = G / FFT_EPT, per = blockDim.x / NT;
@@ -188,18 +203,24 @@ __global__ void __launch_bounds__(1024) k_cols(const cplx<R> *__restrict__ spec,
         const R *W = k == 0 ? W0 : W1;
         return (valid && aly <= nh) ? W[(int64_t)qx * (nh + 1) + aly] : (R)0;
     };
-    C acc[FFT_EPT];
+    C acc[FFT_EPT], v[FFT_EPT];
     const int nin = mode == COL_FWD ? nclass : (mode == COL_ADJ_H ? 2 : 1);
+#pragma unroll 1
     for (int f = 0; f < nin; ++f) {
         const C *col = spec + f * sfstride + (int64_t)qx * ldS;
-        for (int e = lt; e < G; e += NT) buf[lp(e)] = (valid && e < Ey) ? col[e] : mk<C>((R)0, (R)0);
-        __syncthreads();
-        fft_line(buf, G, log2G, lt, NT, tw);
+        int lt_ = opaque(lt);  // per-element indices are recomputed here, not kept live
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
-            const int k = lt + i * NT;
+            const int e = lt_ + i * NT;
+            v[i] = (valid && e < Ey) ? col[e] : mk<C>((R)0, (R)0);
+        }
+        fft_line_reg(v, buf, G, log2G, lt, NT, tw);
+        lt_ = opaque(lt);
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int k = lt_ + i * NT;
             const int ly = k <= G / 2 ? k : k - G;
-            const C x = buf[lp(k)];
+            const C x = v[i];
             C t;
             if (mode == COL_FWD) {
                 const R w = wmul(f, ly < 0 ? -ly : ly);
@@ -213,33 +234,37 @@ __global__ void __launch_bounds__(1024) k_cols(const cplx<R> *__restrict__ spec,
             }
             acc[i] = (f == 0) ? t : cadd(acc[i], t);
         }
-        __syncthreads();
     }
     const int nout = mode == COL_FWD ? (hy ? 2 : 1) : nclass;
+#pragma unroll 1
     for (int o = 0; o < nout; ++o) {
+        int lt_ = opaque(lt);
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
-            const int k = lt + i * NT;
+            const int k = lt_ + i * NT;
             const int ly = k <= G / 2 ? k : k - G;
-            C v = acc[i];
+            C x = acc[i];
             if (mode == COL_FWD) {
-                if (o == 1) {  // (-2 pi i l_y) v
+                if (o == 1) {  // (-2 pi i l_y) x
                     const R l = (R)ly * twopi;
-                    v = mk<C>(l * v.y, -l * v.x);
+                    x = mk<C>(l * x.y, -l * x.x);
                 }
             } else {
                 const R w = wmul(o, ly < 0 ? -ly : ly);
-                v = mk<C>(w * v.x, w * v.y);
+                x = mk<C>(w * x.x, w * x.y);
             }
-            buf[lp(k)] = conjc(v);
+            v[i] = conjc(x);
         }
-        __syncthreads();
-        fft_line(buf, G, log2G, lt, NT, tw);
+        fft_line_reg(v, buf, G, log2G, lt, NT, tw);
+        lt_ = opaque(lt);
         if (valid) {
             C *dst = out + o * ofstride + (int64_t)qx * ldS;
-            for (int e = lt; e < Ey; e += NT) dst[e] = conjc(buf[lp(e)]);
+#pragma unroll
+            for (int i = 0; i < FFT_EPT; ++i) {
+                const int e = lt_ + i * NT;
+                if (e < Ey) dst[e] = conjc(v[i]);
+            }
         }
-        __syncthreads();
     }
 }
 
@@ -265,6 +290,7 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_inv(const cplx<R> *
     const int y0 = 2 * (xcd_block(blockIdx.x, gridDim.x) * per + li);  // T is read transposed
     C *buf = sh + (int64_t)li * lp(G);
     const R twopi = (R)6.283185307179586476925286766559;
+    C v[FFT_EPT];
     for (int pr = 0; pr < os.n; pr += 2) {
         const bool hasb = pr + 1 < os.n;
         const int ya = y0 + os.dr[pr], yb = hasb ? y0 + os.dr[pr + 1] : -1;
@@ -272,7 +298,10 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_inv(const cplx<R> *
         const C *ta = T + os.src[pr] * tfstride;
         const C *tb = hasb ? T + os.src[pr + 1] * tfstride : T;
         const int ma = os.mul[pr], mb = hasb ? os.mul[pr + 1] : 0;
-        for (int e = lt; e < G; e += NT) {
+        int lt_ = opaque(lt);  // per-element indices are recomputed per pair, not kept live
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int e = lt_ + i * NT;
             C A = mk<C>((R)0, (R)0), B = mk<C>((R)0, (R)0);
             int l = -1;
             bool cj = false;
@@ -294,18 +323,21 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_inv(const cplx<R> *
                 }
             }
             // z = A + i B, conjugated for the inverse-by-forward trick
-            buf[lp(e)] = mk<C>(A.x - B.y, -(A.y + B.x));
+            v[i] = mk<C>(A.x - B.y, -(A.y + B.x));
         }
-        __syncthreads();
-        fft_line(buf, G, log2G, lt, NT, tw);
+        fft_line_reg(v, buf, G, log2G, lt, NT, tw);
         R *ga = grid + os.dst[pr] * fstride + (int64_t)ya * Ex;
         R *gb = grid + (hasb ? os.dst[pr + 1] : 0) * fstride + (int64_t)(hasb ? yb : 0) * Ex;
-        for (int e = lt; e < Ex; e += NT) {
-            C z = buf[lp(e)];  // conj of the inverse transform: real part a, imag -b
-            if (va) ga[e] = z.x;
-            if (vb) gb[e] = -z.y;
+        lt_ = opaque(lt);
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const int e = lt_ + i * NT;
+            if (e < Ex) {
+                const C z = v[i];  // conj of the inverse transform: real part a, imag -b
+                if (va) ga[e] = z.x;
+                if (vb) gb[e] = -z.y;
+            }
         }
-        __syncthreads();
     }
 }
 
@@ -397,12 +429,13 @@ static hipError_t cols_t(int G, int nh, const void *spec, int64_t sfstride, void
 {
     const int NT = fft_nt(G), per = fft_per(G);
     const int nb = (nh + 1 + per - 1) / per;
-    hipError_t e = hipFuncSetAttribute((const void *)k_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    auto kern = mode == COL_FWD ? k_cols<R, COL_FWD> : (mode == COL_ADJ_H ? k_cols<R, COL_ADJ_H> : k_cols<R, COL_ADJ_PHI>);
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)fft_lds_bytes<R>(G));
     if (e != hipSuccess) return e;
-    k_cols<R><<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, sfstride, (cplx<R> *)out, ofstride,
-                                                          ldS, Ey, mode, nclass, hy, G, ilog2(G), nh,
-                                                          (const R *)W0, (const R *)W1, (const cplx<R> *)tw);
+    kern<<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, sfstride, (cplx<R> *)out, ofstride, ldS,
+                                                     Ey, nclass, hy, G, ilog2(G), nh, (const R *)W0, (const R *)W1,
+                                                     (const cplx<R> *)tw);
     return hipGetLastError();
 }
 

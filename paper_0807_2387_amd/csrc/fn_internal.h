@@ -73,10 +73,11 @@ struct Plan {
     int tile = 32;                   // spread / gather tile edge, cells (16 or 32)
     NearShape near_fwd{32, 8, 1024}; // near-field shape of the forward volume-class kernel
     NearShape near_adj{32, 8, 512};  // ... and of the adjoint one
-    // FFT twiddles e^{-2 pi i k/N} computed at fn_create: length G in the grid precision
-    // (float2 or double2 pairs as consecutive values) and length n in FP64 (plan transform)
-    std::vector<double> twG64;       // [G][2], FP64 path
-    std::vector<float> twG32;        // [G][2], FP32-mixed path
+    // FFT twiddles computed at fn_create: the grid passes' pass-ordered table of a G-point
+    // line in the grid precision (float2 or double2 pairs as consecutive values,
+    // staged_twiddles), and e^{-2 pi i k/n}, k < n, in FP64 (plan transform)
+    std::vector<double> twG64;       // [G - 8][2], FP64 path
+    std::vector<float> twG32;        // [G - 8][2], FP32-mixed path
     std::vector<double> twn;         // [n][2]
 };
 
@@ -115,7 +116,7 @@ struct Buffers {
     // plan
     void *W = nullptr;               // multiplier table [(n/2+1) x (n/2+1)], R
     void *W2 = nullptr;              // the same for the kernel regularized at eps_S
-    void *tw = nullptr;              // FFT twiddles e^{-2 pi i k/G}, k < G, cplx<R>
+    void *tw = nullptr;              // grid-pass twiddles (staged_twiddles(G)), cplx<R>
     double2 *tw64 = nullptr;         // FP64 twiddles for the plan FFT (length n)
     // geometry, per point set (see set_size), each sorted by cell; perm[s] holds indices
     // relative to the set's first point
@@ -333,5 +334,8 @@ hipError_t launch_coincident_count(const Geom &g, const Buffers &b, int in_set, 
 // host helpers
 double bessel_i0(double x);
 void twiddles(int N, std::vector<double> &re, std::vector<double> &im);
+// Pass-ordered twiddles of an N-point line (N a power of two, N >= 8), interleaved
+// (re, im), max(N - 8, 1) entries: the layout fftd::fft_line_st reads.
+void staged_twiddles(int N, std::vector<double> &t);
 
 }  // namespace fn
