@@ -271,9 +271,11 @@ static Layout make_layout(const Plan &P, int64_t nt, int64_t ns)
         L.off_fr32[s] = take(N[s] * 8);
         L.off_fr64[s] = take(N[s] * 16);
         L.off_cstart[s] = take((size_t)(ncell + 1) * 4);
+        L.off_csub[s] = take((size_t)(ncell * NEAR_SUB + 1) * 4);
     }
     // the surface sources share the per-point source arrays, not the cell starts
     L.off_cstart[2] = P.eps_S > 0.0 ? take((size_t)(ncell + 1) * 4) : L.off_cstart[1];
+    L.off_csub[2] = P.eps_S > 0.0 ? take((size_t)(ncell * NEAR_SUB + 1) * 4) : L.off_csub[1];
     L.off_w = take(N[1] * 8);
     L.off_val = take(N[1] * rs);
     L.off_val64 = take(N[1] * 8);
@@ -321,8 +323,10 @@ static void bind_buffers(fn_ctx *c)
         B.fr32[s] = reinterpret_cast<float *>(b + L.off_fr32[s]);
         B.fr64[s] = reinterpret_cast<double *>(b + L.off_fr64[s]);
         B.cstart[s] = reinterpret_cast<uint32_t *>(b + L.off_cstart[s]);
+        B.csub[s] = reinterpret_cast<uint32_t *>(b + L.off_csub[s]);
     }
     B.cstart[2] = reinterpret_cast<uint32_t *>(b + L.off_cstart[2]);
+    B.csub[2] = reinterpret_cast<uint32_t *>(b + L.off_csub[2]);
     B.key[2] = B.key[1];
     B.perm[2] = B.perm[1];
     B.fr32[2] = B.fr32[1];
@@ -745,7 +749,7 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
     g.rnear_s = P.eps_S > 0.0 ? (int)std::ceil(P.eps_S * P.G) : 0;
     const int64_t ncell = (int64_t)g.ext[0] * g.ext[1];
     int keybits = 1;
-    while (((int64_t)1 << keybits) < ncell) ++keybits;
+    while (((int64_t)1 << keybits) < ncell * NEAR_SUB) ++keybits;
     Buffers &B = c->buf;
     bind_source_sets(c, n_src, g.nsurf);
     const int nsets = g.nsurf > 0 ? 3 : 2;
@@ -759,7 +763,7 @@ static int set_geometry_impl(fn_ctx *c, int64_t n_tgt, const double *tgt_xy, int
             FN_HIP(c, launch_finish_points(xy, s ? src_w + base : nullptr, n, B.perm[s], g.c[0], g.c[1], g.s,
                                            P.G, B.fr32[s], B.fr64[s], s ? B.w + base : nullptr, c->stream));
         }
-        FN_HIP(c, launch_cellstart(B.key[s], n, ncell, B.cstart[s], c->stream));
+        FN_HIP(c, launch_cellstart_sub(B.key[s], n, ncell, B.cstart[s], B.csub[s], c->stream));
         if (c->debug_checks) {  // the sort's scratch keys serve as the permutation counters
             uint32_t bad = 0;
             uint32_t *dbad = reinterpret_cast<uint32_t *>(B.red + RED_PART);

@@ -75,7 +75,10 @@ __global__ void k_prepare(const double *__restrict__ xy, int64_t n, double cx, d
     // the window is sized with a margin; clamping only guards against a rounding slip
     bx = min(max(bx, 0), extx - 2 * m);
     by = min(max(by, 0), exty - 2 * m);
-    key[i] = (uint32_t)by * (uint32_t)extx + (uint32_t)bx;
+    // x slice of the cell: the in-cell fraction vx - floor(vx) (k_finish_points forms it the
+    // same way) times NEAR_SUB, exact for a power of two
+    const int sub = min((int)((vx - floor(vx)) * NEAR_SUB), NEAR_SUB - 1);
+    key[i] = ((uint32_t)by * (uint32_t)extx + (uint32_t)bx) * NEAR_SUB + (uint32_t)sub;
     idx[i] = (uint32_t)i;
 }
 
@@ -110,6 +113,28 @@ __global__ void k_cellstart(const uint32_t *__restrict__ key, int64_t n, int64_t
         if ((int64_t)key[mid] < c) lo = mid + 1; else hi = mid;
     }
     cstart[c] = (uint32_t)lo;
+}
+
+// csub[f] = first sorted index whose slice key >= f, for f in [0, ncell NEAR_SUB], and
+// cstart[c] = csub[c NEAR_SUB]
+__global__ void k_cellstart_sub(const uint32_t *__restrict__ key, int64_t n, int64_t nsub,
+                                uint32_t *__restrict__ cstart, uint32_t *__restrict__ csub)
+{
+    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f > nsub) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)key[mid] < f) lo = mid + 1; else hi = mid;
+    }
+    csub[f] = (uint32_t)lo;
+    if ((f & (NEAR_SUB - 1)) == 0) cstart[f >> NEAR_SUB_LOG2] = (uint32_t)lo;
+}
+
+__global__ void k_key_to_cell(uint32_t *__restrict__ key, int64_t n)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) key[i] >>= NEAR_SUB_LOG2;
 }
 
 // ---------------- stable LSD radix sort, 8-bit digits ----------------
@@ -321,6 +346,15 @@ hipError_t launch_cellstart(const uint32_t *key, int64_t n, int64_t ncell, uint3
 {
     int nb = (int)((ncell + 1 + 255) / 256);
     k_cellstart<<<nb, 256, 0, st>>>(key, n, ncell, cstart);
+    return hipGetLastError();
+}
+
+hipError_t launch_cellstart_sub(uint32_t *key, int64_t n, int64_t ncell, uint32_t *cstart, uint32_t *csub,
+                                hipStream_t st)
+{
+    const int64_t nsub = ncell * NEAR_SUB;
+    k_cellstart_sub<<<(int)((nsub + 1 + 255) / 256), 256, 0, st>>>(key, n, nsub, cstart, csub);
+    if (n > 0) k_key_to_cell<<<(int)((n + 255) / 256), 256, 0, st>>>(key, n);
     return hipGetLastError();
 }
 

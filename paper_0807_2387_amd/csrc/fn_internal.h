@@ -18,6 +18,10 @@ constexpr int MAXM = 8;         // largest window half-width
 constexpr int MAXP = 12;        // largest regularization degree
 constexpr int FFT_EPT = 8;      // complex elements held per thread in the LDS FFT
 constexpr int MAXG = 8192;      // largest FFT grid
+// Points are sorted by cell and, inside a cell, by which of NEAR_SUB equal x slices of it
+// they lie in; the near field cuts each row's candidates at those slice starts.
+constexpr int NEAR_SUB_LOG2 = 2;
+constexpr int NEAR_SUB = 1 << NEAR_SUB_LOG2;
 
 // Workgroups are handed to the 8 XCDs round-robin (block b to XCD b % 8), and
 // each XCD has its own L2.  xcd_block maps the i-th block of XCD x to logical
@@ -125,6 +129,7 @@ struct Buffers {
     float *fr32[3] = {nullptr, nullptr, nullptr};   // [2][N] in-cell fractions, FP32
     double *fr64[3] = {nullptr, nullptr, nullptr};  // [2][N] in-cell fractions, FP64
     uint32_t *cstart[3] = {nullptr, nullptr, nullptr}; // [ncell + 1]
+    uint32_t *csub[3] = {nullptr, nullptr, nullptr};   // [ncell NEAR_SUB + 1] starts of the x slices
     double *w = nullptr;             // source weights, sorted (set 1, then set 2)
     // per-evaluation data
     void *val = nullptr;             // charges s_j = w_j q_j, R, sorted sources (set 1, then set 2)
@@ -151,7 +156,7 @@ struct Buffers {
 struct Layout {
     size_t total = 0;
     size_t off_W, off_W2, off_tw, off_tw64;
-    size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_cstart[3];
+    size_t off_key[2], off_perm[2], off_fr32[2], off_fr64[2], off_cstart[3], off_csub[3];
     size_t off_w, off_val, off_val64, off_aval, off_aval64, off_ptile, off_grid, off_spec, off_spec2, off_far, off_red;
     size_t off_blk_fs, off_blk_as;
     size_t off_grid_a, off_spec_a, off_spec2_a, off_ptile_a, off_far_a;
@@ -248,6 +253,10 @@ hipError_t launch_check_bins(const uint32_t *key, const uint32_t *perm, const ui
 bool debug_checks_from_env();
 hipError_t launch_cellstart(const uint32_t *key, int64_t n, int64_t ncell, uint32_t *cstart,
                             hipStream_t st);
+// 2D binning: key holds cell * NEAR_SUB + x slice, sorted; writes the cell starts cstart
+// [ncell + 1] and the slice starts csub [ncell NEAR_SUB + 1], then turns key into cell keys.
+hipError_t launch_cellstart_sub(uint32_t *key, int64_t n, int64_t ncell, uint32_t *cstart, uint32_t *csub,
+                                hipStream_t st);
 // plan
 hipError_t launch_kr_samples(double2 *a, int n, const double *coef, int p, double eps_I, double eps_B,
                              const double *cB, int ncB, hipStream_t st);

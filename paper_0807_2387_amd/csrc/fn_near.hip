@@ -75,6 +75,7 @@ struct NearSets {
     const uint32_t *key_in;
     const double *f_in;           // [2][n_in] in-cell fractions
     const uint32_t *cs_in;
+    const uint32_t *csub_in;      // starts of the cells' NEAR_SUB x slices [ncell NEAR_SUB + 1]
     const double *pay;            // fwd: s [n_in]; adj H: V [2][n_in]; adj phi: v [n_in]
     int Ex, Ey, nbx;
     int bx, by;                   // home block shape, cells
@@ -327,18 +328,19 @@ __global__ void __launch_bounds__(NTH) k_near(NearSets S, NearArgs na, const dou
             const int ylo = max(r_first, hcy - R), yhi = min(r_last, hcy + R);
             const double hx = (double)hcx + px;
             const double hxs = hx * na.inv_eg, hys = ((double)hcy + py) * na.inv_eg;
-            // raw cell-start bounds of the columns of row r whose cells can hold a point within
-            // eps_I: from the vertical gap between the home point and row r (padded against
-            // rounding); an empty range where the gap alone exceeds eps_I
+            // raw bounds of the points of row r that can lie within eps_I: the x slices
+            // (NEAR_SUB per cell, the sort's second key) meeting [hx - w, hx + w], w from the
+            // vertical gap between the home point and row r (padded against rounding); an
+            // empty range where the gap alone exceeds eps_I
             auto bounds = [&](int r, uint32_t &blo, uint32_t &bhi) {
                 const double gap = r < hcy ? (double)(hcy - r - 1) + py : (r > hcy ? (double)(r - hcy) - py : 0.0);
                 const double h2 = e2 - gap * gap;
                 const double w = (double)__builtin_amdgcn_sqrtf((float)fmax(h2, 0.0)) + 1e-3;  // hardware sqrt, ~1 ulp: far inside the margin
-                const int c0c = max((int)floor(hx - w), 0) + ix0;
-                const int c1c = h2 > 0.0 ? min((int)floor(hx + w), ix1 - ix0 - 1) + ix0 : c0c - 1;
-                const int64_t rb = (int64_t)(iy0 + r) * Ex;
-                blo = S.cs_in[rb + c0c];
-                bhi = S.cs_in[rb + c1c + 1];
+                const int f0 = max((int)floor((hx - w) * NEAR_SUB), 0);
+                const int f1 = h2 > 0.0 ? min((int)floor((hx + w) * NEAR_SUB), (ix1 - ix0) * NEAR_SUB - 1) : f0 - 1;
+                const int64_t rb = ((int64_t)(iy0 + r) * Ex + ix0) * NEAR_SUB;
+                blo = S.csub_in[rb + f0];
+                bhi = S.csub_in[rb + f1 + 1];
             };
             uint32_t nlo = 0, nhi = 0;
             if (ylo <= yhi) bounds(ylo, nlo, nhi);
@@ -510,6 +512,7 @@ NearSets make_sets(const Geom &g, const Buffers &b, int out_set, int in_set, con
     S.key_in = b.key[in_set];
     S.f_in = b.fr64[in_set];
     S.cs_in = b.cstart[in_set];
+    S.csub_in = b.csub[in_set];
     S.pay = out_set ? b.aval64 : b.val64 + set_base(g, in_set);
     S.Ex = g.ext[0];
     S.Ey = g.ext[1];
