@@ -268,6 +268,11 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_cols(const cplx<R> *__re
     }
 }
 
+// Two consecutive complex values, loaded with one instruction.
+template <typename C> struct alignas(2 * sizeof(C)) cpair {
+    C a, b;
+};
+
 // Inverse row pass.  Requested real outputs are paired into complex inverse FFTs.
 // Output list entries: src (0 = T_phi/T, 1 = T_Hy), mul (0 none, 1 = -2 pi i l_x),
 // dst field (0 phi, 1 Hx, 2 Hy), row offset (0 or 1).
@@ -298,6 +303,9 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_inv(const cplx<R> *
         const C *ta = T + os.src[pr] * tfstride;
         const C *tb = hasb ? T + os.src[pr + 1] * tfstride : T;
         const int ma = os.mul[pr], mb = hasb ? os.mul[pr + 1] : 0;
+        // rows ya and yb = ya + 1 of one spectrum sit side by side in T (y fastest, ya even,
+        // ldS a multiple of 64): one two-element load per l instead of two
+        const bool adj = vb && os.src[pr + 1] == os.src[pr] && yb == ya + 1;
         int lt_ = opaque(lt);  // per-element indices are recomputed per pair, not kept live
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
@@ -309,14 +317,20 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_inv(const cplx<R> *
             else if (e >= G - nh) { l = G - e; cj = true; }
             if (l >= 0) {
                 const R mlt = (R)l * twopi;
+                if (adj) {
+                    const cpair<C> t2 = *reinterpret_cast<const cpair<C> *>(ta + (int64_t)l * ldS + ya);
+                    A = t2.a;
+                    B = t2.b;
+                } else {
+                    if (va) A = ta[(int64_t)l * ldS + ya];
+                    if (vb) B = tb[(int64_t)l * ldS + yb];
+                }
                 if (va) {
-                    A = ta[(int64_t)l * ldS + ya];
                     if (ma) A = mk<C>(mlt * A.y, -mlt * A.x);
                     if (l == 0) A.y = (R)0;
                     if (cj) A = conjc(A);
                 }
                 if (vb) {
-                    B = tb[(int64_t)l * ldS + yb];
                     if (mb) B = mk<C>(mlt * B.y, -mlt * B.x);
                     if (l == 0) B.y = (R)0;
                     if (cj) B = conjc(B);
