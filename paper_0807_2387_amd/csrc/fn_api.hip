@@ -903,8 +903,8 @@ static int eval_impl(fn_ctx *c, double *phi, double *H, hipStream_t st)
     if (ncls == 2) FN_STAGE(c, FN_ST_SPREAD, launch_spread(prec, P, g, 2, B, val_s, 1, B.ptile + tfield, st));
     FN_STAGE(c, FN_ST_FOLD, launch_fold(prec, g, P.m, P.tile, B.ptile, ncls, B.grid, fstride, st));
     FN_STAGE(c, FN_ST_ROWS_FWD, launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], ncls, B.spec,
-                                                ldS, sfstride, B.tw, st));
-    FN_STAGE(c, FN_ST_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1], COL_FWD,
+                                                ldS, B.tw, st));
+    FN_STAGE(c, FN_ST_COLS, launch_cols(prec, P.G, nh, B.spec, B.spec2, sfstride, ldS, g.ext[1], COL_FWD,
                                         ncls, want_h, B.W, B.W2, B.tw, st));
     FN_STAGE(c, FN_ST_ROWS_INV, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0],
                                                 g.ext[1], 1, want_phi, want_h, 1, B.tw, st));
@@ -980,8 +980,8 @@ static int adjoint_impl(fn_ctx *c, const double *in, double *u, int kind, hipStr
     FN_STAGE(c, FN_ST_A_SPREAD, launch_spread(prec, P, g, 0, B, B.aval, nf, B.ptile, st));
     FN_STAGE(c, FN_ST_A_FOLD, launch_fold(prec, g, P.m, P.tile, B.ptile, nf, B.grid, fstride, st));
     FN_STAGE(c, FN_ST_A_ROWS_FWD,
-             launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], nf, B.spec, ldS, sfstride, B.tw, st));
-    FN_STAGE(c, FN_ST_A_COLS, launch_cols(prec, P.G, nh, B.spec, sfstride, B.spec2, sfstride, ldS, g.ext[1],
+             launch_rows_fwd(prec, P.G, nh, B.grid, fstride, g.ext[0], g.ext[1], nf, B.spec, ldS, B.tw, st));
+    FN_STAGE(c, FN_ST_A_COLS, launch_cols(prec, P.G, nh, B.spec, B.spec2, sfstride, ldS, g.ext[1],
                                           kind == 0 ? COL_ADJ_H : COL_ADJ_PHI, ncls, 0, B.W, B.W2, B.tw, st));
     FN_STAGE(c, FN_ST_A_ROWS_INV, launch_rows_inv(prec, P.G, nh, B.spec2, sfstride, ldS, B.grid, fstride, g.ext[0],
                                                   g.ext[1], 0, 1, 0, ncls, B.tw, st));

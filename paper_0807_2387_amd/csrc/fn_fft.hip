@@ -15,7 +15,8 @@
 // transforms and the window can be treated as starting at index 0.
 //
 //   rows_fwd  : real rows -> R2C (two real lines packed in one complex FFT),
-//               keep l_x in [0, n/2]; writes S[f][l_x][y] (y contiguous)
+//               keep l_x in [0, n/2]; writes S[l_x][y] (y contiguous), with two
+//               fields interleaved as S[l_x][y][f]
 //   cols      : per l_x: FFT over y (zero-padded to G), multiply by the table
 //               W(|l_x|,|l_y|) = omega b_l / (psi^(l_x/G) psi^(l_y/G))^2 on
 //               |l_y| <= n/2 (zero elsewhere) and by -2 pi i l_y for H_y (or
@@ -118,6 +119,11 @@ __global__ void k_make_W(const double2 *__restrict__ bl, int n, const double *__
 
 // ---------------------------------------------------------------- grid passes
 
+// Two consecutive complex values, moved with one instruction.
+template <typename C> struct alignas(2 * sizeof(C)) cpair {
+    C a, b;
+};
+
 // FP32 row passes: two 1024-thread blocks (72 KB of LDS each) fit a CU when a
 // thread holds at most 64 registers, which they do without spilling; the FP64
 // line (147 KB) leaves room for one block only, so its registers are not capped.
@@ -126,7 +132,7 @@ __global__ void k_make_W(const double2 *__restrict__ bl, int n, const double *__
 template <typename R>
 __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_fwd(const R *__restrict__ grid, int64_t fstride, int Ex, int Ey,
                                                   int nfield, cplx<R> *__restrict__ spec, int64_t ldS,
-                                                  int64_t sfstride, int G, int log2G, int nh,
+                                                  int G, int log2G, int nh,
                                                   const cplx<R> *__restrict__ tw)
 {
     using C = cplx<R>;
@@ -166,14 +172,20 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_fwd(const R *__rest
         for (int i = 0; i < FFT_EPT; ++i) dst[i * snt] = v[i];
     }
     __syncthreads();
-    C *sa = spec;
-    C *sb = (nfield == 1) ? spec : spec + sfstride;
+    // the transposed stores: with one field, rows 2q and 2q + 1 are neighbours in the
+    // spectrum; with two, the fields are interleaved (spec[(l ldS + y) 2 + field]), so
+    // either way a lane stores its two values with one 2-element store
     for (int l = lt; l <= nh; l += NT) {
         C z = buf[lp(l)], zc = conjc(buf[lp((G - l) & (G - 1))]);
         C A = mk<C>((R)0.5 * (z.x + zc.x), (R)0.5 * (z.y + zc.y));
         C B = mk<C>((R)0.5 * (z.y - zc.y), (R)-0.5 * (z.x - zc.x));
-        if (ra) sa[(int64_t)l * ldS + ya] = A;
-        if (rb) sb[(int64_t)l * ldS + yb] = B;
+        if (nfield == 2) {
+            if (ra) *reinterpret_cast<cpair<C> *>(spec + 2 * ((int64_t)l * ldS + ya)) = cpair<C>{A, B};
+        } else if (rb) {
+            *reinterpret_cast<cpair<C> *>(spec + (int64_t)l * ldS + ya) = cpair<C>{A, B};
+        } else if (ra) {
+            spec[(int64_t)l * ldS + ya] = A;
+        }
     }
 }
 
@@ -182,7 +194,7 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_rows_fwd(const R *__rest
 // lt holds y = lt + i NT), and so do the products between the forward and the inverse
 // transforms: fft_line_reg keeps exactly those positions in registers.
 template <typename R, int mode>
-__global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_cols(const cplx<R> *__restrict__ spec, int64_t sfstride,
+__global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_cols(const cplx<R> *__restrict__ spec,
                                                              cplx<R> *__restrict__ out, int64_t ofstride,
                                                              int64_t ldS, int Ey, int nclass, int hy,
                                                              int G, int log2G, int nh, const R *__restrict__ W0,
@@ -205,14 +217,17 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_cols(const cplx<R> *__re
     };
     C acc[FFT_EPT], v[FFT_EPT];
     const int nin = mode == COL_FWD ? nclass : (mode == COL_ADJ_H ? 2 : 1);
+    // two input fields come interleaved from the row pass: element y of field f at
+    // spec[(qx ldS + y) 2 + f]
+    const int is = nin == 2 ? 2 : 1;
 #pragma unroll 1
     for (int f = 0; f < nin; ++f) {
-        const C *col = spec + f * sfstride + (int64_t)qx * ldS;
+        const C *col = spec + f + (int64_t)is * qx * ldS;
         int lt_ = opaque(lt);  // per-element indices are recomputed here, not kept live
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
             const int e = lt_ + i * NT;
-            v[i] = (valid && e < Ey) ? col[e] : mk<C>((R)0, (R)0);
+            v[i] = (valid && e < Ey) ? col[is * e] : mk<C>((R)0, (R)0);
         }
         fft_line_reg(v, buf, G, log2G, lt, NT, tw);
         lt_ = opaque(lt);
@@ -267,11 +282,6 @@ __global__ void __launch_bounds__(1024) FN_ROWS_WAVES k_cols(const cplx<R> *__re
         }
     }
 }
-
-// Two consecutive complex values, loaded with one instruction.
-template <typename C> struct alignas(2 * sizeof(C)) cpair {
-    C a, b;
-};
 
 // Inverse row pass.  Requested real outputs are paired into complex inverse FFTs.
 // Output list entries: src (0 = T_phi/T, 1 = T_Hy), mul (0 none, 1 = -2 pi i l_x),
@@ -413,7 +423,7 @@ static size_t fft_lds_bytes(int G)
 
 template <typename R>
 static hipError_t rows_fwd_t(int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey, int nfield,
-                             void *spec, int64_t ldS, int64_t sfstride, const void *tw, hipStream_t st)
+                             void *spec, int64_t ldS, const void *tw, hipStream_t st)
 {
     const int NT = fft_nt(G), per = fft_per(G);
     const int lines = (nfield == 1) ? (Ey + 1) / 2 : Ey;
@@ -422,22 +432,22 @@ static hipError_t rows_fwd_t(int G, int nh, const void *grid, int64_t fstride, i
                                        (int)fft_lds_bytes<R>(G));
     if (e != hipSuccess) return e;
     k_rows_fwd<R><<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const R *)grid, fstride, Ex, Ey, nfield,
-                                                       (cplx<R> *)spec, ldS, sfstride, G, ilog2(G), nh,
+                                                       (cplx<R> *)spec, ldS, G, ilog2(G), nh,
                                                        (const cplx<R> *)tw);
     return hipGetLastError();
 }
 
 hipError_t launch_rows_fwd(int precision, int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey,
-                           int nfield, void *spec, int64_t ldS, int64_t sfstride, const void *tw,
+                           int nfield, void *spec, int64_t ldS, const void *tw,
                            hipStream_t st)
 {
     if (precision == FN_FP64)
-        return rows_fwd_t<double>(G, nh, grid, fstride, Ex, Ey, nfield, spec, ldS, sfstride, tw, st);
-    return rows_fwd_t<float>(G, nh, grid, fstride, Ex, Ey, nfield, spec, ldS, sfstride, tw, st);
+        return rows_fwd_t<double>(G, nh, grid, fstride, Ex, Ey, nfield, spec, ldS, tw, st);
+    return rows_fwd_t<float>(G, nh, grid, fstride, Ex, Ey, nfield, spec, ldS, tw, st);
 }
 
 template <typename R>
-static hipError_t cols_t(int G, int nh, const void *spec, int64_t sfstride, void *out, int64_t ofstride,
+static hipError_t cols_t(int G, int nh, const void *spec, void *out, int64_t ofstride,
                          int64_t ldS, int Ey, int mode, int nclass, int hy, const void *W0, const void *W1,
                          const void *tw, hipStream_t st)
 {
@@ -447,13 +457,13 @@ static hipError_t cols_t(int G, int nh, const void *spec, int64_t sfstride, void
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)fft_lds_bytes<R>(G));
     if (e != hipSuccess) return e;
-    kern<<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, sfstride, (cplx<R> *)out, ofstride, ldS,
+    kern<<<nb, NT * per, fft_lds_bytes<R>(G), st>>>((const cplx<R> *)spec, (cplx<R> *)out, ofstride, ldS,
                                                      Ey, nclass, hy, G, ilog2(G), nh, (const R *)W0, (const R *)W1,
                                                      (const cplx<R> *)tw);
     return hipGetLastError();
 }
 
-hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t sfstride, void *out,
+hipError_t launch_cols(int precision, int G, int nh, const void *spec, void *out,
                        int64_t ofstride, int64_t ldS, int Ey, int mode, int nclass, int hy, const void *W0,
                        const void *W1, const void *tw, hipStream_t st)
 {
@@ -461,8 +471,8 @@ hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t s
     if (nclass < 1 || nclass > 2 || !W0 || (nclass == 2 && !W1)) return hipErrorInvalidValue;
     if (mode != COL_FWD && mode != COL_ADJ_PHI && mode != COL_ADJ_H) return hipErrorInvalidValue;
     if (precision == FN_FP64)
-        return cols_t<double>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, nclass, hy, W0, W1, tw, st);
-    return cols_t<float>(G, nh, spec, sfstride, out, ofstride, ldS, Ey, mode, nclass, hy, W0, W1, tw, st);
+        return cols_t<double>(G, nh, spec, out, ofstride, ldS, Ey, mode, nclass, hy, W0, W1, tw, st);
+    return cols_t<float>(G, nh, spec, out, ofstride, ldS, Ey, mode, nclass, hy, W0, W1, tw, st);
 }
 
 template <typename R>

@@ -287,11 +287,14 @@ hipError_t launch_gather(int precision, const Plan &P, const Geom &g, int set, c
 //   COL_ADJ_PHI input x: outputs W_k x, k < nclass
 //   COL_ADJ_H   inputs x_0, x_1 (the two components): acc = sum_d 2 pi i l_d x_d;
 //               outputs W_k acc, k < nclass
+// The row pass writes the spectrum as spec[l_x][y] (ldS apart), or, with two fields,
+// interleaved as spec[l_x][y][field]; the column pass reads it the same way (two inputs
+// are always two interleaved fields) and writes its outputs ofstride apart.
 enum ColMode { COL_FWD = 0, COL_ADJ_PHI = 1, COL_ADJ_H = 2 };
 hipError_t launch_rows_fwd(int precision, int G, int nh, const void *grid, int64_t fstride, int Ex, int Ey,
-                           int nfield, void *spec, int64_t ldS, int64_t sfstride, const void *tw,
+                           int nfield, void *spec, int64_t ldS, const void *tw,
                            hipStream_t st);
-hipError_t launch_cols(int precision, int G, int nh, const void *spec, int64_t sfstride, void *out,
+hipError_t launch_cols(int precision, int G, int nh, const void *spec, void *out,
                        int64_t ofstride, int64_t ldS, int Ey, int mode, int nclass, int hy, const void *W0,
                        const void *W1, const void *tw, hipStream_t st);
 // fwd: phi / H grids from T_phi (and T_Hy); adjoint: nout real grids from nout spectra
