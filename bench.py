@@ -77,7 +77,7 @@ def parse():
                          "of 64 meshes, an annulus of 1M nodes), each through the GPU FEM front")
     ap.add_argument("--K", type=int, default=64, help="ball3d: lattice cells across the ball")
     ap.add_argument("--grid3", type=int, default=256)
-    ap.add_argument("--m3", type=int, default=6)
+    ap.add_argument("--m3", type=int, default=4)
     ap.add_argument("--p3", type=int, default=6)
     ap.add_argument("--c3", type=float, default=5.0, help="ball3d: eps_I = c3 / (grid3/2)")
     return ap.parse_args()
