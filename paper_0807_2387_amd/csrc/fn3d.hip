@@ -680,7 +680,9 @@ struct Near3 {
 // eps_I of the home block form, per (z, y) row, one run of cells, hence one contiguous run
 // of sorted points; the runs are concatenated (block prefix sum) and the block's threads
 // take the candidates of the concatenation one each (coalesced loads), each against the
-// home points of the block, KC at a time (positions in registers), with per-home-point
+// home points of the block, KC at a time (positions in registers; 4 in the forward kernel,
+// whose four sums per home point would otherwise hold it to 3 waves per SIMD, 8 in the
+// adjoint, which has one sum and gains more from reusing each candidate), with per-home-point
 // partial sums in registers.  The partial sums are added over the block in a fixed order
 // (wave butterflies, then the waves in order), so the result does not depend on timing.
 // Positions are in grid units relative to the data window: base cell + in-cell fraction.
@@ -690,7 +692,7 @@ struct Near3 {
 // adjoint (home = sources, input = targets with payload V) adds -(1/(4 pi r^3) + cD D(x)) V.d.
 // 1/r: hardware reciprocal square root estimate and two Newton steps.
 constexpr int NB = 256;
-constexpr int KC = 8;
+constexpr int KC_FWD = 4, KC_ADJ = 8;
 
 __device__ __forceinline__ double rsqrt64(double x)
 {
@@ -729,6 +731,7 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
 {
     extern __shared__ uint32_t nsh[];
     constexpr int NV = ADJ ? 1 : 4;
+    constexpr int KC = ADJ ? KC_ADJ : KC_FWD;
     const int ex = mp.ext[0], ey = mp.ext[1];
     const int M2 = 2 * mp.m;
     const int nbx = ex - M2 + 1, nby = ey - M2 + 1, nbz = mp.ext[2] - M2 + 1;
@@ -923,7 +926,7 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
 inline size_t near3_lds_bytes(int nrows)
 {
     const size_t words = ((size_t)NB + 17 + 2 * (size_t)nrows + 1 + 1) & ~(size_t)1;
-    return words * 4 + (size_t)(NB / 64) * KC * 4 * sizeof(double);
+    return words * 4 + (size_t)(NB / 64) * std::max(KC_FWD * 4, KC_ADJ) * sizeof(double);
 }
 
 // values in sorted order: out[f][k] = (w_k) in[perm_k][f] (w NULL: 1), nf components per point
