@@ -600,18 +600,19 @@ __global__ void k3_mul_adj(const double2 *F0, const double2 *F1, const double2 *
     T[o] = make_double2(wv * sx, wv * sy);
 }
 
-// Far values at the points of a set, 16 lanes per point: lane a takes the x tap a (a < 2m),
-// every lane loops over the (b, c) taps, reading 2m consecutive grid values per row across
-// the point's lanes; the 16 partial sums are then added by a butterfly within the group (a
-// fixed order).  nout = 1: out[k] = re A; nout = 4 (forward): A = phi + i H_z,
+// Far values at the points of a set, LG lanes per point (8 when 2m <= 8, else 16): lane a
+// takes the x tap a (a < 2m), every lane loops over the (b, c) taps, reading 2m consecutive
+// grid values per row across the point's lanes; the LG partial sums are then added by a
+// butterfly within the group (a fixed order).  nout = 1: out[k] = re A; nout = 4 (forward): A = phi + i H_z,
 // B = H_x + i H_y -> out[f][k] for f = phi, H_x, H_y, H_z.
+template <int LG>
 __global__ void __launch_bounds__(256) k3_gather(const double *__restrict__ taps, const uint32_t *__restrict__ key,
                                                  int64_t N, Map3 mp, const double2 *__restrict__ A,
                                                  const double2 *__restrict__ B, int nout, int G, double *__restrict__ out)
 {
-    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 4;
-    const int a = threadIdx.x & 15;
-    if (k >= N) return;  // the whole group of 16 leaves together
+    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LG;
+    const int a = threadIdx.x % LG;
+    if (k >= N) return;  // the whole group of LG leaves together
     const int M2 = 2 * mp.m;
     const bool act = a < M2;
     const uint32_t kk = key[k];
@@ -643,12 +644,12 @@ __global__ void __launch_bounds__(256) k3_gather(const double *__restrict__ taps
             }
         }
     }
-    for (int s = 8; s > 0; s >>= 1) {
-        acc0 += __shfl_xor(acc0, s, 16);
+    for (int s = LG / 2; s > 0; s >>= 1) {
+        acc0 += __shfl_xor(acc0, s, LG);
         if (nout == 4) {
-            acc1 += __shfl_xor(acc1, s, 16);
-            acc2 += __shfl_xor(acc2, s, 16);
-            acc3 += __shfl_xor(acc3, s, 16);
+            acc1 += __shfl_xor(acc1, s, LG);
+            acc2 += __shfl_xor(acc2, s, LG);
+            acc3 += __shfl_xor(acc3, s, LG);
         }
     }
     if (a != 0) return;
@@ -1569,7 +1570,8 @@ int fn3_eval(fn3_ctx *ctx, double *phi, double *H)
     // far: phi (re T1), H_z (im T1), H_x (re T2), H_y (im T2) -> far[0..3] as phi, Hx, Hy, Hz
     double *far = B.far;  // [4][nt]: phi, H_x, H_y, H_z
     pi = prof3_begin(c, FN3_ST_GATHER);
-    k3_gather<<<nbk(16 * g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
+    if (2 * P.m <= 8) k3_gather<8><<<nbk(8 * g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
+    else k3_gather<16><<<nbk(16 * g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_NEAR);
@@ -1615,7 +1617,8 @@ int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u)
     prof3_end(c, pi);
     const Map3 mp = map_of(c);
     pi = prof3_begin(c, FN3_ST_A_GATHER);
-    k3_gather<<<nbk(16 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
+    if (2 * P.m <= 8) k3_gather<8><<<nbk(8 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
+    else k3_gather<16><<<nbk(16 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_A_NEAR);

@@ -3,7 +3,7 @@
   * parity with the step-by-step oracle O2 (oracle.fastsum3) element by element: phi, H and
     the H adjoint, FP64, bound 1e-10 (relative L2 and per element, tests.conftest.parity_err),
     on ball and cube clouds at G = 32, 64, 128 (several cells per near radius, ragged point
-    counts, targets coinciding with sources);
+    counts, targets coinciding with sources, window half-widths 4 to 7);
   * accuracy against the direct sum O1 at the tested parameters (the oracle's own bounds);
   * empty source or target sets, degenerate geometry and the parameter checks.
 """
@@ -40,6 +40,7 @@ CASES = [
     ("G32-ball", 701, 903, "ball", 32, 5, 5, 4, 31, 0),
     ("G64-cube", 2999, 4001, "cube", 64, 6, 6, 5, 32, 50),
     ("G128-ball", 9001, 12003, "ball", 128, 7, 8, 8, 33, 100),
+    ("G64-ball-m4", 2501, 3307, "ball", 64, 4, 6, 5, 34, 30),  # 2m <= 8: 8-lane gather groups
 ]
 
 
