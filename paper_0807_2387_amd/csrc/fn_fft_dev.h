@@ -188,8 +188,8 @@ __device__ __forceinline__ int opaque(int x)
     return x;
 }
 
-// A pass of fft_line_reg between its first and last (8 <= L <= N / 64): fft_pass_st
-// with split addresses.
+// A radix-8 pass of fft_line_reg between its first and last (8 <= L <= N / 16):
+// fft_pass_st with split addresses.
 template <int RAD, typename C>
 __device__ __forceinline__ void fft_pass_mid(C *buf, int N, int L, int lt0, int NT, const C *__restrict__ stw)
 {
