@@ -1229,7 +1229,10 @@ Near3 near_of(const fn3_ctx *c, bool adj)
     const double ppc = (double)(adj ? g.ns : g.nt) / std::max(1.0, PI / 6.0 * dia * dia * dia);
     static const int shapes[5][3] = {{2, 2, 1}, {2, 2, 2}, {4, 2, 2}, {4, 4, 2}, {8, 4, 2}};
     int k = 0;
-    while (k < 4 && ppc * shapes[k][0] * shapes[k][1] * shapes[k][2] < 4.0) ++k;
+    // about 4 home points per block in the forward kernel (one register chunk of 4),
+    // about 8 or more in the adjoint (chunks of 8; measured on the ball lattice)
+    const double want = adj ? 8.0 : 4.0;
+    while (k < 4 && ppc * shapes[k][0] * shapes[k][1] * shapes[k][2] < want) ++k;
     for (int d = 0; d < 3; ++d) {
         nr.hb[d] = shapes[k][d];
         const int nb = g.ext[d] - 2 * P.m + 1;
