@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(64 * SW) k3_spread_tile(const double *__restri
     }
     __syncthreads();
     const int x1 = min(x0 + ST, nbx);
-    constexpr int CMAX = 2 * MAXM / SW + 2;  // planes per wave: at most ceil((ST + 2m - 1)/SW)
+    constexpr int CMAX = (ST + 2 * MAXM - 1 + SW - 1) / SW;  // planes per wave: at most ceil((ST + 2m - 1)/SW)
     for (int dz = 0; dz < ST && z0 + dz < nbz; ++dz) {
         const int c0 = max(0, pz0 - dz), c1 = min(M2, pz1 - dz);  // taps c landing in the wave's planes
         if (c0 >= c1) continue;                                   // uniform over the wave
