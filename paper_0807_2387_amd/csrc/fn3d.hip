@@ -694,6 +694,7 @@ struct Near3 {
 // 1/r: hardware reciprocal square root estimate and two Newton steps.
 constexpr int NB = 256;
 constexpr int KC_FWD = 4, KC_ADJ = 8;
+constexpr int RMAP = 8192;  // candidates per block whose row is tabulated in LDS (more: binary search)
 
 __device__ __forceinline__ double rsqrt64(double x)
 {
@@ -751,6 +752,7 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
     uint32_t *rstart = hpre + 9;
     uint32_t *rpre = rstart + nrows;
     double *red = reinterpret_cast<double *>(nsh + ((NB + 17 + 2 * nrows + 1 + 1) & ~1));  // [NB/64][KC][NV]
+    uint16_t *rmap = reinterpret_cast<uint16_t *>(red + (NB / 64) * (KC_FWD * 4 > KC_ADJ ? KC_FWD * 4 : KC_ADJ));  // [RMAP]
     const int t = threadIdx.x;
 
     // home points: one run per home row (at most 8 rows: hb[1] hb[2] <= 8)
@@ -808,6 +810,14 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
     }
     if (t == 0) rpre[nrows] = total;
     __syncthreads();
+    // the row of every candidate, so that a thread finds its candidate's row with one read
+    // (block-uniform choice; a block with more candidates searches the row prefixes)
+    const bool use_map = total <= (uint32_t)RMAP;
+    if (use_map) {
+        for (int r = t * per; r < min(nrows, (t + 1) * per); ++r)
+            for (uint32_t i = rpre[r]; i < rpre[r + 1]; ++i) rmap[i] = (uint16_t)r;
+        __syncthreads();
+    }
 
     const double a0 = nr.a[0];
     for (uint32_t kc0 = 0; kc0 < nhome; kc0 += KC) {
@@ -834,9 +844,13 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
             for (int v = 0; v < NV; ++v) acc[k][v] = 0.0;
         for (uint32_t idx = t; idx < total; idx += NB) {
             int lo = 0, hi = nrows - 1;  // largest row with rpre <= idx (a non-empty row)
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rpre[mid] <= idx) lo = mid; else hi = mid - 1;
+            if (use_map) {
+                lo = rmap[idx];
+            } else {
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (rpre[mid] <= idx) lo = mid; else hi = mid - 1;
+                }
             }
             const uint32_t j = rstart[lo] + (idx - rpre[lo]);
             const double4 q = pos_in[j];
@@ -927,7 +941,7 @@ __global__ void __launch_bounds__(NB) k3_near(const double4 *__restrict__ pos_ou
 inline size_t near3_lds_bytes(int nrows)
 {
     const size_t words = ((size_t)NB + 17 + 2 * (size_t)nrows + 1 + 1) & ~(size_t)1;
-    return words * 4 + (size_t)(NB / 64) * std::max(KC_FWD * 4, KC_ADJ) * sizeof(double);
+    return words * 4 + (size_t)(NB / 64) * std::max(KC_FWD * 4, KC_ADJ) * sizeof(double) + (size_t)RMAP * 2;
 }
 
 // values in sorted order: out[f][k] = (w_k) in[perm_k][f] (w NULL: 1), nf components per point

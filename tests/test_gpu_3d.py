@@ -4,6 +4,7 @@
     the H adjoint, FP64, bound 1e-10 (relative L2 and per element, tests.conftest.parity_err),
     on ball and cube clouds at G = 32, 64, 128 (several cells per near radius, ragged point
     counts, targets coinciding with sources, window half-widths 4 to 7);
+  * a dense cluster (more near-field candidates per home block than the kernel's row table);
   * accuracy against the direct sum O1 at the tested parameters (the oracle's own bounds);
   * empty source or target sets, degenerate geometry and the parameter checks.
 """
@@ -76,6 +77,30 @@ def test_3d_matches_step_by_step_oracle(torch, fn, case):
     _, H2 = S.eval(phi=False)
     torch.cuda.synchronize()
     assert np.array_equal(p2.cpu().numpy(), got["phi"]) and np.array_equal(H2.cpu().numpy(), got["H"])
+
+
+def test_3d_dense_cluster_matches_step_by_step_oracle(torch, fn):
+    """10,000 sources and 300 targets inside a ball of radius 0.02: the home blocks at the
+    cluster see more candidates than the kernel tabulates rows for, so the forward near
+    field takes its row-search path there (FP64 parity bound as above)."""
+    y, x, w, q = synth.random_cloud3(2001, 12003, 35, shape="ball")
+    x[:10000] *= 0.02
+    y[:300] *= 0.02
+    prm = f3.Params3(G=32, m=5, p=6, eps_I=4 / 16, eps_B=1 / 8)
+    F = f3.FastSum3(y, x, w, prm)
+    V = np.random.default_rng(36).standard_normal((len(y), 3))
+    ref = dict(zip(("phi", "H"), F.forward(q)))
+    ref["HT"] = F.adjoint_H(V)
+    S = fn.Solver3(grid=32, m=5, p=6, eps_I=4 / 16, eps_B=1 / 8)
+    S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
+    S.set_charges(dev(torch, q))
+    phi, H = S.eval()
+    u = S.adjoint_H(dev(torch, V))
+    torch.cuda.synchronize()
+    got = dict(phi=phi.cpu().numpy(), H=H.cpu().numpy(), HT=u.cpu().numpy())
+    errs = {k: parity_err(got[k], ref[k]) for k in got}
+    print("3D cluster parity:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) < 1e-10, errs
 
 
 def test_3d_accuracy_against_the_direct_sum(torch, fn):
