@@ -539,6 +539,14 @@ def main_configs(args, torch, synth, fn, dev):
         with torch.cuda.stream(st):
             B = fn.Batch([fn.auto_params(len(y), len(x), fn.FN_FP32_MIXED) for y, x in zip(ys, xs)])
             B.set_geometry(toff, Y, soff, X, W)
+            shapes_from = "library defaults"
+            if not args.no_tune:
+                # per-member shapes: cached, or searched now on each distinct member (not timed)
+                from paper_0807_2387_amd import tune
+                res = tune.apply_batch(B, toff, Y, soff, X, W, Q, V, log=log)
+                shapes_from = (f"autotuner per member: {len({r[0] for r in res})} keys, "
+                               f"{sum(r[2] for r in res)} searched now")
+                log(f"batch_c3: {shapes_from}")
             phi = torch.empty(len(Y), dtype=torch.float64, device=dev)
             H = torch.empty(len(Y), 2, dtype=torch.float64, device=dev)
             u = torch.empty(len(X), dtype=torch.float64, device=dev)
@@ -556,7 +564,8 @@ def main_configs(args, torch, synth, fn, dev):
             ms = _timed(torch, lambda: g.launch(st), args.steps, args.warmup) * 1e3
         record("batch_c3", fn.FN_FP32_MIXED, ms, len(Y) + len(X),
                {"workload": "64 meshes, 5k-200k nodes (disks, ellipses, annuli, rounded rectangles)",
-                "n_nodes": len(Y), "n_src": len(X), "lanes": 4, "graph": True, "params": "fn_params_auto per member"})
+                "n_nodes": len(Y), "n_src": len(X), "lanes": 4, "graph": True, "params": "fn_params_auto per member",
+                "shapes_from": shapes_from})
     for rec in out_lines:
         print(json.dumps(rec), flush=True)
 

@@ -73,6 +73,24 @@ def _dev_ptr(t, name, shape_tail=(), dtype=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+SHAPE_KEYS = ("spread_groups", "near_fwd_bx", "near_fwd_by", "near_fwd_cap", "near_adj_bx", "near_adj_by",
+              "near_adj_cap", "tile")
+
+
+def _set_shapes(ctx, shapes):
+    bad = set(shapes) - set(SHAPE_KEYS)
+    if bad:
+        raise ValueError(f"unknown shape fields {sorted(bad)}")
+    sh = _lib.Shapes(**{k: int(v) for k, v in shapes.items()})
+    _lib.check(_lib.lib().fn_set_shapes(ctx, ctypes.byref(sh)), ctx)
+
+
+def _get_shapes(ctx):
+    sh = _lib.Shapes()
+    _lib.check(_lib.lib().fn_get_shapes(ctx, ctypes.byref(sh)), ctx)
+    return {k: int(getattr(sh, k)) for k in SHAPE_KEYS}
+
+
 class Solver:
     """One fast-summation context bound to the current device and torch stream."""
 
@@ -237,22 +255,15 @@ class Solver:
                                          _dev_ptr(g, "grad", (2,)) if g is not None else None))
         return E, g
 
-    SHAPE_KEYS = ("spread_groups", "near_fwd_bx", "near_fwd_by", "near_fwd_cap", "near_adj_bx", "near_adj_by",
-                  "near_adj_cap", "tile")
+    SHAPE_KEYS = SHAPE_KEYS
 
     def set_shapes(self, **shapes):
         """Kernel work shapes (fn_set_shapes); unnamed fields keep the library default."""
-        bad = set(shapes) - set(self.SHAPE_KEYS)
-        if bad:
-            raise ValueError(f"unknown shape fields {sorted(bad)}")
-        sh = _lib.Shapes(**{k: int(v) for k, v in shapes.items()})
-        self._check(_lib.lib().fn_set_shapes(self._ctx, ctypes.byref(sh)))
+        _set_shapes(self._ctx, shapes)
         return self
 
     def shapes(self):
-        sh = _lib.Shapes()
-        self._check(_lib.lib().fn_get_shapes(self._ctx, ctypes.byref(sh)))
-        return {k: int(getattr(sh, k)) for k in self.SHAPE_KEYS}
+        return _get_shapes(self._ctx)
 
     def set_profiling(self, enable=True):
         self._check(_lib.lib().fn_set_profiling(self._ctx, int(bool(enable))))
@@ -546,6 +557,7 @@ class Batch:
         L = _lib.lib()
         self.count = len(params)
         arr = (_lib.Params * self.count)(*[_params(dict(d)) for d in params])
+        self.params = list(arr)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         b = ctypes.c_void_p()
@@ -586,6 +598,23 @@ class Batch:
                                                 _dev_ptr(src_xy, "src_xy", (2,)), _dev_ptr(src_w, "src_w")))
         self.n_tgt, self.n_src = int(tgt_off[-1]), int(src_off[-1])
         return self
+
+    def _member(self, i):
+        if not 0 <= int(i) < self.count:
+            raise IndexError(f"member {i} of a batch of {self.count}")
+        ctx = ctypes.c_void_p()
+        self._check(_lib.lib().fn_batch_member(self._b, int(i), ctypes.byref(ctx)))
+        return ctx
+
+    def set_shapes(self, i, **shapes):
+        """Kernel work shapes of member i (fn_set_shapes on its context, borrowed with
+        fn_batch_member); unnamed fields keep the library default."""
+        _set_shapes(self._member(i), shapes)
+        return self
+
+    def shapes(self, i):
+        """The shapes in effect for member i."""
+        return _get_shapes(self._member(i))
 
     def set_lanes(self, lanes):
         """Streams an evaluation spreads the members' tasks over (fn_batch_set_lanes)."""

@@ -460,9 +460,13 @@ int fn_params_default(fn_params *p, int32_t grid)
 int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p)
 {
     if (!p || n_tgt < 0 || n_src < 0) return FN_E_INVAL;
-    // about 4 grid cells (one bandwidth cell) per target and per source on average:
-    // G = 2^ceil(log2(2 sqrt((n_tgt + n_src) / 2)))
-    const double want = 2.0 * std::sqrt(0.5 * (double)(n_tgt + n_src));
+    // small problems (fewer than 2^22 points) take the larger near radius n eps_I = 8 with
+    // p = 10: the boundary-layer error of H weighs more there.  Grid: at least 2 grid cells
+    // per point, G^2 >= 2 (n_tgt + n_src), or 4 for the small problems, whose near field
+    // (n eps_I = 8) costs more than the larger grid's spread, FFT and gather
+    const int64_t npt = n_tgt + n_src;
+    const bool small = npt < ((int64_t)1 << 22);
+    const double want = std::sqrt((small ? 4.0 : 2.0) * (double)npt);
     int32_t G = 64;
     while (G < MAXG && G < want) G *= 2;
     fn_params_default(p, G);
@@ -473,8 +477,7 @@ int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p
     const int nb = G >= 128 ? 3 * G / 4 : G / 2;
     p->n = G >= 128 ? nb : 0;
     p->eps_I = 7.0 / nb;
-    if (n_tgt + n_src < ((int64_t)1 << 22)) {
-        // small problems: the boundary-layer error of H weighs more and the near field is cheap
+    if (small) {
         p->p = 10;
         p->eps_I = 8.0 / nb;
     }

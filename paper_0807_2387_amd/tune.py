@@ -18,9 +18,13 @@ other; the median of its stage times decides.  The result is keyed by what sets 
 shape -- grid, window half-width, regularization degree, precision, bandwidth, near radius
 in cells, points per grid cell of the data window and the GPU architecture -- and stored in
 a JSON file: $FEMNFFT_TUNE_CACHE, else ~/.cache/femnfft/tune.json.  Entries measured on
-MI355X for the bench workload ship with the package (tune_cache.json) and are read first.
+MI355X for the bench workloads (the square and the 64-mesh batch's members) ship with the
+package (tune_cache.json) and are read first.
 
     shapes = tune.apply(solver, q, V)       # cached shapes, or tune now and cache them
+
+A batch's members are tuned one distinct key at a time, each on a standalone solver holding
+that member's points, and the winners are set on every member with that key (apply_batch).
 """
 from __future__ import annotations
 
@@ -170,3 +174,29 @@ def apply(solver, q, V, reps=3, log=None, retune=False):
     shapes, trace = tune(solver, q, V, reps=reps, log=log)
     store(key, shapes, {"trials": len(trace)})
     return shapes, key, True
+
+
+def apply_batch(batch, tgt_off, tgt_xy, src_off, src_xy, src_w, q, V, n_surf=None, reps=3, log=None,
+                retune=False):
+    """Set cached or freshly tuned shapes on every member of a Batch whose geometry is set
+    from these arrays (its concatenated inputs, host offsets).  Members that share a cache key
+    share one search.  Returns [(key, shapes, tuned_now)] per member."""
+    from . import Solver
+    done, out = {}, []
+    for i, prm in enumerate(batch.params):
+        t0, t1, s0, s1 = int(tgt_off[i]), int(tgt_off[i + 1]), int(src_off[i]), int(src_off[i + 1])
+        S = Solver(grid=prm.grid, m=prm.m, p=prm.p, eps_I=prm.eps_I, eps_B=prm.eps_B, precision=prm.precision,
+                   n=prm.n, eps_S=prm.eps_S)
+        S.set_geometry(tgt_xy[t0:t1], src_xy[s0:s1], src_w[s0:s1], n_surf=int(n_surf[i]) if n_surf is not None else 0)
+        key = key_of(S)
+        if key in done:
+            shapes, now = done[key], False
+        else:
+            shapes, _, now = apply(S, q[s0:s1], V[t0:t1], reps=reps, log=log, retune=retune)
+            done[key] = shapes
+        del S
+        batch.set_shapes(i, **shapes)
+        out.append((key, shapes, now))
+        if log:
+            log(f"member {i}: {key} {'searched' if now else 'cached'} {shapes}")
+    return out

@@ -111,6 +111,84 @@ def test_batch_members_match_oracle(torch, fn, precision):
         assert max(errs.values()) < tol, (i, errs)
 
 
+MEMBER_SHAPES = {0: dict(tile=16), 2: dict(near_fwd_bx=16, near_fwd_by=16, near_fwd_cap=384, near_adj_bx=64,
+                                            near_adj_by=4, near_adj_cap=128),
+                 5: dict(spread_groups=3, tile=16, near_fwd_bx=64, near_fwd_by=4, near_fwd_cap=2048)}
+
+
+def member_problem(P):
+    ys, xs, ws, qs, Vs, prms = [], [], [], [], [], []
+    for nt, ns, G, p, c, seed in member_clouds():
+        y, x, w, q = synth.random_cloud(nt, ns, seed, neutral=ns > 1)
+        ys.append(y), xs.append(x), ws.append(w), qs.append(q)
+        Vs.append(np.random.default_rng(seed + 7).standard_normal((nt, 2)))
+        prms.append(fs.Params(G=G, m=6, p=p, eps_I=c / (G // 2)))
+    return ys, xs, ws, qs, Vs, prms
+
+
+def check_members(torch, B, ys, xs, ws, qs, Vs, prms, tol):
+    toff, soff = concat(ys)[0], concat(xs)[0]
+    B.set_charges(dev(torch, np.concatenate(qs)))
+    phi, H, u = (a.cpu().numpy() for a in B.eval_with_H_adjoint(dev(torch, np.concatenate(Vs))))
+    for i, pr in enumerate(prms):
+        F = fs.FastSum(ys[i], xs[i], ws[i], pr)
+        p2, h2 = F.forward(qs[i])
+        t, s = slice(toff[i], toff[i + 1]), slice(soff[i], soff[i + 1])
+        errs = dict(phi=parity_err(phi[t], p2), H=parity_err(H[t], h2), HT=parity_err(u[s], F.adjoint_H(Vs[i])))
+        print(i, B.shapes(i), errs, flush=True)
+        assert max(errs.values()) < tol, (i, errs)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_member_shapes_keep_parity(torch, fn, precision):
+    """Shapes set on single members (fn_batch_member + fn_set_shapes) change those members
+    only, and every member still matches O2."""
+    print(f"batch member shapes {precision}", flush=True)
+    P = fn.FN_FP64 if precision == "fp64" else fn.FN_FP32_MIXED
+    ys, xs, ws, qs, Vs, prms = member_problem(P)
+    B = fn.Batch([dict(grid=pr.G, m=6, p=pr.p, eps_I=pr.eps_I, precision=P) for pr in prms])
+    B.set_geometry(concat(ys)[0], dev(torch, concat(ys)[1]), concat(xs)[0], dev(torch, concat(xs)[1]),
+                   dev(torch, np.concatenate(ws)))
+    default = B.shapes(1)
+    for i, sh in MEMBER_SHAPES.items():
+        B.set_shapes(i, **sh)
+        got = B.shapes(i)
+        assert all(got[k] == v for k, v in sh.items()), (i, got)
+    assert B.shapes(1) == default and B.shapes(3) == default
+    with pytest.raises(fn.FemNfftError):
+        B.set_shapes(4, tile=8)
+    with pytest.raises(IndexError):
+        B.shapes(len(prms))
+    check_members(torch, B, ys, xs, ws, qs, Vs, prms, 1e-10 if precision == "fp64" else 1e-6)
+
+
+def test_batch_tuner_sets_member_shapes_and_keeps_parity(torch, fn, tmp_path, monkeypatch):
+    """tune.apply_batch: one search per distinct key, cached; every member gets its key's
+    shapes, and the batch still matches O2 (FP32-mixed 1e-6)."""
+    from paper_0807_2387_amd import tune
+    print("batch tuner", flush=True)
+    monkeypatch.setenv("FEMNFFT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(tune, "PACKAGED", str(tmp_path / "none.json"))
+    P = fn.FN_FP32_MIXED
+    ys, xs, ws, qs, Vs, prms = member_problem(P)
+    toff, Y = concat(ys)
+    soff, X = concat(xs)
+    W = np.concatenate(ws)
+    B = fn.Batch([dict(grid=pr.G, m=6, p=pr.p, eps_I=pr.eps_I, precision=P) for pr in prms])
+    args = (toff, dev(torch, Y), soff, dev(torch, X), dev(torch, W))
+    B.set_geometry(*args)
+    Qd, Vd = dev(torch, np.concatenate(qs)), dev(torch, np.concatenate(Vs))
+    res = tune.apply_batch(B, *args, Qd, Vd, reps=1)
+    keys = [r[0] for r in res]
+    assert sum(r[2] for r in res) == len(set(keys)), "one search per distinct key"
+    for i, (k, sh, _) in enumerate(res):
+        assert B.shapes(i) == sh, i
+        assert tune.lookup(k) == sh
+    res2 = tune.apply_batch(B, *args, Qd, Vd, reps=1)
+    assert not any(r[2] for r in res2) and [r[1] for r in res2] == [r[1] for r in res]
+    check_members(torch, B, ys, xs, ws, qs, Vs, prms, 1e-6)
+
+
 @pytest.mark.slow
 def test_c3_batch_of_64_meshes_vs_direct_sum(torch, fn):
     print("C3: generating 64 meshes", flush=True)

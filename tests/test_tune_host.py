@@ -75,3 +75,59 @@ def test_cache_round_trip_and_key(tmp_path, monkeypatch):
     assert tune.lookup(k) is None or tune.lookup(k) == tune.lookup(k)
     tune.store(k, {"tile": 16}, {"trials": 3})
     assert tune.lookup(k) == {"tile": 16}
+
+
+def test_batch_tuning_searches_each_distinct_key_once(tmp_path, monkeypatch):
+    """apply_batch: members with one key share one search (then a cache hit), every member
+    gets its key's shapes, and a second call searches nothing."""
+    import sys
+    import types
+    import paper_0807_2387_amd as pkg
+    from paper_0807_2387_amd import tune
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None))
+    monkeypatch.setitem(sys.modules, "torch", fake_torch)
+    monkeypatch.setenv("FEMNFFT_TUNE_CACHE", str(tmp_path / "t.json"))
+    monkeypatch.setattr(tune, "PACKAGED", str(tmp_path / "none.json"))
+    monkeypatch.setattr(tune, "arch", lambda: "gfx950")
+
+    class MemberSolver(FakeSolver):
+        def __init__(self, grid, m, p, eps_I, eps_B, precision, n, eps_S):
+            super().__init__()
+            self.params = types.SimpleNamespace(grid=grid, n=n, m=m, p=p, precision=precision)
+            self.nt = self.ns = 0
+
+        def set_geometry(self, y, x, w, n_surf=0):
+            self.nt, self.ns = len(y), len(x)
+
+        def info(self):
+            return dict(win_ext=(100, 100), n_tgt=self.nt, n_src=self.ns, near_cells=5, n_surf=0)
+
+    monkeypatch.setattr(pkg, "Solver", MemberSolver)
+    searches = []
+    real_tune = tune.tune
+    monkeypatch.setattr(tune, "tune", lambda S, q, V, **kw: (searches.append(S.params.grid), real_tune(S, q, V, **kw))[1])
+
+    class FakeBatch:
+        def __init__(self, grids):
+            self.params = [types.SimpleNamespace(grid=g, m=5, p=5, eps_I=0.01, eps_B=1 / 32, precision=1, n=0,
+                                                 eps_S=0.0) for g in grids]
+            self.set = {}
+
+        def set_shapes(self, i, **sh):
+            self.set[i] = sh
+
+    B = FakeBatch([1024, 1024, 2048, 1024])
+    sizes = [(20000, 40000), (20000, 40000), (20000, 40000), (200000, 400000)]
+    toff = [0]
+    soff = [0]
+    for nt, ns in sizes:
+        toff.append(toff[-1] + nt)
+        soff.append(soff[-1] + ns)
+    Y, X = list(range(toff[-1])), list(range(soff[-1]))
+    res = tune.apply_batch(B, toff, Y, soff, X, X, X, Y, reps=1)
+    keys = [r[0] for r in res]
+    assert len(set(keys)) == 3 and keys[0] == keys[1] != keys[3]
+    assert sorted(searches) == [1024, 1024, 2048] and [r[2] for r in res] == [True, False, True, True]
+    assert all(B.set[i] == res[i][1] for i in range(4))
+    res2 = tune.apply_batch(B, toff, Y, soff, X, X, X, Y, reps=1)
+    assert not any(r[2] for r in res2) and len(searches) == 3
