@@ -79,7 +79,8 @@ def parse():
     ap.add_argument("--grid3", type=int, default=256)
     ap.add_argument("--m3", type=int, default=4)
     ap.add_argument("--p3", type=int, default=6)
-    ap.add_argument("--c3", type=float, default=5.0, help="ball3d: eps_I = c3 / (grid3/2)")
+    ap.add_argument("--band3", type=int, default=176, help="ball3d: bandwidth n (0: grid3/2)")
+    ap.add_argument("--c3", type=float, default=5.5, help="ball3d: eps_I = c3 / n")
     return ap.parse_args()
 
 
@@ -609,10 +610,10 @@ def near3_flops_per_pair(stage, p):
     return 6 + 5 + 1 + 2 * (p - 2) + 1 + 5 + 5 + 2
 
 
-def fft3_bytes(G, ext, forward):
+def fft3_bytes(G, n, ext, forward):
     """Bytes the pruned 3D transform must move: each pass reads the elements its lines hold
-    (the data window or the band |l| <= n/2, n = G/2) and writes the ones the next step keeps."""
-    nb = 2 * (G // 4) + 1
+    (the data window or the band |l| <= n/2) and writes the ones the next step keeps."""
+    nb = 2 * (n // 2) + 1
     ex, ey, ez = ext
     if forward:  # x lines of the window's rows, y lines of band x window-z, z lines of band x band
         el = ey * ez * (ex + nb) + nb * ez * (ey + nb) + nb * nb * (ez + nb)
@@ -621,13 +622,13 @@ def fft3_bytes(G, ext, forward):
     return el * 16
 
 
-def roofline3(stage, ms_per_launch, G, m, p, info, nt, ns, pairs):
+def roofline3(stage, ms_per_launch, G, n, m, p, info, nt, ns, pairs):
     """Roofline of one 3D stage: algorithmic HBM bytes (points' cell, fractions and values once,
     every grid value a pass needs read and written once), or near-field flops, per launch."""
     sec = ms_per_launch * 1e-3
     ext = tuple(info["win_ext"])
     win = int(np.prod(ext)) * 16
-    band3 = (2 * (G // 4) + 1) ** 3 * 16
+    band3 = (2 * (n // 2) + 1) ** 3 * 16
     if stage in ("near", "a_near"):
         fl = near3_flops_per_pair(stage, p)
         ach = pairs[stage] * fl / sec / 1e12
@@ -637,9 +638,9 @@ def roofline3(stage, ms_per_launch, G, m, p, info, nt, ns, pairs):
     byts = {
         "charges": ns * 28, "a_values": nt * 52,
         "spread": ns * 36 + win, "a_spread": nt * 60 + 3 * win,
-        "fft": fft3_bytes(G, ext, True), "a_fft": 3 * fft3_bytes(G, ext, True),
+        "fft": fft3_bytes(G, n, ext, True), "a_fft": 3 * fft3_bytes(G, n, ext, True),
         "multiply": 3 * band3, "a_multiply": 4 * band3,
-        "ifft": 2 * fft3_bytes(G, ext, False), "a_ifft": fft3_bytes(G, ext, False),
+        "ifft": 2 * fft3_bytes(G, n, ext, False), "a_ifft": fft3_bytes(G, n, ext, False),
         "gather": nt * 60 + 2 * win, "a_gather": ns * 36 + win,
     }[stage]
     ach = byts / sec / 1e9
@@ -653,14 +654,15 @@ def main_3d(args, torch, synth, fn, dev):
     adjoint, FP64, inputs resident before the timed region."""
     from scipy.spatial import cKDTree
     G, m, p = args.grid3, args.m3, args.p3
-    eps_I, eps_B = args.c3 / (G // 2), 1.0 / 8.0
+    n = args.band3 or G // 2
+    eps_I, eps_B = args.c3 / n, 1.0 / 8.0
     d = synth.ball_lattice3(K=args.K)
     y, x, w, q, V = d["y"], d["x"], d["w"], d["q"], d["V"]
     nt, ns = len(y), len(x)
-    log(f"3D workload: {nt} targets, {ns} sources; G = {G}, m = {m}, p = {p}, eps_I = {eps_I:.5f}")
+    log(f"3D workload: {nt} targets, {ns} sources; G = {G}, n = {n}, m = {m}, p = {p}, eps_I = {eps_I:.5f}")
     tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ty, tx, tw, tq, tV = tt(y), tt(x), tt(w), tt(q), tt(V)
-    S = fn.Solver3(grid=G, m=m, p=p, eps_I=eps_I, eps_B=eps_B)
+    S = fn.Solver3(grid=G, m=m, p=p, eps_I=eps_I, eps_B=eps_B, n=n)
     torch.cuda.synchronize()
     g0 = time.perf_counter()
     S.set_geometry(ty, tx, tw)
@@ -705,8 +707,8 @@ def main_3d(args, torch, synth, fn, dev):
     for k, v in sorted(stages.items(), key=lambda kv: -kv[1]):
         log(f"  {k:12s} {v:9.3f} ms/step")
     dom = max(stages, key=stages.get)
-    roof = roofline3(dom, per_launch[dom], G, m, p, info, nt, ns, pairs)
-    roof_stages = {k: {kk: vv for kk, vv in roofline3(k, per_launch[k], G, m, p, info, nt, ns, pairs).items()
+    roof = roofline3(dom, per_launch[dom], G, n, m, p, info, nt, ns, pairs)
+    roof_stages = {k: {kk: vv for kk, vv in roofline3(k, per_launch[k], G, n, m, p, info, nt, ns, pairs).items()
                        if kk in ("bound", "achieved", "unit", "frac", "ms_per_launch")} for k in stages}
     out = {
         "metric": "source+target points/s for 3D forward+adjoint fast summation (G = 1/(4 pi r), FP64)",
@@ -715,7 +717,7 @@ def main_3d(args, torch, synth, fn, dev):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"ball radius 1, lattice K = {args.K}: jittered nodes as targets, "
                                f"4 random points per lattice cell as sources, smooth random charges",
-                   "n_tgt": nt, "n_src": ns, "grid": G, "bandwidth": G // 2, "m": m, "p": p, "eps_I": eps_I,
+                   "n_tgt": nt, "n_src": ns, "grid": G, "bandwidth": n, "m": m, "p": p, "eps_I": eps_I,
                    "eps_B": eps_B, "precision": "fp64", "parallelism": "single_gpu"},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "stages_ms_from": "HIP events per stage on the context's stream (one stream, stages in order)",

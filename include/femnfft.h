@@ -441,9 +441,11 @@ const char *fn_graph_last_error(void);
  *     H_i   = -grad phi = (1/4pi) sum_j w_j q_j (r_i - r_j) / |r_i - r_j|^3,
  *
  * and the transpose of the H map, u_j = w_j sum_i V_i . (r_i - r_j) / (4 pi |r_i - r_j|^3),
- * by the NFFT method on a G^3 grid (the paper's p^3 N grid in 3D; bandwidth n = G/2), for
- * tetrahedral FEM quadrature points or any point sets.  FP64 throughout (precision must be
- * FN_FP64), grid G a power of two in [16, 256], m <= G/4 - 1, eps_S = 0.  3-vectors are interleaved
+ * by the NFFT method on a G^3 grid (the paper's p^3 N grid in 3D), for tetrahedral FEM
+ * quadrature points or any point sets.  FP64 throughout (precision must be FN_FP64), grid G
+ * a power of two in [16, 256], m <= G/4 - 1, eps_S = 0; bandwidth n = 0 (G/2, oversampling 2)
+ * or even in [G/2, 3G/4] (at n = 3G/4 the window needs m >= 5 for errors below 1e-7, and the
+ * near radius eps_I shrinks with 1/n; FN_E_INVAL otherwise).  3-vectors are interleaved
  * [n][3]; every array is a device pointer; the conventions (ordering, workspace, call order,
  * errors, pairs at distance zero) are those of the 2D context.  The kernel's regularization
  * near the torus boundary needs a wider zone than in 2D: eps_B = 1/8 is the tested setting.

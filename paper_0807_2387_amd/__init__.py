@@ -286,11 +286,12 @@ class Solver:
 class Solver3:
     """The 3D fast summation (fn3_*): G = 1/(4 pi r), FP64, points as [n, 3] device tensors."""
 
-    def __init__(self, grid, m=6, p=8, eps_I=None, eps_B=0.125, stream=None):
+    def __init__(self, grid, m=6, p=8, eps_I=None, eps_B=0.125, stream=None, n=0):
+        """n: bandwidth, 0 for G/2 (oversampling 2), or even in [G/2, 3G/4]."""
         torch = _torch()
         prm = _lib.Params(grid=int(grid), m=int(m), p=int(p), precision=FN_FP64,
-                          eps_I=float(eps_I if eps_I is not None else 6.0 / (grid // 2)), eps_B=float(eps_B), flags=0,
-                          n=0, eps_S=0.0)
+                          eps_I=float(eps_I if eps_I is not None else 6.0 / (n or grid // 2)), eps_B=float(eps_B),
+                          flags=0, n=int(n), eps_S=0.0)
         self.params = prm
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)

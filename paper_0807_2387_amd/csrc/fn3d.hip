@@ -44,11 +44,12 @@ constexpr int MAXG3 = 256;
 constexpr int NT = 256;
 
 struct Plan3 {
-    int G = 0, n = 0, m = 0, p = 0, log2G = 0, log2n = 0;
+    int G = 0, n = 0, m = 0, p = 0, log2G = 0;
     double eps_I = 0, eps_B = 0, kb_b = 0, i0mb = 0;
     double a[MAXP] = {0};
     std::vector<double> cB, psihat;
-    std::vector<double> twG, twn;  // pass-ordered twiddles of G- and n-point lines (staged_twiddles)
+    std::vector<double> twG;   // pass-ordered twiddles of G-point lines (staged_twiddles)
+    std::vector<double> ctab;  // cos(2 pi k / n), k < n: the plan's cosine sums
 };
 
 struct Geom3 {
@@ -62,7 +63,8 @@ struct Geom3 {
 
 struct Buf3 {
     double *W = nullptr;              // [(n/2+1)^3]
-    double2 *twG = nullptr, *twn = nullptr;
+    double2 *twG = nullptr;
+    double *ctab = nullptr;
     uint32_t *key[2] = {nullptr, nullptr}, *perm[2] = {nullptr, nullptr}, *cstart[2] = {nullptr, nullptr};
     double4 *pos[2] = {nullptr, nullptr}; // [N] positions in grid units (base cell + fraction)
     double *taps[2] = {nullptr, nullptr}; // [N][3][2m] window taps
@@ -169,7 +171,6 @@ static bool build_plan(const fn_params &prm, Plan3 &P, std::string &err)
     P.eps_I = prm.eps_I;
     P.eps_B = prm.eps_B;
     while ((1 << P.log2G) < P.G) ++P.log2G;
-    while ((1 << P.log2n) < P.n) ++P.log2n;
     P.kb_b = PI * (2.0 - (double)P.n / P.G);
     P.i0mb = bessel_i0(P.m * P.kb_b);
     {
@@ -210,8 +211,9 @@ static bool build_plan(const fn_params &prm, Plan3 &P, std::string &err)
         const double w = 2.0 * PI * l / P.G;
         P.psihat[l] = bessel_i0(P.m * std::sqrt(P.kb_b * P.kb_b - w * w)) / P.i0mb;
     }
-    fn::staged_twiddles(P.G, P.twG);  // pass-ordered tables of the G- and n-point lines
-    fn::staged_twiddles(P.n, P.twn);
+    fn::staged_twiddles(P.G, P.twG);  // pass-ordered table of the G-point lines
+    P.ctab.resize(P.n);
+    for (int k = 0; k < P.n; ++k) P.ctab[k] = (double)std::cos(2.0L * (long double)PI * k / P.n);
     return true;
 }
 
@@ -230,7 +232,6 @@ __device__ __forceinline__ double kb_psi(double t, double m, double b, double wn
     return (exp(-b * t2 / zm) - exp(-b * zm)) * wnorm / z;
 }
 
-__device__ __forceinline__ int sfreq(int k, int N) { return k <= N / 2 ? k : k - N; }
 
 // ------------------------------------------------------------------ geometry kernels
 
@@ -338,17 +339,21 @@ __global__ void k3_finish(const double *__restrict__ p, const double *__restrict
 
 // ------------------------------------------------------------------ plan kernels
 
-__global__ void k3_kr_samples(double2 *__restrict__ a, int n, const double *__restrict__ coef, int p,
+// b_l = (1/n^3) sum_{j in I_n^3} K_R(|j|/n) e^{-2 pi i j.l/n} is real and even in every
+// component of j and l (K_R is radial and the grid I_n = {-n/2 + 1, ..., n/2} is symmetric
+// up to its Nyquist index, where e^{-2 pi i j l/n} is real), so it is a separable cosine
+// sum over the half grid j_d in [0, n/2] with weight 1 at j_d = 0 and n/2 and 2 between:
+//   b_l = (1/n^3) sum_j prod_d (om_{j_d} cos(2 pi j_d l_d / n)) K_R(|j|/n),  l_d in [0, n/2].
+// Three passes of (n/2 + 1)-term sums (any even n: oversampling 2 or 4/3 alike).
+// Samples on the half grid: a[(j2 nh1 + j1) nh1 + j0] = K_R(|j|/n).
+__global__ void k3_kr_samples(double *__restrict__ a, int n, const double *__restrict__ coef, int p,
                               double eps_I, double eps_B, const double *__restrict__ cB, int ncB)
 {
+    const int nh1 = n / 2 + 1;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t n3 = (int64_t)n * n * n;
-    if (idx >= n3) return;
-    const int j0 = (int)(idx % n), j1 = (int)((idx / n) % n), j2 = (int)(idx / ((int64_t)n * n));
-    const double c0 = sfreq(j0, n) == n / 2 ? -n / 2 : sfreq(j0, n);
-    const double c1 = sfreq(j1, n) == n / 2 ? -n / 2 : sfreq(j1, n);
-    const double c2 = sfreq(j2, n) == n / 2 ? -n / 2 : sfreq(j2, n);
-    const double r = sqrt(c0 * c0 + c1 * c1 + c2 * c2) / n;
+    if (idx >= (int64_t)nh1 * nh1 * nh1) return;
+    const int j0 = (int)(idx % nh1), j1 = (int)((idx / nh1) % nh1), j2 = (int)(idx / ((int64_t)nh1 * nh1));
+    const double r = sqrt((double)j0 * j0 + (double)j1 * j1 + (double)j2 * j2) / n;
     const double rB = 0.5 - eps_B;
     double v;
     if (r < eps_I) {
@@ -364,20 +369,41 @@ __global__ void k3_kr_samples(double2 *__restrict__ a, int n, const double *__re
         for (int k = ncB - 1; k >= 0; --k) acc = acc * t + cB[k];
         v = acc;
     }
-    a[idx] = make_double2(v, 0.0);
+    a[idx] = v;
 }
 
-// W[(l0 (nh+1) + l1)(nh+1) + l2] = omega(l) Re(b_l) / prod psihat(l_d)^2 for l_d in [0, n/2];
-// bl holds n^3 b_l (unnormalized DFT of the samples)
-__global__ void k3_make_W(const double2 *__restrict__ bl, int n, const double *__restrict__ psihat,
+// One axis of the cosine sums: out[.., l, ..] = sum_j om_j cos(2 pi j l / n) in[.., j, ..] along
+// `axis` (0: the fastest index), over the (n/2 + 1)^3 half grid; ctab[k] = cos(2 pi k / n).
+__global__ void k3_cos_pass(const double *__restrict__ in, double *__restrict__ out, int n, int axis,
+                            const double *__restrict__ ctab)
+{
+    const int nh = n / 2, nh1 = nh + 1;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nh1 * nh1 * nh1) return;
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nh1 : (int64_t)nh1 * nh1);
+    const int l = (int)((idx / stride) % nh1);
+    const double *line = in + (idx - (int64_t)l * stride);
+    double acc = 0.0;
+    int jl = 0;  // (j l) mod n
+    for (int j = 0; j <= nh; ++j) {
+        const double om = (j == 0 || j == nh) ? 1.0 : 2.0;
+        acc = fma(om * ctab[jl], line[(int64_t)j * stride], acc);
+        jl += l;
+        if (jl >= n) jl -= n;
+    }
+    out[idx] = acc;
+}
+
+// W[(l0 (nh+1) + l1)(nh+1) + l2] = omega(l) b_l / prod psihat(l_d)^2 for l_d in [0, n/2];
+// bl holds n^3 b_l on the half grid (b_l is symmetric in its three components)
+__global__ void k3_make_W(const double *__restrict__ bl, int n, const double *__restrict__ psihat,
                           double *__restrict__ W)
 {
     const int nh = n / 2, nh1 = nh + 1;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= (int64_t)nh1 * nh1 * nh1) return;
     const int l0 = (int)(idx / ((int64_t)nh1 * nh1)), l1 = (int)((idx / nh1) % nh1), l2 = (int)(idx % nh1);
-    // b_l is even in each component; sample index (l2, l1, l0) in the x-fastest layout
-    const double b = bl[((int64_t)(l0 % n) * n + (l1 % n)) * n + (l2 % n)].x / ((double)n * n * n);
+    const double b = bl[idx] / ((double)n * n * n);
     const double om = (l0 == nh ? 0.5 : 1.0) * (l1 == nh ? 0.5 : 1.0) * (l2 == nh ? 0.5 : 1.0);
     const double ph = psihat[l0] * psihat[l1] * psihat[l2];
     W[idx] = om * b / (ph * ph);
@@ -1047,7 +1073,7 @@ void prof3_end(fn3_ctx *c, int i)
 }
 
 struct Layout3 {
-    size_t total = 0, off_W = 0, off_twG = 0, off_twn = 0, off_key[2] = {0, 0}, off_perm[2] = {0, 0},
+    size_t total = 0, off_W = 0, off_twG = 0, off_ctab = 0, off_key[2] = {0, 0}, off_perm[2] = {0, 0},
            off_cs[2] = {0, 0}, off_fr[2] = {0, 0}, off_taps[2] = {0, 0}, off_w = 0, off_val = 0, off_aval = 0,
            off_grid[3] = {0, 0, 0},
            off_far = 0, off_red = 0, off_skey = 0, off_sval = 0, off_hist = 0, off_tiles = 0;
@@ -1072,7 +1098,7 @@ Layout3 layout3(const Plan3 &P, int64_t nt, int64_t ns)
     const int64_t G3 = (int64_t)P.G * P.G * P.G;
     L.off_W = take((size_t)nh1 * nh1 * nh1 * 8);
     L.off_twG = take((size_t)P.G * 16);
-    L.off_twn = take((size_t)P.n * 16);
+    L.off_ctab = take((size_t)P.n * 8);
     for (int s = 0; s < 2; ++s) {
         L.off_key[s] = take(N[s] * 4);
         L.off_perm[s] = take(N[s] * 4);
@@ -1083,7 +1109,7 @@ Layout3 layout3(const Plan3 &P, int64_t nt, int64_t ns)
     L.off_w = take(N[1] * 8);
     L.off_val = take(N[1] * 8);
     L.off_aval = take(3 * N[0] * 8);
-    // three G^3 complex grids; they also hold the n^3 plan transform (n <= 3G/4 < G)
+    // three G^3 complex grids; two of them also hold the plan's (n/2 + 1)^3 cosine sums
     for (int g = 0; g < 3; ++g) L.off_grid[g] = take((size_t)G3 * 16);
     L.off_far = take(4 * nmax * 8);
     L.off_red = take(8192 * 8);
@@ -1104,7 +1130,7 @@ void bind3(fn3_ctx *c, const Layout3 &L)
     Buf3 &B = c->buf;
     B.W = reinterpret_cast<double *>(b + L.off_W);
     B.twG = reinterpret_cast<double2 *>(b + L.off_twG);
-    B.twn = reinterpret_cast<double2 *>(b + L.off_twn);
+    B.ctab = reinterpret_cast<double *>(b + L.off_ctab);
     for (int s = 0; s < 2; ++s) {
         B.key[s] = reinterpret_cast<uint32_t *>(b + L.off_key[s]);
         B.perm[s] = reinterpret_cast<uint32_t *>(b + L.off_perm[s]);
@@ -1129,7 +1155,6 @@ constexpr size_t PASS_LDS = (size_t)80 << 10;
 
 Set3 s_int(int lo, int len) { return Set3{0, lo, len}; }
 Set3 s_band() { return Set3{1, 0, 0}; }
-Set3 s_all() { return Set3{2, 0, 0}; }
 
 int pass3(fn3_ctx *c, double2 *a, int N, int log2N, int axis, int inv, int nh, Set3 su, Set3 sv, Set3 ld, Set3 stv,
           const double2 *tw)
@@ -1186,21 +1211,21 @@ int build_plan3(fn3_ctx *c)
                                       F * F * F * (int)sizeof(double)));
     }
     F3_HIP(c, hipMemcpyAsync(B.twG, P.twG.data(), P.twG.size() * 8, hipMemcpyHostToDevice, st));
-    F3_HIP(c, hipMemcpyAsync(B.twn, P.twn.data(), P.twn.size() * 8, hipMemcpyHostToDevice, st));
+    F3_HIP(c, hipMemcpyAsync(B.ctab, P.ctab.data(), P.ctab.size() * 8, hipMemcpyHostToDevice, st));
     double *coef = B.red, *cB = B.red + 32, *psi = B.red + 128;
     F3_HIP(c, hipMemcpyAsync(coef, P.a, sizeof(double) * MAXP, hipMemcpyHostToDevice, st));
     F3_HIP(c, hipMemcpyAsync(cB, P.cB.data(), sizeof(double) * P.cB.size(), hipMemcpyHostToDevice, st));
     F3_HIP(c, hipMemcpyAsync(psi, P.psihat.data(), sizeof(double) * P.psihat.size(), hipMemcpyHostToDevice, st));
-    const int64_t n3 = (int64_t)P.n * P.n * P.n;
-    double2 *scr = B.grid[0];
-    k3_kr_samples<<<nbk(n3), NT, 0, st>>>(scr, P.n, coef, P.p, P.eps_I, P.eps_B, cB, (int)P.cB.size());
+    const int64_t nh1 = P.n / 2 + 1, nh3 = nh1 * nh1 * nh1;
+    double *ha = reinterpret_cast<double *>(B.grid[0]), *hb = reinterpret_cast<double *>(B.grid[1]);
+    k3_kr_samples<<<nbk(nh3), NT, 0, st>>>(ha, P.n, coef, P.p, P.eps_I, P.eps_B, cB, (int)P.cB.size());
     F3_LAUNCH(c);
-    int rc = FN_OK;
-    for (int axis = 0; axis < 3 && !rc; ++axis)
-        rc = pass3(c, scr, P.n, P.log2n, axis, 0, 0, s_all(), s_all(), s_all(), s_all(), B.twn);
-    if (rc) return rc;
-    const int64_t nh1 = P.n / 2 + 1;
-    k3_make_W<<<nbk(nh1 * nh1 * nh1), NT, 0, st>>>(scr, P.n, psi, B.W);
+    for (int axis = 0; axis < 3; ++axis) {
+        k3_cos_pass<<<nbk(nh3), NT, 0, st>>>(ha, hb, P.n, axis, B.ctab);
+        F3_LAUNCH(c);
+        std::swap(ha, hb);
+    }
+    k3_make_W<<<nbk(nh3), NT, 0, st>>>(ha, P.n, psi, B.W);
     F3_LAUNCH(c);
     F3_HIP(c, hipStreamSynchronize(st));
     c->plan_ready = true;
@@ -1366,7 +1391,10 @@ int fn3_create(const fn_params *params, void *stream, fn3_ctx **out)
     }
     if (p.precision != FN_FP64) { g_err3 = "the 3D path computes in FP64 only (precision FN_FP64)"; return FN_E_UNSUPPORTED; }
     if (p.eps_S != 0.0 || p.flags != 0) { g_err3 = "eps_S and flags must be 0 in 3D"; return FN_E_UNSUPPORTED; }
-    if (p.n != 0 && (p.n != G / 2)) { g_err3 = "the 3D path uses the bandwidth n = G/2 (n must be 0)"; return FN_E_UNSUPPORTED; }
+    if (p.n != 0 && (p.n % 2 || 2 * p.n < G || 4 * p.n > 3 * G)) {
+        g_err3 = "n must be 0 (G/2) or even with G/2 <= n <= 3G/4";
+        return FN_E_INVAL;
+    }
     fn3_ctx *c = new (std::nothrow) fn3_ctx();
     if (!c) { g_err3 = "out of host memory"; return FN_E_NOMEM; }
     c->prm = p;

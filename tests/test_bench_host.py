@@ -63,15 +63,19 @@ def test_3d_near_flop_accounting_and_roofline_record():
     assert bench.near3_flops_per_pair("a_near", 6) == 6 + 5 + 1 + 8 + 1 + 5 + 5 + 2
     info = {"win_ext": (110, 110, 110)}
     pairs = {"near": 10 ** 9, "a_near": 10 ** 9}
-    r = bench.roofline3("near", 2.0, 256, 6, 6, info, 1000, 4000, pairs)
+    r = bench.roofline3("near", 2.0, 256, 128, 6, 6, info, 1000, 4000, pairs)
     assert r["bound"] == "alu" and abs(r["achieved"] - 1e9 * 47 / 2e-3 / 1e12) < 1e-9
     assert abs(r["frac"] - r["achieved"] / bench.FP64_VEC_TFLOPS) < 1e-15
     # the pruned transform: window rows in, band out, per pass
     nb = 2 * 64 + 1
     fwd = (110 * 110 * (110 + nb) + nb * 110 * (110 + nb) + nb * nb * (110 + nb)) * 16
-    r = bench.roofline3("fft", 1.0, 256, 6, 6, info, 1000, 4000, pairs)
+    r = bench.roofline3("fft", 1.0, 256, 128, 6, 6, info, 1000, 4000, pairs)
     assert r["algorithmic_bytes_per_launch"] == fwd
     assert r["bound"] == "hbm" and abs(r["achieved"] - fwd / 1e-3 / 1e9) < 1e-6
     # an unpruned transform of the whole cube would move 6 G^3 complex values: far more
     assert fwd < 6 * 256 ** 3 * 16 / 4
-    assert bench.fft3_bytes(256, (110, 110, 110), False) == fwd
+    assert bench.fft3_bytes(256, 128, (110, 110, 110), False) == fwd
+    # bandwidth 3G/4: the band holds 2 * 96 + 1 frequencies per axis
+    nb = 2 * 96 + 1
+    assert bench.fft3_bytes(256, 192, (110, 110, 110), True) == (
+        110 * 110 * (110 + nb) + nb * 110 * (110 + nb) + nb * nb * (110 + nb)) * 16

@@ -3,7 +3,8 @@
   * parity with the step-by-step oracle O2 (oracle.fastsum3) element by element: phi, H and
     the H adjoint, FP64, bound 1e-10 (relative L2 and per element, tests.conftest.parity_err),
     on ball and cube clouds at G = 32, 64, 128 (several cells per near radius, ragged point
-    counts, targets coinciding with sources, window half-widths 4 to 7);
+    counts, targets coinciding with sources, window half-widths 4 to 7), at bandwidths G/2
+    and 3G/4;
   * a dense cluster (more near-field candidates per home block than the kernel's row table);
   * accuracy against the direct sum O1 at the tested parameters (the oracle's own bounds);
   * empty source or target sets, degenerate geometry and the parameter checks.
@@ -36,22 +37,26 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-# name, n_tgt, n_src, shape, G, m, p, n eps_I, seed, coincident targets
+# name, n_tgt, n_src, shape, G, m, p, n eps_I, seed, coincident targets, bandwidth (0: G/2)
 CASES = [
-    ("G32-ball", 701, 903, "ball", 32, 5, 5, 4, 31, 0),
-    ("G64-cube", 2999, 4001, "cube", 64, 6, 6, 5, 32, 50),
-    ("G128-ball", 9001, 12003, "ball", 128, 7, 8, 8, 33, 100),
-    ("G64-ball-m4", 2501, 3307, "ball", 64, 4, 6, 5, 34, 30),  # 2m <= 8: 8-lane gather groups
+    ("G32-ball", 701, 903, "ball", 32, 5, 5, 4, 31, 0, 0),
+    ("G64-cube", 2999, 4001, "cube", 64, 6, 6, 5, 32, 50, 0),
+    ("G128-ball", 9001, 12003, "ball", 128, 7, 8, 8, 33, 100, 0),
+    ("G64-ball-m4", 2501, 3307, "ball", 64, 4, 6, 5, 34, 30, 0),  # 2m <= 8: 8-lane gather groups
+    ("G64-ball-n48", 2999, 4001, "ball", 64, 5, 6, 5.5, 37, 20, 48),   # oversampling 4/3
+    ("G128-cube-n96", 9001, 12003, "cube", 128, 6, 6, 5.5, 38, 60, 96),
+    ("G32-ball-n20", 701, 903, "ball", 32, 4, 5, 3, 39, 5, 20),      # n/2 = 10, not a power of two
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_3d_matches_step_by_step_oracle(torch, fn, case):
-    name, nt, ns, shape, G, m, p, c, seed, nco = case
+    name, nt, ns, shape, G, m, p, c, seed, nco, band = case
+    n = band or G // 2
     print(f"3D case {name}: oracle", flush=True)
     y, x, w, q = synth.random_cloud3(nt, ns, seed, shape=shape)
     y[:nco] = x[:nco]
-    prm = f3.Params3(G=G, m=m, p=p, eps_I=c / (G // 2), eps_B=1 / 8)
+    prm = f3.Params3(G=G, m=m, p=p, eps_I=c / n, eps_B=1 / 8, band=band)
     F = f3.FastSum3(y, x, w, prm)
     rng = np.random.default_rng(seed + 1)
     V = rng.standard_normal((nt, 3))
@@ -60,10 +65,10 @@ def test_3d_matches_step_by_step_oracle(torch, fn, case):
     ref["HT"] = F.adjoint_H(V)
     del F
     print("  GPU", flush=True)
-    S = fn.Solver3(grid=G, m=m, p=p, eps_I=c / (G // 2), eps_B=1 / 8)
+    S = fn.Solver3(grid=G, m=m, p=p, eps_I=c / n, eps_B=1 / 8, n=band)
     S.set_geometry(dev(torch, y), dev(torch, x), dev(torch, w))
     info = S.info()
-    assert info["near_cells"] == int(np.ceil(c * 2)) and abs(info["scale"] - f3.torus_map(y, x, 1 / 8)[1]) < 1e-15
+    assert info["near_cells"] == int(np.ceil(c / n * G)) and abs(info["scale"] - f3.torus_map(y, x, 1 / 8)[1]) < 1e-15
     S.set_charges(dev(torch, q))
     phi, H = S.eval()
     u = S.adjoint_H(dev(torch, V))
@@ -150,7 +155,9 @@ def test_3d_empty_sets_and_errors(torch, fn):
     with pytest.raises(fn.FemNfftError, match="non-finite"):
         S.set_geometry(dev(torch, y), dev(torch, bad), dev(torch, w))
     # parameters the 3D path does not take
-    for kw, msg in ((dict(grid=48), "power of two"), (dict(grid=16, m=4), "grid/4"), (dict(grid=512), "power of two")):
+    for kw, msg in ((dict(grid=48), "power of two"), (dict(grid=16, m=4), "grid/4"), (dict(grid=512), "power of two"),
+                    (dict(grid=64, n=50), "G/2 <= n"), (dict(grid=64, n=30), "G/2 <= n"),
+                    (dict(grid=64, n=41), "G/2 <= n")):
         with pytest.raises(fn.FemNfftError, match=msg):
             fn.Solver3(**dict(dict(m=3, p=4, eps_I=0.1), **kw))
 

@@ -115,9 +115,9 @@ def test_regularized_kernel_is_continuous_and_equals_the_kernel_between():
         assert abs(hi - lo) < 1e-6
 
 
-@pytest.mark.parametrize("G", [16, 32])
-def test_b_coefficients_interpolate_on_the_bandwidth_grid(G):
-    prm = f3.Params3(G=G, m=3, p=4, eps_I=4 / (G // 2), eps_B=1 / 8)
+@pytest.mark.parametrize("G,band", [(16, 0), (32, 0), (16, 12), (32, 24)])
+def test_b_coefficients_interpolate_on_the_bandwidth_grid(G, band):
+    prm = f3.Params3(G=G, m=3, p=4, eps_I=4 / (band or G // 2), eps_B=1 / 8, band=band)
     n = prm.n
     b = f3.b_coeffs(prm)
     neg = (-np.arange(n)) % n
@@ -146,6 +146,22 @@ def test_windowed_pipeline_matches_brute_force_ndft():
     prm4 = f3.Params3(G=32, m=4, p=3, eps_I=3 / 16, eps_B=1 / 8)
     phi4, _ = f3.FastSum3(y, x, w, prm4).far_forward(s)
     assert 1e-12 < rel_l2(phi4, phi0) < 1e-6  # window error grows as m shrinks
+
+
+def test_windowed_pipeline_at_oversampling_4_3_matches_brute_force_ndft():
+    """The same with bandwidth n = 3G/4 (oversampling 4/3, Kaiser-Bessel shape
+    b = pi (2 - 1/sigma)): the window error decays like e^{-pi m} instead of e^{-sqrt(2) pi m}."""
+    y, x, w, q = synth.random_cloud3(30, 40, 3)
+    s = w * q
+    errs = {}
+    for m in (4, 6, 8):
+        prm = f3.Params3(G=32, m=m, p=3, eps_I=3 / 24, eps_B=1 / 8, band=24)
+        F = f3.FastSum3(y, x, w, prm)
+        phi, H = F.far_forward(s)
+        phi0, H0 = f3.direct_ndft(F.yt, F.xt, s, prm)
+        errs[m] = max(rel_l2(phi, phi0), rel_l2(H, H0))
+    print(errs)
+    assert errs[8] < 1e-11 and errs[4] > errs[6] > errs[8]
 
 
 def test_fast_sum_matches_direct_sum_and_improves_with_the_near_radius():
