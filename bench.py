@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 24, help="about this many targets (and sources)")
     ap.add_argument("--grid", type=int, default=8192)
-    ap.add_argument("--m", type=int, default=5)
+    ap.add_argument("--m", type=int, default=6)
     ap.add_argument("--p", type=int, default=5)
     ap.add_argument("--c", type=float, default=3.25,
                     help="eps_I = c / n for the volume sources (all sources when --cs 0)")

@@ -1,8 +1,9 @@
 """Parity with the step-by-step oracle (O2) at the grid sizes the bench runs, through the C-ABI.
 
 The small parity cases stop at G = 512, where an FFT block holds several short lines.  These
-cases run the shapes of the timed configuration itself: G = 2048 (m = 6) and G = 8192 (one
-line of G points per FFT block; the bench's m = 5 and the autotuner's kernel shapes),
+cases run the shapes of the timed configuration itself: G = 2048 (m = 6, and m = 5 with tuned
+shapes) and G = 8192 (one line of G points per FFT block; the bench's m = 6 and the
+autotuner's kernel shapes),
 bandwidth 3G/4, p = 5, n eps_I = 3.25 for the volume
 sources and n eps_S = 11 for the boundary Gauss points, eps_B = 1/32, two source classes,
 forward and H adjoint in one overlapped call (as timed) plus the phi adjoint.  The points
@@ -25,7 +26,8 @@ from tests.conftest import max_rel, parity_err, rel_l2
 pytestmark = pytest.mark.gpu
 
 # name, lattice points, G, window half-width m, seed, tuned shapes
-GRIDS = [("G2048", 60_000, 2048, 6, 91, False), ("G8192", 150_000, 8192, 5, 92, True)]
+GRIDS = [("G2048", 60_000, 2048, 6, 91, False), ("G2048-m5", 60_000, 2048, 5, 93, True),
+         ("G8192", 150_000, 8192, 6, 92, True)]
 P_DEG, C_VOL, C_SURF, EPS_B = 5, 3.25, 11.0, 1.0 / 32.0
 
 
