@@ -133,10 +133,10 @@ int fn_params_default(fn_params *p, int32_t grid);
 /* Parameters for n_tgt targets and n_src sources at the accuracy the library is
  * tuned for (relative L2 error of phi, H and the adjoints ~1e-7 against the
  * exact sum on FEM meshes): m = 6, bandwidth n = 3G/4 (oversampling 4/3; G/2 for
- * G = 64), and p = 8, eps_I = 7/n with G = 2^ceil(log2(sqrt(2 N))), N = n_tgt + n_src
+ * G = 64), eps_I = 7/n, and p = 8 with G = 2^ceil(log2(sqrt(2 N))), N = n_tgt + n_src
  * -- or, below 2^22 points in total, where the boundary-layer error of H is a larger
- * share, p = 10, eps_I = 8/n with G = 2^ceil(log2(sqrt(4 N))) (the larger grid keeps
- * that radius's near field cheaper); G clamped to 64..8192. */
+ * share, p = 9 with G = 2^ceil(log2(sqrt(4 N))) (the larger grid keeps the near field
+ * cheaper); G clamped to 64..8192. */
 int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p);
 
 /* Create a context bound to the current device and to the HIP stream

@@ -460,10 +460,10 @@ int fn_params_default(fn_params *p, int32_t grid)
 int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p)
 {
     if (!p || n_tgt < 0 || n_src < 0) return FN_E_INVAL;
-    // small problems (fewer than 2^22 points) take the larger near radius n eps_I = 8 with
-    // p = 10: the boundary-layer error of H weighs more there.  Grid: at least 2 grid cells
-    // per point, G^2 >= 2 (n_tgt + n_src), or 4 for the small problems, whose near field
-    // (n eps_I = 8) costs more than the larger grid's spread, FFT and gather
+    // small problems (fewer than 2^22 points) take p = 9: the boundary-layer error of H
+    // weighs more there.  Grid: at least 2 grid cells per point, G^2 >= 2 (n_tgt + n_src),
+    // or 4 for the small problems, whose near field costs more than the larger grid's
+    // spread, FFT and gather
     const int64_t npt = n_tgt + n_src;
     const bool small = npt < ((int64_t)1 << 22);
     const double want = std::sqrt((small ? 4.0 : 2.0) * (double)npt);
@@ -477,10 +477,7 @@ int fn_params_auto(int64_t n_tgt, int64_t n_src, int32_t precision, fn_params *p
     const int nb = G >= 128 ? 3 * G / 4 : G / 2;
     p->n = G >= 128 ? nb : 0;
     p->eps_I = 7.0 / nb;
-    if (small) {
-        p->p = 10;
-        p->eps_I = 8.0 / nb;
-    }
+    if (small) p->p = 9;
     return FN_OK;
 }
 
