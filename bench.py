@@ -57,6 +57,8 @@ def parse():
                     help="bandwidth n (default 3 grid/4, oversampling 4/3; 0 means grid/2)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and the sampled accuracy check")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="square2d: skip the 64-mesh batch record that the default run adds to its line")
     ap.add_argument("--samples", type=int, default=1536, help="sampled targets/sources for the O1 check")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the forward and the H adjoint one after the other on one stream instead of "
@@ -254,6 +256,14 @@ def main():
         out["fp32_vs_fp64_path_rel_l2"] = {"phi": rel(phi32, f["phi"]), "H": rel(H32, f["H"]),
                                            "HT": rel(u32, f["u"])}
         del f
+    if not args.no_c3:
+        # the batch configuration beside the headline one (its own record, not part of value)
+        del ty, tx, tw, tq, tV, phi32, H32, u32
+        torch.cuda.empty_cache()
+        c3_ms, c3_pts, c3_cfg = batch_c3_step(args, torch, synth, fn, dev)
+        out["batch_c3"] = {"metric": "nodes + quadrature points per second, one step", "value": c3_pts / (c3_ms * 1e-3),
+                           "unit": "points/s", "ms_per_step": c3_ms, "steps": args.steps, "config": c3_cfg}
+        log(f"batch_c3: {c3_ms:.3f} ms per step, {c3_pts / (c3_ms * 1e-3):.3e} points/s")
     print(json.dumps(out), flush=True)
 
 
@@ -525,50 +535,63 @@ def main_configs(args, torch, synth, fn, dev):
                {"workload": "annulus r in [0.5, 1], smooth M, energy and gradient", "n_nodes": mesh.n_nodes,
                 "n_src": mesh.n_sources, "grid": a["grid"], "params": "fn_params_auto"})
     else:  # batch_c3
-        meshes = synth.batch_meshes()
-        xs, ws, qs, Vs, ys = [], [], [], [], []
-        for m in meshes:
-            me = mesh_of(m)
-            x, w = me.sources()
-            Md = tt(m["M"])
-            ys.append(tt(m["nodes"]))
-            xs.append(x), ws.append(w), qs.append(me.charges(Md)), Vs.append(me.lumped_mass()[:, None] * Md)
-        toff = np.cumsum([0] + [len(y) for y in ys])
-        soff = np.cumsum([0] + [len(x) for x in xs])
-        Y, X, W, Q, V = (torch.cat(a) for a in (ys, xs, ws, qs, Vs))
-        st = torch.cuda.Stream()
-        with torch.cuda.stream(st):
-            B = fn.Batch([fn.auto_params(len(y), len(x), fn.FN_FP32_MIXED) for y, x in zip(ys, xs)])
-            B.set_geometry(toff, Y, soff, X, W)
-            shapes_from = "library defaults"
-            if not args.no_tune:
-                # per-member shapes: cached, or searched now on each distinct member (not timed)
-                from paper_0807_2387_amd import tune
-                res = tune.apply_batch(B, toff, Y, soff, X, W, Q, V, log=log)
-                shapes_from = (f"autotuner per member: {len({r[0] for r in res})} keys, "
-                               f"{sum(r[2] for r in res)} searched now")
-                log(f"batch_c3: {shapes_from}")
-            phi = torch.empty(len(Y), dtype=torch.float64, device=dev)
-            H = torch.empty(len(Y), 2, dtype=torch.float64, device=dev)
-            u = torch.empty(len(X), dtype=torch.float64, device=dev)
-
-            def step():
-                B.set_charges(Q)
-                B.eval_with_H_adjoint(V, out_phi=phi, out_H=H, out_u=u)
-
-            step()
-            st.synchronize()
-            g = fn.Graph()
-            with g.capture(st):
-                step()
-            st.synchronize()
-            ms = _timed(torch, lambda: g.launch(st), args.steps, args.warmup) * 1e3
-        record("batch_c3", fn.FN_FP32_MIXED, ms, len(Y) + len(X),
-               {"workload": "64 meshes, 5k-200k nodes (disks, ellipses, annuli, rounded rectangles)",
-                "n_nodes": len(Y), "n_src": len(X), "lanes": 4, "graph": True, "params": "fn_params_auto per member",
-                "shapes_from": shapes_from})
+        ms, npts, cfg = batch_c3_step(args, torch, synth, fn, dev)
+        record("batch_c3", fn.FN_FP32_MIXED, ms, npts, cfg)
     for rec in out_lines:
         print(json.dumps(rec), flush=True)
+
+
+def batch_c3_step(args, torch, synth, fn, dev):
+    """The 64-mesh batch (C3): every mesh through the library's GPU FEM front, one Batch of
+    fn_params_auto members (FP32-mixed), shapes per member from the autotuner (cached, or
+    searched on each distinct member before the timed region; --no-tune: library defaults),
+    set_charges + forward + H adjoint at once over 4 lanes, replayed from a HIP graph.
+    Returns (ms per step, points, config)."""
+    tt = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a)).to(dt or torch.float64).to(dev)
+    meshes = synth.batch_meshes()
+    xs, ws, qs, Vs, ys = [], [], [], [], []
+    for m in meshes:
+        me = fn.Mesh(tt(m["nodes"]), tt(m["tris"], torch.int32), tt(m["bedges"], torch.int32))
+        x, w = me.sources()
+        Md = tt(m["M"])
+        ys.append(tt(m["nodes"]))
+        xs.append(x), ws.append(w), qs.append(me.charges(Md)), Vs.append(me.lumped_mass()[:, None] * Md)
+    toff = np.cumsum([0] + [len(y) for y in ys])
+    soff = np.cumsum([0] + [len(x) for x in xs])
+    Y, X, W, Q, V = (torch.cat(a) for a in (ys, xs, ws, qs, Vs))
+    del xs, ws, qs, Vs, ys
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        B = fn.Batch([fn.auto_params(int(toff[i + 1] - toff[i]), int(soff[i + 1] - soff[i]), fn.FN_FP32_MIXED)
+                      for i in range(len(meshes))])
+        B.set_geometry(toff, Y, soff, X, W)
+        shapes_from = "library defaults"
+        if not args.no_tune:
+            # per-member shapes: cached, or searched now on each distinct member (not timed)
+            from paper_0807_2387_amd import tune
+            res = tune.apply_batch(B, toff, Y, soff, X, W, Q, V, log=log)
+            shapes_from = (f"autotuner per member: {len({r[0] for r in res})} keys, "
+                           f"{sum(r[2] for r in res)} searched now")
+            log(f"batch_c3: {shapes_from}")
+        phi = torch.empty(len(Y), dtype=torch.float64, device=dev)
+        H = torch.empty(len(Y), 2, dtype=torch.float64, device=dev)
+        u = torch.empty(len(X), dtype=torch.float64, device=dev)
+
+        def step():
+            B.set_charges(Q)
+            B.eval_with_H_adjoint(V, out_phi=phi, out_H=H, out_u=u)
+
+        step()
+        st.synchronize()
+        g = fn.Graph()
+        with g.capture(st):
+            step()
+        st.synchronize()
+        ms = _timed(torch, lambda: g.launch(st), args.steps, args.warmup) * 1e3
+    cfg = {"workload": "64 meshes, 5k-200k nodes (disks, ellipses, annuli, rounded rectangles)",
+           "n_nodes": len(Y), "n_src": len(X), "lanes": 4, "graph": True, "params": "fn_params_auto per member",
+           "shapes_from": shapes_from}
+    return ms, len(Y) + len(X), cfg
 
 
 def _configs_vs_direct(d, phi, H, u, args):

@@ -248,6 +248,18 @@ def test_c3_batch_of_64_meshes_vs_direct_sum(torch, fn):
         st.synchronize()
         times["overlapped call, 4 lanes, graph replay"] = timed(lambda: g.launch(st))
         assert torch.equal(phi, ref[0]) and torch.equal(H, ref[1]) and torch.equal(u, ref[2])
+        # the members' tuned shapes (the package's cache; a member it lacks is searched now):
+        # the outputs checked against O1 below are these
+        from paper_0807_2387_amd import tune
+        res = tune.apply_batch(B, toff, dev(torch, Y), soff, dev(torch, X), dev(torch, W), Qd, Vd)
+        print(f"C3 tuned shapes: {len({r[0] for r in res})} keys, {sum(r[2] for r in res)} searched", flush=True)
+        fused()
+        st.synchronize()
+        g = fn.Graph()
+        with g.capture(st):
+            fused()
+        st.synchronize()
+        times["overlapped call, 4 lanes, graph replay, tuned shapes"] = timed(lambda: g.launch(st))
     npts = len(Y) + len(X)
     for k, t in times.items():
         print(f"C3 step (set charges + forward + H adjoint), {k}: {t * 1e3:.2f} ms, {npts / t:.3e} points/s",
