@@ -559,9 +559,11 @@ __global__ void __launch_bounds__(64 * SW) k3_spread_tile(const double *__restri
 }
 
 // Grid value at every data-window point: the sum of the footprints of the tiles that reach
-// it, in tile order, written (value, 0) into the G^3 grid at the window offset.
+// it, in tile order, written into the G^3 grid at the window offset: as (value, 0) for
+// comp 0, into the imaginary part alone for comp 1 (a second real field packed into the
+// same complex grid, after its comp-0 field).
 __global__ void k3_fold(const double *__restrict__ tileout, Map3 mp, int ntx, int nty, int ntz, int G,
-                        double2 *__restrict__ g)
+                        double2 *__restrict__ g, int comp)
 {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int ex = mp.ext[0], ey = mp.ext[1], ez = mp.ext[2];
@@ -579,7 +581,9 @@ __global__ void k3_fold(const double *__restrict__ tileout, Map3 mp, int ntx, in
             const int oz = kz - tz * ST, oy = ky - ty * ST;
             for (int tx = txl; tx <= txh; ++tx) s += tileout[(tb + tx) * F3 + (oz * F + oy) * F + (kx - tx * ST)];
         }
-    g[((int64_t)(kz + mp.wlo[2]) * G + (ky + mp.wlo[1])) * G + (kx + mp.wlo[0])] = make_double2(s, 0.0);
+    const int64_t o = ((int64_t)(kz + mp.wlo[2]) * G + (ky + mp.wlo[1])) * G + (kx + mp.wlo[0]);
+    if (comp == 0) g[o] = make_double2(s, 0.0);
+    else reinterpret_cast<double *>(g)[2 * o + 1] = s;
 }
 
 __device__ __forceinline__ int w_idx(int nh, int a0, int a1, int a2)
@@ -609,19 +613,27 @@ __global__ void k3_mul_fwd(const double2 *__restrict__ F, double2 *__restrict__ 
     T2[o] = make_double2(hx.x - hy.y, hx.y + hy.x); // hx + i hy
 }
 
-// adjoint multiply over the band^3 frequencies: T = sum_d (2 pi i l_d) W F_d (T may be F0)
-__global__ void k3_mul_adj(const double2 *F0, const double2 *F1, const double2 *F2, double2 *T, int G, int nh,
-                           const double *__restrict__ W)
+// adjoint multiply over the band^3 frequencies, T = sum_d (2 pi i l_d) W F_d, with the three
+// fields in two transforms: Z = F0 + i F1 (two real fields packed in one complex grid) and F2.  A real field's spectrum is Hermitian, so at each band frequency
+// F0(l) = (Z(l) + conj Z(-l)) / 2 and F1(l) = (Z(l) - conj Z(-l)) / 2i; T goes to its own
+// grid (the thread of l reads Z at -l too).
+__global__ void k3_mul_adj_packed(const double2 *__restrict__ Z, const double2 *__restrict__ F2,
+                                  double2 *__restrict__ T, int G, int nh, const double *__restrict__ W)
 {
     const int cb = 2 * nh + 1;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= (int64_t)cb * cb * cb) return;
     const int ix = (int)(idx % cb), iy = (int)((idx / cb) % cb), iz = (int)(idx / ((int64_t)cb * cb));
     const int lx = ix <= nh ? ix : ix - cb, ly = iy <= nh ? iy : iy - cb, lz = iz <= nh ? iz : iz - cb;
-    const int64_t o = ((int64_t)(lz < 0 ? lz + G : lz) * G + (ly < 0 ? ly + G : ly)) * G + (lx < 0 ? lx + G : lx);
+    auto at = [G](int x, int y, int z) {
+        return ((int64_t)(z < 0 ? z + G : z) * G + (y < 0 ? y + G : y)) * G + (x < 0 ? x + G : x);
+    };
+    const int64_t o = at(lx, ly, lz), om = at(-lx, -ly, -lz);
     const double wv = W[w_idx(nh, abs(lz), abs(ly), abs(lx))] * 2.0 * PI;
+    const double2 z = Z[o], zm = Z[om], c = F2[o];
+    const double2 a = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));   // F0(l)
+    const double2 b = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));  // F1(l)
     // (i l) f = (-l f.y, l f.x)
-    const double2 a = F0[o], b = F1[o], c = F2[o];
     const double sx = -(lx * a.y + ly * b.y + lz * c.y), sy = lx * a.x + ly * b.x + lz * c.x;
     T[o] = make_double2(wv * sx, wv * sy);
 }
@@ -1338,8 +1350,9 @@ int check_dev(fn3_ctx *c)
     return FN_OK;
 }
 
-// spread nf value fields of set `set` (val [f][N]) into grids 0..nf-1 over the data window
-// (stage st_spread), then transform each (stage st_fft)
+// spread nf value fields of set `set` (val [f][N]) over the data window, two real fields per
+// complex grid (field f into grid f / 2, real part for even f, imaginary for odd f; stage
+// st_spread), then transform each grid (stage st_fft)
 int spread_fft(fn3_ctx *c, int set, const double *val, int64_t N, int nf, int st_spread, int st_fft)
 {
     const Plan3 &P = c->plan;
@@ -1355,12 +1368,12 @@ int spread_fft(fn3_ctx *c, int set, const double *val, int64_t N, int nf, int st
         k3_spread_tile<<<ntiles, 64 * SW, (size_t)F * F * F * sizeof(double), c->stream>>>(
             B.taps[set], B.key[set], B.cstart[set], val + (int64_t)f * N, mp, nt[0], nt[1], B.tiles);
         F3_LAUNCH(c);
-        k3_fold<<<nbk(cells), NT, 0, c->stream>>>(B.tiles, mp, nt[0], nt[1], nt[2], P.G, B.grid[f]);
+        k3_fold<<<nbk(cells), NT, 0, c->stream>>>(B.tiles, mp, nt[0], nt[1], nt[2], P.G, B.grid[f / 2], f % 2);
         F3_LAUNCH(c);
     }
     prof3_end(c, pi);
     pi = prof3_begin(c, st_fft);
-    for (int f = 0; f < nf; ++f) {
+    for (int f = 0; f < (nf + 1) / 2; ++f) {
         int rc = fft3_fwd(c, B.grid[f]);
         if (rc) return rc;
     }
@@ -1651,19 +1664,19 @@ int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u)
     rc = spread_fft(c, 0, B.aval, g.nt, 3, FN3_ST_A_SPREAD, FN3_ST_A_FFT);
     if (rc) return rc;
     const int64_t cb = P.n / 2 * 2 + 1, nband = cb * cb * cb;
-    // T = sum_d 2 pi i l_d W F_d into grid 0 (in place: each element reads its own F values)
+    // T = sum_d 2 pi i l_d W F_d into grid 2, the fields unpacked from grids 0 (F0 + i F1) and 1
     pi = prof3_begin(c, FN3_ST_A_MULTIPLY);
-    k3_mul_adj<<<nbk(nband), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], B.grid[0], P.G, P.n / 2, B.W);
+    k3_mul_adj_packed<<<nbk(nband), NT, 0, st>>>(B.grid[0], B.grid[1], B.grid[2], P.G, P.n / 2, B.W);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_A_IFFT);
-    rc = fft3_inv(c, B.grid[0]);
+    rc = fft3_inv(c, B.grid[2]);
     if (rc) return rc;
     prof3_end(c, pi);
     const Map3 mp = map_of(c);
     pi = prof3_begin(c, FN3_ST_A_GATHER);
-    if (2 * P.m <= 8) k3_gather<8><<<nbk(8 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
-    else k3_gather<16><<<nbk(16 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[0], nullptr, 1, P.G, B.far);
+    if (2 * P.m <= 8) k3_gather<8><<<nbk(8 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[2], nullptr, 1, P.G, B.far);
+    else k3_gather<16><<<nbk(16 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[2], nullptr, 1, P.G, B.far);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_A_NEAR);
