@@ -9,10 +9,13 @@
 //               phi = s (torus sum) and H = s^2 (torus gradient sum)
 //   plan        K_R = T_I (even polynomial of degree 2p-2 matching K and p-1 derivatives at
 //               eps_I) inside eps_I, K up to 1/2 - eps_B, T_B to 1/2, constant beyond;
-//               b_l = DFT of K_R on the n^3 grid; W_l = omega_l b_l / prod_d psihat(l_d/G)^2
-//   spread      g_k = sum_j s_j prod_d psi(G t_jd - k_d), (2m)^3 taps; gathered per grid
-//               point over the points of the (2m)^3 cells that reach it (fixed order, no
-//               atomics), from per-point tap tables
+//               b_l = DFT of K_R on the n^3 grid (bandwidth n: G/2, or any even n up to
+//               3G/4), by separable cosine sums since b_l is real and even;
+//               W_l = omega_l b_l / prod_d psihat(l_d/G)^2
+//   spread      g_k = sum_j s_j prod_d psi(G t_jd - k_d), (2m)^3 taps from per-point tap
+//               tables: each tile of ST^3 cells accumulates its footprint in LDS (each
+//               value updated by one wave in point order, no atomics), and a fold adds the
+//               overlapping footprints per grid point in tile order
 //   FFT         G^3 complex, Stockham line transforms through LDS along each axis
 //   multiply    W_l, and -2 pi i l_d W_l for the field; phi with H_z and H_x with H_y share
 //               one complex inverse transform each (real fields A + iB)
@@ -20,8 +23,9 @@
 //   near field  per target over the cells within eps_I: s_j (K - T_I)(r) and
 //               -s_j grad(K - T_I); a pair at distance 0 adds -s_j a_0 (the far field holds
 //               K_R(0) = a_0 for it, the exact sum leaves it out)
-//   adjoint     V spread at the targets (3 fields), sum_d 2 pi i l_d W_l F_d, inverse
-//               transform, gather at the sources, transposed near field; u = w s^2 (..)
+//   adjoint     V spread at the targets (3 fields, the first two as one complex grid),
+//               sum_d 2 pi i l_d W_l F_d, inverse transform, gather at the sources,
+//               transposed near field; u = w s^2 (..)
 #include "fn_fft_dev.h"
 
 #include <algorithm>
