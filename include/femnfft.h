@@ -412,7 +412,12 @@ int fn_batch_eval_H_adjoint(fn_batch *batch, const double *V, double *u);
  * two calls. */
 int fn_batch_eval_with_H_adjoint(fn_batch *batch, double *phi, double *H, const double *V, double *u);
 int fn_batch_eval_phi_adjoint(fn_batch *batch, const double *v, double *u);
-int fn_batch_member(fn_batch *batch, int32_t i, fn_ctx **out);    /* borrow member i's context */
+/* Borrow member i's context (owned by the batch: never destroy it, and call nothing on it
+ * while a batch call runs).  fn_set_shapes / fn_get_shapes on it set or read that member's
+ * kernel shapes for the following batch evaluations (the batch workspace fits every
+ * supported shape); fn_get_info and fn_last_error read it.  Calls that change its
+ * geometry, workspace or charges belong to the fn_batch_* functions. */
+int fn_batch_member(fn_batch *batch, int32_t i, fn_ctx **out);
 const char *fn_batch_last_error(const fn_batch *batch);
 
 /*
