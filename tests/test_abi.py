@@ -64,3 +64,41 @@ def test_null_context_is_rejected():
         assert f(None, None) == _lib.FN_E_INVAL
     assert L.fn_eval(None, None, None) == _lib.FN_E_INVAL
     assert L.fn_set_geometry(None, 1, None, 1, None, None) == _lib.FN_E_INVAL
+
+
+def test_params_auto_rule():
+    """fn_params_auto as the header states it: n = 3G/4, eps_I = 7/n, m = 6; p = 8 with
+    G^2 >= 2N from 2^22 points up, p = 9 with G^2 >= 4N below (N = targets + sources)."""
+    from paper_0807_2387_amd import _lib
+    L = _lib.lib()
+
+    def grid_for(c, N):
+        G = 64
+        while G < 8192 and G * G < c * N:
+            G *= 2
+        return G
+
+    for nt, ns in ((2_000, 12_000), (100_000, 600_000), (200_000, 1_200_000), (1 << 21, (1 << 21) - 1),
+                   (1 << 21, 1 << 21), (1_000_000, 6_000_000), (1 << 24, 1 << 24), (1 << 26, 1 << 26)):
+        p = _lib.Params()
+        assert L.fn_params_auto(nt, ns, _lib.FN_FP32_MIXED, ctypes.byref(p)) == 0
+        N = nt + ns
+        small = N < (1 << 22)
+        G = grid_for(4.0 if small else 2.0, N)
+        assert p.grid == G, (nt, ns, p.grid, G)
+        n = 3 * G // 4 if G >= 128 else 0
+        assert p.n == n and p.m == 6 and p.p == (9 if small else 8), (nt, ns, p.n, p.m, p.p)
+        assert abs(p.eps_I - 7.0 / (n or G // 2)) < 1e-18 and p.precision == _lib.FN_FP32_MIXED
+    p = _lib.Params()
+    assert L.fn_params_auto(-1, 5, _lib.FN_FP64, ctypes.byref(p)) == _lib.FN_E_INVAL
+
+
+def test_3d_bandwidth_is_checked_before_any_device_call():
+    from paper_0807_2387_amd import _lib
+    L = _lib.lib()
+    ctx = ctypes.c_void_p()
+    for n in (50, 30, 41):  # above 3G/4, below G/2, odd (G = 64)
+        q = _lib.Params(grid=64, m=4, p=6, precision=_lib.FN_FP64, eps_I=5.5 / 48, eps_B=0.125, flags=0, n=n,
+                        eps_S=0.0)
+        assert L.fn3_create(ctypes.byref(q), None, ctypes.byref(ctx)) == _lib.FN_E_INVAL, n
+        assert b"G/2 <= n <= 3G/4" in L.fn3_last_error(None)
