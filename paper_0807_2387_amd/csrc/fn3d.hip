@@ -464,11 +464,12 @@ __global__ void __launch_bounds__(512) k3_pass(double2 *__restrict__ a, int N, i
     };
     const int nl = min(PER, cu - iu0);
     const int LS = lp(N) + 1;  // line stride in LDS: the +1 spreads the PER lines of a transposed copy over the banks
+    const int log2PER = __builtin_ctz(PER);  // N and PER are powers of two: shifts, not divisions
     // copy in: axis 0 with the element index fastest, axes 1 and 2 with the line index fastest
     for (int t = threadIdx.x; t < PER * N; t += blockDim.x) {
         int li, e;
-        if (axis == 0) { li = t / N; e = t % N; }
-        else { li = t % PER; e = t / PER; }
+        if (axis == 0) { li = t >> log2N; e = t & (N - 1); }
+        else { li = t & (PER - 1); e = t >> log2PER; }
         double2 val = make_double2(0.0, 0.0);
         if (li < nl && set_has(ld, e, N, nh)) {
             val = a[base(set_at(su, iu0 + li, N, nh)) + e * stride];
@@ -481,8 +482,8 @@ __global__ void __launch_bounds__(512) k3_pass(double2 *__restrict__ a, int N, i
     fft_line_st(sh3 + (int64_t)li * LS, N, log2N, lt, NT, tw);
     for (int t = threadIdx.x; t < PER * N; t += blockDim.x) {
         int l2, e;
-        if (axis == 0) { l2 = t / N; e = t % N; }
-        else { l2 = t % PER; e = t / PER; }
+        if (axis == 0) { l2 = t >> log2N; e = t & (N - 1); }
+        else { l2 = t & (PER - 1); e = t >> log2PER; }
         if (l2 < nl && set_has(stv, e, N, nh)) {
             double2 val = sh3[(int64_t)l2 * LS + lp(e)];
             if (inv) val.y = -val.y;
