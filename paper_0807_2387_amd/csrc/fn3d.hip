@@ -706,6 +706,133 @@ __global__ void __launch_bounds__(256) k3_gather(const double *__restrict__ taps
     }
 }
 
+// The same far values by tiles, for the grids whose tile footprints fit GATHER_TILE_LDS:
+// one block per tile of ST^3 base cells (the spread's tiles) stages the tile's footprint
+// of the grid(s), F^3 values with F = ST + 2m - 1, in LDS once, then LG lanes per point of
+// the tile (lane a takes the x tap a) read the (b, c) rows from LDS in k3_gather's order
+// and add their partial sums by the same butterfly, so the results are the same bits.
+// The points of the tile are the ST^2 base-cell row runs of the sorted set, taken through
+// their prefix sums.
+constexpr int GATHER_TILE_LDS = 80 << 10;
+inline size_t gather_tile_lds(int m, int ngrid)
+{
+    const size_t F = ST + 2 * m - 1;
+    return F * F * F * sizeof(double2) * ngrid;
+}
+
+template <int LG, int NOUT>
+__global__ void __launch_bounds__(256) k3_gather_tile(const double *__restrict__ taps, const uint32_t *__restrict__ key,
+                                                      const uint32_t *__restrict__ cstart, int64_t N, Map3 mp, int ntx,
+                                                      int nty, const double2 *__restrict__ A,
+                                                      const double2 *__restrict__ B, int G, double *__restrict__ out)
+{
+    extern __shared__ double2 gsh[];  // [NOUT == 4 ? 2 : 1][F^3]
+    __shared__ uint32_t rs[ST * ST], rp[ST * ST + 1];
+    const int M2 = 2 * mp.m, F = ST + M2 - 1, F2 = F * F, F3 = F2 * F;
+    const int t = blockIdx.x, tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    const int ex = mp.ext[0], ey = mp.ext[1], ez = mp.ext[2];
+    const int nbx = ex - M2 + 1, nby = ey - M2 + 1, nbz = ez - M2 + 1;
+    const int x0 = tx * ST, y0 = ty * ST, z0 = tz * ST;
+    if (threadIdx.x < ST * ST) {  // the tile's base-cell rows (dz, dy): their runs of points
+        const int dz = threadIdx.x / ST, dy = threadIdx.x % ST;
+        uint32_t s0 = 0, cnt = 0;
+        if (z0 + dz < nbz && y0 + dy < nby) {
+            const int64_t row = ((int64_t)(z0 + dz) * ey + (y0 + dy)) * ex;
+            s0 = cstart[row + x0];
+            cnt = cstart[row + min(x0 + ST, nbx)] - s0;
+        }
+        rs[threadIdx.x] = s0;
+        rp[threadIdx.x + 1] = cnt;
+    }
+    // footprint: grid points (x0 + fx, y0 + fy, z0 + fz) of the window (none beyond it)
+    for (int i = threadIdx.x; i < F3; i += blockDim.x) {
+        const int fz = i / F2, fy = (i / F) % F, fx = i % F;
+        double2 va = make_double2(0.0, 0.0), vb = va;
+        if (x0 + fx < ex && y0 + fy < ey && z0 + fz < ez) {
+            const int64_t o = ((int64_t)(z0 + fz + mp.wlo[2]) * G + (y0 + fy + mp.wlo[1])) * G + (x0 + fx + mp.wlo[0]);
+            va = A[o];
+            if (NOUT == 4) vb = B[o];
+        }
+        gsh[i] = va;
+        if (NOUT == 4) gsh[F3 + i] = vb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        rp[0] = 0;
+        for (int r = 1; r <= ST * ST; ++r) rp[r] += rp[r - 1];
+    }
+    __syncthreads();
+    const uint32_t total = rp[ST * ST];
+    const int a = threadIdx.x % LG, ngrp = blockDim.x / LG;
+    const bool act = a < M2;
+    // a group's lanes share idx, so every shuffle below runs with its whole group active
+    for (uint32_t idx = threadIdx.x / LG; idx < total; idx += ngrp) {
+        int lo = 0, hi = ST * ST - 1;  // the row of idx: the largest r with rp[r] <= idx (a non-empty row)
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= idx) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t k = (int64_t)rs[lo] + (idx - rp[lo]);
+        const uint32_t kk = key[k];
+        const int lx = (int)(kk % (uint32_t)ex) - x0, ly = (int)((kk / (uint32_t)ex) % (uint32_t)ey) - y0;
+        const int lz = (int)(kk / ((uint32_t)ex * (uint32_t)ey)) - z0;
+        const double *tp = taps + k * 3 * M2;
+        const double txa = act ? tp[a] : 0.0;
+        double ty[LG], tz[LG];  // the point's y and z taps in registers (2m <= LG)
+#pragma unroll
+        for (int i = 0; i < LG; ++i) {
+            ty[i] = i < M2 ? tp[M2 + i] : 0.0;
+            tz[i] = i < M2 ? tp[2 * M2 + i] : 0.0;
+        }
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < LG; ++c) {
+                if (c >= M2) break;
+                const double wz = txa * tz[c];
+                const int zrow = ((lz + c) * F + ly) * F + lx + a;
+#pragma unroll
+                for (int b = 0; b < LG; b += 2) {
+                    if (b >= M2) break;
+                    const double w0 = wz * ty[b], w1 = wz * ty[b + 1];
+                    const int o = zrow + b * F;
+                    const double2 u0 = gsh[o], u1 = gsh[o + F];
+                    if (NOUT == 4) {
+                        const double2 v0 = gsh[F3 + o], v1 = gsh[F3 + o + F];
+                        acc1 = fma(w0, u0.y, acc1);
+                        acc2 = fma(w0, v0.x, acc2);
+                        acc3 = fma(w0, v0.y, acc3);
+                        acc1 = fma(w1, u1.y, acc1);
+                        acc2 = fma(w1, v1.x, acc2);
+                        acc3 = fma(w1, v1.y, acc3);
+                    }
+                    acc0 = fma(w0, u0.x, acc0);
+                    acc0 = fma(w1, u1.x, acc0);
+                }
+            }
+        }
+        for (int sft = LG / 2; sft > 0; sft >>= 1) {
+            acc0 += __shfl_xor(acc0, sft, LG);
+            if (NOUT == 4) {
+                acc1 += __shfl_xor(acc1, sft, LG);
+                acc2 += __shfl_xor(acc2, sft, LG);
+                acc3 += __shfl_xor(acc3, sft, LG);
+            }
+        }
+        if (a == 0) {
+            if (NOUT == 4) {
+                out[k] = acc0;
+                out[N + k] = acc2;
+                out[2 * N + k] = acc3;
+                out[3 * N + k] = acc1;
+            } else {
+                out[k] = acc0;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ near field + final
 
 struct Near3 {
@@ -1226,6 +1353,10 @@ int build_plan3(fn3_ctx *c)
         const int F = ST + 2 * MAXM - 1;
         F3_HIP(c, hipFuncSetAttribute((const void *)k3_spread_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       F * F * F * (int)sizeof(double)));
+        const void *gk[4] = {(const void *)k3_gather_tile<8, 1>, (const void *)k3_gather_tile<8, 4>,
+                             (const void *)k3_gather_tile<16, 1>, (const void *)k3_gather_tile<16, 4>};
+        for (const void *k : gk)
+            F3_HIP(c, hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, GATHER_TILE_LDS));
     }
     F3_HIP(c, hipMemcpyAsync(B.twG, P.twG.data(), P.twG.size() * 8, hipMemcpyHostToDevice, st));
     F3_HIP(c, hipMemcpyAsync(B.ctab, P.ctab.data(), P.ctab.size() * 8, hipMemcpyHostToDevice, st));
@@ -1353,6 +1484,34 @@ int check_dev(fn3_ctx *c)
     if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
         if (hipSetDevice(c->device) != hipSuccess) F3_ERR(c, FN_E_DEVICE, "cannot select the context's device");
     return FN_OK;
+}
+
+// Far values of point set `set` (N points) from grid A (and B: the forward's four fields):
+// by tiles when the footprints fit GATHER_TILE_LDS, else one group of lanes per point.
+void launch_gather3(fn3_ctx *c, int set, int64_t N, const double2 *A, const double2 *B, double *out)
+{
+    const Plan3 &P = c->plan;
+    Buf3 &buf = c->buf;
+    const Map3 mp = map_of(c);
+    const int M2 = 2 * P.m, nout = B ? 4 : 1;
+    const size_t lds = gather_tile_lds(P.m, B ? 2 : 1);
+    hipStream_t st = c->stream;
+    if (lds <= (size_t)GATHER_TILE_LDS) {
+        int nt[3];
+        for (int d = 0; d < 3; ++d) nt[d] = (mp.ext[d] - M2 + 1 + ST - 1) / ST;
+        const int ntiles = nt[0] * nt[1] * nt[2];
+        if (M2 <= 8) {
+            if (B) k3_gather_tile<8, 4><<<ntiles, 256, lds, st>>>(buf.taps[set], buf.key[set], buf.cstart[set], N, mp, nt[0], nt[1], A, B, P.G, out);
+            else k3_gather_tile<8, 1><<<ntiles, 256, lds, st>>>(buf.taps[set], buf.key[set], buf.cstart[set], N, mp, nt[0], nt[1], A, B, P.G, out);
+        } else {
+            if (B) k3_gather_tile<16, 4><<<ntiles, 256, lds, st>>>(buf.taps[set], buf.key[set], buf.cstart[set], N, mp, nt[0], nt[1], A, B, P.G, out);
+            else k3_gather_tile<16, 1><<<ntiles, 256, lds, st>>>(buf.taps[set], buf.key[set], buf.cstart[set], N, mp, nt[0], nt[1], A, B, P.G, out);
+        }
+    } else if (M2 <= 8) {
+        k3_gather<8><<<nbk(8 * N), NT, 0, st>>>(buf.taps[set], buf.key[set], N, mp, A, B, nout, P.G, out);
+    } else {
+        k3_gather<16><<<nbk(16 * N), NT, 0, st>>>(buf.taps[set], buf.key[set], N, mp, A, B, nout, P.G, out);
+    }
 }
 
 // spread nf value fields of set `set` (val [f][N]) over the data window, two real fields per
@@ -1633,8 +1792,7 @@ int fn3_eval(fn3_ctx *ctx, double *phi, double *H)
     // far: phi (re T1), H_z (im T1), H_x (re T2), H_y (im T2) -> far[0..3] as phi, Hx, Hy, Hz
     double *far = B.far;  // [4][nt]: phi, H_x, H_y, H_z
     pi = prof3_begin(c, FN3_ST_GATHER);
-    if (2 * P.m <= 8) k3_gather<8><<<nbk(8 * g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
-    else k3_gather<16><<<nbk(16 * g.nt), NT, 0, st>>>(B.taps[0], B.key[0], g.nt, mp, B.grid[1], B.grid[2], 4, P.G, far);
+    launch_gather3(c, 0, g.nt, B.grid[1], B.grid[2], far);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_NEAR);
@@ -1680,8 +1838,7 @@ int fn3_eval_H_adjoint(fn3_ctx *ctx, const double *V, double *u)
     prof3_end(c, pi);
     const Map3 mp = map_of(c);
     pi = prof3_begin(c, FN3_ST_A_GATHER);
-    if (2 * P.m <= 8) k3_gather<8><<<nbk(8 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[2], nullptr, 1, P.G, B.far);
-    else k3_gather<16><<<nbk(16 * g.ns), NT, 0, st>>>(B.taps[1], B.key[1], g.ns, mp, B.grid[2], nullptr, 1, P.G, B.far);
+    launch_gather3(c, 1, g.ns, B.grid[2], nullptr, B.far);
     F3_LAUNCH(c);
     prof3_end(c, pi);
     pi = prof3_begin(c, FN3_ST_A_NEAR);
