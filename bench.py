@@ -468,8 +468,8 @@ def main_configs(args, torch, synth, fn, dev):
     """The smaller configurations, every step through the library's GPU FEM front:
     disk_c1    disk of ~2k nodes, uniform M = (1, 0) (surface charges only), FP64, G = 64, m = 4,
                eps_I = 4/64; step = set_charges + phi, H + H adjoint (V = l M)
-    ellipse_c2 ellipse a = 2, b = 1, 50k nodes, vortex M with 8 random modes, G = 512 (the
-               library's defaults for it), FP32-mixed and FP64; the same step
+    ellipse_c2 ellipse a = 2, b = 1, 50k nodes, vortex M with 8 random modes, G = 512 at
+               bandwidth 384, p = 8, n eps_I = 7, FP32-mixed and FP64; the same step
     batch_c3   64 meshes of 5k-200k nodes in one batch (fn_params_auto per member, FP32-mixed),
                4 lanes, forward and H adjoint at once, replayed from a HIP graph
     annulus_c4 annulus of 1M nodes, smooth M, fn_params_auto, FP32-mixed; step = energy and
@@ -504,9 +504,11 @@ def main_configs(args, torch, synth, fn, dev):
                 cfg = {"workload": "disk radius 1, 30 polar rings, 128 boundary edges, M = (1, 0)", "grid": 64,
                        "m": 4, "eps_I": 4 / 64, "n_nodes": nt, "n_src": ns}
             else:
-                S = fn.Solver(grid=512, precision=P)
-                cfg = {"workload": "ellipse a = 2, b = 1, vortex M + 8 modes", "grid": 512, "n_nodes": nt,
-                       "n_src": ns, "params": "library defaults for G = 512"}
+                # the configuration's 512^2 grid at bandwidth 3G/4 (oversampling 4/3): the near
+                # radius eps_I = 7/n shrinks by 2/3 at the same n eps_I
+                S = fn.Solver(grid=512, n=384, eps_I=7 / 384, p=8, precision=P)
+                cfg = {"workload": "ellipse a = 2, b = 1, vortex M + 8 modes", "grid": 512, "bandwidth": 384,
+                       "p": 8, "eps_I": 7 / 384, "n_nodes": nt, "n_src": ns}
             S.bind_mesh(mesh)
             phi = torch.empty(nt, dtype=torch.float64, device=dev)
             H = torch.empty(nt, 2, dtype=torch.float64, device=dev)
