@@ -21,6 +21,8 @@ memory and the current stream) into the C calls.
 
     b = Batch([dict(grid=512), dict(grid=1024)])             # independent problems on one stream
     b.set_geometry(tgt_off, tgt_xy, src_off, src_xy, src_w)  # CSR offsets, concatenated arrays
+    b.set_shapes(1, tile=16)                                 # kernel work shapes of member 1
+    tune.apply_batch(b, tgt_off, tgt_xy, src_off, src_xy, src_w, q, V)   # tuned shapes per member
     g = Graph()
     with g.capture(stream):                                  # record library calls issued on `stream`
         b.set_charges(q); b.eval(out_phi=phi, out_H=H)
