@@ -663,14 +663,24 @@ __global__ void __launch_bounds__(256) k3_gather(const double *__restrict__ taps
     const int b2 = (int)(kk / ((uint32_t)mp.ext[0] * (uint32_t)mp.ext[1]));
     const double *tp = taps + k * 3 * M2;
     const double txa = act ? tp[a] : 0.0;
+    double ty[LG], tz[LG];  // the point's y and z taps in registers (2m <= LG)
+#pragma unroll
+    for (int i = 0; i < LG; ++i) {
+        ty[i] = i < M2 ? tp[M2 + i] : 0.0;
+        tz[i] = i < M2 ? tp[2 * M2 + i] : 0.0;
+    }
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     if (act) {
         const int64_t xo = (int64_t)b0 + mp.wlo[0] + a;
-        for (int c = 0; c < M2; ++c) {
-            const double wz = txa * tp[2 * M2 + c];
+#pragma unroll
+        for (int c = 0; c < LG; ++c) {
+            if (c >= M2) break;
+            const double wz = txa * tz[c];
             const int64_t zrow = ((int64_t)(b2 + c + mp.wlo[2]) * G + (b1 + mp.wlo[1])) * G + xo;
-            for (int b = 0; b < M2; b += 2) {  // 2m is even: two rows per trip, loads first
-                const double w0 = wz * tp[M2 + b], w1 = wz * tp[M2 + b + 1];
+#pragma unroll
+            for (int b = 0; b < LG; b += 2) {  // 2m is even: two rows per trip, loads first
+                if (b >= M2) break;
+                const double w0 = wz * ty[b], w1 = wz * ty[b + 1];
                 const int64_t o = zrow + (int64_t)b * G;
                 const double2 u0 = A[o], u1 = A[o + G];
                 if (nout == 4) {
